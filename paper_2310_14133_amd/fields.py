@@ -1,0 +1,165 @@
+"""Seeded synthetic input fields.
+
+These generators only produce inputs; they hold none of the compressor's
+arithmetic.  Both the GPU library's tests and the CPU oracle consume the same
+bytes produced here.  The shapes and statistics stand in for the paper's
+datasets (Table II), which are not available: smooth multiscale fields with a
+k^-3 power spectrum (turbulence / climate / cosmology-like), optionally
+exponentiated for a skewed, log-normal-like distribution (cosmology density),
+plus localized Gaussian features.
+"""
+import numpy as np
+
+
+def _freq_radius(shape):
+    ks = [np.fft.fftfreq(n) for n in shape[:-1]] + [np.fft.rfftfreq(shape[-1])]
+    grids = np.meshgrid(*ks, indexing="ij", sparse=True)
+    k2 = sum(g.astype(np.float64) ** 2 for g in grids)
+    return np.sqrt(k2)
+
+
+def grf(shape, seed, slope=-3.0, log_normal=False, dtype=np.float32):
+    """Gaussian random field with power spectrum P(k) ~ k^slope.
+
+    White N(0,1) noise from `seed` is filtered in Fourier space by
+    |k|^(slope/2) (k in cycles per sample, the k=0 mode removed), then
+    standardised to mean 0, std 1; `log_normal` applies exp().
+    """
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal(shape)
+    spec = np.fft.rfftn(white)
+    k = _freq_radius(shape)
+    with np.errstate(divide="ignore"):
+        amp = np.where(k > 0, k ** (slope / 2.0), 0.0)
+    g = np.fft.irfftn(spec * amp, s=shape, axes=tuple(range(len(shape))))
+    g = (g - g.mean()) / g.std()
+    if log_normal:
+        g = np.exp(g)
+    return np.ascontiguousarray(g.astype(dtype))
+
+
+def grf_torch(shape, seed, slope=-3.0, log_normal=False, device="cuda"):
+    """Same recipe as grf() computed with torch on `device` (fast for 512^3).
+
+    Deterministic for a given seed and device type; its bytes differ from
+    grf()'s.  Whatever it returns is handed unchanged to every consumer.
+    """
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    white = torch.randn(shape, generator=gen, device=device,
+                        dtype=torch.float32)
+    spec = torch.fft.rfftn(white)
+    ks = [torch.fft.fftfreq(n, device=device) for n in shape[:-1]]
+    ks.append(torch.fft.rfftfreq(shape[-1], device=device))
+    k2 = None
+    for i, kv in enumerate(ks):
+        view = [1] * len(shape)
+        view[i] = kv.numel()
+        term = (kv.view(view)) ** 2
+        k2 = term if k2 is None else k2 + term
+    k = torch.sqrt(k2)
+    amp = torch.where(k > 0, k.clamp_min(1e-30) ** (slope / 2.0),
+                      torch.zeros_like(k))
+    spec = spec * amp
+    del k, k2, amp, white
+    g = torch.fft.irfftn(spec, s=shape)
+    del spec
+    g = (g - g.mean()) / g.std()
+    if log_normal:
+        g = torch.exp(g)
+    return g.contiguous()
+
+
+def bumps_and_waves(n=256, seed=1, n_bumps=8, n_waves=3, noise=1e-3,
+                    dtype=np.float32):
+    """2D field: Gaussian bumps + plane waves + white noise.
+
+    Bumps: centres U[0,n)^2, widths U[8,40], amplitudes N(0,1).  Waves:
+    wavevector uniform in the disc |k| <= 0.1 rad/px, phase U[0,2pi),
+    amplitude 1.  Noise: N(0, noise^2).
+    """
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.arange(n, dtype=np.float64),
+                         np.arange(n, dtype=np.float64), indexing="ij")
+    f = np.zeros((n, n), np.float64)
+    for _ in range(n_bumps):
+        cy, cx = rng.uniform(0, n, 2)
+        w = rng.uniform(8, 40)
+        a = rng.normal()
+        f += a * np.exp(-((yy - cy) ** 2 + (xx - cx) ** 2) / (2 * w * w))
+    for _ in range(n_waves):
+        r = 0.1 * np.sqrt(rng.uniform())
+        th = rng.uniform(0, 2 * np.pi)
+        ky, kx = r * np.sin(th), r * np.cos(th)
+        ph = rng.uniform(0, 2 * np.pi)
+        f += np.sin(ky * yy + kx * xx + ph)
+    f += rng.normal(0.0, noise, size=(n, n))
+    return np.ascontiguousarray(f.astype(dtype))
+
+
+def multiscale(shape, seed, n_bumps=16, dtype=np.float32):
+    """k^-3 random field (standardised) + Gaussian bumps.
+
+    Bumps: centres uniform in the box, widths U[0.02, 0.1] * min(shape),
+    amplitudes N(0,1).
+    """
+    base = grf(shape, seed, slope=-3.0, dtype=np.float64)
+    rng = np.random.default_rng(seed + 7919)
+    axes = [np.arange(n, dtype=np.float64) for n in shape]
+    m = min(shape)
+    for _ in range(n_bumps):
+        c = [rng.uniform(0, n) for n in shape]
+        w = rng.uniform(0.02, 0.1) * m
+        a = rng.normal()
+        terms = [np.exp(-((ax - ci) ** 2) / (2 * w * w)) for ax, ci in
+                 zip(axes, c)]
+        g = terms[0]
+        for t in terms[1:]:
+            g = np.multiply.outer(g, t)
+        base += a * g
+    return np.ascontiguousarray(base.astype(dtype))
+
+
+def polynomial(shape, degree, seed=0, max_coef=3, dtype=np.float32):
+    """Integer-coefficient polynomial of total degree <= `degree` in the
+    grid coordinates; values are integers (exact in FP32 for small fields)."""
+    rng = np.random.default_rng(seed)
+    d = len(shape)
+    coords = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in shape],
+                         indexing="ij")
+    f = np.zeros(shape, np.float64)
+    import itertools
+    for powers in itertools.product(range(degree + 1), repeat=d):
+        if sum(powers) > degree:
+            continue
+        c = int(rng.integers(-max_coef, max_coef + 1))
+        term = np.full(shape, float(c))
+        for ax, pw in zip(coords, powers):
+            term = term * ax ** pw
+        f += term
+    return np.ascontiguousarray(f.astype(dtype))
+
+
+def adversarial(shape, kind, seed=0, dtype=np.float32):
+    """Small fields that stress edge cases: 'steps', 'spikes' (+-1e30),
+    'alternating', 'denormal', 'noise'."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    if kind == "steps":
+        f = np.floor(grf(shape, seed, dtype=np.float64) * 2.0)
+    elif kind == "spikes":
+        f = grf(shape, seed, dtype=np.float64)
+        idx = rng.choice(n, size=max(1, n // 50), replace=False)
+        f.reshape(-1)[idx] = rng.choice([-1e30, 1e30], size=idx.size)
+    elif kind == "alternating":
+        f = np.ones(n)
+        f[1::2] = -1.0
+        f = f.reshape(shape) * rng.uniform(0.5, 2.0, size=shape)
+    elif kind == "denormal":
+        f = rng.uniform(-1, 1, size=shape) * 1e-39
+    elif kind == "noise":
+        f = rng.standard_normal(shape)
+    else:
+        raise ValueError(kind)
+    return np.ascontiguousarray(np.asarray(f).astype(dtype))

@@ -1,0 +1,171 @@
+"""Oracle pins: Huffman stage (Sec. VI-A names Huffman over the quantization
+bins) and the compressed stream Z = C(X), X' = D(Z) (Sec. III).  CPU only."""
+import heapq
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2310_14133_amd import fields
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def optimal_cost(weights):
+    """Independent optimum: sum of merged weights of a heap-driven Huffman
+    (the cost of an optimal prefix code is unique)."""
+    h = [int(w) for w in weights if w > 0]
+    if len(h) == 1:
+        return h[0]
+    heapq.heapify(h)
+    cost = 0
+    while len(h) > 1:
+        a = heapq.heappop(h)
+        b = heapq.heappop(h)
+        cost += a + b
+        heapq.heappush(h, a + b)
+    return cost
+
+
+def test_textbook_example(ref):
+    g = json.load(open(os.path.join(GOLD, "huffman_textbook.json")))
+    w = np.array(g["weights"], np.uint64)
+    ln = ref.huffman_lengths(w)
+    assert int(np.sum(w * ln)) == g["optimal_cost"]
+    assert ln.tolist() == g["lengths"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_lengths_optimal_and_complete(ref, seed):
+    rng = np.random.default_rng(seed)
+    nsym = int(rng.integers(2, 3000))
+    kind = seed % 3
+    if kind == 0:
+        w = rng.integers(0, 1000, nsym)
+    elif kind == 1:   # geometric, like quantization bins around R
+        w = (1e6 * 0.6 ** np.abs(np.arange(nsym) - nsym // 2)).astype(np.int64)
+    else:             # many ties
+        w = rng.integers(0, 3, nsym) * 7
+    w[rng.integers(nsym)] += 1
+    w = w.astype(np.uint64)
+    ln = ref.huffman_lengths(w)
+    used = w > 0
+    assert np.all((ln > 0) == used)
+    if used.sum() > 1:
+        # Kraft equality of a full binary tree
+        assert sum(2.0 ** -int(l) for l in ln[used]) == 1.0
+    assert int(np.sum(w * ln)) == optimal_cost(w)
+    code = ref.huffman_codes(ln)
+    # canonical codes are prefix-free and ordered by (length, symbol)
+    syms = np.nonzero(used)[0]
+    order = sorted(syms, key=lambda s: (ln[s], s))
+    strings = [format(int(code[s]), "0%db" % ln[s]) for s in order]
+    for a, b in zip(strings, strings[1:]):
+        assert not b.startswith(a)
+        assert int(b, 2) >= int(a, 2) << (len(b) - len(a))
+    assert strings[0] == "0" * len(strings[0])
+
+
+def test_single_symbol_length_one(ref):
+    w = np.zeros(70, np.uint64)
+    w[33] = 12
+    ln = ref.huffman_lengths(w)
+    assert ln[33] == 1 and ln.sum() == 1
+
+
+def test_fibonacci_weights_depth(ref):
+    """Fibonacci weights give the deepest Huffman tree: depth n-1 for n
+    symbols (textbook worst case)."""
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    ln = ref.huffman_lengths(np.array(fib, np.uint64))
+    assert int(ln.max()) == 39
+    assert int(np.sum(np.array(fib, np.uint64) * ln)) == optimal_cost(fib)
+
+
+CASES = [
+    ("bumps256", lambda: fields.bumps_and_waves(256, 1), 1e-3, None),
+    ("grf3", lambda: fields.grf((33, 40, 47), 2), 1e-3, None),
+    ("grf3_tight", lambda: fields.grf((30, 30, 30), 3), 1e-5, None),
+    ("spikes", lambda: fields.adversarial((60, 70), "spikes", 4), 1e-3, None),
+    ("noise", lambda: fields.adversarial((31, 33, 35), "noise", 5), 1e-4, 8),
+    ("zero", lambda: np.zeros((40, 41), np.float32), 1.0, None),
+]
+
+
+@pytest.mark.parametrize("name,make,rel,s", CASES)
+def test_stream_roundtrip(ref, name, make, rel, s):
+    x = make()
+    vr = float(x.max()) - float(x.min())
+    e = rel * (vr if vr > 0 else 1.0)
+    p = ref.make_params(x.ndim, "cubic", None, 1.25, 2.0,
+                        anchor_stride=s or 0)
+    z = ref.compress(x, e, p)
+    assert z.size <= ref.compress_bound(x.shape)
+    y = ref.decompress(z)
+    codes, recon, unpred, _ = ref.predict_quantize(x, e, p)
+    assert np.array_equal(y, recon)
+    assert np.abs(x.astype(np.float64) - y).max() <= e
+    dims, e2, p2 = ref.inspect(z)
+    assert dims == x.shape and e2 == e
+    assert p2.alpha == 1.25 and p2.beta == 2.0
+    # payload bits = Huffman cost of the bins + word padding per chunk
+    hist = np.bincount(codes, minlength=2 * 32768).astype(np.uint64)
+    ln = ref.huffman_lengths(hist)
+    bits = int(np.sum(hist * ln))
+    nchunks = -(-codes.size // 4096)
+    n_words = int(np.frombuffer(z[176:184].tobytes(), np.uint64)[0])
+    assert bits <= 32 * n_words < bits + 32 * nchunks
+    assert int(np.frombuffer(z[152:160].tobytes(), np.uint64)[0]) == unpred.size
+
+
+def test_stream_header_fields(ref):
+    x = fields.grf((20, 30), 9)
+    p = ref.make_params(2, ["linear", "cubic"] * 8, [[1, 0], [0, 1]] * 8,
+                        1.5, 3.0, anchor_stride=8)
+    z = ref.compress(x, 0.01, p)
+    assert bytes(z[:4]) == b"QOZ1"
+    hdr = z[:184].tobytes()
+    u64 = lambda o: int(np.frombuffer(hdr[o:o + 8], np.uint64)[0])
+    u32 = lambda o: int(np.frombuffer(hdr[o:o + 4], np.uint32)[0])
+    assert hdr[6] == 2
+    assert (u64(8), u64(16), u64(24)) == (20, 30, 1)
+    assert (u32(40), u32(44), u32(48), u32(52)) == (32768, 8, 3, 4096)
+    assert list(hdr[72:75]) == [0, 1, 0]
+    assert list(hdr[88:94]) == [1, 0, 0, 0, 1, 0]  # 3 bytes per level
+    n_anchor = u64(136)
+    assert n_anchor == 3 * 4 and u64(144) == 600 - 12
+
+
+def test_corrupt_streams_rejected(ref):
+    x = fields.grf((40, 50), 1)
+    z = ref.compress(x, 1e-3, ref.make_params(2))
+    assert ref.decompress_status(z) == ref.OK
+    bad = z.copy(); bad[0] ^= 0xFF
+    assert ref.decompress_status(bad) == ref.EFORMAT
+    bad = z.copy(); bad[4] = 9                       # version
+    assert ref.decompress_status(bad) == ref.EFORMAT
+    assert ref.decompress_status(z[:100]) == ref.EFORMAT
+    assert ref.decompress_status(z[:-8]) == ref.EFORMAT
+    for off in (136, 144, 160, 168, 176):            # counts
+        bad = z.copy(); bad[off] ^= 0x01
+        assert ref.decompress_status(bad) == ref.EFORMAT, off
+    bad = z.copy(); bad[40] ^= 0x01                  # radius
+    assert ref.decompress_status(bad) == ref.EFORMAT
+    bad = z.copy(); bad[88] = 1; bad[89] = 1          # order not a permutation
+    assert ref.decompress_status(bad) == ref.EFORMAT
+
+
+def test_payload_bitflips_never_crash(ref):
+    """Random payload corruption decodes to garbage or EFORMAT, never an
+    out-of-bounds access (the oracle checks every read)."""
+    x = fields.grf((48, 48), 2)
+    z = ref.compress(x, 1e-3, ref.make_params(2))
+    rng = np.random.default_rng(0)
+    for _ in range(30):
+        bad = z.copy()
+        pos = int(rng.integers(184, z.size))
+        bad[pos] ^= 1 << int(rng.integers(8))
+        assert ref.decompress_status(bad) in (ref.OK, ref.EFORMAT)
