@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the QoZ hot path on one MI355X.
+
+Workload: a 512^3 float32 Gaussian random field with a k^-3 power spectrum
+(synthetic stand-in for the paper's 512^3 cosmology field), bound
+e = 1e-3 x value range.  One step = online tuning (Algorithm 1 + the
+(alpha, beta) search, ratio target, 32^3 blocks at 1%, all dimension orders)
++ compression with the tuned parameters + decompression, all on the GPU
+through the C ABI with the field resident in HBM.
+
+Prints one JSON line.  `value` is field bytes / wall time per step (GB/s).
+The roofline object describes the kernel kind with the largest summed time
+in the timed region, from HIP events the library records on its stream;
+cpu_baseline times the single-threaded CPU oracle on the same field.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_KINDS_EXCLUDED = ()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=20)
+    ap.add_argument("--log-normal", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-crop", type=int, default=0,
+                    help="edge of a central crop for the CPU baseline "
+                         "(0 = whole field)")
+    ap.add_argument("--traffic", type=str, default="",
+                    help="JSON file with measured HBM bytes per launch of "
+                         "the dominant kernel")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2310_14133_amd as q
+    from paper_2310_14133_amd import fields
+
+    n = args.size
+    dims = (n, n, n)
+    print(f"bench: generating {dims} field (seed {args.seed})", file=sys.stderr,
+          flush=True)
+    x = fields.grf_torch(dims, args.seed, log_normal=args.log_normal,
+                         device="cuda")
+    torch.cuda.synchronize()
+    vmin, vmax = float(x.min()), float(x.max())
+    e = args.eps * (vmax - vmin)
+    shape = q.make_shape(dims)
+    codec = q.Codec(0)
+    ctx = codec.ctx
+    cfg = q.make_tune_config(block=32, sample_rate=0.01, all_orders=1)
+    cap = q.qoz_compress_bound(shape)
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+    CR = q.TARGETS["cr"]
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step(record=None):
+        if record is not None:
+            ev[0].record(stream)
+        p = q.Params()
+        q.qoz_tune(ctx, x.data_ptr(), shape, e, CR, cfg, p, sh)
+        if record is not None:
+            ev[1].record(stream)
+        nb = q.qoz_compress(ctx, x.data_ptr(), shape, e, p, CR, cfg,
+                            out.data_ptr(), cap, sh)
+        if record is not None:
+            ev[2].record(stream)
+        q.qoz_decompress(ctx, out.data_ptr(), nb, y.data_ptr(), y.numel(), sh)
+        if record is not None:
+            ev[3].record(stream)
+            torch.cuda.synchronize()
+            record["tune"].append(ev[0].elapsed_time(ev[1]))
+            record["comp"].append(ev[1].elapsed_time(ev[2]))
+            record["decomp"].append(ev[2].elapsed_time(ev[3]))
+        return p, nb
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps, kernel timing on
+    q.qoz_ctx_reset_timing(ctx)
+    q.qoz_ctx_set_timing(ctx, True)
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        p, nb = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    q.qoz_ctx_set_timing(ctx, False)
+    kernels = q.timing_table(ctx)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    # per-phase split (separate, untimed-for-value passes)
+    rec = {"tune": [], "comp": [], "decomp": []}
+    for _ in range(3):
+        step(rec)
+    med = {k: sorted(v)[len(v) // 2] for k, v in rec.items()}
+
+    psnr, _, maxerr = codec.metrics(x, y, want_ssim=False)
+    field_bytes = x.numel() * 4
+    value = field_bytes / (ms_per_step / 1e3) / 1e9
+    kinds = {k: v for k, v in kernels.items() if v[0] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][1])
+    launches, tot_ms, algo_bytes = kinds[dom]
+    achieved = (algo_bytes / 1e9) / (tot_ms / 1e3)
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            traffic = json.load(f).get(dom)
+
+    line = {
+        "metric": "comp/decomp GB/s, 512^3 f32, eb 1e-3; tune time + CR vs "
+                  "exhaustive @ fixed PSNR",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"QoZ tune+compress+decompress, {n}^3 float32 "
+                        "Gaussian random field P(k)~k^-3"
+                        + (" exp-transformed" if args.log_normal else "")
+                        + f", eb {args.eps:g} x value range, ratio target, "
+                        "32^3 blocks at 1%, all dimension orders",
+            "field_bytes": field_bytes,
+            "abs_eb": e,
+        },
+        "phases_ms": {k: round(v, 4) for k, v in med.items()},
+        "compress_GBps": round(field_bytes / (med["comp"] / 1e3) / 1e9, 3),
+        "decompress_GBps": round(field_bytes / (med["decomp"] / 1e3) / 1e9,
+                                 3),
+        "tune_ms": round(med["tune"], 4),
+        "compression_ratio": round(field_bytes / nb, 4),
+        "psnr_db": round(psnr, 4),
+        "max_abs_err_over_eb": maxerr / e,
+        "params": q.params_dict(p, 3),
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(tot_ms / launches, 5),
+            "algo_bytes_per_launch": algo_bytes / launches,
+        },
+        "kernels": {k: {"launches": v[0], "ms": round(v[1], 4),
+                        "algo_GBps": round((v[2] / 1e9) / (v[1] / 1e3), 1)
+                        if v[1] > 0 else None}
+                    for k, v in kinds.items()},
+    }
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(x, e, args)
+    print(json.dumps(line), flush=True)
+    codec.close()
+
+
+def cpu_baseline(x, e, args):
+    """The oracle (single-threaded C++) on the same workload."""
+    import numpy as np
+
+    from oracle import ref
+    xh = x.cpu().numpy()
+    if args.cpu_crop:
+        c = args.cpu_crop
+        o = (xh.shape[0] - c) // 2
+        xh = np.ascontiguousarray(xh[o:o + c, o:o + c, o:o + c])
+    cfg = ref.tune_config(block=32, sample_rate=0.01, all_orders=1)
+    print(f"bench: cpu baseline on {xh.shape}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    p, _ = ref.tune(xh, e, "cr", cfg, want_trace=False)
+    t1 = time.perf_counter()
+    z = ref.compress(xh, e, p)
+    t2 = time.perf_counter()
+    ref.decompress(z)
+    t3 = time.perf_counter()
+    total = t3 - t0
+    return {"value": round(xh.nbytes / total / 1e9, 5), "unit": "GB/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"whole step (tune+compress+decompress) on "
+                      f"{'x'.join(map(str, xh.shape))} of the same field",
+            "tune_s": round(t1 - t0, 3), "compress_s": round(t2 - t1, 3),
+            "decompress_s": round(t3 - t2, 3)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * qoz.h -- C ABI of the MI355X (gfx950) QoZ library.
+ *
+ * QoZ (Liu, Di, Zhao, Liang, Chen, Cappello, "Dynamic Quality Metric Oriented
+ * Error-bounded Lossy Compression for Scientific Datasets", SC22) compresses
+ * a float32 field X under an absolute bound e: every decompressed value x'
+ * satisfies |x - x'| <= e (Sec. III).  Prediction is a multi-level
+ * interpolation over an anchor grid, with a per-level interpolator (linear or
+ * cubic, and a dimension order) and per-level bounds
+ * e_l = e / min(alpha^(l-1), beta) (Sec. V, Eq. 5); the bins are Huffman
+ * coded (Sec. VI-A).  An online tuner picks the interpolators and
+ * (alpha, beta) for a target metric by trial compression of sampled blocks
+ * (Sec. VI, Algorithm 1, Table I).
+ *
+ * Conventions for every entry point:
+ *  - Device pointers (d_*) are HIP device memory on the context's device;
+ *    host pointers (h_*) are host memory.  The caller owns all of them; the
+ *    library never frees or retains them beyond the call.
+ *  - Work is enqueued on `stream` (0 = the null stream) and the call is
+ *    synchronous: it returns after the stream has drained the work.
+ *  - Return value is a qoz_status; nothing is thrown across the ABI.
+ *    Out-parameters are written only on QOZ_OK, except *out_bytes on
+ *    QOZ_ENOSPACE (the size needed).  On any error the contents of output
+ *    buffers are unspecified.  qoz_last_error() gives a message for the
+ *    calling thread's last failure.
+ *  - A qoz_ctx owns the device scratch of one device and is not thread-safe;
+ *    use one context per thread (or serialise calls).
+ *  - Fields are float32, row-major with dims[0] slowest, ndim 2 or 3, every
+ *    used dimension >= 2, fewer than 2^32 points; unused dims are ignored.
+ */
+#ifndef QOZ_H
+#define QOZ_H
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QOZ_OK = 0,
+  QOZ_EINVAL = 1,   /* bad argument: shape, e <= 0 or non-finite, alpha or
+                       beta < 1, bad order, NaN/Inf in the input */
+  QOZ_ENOSPACE = 2, /* output capacity too small (*out_bytes = needed) */
+  QOZ_EFORMAT = 3,  /* malformed or truncated compressed stream */
+  QOZ_EDEVICE = 4,  /* a HIP runtime error */
+  QOZ_ENOMEM = 5    /* device or host allocation failed */
+} qoz_status;
+
+/* Quality target of the tuner (Sec. III): the ratio at the fixed bound,
+ * PSNR (Eq. 1) or SSIM (Eq. 2-3). */
+typedef enum {
+  QOZ_TARGET_CR = 0,
+  QOZ_TARGET_PSNR = 1,
+  QOZ_TARGET_SSIM = 2
+} qoz_target;
+
+typedef struct {
+  uint32_t ndim;    /* 2 or 3 */
+  uint64_t dims[3]; /* dims[0] slowest */
+} qoz_shape;
+
+#define QOZ_MAX_LEVELS 16
+
+/* Parameter set theta (Sec. III, Sec. V-B, Eq. 5). */
+typedef struct {
+  uint32_t anchor_stride; /* s: power of two >= 2; 0 -> 64 (2D), 32 (3D)
+                             (the paper's settings, Sec. VII-A) */
+  uint32_t levels;        /* log2(s); written by the library */
+  uint8_t interp[QOZ_MAX_LEVELS];   /* [l-1]: 0 linear, 1 cubic */
+  uint8_t order[QOZ_MAX_LEVELS][3]; /* [l-1]: permutation of 0..ndim-1,
+                                       the dimension swept first first */
+  double alpha, beta;               /* >= 1 */
+} qoz_params;
+
+/* Tuner configuration (Sec. VI-A, VI-B); zero fields take the defaults. */
+typedef struct {
+  uint32_t block;         /* b: power of two; 0 -> 64 (2D), 16 (3D) */
+  uint32_t sample_stride; /* S; 0 -> round(b * r^(-1/ndim)) */
+  double sample_rate;     /* r in (0,1]; 0 -> 0.01 (2D), 0.005 (3D) */
+  uint32_t all_orders;    /* 0: increasing and decreasing dimension orders
+                             (Sec. VI-B); 1: all ndim! orders */
+  uint32_t ssim_window;   /* 0 -> 7 */
+} qoz_tune_config;
+
+typedef struct qoz_ctx qoz_ctx;
+
+/* Create a context on HIP device `hip_device`.  Errors: EINVAL (bad
+ * device), EDEVICE. */
+qoz_status qoz_ctx_create(int hip_device, qoz_ctx** out);
+void qoz_ctx_destroy(qoz_ctx* ctx);
+
+/* Worst-case size in bytes of a compressed stream of this shape (any
+ * parameters).  Errors: EINVAL. */
+qoz_status qoz_compress_bound(qoz_shape shape, size_t* bytes);
+
+/* Online tuning (Sec. VI): sample blocks of d_x, choose per-level
+ * interpolators by mean L1 prediction error (Algorithm 1), then (alpha,
+ * beta) by the rate-quality comparison of Table I for `target` at bound
+ * abs_eb.  On input out->anchor_stride selects s (0 = default); on QOZ_OK
+ * *out holds the tuned parameters.  cfg may be NULL (defaults).
+ * Errors: EINVAL (shape, bound, target, cfg, non-finite input), EDEVICE,
+ * ENOMEM. */
+qoz_status qoz_tune(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
+                    double abs_eb, qoz_target target,
+                    const qoz_tune_config* cfg, qoz_params* out,
+                    hipStream_t stream);
+
+/* Compression Z = C_theta(X) (Sec. III) into d_out[0..cap).  params == NULL
+ * runs qoz_tune(target, cfg) first.  On QOZ_OK *out_bytes is the stream
+ * size; on QOZ_ENOSPACE it is the size needed.  The stream is
+ * self-describing (shape, bound and parameters are in its header).
+ * Errors: EINVAL, ENOSPACE, EDEVICE, ENOMEM. */
+qoz_status qoz_compress(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
+                        double abs_eb, const qoz_params* params,
+                        qoz_target target, const qoz_tune_config* cfg,
+                        void* d_out, size_t cap, size_t* out_bytes,
+                        hipStream_t stream);
+
+/* Decompression X' = D_theta(Z) (Sec. III) of d_in[0..in_bytes) into
+ * d_y (capacity y_cap_elems floats).  *out_shape (may be NULL) receives the
+ * shape.  Errors: EFORMAT (bad stream), ENOSPACE (y too small), EDEVICE,
+ * ENOMEM. */
+qoz_status qoz_decompress(qoz_ctx* ctx, const void* d_in, size_t in_bytes,
+                          float* d_y, size_t y_cap_elems,
+                          qoz_shape* out_shape, hipStream_t stream);
+
+/* Parse a stream header held in host memory.  Any output may be NULL.
+ * Errors: EFORMAT. */
+qoz_status qoz_inspect(const void* h_in, size_t in_bytes, qoz_shape* shape,
+                       double* abs_eb, qoz_params* params);
+
+/* Quality of d_y against d_x (Sec. III): PSNR (Eq. 1) with
+ * vrange = max(X) - min(X); mean SSIM (Eq. 2-3) over all ssim_window^ndim
+ * windows inside the field (0 -> 7; a dimension shorter than the window
+ * uses its length); maximum absolute error.  Sums in FP64.  Any output may
+ * be NULL.  Errors: EINVAL, EDEVICE, ENOMEM. */
+qoz_status qoz_metrics(qoz_ctx* ctx, const float* d_x, const float* d_y,
+                       qoz_shape shape, uint32_t ssim_window, double* psnr,
+                       double* ssim, double* max_abs_err, hipStream_t stream);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char* qoz_last_error(void);
+
+/* ---- instrumentation ----------------------------------------------------
+ * With timing on, the library brackets its kernel launches with HIP events
+ * on the call's stream and accumulates, per kernel kind, the launch count,
+ * the summed duration and the algorithmic bytes those launches must move
+ * (inputs read once plus outputs written once).  Kinds are numbered
+ * 0..qoz_prof_kinds()-1 and named by qoz_prof_name().  Errors: EINVAL. */
+qoz_status qoz_ctx_set_timing(qoz_ctx* ctx, int on);
+qoz_status qoz_ctx_reset_timing(qoz_ctx* ctx);
+int qoz_prof_kinds(void);
+const char* qoz_prof_name(int kind);
+qoz_status qoz_ctx_get_timing(qoz_ctx* ctx, int kind, uint64_t* launches,
+                              double* total_ms, double* algo_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,333 @@
+"""Python binding of the QoZ GPU library (libqoz.so, gfx950).
+
+The functions named qoz_* mirror the C entry points of include/qoz.h one to
+one and only marshal arguments: device pointers are plain integers (for
+example torch.Tensor.data_ptr() of a contiguous tensor on the context's
+device) and streams are raw hipStream_t handles
+(torch.cuda.current_stream().cuda_stream).  Every computation runs in the
+library's HIP kernels; nothing here computes on the host.  If the library
+has not been built, every call raises.
+
+The Codec class at the bottom is a convenience over torch tensors (torch is
+used only for device memory and streams).
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqoz.so")
+
+QOZ_OK, QOZ_EINVAL, QOZ_ENOSPACE, QOZ_EFORMAT, QOZ_EDEVICE, QOZ_ENOMEM = range(6)
+TARGETS = {"cr": 0, "psnr": 1, "ssim": 2}
+MAX_LEVELS = 16
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOSPACE", 3: "EFORMAT",
+                4: "EDEVICE", 5: "ENOMEM"}
+
+
+class Shape(C.Structure):
+    _fields_ = [("ndim", C.c_uint32), ("dims", C.c_uint64 * 3)]
+
+
+class Params(C.Structure):
+    _fields_ = [("anchor_stride", C.c_uint32), ("levels", C.c_uint32),
+                ("interp", C.c_uint8 * MAX_LEVELS),
+                ("order", (C.c_uint8 * 3) * MAX_LEVELS),
+                ("alpha", C.c_double), ("beta", C.c_double)]
+
+
+class TuneConfig(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("sample_stride", C.c_uint32),
+                ("sample_rate", C.c_double), ("all_orders", C.c_uint32),
+                ("ssim_window", C.c_uint32)]
+
+
+class QozError(RuntimeError):
+    def __init__(self, status, what, message=""):
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}"
+                         + (f" ({message})" if message else ""))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libqoz.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"QoZ GPU library not built ({LIB_PATH} missing); run "
+                "python -c 'import __graft_entry__ as g; g.build()'")
+        L = C.CDLL(LIB_PATH)
+        vp, sz, u32, u64, dbl = (C.c_void_p, C.c_size_t, C.c_uint32,
+                                 C.c_uint64, C.c_double)
+        L.qoz_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.qoz_ctx_destroy.argtypes = [vp]
+        L.qoz_ctx_destroy.restype = None
+        L.qoz_compress_bound.argtypes = [Shape, C.POINTER(sz)]
+        L.qoz_tune.argtypes = [vp, vp, Shape, dbl, C.c_int,
+                               C.POINTER(TuneConfig), C.POINTER(Params), vp]
+        L.qoz_compress.argtypes = [vp, vp, Shape, dbl, C.POINTER(Params),
+                                   C.c_int, C.POINTER(TuneConfig), vp, sz,
+                                   C.POINTER(sz), vp]
+        L.qoz_decompress.argtypes = [vp, vp, sz, vp, sz, C.POINTER(Shape), vp]
+        L.qoz_inspect.argtypes = [vp, sz, C.POINTER(Shape),
+                                  C.POINTER(dbl), C.POINTER(Params)]
+        L.qoz_metrics.argtypes = [vp, vp, vp, Shape, u32, C.POINTER(dbl),
+                                  C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.qoz_last_error.restype = C.c_char_p
+        L.qoz_ctx_set_timing.argtypes = [vp, C.c_int]
+        L.qoz_ctx_reset_timing.argtypes = [vp]
+        L.qoz_prof_name.restype = C.c_char_p
+        L.qoz_ctx_get_timing.argtypes = [vp, C.c_int, C.POINTER(u64),
+                                         C.POINTER(dbl), C.POINTER(dbl)]
+        for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
+                   "qoz_compress", "qoz_decompress", "qoz_inspect",
+                   "qoz_metrics", "qoz_ctx_set_timing",
+                   "qoz_ctx_reset_timing", "qoz_ctx_get_timing"):
+            getattr(L, fn).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != QOZ_OK:
+        msg = lib().qoz_last_error()
+        raise QozError(st, what, msg.decode() if msg else "")
+
+
+def make_shape(dims):
+    s = Shape()
+    s.ndim = len(dims)
+    for i in range(3):
+        s.dims[i] = int(dims[i]) if i < len(dims) else 1
+    return s
+
+
+def make_params(ndim, interp="cubic", order=None, alpha=1.0, beta=1.0,
+                anchor_stride=0):
+    """interp / order: one value for every level or a per-level list."""
+    p = Params()
+    p.anchor_stride = anchor_stride
+    for l in range(MAX_LEVELS):
+        it = interp[l] if isinstance(interp, (list, tuple)) else interp
+        p.interp[l] = {"linear": 0, "cubic": 1, 0: 0, 1: 1}[it]
+        if order is None:
+            o = list(range(ndim))
+        elif isinstance(order[0], (list, tuple)):
+            o = order[l]
+        else:
+            o = order
+        for j in range(3):
+            p.order[l][j] = o[j] if j < ndim else 0
+    p.alpha, p.beta = alpha, beta
+    return p
+
+
+def make_tune_config(block=0, sample_stride=0, sample_rate=0.0, all_orders=0,
+                     ssim_window=0):
+    c = TuneConfig()
+    c.block, c.sample_stride, c.sample_rate = block, sample_stride, sample_rate
+    c.all_orders, c.ssim_window = all_orders, ssim_window
+    return c
+
+
+def params_dict(p, ndim):
+    L = p.levels
+    return {"anchor_stride": p.anchor_stride, "levels": L,
+            "interp": [p.interp[l] for l in range(L)],
+            "order": [tuple(p.order[l][j] for j in range(ndim))
+                      for l in range(L)],
+            "alpha": p.alpha, "beta": p.beta}
+
+
+# ---- C entry points (same names, argument marshalling only) -------------
+
+def qoz_ctx_create(device=0):
+    h = C.c_void_p()
+    _check(lib().qoz_ctx_create(int(device), C.byref(h)), "qoz_ctx_create")
+    return h
+
+
+def qoz_ctx_destroy(ctx):
+    lib().qoz_ctx_destroy(ctx)
+
+
+def qoz_compress_bound(shape):
+    n = C.c_size_t()
+    _check(lib().qoz_compress_bound(shape, C.byref(n)), "qoz_compress_bound")
+    return n.value
+
+
+def qoz_tune(ctx, d_x, shape, abs_eb, target, cfg, params, stream):
+    """params: in (anchor_stride) / out Params."""
+    _check(lib().qoz_tune(ctx, C.c_void_p(d_x), shape, C.c_double(abs_eb),
+                          int(target), C.byref(cfg) if cfg else None,
+                          C.byref(params), C.c_void_p(stream)), "qoz_tune")
+    return params
+
+
+def qoz_compress(ctx, d_x, shape, abs_eb, params, target, cfg, d_out, cap,
+                 stream):
+    """Returns the stream size; raises QozError (ENOSPACE carries .needed)."""
+    nb = C.c_size_t()
+    st = lib().qoz_compress(ctx, C.c_void_p(d_x), shape, C.c_double(abs_eb),
+                            C.byref(params) if params else None, int(target),
+                            C.byref(cfg) if cfg else None, C.c_void_p(d_out),
+                            C.c_size_t(cap), C.byref(nb), C.c_void_p(stream))
+    if st == QOZ_ENOSPACE:
+        e = QozError(st, "qoz_compress")
+        e.needed = nb.value
+        raise e
+    _check(st, "qoz_compress")
+    return nb.value
+
+
+def qoz_decompress(ctx, d_in, in_bytes, d_y, y_cap_elems, stream):
+    sh = Shape()
+    _check(lib().qoz_decompress(ctx, C.c_void_p(d_in), C.c_size_t(in_bytes),
+                                C.c_void_p(d_y), C.c_size_t(y_cap_elems),
+                                C.byref(sh), C.c_void_p(stream)),
+           "qoz_decompress")
+    return sh
+
+
+def qoz_inspect(h_bytes):
+    """h_bytes: bytes / bytearray / numpy uint8 array of (at least) the
+    stream header in host memory."""
+    import numpy as np
+    buf = np.ascontiguousarray(np.frombuffer(bytes(h_bytes), np.uint8)
+                               if not isinstance(h_bytes, np.ndarray)
+                               else h_bytes, np.uint8)
+    sh, e, p = Shape(), C.c_double(), Params()
+    _check(lib().qoz_inspect(buf.ctypes.data_as(C.c_void_p),
+                             C.c_size_t(buf.size), C.byref(sh), C.byref(e),
+                             C.byref(p)), "qoz_inspect")
+    return sh, e.value, p
+
+
+def qoz_metrics(ctx, d_x, d_y, shape, ssim_window, stream, want_ssim=True):
+    ps, ss, me = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().qoz_metrics(ctx, C.c_void_p(d_x), C.c_void_p(d_y), shape,
+                             C.c_uint32(ssim_window), C.byref(ps),
+                             C.byref(ss) if want_ssim else None, C.byref(me),
+                             C.c_void_p(stream)), "qoz_metrics")
+    return ps.value, (ss.value if want_ssim else None), me.value
+
+
+def qoz_last_error():
+    m = lib().qoz_last_error()
+    return m.decode() if m else ""
+
+
+def qoz_ctx_set_timing(ctx, on):
+    _check(lib().qoz_ctx_set_timing(ctx, int(bool(on))), "qoz_ctx_set_timing")
+
+
+def qoz_ctx_reset_timing(ctx):
+    _check(lib().qoz_ctx_reset_timing(ctx), "qoz_ctx_reset_timing")
+
+
+def qoz_prof_kinds():
+    return lib().qoz_prof_kinds()
+
+
+def qoz_prof_name(kind):
+    return lib().qoz_prof_name(int(kind)).decode()
+
+
+def qoz_ctx_get_timing(ctx, kind):
+    n, ms, b = C.c_uint64(), C.c_double(), C.c_double()
+    _check(lib().qoz_ctx_get_timing(ctx, int(kind), C.byref(n), C.byref(ms),
+                                    C.byref(b)), "qoz_ctx_get_timing")
+    return n.value, ms.value, b.value
+
+
+def timing_table(ctx):
+    """{kind name: (launches, total ms, algorithmic bytes)}"""
+    return {qoz_prof_name(k): qoz_ctx_get_timing(ctx, k)
+            for k in range(qoz_prof_kinds())}
+
+
+# ---- torch convenience ----------------------------------------------------
+
+class Codec:
+    """Owns one library context on a HIP device; tensors in and out.
+
+    torch supplies device memory and the current stream; all compression
+    work runs in libqoz.so.
+    """
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.ctx = qoz_ctx_create(device)
+
+    def close(self):
+        if self.ctx:
+            qoz_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def _field(self, t):
+        if t.device != self.device or t.dtype != self.torch.float32 \
+                or not t.is_contiguous() or t.dim() not in (2, 3):
+            raise ValueError("need a contiguous 2D/3D float32 tensor on "
+                             f"{self.device}")
+        return make_shape(tuple(t.shape))
+
+    def tune(self, x, abs_eb, target="cr", cfg=None, anchor_stride=0):
+        sh = self._field(x)
+        p = Params()
+        p.anchor_stride = anchor_stride
+        return qoz_tune(self.ctx, x.data_ptr(), sh, abs_eb, TARGETS[target],
+                        cfg, p, self._stream())
+
+    def compress(self, x, abs_eb, params=None, target="cr", cfg=None):
+        sh = self._field(x)
+        cap = qoz_compress_bound(sh)
+        out = self.torch.empty(cap, dtype=self.torch.uint8, device=self.device)
+        n = qoz_compress(self.ctx, x.data_ptr(), sh, abs_eb, params,
+                         TARGETS[target], cfg, out.data_ptr(), cap,
+                         self._stream())
+        return out[:n]
+
+    def compress_into(self, x, abs_eb, params, out, target="cr", cfg=None):
+        sh = self._field(x)
+        return qoz_compress(self.ctx, x.data_ptr(), sh, abs_eb, params,
+                            TARGETS[target], cfg, out.data_ptr(),
+                            out.numel(), self._stream())
+
+    def decompress(self, buf, out=None):
+        head = buf[:184].cpu().numpy()
+        sh, _, _ = qoz_inspect(head.tobytes() + bytes(0)) \
+            if buf.numel() >= 184 else (None, None, None)
+        if sh is None:
+            raise QozError(QOZ_EFORMAT, "decompress", "stream too short")
+        dims = tuple(int(sh.dims[i]) for i in range(sh.ndim))
+        if out is None:
+            out = self.torch.empty(dims, dtype=self.torch.float32,
+                                   device=self.device)
+        qoz_decompress(self.ctx, buf.data_ptr(), buf.numel(), out.data_ptr(),
+                       out.numel(), self._stream())
+        return out
+
+    def metrics(self, x, y, ssim_window=7, want_ssim=True):
+        sh = self._field(x)
+        return qoz_metrics(self.ctx, x.data_ptr(), y.data_ptr(), sh,
+                           ssim_window, self._stream(), want_ssim)
+
+
+def rel_to_abs(vmin, vmax, eps):
+    """Value-range-relative bound (Sec. VII-A): e = eps * (max - min)."""
+    return float(eps) * (float(vmax) - float(vmin))

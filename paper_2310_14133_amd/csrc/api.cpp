@@ -1,0 +1,419 @@
+/*
+ * Entry points of the QoZ GPU library: compression C_theta, decompression
+ * D_theta (Sec. III), stream inspection, and quality metrics (Eq. 1-3).
+ * The tuner entry point is in tune_host.cpp.
+ *
+ * Host/device traffic per compression: one 256 KB histogram read-back to
+ * build the Huffman code on the host, one read-back of the payload size,
+ * and the small header and codebook uploads.
+ */
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "qoz_internal.h"
+
+namespace qoz {
+
+/* pinned staging regions */
+constexpr size_t kPinHist = 0;                 /* 256 KB */
+constexpr size_t kPinTable = 256u << 10;       /* 512 KB */
+constexpr size_t kPinStage = 768u << 10;       /* 256 KB */
+constexpr size_t kPinStatus = 1024u << 10;     /* 4 KB */
+constexpr size_t kPinSmall = (1024u << 10) + 4096;
+constexpr size_t kPinBase = 2u << 20;
+
+static inline uint8_t* pin(qoz_ctx* c, size_t off) {
+  return (uint8_t*)c->pinned + off;
+}
+
+#define PROF(kind, bytes, launch)                 \
+  do {                                            \
+    hipEvent_t ev_ = prof_begin(c, s);            \
+    launch;                                       \
+    prof_end(c, s, ev_, (kind), (double)(bytes)); \
+  } while (0)
+
+static qoz_status sync_checked(hipStream_t s) {
+  QOZ_HIP(hipGetLastError());
+  QOZ_HIP(hipStreamSynchronize(s));
+  return QOZ_OK;
+}
+
+qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
+                              void* d_out, size_t cap, size_t* out_bytes,
+                              hipStream_t s) {
+  const uint64_t N = (uint64_t)P.g.n[0] * P.g.n[1] * P.g.n[2];
+  const uint64_t nch = P.n_chunks;
+  QOZ_TRY(ensure_pinned(c, kPinBase));
+  QOZ_TRY(ensure(c->W, 4 * N));
+  QOZ_TRY(ensure(c->codes, 4 * (P.n_codes + 4)));
+  QOZ_TRY(ensure(c->hist, 4 * kNSym));
+  QOZ_TRY(ensure(c->status, 256));
+  QOZ_TRY(ensure(c->anchors, 4 * P.n_anchor));
+  QOZ_TRY(ensure(c->chunk_bits, 4 * nch));
+  QOZ_TRY(ensure(c->chunk_zeros, 4 * nch));
+  QOZ_TRY(ensure(c->coff, 8 * (nch + 1)));
+  QOZ_TRY(ensure(c->upre, 4 * (nch + 1)));
+  QOZ_TRY(ensure(c->enc_table, 8 * kNSym));
+  float* W = (float*)c->W.p;
+  int32_t* codes = (int32_t*)c->codes.p;
+  uint32_t* hist = (uint32_t*)c->hist.p;
+  uint32_t* st = (uint32_t*)c->status.p;
+  uint64_t* totals = (uint64_t*)((uint8_t*)c->status.p + 64);
+
+  launch_init_status(st, s);
+  launch_zero_u32(hist, kNSym, s);
+  PROF(PK_ANCHOR, 8.0 * P.n_anchor,
+       launch_anchor_copy(P.g, P.s, P.na, d_x, W, (float*)c->anchors.p, st,
+                          s));
+  for (size_t i = 0; i < P.sweeps.size(); ++i) {
+    const Sweep& sw = P.sweeps[i];
+    const bool last = i + 1 == P.sweeps.size();
+    PROF(sw.level == 1 ? PK_SWEEP_COMP_L1 : PK_SWEEP_COMP,
+         (double)sw.count * (last ? 12.0 : 16.0),
+         launch_sweep_comp(P.g, sw, d_x, W, codes, !last, st, s));
+  }
+  PROF(PK_HIST, 4.0 * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinHist), hist, 4 * kNSym,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
+                         s));
+  QOZ_TRY(sync_checked(s));
+  if (((uint32_t*)pin(c, kPinStatus))[0] & kStNonFinite)
+    return fail(QOZ_EINVAL, "input contains NaN or Inf");
+
+  /* Huffman code on the host */
+  const uint32_t* h = (const uint32_t*)pin(c, kPinHist);
+  std::vector<uint8_t> len(kNSym);
+  std::vector<uint64_t> code(kNSym);
+  if (!huffman_lengths(h, kNSym, len.data()))
+    return fail(QOZ_EINVAL, "Huffman code longer than 63 bits");
+  canonical_codes(len.data(), kNSym, code.data());
+  uint64_t n_used = 0;
+  int32_t lo = -1, hi = -1;
+  for (uint32_t sy = 0; sy < kNSym; ++sy) {
+    if (!len[sy]) continue;
+    ++n_used;
+    if (sy == 0) continue;
+    if (lo < 0) lo = (int32_t)sy;
+    hi = (int32_t)sy;
+  }
+  const uint64_t n_unpred = h[0];
+  const uint32_t tab_n = lo < 0 ? 0 : (uint32_t)(hi - lo + 1);
+  uint64_t* tab = (uint64_t*)pin(c, kPinTable);
+  for (uint32_t i = 0; i < tab_n; ++i) {
+    uint32_t sy = (uint32_t)lo + i;
+    tab[i] = len[sy] ? (code[sy] << 8) | len[sy] : 0;
+  }
+  const uint64_t zero_entry = len[0] ? (code[0] << 8) | len[0] : 0;
+  if (tab_n)
+    QOZ_HIP(hipMemcpyAsync(c->enc_table.p, tab, 8ull * tab_n,
+                           hipMemcpyHostToDevice, s));
+  const uint64_t* dtab = (const uint64_t*)c->enc_table.p;
+  PROF(PK_HUFF_LEN, 4.0 * P.n_codes + 8.0 * nch,
+       (launch_huff_len(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
+                        (uint32_t*)c->chunk_bits.p,
+                        (uint32_t*)c->chunk_zeros.p, s),
+        launch_chunk_scan((uint32_t*)c->chunk_bits.p,
+                          (uint32_t*)c->chunk_zeros.p, nch,
+                          (uint64_t*)c->coff.p, (uint32_t*)c->upre.p, totals,
+                          s)));
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus + 64), totals, 16,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_TRY(sync_checked(s));
+  const uint64_t n_words = ((uint64_t*)pin(c, kPinStatus + 64))[0];
+  const Layout lay = layout_of(P.n_anchor, n_used, nch, n_unpred, n_words);
+  if (!d_out || lay.total > cap) {
+    *out_bytes = lay.total;
+    prof_collect(c);
+    return fail(QOZ_ENOSPACE, "output capacity too small");
+  }
+  uint8_t* out = (uint8_t*)d_out;
+  /* section padding must read as zero */
+  launch_zero_u32((uint32_t*)out, lay.payload / 4, s);
+  uint8_t* hs = pin(c, kPinStage);
+  write_header(hs, P, n_unpred, n_used, n_words);
+  QOZ_HIP(hipMemcpyAsync(out, hs, kHeaderBytes, hipMemcpyHostToDevice, s));
+  uint8_t* cb = pin(c, kPinStage + 256);
+  const size_t cb_bytes = lay.coff - lay.syms;
+  std::memset(cb, 0, cb_bytes);
+  {
+    uint64_t k = 0;
+    for (uint32_t sy = 0; sy < kNSym; ++sy)
+      if (len[sy]) {
+        uint16_t v = (uint16_t)sy;
+        std::memcpy(cb + 2 * k, &v, 2);
+        cb[(lay.lens - lay.syms) + k] = len[sy];
+        ++k;
+      }
+  }
+  QOZ_HIP(hipMemcpyAsync(out + lay.syms, cb, cb_bytes, hipMemcpyHostToDevice,
+                         s));
+  if (P.n_anchor)
+    QOZ_HIP(hipMemcpyAsync(out + lay.anchors, c->anchors.p, 4 * P.n_anchor,
+                           hipMemcpyDeviceToDevice, s));
+  QOZ_HIP(hipMemcpyAsync(out + lay.coff, c->coff.p, 8 * (nch + 1),
+                         hipMemcpyDeviceToDevice, s));
+  QOZ_HIP(hipMemcpyAsync(out + lay.upre, c->upre.p, 4 * (nch + 1),
+                         hipMemcpyDeviceToDevice, s));
+  SweepTable tbl;
+  fill_sweep_table(P, &tbl);
+  PROF(PK_HUFF_ENC, 4.0 * P.n_codes + 4.0 * n_words + 4.0 * n_unpred,
+       launch_huff_encode(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
+                          (const uint64_t*)c->coff.p,
+                          (const uint32_t*)c->upre.p,
+                          (uint32_t*)(out + lay.payload),
+                          (cap - lay.payload) / 4, (float*)(out + lay.unpred),
+                          d_x, P.g, tbl, st, s));
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
+                         s));
+  QOZ_TRY(sync_checked(s));
+  prof_collect(c);
+  if (((uint32_t*)pin(c, kPinStatus))[0] & kStOverflow) {
+    *out_bytes = lay.total;
+    return fail(QOZ_ENOSPACE, "output capacity too small");
+  }
+  *out_bytes = lay.total;
+  return QOZ_OK;
+}
+
+}  // namespace qoz
+
+using namespace qoz;
+
+extern "C" {
+
+qoz_status qoz_compress_bound(qoz_shape shape, size_t* bytes) {
+  clear_error();
+  int d;
+  uint64_t n[3];
+  if (!bytes || !shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  uint64_t N = 1;
+  for (int i = 0; i < d; ++i) N *= n[i];
+  /* every point a bin (no anchors): <= 16 bits each plus a padding word per
+   * chunk, every bin possibly unpredictable, all 65536 symbols used */
+  uint64_t chunks = (N + kChunk - 1) / kChunk;
+  Layout lay = layout_of(0, kNSym, chunks, N, (N + 1) / 2 + chunks);
+  *bytes = lay.total + 64;
+  return QOZ_OK;
+}
+
+qoz_status qoz_compress(qoz_ctx* c, const float* d_x, qoz_shape shape,
+                        double abs_eb, const qoz_params* params,
+                        qoz_target target, const qoz_tune_config* cfg,
+                        void* d_out, size_t cap, size_t* out_bytes,
+                        hipStream_t s) {
+  clear_error();
+  if (!c || !d_x || !out_bytes) return fail(QOZ_EINVAL, "NULL argument");
+  if (((uintptr_t)d_out & 7) != 0)
+    return fail(QOZ_EINVAL, "output must be 8-byte aligned");
+  QOZ_TRY(set_device(c));
+  qoz_params p;
+  if (params) {
+    p = *params;
+  } else {
+    std::memset(&p, 0, sizeof(p));
+    QOZ_TRY(qoz_tune(c, d_x, shape, abs_eb, target, cfg, &p, s));
+  }
+  Plan P;
+  QOZ_TRY(make_plan(shape, abs_eb, p, &P));
+  return compress_with_plan(c, d_x, P, d_out, cap, out_bytes, s);
+}
+
+qoz_status qoz_inspect(const void* h_in, size_t in_bytes, qoz_shape* shape,
+                       double* abs_eb, qoz_params* params) {
+  clear_error();
+  if (!h_in) return fail(QOZ_EFORMAT, "NULL stream");
+  Plan P;
+  uint64_t nu, nused, nw;
+  QOZ_TRY(parse_header((const uint8_t*)h_in, in_bytes, false, &P, &nu, &nused,
+                       &nw));
+  if (shape) {
+    std::memset(shape, 0, sizeof(*shape));
+    shape->ndim = (uint32_t)P.d;
+    if (P.d == 2) {
+      shape->dims[0] = P.g.n[1];
+      shape->dims[1] = P.g.n[2];
+      shape->dims[2] = 1;
+    } else {
+      for (int i = 0; i < 3; ++i) shape->dims[i] = P.g.n[i];
+    }
+  }
+  if (abs_eb) *abs_eb = P.e;
+  if (params) {
+    std::memset(params, 0, sizeof(*params));
+    params->anchor_stride = P.s;
+    params->levels = P.L;
+    std::memcpy(params->interp, P.interp, sizeof(P.interp));
+    std::memcpy(params->order, P.order, sizeof(P.order));
+    params->alpha = P.alpha;
+    params->beta = P.beta;
+  }
+  return QOZ_OK;
+}
+
+qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
+                          float* d_y, size_t y_cap_elems,
+                          qoz_shape* out_shape, hipStream_t s) {
+  clear_error();
+  if (!c || !d_in) return fail(QOZ_EINVAL, "NULL argument");
+  if (((uintptr_t)d_in & 7) != 0)
+    return fail(QOZ_EINVAL, "stream must be 8-byte aligned");
+  QOZ_TRY(set_device(c));
+  QOZ_TRY(ensure_pinned(c, kPinBase));
+  if (in_bytes < kHeaderBytes) return fail(QOZ_EFORMAT, "stream too short");
+  uint8_t* hs = pin(c, kPinStage);
+  QOZ_HIP(hipMemcpyAsync(hs, d_in, kHeaderBytes, hipMemcpyDeviceToHost, s));
+  QOZ_TRY(sync_checked(s));
+  Plan P;
+  uint64_t nu, nused, nw;
+  QOZ_TRY(parse_header(hs, in_bytes, true, &P, &nu, &nused, &nw));
+  const uint64_t N = (uint64_t)P.g.n[0] * P.g.n[1] * P.g.n[2];
+  if (!d_y || y_cap_elems < N)
+    return fail(QOZ_ENOSPACE, "output field too small");
+  const uint64_t nch = P.n_chunks;
+  const Layout lay = layout_of(P.n_anchor, nused, nch, nu, nw);
+  const uint8_t* in = (const uint8_t*)d_in;
+  uint8_t* cb = pin(c, kPinStage + 256);
+  QOZ_HIP(hipMemcpyAsync(cb, in + lay.syms, lay.coff - lay.syms,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_TRY(sync_checked(s));
+  DecTables* dt = (DecTables*)pin(c, kPinTable);
+  std::vector<uint32_t> sorted;
+  if (!build_dec_tables((const uint16_t*)cb, cb + (lay.lens - lay.syms),
+                        (uint32_t)nused, dt, &sorted))
+    return fail(QOZ_EFORMAT, "bad Huffman codebook");
+  const size_t syms_off = (sizeof(DecTables) + 255) / 256 * 256;
+  std::memcpy(pin(c, kPinTable + syms_off), sorted.data(),
+              4 * sorted.size());
+  QOZ_TRY(ensure(c->dec_tables, sizeof(DecTables)));
+  QOZ_TRY(ensure(c->dec_syms, 4 * kNSym));
+  QOZ_TRY(ensure(c->codes, 4 * (P.n_codes + 4)));
+  QOZ_TRY(ensure(c->status, 256));
+  QOZ_HIP(hipMemcpyAsync(c->dec_tables.p, dt, sizeof(DecTables),
+                         hipMemcpyHostToDevice, s));
+  QOZ_HIP(hipMemcpyAsync(c->dec_syms.p, pin(c, kPinTable + syms_off),
+                         4 * sorted.size(), hipMemcpyHostToDevice, s));
+  uint32_t* st = (uint32_t*)c->status.p;
+  int32_t* codes = (int32_t*)c->codes.p;
+  launch_init_status(st, s);
+  PROF(PK_HUFF_DEC, 4.0 * nw + 4.0 * P.n_codes,
+       launch_huff_decode((const uint32_t*)(in + lay.payload), nw,
+                          (const uint64_t*)(in + lay.coff),
+                          (const uint32_t*)(in + lay.upre), nch, P.n_codes, nu,
+                          (const DecTables*)c->dec_tables.p,
+                          (const uint32_t*)c->dec_syms.p, codes, st, s));
+  PROF(PK_ANCHOR, 8.0 * P.n_anchor,
+       launch_anchor_scatter(P.g, P.s, P.na, (const float*)(in + lay.anchors),
+                             d_y, s));
+  for (const Sweep& sw : P.sweeps)
+    PROF(sw.level == 1 ? PK_SWEEP_DEC_L1 : PK_SWEEP_DEC,
+         (double)sw.count * 12.0,
+         launch_sweep_decomp(P.g, sw, d_y, codes,
+                             (const float*)(in + lay.unpred), nu, st, s));
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
+                         s));
+  QOZ_TRY(sync_checked(s));
+  prof_collect(c);
+  if (((uint32_t*)pin(c, kPinStatus))[0] & kStBadStream)
+    return fail(QOZ_EFORMAT, "corrupt Huffman payload or chunk tables");
+  if (out_shape) {
+    std::memset(out_shape, 0, sizeof(*out_shape));
+    out_shape->ndim = (uint32_t)P.d;
+    if (P.d == 2) {
+      out_shape->dims[0] = P.g.n[1];
+      out_shape->dims[1] = P.g.n[2];
+      out_shape->dims[2] = 1;
+    } else {
+      for (int i = 0; i < 3; ++i) out_shape->dims[i] = P.g.n[i];
+    }
+  }
+  return QOZ_OK;
+}
+
+qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
+                       qoz_shape shape, uint32_t ssim_window, double* psnr,
+                       double* ssim, double* max_abs_err, hipStream_t s) {
+  clear_error();
+  if (!c || !d_x || !d_y) return fail(QOZ_EINVAL, "NULL argument");
+  int d;
+  uint64_t n[3] = {1, 1, 1};
+  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  if (ssim_window == 0) ssim_window = 7;
+  if (ssim_window > 11) return fail(QOZ_EINVAL, "ssim_window must be <= 11");
+  QOZ_TRY(set_device(c));
+  const Geo g = make_geo(d, n);
+  const uint64_t N = (uint64_t)g.n[0] * g.n[1] * g.n[2];
+  const uint32_t rp = range_parts(N), sp = sse_parts(N);
+  SsimJob j;
+  j.P = g.n[0];
+  j.Rn = g.n[1];
+  j.Cn = g.n[2];
+  j.wp = g.n[0] < ssim_window ? g.n[0] : ssim_window;
+  j.wr = g.n[1] < ssim_window ? g.n[1] : ssim_window;
+  j.wc = g.n[2] < ssim_window ? g.n[2] : ssim_window;
+  j.field_stride = N;
+  j.batch = 1;
+  j.x_mod = 1;
+  const uint64_t qp = ssim ? ssim_parts(j) : 0;
+  const size_t small = 8 * (2 * (size_t)rp + 2 * (size_t)sp + qp) + 1024;
+  QOZ_TRY(ensure_pinned(c, kPinSmall + small));
+  QOZ_TRY(ensure(c->partial, small));
+  QOZ_TRY(ensure(c->ssim_part, 8 * (qp + 1)));
+  QOZ_TRY(ensure(c->status, 256));
+  uint8_t* dp = (uint8_t*)c->partial.p;
+  float* pmin = (float*)dp;
+  float* pmax = pmin + rp;
+  double* psse = (double*)(dp + 8 * (size_t)rp);
+  double* pmx = psse + sp;
+  uint32_t* st = (uint32_t*)c->status.p;
+  launch_init_status(st, s);
+  PROF(PK_CHECK, 4.0 * N, launch_range(d_x, N, pmin, pmax, st, rp, s));
+  PROF(PK_REDUCE, 8.0 * N, launch_sse_max(d_x, d_y, N, psse, pmx, sp, s));
+  const size_t part_bytes = 8 * (size_t)rp + 16 * (size_t)sp;
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinSmall), dp, part_bytes,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
+                         s));
+  QOZ_TRY(sync_checked(s));
+  const float* hmin = (const float*)pin(c, kPinSmall);
+  const float* hmax = hmin + rp;
+  float lo = hmin[0], hi = hmax[0];
+  for (uint32_t i = 1; i < rp; ++i) {
+    lo = std::fmin(lo, hmin[i]);
+    hi = std::fmax(hi, hmax[i]);
+  }
+  const double vrange = (double)hi - (double)lo;
+  const double* hsse = (const double*)(pin(c, kPinSmall) + 8 * (size_t)rp);
+  double sse = 0.0, mx = 0.0;
+  for (uint32_t i = 0; i < sp; ++i) {
+    sse += hsse[i];
+    mx = std::fmax(mx, hsse[sp + i]);
+  }
+  if (psnr) {
+    double mse = sse / (double)N;
+    *psnr = mse == 0.0 ? std::numeric_limits<double>::infinity()
+                       : 20.0 * std::log10(vrange / std::sqrt(mse));
+  }
+  if (max_abs_err) *max_abs_err = mx;
+  if (ssim) {
+    j.c1 = (0.01 * vrange) * (0.01 * vrange);
+    j.c2 = (0.03 * vrange) * (0.03 * vrange);
+    double* parts = (double*)c->ssim_part.p;
+    PROF(PK_SSIM, 8.0 * N, launch_ssim(j, d_x, d_y, parts, s));
+    QOZ_HIP(hipMemcpyAsync(pin(c, kPinSmall), parts, 8 * qp,
+                           hipMemcpyDeviceToHost, s));
+    QOZ_TRY(sync_checked(s));
+    const double* hp = (const double*)pin(c, kPinSmall);
+    double tot = 0.0;
+    for (uint64_t i = 0; i < qp; ++i) tot += hp[i];
+    const double nwin = (double)(j.P - j.wp + 1) * (double)(j.Rn - j.wr + 1) *
+                        (double)(j.Cn - j.wc + 1);
+    *ssim = tot / nwin;
+  }
+  prof_collect(c);
+  return QOZ_OK;
+}
+
+}  // extern "C"

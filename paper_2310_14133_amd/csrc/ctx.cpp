@@ -1,0 +1,189 @@
+/*
+ * Context, scratch memory, error reporting and kernel timing of the QoZ GPU
+ * library.
+ */
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "qoz_internal.h"
+
+namespace qoz {
+
+static thread_local std::string g_last_error;
+
+qoz_status fail(qoz_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+qoz_status hip_fail(hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  g_last_error = m;
+  return e == hipErrorOutOfMemory ? QOZ_ENOMEM : QOZ_EDEVICE;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+qoz_status set_device(qoz_ctx* c) {
+  QOZ_HIP(hipSetDevice(c->device));
+  return QOZ_OK;
+}
+
+qoz_status ensure(DevBuf& b, size_t bytes) {
+  if (bytes <= b.bytes && b.p) return QOZ_OK;
+  if (b.p) {
+    QOZ_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes < 256 ? 256 : bytes;
+  QOZ_HIP(hipMalloc(&b.p, want));
+  b.bytes = want;
+  return QOZ_OK;
+}
+
+qoz_status ensure_pinned(qoz_ctx* c, size_t bytes) {
+  if (bytes <= c->pinned_bytes && c->pinned) return QOZ_OK;
+  if (c->pinned) {
+    QOZ_HIP(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+  }
+  QOZ_HIP(hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+  c->pinned_bytes = bytes;
+  return QOZ_OK;
+}
+
+hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s) {
+  if (!c->timing) return nullptr;
+  hipEvent_t e;
+  if (!c->event_pool.empty()) {
+    e = c->event_pool.back();
+    c->event_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  (void)hipEventRecord(e, s);
+  return e;
+}
+
+void prof_end(qoz_ctx* c, hipStream_t s, hipEvent_t a, int kind,
+              double bytes) {
+  if (!c->timing || !a) return;
+  hipEvent_t b;
+  if (!c->event_pool.empty()) {
+    b = c->event_pool.back();
+    c->event_pool.pop_back();
+  } else if (hipEventCreate(&b) != hipSuccess) {
+    c->event_pool.push_back(a);
+    return;
+  }
+  (void)hipEventRecord(b, s);
+  c->pending.push_back({kind, a, b, bytes});
+}
+
+void prof_collect(qoz_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_launches[p.kind] += 1;
+      c->prof_ms[p.kind] += ms;
+      c->prof_bytes[p.kind] += p.bytes;
+    }
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+static const char* kProfNames[PK_COUNT] = {
+    "check_range",     "anchors",         "sweep_comp_level1",
+    "sweep_comp",      "histogram",       "huffman_lengths",
+    "huffman_encode",  "huffman_decode",  "sweep_decomp_level1",
+    "sweep_decomp",    "tune_gather",     "tune_alg1",
+    "tune_trial",      "ssim",            "reduce"};
+
+}  // namespace qoz
+
+using namespace qoz;
+
+extern "C" {
+
+qoz_status qoz_ctx_create(int hip_device, qoz_ctx** out) {
+  clear_error();
+  if (!out) return fail(QOZ_EINVAL, "out is NULL");
+  int n = 0;
+  QOZ_HIP(hipGetDeviceCount(&n));
+  if (hip_device < 0 || hip_device >= n)
+    return fail(QOZ_EINVAL, "no such HIP device");
+  qoz_ctx* c = new (std::nothrow) qoz_ctx();
+  if (!c) return fail(QOZ_ENOMEM, "context allocation failed");
+  c->device = hip_device;
+  qoz_status st = set_device(c);
+  if (st == QOZ_OK) st = ensure_pinned(c, 2u << 20);
+  if (st != QOZ_OK) {
+    qoz_ctx_destroy(c);
+    return st;
+  }
+  *out = c;
+  return QOZ_OK;
+}
+
+void qoz_ctx_destroy(qoz_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  DevBuf* bufs[] = {&c->W,          &c->codes,      &c->hist,
+                    &c->chunk_bits, &c->chunk_zeros, &c->coff,
+                    &c->upre,       &c->status,     &c->enc_table,
+                    &c->dec_tables, &c->dec_syms,   &c->anchors,
+                    &c->partial,    &c->tune_x,     &c->tune_wc,
+                    &c->tune_wt,    &c->tune_desc,  &c->tune_hist,
+                    &c->tune_stats, &c->tune_l1,    &c->ssim_part};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* qoz_last_error(void) { return g_last_error.c_str(); }
+
+qoz_status qoz_ctx_set_timing(qoz_ctx* c, int on) {
+  if (!c) return fail(QOZ_EINVAL, "ctx is NULL");
+  c->timing = on != 0;
+  return QOZ_OK;
+}
+
+qoz_status qoz_ctx_reset_timing(qoz_ctx* c) {
+  if (!c) return fail(QOZ_EINVAL, "ctx is NULL");
+  for (int k = 0; k < PK_COUNT; ++k) {
+    c->prof_launches[k] = 0;
+    c->prof_ms[k] = 0;
+    c->prof_bytes[k] = 0;
+  }
+  return QOZ_OK;
+}
+
+int qoz_prof_kinds(void) { return PK_COUNT; }
+
+const char* qoz_prof_name(int kind) {
+  return kind >= 0 && kind < PK_COUNT ? kProfNames[kind] : "";
+}
+
+qoz_status qoz_ctx_get_timing(qoz_ctx* c, int kind, uint64_t* launches,
+                              double* total_ms, double* algo_bytes) {
+  if (!c || kind < 0 || kind >= PK_COUNT)
+    return fail(QOZ_EINVAL, "bad context or kind");
+  if (launches) *launches = c->prof_launches[kind];
+  if (total_ms) *total_ms = c->prof_ms[kind];
+  if (algo_bytes) *algo_bytes = c->prof_bytes[kind];
+  return QOZ_OK;
+}
+
+}  // extern "C"

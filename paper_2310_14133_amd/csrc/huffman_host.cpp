@@ -1,0 +1,129 @@
+/*
+ * Host side of the Huffman stage (the entropy coder named in Sec. VI-A):
+ * code lengths by the two-queue construction, canonical code values, and the
+ * decoder's lookup tables.
+ *
+ * Tie rules (shared by encoder and decoder so streams are reproducible):
+ * leaves are ordered by (count, symbol); when a leaf and a merged node have
+ * equal weight the leaf is taken first; a single used symbol gets length 1;
+ * canonical codes are assigned in (length, symbol) order.
+ */
+#include <algorithm>
+#include <cstring>
+
+#include "qoz_internal.h"
+
+namespace qoz {
+
+bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len) {
+  std::memset(len, 0, nsym);
+  std::vector<uint32_t> sym;
+  for (uint32_t s = 0; s < nsym; ++s)
+    if (hist[s]) sym.push_back(s);
+  const size_t n = sym.size();
+  if (n == 0) return true;
+  if (n == 1) {
+    len[sym[0]] = 1;
+    return true;
+  }
+  std::stable_sort(sym.begin(), sym.end(), [&](uint32_t a, uint32_t b) {
+    return hist[a] < hist[b];
+  });
+  /* nodes [0, n) are leaves in queue order, [n, 2n-1) merged nodes in
+   * creation order; up[] links each node to its parent */
+  std::vector<uint64_t> w(2 * n - 1);
+  std::vector<uint32_t> up(2 * n - 1, 0);
+  for (size_t i = 0; i < n; ++i) w[i] = hist[sym[i]];
+  size_t leaf = 0, merged = n, made = n;
+  for (; made < 2 * n - 1; ++made) {
+    size_t pick[2];
+    for (int t = 0; t < 2; ++t) {
+      bool use_leaf =
+          leaf < n && (merged >= made || w[leaf] <= w[merged]);
+      pick[t] = use_leaf ? leaf++ : merged++;
+    }
+    w[made] = w[pick[0]] + w[pick[1]];
+    up[pick[0]] = (uint32_t)made;
+    up[pick[1]] = (uint32_t)made;
+  }
+  /* depth of each node, root (last made) at 0, parents made after
+   * children so one backward pass suffices */
+  std::vector<uint8_t> depth(2 * n - 1, 0);
+  for (size_t v = 2 * n - 2; v-- > 0;) {
+    unsigned dp = depth[up[v]] + 1u;
+    if (dp > (unsigned)kMaxCodeLen) return false;
+    depth[v] = (uint8_t)dp;
+  }
+  for (size_t i = 0; i < n; ++i) len[sym[i]] = depth[i];
+  return true;
+}
+
+void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code) {
+  uint32_t count[kMaxCodeLen + 2] = {0};
+  for (uint32_t s = 0; s < nsym; ++s) count[len[s]]++;
+  count[0] = 0;
+  uint64_t next[kMaxCodeLen + 2] = {0};
+  uint64_t c = 0;
+  for (int l = 1; l <= kMaxCodeLen; ++l) {
+    c = (c + count[l - 1]) << 1;
+    next[l] = c;
+  }
+  /* with the DEFLATE rule the first code of length l is
+   * (first(l-1) + count(l-1)) << 1, starting from first(1) = 0 */
+  for (uint32_t s = 0; s < nsym; ++s) {
+    code[s] = 0;
+    if (len[s]) code[s] = next[len[s]]++;
+  }
+}
+
+uint64_t huffman_cost(const uint32_t* hist, uint32_t nsym) {
+  std::vector<uint8_t> len(nsym);
+  if (!huffman_lengths(hist, nsym, len.data())) return ~0ull;
+  uint64_t bits = 0;
+  for (uint32_t s = 0; s < nsym; ++s) bits += (uint64_t)hist[s] * len[s];
+  return bits;
+}
+
+bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
+                      uint32_t n_used, DecTables* t,
+                      std::vector<uint32_t>* sorted) {
+  std::memset(t, 0, sizeof(*t));
+  std::vector<uint8_t> len(kNSym, 0);
+  int prev = -1;
+  for (uint32_t i = 0; i < n_used; ++i) {
+    if ((int)syms[i] <= prev) return false;
+    if (lens[i] < 1 || lens[i] > kMaxCodeLen) return false;
+    prev = syms[i];
+    len[syms[i]] = lens[i];
+  }
+  /* Kraft sum must not exceed one */
+  unsigned __int128 kraft = 0;
+  for (uint32_t i = 0; i < n_used; ++i)
+    kraft += (unsigned __int128)1 << (kMaxCodeLen - lens[i]);
+  if (kraft > ((unsigned __int128)1 << kMaxCodeLen)) return false;
+  std::vector<uint64_t> code(kNSym);
+  canonical_codes(len.data(), kNSym, code.data());
+  sorted->clear();
+  for (int l = 1; l <= kMaxCodeLen; ++l) {
+    t->off[l] = (uint32_t)sorted->size();
+    for (uint32_t i = 0; i < n_used; ++i)
+      if (lens[i] == l) {
+        if (t->cnt[l] == 0) t->first[l] = code[syms[i]];
+        t->cnt[l]++;
+        sorted->push_back(syms[i]);
+      }
+    if (t->cnt[l]) t->maxlen = (uint32_t)l;
+  }
+  for (uint32_t i = 0; i < n_used; ++i) {
+    uint32_t l = lens[i];
+    if (l > (uint32_t)kLutBits) continue;
+    uint64_t c = code[syms[i]];
+    uint32_t base = (uint32_t)(c << (kLutBits - l));
+    uint32_t span = 1u << (kLutBits - l);
+    for (uint32_t k = 0; k < span; ++k)
+      t->lut[base + k] = ((uint32_t)syms[i] << 8) | l;
+  }
+  return true;
+}
+
+}  // namespace qoz

@@ -1,0 +1,411 @@
+/*
+ * Huffman stage over the quantization bins (Sec. VI-A names Huffman as the
+ * entropy coder of the pipeline), for gfx950.
+ *
+ *  - k_hist:       65536-bin histogram; a 4096-bin LDS window centred on
+ *                  the zero bin plus a per-lane counter for the zero bin
+ *                  itself absorb the concentrated traffic, the rest goes to
+ *                  global atomics.
+ *  - k_huff_len:   bits and unpredictable count per 4096-bin chunk.
+ *  - k_chunk_scan: exclusive scans -> chunk word offsets and unpredictable
+ *                  ranks (one workgroup).
+ *  - k_huff_encode: one workgroup per chunk packs its codes MSB-first into
+ *                  an LDS word buffer (ds_or), then stores the words
+ *                  coalesced; lanes holding bin 0 gather their exact value
+ *                  into the unpredictable list at their global rank.
+ *  - k_huff_decode: one lane per chunk, canonical decoding through a
+ *                  2^12-entry LDS table with a per-length fallback for
+ *                  longer codes; unpredictable bins are replaced by the
+ *                  complement of their rank so the inverse sweep can fetch
+ *                  the exact value directly.
+ */
+#include "qoz_device.h"
+#include "qoz_internal.h"
+
+namespace qoz {
+
+constexpr uint32_t kHistPerBlock = 1u << 16;
+constexpr uint32_t kHistThreads = 512;
+
+__global__ __launch_bounds__(kHistThreads) void k_hist(
+    const int32_t* __restrict__ codes, uint64_t n, uint32_t* hist) {
+  __shared__ uint32_t lh[kHistWin];
+  for (uint32_t i = threadIdx.x; i < kHistWin; i += blockDim.x) lh[i] = 0;
+  __syncthreads();
+  const uint64_t b0 = (uint64_t)blockIdx.x * kHistPerBlock;
+  const uint64_t b1 = b0 + kHistPerBlock < n ? b0 + kHistPerBlock : n;
+  uint32_t center = 0;
+  const uint64_t nvec = (b1 - b0) / 4;
+  const int4* v4 = reinterpret_cast<const int4*>(codes + b0);
+  for (uint64_t i = threadIdx.x; i < nvec; i += blockDim.x) {
+    int4 q = v4[i];
+    hist_add(lh, hist, q.x, center);
+    hist_add(lh, hist, q.y, center);
+    hist_add(lh, hist, q.z, center);
+    hist_add(lh, hist, q.w, center);
+  }
+  for (uint64_t i = b0 + nvec * 4 + threadIdx.x; i < b1; i += blockDim.x)
+    hist_add(lh, hist, codes[i], center);
+  center = wave_sum_u32(center);
+  if ((threadIdx.x & 63) == 0 && center)
+    atomicAdd(&lh[kRadius - kHistBase], center);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kHistWin; i += blockDim.x) {
+    uint32_t v = lh[i];
+    if (v) atomicAdd(&hist[kHistBase + (int32_t)i], v);
+  }
+}
+
+void launch_hist(const int32_t* codes, uint64_t n, uint32_t* hist,
+                 hipStream_t s) {
+  if (!n) return;
+  uint64_t blocks = (n + kHistPerBlock - 1) / kHistPerBlock;
+  hipLaunchKernelGGL(k_hist, dim3((uint32_t)blocks), dim3(kHistThreads), 0, s,
+                     codes, n, hist);
+}
+
+/* Code table: entry = (code << 8) | length for symbols in [lo, lo + tn);
+ * symbol 0 (unpredictable) has its own entry. */
+__device__ __forceinline__ uint64_t code_entry(const uint64_t* tab,
+                                               int32_t lo, uint32_t tn,
+                                               uint64_t zero_entry,
+                                               int32_t sym) {
+  if (sym == 0) return zero_entry;
+  uint32_t o = (uint32_t)(sym - lo);
+  return o < tn ? tab[o] : 0;
+}
+
+constexpr uint32_t kEncThreads = 256;
+constexpr uint32_t kEncPerThread = kChunk / kEncThreads; /* 16 */
+
+__device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v,
+                                                     uint32_t* sh) {
+  v = wave_sum_u32(v);
+  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  uint32_t r = 0;
+  if (threadIdx.x == 0)
+    for (uint32_t w = 0; w < blockDim.x / 64; ++w) r += sh[w];
+  return r;
+}
+
+__global__ __launch_bounds__(kEncThreads) void k_huff_len(
+    const int32_t* __restrict__ codes, uint64_t n,
+    const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
+    uint64_t zero_entry, uint32_t* chunk_bits, uint32_t* chunk_zeros) {
+  __shared__ uint32_t sh[2][kEncThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kChunk;
+  uint32_t bits = 0, zeros = 0;
+  for (uint32_t k = 0; k < kEncPerThread; ++k) {
+    uint64_t i = base + k * kEncThreads + threadIdx.x;
+    if (i < n) {
+      int32_t sym = codes[i];
+      bits += (uint32_t)(code_entry(tab, lo, tn, zero_entry, sym) & 0xff);
+      zeros += sym == 0;
+    }
+  }
+  uint32_t tb = block_reduce_u32(bits, sh[0]);
+  uint32_t tz = block_reduce_u32(zeros, sh[1]);
+  if (threadIdx.x == 0) {
+    chunk_bits[blockIdx.x] = tb;
+    chunk_zeros[blockIdx.x] = tz;
+  }
+}
+
+void launch_huff_len(const int32_t* codes, uint64_t n_codes,
+                     const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
+                     uint64_t zero_entry, uint32_t* chunk_bits,
+                     uint32_t* chunk_zeros, hipStream_t s) {
+  uint64_t chunks = (n_codes + kChunk - 1) / kChunk;
+  if (!chunks) return;
+  hipLaunchKernelGGL(k_huff_len, dim3((uint32_t)chunks), dim3(kEncThreads), 0,
+                     s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
+                     chunk_bits, chunk_zeros);
+}
+
+/* Exclusive scans over chunks (one workgroup of 1024 lanes, each owning a
+ * contiguous run of chunks). totals[0] = words, totals[1] = unpredictables. */
+constexpr uint32_t kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(
+    const uint32_t* __restrict__ bits, const uint32_t* __restrict__ zeros,
+    uint64_t n, uint64_t* coff, uint32_t* upre, uint64_t* totals) {
+  __shared__ uint64_t sw[kScanThreads], sz[kScanThreads];
+  const uint64_t per = (n + kScanThreads - 1) / kScanThreads;
+  const uint64_t a = threadIdx.x * per;
+  const uint64_t b = a + per < n ? a + per : n;
+  uint64_t w = 0, z = 0;
+  for (uint64_t i = a; i < b; ++i) {
+    w += (bits[i] + 31) / 32;
+    z += zeros[i];
+  }
+  sw[threadIdx.x] = w;
+  sz[threadIdx.x] = z;
+  __syncthreads();
+  /* inclusive Hillis-Steele scan over the 1024 partials */
+  for (uint32_t o = 1; o < kScanThreads; o <<= 1) {
+    uint64_t vw = threadIdx.x >= o ? sw[threadIdx.x - o] : 0;
+    uint64_t vz = threadIdx.x >= o ? sz[threadIdx.x - o] : 0;
+    __syncthreads();
+    sw[threadIdx.x] += vw;
+    sz[threadIdx.x] += vz;
+    __syncthreads();
+  }
+  uint64_t rw = threadIdx.x ? sw[threadIdx.x - 1] : 0;
+  uint64_t rz = threadIdx.x ? sz[threadIdx.x - 1] : 0;
+  for (uint64_t i = a; i < b; ++i) {
+    coff[i] = rw;
+    upre[i] = (uint32_t)rz;
+    rw += (bits[i] + 31) / 32;
+    rz += zeros[i];
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    coff[n] = sw[kScanThreads - 1];
+    upre[n] = (uint32_t)sz[kScanThreads - 1];
+    totals[0] = sw[kScanThreads - 1];
+    totals[1] = sz[kScanThreads - 1];
+  }
+}
+
+void launch_chunk_scan(const uint32_t* chunk_bits,
+                       const uint32_t* chunk_zeros, uint64_t n_chunks,
+                       uint64_t* coff, uint32_t* upre, uint64_t* totals,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, s,
+                     chunk_bits, chunk_zeros, n_chunks, coff, upre, totals);
+}
+
+/* Flat index of the point whose bin sits at stream position pos. */
+__device__ uint32_t point_of(const SweepTable& t, const Geo& g, uint64_t pos) {
+  uint32_t lo = 0, hi = t.n; /* find last sweep with off <= pos */
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (t.off[mid] <= pos) lo = mid;
+    else hi = mid;
+  }
+  uint64_t local = pos - t.off[lo];
+  uint32_t c2 = t.cnt[lo][2], c1 = t.cnt[lo][1];
+  uint32_t i2 = (uint32_t)(local % c2);
+  uint64_t r = local / c2;
+  uint32_t i1 = (uint32_t)(r % c1);
+  uint32_t i0 = (uint32_t)(r / c1);
+  uint32_t p0 = t.start[lo][0] + i0 * t.step[lo][0];
+  uint32_t p1 = t.start[lo][1] + i1 * t.step[lo][1];
+  uint32_t p2 = t.start[lo][2] + i2 * t.step[lo][2];
+  return p0 * g.st[0] + p1 * g.st[1] + p2;
+}
+
+constexpr uint32_t kEncMaxWords = kChunk * kMaxCodeLen / 32 + 2;
+
+__device__ __forceinline__ void put_bits(uint32_t* words, uint32_t pos,
+                                         uint64_t code, uint32_t len) {
+  /* MSB-first: bit q of the chunk is bit (31 - q % 32) of word q / 32 */
+  while (len) {
+    uint32_t o = pos & 31;
+    uint32_t take = 32 - o < len ? 32 - o : len;
+    uint32_t part = (uint32_t)((code >> (len - take)) &
+                               ((take == 32) ? 0xffffffffull
+                                             : ((1ull << take) - 1)));
+    atomicOr(&words[pos >> 5], part << (32 - o - take));
+    pos += take;
+    len -= take;
+  }
+}
+
+__global__ __launch_bounds__(kEncThreads) void k_huff_encode(
+    const int32_t* __restrict__ codes, uint64_t n,
+    const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
+    uint64_t zero_entry, const uint64_t* __restrict__ coff,
+    const uint32_t* __restrict__ upre, uint32_t* payload, uint64_t cap_words,
+    float* unpred, const float* __restrict__ x, Geo g, SweepTable st,
+    uint32_t* status) {
+  __shared__ uint32_t words[kEncMaxWords];
+  __shared__ uint32_t sbits[kEncThreads], szero[kEncThreads];
+  const uint32_t c = blockIdx.x;
+  const uint64_t w0 = coff[c];
+  const uint32_t nw = (uint32_t)(coff[c + 1] - w0);
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) words[i] = 0;
+  const uint64_t first = (uint64_t)c * kChunk + threadIdx.x * kEncPerThread;
+  int32_t sym[kEncPerThread];
+  uint64_t ent[kEncPerThread];
+  uint32_t bits = 0, zeros = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kEncPerThread; ++k) {
+    uint64_t i = first + k;
+    sym[k] = i < n ? codes[i] : -1;
+    ent[k] = sym[k] >= 0 ? code_entry(tab, lo, tn, zero_entry, sym[k]) : 0;
+    bits += (uint32_t)(ent[k] & 0xff);
+    zeros += sym[k] == 0;
+  }
+  sbits[threadIdx.x] = bits;
+  szero[threadIdx.x] = zeros;
+  __syncthreads();
+  for (uint32_t o = 1; o < kEncThreads; o <<= 1) {
+    uint32_t vb = threadIdx.x >= o ? sbits[threadIdx.x - o] : 0;
+    uint32_t vz = threadIdx.x >= o ? szero[threadIdx.x - o] : 0;
+    __syncthreads();
+    sbits[threadIdx.x] += vb;
+    szero[threadIdx.x] += vz;
+    __syncthreads();
+  }
+  uint32_t pos = sbits[threadIdx.x] - bits;
+  uint32_t zr = upre[c] + szero[threadIdx.x] - zeros;
+#pragma unroll
+  for (uint32_t k = 0; k < kEncPerThread; ++k) {
+    uint32_t len = (uint32_t)(ent[k] & 0xff);
+    if (len) put_bits(words, pos, ent[k] >> 8, len);
+    pos += len;
+    if (sym[k] == 0) {
+      unpred[zr] = x[point_of(st, g, first + k)];
+      ++zr;
+    }
+  }
+  __syncthreads();
+  bool over = false;
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+    if (w0 + i < cap_words)
+      payload[w0 + i] = words[i];
+    else
+      over = true;
+  }
+  if (over) atomicOr(status, kStOverflow);
+}
+
+void launch_huff_encode(const int32_t* codes, uint64_t n_codes,
+                        const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
+                        uint64_t zero_entry, const uint64_t* coff,
+                        const uint32_t* upre, uint32_t* payload,
+                        uint64_t payload_cap_words, float* unpred,
+                        const float* x, const Geo& g, const SweepTable& st,
+                        uint32_t* status, hipStream_t s) {
+  uint64_t chunks = (n_codes + kChunk - 1) / kChunk;
+  if (!chunks) return;
+  hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)chunks), dim3(kEncThreads),
+                     0, s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
+                     coff, upre, payload, payload_cap_words, unpred, x, g, st,
+                     status);
+}
+
+/* ---- decoding -------------------------------------------------------- */
+
+constexpr uint32_t kDecThreads = 64;
+
+/* The `len` (1..63) bits starting at bit `pos` (MSB-first) of words
+ * [0, nw); bits past the end read as zero. */
+__device__ __forceinline__ uint64_t peek_abs(const uint32_t* w, uint64_t nw,
+                                             uint64_t pos, uint32_t len) {
+  const uint64_t wi = pos >> 5;
+  const uint32_t o = (uint32_t)(pos & 31);
+  const uint64_t a = wi < nw ? w[wi] : 0;
+  const uint64_t b = wi + 1 < nw ? w[wi + 1] : 0;
+  const uint64_t c = wi + 2 < nw ? w[wi + 2] : 0;
+  const uint64_t window = (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
+  return window >> (64 - len);
+}
+
+__global__ __launch_bounds__(kDecThreads) void k_huff_decode(
+    const uint32_t* __restrict__ payload, uint64_t n_words,
+    const uint64_t* __restrict__ coff, const uint32_t* __restrict__ upre,
+    uint64_t n_chunks, uint64_t n_codes, uint64_t n_unpred,
+    const DecTables* __restrict__ tabs, const uint32_t* __restrict__ syms,
+    int32_t* __restrict__ codes, uint32_t* status) {
+  __shared__ uint32_t lut[1u << kLutBits];
+  __shared__ uint64_t first[kMaxCodeLen + 1];
+  __shared__ uint32_t cnt[kMaxCodeLen + 1], off[kMaxCodeLen + 1];
+  for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += blockDim.x)
+    lut[i] = tabs->lut[i];
+  for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxCodeLen; i += blockDim.x) {
+    first[i] = tabs->first[i];
+    cnt[i] = tabs->cnt[i];
+    off[i] = tabs->off[i];
+  }
+  const uint32_t maxlen = tabs->maxlen;
+  __syncthreads();
+  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_chunks) return;
+  const uint64_t w0 = coff[c], w1 = coff[c + 1];
+  const uint32_t u0 = upre[c], u1 = upre[c + 1];
+  if (w0 > w1 || w1 > n_words || (c == 0 && w0 != 0) || u0 > u1 ||
+      u1 > n_unpred || (c + 1 == n_chunks && (w1 != n_words || u1 != n_unpred))) {
+    atomicOr(status, kStBadStream);
+    return;
+  }
+  const uint32_t* w = payload + w0;
+  const uint64_t nw = w1 - w0;
+  const uint64_t avail = nw * 32;
+  const uint64_t lo = c * kChunk;
+  const uint64_t hi = lo + kChunk < n_codes ? lo + kChunk : n_codes;
+  uint64_t buf = 0;   /* next bits, MSB-aligned */
+  int nb = 0;         /* valid bits in buf */
+  uint64_t wp = 0;    /* next word to load */
+  uint64_t used = 0;  /* bits consumed */
+  uint32_t z = 0;
+  bool bad = false;
+  for (uint64_t i = lo; i < hi; ++i) {
+    while (nb <= 32 && wp < nw) {
+      buf |= (uint64_t)w[wp++] << (32 - nb);
+      nb += 32;
+    }
+    uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+    uint32_t len = e & 0xff, sym;
+    if (len) {
+      sym = e >> 8;
+    } else {
+      sym = 0xffffffffu;
+      for (uint32_t L = kLutBits + 1; L <= maxlen; ++L) {
+        uint64_t v = (int)L <= nb ? buf >> (64 - L)
+                                  : peek_abs(w, nw, used, L);
+        if (cnt[L] && v - first[L] < cnt[L]) {
+          sym = syms[off[L] + (uint32_t)(v - first[L])];
+          len = L;
+          break;
+        }
+      }
+      if (sym == 0xffffffffu) {
+        bad = true;
+        break;
+      }
+    }
+    used += len;
+    if ((int)len <= nb) {
+      buf <<= len;
+      nb -= (int)len;
+    } else { /* re-seat the window after a code longer than the buffer */
+      wp = used >> 5;
+      uint32_t o = (uint32_t)(used & 31);
+      buf = 0;
+      nb = 0;
+      if (wp < nw) {
+        buf = ((uint64_t)w[wp] << 32) << o;
+        nb = 32 - (int)o;
+        ++wp;
+      }
+    }
+    int32_t out;
+    if (sym == 0) {
+      uint32_t rank = u0 + z;
+      ++z;
+      out = (int32_t)~rank;
+    } else {
+      out = (int32_t)sym;
+    }
+    codes[i] = out;
+  }
+  if (bad || used > avail || z != u1 - u0) atomicOr(status, kStBadStream);
+}
+
+void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
+                        const uint64_t* coff, const uint32_t* upre,
+                        uint64_t n_chunks, uint64_t n_codes,
+                        uint64_t n_unpred, const DecTables* tabs,
+                        const uint32_t* syms, int32_t* codes,
+                        uint32_t* status, hipStream_t s) {
+  if (!n_chunks) return;
+  uint64_t blocks = (n_chunks + kDecThreads - 1) / kDecThreads;
+  hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecThreads),
+                     0, s, payload, n_words, coff, upre, n_chunks, n_codes,
+                     n_unpred, tabs, syms, codes, status);
+}
+
+}  // namespace qoz

@@ -1,0 +1,284 @@
+/*
+ * Internal declarations of the QoZ GPU library (gfx950).  Not part of the
+ * public ABI.
+ *
+ * Geometry convention: every field is handled as a 3D grid (n0, n1, n2)
+ * with n2 contiguous; a 2D field (a, b) becomes (1, a, b) and its dimension
+ * order is shifted by one (real dimension m -> grid dimension m + 1).
+ */
+#ifndef QOZ_INTERNAL_H
+#define QOZ_INTERNAL_H
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qoz.h"
+
+namespace qoz {
+
+constexpr int32_t kRadius = 32768;         /* bins on each side of zero */
+constexpr uint32_t kNSym = 2 * kRadius;    /* Huffman alphabet */
+constexpr uint32_t kChunk = 4096;          /* bins per Huffman chunk */
+constexpr size_t kHeaderBytes = 184;
+constexpr int kLutBits = 12;               /* decoder fast-table width */
+constexpr int kMaxCodeLen = 63;
+
+/* status word bits reported by kernels */
+constexpr uint32_t kStNonFinite = 1u;
+constexpr uint32_t kStBadStream = 2u;
+constexpr uint32_t kStOverflow = 4u;
+
+struct Geo {
+  uint32_t n[3];  /* grid extents */
+  uint32_t st[3]; /* element strides: st[2] = 1 */
+};
+
+/* One (level, dimension) sweep: its target sub-grid and quantizer. */
+struct Sweep {
+  uint32_t start[3], step[3], cnt[3];
+  uint32_t k;      /* grid dimension interpolated along */
+  uint32_t h;      /* 2^(l-1) */
+  uint32_t cubic;  /* 0 linear, 1 cubic */
+  uint32_t level;
+  uint64_t code_off; /* position of the first target's bin in the stream */
+  uint64_t count;    /* targets */
+  float twoeb, inv;  /* FP32 bin width 2 e_l and its reciprocal */
+  double eb;         /* e_l */
+};
+
+/* Complete plan of one compression / decompression. */
+struct Plan {
+  Geo g;
+  int d = 0;           /* real dimensionality */
+  uint32_t s = 0, L = 0;
+  double e = 0, alpha = 1, beta = 1;
+  uint8_t interp[QOZ_MAX_LEVELS];
+  uint8_t order[QOZ_MAX_LEVELS][3]; /* real dimensions */
+  uint32_t na[3];      /* anchors per grid dimension */
+  uint64_t n_anchor = 0, n_codes = 0, n_chunks = 0;
+  std::vector<Sweep> sweeps;
+};
+
+/* Byte offsets of the stream sections (see the stream layout notes). */
+struct Layout {
+  uint64_t anchors, syms, lens, coff, upre, unpred, payload, total;
+};
+
+/* Sweep table used by kernels that map a stream position back to a point. */
+struct SweepTable {
+  uint32_t n;
+  uint64_t off[3 * QOZ_MAX_LEVELS + 1];
+  uint32_t start[3 * QOZ_MAX_LEVELS][3];
+  uint32_t step[3 * QOZ_MAX_LEVELS][3];
+  uint32_t cnt[3 * QOZ_MAX_LEVELS][3];
+};
+
+/* Canonical-Huffman decoding tables (device copy). */
+struct DecTables {
+  uint32_t lut[1u << kLutBits]; /* (symbol << 8) | length, 0 = long code */
+  uint64_t first[kMaxCodeLen + 1];
+  uint32_t cnt[kMaxCodeLen + 1];
+  uint32_t off[kMaxCodeLen + 1];
+  uint32_t maxlen;
+};
+
+/* Tuner: one level of a candidate parameter set on the sampled blocks. */
+struct TrialLevel {
+  float twoeb, inv;
+  double eb;
+  uint32_t cubic;
+  uint32_t order[3]; /* grid dimensions */
+};
+struct TrialDesc {
+  TrialLevel lv[QOZ_MAX_LEVELS];
+};
+
+/* Profiling kinds */
+enum ProfKind {
+  PK_CHECK = 0,
+  PK_ANCHOR,
+  PK_SWEEP_COMP_L1,
+  PK_SWEEP_COMP,
+  PK_HIST,
+  PK_HUFF_LEN,
+  PK_HUFF_ENC,
+  PK_HUFF_DEC,
+  PK_SWEEP_DEC_L1,
+  PK_SWEEP_DEC,
+  PK_TUNE_GATHER,
+  PK_TUNE_ALG1,
+  PK_TUNE_TRIAL,
+  PK_SSIM,
+  PK_REDUCE,
+  PK_COUNT
+};
+
+/* Growable device buffer. */
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct PendingEvent {
+  int kind;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace qoz
+
+struct qoz_ctx {
+  int device = 0;
+  /* scratch */
+  qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
+      enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
+      tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part;
+  /* pinned host staging */
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  /* instrumentation */
+  bool timing = false;
+  std::vector<qoz::PendingEvent> pending;
+  std::vector<hipEvent_t> event_pool;
+  uint64_t prof_launches[qoz::PK_COUNT] = {0};
+  double prof_ms[qoz::PK_COUNT] = {0};
+  double prof_bytes[qoz::PK_COUNT] = {0};
+};
+
+namespace qoz {
+
+/* ---- errors --------------------------------------------------------- */
+qoz_status fail(qoz_status st, const std::string& msg);
+qoz_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+#define QOZ_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return qoz::hip_fail(e_, #call); \
+  } while (0)
+#define QOZ_TRY(expr)                     \
+  do {                                    \
+    qoz_status s_ = (expr);               \
+    if (s_ != QOZ_OK) return s_;          \
+  } while (0)
+
+/* ---- context helpers ------------------------------------------------- */
+qoz_status ensure(DevBuf& b, size_t bytes);
+qoz_status ensure_pinned(qoz_ctx* c, size_t bytes);
+/* Instrumented launch bracket: call prof_begin before and prof_end after a
+ * launch; resolved by prof_collect after the stream is synchronised. */
+hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s);
+void prof_end(qoz_ctx* c, hipStream_t s, hipEvent_t a, int kind,
+              double bytes);
+void prof_collect(qoz_ctx* c);
+qoz_status set_device(qoz_ctx* c);
+
+/* ---- host planning (plan.cpp) --------------------------------------- */
+bool shape_ok(const qoz_shape& sh, int* d, uint64_t n[3]);
+Geo make_geo(int d, const uint64_t* n);
+bool params_ok(const qoz_params& p, int d, uint32_t* L);
+void level_bounds(double e, double alpha, double beta, uint32_t L,
+                  double* eb, float* twoeb, float* inv);
+qoz_status make_plan(const qoz_shape& sh, double e, const qoz_params& p,
+                     Plan* plan);
+/* target sub-grid of sweep j of level l over geometry g (grid dims) */
+void sweep_grid(const Geo& g, const uint32_t* order_grid, int d, int j,
+                uint32_t h, uint32_t* start, uint32_t* step, uint32_t* cnt);
+Layout layout_of(uint64_t n_anchor, uint64_t n_used, uint64_t n_chunks,
+                 uint64_t n_unpred, uint64_t n_words);
+void write_header(uint8_t* h, const Plan& p, uint64_t n_unpred,
+                  uint64_t n_used, uint64_t n_words);
+qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* plan,
+                        uint64_t* n_unpred, uint64_t* n_used,
+                        uint64_t* n_words);
+void fill_sweep_table(const Plan& p, SweepTable* t);
+
+/* ---- Huffman (host side, huffman_host.cpp) ---------------------------- */
+bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
+void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code);
+bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
+                      uint32_t n_used, DecTables* t,
+                      std::vector<uint32_t>* sorted_syms);
+uint64_t huffman_cost(const uint32_t* hist, uint32_t nsym);
+
+/* ---- launchers (kernels_*.hip) -------------------------------------- */
+void launch_init_status(uint32_t* status, hipStream_t s);
+void launch_anchor_copy(const Geo& g, uint32_t stride, const uint32_t na[3],
+                        const float* x, float* W, float* out, uint32_t* status,
+                        hipStream_t s);
+void launch_anchor_scatter(const Geo& g, uint32_t stride, const uint32_t na[3],
+                           const float* in, float* W, hipStream_t s);
+void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
+                       float* W, int32_t* codes, bool write_w,
+                       uint32_t* status, hipStream_t s);
+void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
+                         const int32_t* codes, const float* unpred,
+                         uint64_t n_unpred, uint32_t* status, hipStream_t s);
+void launch_hist(const int32_t* codes, uint64_t n, uint32_t* hist,
+                 hipStream_t s);
+void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
+void launch_huff_len(const int32_t* codes, uint64_t n_codes,
+                     const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
+                     uint64_t zero_entry, uint32_t* chunk_bits,
+                     uint32_t* chunk_zeros, hipStream_t s);
+void launch_chunk_scan(const uint32_t* chunk_bits,
+                       const uint32_t* chunk_zeros, uint64_t n_chunks,
+                       uint64_t* coff, uint32_t* upre, uint64_t* totals,
+                       hipStream_t s);
+void launch_huff_encode(const int32_t* codes, uint64_t n_codes,
+                        const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
+                        uint64_t zero_entry, const uint64_t* coff,
+                        const uint32_t* upre, uint32_t* payload,
+                        uint64_t payload_cap_words, float* unpred,
+                        const float* x, const Geo& g, const SweepTable& st,
+                        uint32_t* status, hipStream_t s);
+void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
+                        const uint64_t* coff, const uint32_t* upre,
+                        uint64_t n_chunks, uint64_t n_codes,
+                        uint64_t n_unpred, const DecTables* tabs,
+                        const uint32_t* syms, int32_t* codes,
+                        uint32_t* status, hipStream_t s);
+void launch_range(const float* x, uint64_t n, float* part_min,
+                  float* part_max, uint32_t* status, uint32_t nparts,
+                  hipStream_t s);
+uint32_t range_parts(uint64_t n);
+void launch_sse_max(const float* x, const float* y, uint64_t n,
+                    double* part_sse, double* part_max, uint32_t nparts,
+                    hipStream_t s);
+uint32_t sse_parts(uint64_t n);
+/* SSIM sums over a batch of equally shaped fields */
+struct SsimJob {
+  uint32_t P, Rn, Cn;  /* field extents (2D: P = 1) */
+  uint32_t wp, wr, wc; /* window extents */
+  uint64_t field_stride; /* elements between batch items */
+  uint32_t batch;        /* items; y item i is compared with x item i % x_mod */
+  uint32_t x_mod;
+  double c1, c2;
+};
+uint64_t ssim_parts(const SsimJob& j);
+void launch_ssim(const SsimJob& j, const float* x, const float* y,
+                 double* parts, hipStream_t s);
+
+/* tuner kernels (kernels_tune.hip) */
+struct BlockGeo {
+  Geo g;             /* block grid */
+  uint32_t size;     /* points per block */
+  uint32_t nb;       /* blocks */
+  uint32_t Lt;
+  uint32_t d;
+};
+void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
+                          const uint32_t* origins_dev, float* xs,
+                          hipStream_t s);
+void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
+                       const float* wc, float* wt, uint32_t ncand,
+                       const TrialDesc* cand_desc, double* l1_part,
+                       hipStream_t s);
+void launch_trial(const BlockGeo& bg, const float* xs, float* wt,
+                  uint32_t ntrial, const TrialDesc* desc, uint32_t* hist,
+                  double* sse_part, uint32_t* unpred_part, hipStream_t s);
+
+}  // namespace qoz
+#endif

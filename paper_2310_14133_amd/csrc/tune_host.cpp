@@ -1,0 +1,427 @@
+/*
+ * Online tuner (Sec. VI): uniform block sampling (Sec. VI-A), level-adapted
+ * interpolator selection (Algorithm 1, Sec. VI-B) and the (alpha, beta)
+ * search with the rate-quality comparison of Table I (Sec. VI-C).
+ *
+ * GPU work per tuning: one gather of the sampled blocks, one launch per
+ * level of Algorithm 1 covering every (candidate, block) pair, and a single
+ * launch covering every distinct (alpha, beta, e') trial on every block.
+ * The decisions (argmin, Table I) are taken on the host from per-block
+ * partial sums read back after each launch.
+ *
+ * Choices where the paper is open: blocks of b+1 points per dimension at
+ * origins k*S, S = round(b r^(-1/d)), their 2^Lt grid exact; the whole field
+ * as one block when none fits; Algorithm 1 at bound e on every level over
+ * committed higher levels, L1 of the prediction before quantization, first
+ * strict minimum; bit rate = (Huffman bits of the aggregated bins + 32 per
+ * unpredictable value) / points in the blocks; Table I with the incumbent
+ * starting at the first pair, pairs in order alpha-major, case 3 re-run at
+ * 0.8e and case 4 at 1.2e (as the table states), ties and degenerate lines
+ * keep the incumbent; ratio mode compares bit rates only.
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "qoz_internal.h"
+
+namespace qoz {
+
+static const double kAlpha[5] = {1.0, 1.25, 1.5, 1.75, 2.0};
+static const double kBeta[4] = {1.5, 2.0, 3.0, 4.0};
+constexpr size_t kPinTune = 2u << 20;
+
+static int table1_case(double BI, double MI, double BII, double MII) {
+  if (BI <= BII && MI >= MII) return 1;
+  if (BI >= BII && MI <= MII) return 2;
+  if (BI > BII && MI > MII) return 3;
+  return 4;
+}
+
+/* II wins when (B_I, M_I) lies strictly below the line through II's two
+ * results; a vertical line keeps I. */
+static bool table1_line_prefers_II(double BI, double MI, double BII,
+                                   double MII, double BIIp, double MIIp) {
+  if (BIIp == BII) return false;
+  double rise = (MIIp - MII) * (BI - BII);
+  double Mline = MII + rise / (BIIp - BII);
+  return MI < Mline;
+}
+
+struct Cand {
+  uint8_t interp;
+  uint8_t order[3]; /* real dimensions */
+};
+
+static uint32_t log2_floor(uint32_t v) {
+  uint32_t l = 0;
+  while ((2u << l) <= v) ++l;
+  return l;
+}
+
+}  // namespace qoz
+
+using namespace qoz;
+
+extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
+                               double e, qoz_target target,
+                               const qoz_tune_config* cfg, qoz_params* out,
+                               hipStream_t s) {
+  clear_error();
+  if (!c || !d_x || !out) return fail(QOZ_EINVAL, "NULL argument");
+  if (target < QOZ_TARGET_CR || target > QOZ_TARGET_SSIM)
+    return fail(QOZ_EINVAL, "bad target");
+  if (!(e > 0.0) || !std::isfinite(e))
+    return fail(QOZ_EINVAL, "error bound must be finite and > 0");
+  int d;
+  uint64_t n[3] = {1, 1, 1};
+  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  QOZ_TRY(set_device(c));
+  const Geo g = make_geo(d, n);
+  const uint64_t N = (uint64_t)g.n[0] * g.n[1] * g.n[2];
+  const uint32_t sa = out->anchor_stride ? out->anchor_stride
+                                         : (d == 2 ? 64u : 32u);
+  if (sa < 2 || (sa & (sa - 1))) return fail(QOZ_EINVAL, "bad anchor stride");
+  const uint32_t L = log2_floor(sa);
+  if (L > QOZ_MAX_LEVELS) return fail(QOZ_EINVAL, "anchor stride too large");
+
+  /* sampling plan (Sec. VI-A) */
+  const uint32_t b = (cfg && cfg->block) ? cfg->block : (d == 2 ? 64u : 16u);
+  if (b < 2 || (b & (b - 1))) return fail(QOZ_EINVAL, "bad block size");
+  const double r = (cfg && cfg->sample_rate > 0.0) ? cfg->sample_rate
+                                                   : (d == 2 ? 0.01 : 0.005);
+  if (!(r > 0.0 && r <= 1.0)) return fail(QOZ_EINVAL, "bad sample rate");
+  uint32_t S = (cfg && cfg->sample_stride)
+                   ? cfg->sample_stride
+                   : (uint32_t)std::llround((double)b * std::pow(r, -1.0 / d));
+  if (S < 1) S = 1;
+  const uint32_t Lt = log2_floor(b < sa ? b : sa);
+  const bool all_orders = cfg && cfg->all_orders;
+  const uint32_t w = (cfg && cfg->ssim_window) ? cfg->ssim_window : 7;
+  if (w > 11) return fail(QOZ_EINVAL, "ssim_window must be <= 11");
+  uint64_t m[3] = {1, 1, 1};
+  bool whole = false;
+  for (int i = 0; i < d; ++i) {
+    m[i] = 0;
+    while (m[i] * S + b <= n[i] - 1) ++m[i];
+    whole |= m[i] == 0;
+  }
+  uint64_t bd[3];
+  for (int i = 0; i < d; ++i) bd[i] = whole ? n[i] : (uint64_t)b + 1;
+  if (whole)
+    for (int i = 0; i < 3; ++i) m[i] = 1;
+  BlockGeo bg;
+  bg.g = make_geo(d, bd);
+  bg.size = bg.g.n[0] * bg.g.n[1] * bg.g.n[2];
+  bg.nb = (uint32_t)(m[0] * m[1] * (d == 3 ? m[2] : 1));
+  bg.Lt = Lt;
+  bg.d = (uint32_t)d;
+  std::vector<uint32_t> origins;
+  for (uint64_t k0 = 0; k0 < m[0]; ++k0)
+    for (uint64_t k1 = 0; k1 < m[1]; ++k1)
+      for (uint64_t k2 = 0; k2 < (d == 3 ? m[2] : 1); ++k2) {
+        uint32_t o[3] = {(uint32_t)(k0 * S), (uint32_t)(k1 * S),
+                         (uint32_t)(k2 * S)};
+        if (whole) o[0] = o[1] = o[2] = 0;
+        if (d == 2) {
+          origins.push_back(0);
+          origins.push_back(o[0]);
+          origins.push_back(o[1]);
+        } else {
+          origins.insert(origins.end(), o, o + 3);
+        }
+      }
+
+  /* candidates (Sec. V-B, VI-B): interpolation type outer, order inner */
+  std::vector<Cand> cands;
+  {
+    std::vector<std::vector<uint8_t>> orders;
+    std::vector<uint8_t> p(d);
+    for (int i = 0; i < d; ++i) p[i] = (uint8_t)i;
+    if (all_orders) {
+      do orders.push_back(p);
+      while (std::next_permutation(p.begin(), p.end()));
+    } else {
+      orders.push_back(p);
+      std::reverse(p.begin(), p.end());
+      orders.push_back(p);
+    }
+    for (uint8_t t = 0; t < 2; ++t)
+      for (auto& o : orders) {
+        Cand cd;
+        cd.interp = t;
+        for (int i = 0; i < 3; ++i) cd.order[i] = i < d ? o[i] : 0;
+        cands.push_back(cd);
+      }
+  }
+  const uint32_t ncand = (uint32_t)cands.size();
+  const uint32_t shift = d == 2 ? 1 : 0;
+  const uint32_t max_trials = 60;
+  const uint32_t nslots = std::max(ncand, max_trials);
+
+  /* scratch */
+  const uint64_t bsz = (uint64_t)bg.nb * bg.size;
+  const uint32_t rp = range_parts(N);
+  QOZ_TRY(ensure(c->status, 256));
+  QOZ_TRY(ensure(c->partial, 8 * (size_t)rp + 16 * (size_t)bg.nb + 64));
+  QOZ_TRY(ensure(c->tune_x, 4 * bsz));
+  QOZ_TRY(ensure(c->tune_wc, 4 * bsz));
+  QOZ_TRY(ensure(c->tune_wt, 4 * bsz * nslots));
+  QOZ_TRY(ensure(c->tune_desc, sizeof(TrialDesc) * nslots));
+  QOZ_TRY(ensure(c->tune_l1, 8 * (size_t)nslots * bg.nb));
+  QOZ_TRY(ensure(c->tune_stats, 12 * (size_t)nslots * bg.nb));
+  QOZ_TRY(ensure(c->tune_hist, 4 * (size_t)kNSym * max_trials));
+  SsimJob sj;
+  std::memset(&sj, 0, sizeof(sj));
+  uint64_t ssim_np = 0;
+  if (target == QOZ_TARGET_SSIM) {
+    sj.P = bg.g.n[0];
+    sj.Rn = bg.g.n[1];
+    sj.Cn = bg.g.n[2];
+    sj.wp = std::min(sj.P, w);
+    sj.wr = std::min(sj.Rn, w);
+    sj.wc = std::min(sj.Cn, w);
+    sj.field_stride = bg.size;
+    sj.batch = max_trials * bg.nb;
+    sj.x_mod = bg.nb;
+    ssim_np = ssim_parts(sj);
+    QOZ_TRY(ensure(c->ssim_part, 8 * ssim_np));
+  }
+  const size_t pin_need = kPinTune + 4 * (size_t)kNSym * max_trials +
+                          12 * (size_t)nslots * bg.nb +
+                          8 * (size_t)nslots * bg.nb + 8 * ssim_np +
+                          sizeof(TrialDesc) * nslots + 8 * rp +
+                          12 * (size_t)bg.nb + 4096;
+  QOZ_TRY(ensure_pinned(c, pin_need));
+  uint8_t* pbase = (uint8_t*)c->pinned + kPinTune;
+  uint32_t* h_hist = (uint32_t*)pbase;
+  double* h_sse = (double*)(pbase + 4 * (size_t)kNSym * max_trials);
+  uint32_t* h_un = (uint32_t*)(h_sse + (size_t)nslots * bg.nb);
+  double* h_l1 = (double*)(pbase + 4 * (size_t)kNSym * max_trials +
+                           12 * (size_t)nslots * bg.nb);
+  double* h_ssim = h_l1 + (size_t)nslots * bg.nb;
+  TrialDesc* h_desc = (TrialDesc*)(h_ssim + ssim_np);
+  float* h_range = (float*)(h_desc + nslots);
+  uint32_t* h_status = (uint32_t*)(h_range + 2 * rp);
+
+  float* xs = (float*)c->tune_x.p;
+  float* wc = (float*)c->tune_wc.p;
+  float* wt = (float*)c->tune_wt.p;
+  TrialDesc* ddesc = (TrialDesc*)c->tune_desc.p;
+  double* dl1 = (double*)c->tune_l1.p;
+  double* dsse = (double*)c->tune_stats.p;
+  uint32_t* dun = (uint32_t*)(dsse + (size_t)nslots * bg.nb);
+  uint32_t* dhist = (uint32_t*)c->tune_hist.p;
+  uint32_t* st = (uint32_t*)c->status.p;
+  float* pmin = (float*)c->partial.p;
+  float* pmax = pmin + rp;
+  uint32_t* dorig = (uint32_t*)(pmax + rp);
+
+  /* value range and finiteness of the whole field */
+  launch_init_status(st, s);
+  {
+    hipEvent_t ev = prof_begin(c, s);
+    launch_range(d_x, N, pmin, pmax, st, rp, s);
+    prof_end(c, s, ev, PK_CHECK, 4.0 * N);
+  }
+  QOZ_HIP(hipMemcpyAsync(h_range, pmin, 8 * (size_t)rp,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_HIP(hipMemcpyAsync(h_status, st, 16, hipMemcpyDeviceToHost, s));
+  std::memcpy(h_status + 8, origins.data(), 4 * origins.size());
+  QOZ_HIP(hipMemcpyAsync(dorig, h_status + 8, 4 * origins.size(),
+                         hipMemcpyHostToDevice, s));
+  {
+    hipEvent_t ev = prof_begin(c, s);
+    launch_gather_blocks(d_x, g, bg, dorig, xs, s);
+    prof_end(c, s, ev, PK_TUNE_GATHER, 8.0 * bsz);
+  }
+  QOZ_HIP(hipMemcpyAsync(wc, xs, 4 * bsz, hipMemcpyDeviceToDevice, s));
+  QOZ_HIP(hipGetLastError());
+  QOZ_HIP(hipStreamSynchronize(s));
+  if (h_status[0] & kStNonFinite) {
+    prof_collect(c);
+    return fail(QOZ_EINVAL, "input contains NaN or Inf");
+  }
+  float lo = h_range[0], hi = h_range[rp];
+  for (uint32_t i = 1; i < rp; ++i) {
+    lo = std::fmin(lo, h_range[i]);
+    hi = std::fmax(hi, h_range[rp + i]);
+  }
+  const double vrange = (double)hi - (double)lo;
+
+  /* ---- Algorithm 1 ---- */
+  uint8_t Is_interp[QOZ_MAX_LEVELS] = {0};
+  uint8_t Is_order[QOZ_MAX_LEVELS][3];
+  for (int l = 0; l < QOZ_MAX_LEVELS; ++l)
+    for (int j = 0; j < 3; ++j) Is_order[l][j] = (uint8_t)(j < d ? j : 0);
+  double ueb[QOZ_MAX_LEVELS];
+  float utw[QOZ_MAX_LEVELS], uiv[QOZ_MAX_LEVELS];
+  level_bounds(e, 1.0, 1.0, Lt, ueb, utw, uiv);
+  for (uint32_t l = Lt; l >= 1; --l) {
+    std::memset(h_desc, 0, sizeof(TrialDesc) * ncand);
+    for (uint32_t ci = 0; ci < ncand; ++ci) {
+      TrialLevel& lv = h_desc[ci].lv[l - 1];
+      lv.twoeb = utw[l - 1];
+      lv.inv = uiv[l - 1];
+      lv.eb = ueb[l - 1];
+      lv.cubic = cands[ci].interp;
+      for (int j = 0; j < 3; ++j)
+        lv.order[j] = j < d ? cands[ci].order[j] + shift : 0;
+    }
+    QOZ_HIP(hipMemcpyAsync(ddesc, h_desc, sizeof(TrialDesc) * ncand,
+                           hipMemcpyHostToDevice, s));
+    {
+      hipEvent_t ev = prof_begin(c, s);
+      launch_alg1_level(bg, l, xs, wc, wt, ncand, ddesc, dl1, s);
+      prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
+    }
+    QOZ_HIP(hipMemcpyAsync(h_l1, dl1, 8 * (size_t)ncand * bg.nb,
+                           hipMemcpyDeviceToHost, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    /* level-l targets: points of the 2^(l-1) grid off the 2^l grid */
+    uint64_t on_fine = 1, on_coarse = 1;
+    for (int i = 0; i < 3; ++i) {
+      on_fine *= (bg.g.n[i] - 1) / (1u << (l - 1)) + 1;
+      on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
+    }
+    const double count = (double)(on_fine - on_coarse) * bg.nb;
+    double best = std::numeric_limits<double>::infinity();
+    uint32_t ib = 0;
+    for (uint32_t ci = 0; ci < ncand; ++ci) {
+      double sum = 0.0;
+      for (uint32_t k = 0; k < bg.nb; ++k) sum += h_l1[(size_t)ci * bg.nb + k];
+      double cur = count > 0 ? sum / count : 0.0;
+      if (cur < best) {
+        best = cur;
+        ib = ci;
+      }
+    }
+    Is_interp[l - 1] = cands[ib].interp;
+    std::memcpy(Is_order[l - 1], cands[ib].order, 3);
+    QOZ_HIP(hipMemcpyAsync(wc, wt + (size_t)ib * bsz, 4 * bsz,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  for (uint32_t l = Lt + 1; l <= L; ++l) {
+    Is_interp[l - 1] = Is_interp[Lt - 1];
+    std::memcpy(Is_order[l - 1], Is_order[Lt - 1], 3);
+  }
+
+  /* ---- (alpha, beta) trials, deduplicated by level-bound vector ---- */
+  const int nf = target == QOZ_TARGET_CR ? 1 : 3;
+  const double factors[3] = {1.0, 0.8, 1.2};
+  struct Vec {
+    double eb[QOZ_MAX_LEVELS];
+    float tw[QOZ_MAX_LEVELS], iv[QOZ_MAX_LEVELS];
+  };
+  std::vector<Vec> vecs;
+  int trial_of[3][20];
+  for (int f = 0; f < nf; ++f)
+    for (int i = 0; i < 20; ++i) {
+      Vec v;
+      std::memset(&v, 0, sizeof(v));
+      const double ef = f == 0 ? e : e * factors[f];
+      level_bounds(ef, kAlpha[i / 4], kBeta[i % 4], Lt, v.eb, v.tw, v.iv);
+      int found = -1;
+      for (size_t k = 0; k < vecs.size(); ++k)
+        if (std::memcmp(&vecs[k], &v, sizeof(Vec)) == 0) {
+          found = (int)k;
+          break;
+        }
+      if (found < 0) {
+        found = (int)vecs.size();
+        vecs.push_back(v);
+      }
+      trial_of[f][i] = found;
+    }
+  const uint32_t ntrial = (uint32_t)vecs.size();
+  std::memset(h_desc, 0, sizeof(TrialDesc) * ntrial);
+  for (uint32_t t = 0; t < ntrial; ++t)
+    for (uint32_t l = 1; l <= Lt; ++l) {
+      TrialLevel& lv = h_desc[t].lv[l - 1];
+      lv.twoeb = vecs[t].tw[l - 1];
+      lv.inv = vecs[t].iv[l - 1];
+      lv.eb = vecs[t].eb[l - 1];
+      lv.cubic = Is_interp[l - 1];
+      for (int j = 0; j < 3; ++j)
+        lv.order[j] = j < d ? Is_order[l - 1][j] + shift : 0;
+    }
+  QOZ_HIP(hipMemcpyAsync(ddesc, h_desc, sizeof(TrialDesc) * ntrial,
+                         hipMemcpyHostToDevice, s));
+  launch_zero_u32(dhist, (uint64_t)kNSym * ntrial, s);
+  {
+    hipEvent_t ev = prof_begin(c, s);
+    launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun, s);
+    prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ntrial);
+  }
+  if (target == QOZ_TARGET_SSIM) {
+    sj.batch = ntrial * bg.nb;
+    sj.c1 = (0.01 * vrange) * (0.01 * vrange);
+    sj.c2 = (0.03 * vrange) * (0.03 * vrange);
+    ssim_np = ssim_parts(sj);
+    hipEvent_t ev = prof_begin(c, s);
+    launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
+    prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
+    QOZ_HIP(hipMemcpyAsync(h_ssim, c->ssim_part.p, 8 * ssim_np,
+                           hipMemcpyDeviceToHost, s));
+  }
+  QOZ_HIP(hipMemcpyAsync(h_hist, dhist, 4 * (size_t)kNSym * ntrial,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_HIP(hipMemcpyAsync(h_sse, dsse, 12 * (size_t)nslots * bg.nb,
+                         hipMemcpyDeviceToHost, s));
+  QOZ_HIP(hipGetLastError());
+  QOZ_HIP(hipStreamSynchronize(s));
+  prof_collect(c);
+
+  const double npts = (double)bg.size * bg.nb;
+  const uint64_t per_item = sj.batch ? ssim_np / sj.batch : 0;
+  const double nwin = (double)(sj.P - sj.wp + 1) * (double)(sj.Rn - sj.wr + 1) *
+                      (double)(sj.Cn - sj.wc + 1) * bg.nb;
+  std::vector<double> B(ntrial), M(ntrial, 0.0);
+  for (uint32_t t = 0; t < ntrial; ++t) {
+    uint64_t bits = huffman_cost(h_hist + (size_t)t * kNSym, kNSym);
+    uint64_t U = 0;
+    double sse = 0.0;
+    for (uint32_t k = 0; k < bg.nb; ++k) {
+      U += h_un[(size_t)t * bg.nb + k];
+      sse += h_sse[(size_t)t * bg.nb + k];
+    }
+    B[t] = ((double)bits + 32.0 * (double)U) / npts;
+    if (target == QOZ_TARGET_PSNR) {
+      M[t] = sse == 0.0 ? std::numeric_limits<double>::infinity()
+                        : 20.0 * std::log10(vrange / std::sqrt(sse / npts));
+    } else if (target == QOZ_TARGET_SSIM) {
+      double sum = 0.0;
+      for (uint64_t q = 0; q < per_item * bg.nb; ++q)
+        sum += h_ssim[(uint64_t)t * bg.nb * per_item + q];
+      M[t] = sum / nwin;
+    }
+  }
+  int inc = 0;
+  for (int i = 1; i < 20; ++i) {
+    const int tI = trial_of[0][inc], tII = trial_of[0][i];
+    const int cs = table1_case(B[tI], M[tI], B[tII], M[tII]);
+    if (cs == 1) continue;
+    if (cs == 2) {
+      inc = i;
+      continue;
+    }
+    const int tp = trial_of[cs == 3 ? 1 : 2][i];
+    if (table1_line_prefers_II(B[tI], M[tI], B[tII], M[tII], B[tp], M[tp]))
+      inc = i;
+  }
+
+  qoz_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.anchor_stride = sa;
+  p.levels = L;
+  for (uint32_t l = 0; l < L; ++l) {
+    p.interp[l] = Is_interp[l];
+    for (int j = 0; j < 3; ++j) p.order[l][j] = j < d ? Is_order[l][j] : 0;
+  }
+  p.alpha = kAlpha[inc / 4];
+  p.beta = kBeta[inc % 4];
+  *out = p;
+  return QOZ_OK;
+}
