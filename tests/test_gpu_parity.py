@@ -181,8 +181,12 @@ def test_metrics_parity(codec, ref):
 
 
 def near_tie(vals, chosen, rel=1e-9):
+    """Another candidate within `rel` of the chosen one but not equal to it.
+    Exact ties (identical predictions, e.g. linear and cubic where only two
+    stencil points exist) are resolved identically on both sides."""
     best = vals[chosen]
-    return any(i != chosen and abs(v - best) <= rel * max(abs(best), 1e-300)
+    return any(i != chosen and
+               0 < abs(v - best) <= rel * max(abs(best), 1e-300)
                for i, v in enumerate(vals))
 
 
