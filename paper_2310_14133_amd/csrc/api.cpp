@@ -47,7 +47,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   const uint64_t nch = P.n_chunks;
   QOZ_TRY(ensure_pinned(c, kPinBase));
   QOZ_TRY(ensure(c->W, 4 * N));
-  QOZ_TRY(ensure(c->codes, 4 * (P.n_codes + 4)));
+  QOZ_TRY(ensure(c->codes, 2 * (P.n_codes + 16)));
   QOZ_TRY(ensure(c->hist, 4 * kNSym));
   QOZ_TRY(ensure(c->status, 256));
   QOZ_TRY(ensure(c->anchors, 4 * P.n_anchor));
@@ -57,7 +57,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   QOZ_TRY(ensure(c->upre, 4 * (nch + 1)));
   QOZ_TRY(ensure(c->enc_table, 8 * kNSym));
   float* W = (float*)c->W.p;
-  int32_t* codes = (int32_t*)c->codes.p;
+  uint16_t* codes = (uint16_t*)c->codes.p;
   uint32_t* hist = (uint32_t*)c->hist.p;
   uint32_t* st = (uint32_t*)c->status.p;
   uint64_t* totals = (uint64_t*)((uint8_t*)c->status.p + 64);
@@ -71,10 +71,10 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     const Sweep& sw = P.sweeps[i];
     const bool last = i + 1 == P.sweeps.size();
     PROF(sw.level == 1 ? PK_SWEEP_COMP_L1 : PK_SWEEP_COMP,
-         (double)sw.count * (last ? 12.0 : 16.0),
+         (double)sw.count * (last ? 10.0 : 14.0),
          launch_sweep_comp(P.g, sw, d_x, W, codes, !last, st, s));
   }
-  PROF(PK_HIST, 4.0 * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
+  PROF(PK_HIST, 2.0 * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
   QOZ_HIP(hipMemcpyAsync(pin(c, kPinHist), hist, 4 * kNSym,
                          hipMemcpyDeviceToHost, s));
   QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
@@ -111,7 +111,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     QOZ_HIP(hipMemcpyAsync(c->enc_table.p, tab, 8ull * tab_n,
                            hipMemcpyHostToDevice, s));
   const uint64_t* dtab = (const uint64_t*)c->enc_table.p;
-  PROF(PK_HUFF_LEN, 4.0 * P.n_codes + 8.0 * nch,
+  PROF(PK_HUFF_LEN, 2.0 * P.n_codes + 8.0 * nch,
        (launch_huff_len(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
                         (uint32_t*)c->chunk_bits.p,
                         (uint32_t*)c->chunk_zeros.p, s),
@@ -159,7 +159,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                          hipMemcpyDeviceToDevice, s));
   SweepTable tbl;
   fill_sweep_table(P, &tbl);
-  PROF(PK_HUFF_ENC, 4.0 * P.n_codes + 4.0 * n_words + 4.0 * n_unpred,
+  PROF(PK_HUFF_ENC, 2.0 * P.n_codes + 4.0 * n_words + 4.0 * n_unpred,
        launch_huff_encode(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
                           (const uint64_t*)c->coff.p,
                           (const uint32_t*)c->upre.p,
@@ -289,29 +289,34 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
               4 * sorted.size());
   QOZ_TRY(ensure(c->dec_tables, sizeof(DecTables)));
   QOZ_TRY(ensure(c->dec_syms, 4 * kNSym));
-  QOZ_TRY(ensure(c->codes, 4 * (P.n_codes + 4)));
+  QOZ_TRY(ensure(c->codes, 2 * (P.n_codes + 16)));
   QOZ_TRY(ensure(c->status, 256));
   QOZ_HIP(hipMemcpyAsync(c->dec_tables.p, dt, sizeof(DecTables),
                          hipMemcpyHostToDevice, s));
   QOZ_HIP(hipMemcpyAsync(c->dec_syms.p, pin(c, kPinTable + syms_off),
                          4 * sorted.size(), hipMemcpyHostToDevice, s));
+  QOZ_TRY(ensure(c->upos, 4 * (nu + 1)));
   uint32_t* st = (uint32_t*)c->status.p;
-  int32_t* codes = (int32_t*)c->codes.p;
+  uint16_t* codes = (uint16_t*)c->codes.p;
+  uint32_t* upos = (uint32_t*)c->upos.p;
   launch_init_status(st, s);
-  PROF(PK_HUFF_DEC, 4.0 * nw + 4.0 * P.n_codes,
+  PROF(PK_HUFF_DEC, 4.0 * nw + 2.0 * P.n_codes,
        launch_huff_decode((const uint32_t*)(in + lay.payload), nw,
                           (const uint64_t*)(in + lay.coff),
                           (const uint32_t*)(in + lay.upre), nch, P.n_codes, nu,
                           (const DecTables*)c->dec_tables.p,
-                          (const uint32_t*)c->dec_syms.p, codes, st, s));
+                          (const uint32_t*)c->dec_syms.p, codes, upos, st, s));
+  SweepTable tbl;
+  fill_sweep_table(P, &tbl);
+  launch_unpred_scatter(P.g, tbl, upos, (const float*)(in + lay.unpred), nu,
+                        P.n_codes, d_y, st, s);
   PROF(PK_ANCHOR, 8.0 * P.n_anchor,
        launch_anchor_scatter(P.g, P.s, P.na, (const float*)(in + lay.anchors),
                              d_y, s));
   for (const Sweep& sw : P.sweeps)
     PROF(sw.level == 1 ? PK_SWEEP_DEC_L1 : PK_SWEEP_DEC,
-         (double)sw.count * 12.0,
-         launch_sweep_decomp(P.g, sw, d_y, codes,
-                             (const float*)(in + lay.unpred), nu, st, s));
+         (double)sw.count * 10.0,
+         launch_sweep_decomp(P.g, sw, d_y, codes, s));
   QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
                          s));
   QOZ_TRY(sync_checked(s));

@@ -103,6 +103,19 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
   if (kraft > ((unsigned __int128)1 << kMaxCodeLen)) return false;
   std::vector<uint64_t> code(kNSym);
   canonical_codes(len.data(), kNSym, code.data());
+  t->n_used = n_used;
+  t->zlen = len[0];
+  t->zcode = len[0] ? code[0] : 0;
+  {
+    uint64_t per_len[kMaxCodeLen + 2] = {0};
+    for (uint32_t i = 0; i < n_used; ++i) per_len[lens[i]]++;
+    uint64_t c = 0; /* first canonical code of length L */
+    t->lim_half[0] = 0;
+    for (int L = 1; L <= kMaxCodeLen; ++L) {
+      c = (c + per_len[L - 1]) << 1;
+      t->lim_half[L] = (c + per_len[L]) << (63 - L);
+    }
+  }
   sorted->clear();
   for (int l = 1; l <= kMaxCodeLen; ++l) {
     t->off[l] = (uint32_t)sorted->size();
@@ -113,6 +126,48 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
         sorted->push_back(syms[i]);
       }
     if (t->cnt[l]) t->maxlen = (uint32_t)l;
+  }
+  /* two-level table: 11-bit first level, per-prefix second level of up to
+   * 10 more bits (codes up to 21 bits), at most 2048 second-level entries */
+  {
+    const int kL1 = 11, kSubMax = 10;
+    const uint32_t kSubCap = 2048;
+    std::vector<uint32_t> pmax(1u << kL1, 0);
+    for (uint32_t i = 0; i < n_used; ++i) {
+      const uint32_t l = lens[i];
+      const uint64_t cv = code[syms[i]];
+      if (l <= (uint32_t)kL1) {
+        const uint32_t base = (uint32_t)(cv << (kL1 - l));
+        for (uint32_t k = 0; k < (1u << (kL1 - l)); ++k)
+          t->l1[base + k] = ((uint32_t)syms[i] << 8) | l;
+      } else {
+        const uint32_t p = (uint32_t)(cv >> (l - kL1));
+        if (l > pmax[p]) pmax[p] = l;
+      }
+    }
+    t->n_sub = 0;
+    for (uint32_t p = 0; p < (1u << kL1); ++p) {
+      if (!pmax[p]) continue;
+      uint32_t sb = pmax[p] - kL1;
+      if (sb > (uint32_t)kSubMax) sb = kSubMax;
+      if (t->n_sub + (1u << sb) > kSubCap) continue; /* left to lim_half */
+      t->l1[p] = (t->n_sub << 8) | 0x80u | sb;
+      t->n_sub += 1u << sb;
+    }
+    for (uint32_t i = 0; i < n_used; ++i) {
+      const uint32_t l = lens[i];
+      if (l <= (uint32_t)kL1) continue;
+      const uint64_t cv = code[syms[i]];
+      const uint32_t p = (uint32_t)(cv >> (l - kL1));
+      const uint32_t e = t->l1[p];
+      if (!(e & 0x80u)) continue;
+      const uint32_t sb = e & 0x7fu, base = e >> 8;
+      if (l - kL1 > sb) continue; /* longer than this subtable covers */
+      const uint32_t suffix = (uint32_t)(cv & ((1ull << (l - kL1)) - 1));
+      const uint32_t at = base + (suffix << (sb - (l - kL1)));
+      for (uint32_t k = 0; k < (1u << (sb - (l - kL1))); ++k)
+        t->sub[at + k] = ((uint32_t)syms[i] << 8) | (l - kL1);
+    }
   }
   for (uint32_t i = 0; i < n_used; ++i) {
     uint32_t l = lens[i];

@@ -13,11 +13,7 @@
  *                  an LDS word buffer (ds_or), then stores the words
  *                  coalesced; lanes holding bin 0 gather their exact value
  *                  into the unpredictable list at their global rank.
- *  - k_huff_decode: one lane per chunk, canonical decoding through a
- *                  2^12-entry LDS table with a per-length fallback for
- *                  longer codes; unpredictable bins are replaced by the
- *                  complement of their rank so the inverse sweep can fetch
- *                  the exact value directly.
+ * Decoding is in kernels_decode.hip.
  */
 #include "qoz_device.h"
 #include "qoz_internal.h"
@@ -28,23 +24,26 @@ constexpr uint32_t kHistPerBlock = 1u << 16;
 constexpr uint32_t kHistThreads = 512;
 
 __global__ __launch_bounds__(kHistThreads) void k_hist(
-    const int32_t* __restrict__ codes, uint64_t n, uint32_t* hist) {
+    const uint16_t* __restrict__ codes, uint64_t n, uint32_t* hist) {
   __shared__ uint32_t lh[kHistWin];
   for (uint32_t i = threadIdx.x; i < kHistWin; i += blockDim.x) lh[i] = 0;
   __syncthreads();
   const uint64_t b0 = (uint64_t)blockIdx.x * kHistPerBlock;
   const uint64_t b1 = b0 + kHistPerBlock < n ? b0 + kHistPerBlock : n;
   uint32_t center = 0;
-  const uint64_t nvec = (b1 - b0) / 4;
-  const int4* v4 = reinterpret_cast<const int4*>(codes + b0);
+  /* eight 16-bit bins per 16-byte load */
+  const uint64_t nvec = (b1 - b0) / 8;
+  const uint4* v4 = reinterpret_cast<const uint4*>(codes + b0);
   for (uint64_t i = threadIdx.x; i < nvec; i += blockDim.x) {
-    int4 q = v4[i];
-    hist_add(lh, hist, q.x, center);
-    hist_add(lh, hist, q.y, center);
-    hist_add(lh, hist, q.z, center);
-    hist_add(lh, hist, q.w, center);
+    const uint4 q = v4[i];
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      hist_add(lh, hist, (int32_t)(w[k] & 0xffffu), center);
+      hist_add(lh, hist, (int32_t)(w[k] >> 16), center);
+    }
   }
-  for (uint64_t i = b0 + nvec * 4 + threadIdx.x; i < b1; i += blockDim.x)
+  for (uint64_t i = b0 + nvec * 8 + threadIdx.x; i < b1; i += blockDim.x)
     hist_add(lh, hist, codes[i], center);
   center = wave_sum_u32(center);
   if ((threadIdx.x & 63) == 0 && center)
@@ -56,7 +55,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(
   }
 }
 
-void launch_hist(const int32_t* codes, uint64_t n, uint32_t* hist,
+void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s) {
   if (!n) return;
   uint64_t blocks = (n + kHistPerBlock - 1) / kHistPerBlock;
@@ -91,7 +90,7 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v,
 }
 
 __global__ __launch_bounds__(kEncThreads) void k_huff_len(
-    const int32_t* __restrict__ codes, uint64_t n,
+    const uint16_t* __restrict__ codes, uint64_t n,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, uint32_t* chunk_bits, uint32_t* chunk_zeros) {
   __shared__ uint32_t sh[2][kEncThreads / 64];
@@ -113,7 +112,7 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_len(
   }
 }
 
-void launch_huff_len(const int32_t* codes, uint64_t n_codes,
+void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
                      uint32_t* chunk_zeros, hipStream_t s) {
@@ -176,26 +175,6 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
                      chunk_bits, chunk_zeros, n_chunks, coff, upre, totals);
 }
 
-/* Flat index of the point whose bin sits at stream position pos. */
-__device__ uint32_t point_of(const SweepTable& t, const Geo& g, uint64_t pos) {
-  uint32_t lo = 0, hi = t.n; /* find last sweep with off <= pos */
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) / 2;
-    if (t.off[mid] <= pos) lo = mid;
-    else hi = mid;
-  }
-  uint64_t local = pos - t.off[lo];
-  uint32_t c2 = t.cnt[lo][2], c1 = t.cnt[lo][1];
-  uint32_t i2 = (uint32_t)(local % c2);
-  uint64_t r = local / c2;
-  uint32_t i1 = (uint32_t)(r % c1);
-  uint32_t i0 = (uint32_t)(r / c1);
-  uint32_t p0 = t.start[lo][0] + i0 * t.step[lo][0];
-  uint32_t p1 = t.start[lo][1] + i1 * t.step[lo][1];
-  uint32_t p2 = t.start[lo][2] + i2 * t.step[lo][2];
-  return p0 * g.st[0] + p1 * g.st[1] + p2;
-}
-
 constexpr uint32_t kEncMaxWords = kChunk * kMaxCodeLen / 32 + 2;
 
 __device__ __forceinline__ void put_bits(uint32_t* words, uint32_t pos,
@@ -214,7 +193,7 @@ __device__ __forceinline__ void put_bits(uint32_t* words, uint32_t pos,
 }
 
 __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
-    const int32_t* __restrict__ codes, uint64_t n,
+    const uint16_t* __restrict__ codes, uint64_t n,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, const uint64_t* __restrict__ coff,
     const uint32_t* __restrict__ upre, uint32_t* payload, uint64_t cap_words,
@@ -272,7 +251,7 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
   if (over) atomicOr(status, kStOverflow);
 }
 
-void launch_huff_encode(const int32_t* codes, uint64_t n_codes,
+void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
                         const uint32_t* upre, uint32_t* payload,
@@ -285,127 +264,6 @@ void launch_huff_encode(const int32_t* codes, uint64_t n_codes,
                      0, s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
                      coff, upre, payload, payload_cap_words, unpred, x, g, st,
                      status);
-}
-
-/* ---- decoding -------------------------------------------------------- */
-
-constexpr uint32_t kDecThreads = 64;
-
-/* The `len` (1..63) bits starting at bit `pos` (MSB-first) of words
- * [0, nw); bits past the end read as zero. */
-__device__ __forceinline__ uint64_t peek_abs(const uint32_t* w, uint64_t nw,
-                                             uint64_t pos, uint32_t len) {
-  const uint64_t wi = pos >> 5;
-  const uint32_t o = (uint32_t)(pos & 31);
-  const uint64_t a = wi < nw ? w[wi] : 0;
-  const uint64_t b = wi + 1 < nw ? w[wi + 1] : 0;
-  const uint64_t c = wi + 2 < nw ? w[wi + 2] : 0;
-  const uint64_t window = (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
-  return window >> (64 - len);
-}
-
-__global__ __launch_bounds__(kDecThreads) void k_huff_decode(
-    const uint32_t* __restrict__ payload, uint64_t n_words,
-    const uint64_t* __restrict__ coff, const uint32_t* __restrict__ upre,
-    uint64_t n_chunks, uint64_t n_codes, uint64_t n_unpred,
-    const DecTables* __restrict__ tabs, const uint32_t* __restrict__ syms,
-    int32_t* __restrict__ codes, uint32_t* status) {
-  __shared__ uint32_t lut[1u << kLutBits];
-  __shared__ uint64_t first[kMaxCodeLen + 1];
-  __shared__ uint32_t cnt[kMaxCodeLen + 1], off[kMaxCodeLen + 1];
-  for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += blockDim.x)
-    lut[i] = tabs->lut[i];
-  for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxCodeLen; i += blockDim.x) {
-    first[i] = tabs->first[i];
-    cnt[i] = tabs->cnt[i];
-    off[i] = tabs->off[i];
-  }
-  const uint32_t maxlen = tabs->maxlen;
-  __syncthreads();
-  const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_chunks) return;
-  const uint64_t w0 = coff[c], w1 = coff[c + 1];
-  const uint32_t u0 = upre[c], u1 = upre[c + 1];
-  if (w0 > w1 || w1 > n_words || (c == 0 && w0 != 0) || u0 > u1 ||
-      u1 > n_unpred || (c + 1 == n_chunks && (w1 != n_words || u1 != n_unpred))) {
-    atomicOr(status, kStBadStream);
-    return;
-  }
-  const uint32_t* w = payload + w0;
-  const uint64_t nw = w1 - w0;
-  const uint64_t avail = nw * 32;
-  const uint64_t lo = c * kChunk;
-  const uint64_t hi = lo + kChunk < n_codes ? lo + kChunk : n_codes;
-  uint64_t buf = 0;   /* next bits, MSB-aligned */
-  int nb = 0;         /* valid bits in buf */
-  uint64_t wp = 0;    /* next word to load */
-  uint64_t used = 0;  /* bits consumed */
-  uint32_t z = 0;
-  bool bad = false;
-  for (uint64_t i = lo; i < hi; ++i) {
-    while (nb <= 32 && wp < nw) {
-      buf |= (uint64_t)w[wp++] << (32 - nb);
-      nb += 32;
-    }
-    uint32_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-    uint32_t len = e & 0xff, sym;
-    if (len) {
-      sym = e >> 8;
-    } else {
-      sym = 0xffffffffu;
-      for (uint32_t L = kLutBits + 1; L <= maxlen; ++L) {
-        uint64_t v = (int)L <= nb ? buf >> (64 - L)
-                                  : peek_abs(w, nw, used, L);
-        if (cnt[L] && v - first[L] < cnt[L]) {
-          sym = syms[off[L] + (uint32_t)(v - first[L])];
-          len = L;
-          break;
-        }
-      }
-      if (sym == 0xffffffffu) {
-        bad = true;
-        break;
-      }
-    }
-    used += len;
-    if ((int)len <= nb) {
-      buf <<= len;
-      nb -= (int)len;
-    } else { /* re-seat the window after a code longer than the buffer */
-      wp = used >> 5;
-      uint32_t o = (uint32_t)(used & 31);
-      buf = 0;
-      nb = 0;
-      if (wp < nw) {
-        buf = ((uint64_t)w[wp] << 32) << o;
-        nb = 32 - (int)o;
-        ++wp;
-      }
-    }
-    int32_t out;
-    if (sym == 0) {
-      uint32_t rank = u0 + z;
-      ++z;
-      out = (int32_t)~rank;
-    } else {
-      out = (int32_t)sym;
-    }
-    codes[i] = out;
-  }
-  if (bad || used > avail || z != u1 - u0) atomicOr(status, kStBadStream);
-}
-
-void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
-                        const uint64_t* coff, const uint32_t* upre,
-                        uint64_t n_chunks, uint64_t n_codes,
-                        uint64_t n_unpred, const DecTables* tabs,
-                        const uint32_t* syms, int32_t* codes,
-                        uint32_t* status, hipStream_t s) {
-  if (!n_chunks) return;
-  uint64_t blocks = (n_chunks + kDecThreads - 1) / kDecThreads;
-  hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecThreads),
-                     0, s, payload, n_words, coff, upre, n_chunks, n_codes,
-                     n_unpred, tabs, syms, codes, status);
 }
 
 }  // namespace qoz

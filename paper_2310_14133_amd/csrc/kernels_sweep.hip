@@ -121,7 +121,7 @@ __device__ __forceinline__ SweepPoint sweep_point(const Geo& g,
 template <bool WRITE_W>
 __global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_comp(
     Geo g, Sweep s, const float* __restrict__ x, float* W,
-    int32_t* __restrict__ codes, uint32_t* status) {
+    uint16_t* __restrict__ codes, uint32_t* status) {
   const uint32_t i2 = blockIdx.x * kSweepTX + threadIdx.x;
   if (i2 >= s.cnt[2]) return;
   const uint32_t rows = s.cnt[0] * s.cnt[1];
@@ -136,41 +136,61 @@ __global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_comp(
     float rec;
     int32_t code = quantize_bin(xv, pred, s.inv, s.twoeb, s.eb, &rec);
     if (WRITE_W) W[sp.idx] = rec;
-    codes[sp.pos] = code;
+    codes[sp.pos] = (uint16_t)code;
     bad |= !isfinite(xv);
   }
   if (bad) atomicOr(status, kStNonFinite);
 }
 
 /* Decompression: bins >= 1 reconstruct pred + (bin - R) * 2e_l with the
- * same two roundings as the compressor; negative entries carry the rank of
- * an unpredictable value (bitwise complement), written by the decoder. */
+ * same two roundings as the compressor.  Bin 0 (unpredictable) is skipped:
+ * its exact value was scattered into W before the sweeps. */
 __global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_decomp(
-    Geo g, Sweep s, float* W, const int32_t* __restrict__ codes,
-    const float* __restrict__ unpred, uint64_t n_unpred, uint32_t* status) {
+    Geo g, Sweep s, float* W, const uint16_t* __restrict__ codes) {
   const uint32_t i2 = blockIdx.x * kSweepTX + threadIdx.x;
   if (i2 >= s.cnt[2]) return;
   const uint32_t rows = s.cnt[0] * s.cnt[1];
   const uint32_t sk = g.st[s.k];
   const uint32_t nk = g.n[s.k];
-  bool bad = false;
   for (uint32_t r = blockIdx.y * kSweepTY + threadIdx.y; r < rows;
        r += gridDim.y * kSweepTY) {
     SweepPoint sp = sweep_point(g, s, r, i2);
-    int32_t code = codes[sp.pos];
-    float v;
-    if (code < 0) {
-      uint32_t u = ~(uint32_t)code;
-      bool ok = u < n_unpred;
-      bad |= !ok;
-      v = ok ? unpred[u] : 0.0f;
-    } else {
-      float pred = predict_at(W, sp.idx, sp.pk, sk, nk, s.h, s.cubic);
-      v = dequantize_bin(pred, code, s.twoeb);
+    const int32_t code = codes[sp.pos];
+    if (code == 0) continue;
+    float pred = predict_at(W, sp.idx, sp.pk, sk, nk, s.h, s.cubic);
+    W[sp.idx] = dequantize_bin(pred, code, s.twoeb);
+  }
+}
+
+/* Unpredictable values to their points: upos[r] is the stream position of
+ * the r-th unpredictable bin (recorded by the decoder). */
+__global__ void k_unpred_scatter(Geo g, SweepTable st,
+                                 const uint32_t* __restrict__ upos,
+                                 const float* __restrict__ vals,
+                                 uint64_t n_unpred, uint64_t n_codes,
+                                 float* __restrict__ W, uint32_t* status) {
+  bool bad = false;
+  for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       r < n_unpred; r += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t pos = upos[r];
+    if (pos >= n_codes) {
+      bad = true;
+      continue;
     }
-    W[sp.idx] = v;
+    W[point_of(st, g, pos)] = vals[r];
   }
   if (bad) atomicOr(status, kStBadStream);
+}
+
+void launch_unpred_scatter(const Geo& g, const SweepTable& st,
+                           const uint32_t* upos, const float* vals,
+                           uint64_t n_unpred, uint64_t n_codes, float* W,
+                           uint32_t* status, hipStream_t s) {
+  if (!n_unpred) return;
+  uint64_t blocks = (n_unpred + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_unpred_scatter, dim3((uint32_t)blocks), dim3(256), 0,
+                     s, g, st, upos, vals, n_unpred, n_codes, W, status);
 }
 
 static dim3 sweep_grid_dim(const Sweep& sw) {
@@ -182,7 +202,7 @@ static dim3 sweep_grid_dim(const Sweep& sw) {
 }
 
 void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
-                       float* W, int32_t* codes, bool write_w,
+                       float* W, uint16_t* codes, bool write_w,
                        uint32_t* status, hipStream_t s) {
   if (sw.count == 0) return;
   dim3 grid = sweep_grid_dim(sw), block(kSweepTX, kSweepTY);
@@ -195,12 +215,10 @@ void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
 }
 
 void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
-                         const int32_t* codes, const float* unpred,
-                         uint64_t n_unpred, uint32_t* status, hipStream_t s) {
+                         const uint16_t* codes, hipStream_t s) {
   if (sw.count == 0) return;
   dim3 grid = sweep_grid_dim(sw), block(kSweepTX, kSweepTY);
-  hipLaunchKernelGGL(k_sweep_decomp, grid, block, 0, s, g, sw, W, codes,
-                     unpred, n_unpred, status);
+  hipLaunchKernelGGL(k_sweep_decomp, grid, block, 0, s, g, sw, W, codes);
 }
 
 }  // namespace qoz

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qoz_internal.h"
+
 namespace qoz {
 
 /* Interpolated value at a midpoint from a = f(-3h), b = f(-h), c = f(+h),
@@ -110,6 +112,26 @@ __device__ __forceinline__ float dequantize_bin(float pred, int32_t code,
                                                 float twoeb) {
   const float t = (float)(code - 32768) * twoeb;
   return pred + t;
+}
+
+/* Flat index of the point whose bin sits at stream position pos. */
+__device__ __forceinline__ uint32_t point_of(const SweepTable& t, const Geo& g, uint64_t pos) {
+  uint32_t lo = 0, hi = t.n; /* find last sweep with off <= pos */
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (t.off[mid] <= pos) lo = mid;
+    else hi = mid;
+  }
+  uint64_t local = pos - t.off[lo];
+  uint32_t c2 = t.cnt[lo][2], c1 = t.cnt[lo][1];
+  uint32_t i2 = (uint32_t)(local % c2);
+  uint64_t r = local / c2;
+  uint32_t i1 = (uint32_t)(r % c1);
+  uint32_t i0 = (uint32_t)(r / c1);
+  uint32_t p0 = t.start[lo][0] + i0 * t.step[lo][0];
+  uint32_t p1 = t.start[lo][1] + i1 * t.step[lo][1];
+  uint32_t p2 = t.start[lo][2] + i2 * t.step[lo][2];
+  return p0 * g.st[0] + p1 * g.st[1] + p2;
 }
 
 }  // namespace qoz

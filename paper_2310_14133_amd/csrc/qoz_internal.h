@@ -82,6 +82,21 @@ struct DecTables {
   uint32_t cnt[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
   uint32_t maxlen;
+  uint32_t n_used;
+  uint32_t zlen;  /* length of symbol 0's code (0 if unused) */
+  uint64_t zcode; /* symbol 0's code */
+  /* (first code of length L + count of length L) << (63 - L): a 64-bit
+   * left-justified window V starts with a codeword longer than L iff
+   * (V >> 1) >= lim_half[L] */
+  uint64_t lim_half[kMaxCodeLen + 1];
+  /* two-level table: l1 indexed by the first 11 bits holds either
+   * (symbol << 8) | length for codes up to 11 bits, or, for prefixes of
+   * longer codes, (subtable base << 8) | 0x80 | subtable bits; sub entries
+   * hold (symbol << 8) | (length - 11); 0 marks a code longer than the
+   * tables cover (decoded from lim_half). */
+  uint32_t l1[1u << 11];
+  uint32_t n_sub;
+  uint32_t sub[2048];
 };
 
 /* Tuner: one level of a candidate parameter set on the sampled blocks. */
@@ -134,7 +149,7 @@ struct qoz_ctx {
   /* scratch */
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
-      tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part;
+      tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos;
   /* pinned host staging */
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
@@ -211,15 +226,18 @@ void launch_anchor_copy(const Geo& g, uint32_t stride, const uint32_t na[3],
 void launch_anchor_scatter(const Geo& g, uint32_t stride, const uint32_t na[3],
                            const float* in, float* W, hipStream_t s);
 void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
-                       float* W, int32_t* codes, bool write_w,
+                       float* W, uint16_t* codes, bool write_w,
                        uint32_t* status, hipStream_t s);
 void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
-                         const int32_t* codes, const float* unpred,
-                         uint64_t n_unpred, uint32_t* status, hipStream_t s);
-void launch_hist(const int32_t* codes, uint64_t n, uint32_t* hist,
+                         const uint16_t* codes, hipStream_t s);
+void launch_unpred_scatter(const Geo& g, const SweepTable& st,
+                           const uint32_t* upos, const float* vals,
+                           uint64_t n_unpred, uint64_t n_codes, float* W,
+                           uint32_t* status, hipStream_t s);
+void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s);
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
-void launch_huff_len(const int32_t* codes, uint64_t n_codes,
+void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
                      uint32_t* chunk_zeros, hipStream_t s);
@@ -227,7 +245,7 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
                        const uint32_t* chunk_zeros, uint64_t n_chunks,
                        uint64_t* coff, uint32_t* upre, uint64_t* totals,
                        hipStream_t s);
-void launch_huff_encode(const int32_t* codes, uint64_t n_codes,
+void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
                         const uint32_t* upre, uint32_t* payload,
@@ -238,8 +256,8 @@ void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
                         uint64_t n_chunks, uint64_t n_codes,
                         uint64_t n_unpred, const DecTables* tabs,
-                        const uint32_t* syms, int32_t* codes,
-                        uint32_t* status, hipStream_t s);
+                        const uint32_t* syms, uint16_t* codes,
+                        uint32_t* upos, uint32_t* status, hipStream_t s);
 void launch_range(const float* x, uint64_t n, float* part_min,
                   float* part_max, uint32_t* status, uint32_t nparts,
                   hipStream_t s);

@@ -163,3 +163,39 @@ def adversarial(shape, kind, seed=0, dtype=np.float32):
     else:
         raise ValueError(kind)
     return np.ascontiguousarray(np.asarray(f).astype(dtype))
+
+
+def bins_field(bins, n0, n1):
+    """2D field whose quantization bins (anchor stride 2, linear
+    interpolation, order (0, 1), bound 0.5 so the bin width is 1) are the
+    given integers, in stream order.  Anchors are 0; the first sweep's
+    targets (odd row, even column) take the bin value itself; the second
+    sweep's targets (odd column) take the mean of their left and right
+    neighbours plus the bin value.  n0 and n1 must be odd.  Used to force
+    chosen histograms, e.g. very long Huffman codes."""
+    assert n0 % 2 == 1 and n1 % 2 == 1
+    f = np.zeros((n0, n1), np.float64)
+    bins = np.asarray(bins, np.float64)
+    n_s0 = (n0 // 2) * (n1 // 2 + 1)
+    n_s1 = n0 * (n1 // 2)
+    assert bins.size == n_s0 + n_s1
+    f[1::2, 0::2] = bins[:n_s0].reshape(n0 // 2, n1 // 2 + 1)
+    mean = 0.5 * (f[:, 0:-1:2] + f[:, 2::2])
+    f[:, 1::2] = mean + bins[n_s0:].reshape(n0, n1 // 2)
+    return np.ascontiguousarray(f.astype(np.float32))
+
+
+def fibonacci_bins(total, n_syms, seed=0):
+    """`total` bins whose counts follow a Fibonacci sequence over n_syms
+    distinct values (the rest are 0), shuffled."""
+    fib = [1, 1]
+    while len(fib) < n_syms:
+        fib.append(fib[-1] + fib[-2])
+    vals = []
+    for k, cnt in enumerate(fib[:n_syms]):
+        vals += [k + 1] * cnt
+    vals = vals[:total]
+    vals += [0] * (total - len(vals))
+    v = np.array(vals, np.int64)
+    np.random.default_rng(seed).shuffle(v)
+    return v

@@ -235,3 +235,14 @@ def test_tune_parity(codec, ref, name, make, s, cfgkw, target, rel):
             (q.params_dict(gp, d), ref.params_to_dict(rp, d))
     # downstream: the GPU's parameters give the oracle's stream
     roundtrip_check(codec, ref, x, e, rp)
+
+
+@pytest.mark.parametrize("n_syms", [12, 28])
+def test_long_codes_bitexact(codec, ref, n_syms):
+    """Fibonacci-distributed bins: codes longer than the decoder's tables
+    (up to 26 bits) go through the canonical-limit path."""
+    n0, n1 = 1025, 1025
+    n_t = (n0 // 2) * (n1 // 2 + 1) + n0 * (n1 // 2)
+    x = fields.bins_field(fields.fibonacci_bins(n_t, n_syms, seed=5), n0, n1)
+    rp = ref.make_params(2, "linear", (0, 1), 1.0, 1.0, anchor_stride=2)
+    roundtrip_check(codec, ref, x, 0.5, rp)

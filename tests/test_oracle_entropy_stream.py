@@ -169,3 +169,19 @@ def test_payload_bitflips_never_crash(ref):
         pos = int(rng.integers(184, z.size))
         bad[pos] ^= 1 << int(rng.integers(8))
         assert ref.decompress_status(bad) in (ref.OK, ref.EFORMAT)
+
+
+def test_long_codes_roundtrip(ref):
+    """Bins with Fibonacci counts force Huffman codes up to 26 bits; the
+    field is built so its bins are exactly the chosen ones."""
+    n0, n1 = 513, 1025
+    n_t = (n0 // 2) * (n1 // 2 + 1) + n0 * (n1 // 2)
+    b = fields.fibonacci_bins(n_t, 27, seed=3)
+    x = fields.bins_field(b, n0, n1)
+    p = ref.make_params(2, "linear", (0, 1), 1.0, 1.0, anchor_stride=2)
+    codes, recon, unpred, _ = ref.predict_quantize(x, 0.5, p)
+    assert np.array_equal(codes - 32768, b) and unpred.size == 0
+    hist = np.bincount(codes, minlength=65536).astype(np.uint64)
+    assert ref.huffman_lengths(hist).max() >= 24
+    z = ref.compress(x, 0.5, p)
+    assert np.array_equal(ref.decompress(z), recon)
