@@ -3,23 +3,26 @@
  * for gfx950, without any per-symbol index in the stream.
  *
  * One workgroup decodes one 4096-bin chunk at a time (persistent over
- * chunks); the chunk's words are staged in LDS.  The chunk's bits are cut
- * into one subsequence per lane (at least 128 bits each).  Huffman codes
+ * chunks); the chunk's words are staged in LDS and its bits are cut into
+ * one subsequence per lane (at least 128 bits).  Huffman codes
  * resynchronise within a few codewords when decoding starts at an arbitrary
  * bit, which gives a parallel decoder:
- *  1. every subsequence is decoded from its nominal first bit, counting the
- *     codewords that start inside it and recording which bit positions of
- *     its first 64 bits start a codeword (and which of those are symbol 0);
- *  2. its true start is its predecessor's exit; decoding from there stops
- *     at the first recorded boundary (the paths coincide from then on), so
- *     counts follow from population counts -- usually after two or three
- *     codewords.  Starts are re-propagated until none changes (only needed
- *     when a subsequence did not resynchronise inside its window);
- *  3. an exclusive scan of the counts gives each subsequence's first bin;
- *     a last decode writes the bins into LDS, which is stored coalesced.
- * Decoding uses a two-level table (11 bits, then up to 10 more); codes the
- * tables do not cover come from per-length limits of the canonical code.
- * Unpredictable bins (symbol 0) also record their stream position, so the
+ *  1. each lane walks its subsequence from the nominal first bit using code
+ *     lengths only, counting codewords and symbol-0 codewords, and keeps a
+ *     bitmap of the codeword starts (and symbol-0 starts) in its first 64
+ *     bits;
+ *  2. its true start is its predecessor's exit; walking from there stops at
+ *     the first start in the bitmap (the walks coincide from then on),
+ *     usually after two or three codewords, and the counts follow from
+ *     population counts.  Starts are re-propagated until none changes
+ *     (needed only when a subsequence did not resynchronise inside its
+ *     window);
+ *  3. an exclusive scan of the counts gives each lane its first bin index
+ *     and unpredictable rank, and each lane decodes its codewords.
+ * The walks read lengths from a 13-bit table (one byte per entry); the
+ * final decode reads symbols from a 12-bit table; longer codes are sized by
+ * comparing the window with the canonical code's per-length limits held in
+ * registers.  Unpredictable bins also record their stream position, so the
  * exact values can be placed before the inverse sweeps.  Every read is
  * bounded by the chunk's words (zero beyond), and the stream is rejected if
  * a chunk does not end inside its words or its unpredictable count
@@ -31,17 +34,19 @@ namespace qoz {
 
 constexpr uint32_t kDecWG = 256;
 constexpr uint32_t kMinSubBits = 128;
-constexpr uint32_t kL1Bits = 11;
-constexpr uint32_t kSubCap = 2048;
+constexpr uint32_t kLenBits = 13;  /* length table width */
+constexpr uint32_t kSymBits = 12;  /* symbol table width */
+constexpr uint32_t kRegMax = 27;   /* longest code sized from registers */
 constexpr uint32_t kMaxChunkWords = kChunk * kMaxCodeLen / 32 + 2;
 constexpr uint32_t kStageWords = 4096; /* chunks up to 32 bits/bin in LDS */
 constexpr uint32_t kInvalidSym = 0xffffffffu;
 
 struct DecShared {
   uint32_t words[kStageWords];
-  uint32_t l1[1u << kL1Bits];
-  uint32_t sub[kSubCap];
-  uint16_t out[kChunk];
+  uint8_t lz[1u << kLenBits];   /* length | 0x80 if symbol 0; 0 = longer */
+  uint16_t sym[1u << kSymBits]; /* symbol of codes up to kSymBits bits */
+  uint64_t first[kMaxCodeLen + 1];
+  uint32_t off[kMaxCodeLen + 1];
   uint32_t start[kDecWG], exitp[kDecWG];
   uint32_t count[kDecWG], zeros[kDecWG];
   uint32_t scan_c[kDecWG], scan_z[kDecWG];
@@ -73,14 +78,6 @@ struct BitReader {
     ++wp;
     refill();
   }
-  /* the 64 bits at the current position, from memory */
-  __device__ __forceinline__ uint64_t window64() const {
-    const uint32_t wi = pos >> 5, o = pos & 31;
-    const uint64_t a = wi < nw ? w[wi] : 0;
-    const uint64_t b = wi + 1 < nw ? w[wi + 1] : 0;
-    const uint64_t c = wi + 2 < nw ? w[wi + 2] : 0;
-    return (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
-  }
   __device__ __forceinline__ void advance(uint32_t len) {
     if ((int)len <= nb) {
       buf <<= len;
@@ -91,59 +88,94 @@ struct BitReader {
       seek(pos + len);
     }
   }
+  /* the 64 bits at the current position, from memory */
+  __device__ __forceinline__ uint64_t window() const {
+    const uint32_t wi = pos >> 5, o = pos & 31;
+    const uint64_t a = wi < nw ? w[wi] : 0;
+    const uint64_t b = wi + 1 < nw ? w[wi + 1] : 0;
+    const uint64_t c = wi + 2 < nw ? w[wi + 2] : 0;
+    return (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
+  }
 };
 
-/* Codes the tables do not cover: the length is the smallest L whose
- * canonical limit exceeds the window.  Returns 0 if invalid. */
-__device__ __noinline__ uint32_t slow_code(const BitReader& br,
-                                           const DecTables* tabs,
-                                           const uint32_t* syms,
-                                           uint32_t* sym) {
-  const uint64_t h = br.window64() >> 1;
-  const uint32_t maxlen = tabs->maxlen;
-  for (uint32_t L = 1; L <= maxlen; ++L) {
-    if (h < tabs->lim_half[L]) {
-      if (!tabs->cnt[L]) return 0;
-      const uint64_t v = (h << 1) >> (64 - L);
-      const uint64_t k = v - tabs->first[L];
-      if (k >= tabs->cnt[L]) return 0;
-      *sym = syms[tabs->off[L] + (uint32_t)k];
-      return L;
-    }
-  }
+/* Top 32 bits of the canonical code's per-length limits: a window whose
+ * top 32 bits are >= top[L] starts with a codeword longer than L (exact
+ * for L <= 32; a limit of 2^64 is stored as 0xffffffff, which only the
+ * exact fallback in long_len resolves). */
+struct Limits {
+  uint32_t top[kRegMax + 1];
+};
+
+/* Length of the codeword heading window V, known to be at least kFrom bits
+ * long; 0 if invalid.  The register compares are exact below kRegMax; a
+ * count that reaches kRegMax (a code that long, a saturated limit or an
+ * invalid window) is decided again with the exact 64-bit limits. */
+template <uint32_t kFrom>
+__device__ __forceinline__ uint32_t long_len(uint64_t V, const Limits& lim,
+                                             const DecTables* tabs,
+                                             uint32_t maxlen) {
+  const uint32_t top = (uint32_t)(V >> 32);
+  uint32_t len = kFrom;
+#pragma unroll
+  for (uint32_t L = kFrom; L < kRegMax; ++L) len += top >= lim.top[L] ? 1u : 0u;
+  if (len < kRegMax) return len <= maxlen ? len : maxlen;
+  const uint64_t h = V >> 1;
+  for (uint32_t L = kFrom; L <= maxlen; ++L)
+    if (h < tabs->lim_half[L]) return tabs->cnt[L] ? L : 0;
   return 0;
 }
 
-/* Decode the codeword at the reader; returns its length (advancing) and
- * symbol (kInvalidSym for an invalid prefix, which advances one bit). */
-__device__ __forceinline__ uint32_t decode_one(BitReader& br,
-                                               const DecShared& sh,
-                                               const DecTables* tabs,
-                                               const uint32_t* syms) {
-  const uint32_t e = sh.l1[(uint32_t)(br.buf >> (64 - kL1Bits))];
-  const uint32_t lb = e & 0xff;
-  uint32_t len = 0, sym = kInvalidSym;
-  if (lb && !(lb & 0x80u)) {
-    len = lb;
-    sym = e >> 8;
-  } else if (lb & 0x80u) {
-    const uint32_t sb = lb & 0x7fu;
-    const uint32_t e2 =
-        sh.sub[(e >> 8) + (uint32_t)((br.buf << kL1Bits) >> (64 - sb))];
-    if (e2) {
-      len = kL1Bits + (e2 & 0xff);
-      sym = e2 >> 8;
-    }
+/* Length and symbol-0 flag of the codeword at the reader.  The buffer holds
+ * at least 33 valid bits: a prefix-free code decodes any length up to that
+ * from it, and a longer or invalid result is decided again from memory. */
+__device__ __forceinline__ uint32_t walk_len(const BitReader& br,
+                                             const Limits& lim,
+                                             const DecShared& sh,
+                                             const DecTables* tabs,
+                                             uint32_t maxlen, uint32_t zlen,
+                                             uint64_t zcode, bool* zero) {
+  const uint32_t e = sh.lz[(uint32_t)(br.buf >> (64 - kLenBits))];
+  if (e & 0x3f) {
+    *zero = (e & 0x80) != 0;
+    return e & 0x3f;
   }
+  uint64_t V = br.buf;
+  uint32_t len = long_len<kLenBits + 1>(V, lim, tabs, maxlen);
+  if (len == 0 || (int)len > br.nb) {
+    V = br.window();
+    len = long_len<kLenBits + 1>(V, lim, tabs, maxlen);
+  }
+  *zero = len && len == zlen && (V >> (64 - len)) == zcode;
+  return len;
+}
+
+/* Symbol and length of the codeword at the reader. */
+__device__ __forceinline__ uint32_t read_sym(const BitReader& br,
+                                             const Limits& lim,
+                                             const DecShared& sh,
+                                             const DecTables* tabs,
+                                             const uint32_t* syms,
+                                             uint32_t maxlen,
+                                             uint32_t* len_out) {
+  const uint32_t e = sh.lz[(uint32_t)(br.buf >> (64 - kLenBits))];
+  uint32_t len = e & 0x3f;
+  if (len && len <= kSymBits) {
+    *len_out = len;
+    return sh.sym[(uint32_t)(br.buf >> (64 - kSymBits))];
+  }
+  uint64_t V = br.buf;
   if (!len) {
-    len = slow_code(br, tabs, syms, &sym);
-    if (!len) {
-      len = 1;
-      sym = kInvalidSym;
+    len = long_len<kLenBits + 1>(V, lim, tabs, maxlen);
+    if (len == 0 || (int)len > br.nb) {
+      V = br.window();
+      len = long_len<kLenBits + 1>(V, lim, tabs, maxlen);
     }
   }
-  br.advance(len);
-  return sym;
+  *len_out = len;
+  if (!len) return kInvalidSym;
+  const uint64_t r = (V >> (64 - len)) - sh.first[len];
+  if (r >= tabs->cnt[len]) return kInvalidSym; /* past the last code */
+  return syms[sh.off[len] + (uint32_t)r];
 }
 
 __device__ __forceinline__ void block_exclusive_scan2(uint32_t* a, uint32_t* b,
@@ -177,10 +209,35 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     uint16_t* __restrict__ codes, uint32_t* __restrict__ upos,
     uint32_t* status) {
   __shared__ DecShared sh;
-  for (uint32_t i = threadIdx.x; i < (1u << kL1Bits); i += kDecWG)
-    sh.l1[i] = tabs->l1[i];
-  const uint32_t n_sub = tabs->n_sub;
-  for (uint32_t i = threadIdx.x; i < n_sub; i += kDecWG) sh.sub[i] = tabs->sub[i];
+  /* Length table from the canonical limits: for L <= kLenBits the limit is
+   * a multiple of 2^(64 - kLenBits), so the first kLenBits bits decide it
+   * exactly.  Symbol 0 is flagged from its own code. */
+  const uint32_t zlen = tabs->zlen;
+  const uint64_t zcode = tabs->zcode;
+  for (uint32_t i = threadIdx.x; i < (1u << kLenBits); i += kDecWG) {
+    const uint64_t h = (uint64_t)i << (63 - kLenBits);
+    uint32_t len = 0;
+    for (uint32_t L = 1; L <= kLenBits; ++L)
+      if (h < tabs->lim_half[L]) {
+        len = tabs->cnt[L] ? L : 0;
+        break;
+      }
+    const bool z = len && len == zlen && (i >> (kLenBits - len)) == zcode;
+    sh.lz[i] = (uint8_t)(len | (z ? 0x80u : 0u));
+  }
+  for (uint32_t i = threadIdx.x; i < (1u << kSymBits); i += kDecWG)
+    sh.sym[i] = (uint16_t)(tabs->lut[i] >> 8);
+  for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxCodeLen; i += kDecWG) {
+    sh.first[i] = tabs->first[i];
+    sh.off[i] = tabs->off[i];
+  }
+  const uint32_t maxlen = tabs->maxlen;
+  Limits lim;
+#pragma unroll
+  for (uint32_t L = 0; L <= kRegMax; ++L) {
+    const uint64_t h = tabs->lim_half[L];
+    lim.top[L] = h >= (1ull << 63) ? 0xffffffffu : (uint32_t)(h >> 31);
+  }
   if (threadIdx.x == 0) sh.bad = 0;
   __syncthreads();
 
@@ -218,21 +275,24 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     const uint32_t s_hi = mine ? (s_lo + sub < nbits ? s_lo + sub : nbits) : 0;
     __syncthreads();
 
-    /* 1: speculative decode from the nominal start, with the boundary and
-     * zero-symbol maps of the first 64 bits */
+    /* 1: walk from the nominal start */
     uint64_t bmap = 0, zmap = 0;
     uint32_t spec_n = 0, spec_z = 0, spec_exit = 0;
     if (mine) {
       br.seek(s_lo);
       while (br.pos < s_hi) {
         const uint32_t rel = br.pos - s_lo;
-        const uint32_t s = decode_one(br, sh, tabs, syms);
+        bool zero;
+        uint32_t len =
+            walk_len(br, lim, sh, tabs, maxlen, zlen, zcode, &zero);
+        if (!len) len = 1;
         if (rel < 64) {
           bmap |= 1ull << rel;
-          if (s == 0) zmap |= 1ull << rel;
+          if (zero) zmap |= 1ull << rel;
         }
-        spec_z += s == 0 ? 1u : 0u;
+        spec_z += zero ? 1u : 0u;
         ++spec_n;
+        br.advance(len);
       }
       spec_exit = br.pos;
       sh.start[i] = s_lo;
@@ -261,9 +321,13 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
             synced = true;
             break;
           }
-          const uint32_t s = decode_one(br, sh, tabs, syms);
-          z += s == 0 ? 1u : 0u;
+          bool zero;
+          uint32_t len =
+              walk_len(br, lim, sh, tabs, maxlen, zlen, zcode, &zero);
+          if (!len) len = 1;
+          z += zero ? 1u : 0u;
           ++n;
+          br.advance(len);
         }
         if (!synced) ex = br.pos;
         sh.start[i] = want;
@@ -280,7 +344,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
       if (!again) break;
     }
 
-    /* 3: offsets, then the final decode into LDS */
+    /* 3: offsets, then the final decode straight to the bin array */
     uint32_t off_n, off_z, tot_n;
     block_exclusive_scan2(sh.scan_c, sh.scan_z, mine ? sh.count[i] : 0,
                           mine ? sh.zeros[i] : 0, &off_n, &off_z, &tot_n);
@@ -290,18 +354,20 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
       br.seek(sh.start[i]);
       const uint32_t n = sh.count[i];
       for (uint32_t k = 0; k < n && off_n < nsym; ++k, ++off_n) {
-        const uint32_t s = decode_one(br, sh, tabs, syms);
+        uint32_t len;
+        const uint32_t s = read_sym(br, lim, sh, tabs, syms, maxlen, &len);
         if (s == kInvalidSym) {
           bad = true;
           break;
         }
-        sh.out[off_n] = (uint16_t)s;
+        codes[base + off_n] = (uint16_t)s;
         if (s == 0) {
           const uint32_t rank = u0 + off_z;
           if (rank < u1) upos[rank] = (uint32_t)(base + off_n);
           ++off_z;
           ++valid_zeros;
         }
+        br.advance(len);
         if (off_n + 1 == nsym && br.pos > nbits) bad = true;
       }
     }
@@ -313,8 +379,6 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
       for (uint32_t t = 0; t < kDecWG; ++t) z += sh.scan_c[t];
       if (z != u1 - u0) sh.bad = 1;
     }
-    for (uint32_t k = threadIdx.x; k < nsym; k += kDecWG)
-      codes[base + k] = sh.out[k];
     __syncthreads();
   }
   __syncthreads();
@@ -328,7 +392,7 @@ void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint32_t* syms, uint16_t* codes,
                         uint32_t* upos, uint32_t* status, hipStream_t s) {
   if (!n_chunks) return;
-  uint64_t blocks = n_chunks < 768 ? n_chunks : 768; /* 3 per CU */
+  uint64_t blocks = n_chunks < 1024 ? n_chunks : 1024; /* 4 per CU */
   hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecWG), 0,
                      s, payload, n_words, coff, upre, n_chunks, n_codes,
                      n_unpred, tabs, syms, codes, upos, status);
