@@ -5,10 +5,13 @@
  * Reading (the paper fixes no container): a 184-byte little-endian header,
  * then 8-byte-aligned sections: anchors f32[A]; codebook symbols u16[U_s]
  * (ascending) and lengths u8[U_s]; chunk word offsets u64[C+1]; number of
- * unpredictable values before each chunk u32[C+1]; unpredictable values
- * f32[U]; Huffman payload u32[W], each chunk of 4096 bins starting on a word
- * boundary and packed most-significant bit first.  No dictionary (zstd)
- * stage follows the Huffman stage.
+ * unpredictable values before each chunk u32[C+1]; segment bit lengths
+ * u16[7 C]; unpredictable values f32[U]; Huffman payload u32[W], each chunk
+ * of 4096 bins starting on a word boundary and packed most-significant bit
+ * first.  A chunk is cut into eight segments of 512 bins; the stream keeps
+ * the payload bits of its first seven (0 for a segment past the last bin),
+ * so each segment can be decoded on its own.  No dictionary (zstd) stage
+ * follows the Huffman stage.
  */
 #include <cmath>
 #include <cstring>
@@ -27,8 +30,12 @@ struct Counts {
 };
 
 struct Layout {
-  size_t anchors, syms, lens, coff, upre, unpred, payload, total;
+  size_t anchors, syms, lens, coff, upre, segs, unpred, payload, total;
 };
+
+const uint32_t kSegPerChunk = QREF_CHUNK / QREF_SEG;
+const uint32_t kSegLog2 = 9;
+static_assert((1u << kSegLog2) == QREF_SEG, "segment size");
 
 size_t al8(size_t v) { return (v + 7) & ~(size_t)7; }
 
@@ -45,6 +52,8 @@ Layout layout_of(const Counts& c) {
   off = al8(off + 8 * (c.n_chunks + 1));
   l.upre = off;
   off = al8(off + 4 * (c.n_chunks + 1));
+  l.segs = off;
+  off = al8(off + 2 * (kSegPerChunk - 1) * c.n_chunks);
   l.unpred = off;
   off = al8(off + 4 * c.n_unpred);
   l.payload = off;
@@ -80,7 +89,8 @@ extern "C" int qref_compress_bound(qref_shape shape, uint32_t anchor_stride,
   uint64_t cmax = (N + QREF_CHUNK - 1) / QREF_CHUNK;
   uint64_t wmax = (N + 1) / 2 + cmax;
   size_t b = kHeader + 4 * N + 8 + al8(2 * 65536) + al8(65536) +
-             8 * (cmax + 1) + al8(4 * (cmax + 1)) + 8 + 4 * wmax + 64;
+             8 * (cmax + 1) + al8(4 * (cmax + 1)) +
+             al8(2 * (kSegPerChunk - 1) * cmax) + 8 + 4 * wmax + 64;
   *bytes = b;
   return QREF_OK;
 }
@@ -134,6 +144,7 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   /* chunked MSB-first packing */
   std::vector<uint64_t> coff(c.n_chunks + 1);
   std::vector<uint32_t> upre(c.n_chunks + 1);
+  std::vector<uint16_t> segs((kSegPerChunk - 1) * c.n_chunks, 0);
   std::vector<uint32_t> words;
   uint64_t zeros = 0;
   for (uint64_t ch = 0; ch < c.n_chunks; ++ch) {
@@ -146,6 +157,9 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
     for (uint64_t i = lo; i < hi; ++i) {
       int32_t s = codes[i];
       if (s == 0) ++zeros;
+      const uint64_t j = (i - lo) / QREF_SEG;
+      if (j + 1 < kSegPerChunk)
+        segs[ch * (kSegPerChunk - 1) + j] += (uint16_t)len[s];
       for (int b = len[s] - 1; b >= 0; --b) {
         uint32_t bit = (uint32_t)((code[s] >> b) & 1u);
         size_t wi = base + bitpos / 32;
@@ -167,9 +181,9 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   uint8_t* o = (uint8_t*)out;
   std::memset(o, 0, lay.total);
   std::memcpy(o, "QOZ1", 4);
-  put<uint16_t>(o, 4, 1);
+  put<uint16_t>(o, 4, 2);
   put<uint8_t>(o, 6, (uint8_t)g.d);
-  put<uint8_t>(o, 7, 0);
+  put<uint8_t>(o, 7, (uint8_t)kSegLog2);
   for (int i = 0; i < 3; ++i)
     put<uint64_t>(o, 8 + 8 * i, (uint64_t)(i < g.d ? g.n[i] : 1));
   put<double>(o, 32, e);
@@ -203,6 +217,8 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
     put<uint64_t>(o, lay.coff + 8 * ch, coff[ch]);
     put<uint32_t>(o, lay.upre + 4 * ch, upre[ch]);
   }
+  for (size_t k = 0; k < segs.size(); ++k)
+    put<uint16_t>(o, lay.segs + 2 * k, segs[k]);
   std::memcpy(o + lay.unpred, unpred.data(), 4 * n_unpred);
   std::memcpy(o + lay.payload, words.data(), 4 * c.n_words);
   *out_bytes = lay.total;
@@ -223,7 +239,8 @@ struct Parsed {
 int parse(const uint8_t* in, size_t n, Parsed* P) {
   if (!in || n < kHeader) return QREF_EFORMAT;
   if (std::memcmp(in, "QOZ1", 4) != 0) return QREF_EFORMAT;
-  if (get<uint16_t>(in, 4) != 1) return QREF_EFORMAT;
+  if (get<uint16_t>(in, 4) != 2) return QREF_EFORMAT;
+  if (get<uint8_t>(in, 7) != kSegLog2) return QREF_EFORMAT;
   qref_shape sh;
   std::memset(&sh, 0, sizeof(sh));
   sh.ndim = get<uint8_t>(in, 6);
@@ -345,7 +362,24 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
     uint64_t bitpos = 0;
     uint64_t lo = ch * QREF_CHUNK;
     uint64_t hi = std::min<uint64_t>(lo + QREF_CHUNK, c.n_codes);
+    /* segment j must start where the bit lengths of 0..j-1 say, and a
+     * segment past the last bin has length 0 */
+    uint64_t seg_end = 0;
+    for (uint32_t j = 0; j + 1 < kSegPerChunk; ++j) {
+      const uint16_t b =
+          get<uint16_t>(in, lay.segs + 2 * (ch * (kSegPerChunk - 1) + j));
+      if (lo + (uint64_t)j * QREF_SEG >= hi && b != 0) return QREF_EFORMAT;
+    }
     for (uint64_t i = lo; i < hi; ++i) {
+      if ((i - lo) % QREF_SEG == 0) {
+        if (bitpos != seg_end) return QREF_EFORMAT;
+        const uint64_t j = (i - lo) / QREF_SEG;
+        if (j + 1 < kSegPerChunk)
+          seg_end += get<uint16_t>(
+              in, lay.segs + 2 * (ch * (kSegPerChunk - 1) + j));
+        else
+          seg_end = nbits;
+      }
       uint64_t v = 0;
       int l = 0;
       for (;;) {
@@ -362,6 +396,9 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
       codes[i] = s;
       if (s == 0) ++zeros;
     }
+    /* a last segment with a stored length must end exactly there */
+    if ((hi - lo - 1) / QREF_SEG + 1 < kSegPerChunk && bitpos != seg_end)
+      return QREF_EFORMAT;
   }
   if (get<uint64_t>(in, lay.coff + 8 * c.n_chunks) != c.n_words)
     return QREF_EFORMAT;

@@ -159,10 +159,12 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                          hipMemcpyDeviceToDevice, s));
   SweepTable tbl;
   fill_sweep_table(P, &tbl);
-  PROF(PK_HUFF_ENC, 2.0 * P.n_codes + 4.0 * n_words + 4.0 * n_unpred,
+  PROF(PK_HUFF_ENC,
+       2.0 * P.n_codes + 4.0 * n_words + 8.0 * n_unpred + 26.0 * nch,
        launch_huff_encode(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
                           (const uint64_t*)c->coff.p,
                           (const uint32_t*)c->upre.p,
+                          (uint16_t*)(out + lay.segs),
                           (uint32_t*)(out + lay.payload),
                           (cap - lay.payload) / 4, (float*)(out + lay.unpred),
                           d_x, P.g, tbl, st, s));
@@ -300,10 +302,11 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   uint16_t* codes = (uint16_t*)c->codes.p;
   uint32_t* upos = (uint32_t*)c->upos.p;
   launch_init_status(st, s);
-  PROF(PK_HUFF_DEC, 4.0 * nw + 2.0 * P.n_codes,
+  PROF(PK_HUFF_DEC, 4.0 * nw + 2.0 * P.n_codes + 4.0 * nu + 26.0 * nch,
        launch_huff_decode((const uint32_t*)(in + lay.payload), nw,
                           (const uint64_t*)(in + lay.coff),
-                          (const uint32_t*)(in + lay.upre), nch, P.n_codes, nu,
+                          (const uint32_t*)(in + lay.upre),
+                          (const uint16_t*)(in + lay.segs), nch, P.n_codes, nu,
                           (const DecTables*)c->dec_tables.p,
                           (const uint32_t*)c->dec_syms.p, codes, upos, st, s));
   SweepTable tbl;

@@ -127,56 +127,17 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
       }
     if (t->cnt[l]) t->maxlen = (uint32_t)l;
   }
-  /* two-level table: 11-bit first level, per-prefix second level of up to
-   * 10 more bits (codes up to 21 bits), at most 2048 second-level entries */
-  {
-    const int kL1 = 11, kSubMax = 10;
-    const uint32_t kSubCap = 2048;
-    std::vector<uint32_t> pmax(1u << kL1, 0);
-    for (uint32_t i = 0; i < n_used; ++i) {
-      const uint32_t l = lens[i];
-      const uint64_t cv = code[syms[i]];
-      if (l <= (uint32_t)kL1) {
-        const uint32_t base = (uint32_t)(cv << (kL1 - l));
-        for (uint32_t k = 0; k < (1u << (kL1 - l)); ++k)
-          t->l1[base + k] = ((uint32_t)syms[i] << 8) | l;
-      } else {
-        const uint32_t p = (uint32_t)(cv >> (l - kL1));
-        if (l > pmax[p]) pmax[p] = l;
-      }
-    }
-    t->n_sub = 0;
-    for (uint32_t p = 0; p < (1u << kL1); ++p) {
-      if (!pmax[p]) continue;
-      uint32_t sb = pmax[p] - kL1;
-      if (sb > (uint32_t)kSubMax) sb = kSubMax;
-      if (t->n_sub + (1u << sb) > kSubCap) continue; /* left to lim_half */
-      t->l1[p] = (t->n_sub << 8) | 0x80u | sb;
-      t->n_sub += 1u << sb;
-    }
-    for (uint32_t i = 0; i < n_used; ++i) {
-      const uint32_t l = lens[i];
-      if (l <= (uint32_t)kL1) continue;
-      const uint64_t cv = code[syms[i]];
-      const uint32_t p = (uint32_t)(cv >> (l - kL1));
-      const uint32_t e = t->l1[p];
-      if (!(e & 0x80u)) continue;
-      const uint32_t sb = e & 0x7fu, base = e >> 8;
-      if (l - kL1 > sb) continue; /* longer than this subtable covers */
-      const uint32_t suffix = (uint32_t)(cv & ((1ull << (l - kL1)) - 1));
-      const uint32_t at = base + (suffix << (sb - (l - kL1)));
-      for (uint32_t k = 0; k < (1u << (sb - (l - kL1))); ++k)
-        t->sub[at + k] = ((uint32_t)syms[i] << 8) | (l - kL1);
-    }
-  }
+  /* Fast table: a code of length l <= kFastBits fills the
+   * 2^(kFastBits - l) entries that start with it; entries of longer (or
+   * invalid) codes stay 0. */
   for (uint32_t i = 0; i < n_used; ++i) {
-    uint32_t l = lens[i];
-    if (l > (uint32_t)kLutBits) continue;
-    uint64_t c = code[syms[i]];
-    uint32_t base = (uint32_t)(c << (kLutBits - l));
-    uint32_t span = 1u << (kLutBits - l);
-    for (uint32_t k = 0; k < span; ++k)
-      t->lut[base + k] = ((uint32_t)syms[i] << 8) | l;
+    const uint32_t l = lens[i];
+    if (l > (uint32_t)kFastBits) continue;
+    const uint32_t e =
+        ((uint32_t)syms[i] << 8) | (syms[i] == 0 ? 0x80u : 0u) | l;
+    const uint32_t base = (uint32_t)(code[syms[i]] << (kFastBits - l));
+    for (uint32_t k = 0; k < (1u << (kFastBits - l)); ++k)
+      t->fast[base + k] = e;
   }
   return true;
 }

@@ -196,7 +196,8 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
     const uint16_t* __restrict__ codes, uint64_t n,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, const uint64_t* __restrict__ coff,
-    const uint32_t* __restrict__ upre, uint32_t* payload, uint64_t cap_words,
+    const uint32_t* __restrict__ upre, uint16_t* __restrict__ segs,
+    uint32_t* payload, uint64_t cap_words,
     float* unpred, const float* __restrict__ x, Geo g, SweepTable st,
     uint32_t* status) {
   __shared__ uint32_t words[kEncMaxWords];
@@ -230,6 +231,18 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
   }
   uint32_t pos = sbits[threadIdx.x] - bits;
   uint32_t zr = upre[c] + szero[threadIdx.x] - zeros;
+  /* payload bits of segments 0..6: the last lane of each segment holds the
+   * inclusive bit count at the segment's end */
+  constexpr uint32_t kLanesPerSeg = kSeg / kEncPerThread;
+  static_assert(kLanesPerSeg * kEncPerThread == kSeg, "segment lanes");
+  if (threadIdx.x % kLanesPerSeg == kLanesPerSeg - 1) {
+    const uint32_t j = threadIdx.x / kLanesPerSeg;
+    if (j + 1 < kSegPerChunk) {
+      const uint32_t before = j ? sbits[j * kLanesPerSeg - 1] : 0u;
+      segs[(uint64_t)c * (kSegPerChunk - 1) + j] =
+          (uint16_t)(sbits[threadIdx.x] - before);
+    }
+  }
 #pragma unroll
   for (uint32_t k = 0; k < kEncPerThread; ++k) {
     uint32_t len = (uint32_t)(ent[k] & 0xff);
@@ -254,7 +267,8 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
 void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
-                        const uint32_t* upre, uint32_t* payload,
+                        const uint32_t* upre, uint16_t* segs,
+                        uint32_t* payload,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
                         uint32_t* status, hipStream_t s) {
@@ -262,8 +276,8 @@ void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
   if (!chunks) return;
   hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)chunks), dim3(kEncThreads),
                      0, s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
-                     coff, upre, payload, payload_cap_words, unpred, x, g, st,
-                     status);
+                     coff, upre, segs, payload, payload_cap_words, unpred, x,
+                     g, st, status);
 }
 
 }  // namespace qoz

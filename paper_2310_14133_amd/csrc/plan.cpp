@@ -168,7 +168,9 @@ void fill_sweep_table(const Plan& p, SweepTable* t) {
 /* Stream layout: header, then 8-byte-aligned sections in this order:
  * anchors f32, codebook symbols u16, codebook lengths u8, chunk word
  * offsets u64[chunks+1], unpredictable counts before each chunk
- * u32[chunks+1], unpredictable values f32, Huffman payload u32. */
+ * u32[chunks+1], payload bits of the first seven 512-bin segments of each
+ * chunk u16[7 chunks] (0 past the last bin), unpredictable values f32,
+ * Huffman payload u32. */
 static uint64_t up8(uint64_t v) { return (v + 7) / 8 * 8; }
 
 Layout layout_of(uint64_t n_anchor, uint64_t n_used, uint64_t n_chunks,
@@ -185,6 +187,8 @@ Layout layout_of(uint64_t n_anchor, uint64_t n_used, uint64_t n_chunks,
   o = up8(o + 8 * (n_chunks + 1));
   L.upre = o;
   o = up8(o + 4 * (n_chunks + 1));
+  L.segs = o;
+  o = up8(o + 2 * (kSegPerChunk - 1) * n_chunks);
   L.unpred = o;
   o = up8(o + 4 * n_unpred);
   L.payload = o;
@@ -207,9 +211,9 @@ void write_header(uint8_t* h, const Plan& p, uint64_t n_unpred,
                   uint64_t n_used, uint64_t n_words) {
   std::memset(h, 0, kHeaderBytes);
   std::memcpy(h, "QOZ1", 4);
-  wr<uint16_t>(h, 4, 1);
+  wr<uint16_t>(h, 4, kStreamVersion);
   wr<uint8_t>(h, 6, (uint8_t)p.d);
-  wr<uint8_t>(h, 7, 0);
+  wr<uint8_t>(h, 7, (uint8_t)kSegLog2);
   uint64_t dims[3] = {1, 1, 1};
   if (p.d == 2) {
     dims[0] = p.g.n[1];
@@ -242,7 +246,9 @@ qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* 
                         uint64_t* n_words) {
   if (in_bytes < kHeaderBytes) return fail(QOZ_EFORMAT, "stream too short");
   if (std::memcmp(h, "QOZ1", 4) != 0) return fail(QOZ_EFORMAT, "bad magic");
-  if (rd<uint16_t>(h, 4) != 1) return fail(QOZ_EFORMAT, "bad version");
+  if (rd<uint16_t>(h, 4) != kStreamVersion)
+    return fail(QOZ_EFORMAT, "bad version");
+  if (h[7] != kSegLog2) return fail(QOZ_EFORMAT, "unsupported segment size");
   qoz_shape sh;
   std::memset(&sh, 0, sizeof(sh));
   sh.ndim = h[6];

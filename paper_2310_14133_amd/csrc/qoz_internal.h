@@ -21,8 +21,12 @@ namespace qoz {
 constexpr int32_t kRadius = 32768;         /* bins on each side of zero */
 constexpr uint32_t kNSym = 2 * kRadius;    /* Huffman alphabet */
 constexpr uint32_t kChunk = 4096;          /* bins per Huffman chunk */
+constexpr uint32_t kSegLog2 = 9;           /* a chunk holds 8 segments of */
+constexpr uint32_t kSeg = 1u << kSegLog2;  /* 512 bins, each decodable alone */
+constexpr uint32_t kSegPerChunk = kChunk / kSeg;
 constexpr size_t kHeaderBytes = 184;
-constexpr int kLutBits = 12;               /* decoder fast-table width */
+constexpr uint16_t kStreamVersion = 2;
+constexpr int kFastBits = 13;              /* decoder table width */
 constexpr int kMaxCodeLen = 63;
 
 /* status word bits reported by kernels */
@@ -63,7 +67,7 @@ struct Plan {
 
 /* Byte offsets of the stream sections (see the stream layout notes). */
 struct Layout {
-  uint64_t anchors, syms, lens, coff, upre, unpred, payload, total;
+  uint64_t anchors, syms, lens, coff, upre, segs, unpred, payload, total;
 };
 
 /* Sweep table used by kernels that map a stream position back to a point. */
@@ -77,7 +81,9 @@ struct SweepTable {
 
 /* Canonical-Huffman decoding tables (device copy). */
 struct DecTables {
-  uint32_t lut[1u << kLutBits]; /* (symbol << 8) | length, 0 = long code */
+  /* indexed by the next kFastBits bits: (symbol << 8) | 0x80 if the
+   * symbol is 0 | code length; 0 for a longer (or invalid) code */
+  uint32_t fast[1u << kFastBits];
   uint64_t first[kMaxCodeLen + 1];
   uint32_t cnt[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
@@ -89,14 +95,6 @@ struct DecTables {
    * left-justified window V starts with a codeword longer than L iff
    * (V >> 1) >= lim_half[L] */
   uint64_t lim_half[kMaxCodeLen + 1];
-  /* two-level table: l1 indexed by the first 11 bits holds either
-   * (symbol << 8) | length for codes up to 11 bits, or, for prefixes of
-   * longer codes, (subtable base << 8) | 0x80 | subtable bits; sub entries
-   * hold (symbol << 8) | (length - 11); 0 marks a code longer than the
-   * tables cover (decoded from lim_half). */
-  uint32_t l1[1u << 11];
-  uint32_t n_sub;
-  uint32_t sub[2048];
 };
 
 /* Tuner: one level of a candidate parameter set on the sampled blocks. */
@@ -248,13 +246,14 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
 void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
-                        const uint32_t* upre, uint32_t* payload,
+                        const uint32_t* upre, uint16_t* segs,
+                        uint32_t* payload,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
                         uint32_t* status, hipStream_t s);
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
-                        uint64_t n_chunks, uint64_t n_codes,
+                        const uint16_t* segs, uint64_t n_chunks, uint64_t n_codes,
                         uint64_t n_unpred, const DecTables* tabs,
                         const uint32_t* syms, uint16_t* codes,
                         uint32_t* upos, uint32_t* status, hipStream_t s);

@@ -128,6 +128,8 @@ def test_stream_header_fields(ref):
     z = ref.compress(x, 0.01, p)
     assert bytes(z[:4]) == b"QOZ1"
     hdr = z[:184].tobytes()
+    assert int(np.frombuffer(hdr[4:6], np.uint16)[0]) == 2  # version
+    assert hdr[7] == 9                               # log2 segment size
     u64 = lambda o: int(np.frombuffer(hdr[o:o + 8], np.uint64)[0])
     u32 = lambda o: int(np.frombuffer(hdr[o:o + 4], np.uint32)[0])
     assert hdr[6] == 2
@@ -185,3 +187,52 @@ def test_long_codes_roundtrip(ref):
     assert ref.huffman_lengths(hist).max() >= 24
     z = ref.compress(x, 0.5, p)
     assert np.array_equal(ref.decompress(z), recon)
+
+
+def _segs_section(z):
+    """Offset of the segment table: header, then 8-aligned anchors f32,
+    symbols u16, lengths u8, chunk offsets u64[C+1], unpredictable
+    prefix u32[C+1]."""
+    u64 = lambda o: int(np.frombuffer(z[o:o + 8].tobytes(), np.uint64)[0])
+    al8 = lambda v: (v + 7) // 8 * 8
+    n_anchor, n_used, n_chunks = u64(136), u64(160), u64(168)
+    off = al8(184 + 4 * n_anchor)
+    off = al8(off + 2 * n_used)
+    off = al8(off + n_used)
+    off = al8(off + 8 * (n_chunks + 1))
+    off = al8(off + 4 * (n_chunks + 1))
+    return off, n_chunks
+
+
+@pytest.mark.parametrize("shape,rel", [((70, 90, 40), 1e-3), ((33, 1500), 1e-4)])
+def test_segment_table(ref, shape, rel):
+    """Each stored segment length is the sum of the Huffman code lengths of
+    its 512 bins (0 past the last bin), so a segment decodes on its own."""
+    x = fields.grf(shape, 4)
+    e = rel * (float(x.max()) - float(x.min()))
+    p = ref.make_params(x.ndim, "cubic", None, 1.25, 2.0)
+    z = ref.compress(x, e, p)
+    codes, _, _, _ = ref.predict_quantize(x, e, p)
+    hist = np.bincount(codes, minlength=65536).astype(np.uint64)
+    ln = ref.huffman_lengths(hist).astype(np.int64)
+    off, n_chunks = _segs_section(z)
+    segs = np.frombuffer(z[off:off + 14 * n_chunks].tobytes(), np.uint16)
+    segs = segs.reshape(n_chunks, 7).astype(np.int64)
+    per_bin = ln[codes]
+    pad = np.zeros(n_chunks * 4096, np.int64)
+    pad[:per_bin.size] = per_bin
+    want = pad.reshape(n_chunks, 8, 512).sum(axis=2)[:, :7]
+    assert n_chunks >= 2 and codes.size % 4096 != 0
+    assert np.array_equal(segs, want)
+    # a wrong length is rejected
+    bad = z.copy()
+    bad[off + 2] ^= 0x01
+    assert ref.decompress_status(bad) == ref.EFORMAT
+    # so is a nonzero length past the last bin
+    last = n_chunks - 1
+    tail_segs = -(-(codes.size - last * 4096) // 512)
+    if tail_segs < 7:
+        bad = z.copy()
+        k = off + 2 * (7 * last + 6)
+        bad[k] = 1
+        assert ref.decompress_status(bad) == ref.EFORMAT
