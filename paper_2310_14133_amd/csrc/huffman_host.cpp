@@ -127,17 +127,20 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
       }
     if (t->cnt[l]) t->maxlen = (uint32_t)l;
   }
-  /* Fast table: a code of length l <= kFastBits fills the
-   * 2^(kFastBits - l) entries that start with it; entries of longer (or
-   * invalid) codes stay 0. */
+  /* Fast tables: a code of length l fills the 2^(width - l) entries that
+   * start with it (l <= width); entries of longer (or invalid) codes stay 0
+   * in the length table. */
   for (uint32_t i = 0; i < n_used; ++i) {
     const uint32_t l = lens[i];
-    if (l > (uint32_t)kFastBits) continue;
-    const uint32_t e =
-        ((uint32_t)syms[i] << 8) | (syms[i] == 0 ? 0x80u : 0u) | l;
-    const uint32_t base = (uint32_t)(code[syms[i]] << (kFastBits - l));
-    for (uint32_t k = 0; k < (1u << (kFastBits - l)); ++k)
-      t->fast[base + k] = e;
+    if (l > (uint32_t)kLenBits) continue;
+    const uint64_t cv = code[syms[i]];
+    const uint8_t e = (uint8_t)(l | (syms[i] == 0 ? 0x80u : 0u));
+    const uint32_t base = (uint32_t)(cv << (kLenBits - l));
+    for (uint32_t k = 0; k < (1u << (kLenBits - l)); ++k) t->lz[base + k] = e;
+    if (l > (uint32_t)kSymBits) continue;
+    const uint32_t sbase = (uint32_t)(cv << (kSymBits - l));
+    for (uint32_t k = 0; k < (1u << (kSymBits - l)); ++k)
+      t->sym[sbase + k] = syms[i];
   }
   return true;
 }

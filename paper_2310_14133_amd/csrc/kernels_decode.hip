@@ -5,16 +5,19 @@
  * A chunk of 4096 bins is stored as eight segments of 512 bins whose bit
  * lengths the stream keeps, so every segment decodes on its own: one lane
  * per segment, eight lanes per chunk, a wave covers eight consecutive
- * chunks.  A lane streams its segment's payload words from global memory
- * into a 64-bit bit buffer through a queue of words loaded ahead, and looks
- * each codeword up in a 13-bit table in LDS holding symbol, length and a
- * symbol-0 flag.  Longer codes are sized by comparing the top 32 bits of the
- * buffer with the canonical code's per-length limits (held in registers) and
- * mapped to their symbol through the canonical order.  Bins are written
- * eight at a time (16-byte stores).  Symbol-0 bins (unpredictable values)
- * are counted per segment; a scan over the chunk's eight lanes ranks them
- * and their stream positions go to `upos`, so the exact values can be
- * placed before the inverse sweeps.
+ * chunks.  Each lane keeps its next payload words in a 16-word ring in LDS
+ * (word k of every lane's ring in one LDS row, so a wave's reads fall in
+ * distinct banks) and a 64-bit bit buffer refilled from it; global loads
+ * happen only at the ends of 8-bin groups, where a lane that has used half
+ * its ring fetches the next eight words into registers and, one group
+ * later, writes them over the used half.  Codewords are looked up in a
+ * 13-bit length table and a 12-bit symbol table in LDS; longer codes are
+ * sized by comparing the top 32 bits of the buffer with the canonical
+ * code's per-length limits (held in registers) and mapped to their symbol
+ * through the canonical order.  Bins are written eight at a time (16-byte
+ * stores).  Symbol-0 bins (unpredictable values) are counted per segment;
+ * a scan over the chunk's eight lanes ranks them and their stream positions
+ * go to `upos`, so the exact values can be placed before the inverse sweeps.
  *
  * Every payload read is bounded by the chunk's words (zero beyond).  The
  * stream is rejected if a chunk table entry is inconsistent, a segment does
@@ -30,12 +33,16 @@ constexpr uint32_t kDecWG = 256; /* 4 waves: 32 chunks */
 constexpr uint32_t kChunksPerWG = kDecWG / kSegPerChunk;
 constexpr uint32_t kRegMax = 27; /* longest code sized from registers */
 constexpr uint32_t kMaxChunkWords = kChunk * kMaxCodeLen / 32 + 2;
-constexpr uint32_t kSortedLds = 2048; /* canonical symbols kept in LDS */
+constexpr uint32_t kSortedLds = 1024; /* canonical symbols kept in LDS */
+constexpr uint32_t kRing = 16;        /* payload words per lane in LDS */
+constexpr uint32_t kHalf = kRing / 2;
 constexpr uint32_t kInvalid = 0xffffffffu;
 constexpr uint32_t kZeroCap = 4; /* symbol-0 positions kept per lane */
 
 struct DecShared {
-  uint32_t fast[1u << kFastBits];
+  uint32_t ring[kRing][kDecWG];
+  uint8_t lz[1u << kLenBits];
+  uint16_t sym[1u << kSymBits];
   uint16_t sorted[kSortedLds];
   uint64_t first[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
@@ -59,39 +66,31 @@ struct Words {
   }
 };
 
-/* MSB-first bit buffer: buf holds nb >= 33 valid bits from pos on; the
- * next four words after them wait in q0..q3 and wp is the word after q3. */
-struct Bits {
+/* One lane's reader: buf holds nb >= 33 valid bits from pos on; the ring
+ * holds words [B, B + kRing); wp is the next word to append to buf; pf
+ * holds words [B + kRing, B + kRing + kHalf) once fetched (pending). */
+struct Reader {
   uint64_t buf;
   int nb;
-  uint32_t pos, wp;
-  uint32_t q0, q1, q2, q3;
+  uint32_t pos, wp, B;
+  bool pending;
+  uint32_t pf[kHalf];
 
-  __device__ __forceinline__ void seek(const Words& W, uint32_t p) {
+  __device__ __forceinline__ void seek(DecShared& sh, const Words& W,
+                                       uint32_t p) {
     pos = p;
     const uint32_t wi = p >> 5, o = p & 31;
-    buf = (((uint64_t)W(wi) << 32) | W(wi + 1)) << o;
+    uint32_t v[kRing];
+#pragma unroll
+    for (uint32_t k = 0; k < kRing; ++k) v[k] = W(wi + k);
+#pragma unroll
+    for (uint32_t k = 0; k < kRing; ++k)
+      sh.ring[(wi + k) % kRing][threadIdx.x] = v[k];
+    buf = (((uint64_t)v[0] << 32) | v[1]) << o;
     nb = 64 - (int)o;
-    q0 = W(wi + 2);
-    q1 = W(wi + 3);
-    q2 = W(wi + 4);
-    q3 = W(wi + 5);
-    wp = wi + 6;
-  }
-  /* consume len <= 32 bits */
-  __device__ __forceinline__ void take(const Words& W, uint32_t len) {
-    buf <<= len;
-    nb -= (int)len;
-    pos += len;
-    if (nb <= 32) {
-      buf |= (uint64_t)q0 << (32 - nb);
-      nb += 32;
-      q0 = q1;
-      q1 = q2;
-      q2 = q3;
-      q3 = W(wp);
-      ++wp;
-    }
+    wp = wi + 2;
+    B = wi;
+    pending = false;
   }
   /* the 64 bits at pos, from memory */
   __device__ __forceinline__ uint64_t window(const Words& W) const {
@@ -99,32 +98,50 @@ struct Bits {
     const uint64_t a = W(wi), b = W(wi + 1), c = W(wi + 2);
     return (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
   }
+  /* end of an 8-bin group: move fetched words into the used half, fetch
+   * the next ones once half the ring is used */
+  __device__ __forceinline__ void group_end(DecShared& sh, const Words& W) {
+    if (pending && wp >= B + kHalf) {
+#pragma unroll
+      for (uint32_t k = 0; k < kHalf; ++k)
+        sh.ring[(B + k) % kRing][threadIdx.x] = pf[k];
+      B += kHalf;
+      pending = false;
+    }
+    if (!pending && wp >= B + kHalf / 2) {
+#pragma unroll
+      for (uint32_t k = 0; k < kHalf; ++k) pf[k] = W(B + kRing + k);
+      pending = true;
+    }
+  }
 };
 
-/* Symbol of the codeword at the buffer, longer than kFastBits bits (or
- * invalid): kInvalid if invalid, else the symbol with *len_out set. */
+/* Symbol and length of a codeword the fast tables do not resolve (longer
+ * than kSymBits bits, or invalid): kInvalid if invalid. */
 __device__ __forceinline__ uint32_t slow_symbol(
-    const Bits& bt, const Words& W, const Limits& lim, const DecShared& sh,
-    const DecTables* __restrict__ tabs, const uint32_t* __restrict__ syms,
-    uint32_t maxlen, uint32_t* len_out) {
-  const uint32_t top = (uint32_t)(bt.buf >> 32);
-  uint32_t len = kFastBits + 1;
+    const Reader& rd, const Words& W, uint32_t len, const Limits& lim,
+    const DecShared& sh, const DecTables* __restrict__ tabs,
+    const uint32_t* __restrict__ syms, uint32_t maxlen, uint32_t* len_out) {
+  const uint32_t top = (uint32_t)(rd.buf >> 32);
+  uint64_t V = rd.buf;
+  if (len == 0) { /* longer than kLenBits */
+    len = kLenBits + 1;
 #pragma unroll
-  for (uint32_t L = kFastBits + 1; L < kRegMax; ++L)
-    len += top >= lim.top[L] ? 1u : 0u;
-  uint64_t V = bt.buf;
-  if (len < kRegMax) {
-    len = len <= maxlen ? len : maxlen;
-  } else { /* a code of kRegMax bits or more, or a saturated limit */
-    V = bt.window(W);
-    const uint64_t h = V >> 1;
-    len = 0;
-    for (uint32_t L = kFastBits + 1; L <= maxlen; ++L)
-      if (h < tabs->lim_half[L]) {
-        len = sh.cnt[L] ? L : 0;
-        break;
-      }
-    if (!len) return kInvalid;
+    for (uint32_t L = kLenBits + 1; L < kRegMax; ++L)
+      len += top >= lim.top[L] ? 1u : 0u;
+    if (len < kRegMax) {
+      len = len <= maxlen ? len : maxlen;
+    } else { /* a code of kRegMax bits or more, or a saturated limit */
+      V = rd.window(W);
+      const uint64_t h = V >> 1;
+      len = 0;
+      for (uint32_t L = kLenBits + 1; L <= maxlen; ++L)
+        if (h < tabs->lim_half[L]) {
+          len = sh.cnt[L] ? L : 0;
+          break;
+        }
+      if (!len) return kInvalid;
+    }
   }
   const uint64_t r = (V >> (64 - len)) - sh.first[len];
   if (r >= sh.cnt[len]) return kInvalid; /* past the last code */
@@ -158,9 +175,13 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     uint32_t* __restrict__ upos, uint32_t* status) {
   __shared__ DecShared sh;
   {
-    const uint4* src = reinterpret_cast<const uint4*>(tabs->fast);
-    uint4* dst = reinterpret_cast<uint4*>(sh.fast);
-    for (uint32_t i = threadIdx.x; i < (1u << kFastBits) / 4; i += kDecWG)
+    const uint4* src = reinterpret_cast<const uint4*>(tabs->lz);
+    uint4* dst = reinterpret_cast<uint4*>(sh.lz);
+    for (uint32_t i = threadIdx.x; i < sizeof(sh.lz) / 16; i += kDecWG)
+      dst[i] = src[i];
+    src = reinterpret_cast<const uint4*>(tabs->sym);
+    dst = reinterpret_cast<uint4*>(sh.sym);
+    for (uint32_t i = threadIdx.x; i < sizeof(sh.sym) / 16; i += kDecWG)
       dst[i] = src[i];
   }
   const uint32_t n_used = tabs->n_used;
@@ -216,24 +237,36 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
   const uint32_t n_run = have && !bad ? seg_n : 0u;
   uint32_t nz = 0, zp01 = 0, zp23 = 0, t = 0;
   bool inv = false;
-  Bits bt;
-  bt.seek(W, start);
+  Reader rd;
+  rd.seek(sh, W, start);
   /* one codeword; an invalid one is flagged and skipped as one bit */
   auto step = [&]() -> uint32_t {
-    const uint32_t e = sh.fast[(uint32_t)(bt.buf >> (64 - kFastBits))];
-    uint32_t len = e & 0x3fu, s = e >> 8;
-    if (__builtin_expect(len == 0, 0)) {
-      s = slow_symbol(bt, W, lim, sh, tabs, syms, maxlen, &len);
+    const uint32_t hi = (uint32_t)(rd.buf >> 32);
+    const uint32_t e = sh.lz[hi >> (32 - kLenBits)];
+    uint32_t s = sh.sym[hi >> (32 - kSymBits)];
+    uint32_t nx = sh.ring[rd.wp % kRing][threadIdx.x];
+    uint32_t len = e & 0x3fu;
+    if (__builtin_expect(len == 0 || len > (uint32_t)kSymBits, 0)) {
+      s = slow_symbol(rd, W, len, lim, sh, tabs, syms, maxlen, &len);
       if (s == kInvalid) {
         inv = true;
         s = 1;
         len = 1;
       }
     }
-    if (__builtin_expect(len <= 32, 1))
-      bt.take(W, len);
-    else
-      bt.seek(W, bt.pos + len);
+    if (__builtin_expect(len <= 32, 1)) {
+      rd.buf <<= len;
+      rd.nb -= (int)len;
+      rd.pos += len;
+      const bool need = rd.nb <= 32;
+      if (__builtin_expect(need && rd.wp >= rd.B + kRing, 0))
+        nx = W(rd.wp); /* ring used up by long codes */
+      rd.buf |= (uint64_t)(need ? nx : 0u) << ((uint32_t)(32 - rd.nb) & 31u);
+      rd.wp += need ? 1u : 0u;
+      rd.nb += need ? 32 : 0;
+    } else {
+      rd.seek(sh, W, rd.pos + len);
+    }
     if (__builtin_expect(s == 0, 0)) {
       if (nz < kZeroCap) {
         const uint32_t v = t << ((nz & 1u) * 16);
@@ -255,6 +288,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
       const uint32_t lo = step();
       pk[u >> 1] = lo | (step() << 16);
     }
+    rd.group_end(sh, W);
     *reinterpret_cast<uint4*>(codes + out0 + t - 8) =
         make_uint4(pk[0], pk[1], pk[2], pk[3]);
   }
@@ -264,7 +298,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
   }
   if (have && !bad) {
     const uint32_t end = j + 1 < kSegPerChunk ? start + d : nbits;
-    if (inv || (j + 1 < kSegPerChunk ? bt.pos != end : bt.pos > end))
+    if (inv || (j + 1 < kSegPerChunk ? rd.pos != end : rd.pos > end))
       bad = true;
   }
 

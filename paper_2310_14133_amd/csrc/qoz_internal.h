@@ -26,7 +26,8 @@ constexpr uint32_t kSeg = 1u << kSegLog2;  /* 512 bins, each decodable alone */
 constexpr uint32_t kSegPerChunk = kChunk / kSeg;
 constexpr size_t kHeaderBytes = 184;
 constexpr uint16_t kStreamVersion = 2;
-constexpr int kFastBits = 13;              /* decoder table width */
+constexpr int kLenBits = 13;               /* decoder length-table width */
+constexpr int kSymBits = 12;               /* decoder symbol-table width */
 constexpr int kMaxCodeLen = 63;
 
 /* status word bits reported by kernels */
@@ -81,9 +82,11 @@ struct SweepTable {
 
 /* Canonical-Huffman decoding tables (device copy). */
 struct DecTables {
-  /* indexed by the next kFastBits bits: (symbol << 8) | 0x80 if the
-   * symbol is 0 | code length; 0 for a longer (or invalid) code */
-  uint32_t fast[1u << kFastBits];
+  /* indexed by the next kLenBits bits: code length | 0x80 if the code is
+   * symbol 0's; 0 for a longer (or invalid) code */
+  uint8_t lz[1u << kLenBits];
+  /* indexed by the next kSymBits bits: the symbol of codes that short */
+  uint16_t sym[1u << kSymBits];
   uint64_t first[kMaxCodeLen + 1];
   uint32_t cnt[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
