@@ -57,18 +57,45 @@ struct Limits {
   uint32_t top[kRegMax + 1];
 };
 
-/* The words of one chunk, zero past its end. */
+/* four payload words; a word-aligned 16-byte load */
+struct __attribute__((aligned(4))) Quad {
+  uint32_t x, y, z, w;
+};
+
+/* The words of one chunk, zero past its end; `room` is the number of
+ * payload words from the chunk start to the end of the payload, so a block
+ * below it can be read with wide loads. */
 struct Words {
   const uint32_t* w;
-  uint32_t nw;
+  uint32_t nw, room;
   __device__ __forceinline__ uint32_t operator()(uint32_t i) const {
     return i < nw ? w[i] : 0u;
+  }
+  /* words i .. i + 4n - 1 into v */
+  template <uint32_t n>
+  __device__ __forceinline__ void block(uint32_t i, uint32_t* v) const {
+    if (i + 4 * n <= room) {
+#pragma unroll
+      for (uint32_t k = 0; k < n; ++k) {
+        const Quad q = *reinterpret_cast<const Quad*>(w + i + 4 * k);
+        v[4 * k] = i + 4 * k < nw ? q.x : 0u;
+        v[4 * k + 1] = i + 4 * k + 1 < nw ? q.y : 0u;
+        v[4 * k + 2] = i + 4 * k + 2 < nw ? q.z : 0u;
+        v[4 * k + 3] = i + 4 * k + 3 < nw ? q.w : 0u;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < 4 * n; ++k) v[k] = (*this)(i + k);
+    }
   }
 };
 
 /* One lane's reader: buf holds nb >= 33 valid bits from pos on; the ring
  * holds words [B, B + kRing); wp is the next word to append to buf; pf
- * holds words [B + kRing, B + kRing + kHalf) once fetched (pending). */
+ * holds words [B + kRing, B + kRing + kHalf), always in flight.  A step
+ * appends at most one word, and the group end slides the ring whenever
+ * wp - B >= kHalf, so wp - B <= 7 when a group starts and every ring read
+ * in its eight steps is of a word the ring holds. */
 struct Reader {
   uint64_t buf;
   int nb;
@@ -81,8 +108,8 @@ struct Reader {
     pos = p;
     const uint32_t wi = p >> 5, o = p & 31;
     uint32_t v[kRing];
-#pragma unroll
-    for (uint32_t k = 0; k < kRing; ++k) v[k] = W(wi + k);
+    W.block<kRing / 4>(wi, v);
+    W.block<kHalf / 4>(wi + kRing, pf);
 #pragma unroll
     for (uint32_t k = 0; k < kRing; ++k)
       sh.ring[(wi + k) % kRing][threadIdx.x] = v[k];
@@ -90,7 +117,7 @@ struct Reader {
     nb = 64 - (int)o;
     wp = wi + 2;
     B = wi;
-    pending = false;
+    pending = true;
   }
   /* the 64 bits at pos, from memory */
   __device__ __forceinline__ uint64_t window(const Words& W) const {
@@ -98,8 +125,8 @@ struct Reader {
     const uint64_t a = W(wi), b = W(wi + 1), c = W(wi + 2);
     return (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
   }
-  /* end of an 8-bin group: move fetched words into the used half, fetch
-   * the next ones once half the ring is used */
+  /* end of an 8-bin group: once the first half of the ring is used, move
+   * the fetched words over it; keep the next half always in flight */
   __device__ __forceinline__ void group_end(DecShared& sh, const Words& W) {
     if (pending && wp >= B + kHalf) {
 #pragma unroll
@@ -108,9 +135,8 @@ struct Reader {
       B += kHalf;
       pending = false;
     }
-    if (!pending && wp >= B + kHalf / 2) {
-#pragma unroll
-      for (uint32_t k = 0; k < kHalf; ++k) pf[k] = W(B + kRing + k);
+    if (!pending) {
+      W.block<kHalf / 4>(B + kRing, pf);
       pending = true;
     }
   }
@@ -232,7 +258,8 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
   if (have && (start > nbits || (seg_n == 0 && d != 0))) bad = true;
 
   /* decode */
-  const Words W{payload + w0, have && !bad ? nw : 0u};
+  const Words W{payload + w0, have && !bad ? nw : 0u,
+                have && !bad ? (uint32_t)(n_words - w0) : 0u};
   const uint64_t out0 = c * kChunk + seg_lo;
   const uint32_t n_run = have && !bad ? seg_n : 0u;
   uint32_t nz = 0, zp01 = 0, zp23 = 0, t = 0;
@@ -253,20 +280,20 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
         s = 1;
         len = 1;
       }
+      /* a code longer than the buffer's guaranteed bits: seek past it */
+      if (len > 32) {
+        rd.seek(sh, W, rd.pos + len);
+        len = 0;
+        nx = 0;
+      }
     }
-    if (__builtin_expect(len <= 32, 1)) {
-      rd.buf <<= len;
-      rd.nb -= (int)len;
-      rd.pos += len;
-      const bool need = rd.nb <= 32;
-      if (__builtin_expect(need && rd.wp >= rd.B + kRing, 0))
-        nx = W(rd.wp); /* ring used up by long codes */
-      rd.buf |= (uint64_t)(need ? nx : 0u) << ((uint32_t)(32 - rd.nb) & 31u);
-      rd.wp += need ? 1u : 0u;
-      rd.nb += need ? 32 : 0;
-    } else {
-      rd.seek(sh, W, rd.pos + len);
-    }
+    rd.buf <<= len;
+    rd.nb -= (int)len;
+    rd.pos += len;
+    const bool need = rd.nb <= 32;
+    rd.buf |= (uint64_t)(need ? nx : 0u) << ((uint32_t)(32 - rd.nb) & 31u);
+    rd.wp += need ? 1u : 0u;
+    rd.nb += need ? 32 : 0;
     if (__builtin_expect(s == 0, 0)) {
       if (nz < kZeroCap) {
         const uint32_t v = t << ((nz & 1u) * 16);
