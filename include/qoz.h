@@ -151,6 +151,10 @@ const char* qoz_last_error(void);
  * (inputs read once plus outputs written once).  Kinds are numbered
  * 0..qoz_prof_kinds()-1 and named by qoz_prof_name().  Errors: EINVAL. */
 qoz_status qoz_ctx_set_timing(qoz_ctx* ctx, int on);
+/* Time only the kinds whose bit is set (bit k = kind k); timing every
+ * launch adds a pair of event records per kernel to the caller's host
+ * time, so a benchmark can time just the kinds it reports. */
+qoz_status qoz_ctx_set_timing_mask(qoz_ctx* ctx, uint64_t mask);
 qoz_status qoz_ctx_reset_timing(qoz_ctx* ctx);
 int qoz_prof_kinds(void);
 const char* qoz_prof_name(int kind);

@@ -78,6 +78,7 @@ def lib():
                                   C.POINTER(dbl), C.POINTER(dbl), vp]
         L.qoz_last_error.restype = C.c_char_p
         L.qoz_ctx_set_timing.argtypes = [vp, C.c_int]
+        L.qoz_ctx_set_timing_mask.argtypes = [vp, C.c_uint64]
         L.qoz_ctx_reset_timing.argtypes = [vp]
         L.qoz_prof_name.restype = C.c_char_p
         L.qoz_ctx_get_timing.argtypes = [vp, C.c_int, C.POINTER(u64),
@@ -85,6 +86,7 @@ def lib():
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
                    "qoz_metrics", "qoz_ctx_set_timing",
+                   "qoz_ctx_set_timing_mask",
                    "qoz_ctx_reset_timing", "qoz_ctx_get_timing"):
             getattr(L, fn).restype = C.c_int
         _lib = L
@@ -223,6 +225,11 @@ def qoz_last_error():
 
 def qoz_ctx_set_timing(ctx, on):
     _check(lib().qoz_ctx_set_timing(ctx, int(bool(on))), "qoz_ctx_set_timing")
+
+
+def qoz_ctx_set_timing_mask(ctx, mask):
+    _check(lib().qoz_ctx_set_timing_mask(ctx, int(mask)),
+           "qoz_ctx_set_timing_mask")
 
 
 def qoz_ctx_reset_timing(ctx):

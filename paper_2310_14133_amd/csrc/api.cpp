@@ -7,6 +7,7 @@
  * build the Huffman code on the host, one read-back of the payload size,
  * and the small header and codebook uploads.
  */
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -29,7 +30,7 @@ static inline uint8_t* pin(qoz_ctx* c, size_t off) {
 
 #define PROF(kind, bytes, launch)                 \
   do {                                            \
-    hipEvent_t ev_ = prof_begin(c, s);            \
+    hipEvent_t ev_ = prof_begin(c, s, (kind));    \
     launch;                                       \
     prof_end(c, s, ev_, (kind), (double)(bytes)); \
   } while (0)
@@ -75,7 +76,11 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
          launch_sweep_comp(P.g, sw, d_x, W, codes, !last, st, s));
   }
   PROF(PK_HIST, 2.0 * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinHist), hist, 4 * kNSym,
+  /* used symbols sorted on the device; the tree is built on the host */
+  QOZ_TRY(ensure(c->hsort, 8 * (kSortCap + 1)));
+  launch_hist_sort(hist, 1, (uint64_t*)c->hsort.p, s);
+  uint64_t* hk = (uint64_t*)pin(c, kPinHist);
+  QOZ_HIP(hipMemcpyAsync(hk, c->hsort.p, 8 * (kSortCap + 1),
                          hipMemcpyDeviceToHost, s));
   QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
                          s));
@@ -83,30 +88,59 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   if (((uint32_t*)pin(c, kPinStatus))[0] & kStNonFinite)
     return fail(QOZ_EINVAL, "input contains NaN or Inf");
 
-  /* Huffman code on the host */
-  const uint32_t* h = (const uint32_t*)pin(c, kPinHist);
-  std::vector<uint8_t> len(kNSym);
-  std::vector<uint64_t> code(kNSym);
-  if (!huffman_lengths(h, kNSym, len.data()))
-    return fail(QOZ_EINVAL, "Huffman code longer than 63 bits");
-  canonical_codes(len.data(), kNSym, code.data());
-  uint64_t n_used = 0;
-  int32_t lo = -1, hi = -1;
-  for (uint32_t sy = 0; sy < kNSym; ++sy) {
-    if (!len[sy]) continue;
-    ++n_used;
-    if (sy == 0) continue;
-    if (lo < 0) lo = (int32_t)sy;
-    hi = (int32_t)sy;
+  /* Huffman code on the host: lengths of the used symbols (in key order),
+   * then canonical codes in ascending symbol order */
+  std::vector<uint16_t> usym;
+  std::vector<uint8_t> ulen;
+  {
+    const uint64_t n_keys = hk[0];
+    std::vector<uint8_t> klen;
+    std::vector<uint64_t> keys;
+    if (n_keys <= kSortCap) {
+      keys.assign(hk + 1, hk + 1 + n_keys);
+    } else { /* too many used symbols for the device sort */
+      uint32_t* h = (uint32_t*)pin(c, kPinTable);
+      QOZ_HIP(hipMemcpyAsync(h, hist, 4 * kNSym, hipMemcpyDeviceToHost, s));
+      QOZ_TRY(sync_checked(s));
+      for (uint32_t sy = 0; sy < kNSym; ++sy)
+        if (h[sy]) keys.push_back(((uint64_t)h[sy] << 16) | sy);
+      std::sort(keys.begin(), keys.end());
+    }
+    klen.resize(keys.size());
+    if (!huffman_lengths_sorted(keys.data(), (uint32_t)keys.size(),
+                                klen.data()))
+      return fail(QOZ_EINVAL, "Huffman code longer than 63 bits");
+    std::vector<uint32_t> idx(keys.size());
+    for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+      return (keys[a] & 0xffffu) < (keys[b] & 0xffffu);
+    });
+    usym.resize(keys.size());
+    ulen.resize(keys.size());
+    for (uint32_t i = 0; i < idx.size(); ++i) {
+      usym[i] = (uint16_t)(keys[idx[i]] & 0xffffu);
+      ulen[i] = klen[idx[i]];
+    }
   }
-  const uint64_t n_unpred = h[0];
+  const uint64_t n_used = usym.size();
+  std::vector<uint64_t> ucode(n_used);
+  canonical_codes_sparse(usym.data(), ulen.data(), (uint32_t)n_used,
+                         ucode.data());
+  uint64_t zero_entry = 0;
+  int32_t lo = -1, hi = -1;
+  for (uint64_t i = 0; i < n_used; ++i) {
+    if (usym[i] == 0) {
+      zero_entry = (ucode[i] << 8) | ulen[i];
+      continue;
+    }
+    if (lo < 0) lo = usym[i];
+    hi = usym[i];
+  }
   const uint32_t tab_n = lo < 0 ? 0 : (uint32_t)(hi - lo + 1);
   uint64_t* tab = (uint64_t*)pin(c, kPinTable);
-  for (uint32_t i = 0; i < tab_n; ++i) {
-    uint32_t sy = (uint32_t)lo + i;
-    tab[i] = len[sy] ? (code[sy] << 8) | len[sy] : 0;
-  }
-  const uint64_t zero_entry = len[0] ? (code[0] << 8) | len[0] : 0;
+  std::memset(tab, 0, 8ull * tab_n);
+  for (uint64_t i = 0; i < n_used; ++i)
+    if (usym[i]) tab[usym[i] - lo] = (ucode[i] << 8) | ulen[i];
   if (tab_n)
     QOZ_HIP(hipMemcpyAsync(c->enc_table.p, tab, 8ull * tab_n,
                            hipMemcpyHostToDevice, s));
@@ -123,6 +157,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                          hipMemcpyDeviceToHost, s));
   QOZ_TRY(sync_checked(s));
   const uint64_t n_words = ((uint64_t*)pin(c, kPinStatus + 64))[0];
+  const uint64_t n_unpred = ((uint64_t*)pin(c, kPinStatus + 64))[1];
   const Layout lay = layout_of(P.n_anchor, n_used, nch, n_unpred, n_words);
   if (!d_out || lay.total > cap) {
     *out_bytes = lay.total;
@@ -138,16 +173,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   uint8_t* cb = pin(c, kPinStage + 256);
   const size_t cb_bytes = lay.coff - lay.syms;
   std::memset(cb, 0, cb_bytes);
-  {
-    uint64_t k = 0;
-    for (uint32_t sy = 0; sy < kNSym; ++sy)
-      if (len[sy]) {
-        uint16_t v = (uint16_t)sy;
-        std::memcpy(cb + 2 * k, &v, 2);
-        cb[(lay.lens - lay.syms) + k] = len[sy];
-        ++k;
-      }
-  }
+  std::memcpy(cb, usym.data(), 2 * n_used);
+  std::memcpy(cb + (lay.lens - lay.syms), ulen.data(), n_used);
   QOZ_HIP(hipMemcpyAsync(out + lay.syms, cb, cb_bytes, hipMemcpyHostToDevice,
                          s));
   if (P.n_anchor)

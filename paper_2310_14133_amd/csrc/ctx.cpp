@@ -55,8 +55,8 @@ qoz_status ensure_pinned(qoz_ctx* c, size_t bytes) {
   return QOZ_OK;
 }
 
-hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s) {
-  if (!c->timing) return nullptr;
+hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s, int kind) {
+  if (!((c->timing_mask >> kind) & 1u)) return nullptr;
   hipEvent_t e;
   if (!c->event_pool.empty()) {
     e = c->event_pool.back();
@@ -70,7 +70,7 @@ hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s) {
 
 void prof_end(qoz_ctx* c, hipStream_t s, hipEvent_t a, int kind,
               double bytes) {
-  if (!c->timing || !a) return;
+  if (!a) return;
   hipEvent_t b;
   if (!c->event_pool.empty()) {
     b = c->event_pool.back();
@@ -141,7 +141,7 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->partial,    &c->tune_x,     &c->tune_wc,
                     &c->tune_wt,    &c->tune_desc,  &c->tune_hist,
                     &c->tune_stats, &c->tune_l1,    &c->ssim_part,
-                    &c->upos};
+                    &c->upos,       &c->hsort};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);
@@ -157,7 +157,13 @@ const char* qoz_last_error(void) { return g_last_error.c_str(); }
 
 qoz_status qoz_ctx_set_timing(qoz_ctx* c, int on) {
   if (!c) return fail(QOZ_EINVAL, "ctx is NULL");
-  c->timing = on != 0;
+  c->timing_mask = on ? ~0ull : 0ull;
+  return QOZ_OK;
+}
+
+qoz_status qoz_ctx_set_timing_mask(qoz_ctx* c, uint64_t mask) {
+  if (!c) return fail(QOZ_EINVAL, "ctx is NULL");
+  c->timing_mask = mask;
   return QOZ_OK;
 }
 

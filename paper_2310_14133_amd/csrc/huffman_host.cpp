@@ -58,6 +58,73 @@ bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len) {
   return true;
 }
 
+/* Two-queue construction over leaves already in (count, symbol) order,
+ * with the same tie rule as huffman_lengths (leaf first on equal weight). */
+bool huffman_lengths_sorted(const uint64_t* keys, uint32_t n, uint8_t* len) {
+  if (n == 0) return true;
+  if (n == 1) {
+    len[0] = 1;
+    return true;
+  }
+  std::vector<uint64_t> w(2 * (size_t)n - 1);
+  std::vector<uint32_t> up(2 * (size_t)n - 1, 0);
+  for (uint32_t i = 0; i < n; ++i) w[i] = keys[i] >> 16;
+  size_t leaf = 0, merged = n, made = n;
+  for (; made < 2 * (size_t)n - 1; ++made) {
+    size_t pick[2];
+    for (int t = 0; t < 2; ++t) {
+      const bool use_leaf = leaf < n && (merged >= made || w[leaf] <= w[merged]);
+      pick[t] = use_leaf ? leaf++ : merged++;
+    }
+    w[made] = w[pick[0]] + w[pick[1]];
+    up[pick[0]] = (uint32_t)made;
+    up[pick[1]] = (uint32_t)made;
+  }
+  std::vector<uint8_t> depth(2 * (size_t)n - 1, 0);
+  for (size_t v = 2 * (size_t)n - 2; v-- > 0;) {
+    const unsigned dp = depth[up[v]] + 1u;
+    if (dp > (unsigned)kMaxCodeLen) return false;
+    depth[v] = (uint8_t)dp;
+  }
+  for (uint32_t i = 0; i < n; ++i) len[i] = depth[i];
+  return true;
+}
+
+/* Total code bits = sum of the merged weights (any optimal merge order has
+ * the same total). */
+uint64_t huffman_cost_sorted(const uint64_t* keys, uint32_t n) {
+  if (n == 0) return 0;
+  if (n == 1) return keys[0] >> 16;
+  std::vector<uint64_t> q(n);
+  size_t leaf = 0, qh = 0, qt = 0;
+  uint64_t cost = 0;
+  for (uint32_t made = 0; made + 1 < n; ++made) {
+    uint64_t s = 0;
+    for (int t = 0; t < 2; ++t) {
+      const bool use_leaf =
+          leaf < n && (qh >= qt || (keys[leaf] >> 16) <= q[qh]);
+      s += use_leaf ? keys[leaf++] >> 16 : q[qh++];
+    }
+    q[qt++] = s;
+    cost += s;
+  }
+  return cost;
+}
+
+void canonical_codes_sparse(const uint16_t* syms, const uint8_t* lens,
+                            uint32_t n, uint64_t* codes) {
+  uint64_t count[kMaxCodeLen + 2] = {0};
+  for (uint32_t i = 0; i < n; ++i) count[lens[i]]++;
+  uint64_t next[kMaxCodeLen + 2] = {0};
+  uint64_t c = 0;
+  for (int l = 1; l <= kMaxCodeLen; ++l) {
+    c = (c + (l > 1 ? count[l - 1] : 0)) << 1;
+    next[l] = c;
+  }
+  /* ascending symbols: codes of one length are handed out in symbol order */
+  for (uint32_t i = 0; i < n; ++i) codes[i] = next[lens[i]]++;
+}
+
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code) {
   uint32_t count[kMaxCodeLen + 2] = {0};
   for (uint32_t s = 0; s < nsym; ++s) count[len[s]]++;

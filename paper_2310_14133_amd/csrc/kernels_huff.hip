@@ -123,48 +123,135 @@ void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      chunk_bits, chunk_zeros);
 }
 
-/* Exclusive scans over chunks (one workgroup of 1024 lanes, each owning a
- * contiguous run of chunks). totals[0] = words, totals[1] = unpredictables. */
+/* Exclusive scans over chunks in one workgroup: tiles of 8192 chunk counts
+ * are staged in LDS with coalesced loads, each lane scans a contiguous run
+ * of 8, the lane sums are scanned with wave shuffles, and a running total
+ * carries across tiles.  totals[0] = words, totals[1] = unpredictables. */
 constexpr uint32_t kScanThreads = 1024;
+constexpr uint32_t kScanPer = 8;
+constexpr uint32_t kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+  const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint64_t t = __shfl_up(v, o, 64);
+    v += lane >= o ? t : 0ull;
+  }
+  return v;
+}
 
 __global__ __launch_bounds__(kScanThreads) void k_chunk_scan(
     const uint32_t* __restrict__ bits, const uint32_t* __restrict__ zeros,
     uint64_t n, uint64_t* coff, uint32_t* upre, uint64_t* totals) {
-  __shared__ uint64_t sw[kScanThreads], sz[kScanThreads];
-  const uint64_t per = (n + kScanThreads - 1) / kScanThreads;
-  const uint64_t a = threadIdx.x * per;
-  const uint64_t b = a + per < n ? a + per : n;
-  uint64_t w = 0, z = 0;
-  for (uint64_t i = a; i < b; ++i) {
-    w += (bits[i] + 31) / 32;
-    z += zeros[i];
+  __shared__ uint32_t tw[kScanTile], tz[kScanTile];
+  __shared__ uint64_t ww[kScanThreads / 64], wz[kScanThreads / 64];
+  const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
+  uint64_t run_w = 0, run_z = 0;
+  for (uint64_t base = 0; base < n; base += kScanTile) {
+    const uint32_t cnt = (uint32_t)(n - base < kScanTile ? n - base : kScanTile);
+    for (uint32_t i = t; i < kScanTile; i += kScanThreads) {
+      tw[i] = i < cnt ? (bits[base + i] + 31) / 32 : 0u;
+      tz[i] = i < cnt ? zeros[base + i] : 0u;
+    }
+    __syncthreads();
+    uint64_t sw = 0, sz = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanPer; ++k) {
+      sw += tw[t * kScanPer + k];
+      sz += tz[t * kScanPer + k];
+    }
+    const uint64_t iw = wave_incl_scan_u64(sw), iz = wave_incl_scan_u64(sz);
+    if (lane == 63) {
+      ww[wave] = iw;
+      wz[wave] = iz;
+    }
+    __syncthreads();
+    uint64_t ow = run_w + iw - sw, oz = run_z + iz - sz;
+    uint64_t tot_w = 0, tot_z = 0;
+    for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
+      ow += w < wave ? ww[w] : 0ull;
+      oz += w < wave ? wz[w] : 0ull;
+      tot_w += ww[w];
+      tot_z += wz[w];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kScanPer; ++k) {
+      const uint32_t i = t * kScanPer + k;
+      if (i < cnt) {
+        coff[base + i] = ow;
+        upre[base + i] = (uint32_t)oz;
+      }
+      ow += tw[i];
+      oz += tz[i];
+    }
+    run_w += tot_w;
+    run_z += tot_z;
+    __syncthreads();
   }
-  sw[threadIdx.x] = w;
-  sz[threadIdx.x] = z;
+  if (t == 0) {
+    coff[n] = run_w;
+    upre[n] = (uint32_t)run_z;
+    totals[0] = run_w;
+    totals[1] = run_z;
+  }
+}
+
+/* Used symbols of each histogram as keys (count << 16) | symbol, sorted
+ * ascending in LDS (bitonic), which is the (count, symbol) leaf order of
+ * the two-queue Huffman construction.  out[h * (kSortCap + 1)] = number of
+ * used symbols; the next min(that, kSortCap) entries are the sorted keys
+ * (more used symbols than kSortCap: the caller falls back to the whole
+ * histogram). */
+constexpr uint32_t kSortThreads = 1024;
+
+__global__ __launch_bounds__(kSortThreads) void k_hist_sort(
+    const uint32_t* __restrict__ hist, uint64_t* __restrict__ out) {
+  __shared__ uint64_t keys[kSortCap];
+  __shared__ uint32_t n_used;
+  const uint32_t* hh = hist + (uint64_t)blockIdx.x * kNSym;
+  uint64_t* o = out + (uint64_t)blockIdx.x * (kSortCap + 1);
+  if (threadIdx.x == 0) n_used = 0;
   __syncthreads();
-  /* inclusive Hillis-Steele scan over the 1024 partials */
-  for (uint32_t o = 1; o < kScanThreads; o <<= 1) {
-    uint64_t vw = threadIdx.x >= o ? sw[threadIdx.x - o] : 0;
-    uint64_t vz = threadIdx.x >= o ? sz[threadIdx.x - o] : 0;
-    __syncthreads();
-    sw[threadIdx.x] += vw;
-    sz[threadIdx.x] += vz;
-    __syncthreads();
+  for (uint32_t i = threadIdx.x; i < kNSym; i += kSortThreads) {
+    const uint32_t v = hh[i];
+    if (v) {
+      const uint32_t k = atomicAdd(&n_used, 1u);
+      if (k < kSortCap) keys[k] = ((uint64_t)v << 16) | i;
+    }
   }
-  uint64_t rw = threadIdx.x ? sw[threadIdx.x - 1] : 0;
-  uint64_t rz = threadIdx.x ? sz[threadIdx.x - 1] : 0;
-  for (uint64_t i = a; i < b; ++i) {
-    coff[i] = rw;
-    upre[i] = (uint32_t)rz;
-    rw += (bits[i] + 31) / 32;
-    rz += zeros[i];
-  }
-  if (threadIdx.x == kScanThreads - 1) {
-    coff[n] = sw[kScanThreads - 1];
-    upre[n] = (uint32_t)sz[kScanThreads - 1];
-    totals[0] = sw[kScanThreads - 1];
-    totals[1] = sz[kScanThreads - 1];
-  }
+  __syncthreads();
+  const uint32_t n = n_used;
+  const uint32_t m = n < kSortCap ? n : kSortCap;
+  uint32_t p2 = 2;
+  while (p2 < m) p2 <<= 1;
+  for (uint32_t i = m + threadIdx.x; i < p2; i += kSortThreads)
+    keys[i] = ~0ull;
+  __syncthreads();
+  for (uint32_t k = 2; k <= p2; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < p2; i += kSortThreads) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = keys[i], b = keys[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (threadIdx.x == 0) o[0] = n;
+  for (uint32_t i = threadIdx.x; i < m; i += kSortThreads) o[1 + i] = keys[i];
+}
+
+void launch_hist_sort(const uint32_t* hist, uint32_t n_hist, uint64_t* out,
+                      hipStream_t s) {
+  if (!n_hist) return;
+  hipLaunchKernelGGL(k_hist_sort, dim3(n_hist), dim3(kSortThreads), 0, s,
+                     hist, out);
 }
 
 void launch_chunk_scan(const uint32_t* chunk_bits,

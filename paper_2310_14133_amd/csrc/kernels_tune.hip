@@ -139,6 +139,55 @@ void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
                      s, bg, l, xs, wc, wt, cand_desc, l1_part);
 }
 
+/* Algorithm 1's choice at one level, on the device: the mean absolute
+ * prediction error of each candidate (its per-block sums added in block
+ * order, then divided by the level's target count) and the first strict
+ * minimum over candidates in order. */
+constexpr uint32_t kPickThreads = 64;
+
+__global__ __launch_bounds__(kPickThreads) void k_alg1_pick(
+    const double* __restrict__ l1_part, uint32_t ncand, uint32_t nb,
+    double count, uint32_t* pick) {
+  __shared__ double cur[kPickThreads];
+  for (uint32_t ci = threadIdx.x; ci < ncand; ci += kPickThreads) {
+    double sum = 0.0;
+    for (uint32_t k = 0; k < nb; ++k) sum += l1_part[(size_t)ci * nb + k];
+    cur[ci] = count > 0 ? sum / count : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double best = INFINITY;
+    uint32_t ib = 0;
+    for (uint32_t ci = 0; ci < ncand; ++ci)
+      if (cur[ci] < best) {
+        best = cur[ci];
+        ib = ci;
+      }
+    *pick = ib;
+  }
+}
+
+/* commit the chosen candidate's working copy: wc = wt[pick] */
+__global__ void k_commit_copy(const float* __restrict__ wt,
+                              const uint32_t* __restrict__ pick, uint64_t n,
+                              float* __restrict__ wc) {
+  const float* src = wt + (uint64_t)(*pick) * n;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    wc[i] = src[i];
+}
+
+void launch_alg1_pick(const double* l1_part, uint32_t ncand, uint32_t nb,
+                      double count, uint32_t* pick, const float* wt,
+                      uint64_t bsz, float* wc, hipStream_t s) {
+  hipLaunchKernelGGL(k_alg1_pick, dim3(1), dim3(kPickThreads), 0, s, l1_part,
+                     ncand, nb, count, pick);
+  uint64_t blocks = (bsz + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_commit_copy, dim3((uint32_t)blocks), dim3(256), 0, s,
+                     wt, pick, bsz, wc);
+}
+
 __global__ __launch_bounds__(kTuneThreads) void k_trial(
     BlockGeo bg, const float* __restrict__ xs, float* wt,
     const TrialDesc* desc, uint32_t* hist, double* sse_part,

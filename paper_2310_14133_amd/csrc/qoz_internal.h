@@ -150,12 +150,13 @@ struct qoz_ctx {
   /* scratch */
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
-      tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos;
+      tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
+      hsort;
   /* pinned host staging */
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   /* instrumentation */
-  bool timing = false;
+  uint64_t timing_mask = 0; /* bit k: time launches of kind k */
   std::vector<qoz::PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
   uint64_t prof_launches[qoz::PK_COUNT] = {0};
@@ -185,7 +186,7 @@ qoz_status ensure(DevBuf& b, size_t bytes);
 qoz_status ensure_pinned(qoz_ctx* c, size_t bytes);
 /* Instrumented launch bracket: call prof_begin before and prof_end after a
  * launch; resolved by prof_collect after the stream is synchronised. */
-hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s);
+hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s, int kind);
 void prof_end(qoz_ctx* c, hipStream_t s, hipEvent_t a, int kind,
               double bytes);
 void prof_collect(qoz_ctx* c);
@@ -213,6 +214,16 @@ void fill_sweep_table(const Plan& p, SweepTable* t);
 
 /* ---- Huffman (host side, huffman_host.cpp) ---------------------------- */
 bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
+/* Used symbols sorted on the device: keys (count << 16) | symbol in
+ * ascending order; lengths per key, or the total code bits. */
+constexpr uint32_t kSortCap = 4096;
+bool huffman_lengths_sorted(const uint64_t* keys, uint32_t n, uint8_t* len);
+uint64_t huffman_cost_sorted(const uint64_t* keys, uint32_t n);
+/* Canonical codes for ascending symbols syms[0..n) with lengths lens. */
+void canonical_codes_sparse(const uint16_t* syms, const uint8_t* lens,
+                            uint32_t n, uint64_t* codes);
+void launch_hist_sort(const uint32_t* hist, uint32_t n_hist, uint64_t* out,
+                      hipStream_t s);
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code);
 bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
                       uint32_t n_used, DecTables* t,
@@ -296,6 +307,9 @@ void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
                        const float* wc, float* wt, uint32_t ncand,
                        const TrialDesc* cand_desc, double* l1_part,
                        hipStream_t s);
+void launch_alg1_pick(const double* l1_part, uint32_t ncand, uint32_t nb,
+                      double count, uint32_t* pick, const float* wt,
+                      uint64_t bsz, float* wc, hipStream_t s);
 void launch_trial(const BlockGeo& bg, const float* xs, float* wt,
                   uint32_t ntrial, const TrialDesc* desc, uint32_t* hist,
                   double* sse_part, uint32_t* unpred_part, hipStream_t s);

@@ -168,7 +168,9 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   QOZ_TRY(ensure(c->tune_x, 4 * bsz));
   QOZ_TRY(ensure(c->tune_wc, 4 * bsz));
   QOZ_TRY(ensure(c->tune_wt, 4 * bsz * nslots));
-  QOZ_TRY(ensure(c->tune_desc, sizeof(TrialDesc) * nslots));
+  const uint32_t adesc_n = QOZ_MAX_LEVELS * ncand;
+  QOZ_TRY(ensure(c->tune_desc,
+                 sizeof(TrialDesc) * (nslots + adesc_n) + 4 * QOZ_MAX_LEVELS));
   QOZ_TRY(ensure(c->tune_l1, 8 * (size_t)nslots * bg.nb));
   QOZ_TRY(ensure(c->tune_stats, 12 * (size_t)nslots * bg.nb));
   QOZ_TRY(ensure(c->tune_hist, 4 * (size_t)kNSym * max_trials));
@@ -191,7 +193,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   const size_t pin_need = kPinTune + 4 * (size_t)kNSym * max_trials +
                           12 * (size_t)nslots * bg.nb +
                           8 * (size_t)nslots * bg.nb + 8 * ssim_np +
-                          sizeof(TrialDesc) * nslots + 8 * rp +
+                          sizeof(TrialDesc) * (nslots + adesc_n) + 8 * rp +
                           12 * (size_t)bg.nb + 4096;
   QOZ_TRY(ensure_pinned(c, pin_need));
   uint8_t* pbase = (uint8_t*)c->pinned + kPinTune;
@@ -202,13 +204,16 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                            12 * (size_t)nslots * bg.nb);
   double* h_ssim = h_l1 + (size_t)nslots * bg.nb;
   TrialDesc* h_desc = (TrialDesc*)(h_ssim + ssim_np);
-  float* h_range = (float*)(h_desc + nslots);
+  TrialDesc* h_adesc = h_desc + nslots;
+  float* h_range = (float*)(h_adesc + adesc_n);
   uint32_t* h_status = (uint32_t*)(h_range + 2 * rp);
 
   float* xs = (float*)c->tune_x.p;
   float* wc = (float*)c->tune_wc.p;
   float* wt = (float*)c->tune_wt.p;
   TrialDesc* ddesc = (TrialDesc*)c->tune_desc.p;
+  TrialDesc* dadesc = ddesc + nslots;
+  uint32_t* dpick = (uint32_t*)(dadesc + adesc_n);
   double* dl1 = (double*)c->tune_l1.p;
   double* dsse = (double*)c->tune_stats.p;
   uint32_t* dun = (uint32_t*)(dsse + (size_t)nslots * bg.nb);
@@ -221,7 +226,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   /* value range and finiteness of the whole field */
   launch_init_status(st, s);
   {
-    hipEvent_t ev = prof_begin(c, s);
+    hipEvent_t ev = prof_begin(c, s, PK_CHECK);
     launch_range(d_x, N, pmin, pmax, st, rp, s);
     prof_end(c, s, ev, PK_CHECK, 4.0 * N);
   }
@@ -232,7 +237,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   QOZ_HIP(hipMemcpyAsync(dorig, h_status + 8, 4 * origins.size(),
                          hipMemcpyHostToDevice, s));
   {
-    hipEvent_t ev = prof_begin(c, s);
+    hipEvent_t ev = prof_begin(c, s, PK_TUNE_GATHER);
     launch_gather_blocks(d_x, g, bg, dorig, xs, s);
     prof_end(c, s, ev, PK_TUNE_GATHER, 8.0 * bsz);
   }
@@ -258,10 +263,13 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   double ueb[QOZ_MAX_LEVELS];
   float utw[QOZ_MAX_LEVELS], uiv[QOZ_MAX_LEVELS];
   level_bounds(e, 1.0, 1.0, Lt, ueb, utw, uiv);
-  for (uint32_t l = Lt; l >= 1; --l) {
-    std::memset(h_desc, 0, sizeof(TrialDesc) * ncand);
+  /* every level's candidates go up at once; each level's choice and the
+   * commit of its working copy happen on the device, so the levels run
+   * back to back and the host reads the choices once */
+  std::memset(h_adesc, 0, sizeof(TrialDesc) * adesc_n);
+  for (uint32_t l = Lt; l >= 1; --l)
     for (uint32_t ci = 0; ci < ncand; ++ci) {
-      TrialLevel& lv = h_desc[ci].lv[l - 1];
+      TrialLevel& lv = h_adesc[(l - 1) * ncand + ci].lv[l - 1];
       lv.twoeb = utw[l - 1];
       lv.inv = uiv[l - 1];
       lv.eb = ueb[l - 1];
@@ -269,17 +277,15 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       for (int j = 0; j < 3; ++j)
         lv.order[j] = j < d ? cands[ci].order[j] + shift : 0;
     }
-    QOZ_HIP(hipMemcpyAsync(ddesc, h_desc, sizeof(TrialDesc) * ncand,
-                           hipMemcpyHostToDevice, s));
+  QOZ_HIP(hipMemcpyAsync(dadesc, h_adesc, sizeof(TrialDesc) * Lt * ncand,
+                         hipMemcpyHostToDevice, s));
+  for (uint32_t l = Lt; l >= 1; --l) {
     {
-      hipEvent_t ev = prof_begin(c, s);
-      launch_alg1_level(bg, l, xs, wc, wt, ncand, ddesc, dl1, s);
+      hipEvent_t ev = prof_begin(c, s, PK_TUNE_ALG1);
+      launch_alg1_level(bg, l, xs, wc, wt, ncand, dadesc + (l - 1) * ncand,
+                        dl1, s);
       prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
     }
-    QOZ_HIP(hipMemcpyAsync(h_l1, dl1, 8 * (size_t)ncand * bg.nb,
-                           hipMemcpyDeviceToHost, s));
-    QOZ_HIP(hipGetLastError());
-    QOZ_HIP(hipStreamSynchronize(s));
     /* level-l targets: points of the 2^(l-1) grid off the 2^l grid */
     uint64_t on_fine = 1, on_coarse = 1;
     for (int i = 0; i < 3; ++i) {
@@ -287,21 +293,18 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
     }
     const double count = (double)(on_fine - on_coarse) * bg.nb;
-    double best = std::numeric_limits<double>::infinity();
-    uint32_t ib = 0;
-    for (uint32_t ci = 0; ci < ncand; ++ci) {
-      double sum = 0.0;
-      for (uint32_t k = 0; k < bg.nb; ++k) sum += h_l1[(size_t)ci * bg.nb + k];
-      double cur = count > 0 ? sum / count : 0.0;
-      if (cur < best) {
-        best = cur;
-        ib = ci;
-      }
-    }
+    launch_alg1_pick(dl1, ncand, bg.nb, count, dpick + (l - 1), wt, bsz, wc,
+                     s);
+  }
+  uint32_t* h_pick = h_status + 8 + 3 * (size_t)bg.nb; /* after origins */
+  QOZ_HIP(hipMemcpyAsync(h_pick, dpick, 4 * Lt, hipMemcpyDeviceToHost, s));
+  QOZ_HIP(hipGetLastError());
+  QOZ_HIP(hipStreamSynchronize(s));
+  for (uint32_t l = Lt; l >= 1; --l) {
+    const uint32_t ib = h_pick[l - 1];
+    if (ib >= ncand) return fail(QOZ_EDEVICE, "bad tuner choice");
     Is_interp[l - 1] = cands[ib].interp;
     std::memcpy(Is_order[l - 1], cands[ib].order, 3);
-    QOZ_HIP(hipMemcpyAsync(wc, wt + (size_t)ib * bsz, 4 * bsz,
-                           hipMemcpyDeviceToDevice, s));
   }
   for (uint32_t l = Lt + 1; l <= L; ++l) {
     Is_interp[l - 1] = Is_interp[Lt - 1];
@@ -351,7 +354,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                          hipMemcpyHostToDevice, s));
   launch_zero_u32(dhist, (uint64_t)kNSym * ntrial, s);
   {
-    hipEvent_t ev = prof_begin(c, s);
+    hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
     launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun, s);
     prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ntrial);
   }
@@ -360,13 +363,18 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     sj.c1 = (0.01 * vrange) * (0.01 * vrange);
     sj.c2 = (0.03 * vrange) * (0.03 * vrange);
     ssim_np = ssim_parts(sj);
-    hipEvent_t ev = prof_begin(c, s);
+    hipEvent_t ev = prof_begin(c, s, PK_SSIM);
     launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
     prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
     QOZ_HIP(hipMemcpyAsync(h_ssim, c->ssim_part.p, 8 * ssim_np,
                            hipMemcpyDeviceToHost, s));
   }
-  QOZ_HIP(hipMemcpyAsync(h_hist, dhist, 4 * (size_t)kNSym * ntrial,
+  /* used symbols of every trial histogram, sorted on the device */
+  QOZ_TRY(ensure(c->hsort, 8 * (size_t)(kSortCap + 1) * ntrial));
+  launch_hist_sort(dhist, ntrial, (uint64_t*)c->hsort.p, s);
+  uint64_t* h_keys = (uint64_t*)h_hist;
+  QOZ_HIP(hipMemcpyAsync(h_keys, c->hsort.p,
+                         8 * (size_t)(kSortCap + 1) * ntrial,
                          hipMemcpyDeviceToHost, s));
   QOZ_HIP(hipMemcpyAsync(h_sse, dsse, 12 * (size_t)nslots * bg.nb,
                          hipMemcpyDeviceToHost, s));
@@ -380,7 +388,16 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                       (double)(sj.Cn - sj.wc + 1) * bg.nb;
   std::vector<double> B(ntrial), M(ntrial, 0.0);
   for (uint32_t t = 0; t < ntrial; ++t) {
-    uint64_t bits = huffman_cost(h_hist + (size_t)t * kNSym, kNSym);
+    const uint64_t* kt = h_keys + (size_t)t * (kSortCap + 1);
+    uint64_t bits;
+    if (kt[0] <= kSortCap) {
+      bits = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
+    } else { /* too many used symbols for the device sort */
+      std::vector<uint32_t> hh(kNSym);
+      QOZ_HIP(hipMemcpy(hh.data(), dhist + (size_t)t * kNSym, 4 * kNSym,
+                        hipMemcpyDeviceToHost));
+      bits = huffman_cost(hh.data(), kNSym);
+    }
     uint64_t U = 0;
     double sse = 0.0;
     for (uint32_t k = 0; k < bg.nb; ++k) {
