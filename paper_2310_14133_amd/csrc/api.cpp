@@ -8,6 +8,7 @@
  * and the small header and codebook uploads.
  */
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -68,8 +69,20 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   PROF(PK_ANCHOR, 8.0 * P.n_anchor,
        launch_anchor_copy(P.g, P.s, P.na, d_x, W, (float*)c->anchors.p, st,
                           s));
+  size_t fa = SIZE_MAX, fb = SIZE_MAX;
+  RowJob rj;
+  const bool fuse = level1_rows(P, &fa, &fb, &rj);
   for (size_t i = 0; i < P.sweeps.size(); ++i) {
     const Sweep& sw = P.sweeps[i];
+    if (fuse && (i == fa || i == fb)) {
+      if (i == fb) { /* sweep A (if any) and B as one row pass */
+        const bool write_w = fb + 1 < P.sweeps.size();
+        const double tg = (double)rj.B.count + (fa != SIZE_MAX ? rj.A.count : 0);
+        PROF(PK_ROW_COMP_L1, tg * (write_w ? 14.0 : 10.0),
+             launch_row_comp(P.g, rj, d_x, W, codes, write_w, st, s));
+      }
+      continue;
+    }
     const bool last = i + 1 == P.sweeps.size();
     PROF(sw.level == 1 ? PK_SWEEP_COMP_L1 : PK_SWEEP_COMP,
          (double)sw.count * (last ? 10.0 : 14.0),
@@ -343,10 +356,23 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   PROF(PK_ANCHOR, 8.0 * P.n_anchor,
        launch_anchor_scatter(P.g, P.s, P.na, (const float*)(in + lay.anchors),
                              d_y, s));
-  for (const Sweep& sw : P.sweeps)
+  size_t fa = SIZE_MAX, fb = SIZE_MAX;
+  RowJob rj;
+  const bool fuse = level1_rows(P, &fa, &fb, &rj);
+  for (size_t i = 0; i < P.sweeps.size(); ++i) {
+    const Sweep& sw = P.sweeps[i];
+    if (fuse && (i == fa || i == fb)) {
+      if (i == fb) {
+        const double tg = (double)rj.B.count + (fa != SIZE_MAX ? rj.A.count : 0);
+        PROF(PK_ROW_DEC_L1, tg * 10.0,
+             launch_row_decomp(P.g, rj, d_y, codes, s));
+      }
+      continue;
+    }
     PROF(sw.level == 1 ? PK_SWEEP_DEC_L1 : PK_SWEEP_DEC,
          (double)sw.count * 10.0,
          launch_sweep_decomp(P.g, sw, d_y, codes, s));
+  }
   QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
                          s));
   QOZ_TRY(sync_checked(s));

@@ -103,7 +103,8 @@ static const char* kProfNames[PK_COUNT] = {
     "sweep_comp",      "histogram",       "huffman_lengths",
     "huffman_encode",  "huffman_decode",  "sweep_decomp_level1",
     "sweep_decomp",    "tune_gather",     "tune_alg1",
-    "tune_trial",      "ssim",            "reduce"};
+    "tune_trial",      "ssim",            "reduce",
+    "row_comp_level1", "row_decomp_level1"};
 
 }  // namespace qoz
 

@@ -193,6 +193,272 @@ void launch_unpred_scatter(const Geo& g, const SweepTable& st,
                      s, g, st, upos, vals, n_unpred, n_codes, W, status);
 }
 
+/* ---- level-1 row kernels ------------------------------------------------
+ * The sweep along the contiguous dimension (targets at odd positions of a
+ * row) reads only even positions of the same row, so it is fused with the
+ * sweep just before it in the level's order (its targets sit at the even
+ * positions of rows that are odd along that sweep's dimension, and are
+ * predicted from neighbour rows).  A workgroup takes several rows; each
+ * lane takes 8-point spans.  Phase 1 computes the even positions (sweep A,
+ * or the known values) into LDS, phase 2 predicts and quantizes the odd
+ * positions (sweep B).  Every target is computed exactly as the per-sweep
+ * kernels compute it; only the schedule and the memory access change.
+ * Rows are the (p0, p1) pairs of the row set (steps 1 or 2). */
+constexpr uint32_t kRowThreads = 256;
+constexpr uint32_t kSpan = 8;
+
+__device__ __forceinline__ uint64_t stream_pos(const Sweep& s, uint32_t p0,
+                                               uint32_t p1, uint32_t p2) {
+  const uint32_t i0 = (p0 - s.start[0]) >> (s.step[0] >> 1);
+  const uint32_t i1 = (p1 - s.start[1]) >> (s.step[1] >> 1);
+  const uint32_t i2 = (p2 - s.start[2]) >> (s.step[2] >> 1);
+  return s.code_off + ((uint64_t)i0 * s.cnt[1] + i1) * s.cnt[2] + i2;
+}
+
+/* a 4-byte-aligned 16-byte load */
+struct __attribute__((aligned(4))) F4 {
+  float x, y, z, w;
+};
+
+/* points p .. p + kSpan - 1 of a row (zero past n) */
+__device__ __forceinline__ void load_span(const float* __restrict__ r,
+                                          uint32_t p, uint32_t n, float* v) {
+  if (p + kSpan <= n) {
+    const F4 a = *reinterpret_cast<const F4*>(r + p);
+    const F4 b = *reinterpret_cast<const F4*>(r + p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < kSpan; ++k) v[k] = p + k < n ? r[p + k] : 0.0f;
+  }
+}
+
+struct RowCtx {
+  uint32_t p0, p1, row, pa;
+  bool hasA;
+};
+
+__device__ __forceinline__ RowCtx row_ctx(const Geo& g, const RowJob& rj,
+                                          uint32_t r) {
+  RowCtx c;
+  const uint32_t i0 = r / rj.rcnt[1];
+  const uint32_t i1 = r - i0 * rj.rcnt[1];
+  c.p0 = i0 * rj.rstep[0];
+  c.p1 = i1 * rj.rstep[1];
+  c.row = c.p0 * g.st[0] + c.p1 * g.st[1];
+  c.pa = rj.a == 0 ? c.p0 : c.p1;
+  c.hasA = rj.a >= 0 && (c.pa & 1u);
+  return c;
+}
+
+/* Sweep-A predictions of the even points of span [p, p + kSpan): the
+ * neighbour rows at -3, -1, +1, +3 along a (present ones only). */
+__device__ __forceinline__ void predict_span_A(const Geo& g, const RowJob& rj,
+                                               const float* W, const RowCtx& c,
+                                               uint32_t p, float* pred) {
+  const uint32_t sa = g.st[rj.a], na = g.n[rj.a], n2 = g.n[2];
+  const bool ha = c.pa >= 3, hc = c.pa + 1 < na, hd = c.pa + 3 < na;
+  const bool cub = rj.A.cubic != 0;
+  /* the points each rule reads (see interp_mid); the rest stay unread */
+  const bool la = ha && (cub || !hc), ld = hd && cub;
+  float vb[kSpan], vc[kSpan], va[kSpan], vd[kSpan];
+  load_span(W + c.row - sa, p, n2, vb);
+  if (hc) load_span(W + c.row + sa, p, n2, vc);
+  if (la) load_span(W + c.row - 3 * sa, p, n2, va);
+  if (ld) load_span(W + c.row + 3 * sa, p, n2, vd);
+#pragma unroll
+  for (uint32_t k = 0; k < kSpan / 2; ++k)
+    pred[k] = interp_mid(rj.A.cubic, la ? va[2 * k] : 0.0f, vb[2 * k],
+                         hc ? vc[2 * k] : 0.0f, ld ? vd[2 * k] : 0.0f, ha, hc,
+                         hd);
+}
+
+template <bool WRITE_W>
+__global__ __launch_bounds__(kRowThreads) void k_row_comp(
+    Geo g, RowJob rj, const float* __restrict__ x, float* W,
+    uint16_t* __restrict__ codes, uint32_t* status) {
+  extern __shared__ float E[]; /* per row: E[t + 1] = value at 2t */
+  const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
+  const uint32_t spans = (n2 + kSpan - 1) / kSpan;
+  const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
+  const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
+  const uint32_t items = rj.rows_per_wg * spans;
+  bool bad = false;
+  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
+    const uint32_t rl = it / spans, u = it - rl * spans;
+    if (r0 + rl >= rows) break;
+    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const uint32_t p = u * kSpan;
+    float* Er = E + rl * es;
+    float xv[kSpan];
+    if (c.hasA) {
+      float pred[kSpan / 2];
+      load_span(x + c.row, p, n2, xv);
+      predict_span_A(g, rj, W, c, p, pred);
+      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k) {
+        if (p + 2 * k >= n2) break;
+        float e;
+        const int32_t code =
+            quantize_bin(xv[2 * k], pred[k], rj.A.inv, rj.A.twoeb, rj.A.eb, &e);
+        codes[pos + k] = (uint16_t)code;
+        bad |= !isfinite(xv[2 * k]);
+        Er[p / 2 + k + 1] = e;
+      }
+    } else {
+      float wv[kSpan];
+      load_span(W + c.row, p, n2, wv);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k)
+        if (p + 2 * k < n2) Er[p / 2 + k + 1] = wv[2 * k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
+    const uint32_t rl = it / spans, u = it - rl * spans;
+    if (r0 + rl >= rows) break;
+    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const uint32_t p = u * kSpan;
+    const float* Er = E + rl * es;
+    float xv[kSpan], out[kSpan];
+    load_span(x + c.row, p, n2, xv);
+    const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
+#pragma unroll
+    for (uint32_t k = 0; k < kSpan / 2; ++k) {
+      const uint32_t t = p / 2 + k, q = 2 * t + 1;
+      out[2 * k] = Er[t + 1];
+      out[2 * k + 1] = 0.0f;
+      if (q >= n2) continue;
+      const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
+      const float pred =
+          interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
+                     hc ? Er[t + 2] : 0.0f, hd ? Er[t + 3] : 0.0f, ha, hc, hd);
+      float rec;
+      const int32_t code =
+          quantize_bin(xv[2 * k + 1], pred, rj.B.inv, rj.B.twoeb, rj.B.eb, &rec);
+      codes[pos + k] = (uint16_t)code;
+      bad |= !isfinite(xv[2 * k + 1]);
+      out[2 * k + 1] = rec;
+    }
+    if (WRITE_W) {
+      float* wr = W + c.row;
+      if (p + kSpan <= n2) {
+        *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
+        *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
+      } else {
+        for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+      }
+    }
+  }
+  if (bad) atomicOr(status, kStNonFinite);
+}
+
+/* Decompression: bin 0 keeps the exact value already scattered into W. */
+__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
+    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
+  extern __shared__ float E[];
+  const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
+  const uint32_t spans = (n2 + kSpan - 1) / kSpan;
+  const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
+  const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
+  const uint32_t items = rj.rows_per_wg * spans;
+  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
+    const uint32_t rl = it / spans, u = it - rl * spans;
+    if (r0 + rl >= rows) break;
+    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const uint32_t p = u * kSpan;
+    float* Er = E + rl * es;
+    if (c.hasA) {
+      float pred[kSpan / 2];
+      predict_span_A(g, rj, W, c, p, pred);
+      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k) {
+        if (p + 2 * k >= n2) break;
+        const int32_t code = codes[pos + k];
+        Er[p / 2 + k + 1] = code ? dequantize_bin(pred[k], code, rj.A.twoeb)
+                                 : W[c.row + p + 2 * k];
+      }
+    } else {
+      float wv[kSpan];
+      load_span(W + c.row, p, n2, wv);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k)
+        if (p + 2 * k < n2) Er[p / 2 + k + 1] = wv[2 * k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
+    const uint32_t rl = it / spans, u = it - rl * spans;
+    if (r0 + rl >= rows) break;
+    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const uint32_t p = u * kSpan;
+    const float* Er = E + rl * es;
+    float out[kSpan];
+    const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
+#pragma unroll
+    for (uint32_t k = 0; k < kSpan / 2; ++k) {
+      const uint32_t t = p / 2 + k, q = 2 * t + 1;
+      out[2 * k] = Er[t + 1];
+      out[2 * k + 1] = 0.0f;
+      if (q >= n2) continue;
+      const int32_t code = codes[pos + k];
+      if (code) {
+        const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
+        const float pred = interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
+                                      hc ? Er[t + 2] : 0.0f,
+                                      hd ? Er[t + 3] : 0.0f, ha, hc, hd);
+        out[2 * k + 1] = dequantize_bin(pred, code, rj.B.twoeb);
+      } else {
+        out[2 * k + 1] = W[c.row + q];
+      }
+    }
+    float* wr = W + c.row;
+    if (p + kSpan <= n2) {
+      *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
+      *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
+    } else {
+      for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+    }
+  }
+}
+
+static uint32_t row_blocks(const Geo& g, RowJob* rj, size_t* lds) {
+  const uint32_t rows = rj->rcnt[0] * rj->rcnt[1];
+  const uint32_t spans = (g.n[2] + kSpan - 1) / kSpan;
+  rj->rows_per_wg = spans >= kRowThreads ? 1u : kRowThreads / spans;
+  if (rj->rows_per_wg > rows) rj->rows_per_wg = rows;
+  *lds = 4 * (size_t)rj->rows_per_wg * ((g.n[2] + 1) / 2 + 3);
+  return (rows + rj->rows_per_wg - 1) / rj->rows_per_wg;
+}
+
+void launch_row_comp(const Geo& g, const RowJob& rj_in, const float* x,
+                     float* W, uint16_t* codes, bool write_w,
+                     uint32_t* status, hipStream_t s) {
+  if (!rj_in.rcnt[0] || !rj_in.rcnt[1]) return;
+  RowJob rj = rj_in;
+  size_t lds;
+  const uint32_t blocks = row_blocks(g, &rj, &lds);
+  if (write_w)
+    hipLaunchKernelGGL(k_row_comp<true>, dim3(blocks), dim3(kRowThreads), lds,
+                       s, g, rj, x, W, codes, status);
+  else
+    hipLaunchKernelGGL(k_row_comp<false>, dim3(blocks), dim3(kRowThreads),
+                       lds, s, g, rj, x, W, codes, status);
+}
+
+void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
+                       const uint16_t* codes, hipStream_t s) {
+  if (!rj_in.rcnt[0] || !rj_in.rcnt[1]) return;
+  RowJob rj = rj_in;
+  size_t lds;
+  const uint32_t blocks = row_blocks(g, &rj, &lds);
+  hipLaunchKernelGGL(k_row_decomp, dim3(blocks), dim3(kRowThreads), lds, s, g,
+                     rj, W, codes);
+}
+
 static dim3 sweep_grid_dim(const Sweep& sw) {
   uint32_t gx = (sw.cnt[2] + kSweepTX - 1) / kSweepTX;
   uint64_t rows = (uint64_t)sw.cnt[0] * sw.cnt[1];

@@ -150,6 +150,32 @@ qoz_status make_plan(const qoz_shape& sh, double e, const qoz_params& p_in,
   return QOZ_OK;
 }
 
+bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj) {
+  const size_t ns = P.sweeps.size(), d = (size_t)P.d;
+  if (ns < d || P.g.n[2] > 2 * kRowMaxEven) return false;
+  const size_t first = ns - d; /* the level-1 sweeps close the schedule */
+  size_t jb = d;
+  for (size_t j = 0; j < d; ++j)
+    if (P.sweeps[first + j].k == 2) jb = j;
+  if (jb == d) return false;
+  std::memset(rj, 0, sizeof(*rj));
+  *ib = first + jb;
+  *ia = jb > 0 ? first + jb - 1 : SIZE_MAX;
+  rj->B = P.sweeps[*ib];
+  rj->a = -1;
+  if (jb > 0) {
+    rj->A = P.sweeps[*ia];
+    rj->a = (int32_t)rj->A.k;
+  }
+  /* B's targets fill rows of its (p0, p1) sub-grid; A's are those rows
+   * that are odd along a */
+  for (int m = 0; m < 2; ++m) {
+    rj->rstep[m] = rj->B.step[m];
+    rj->rcnt[m] = rj->B.cnt[m];
+  }
+  return true;
+}
+
 void fill_sweep_table(const Plan& p, SweepTable* t) {
   std::memset(t, 0, sizeof(*t));
   t->n = (uint32_t)p.sweeps.size();

@@ -53,6 +53,17 @@ struct Sweep {
   double eb;         /* e_l */
 };
 
+/* Level-1 fusion of sweep A (along dimension a, or none: a = -1) with the
+ * following sweep B along the contiguous dimension, one row at a time over
+ * the rows (p0, p1) = (i0 * rstep[0], i1 * rstep[1]). */
+constexpr uint32_t kRowMaxEven = 8192; /* rows of up to 16384 points */
+struct RowJob {
+  int32_t a;
+  uint32_t rstep[2], rcnt[2];
+  uint32_t rows_per_wg; /* set by the launcher */
+  Sweep A, B;
+};
+
 /* Complete plan of one compression / decompression. */
 struct Plan {
   Geo g;
@@ -128,6 +139,8 @@ enum ProfKind {
   PK_TUNE_TRIAL,
   PK_SSIM,
   PK_REDUCE,
+  PK_ROW_COMP_L1,
+  PK_ROW_DEC_L1,
   PK_COUNT
 };
 
@@ -211,6 +224,10 @@ qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* 
                         uint64_t* n_unpred, uint64_t* n_used,
                         uint64_t* n_words);
 void fill_sweep_table(const Plan& p, SweepTable* t);
+/* Level-1 row fusion: indices of sweeps A (SIZE_MAX if none) and B and the
+ * job; false when the level has no sweep along the contiguous dimension or
+ * its rows are too long for the row kernels. */
+bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj);
 
 /* ---- Huffman (host side, huffman_host.cpp) ---------------------------- */
 bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
@@ -240,6 +257,11 @@ void launch_anchor_scatter(const Geo& g, uint32_t stride, const uint32_t na[3],
 void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
                        float* W, uint16_t* codes, bool write_w,
                        uint32_t* status, hipStream_t s);
+void launch_row_comp(const Geo& g, const RowJob& rj, const float* x, float* W,
+                     uint16_t* codes, bool write_w, uint32_t* status,
+                     hipStream_t s);
+void launch_row_decomp(const Geo& g, const RowJob& rj, float* W,
+                       const uint16_t* codes, hipStream_t s);
 void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
                          const uint16_t* codes, hipStream_t s);
 void launch_unpred_scatter(const Geo& g, const SweepTable& st,
