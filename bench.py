@@ -44,9 +44,15 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=0,
                     help="edge of a central crop for the CPU baseline "
                          "(0 = whole field)")
-    ap.add_argument("--traffic", type=str, default="",
-                    help="JSON file with measured HBM bytes per launch of "
-                         "the dominant kernel")
+    ap.add_argument("--traffic", type=str,
+                    default=os.path.join(ROOT, "profiles",
+                                         "traffic_512cube_grf.json"),
+                    help="measured HBM bytes per launch (rocprofv3 FETCH_SIZE"
+                         " + WRITE_SIZE, copy-calibrated); ignored for a "
+                         "kernel whose source changed since")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times "
+                         "(the reference for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -57,6 +63,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        n = 64 << 20
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 4, "copies": 3}), flush=True)
+        return
 
     import paper_2310_14133_amd as q
     from paper_2310_14133_amd import fields
@@ -145,10 +161,8 @@ def main():
     value = field_bytes / (ms_per_step / 1e3) / 1e9
     launches, tot_ms, algo_bytes = timed
     achieved = (algo_bytes / 1e9) / (tot_ms / 1e3)
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            traffic = json.load(f).get(dom)
+    from paper_2310_14133_amd import profiling
+    traffic = profiling.load_traffic(args.traffic, dom)
 
     line = {
         "metric": "comp/decomp GB/s, 512^3 f32, eb 1e-3; tune time + CR vs "
