@@ -8,9 +8,11 @@
  * unpredictable values before each chunk u32[C+1]; segment bit lengths
  * u16[7 C]; unpredictable values f32[U]; Huffman payload u32[W], each chunk
  * of 4096 bins starting on a word boundary and packed most-significant bit
- * first.  A chunk is cut into eight segments of 512 bins; the stream keeps
- * the payload bits of its first seven (0 for a segment past the last bin),
- * so each segment can be decoded on its own.  No dictionary (zstd) stage
+ * first.  A chunk is cut into eight interleaved segments: segment j holds
+ * the chunk's bins j, j + 8, j + 16, ... and the payload stores segment 0,
+ * then segment 1, and so on; the stream keeps the payload bits of segments
+ * 0..6 (0 for an empty segment), so each segment can be decoded on its own.
+ * Unpredictable values stay in bin order.  No dictionary (zstd) stage
  * follows the Huffman stage.
  */
 #include <cmath>
@@ -154,18 +156,21 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
     uint64_t hi = std::min<uint64_t>(lo + QREF_CHUNK, n_codes);
     uint64_t bitpos = 0;
     size_t base = words.size();
-    for (uint64_t i = lo; i < hi; ++i) {
-      int32_t s = codes[i];
-      if (s == 0) ++zeros;
-      const uint64_t j = (i - lo) / QREF_SEG;
-      if (j + 1 < kSegPerChunk)
-        segs[ch * (kSegPerChunk - 1) + j] += (uint16_t)len[s];
-      for (int b = len[s] - 1; b >= 0; --b) {
-        uint32_t bit = (uint32_t)((code[s] >> b) & 1u);
-        size_t wi = base + bitpos / 32;
-        if (wi >= words.size()) words.push_back(0);
-        words[wi] |= bit << (31 - (bitpos % 32));
-        ++bitpos;
+    for (uint64_t i = lo; i < hi; ++i)
+      if (codes[i] == 0) ++zeros;
+    /* segment j: the chunk's bins j, j + 8, ..., segments in order */
+    for (uint32_t j = 0; j < kSegPerChunk; ++j) {
+      for (uint64_t i = lo + j; i < hi; i += kSegPerChunk) {
+        int32_t s = codes[i];
+        if (j + 1 < kSegPerChunk)
+          segs[ch * (kSegPerChunk - 1) + j] += (uint16_t)len[s];
+        for (int b = len[s] - 1; b >= 0; --b) {
+          uint32_t bit = (uint32_t)((code[s] >> b) & 1u);
+          size_t wi = base + bitpos / 32;
+          if (wi >= words.size()) words.push_back(0);
+          words[wi] |= bit << (31 - (bitpos % 32));
+          ++bitpos;
+        }
       }
     }
   }
@@ -181,7 +186,7 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   uint8_t* o = (uint8_t*)out;
   std::memset(o, 0, lay.total);
   std::memcpy(o, "QOZ1", 4);
-  put<uint16_t>(o, 4, 2);
+  put<uint16_t>(o, 4, 3);
   put<uint8_t>(o, 6, (uint8_t)g.d);
   put<uint8_t>(o, 7, (uint8_t)kSegLog2);
   for (int i = 0; i < 3; ++i)
@@ -239,7 +244,7 @@ struct Parsed {
 int parse(const uint8_t* in, size_t n, Parsed* P) {
   if (!in || n < kHeader) return QREF_EFORMAT;
   if (std::memcmp(in, "QOZ1", 4) != 0) return QREF_EFORMAT;
-  if (get<uint16_t>(in, 4) != 2) return QREF_EFORMAT;
+  if (get<uint16_t>(in, 4) != 3) return QREF_EFORMAT;
   if (get<uint8_t>(in, 7) != kSegLog2) return QREF_EFORMAT;
   qref_shape sh;
   std::memset(&sh, 0, sizeof(sh));
@@ -362,43 +367,42 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
     uint64_t bitpos = 0;
     uint64_t lo = ch * QREF_CHUNK;
     uint64_t hi = std::min<uint64_t>(lo + QREF_CHUNK, c.n_codes);
-    /* segment j must start where the bit lengths of 0..j-1 say, and a
-     * segment past the last bin has length 0 */
+    /* segment j (bins j, j + 8, ...) must start where the bit lengths of
+     * segments 0..j-1 say; an empty segment has length 0; a segment with a
+     * stored length must end exactly there, the last one inside the
+     * chunk's words */
     uint64_t seg_end = 0;
-    for (uint32_t j = 0; j + 1 < kSegPerChunk; ++j) {
+    for (uint32_t j = 0; j < kSegPerChunk; ++j) {
       const uint16_t b =
-          get<uint16_t>(in, lay.segs + 2 * (ch * (kSegPerChunk - 1) + j));
-      if (lo + (uint64_t)j * QREF_SEG >= hi && b != 0) return QREF_EFORMAT;
-    }
-    for (uint64_t i = lo; i < hi; ++i) {
-      if ((i - lo) % QREF_SEG == 0) {
-        if (bitpos != seg_end) return QREF_EFORMAT;
-        const uint64_t j = (i - lo) / QREF_SEG;
-        if (j + 1 < kSegPerChunk)
-          seg_end += get<uint16_t>(
-              in, lay.segs + 2 * (ch * (kSegPerChunk - 1) + j));
-        else
-          seg_end = nbits;
+          j + 1 < kSegPerChunk
+              ? get<uint16_t>(in, lay.segs + 2 * (ch * (kSegPerChunk - 1) + j))
+              : 0;
+      if (lo + j >= hi) {
+        if (b != 0) return QREF_EFORMAT;
+        continue;
       }
-      uint64_t v = 0;
-      int l = 0;
-      for (;;) {
-        if (bitpos >= nbits) return QREF_EFORMAT;
-        uint32_t word = get<uint32_t>(in, lay.payload + 4 * (w0 + bitpos / 32));
-        uint32_t bit = (word >> (31 - (bitpos % 32))) & 1u;
-        ++bitpos;
-        v = (v << 1) | bit;
-        ++l;
-        if (l > 63) return QREF_EFORMAT;
-        if (cnt[l] && v >= first[l] && v - first[l] < cnt[l]) break;
+      if (bitpos != seg_end) return QREF_EFORMAT;
+      seg_end = j + 1 < kSegPerChunk ? seg_end + b : nbits;
+      for (uint64_t i = lo + j; i < hi; i += kSegPerChunk) {
+        uint64_t v = 0;
+        int l = 0;
+        for (;;) {
+          if (bitpos >= nbits) return QREF_EFORMAT;
+          uint32_t word =
+              get<uint32_t>(in, lay.payload + 4 * (w0 + bitpos / 32));
+          uint32_t bit = (word >> (31 - (bitpos % 32))) & 1u;
+          ++bitpos;
+          v = (v << 1) | bit;
+          ++l;
+          if (l > 63) return QREF_EFORMAT;
+          if (cnt[l] && v >= first[l] && v - first[l] < cnt[l]) break;
+        }
+        int32_t s = (int32_t)sorted[fidx[l] + (v - first[l])];
+        codes[i] = s;
+        if (s == 0) ++zeros;
       }
-      int32_t s = (int32_t)sorted[fidx[l] + (v - first[l])];
-      codes[i] = s;
-      if (s == 0) ++zeros;
+      if (j + 1 < kSegPerChunk && bitpos != seg_end) return QREF_EFORMAT;
     }
-    /* a last segment with a stored length must end exactly there */
-    if ((hi - lo - 1) / QREF_SEG + 1 < kSegPerChunk && bitpos != seg_end)
-      return QREF_EFORMAT;
   }
   if (get<uint64_t>(in, lay.coff + 8 * c.n_chunks) != c.n_words)
     return QREF_EFORMAT;

@@ -37,10 +37,11 @@ constexpr uint32_t kSortedLds = 1024; /* canonical symbols kept in LDS */
 constexpr uint32_t kRing = 16;        /* payload words per lane in LDS */
 constexpr uint32_t kHalf = kRing / 2;
 constexpr uint32_t kInvalid = 0xffffffffu;
-constexpr uint32_t kZeroCap = 4; /* symbol-0 positions kept per lane */
 
 struct DecShared {
   uint32_t ring[kRing][kDecWG];
+  /* per chunk, the 64 bins of the group being decoded, in bin order */
+  __align__(16) uint16_t tb[kChunksPerWG][64];
   uint8_t lz[1u << kLenBits];
   uint16_t sym[1u << kSymBits];
   uint16_t sorted[kSortedLds];
@@ -252,17 +253,15 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
   const uint32_t start = group_incl_scan(d, j) - d;
   const uint32_t nw = bad ? 0u : (uint32_t)(w1 - w0);
   const uint32_t nbits = nw * 32;
-  const uint32_t seg_lo = j * kSeg;
-  const uint32_t seg_n =
-      nsym > seg_lo ? (nsym - seg_lo < kSeg ? nsym - seg_lo : kSeg) : 0u;
+  /* segment j holds the chunk's bins j, j + 8, ... */
+  const uint32_t seg_n = j < nsym ? (nsym - j + 7) / 8 : 0u;
   if (have && (start > nbits || (seg_n == 0 && d != 0))) bad = true;
+  const bool chunk_ok = have && group_or(bad ? 1u : 0u) == 0;
 
   /* decode */
-  const Words W{payload + w0, have && !bad ? nw : 0u,
-                have && !bad ? (uint32_t)(n_words - w0) : 0u};
-  const uint64_t out0 = c * kChunk + seg_lo;
-  const uint32_t n_run = have && !bad ? seg_n : 0u;
-  uint32_t nz = 0, zp01 = 0, zp23 = 0, t = 0;
+  const Words W{payload + w0, chunk_ok ? nw : 0u,
+                chunk_ok ? (uint32_t)(n_words - w0) : 0u};
+  const uint64_t base = c * kChunk;
   bool inv = false;
   Reader rd;
   rd.seek(sh, W, start);
@@ -294,21 +293,56 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     rd.buf |= (uint64_t)(need ? nx : 0u) << ((uint32_t)(32 - rd.nb) & 31u);
     rd.wp += need ? 1u : 0u;
     rd.nb += need ? 32 : 0;
-    if (__builtin_expect(s == 0, 0)) {
-      if (nz < kZeroCap) {
-        const uint32_t v = t << ((nz & 1u) * 16);
-        if (nz < 2)
-          zp01 |= v;
-        else
-          zp23 |= v;
-      }
-      ++nz;
-    }
-    ++t;
     return s;
   };
-  /* groups of eight bins, one 16-byte store each */
-  while (t + 8 <= n_run) {
+  /* Group g: step u of lane j is bin 64 g + 8 u + j.  The chunk's eight
+   * lanes (one wave) put their steps into the chunk's LDS block in bin
+   * order, then lane j takes bins 64 g + 8 j .. + 7: one 16-byte store per
+   * lane, a full 128-byte line per chunk.  Symbol-0 bins are ranked in bin
+   * order: zeros of earlier groups, then of lower lanes, then within. */
+  uint16_t* blk = sh.tb[threadIdx.x / kSegPerChunk];
+  uint32_t zacc = 0;
+  bool zbad = false;
+  auto emit = [&](uint32_t g, const uint32_t* pk, uint32_t nsteps) {
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u)
+      blk[8 * u + j] =
+          u < nsteps ? (uint16_t)(pk[u >> 1] >> (16 * (u & 1))) : (uint16_t)1;
+    __builtin_amdgcn_wave_barrier();
+    const uint4 q = *reinterpret_cast<const uint4*>(blk + 8 * j);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t nat = 64 * g + 8 * j; /* first bin of this lane's run */
+    const uint32_t nval = nat < nsym ? (nsym - nat < 8 ? nsym - nat : 8) : 0;
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    uint32_t zm = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i)
+      zm |= (i < nval && ((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) == 0)
+                ? 1u << i
+                : 0u;
+    if (__any(zm != 0)) {
+      const uint32_t zc = __popc(zm);
+      const uint32_t zi = group_incl_scan(zc, j);
+      uint32_t r = u0 + zacc + zi - zc;
+      for (uint32_t m = zm; m; m &= m - 1) {
+        if (r < u1)
+          upos[r] = (uint32_t)(base + nat + (uint32_t)__ffs(m) - 1);
+        else
+          zbad = true;
+        ++r;
+      }
+      zacc += __shfl(zi, kSegPerChunk - 1, kSegPerChunk);
+    }
+    if (nval == 8) {
+      *reinterpret_cast<uint4*>(codes + base + nat) = q;
+    } else {
+      for (uint32_t i = 0; i < nval; ++i)
+        codes[base + nat + i] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+    }
+  };
+  const uint32_t g_full = chunk_ok ? nsym / 64 : 0u;
+  const uint32_t g_all = chunk_ok ? (nsym + 63) / 64 : 0u;
+  for (uint32_t g = 0; g < g_full; ++g) {
     uint32_t pk[4];
 #pragma unroll
     for (uint32_t u = 0; u < 8; u += 2) {
@@ -316,38 +350,20 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
       pk[u >> 1] = lo | (step() << 16);
     }
     rd.group_end(sh, W);
-    *reinterpret_cast<uint4*>(codes + out0 + t - 8) =
-        make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    emit(g, pk, 8);
   }
-  while (t < n_run) {
-    const uint32_t s = step();
-    codes[out0 + t - 1] = (uint16_t)s;
+  if (g_all > g_full) { /* the last, partial group of the stream */
+    const uint32_t have_steps = seg_n > 8 * g_full ? seg_n - 8 * g_full : 0u;
+    uint32_t pk[4] = {0, 0, 0, 0};
+    for (uint32_t u = 0; u < have_steps; ++u)
+      pk[u >> 1] |= step() << (16 * (u & 1));
+    emit(g_full, pk, have_steps);
   }
-  if (have && !bad) {
+  if (chunk_ok) {
     const uint32_t end = j + 1 < kSegPerChunk ? start + d : nbits;
-    if (inv || (j + 1 < kSegPerChunk ? rd.pos != end : rd.pos > end))
+    if (inv || zbad || (j + 1 < kSegPerChunk ? rd.pos != end : rd.pos > end))
       bad = true;
-  }
-
-  /* ranks of the symbol-0 bins: scan of the counts over the chunk */
-  const uint32_t zi = group_incl_scan(nz, j);
-  const uint32_t ztot = __shfl(zi, kSegPerChunk - 1, kSegPerChunk);
-  const bool badc = group_or(bad ? 1u : 0u) != 0;
-  if (have && !badc && ztot != u1 - u0) bad = true;
-  if (have && !bad && !badc && nz) {
-    const uint32_t r0 = u0 + zi - nz;
-    if (nz <= kZeroCap) {
-      for (uint32_t k = 0; k < nz; ++k) {
-        const uint32_t w = k < 2 ? zp01 : zp23;
-        const uint32_t at = (w >> ((k & 1u) * 16)) & 0xffffu;
-        upos[r0 + k] = (uint32_t)(out0 + at);
-      }
-    } else { /* more than the lane kept: find them in its own output */
-      __threadfence();
-      uint32_t k = 0;
-      for (uint32_t i = 0; i < seg_n && k < nz; ++i)
-        if (codes[out0 + i] == 0) upos[r0 + k++] = (uint32_t)(out0 + i);
-    }
+    if (zacc != u1 - u0) bad = true;
   }
   if (have && bad) atomicOr(status, kStBadStream);
 }

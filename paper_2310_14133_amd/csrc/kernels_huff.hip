@@ -279,6 +279,13 @@ __device__ __forceinline__ void put_bits(uint32_t* words, uint32_t pos,
   }
 }
 
+/* Segment-major packing: segment j holds the chunk's bins j, j + 8, ....
+ * The chunk's bins are staged in LDS by segment (cbin[j * 512 + k] = bin
+ * 8k + j), lane t packs bins k in [16 (t mod 32), +16) of segment t / 32,
+ * so the thread-order scan of bit counts is the payload order.
+ * Unpredictable values are gathered in bin order: the staging lanes count
+ * the zero bins of their two 8-bin groups (rounds 0 and 1, packed in one
+ * scan word) and rank them in bin order. */
 __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
     const uint16_t* __restrict__ codes, uint64_t n,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
@@ -287,26 +294,63 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
     uint32_t* payload, uint64_t cap_words,
     float* unpred, const float* __restrict__ x, Geo g, SweepTable st,
     uint32_t* status) {
+  constexpr uint32_t kRounds = kChunk / (8 * kEncThreads); /* 2 */
+  constexpr uint32_t kSegBins = kChunk / kSegPerChunk;      /* 512 */
   __shared__ uint32_t words[kEncMaxWords];
+  __shared__ __align__(16) uint16_t cbin[kChunk];
   __shared__ uint32_t sbits[kEncThreads], szero[kEncThreads];
   const uint32_t c = blockIdx.x;
+  const uint64_t base = (uint64_t)c * kChunk;
+  const uint32_t nsym = (uint32_t)(n - base < kChunk ? n - base : kChunk);
   const uint64_t w0 = coff[c];
   const uint32_t nw = (uint32_t)(coff[c + 1] - w0);
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) words[i] = 0;
-  const uint64_t first = (uint64_t)c * kChunk + threadIdx.x * kEncPerThread;
-  int32_t sym[kEncPerThread];
-  uint64_t ent[kEncPerThread];
-  uint32_t bits = 0, zeros = 0;
+  /* staging: lane t takes the 8-bin groups m = t + 256 r */
+  uint32_t v[kRounds][8];
+  uint32_t zpack = 0;
 #pragma unroll
-  for (uint32_t k = 0; k < kEncPerThread; ++k) {
-    uint64_t i = first + k;
-    sym[k] = i < n ? codes[i] : -1;
-    ent[k] = sym[k] >= 0 ? code_entry(tab, lo, tn, zero_entry, sym[k]) : 0;
-    bits += (uint32_t)(ent[k] & 0xff);
-    zeros += sym[k] == 0;
+  for (uint32_t r = 0; r < kRounds; ++r) {
+    const uint32_t m = threadIdx.x + r * kEncThreads;
+    if (8 * m + 8 <= nsym) {
+      const uint4 q = *reinterpret_cast<const uint4*>(codes + base + 8 * m);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) v[r][i] = (w[i / 2] >> (16 * (i & 1))) & 0xffffu;
+    } else {
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i)
+        v[r][i] = 8 * m + i < nsym ? codes[base + 8 * m + i] : 1u;
+    }
+    uint32_t z = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i) {
+      cbin[i * kSegBins + m] = (uint16_t)v[r][i];
+      z += v[r][i] == 0 ? 1u : 0u;
+    }
+    zpack |= z << (16 * r);
+  }
+  __syncthreads();
+  constexpr uint32_t kLanesPerSeg = kSeg / kEncPerThread;
+  static_assert(kLanesPerSeg * kEncPerThread == kSeg, "segment lanes");
+  static_assert(kRounds == 2 && kSegBins == kSeg, "chunk layout");
+  const uint32_t j = threadIdx.x / kLanesPerSeg;
+  const uint32_t k0 = (threadIdx.x % kLanesPerSeg) * kEncPerThread;
+  uint64_t ent[kEncPerThread];
+  uint32_t bits = 0;
+  {
+    const uint4* cb = reinterpret_cast<const uint4*>(cbin + j * kSegBins + k0);
+    const uint4 qa = cb[0], qb = cb[1];
+    const uint32_t w[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+    for (uint32_t k = 0; k < kEncPerThread; ++k) {
+      const uint32_t b = (k0 + k) * kSegPerChunk + j; /* bin in the chunk */
+      const uint32_t sym = (w[k / 2] >> (16 * (k & 1))) & 0xffffu;
+      ent[k] = b < nsym ? code_entry(tab, lo, tn, zero_entry, (int32_t)sym) : 0;
+      bits += (uint32_t)(ent[k] & 0xff);
+    }
   }
   sbits[threadIdx.x] = bits;
-  szero[threadIdx.x] = zeros;
+  szero[threadIdx.x] = zpack;
   __syncthreads();
   for (uint32_t o = 1; o < kEncThreads; o <<= 1) {
     uint32_t vb = threadIdx.x >= o ? sbits[threadIdx.x - o] : 0;
@@ -317,28 +361,32 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
     __syncthreads();
   }
   uint32_t pos = sbits[threadIdx.x] - bits;
-  uint32_t zr = upre[c] + szero[threadIdx.x] - zeros;
+  const uint32_t zex = szero[threadIdx.x] - zpack;
+  const uint32_t ztot0 = szero[kEncThreads - 1] & 0xffffu;
+  uint32_t zr[kRounds] = {upre[c] + (zex & 0xffffu),
+                          upre[c] + ztot0 + (zex >> 16)};
   /* payload bits of segments 0..6: the last lane of each segment holds the
    * inclusive bit count at the segment's end */
-  constexpr uint32_t kLanesPerSeg = kSeg / kEncPerThread;
-  static_assert(kLanesPerSeg * kEncPerThread == kSeg, "segment lanes");
-  if (threadIdx.x % kLanesPerSeg == kLanesPerSeg - 1) {
-    const uint32_t j = threadIdx.x / kLanesPerSeg;
-    if (j + 1 < kSegPerChunk) {
-      const uint32_t before = j ? sbits[j * kLanesPerSeg - 1] : 0u;
-      segs[(uint64_t)c * (kSegPerChunk - 1) + j] =
-          (uint16_t)(sbits[threadIdx.x] - before);
-    }
+  if (threadIdx.x % kLanesPerSeg == kLanesPerSeg - 1 && j + 1 < kSegPerChunk) {
+    const uint32_t before = j ? sbits[j * kLanesPerSeg - 1] : 0u;
+    segs[(uint64_t)c * (kSegPerChunk - 1) + j] =
+        (uint16_t)(sbits[threadIdx.x] - before);
   }
 #pragma unroll
   for (uint32_t k = 0; k < kEncPerThread; ++k) {
-    uint32_t len = (uint32_t)(ent[k] & 0xff);
+    const uint32_t len = (uint32_t)(ent[k] & 0xff);
     if (len) put_bits(words, pos, ent[k] >> 8, len);
     pos += len;
-    if (sym[k] == 0) {
-      unpred[zr] = x[point_of(st, g, first + k)];
-      ++zr;
-    }
+  }
+#pragma unroll
+  for (uint32_t r = 0; r < kRounds; ++r) {
+    const uint32_t m = threadIdx.x + r * kEncThreads;
+#pragma unroll
+    for (uint32_t i = 0; i < 8; ++i)
+      if (v[r][i] == 0) {
+        unpred[zr[r]] = x[point_of(st, g, base + 8 * m + i)];
+        ++zr[r];
+      }
   }
   __syncthreads();
   bool over = false;

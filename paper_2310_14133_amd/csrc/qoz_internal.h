@@ -25,7 +25,7 @@ constexpr uint32_t kSegLog2 = 9;           /* a chunk holds 8 segments of */
 constexpr uint32_t kSeg = 1u << kSegLog2;  /* 512 bins, each decodable alone */
 constexpr uint32_t kSegPerChunk = kChunk / kSeg;
 constexpr size_t kHeaderBytes = 184;
-constexpr uint16_t kStreamVersion = 2;
+constexpr uint16_t kStreamVersion = 3;
 constexpr int kLenBits = 13;               /* decoder length-table width */
 constexpr int kSymBits = 12;               /* decoder symbol-table width */
 constexpr int kMaxCodeLen = 63;

@@ -128,7 +128,7 @@ def test_stream_header_fields(ref):
     z = ref.compress(x, 0.01, p)
     assert bytes(z[:4]) == b"QOZ1"
     hdr = z[:184].tobytes()
-    assert int(np.frombuffer(hdr[4:6], np.uint16)[0]) == 2  # version
+    assert int(np.frombuffer(hdr[4:6], np.uint16)[0]) == 3  # version
     assert hdr[7] == 9                               # log2 segment size
     u64 = lambda o: int(np.frombuffer(hdr[o:o + 8], np.uint64)[0])
     u32 = lambda o: int(np.frombuffer(hdr[o:o + 4], np.uint32)[0])
@@ -204,10 +204,12 @@ def _segs_section(z):
     return off, n_chunks
 
 
-@pytest.mark.parametrize("shape,rel", [((70, 90, 40), 1e-3), ((33, 1500), 1e-4)])
+@pytest.mark.parametrize("shape,rel", [((70, 90, 40), 1e-3), ((33, 1500), 1e-4),
+                                       ((2, 2065), 1e-3)])
 def test_segment_table(ref, shape, rel):
-    """Each stored segment length is the sum of the Huffman code lengths of
-    its 512 bins (0 past the last bin), so a segment decodes on its own."""
+    """Segment j of a chunk holds its bins j, j + 8, j + 16, ...; each stored
+    segment length is the sum of the Huffman code lengths of those bins
+    (0 for an empty segment), so a segment decodes on its own."""
     x = fields.grf(shape, 4)
     e = rel * (float(x.max()) - float(x.min()))
     p = ref.make_params(x.ndim, "cubic", None, 1.25, 2.0)
@@ -221,18 +223,17 @@ def test_segment_table(ref, shape, rel):
     per_bin = ln[codes]
     pad = np.zeros(n_chunks * 4096, np.int64)
     pad[:per_bin.size] = per_bin
-    want = pad.reshape(n_chunks, 8, 512).sum(axis=2)[:, :7]
+    want = pad.reshape(n_chunks, 512, 8).sum(axis=1)[:, :7]
     assert n_chunks >= 2 and codes.size % 4096 != 0
     assert np.array_equal(segs, want)
     # a wrong length is rejected
     bad = z.copy()
     bad[off + 2] ^= 0x01
     assert ref.decompress_status(bad) == ref.EFORMAT
-    # so is a nonzero length past the last bin
-    last = n_chunks - 1
-    tail_segs = -(-(codes.size - last * 4096) // 512)
-    if tail_segs < 7:
+    # so is a nonzero length for an empty segment
+    tail = codes.size - (n_chunks - 1) * 4096
+    if tail < 7:
+        assert np.all(segs[-1, tail:] == 0)
         bad = z.copy()
-        k = off + 2 * (7 * last + 6)
-        bad[k] = 1
+        bad[off + 2 * (7 * (n_chunks - 1) + 6)] = 1
         assert ref.decompress_status(bad) == ref.EFORMAT
