@@ -89,26 +89,71 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v,
   return r;
 }
 
+/* Bits and symbol-0 count per chunk.  Workgroups are persistent over
+ * chunks; code lengths of the symbols [lo, lo + tn) sit in LDS as bytes
+ * (from the code table in global memory when the range is wider than the
+ * LDS copy).  A lane reads 16 bins as two 16-byte loads. */
+constexpr uint32_t kLenLds = 16384;
+
 __global__ __launch_bounds__(kEncThreads) void k_huff_len(
     const uint16_t* __restrict__ codes, uint64_t n,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, uint32_t* chunk_bits, uint32_t* chunk_zeros) {
-  __shared__ uint32_t sh[2][kEncThreads / 64];
-  const uint64_t base = (uint64_t)blockIdx.x * kChunk;
-  uint32_t bits = 0, zeros = 0;
-  for (uint32_t k = 0; k < kEncPerThread; ++k) {
-    uint64_t i = base + k * kEncThreads + threadIdx.x;
-    if (i < n) {
-      int32_t sym = codes[i];
-      bits += (uint32_t)(code_entry(tab, lo, tn, zero_entry, sym) & 0xff);
-      zeros += sym == 0;
+  __shared__ uint8_t lens[kLenLds];
+  __shared__ uint32_t wsum[2][kEncThreads / 64];
+  const bool in_lds = tn <= kLenLds;
+  if (in_lds)
+    for (uint32_t i = threadIdx.x; i < tn; i += kEncThreads)
+      lens[i] = (uint8_t)(tab[i] & 0xff);
+  __syncthreads();
+  const uint32_t zlen = (uint32_t)(zero_entry & 0xff);
+  const uint64_t n_chunks = (n + kChunk - 1) / kChunk;
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+    const uint64_t b0 = c * kChunk + (uint64_t)threadIdx.x * kEncPerThread;
+    uint32_t sym[kEncPerThread];
+    if (b0 + kEncPerThread <= n) {
+      const uint4* p = reinterpret_cast<const uint4*>(codes + b0);
+      const uint4 q0 = p[0], q1 = p[1];
+      const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+      for (uint32_t k = 0; k < kEncPerThread; ++k)
+        sym[k] = (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < kEncPerThread; ++k)
+        sym[k] = b0 + k < n ? codes[b0 + k] : 0xffffffffu;
     }
-  }
-  uint32_t tb = block_reduce_u32(bits, sh[0]);
-  uint32_t tz = block_reduce_u32(zeros, sh[1]);
-  if (threadIdx.x == 0) {
-    chunk_bits[blockIdx.x] = tb;
-    chunk_zeros[blockIdx.x] = tz;
+    uint32_t bits = 0, zeros = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kEncPerThread; ++k) {
+      const uint32_t s = sym[k];
+      if (s == 0xffffffffu) continue;
+      if (s == 0) {
+        bits += zlen;
+        ++zeros;
+        continue;
+      }
+      const uint32_t o = s - (uint32_t)lo;
+      bits += o < tn ? (in_lds ? lens[o] : (uint32_t)(tab[o] & 0xff)) : 0u;
+    }
+    bits = wave_sum_u32(bits);
+    zeros = wave_sum_u32(zeros);
+    if (lane == 0) {
+      wsum[0][wave] = bits;
+      wsum[1][wave] = zeros;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tb = 0, tz = 0;
+      for (uint32_t w = 0; w < kEncThreads / 64; ++w) {
+        tb += wsum[0][w];
+        tz += wsum[1][w];
+      }
+      chunk_bits[c] = tb;
+      chunk_zeros[c] = tz;
+    }
+    __syncthreads();
   }
 }
 
@@ -118,8 +163,9 @@ void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      uint32_t* chunk_zeros, hipStream_t s) {
   uint64_t chunks = (n_codes + kChunk - 1) / kChunk;
   if (!chunks) return;
-  hipLaunchKernelGGL(k_huff_len, dim3((uint32_t)chunks), dim3(kEncThreads), 0,
-                     s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
+  const uint32_t blocks = chunks < 2048 ? (uint32_t)chunks : 2048u;
+  hipLaunchKernelGGL(k_huff_len, dim3(blocks), dim3(kEncThreads), 0, s,
+                     codes, n_codes, table, tab_lo, tab_n, zero_entry,
                      chunk_bits, chunk_zeros);
 }
 

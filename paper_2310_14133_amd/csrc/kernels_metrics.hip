@@ -28,19 +28,51 @@ uint32_t range_parts(uint64_t n) {
 }
 uint32_t sse_parts(uint64_t n) { return range_parts(n); }
 
+/* four floats; a word-aligned 16-byte load */
+struct __attribute__((aligned(4))) Q4 {
+  float a, b, c, d;
+};
+
+/* Grid-stride over 4-float groups with four groups in flight per lane; the
+ * last n mod 4 values go to the first lanes. */
+template <class F>
+__device__ __forceinline__ void for_each4(const float* __restrict__ x,
+                                          uint64_t n, F&& f) {
+  const uint64_t n4 = n / 4;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const Q4* x4 = reinterpret_cast<const Q4*>(x);
+  uint64_t i = gid;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    const Q4 v0 = x4[i], v1 = x4[i + stride], v2 = x4[i + 2 * stride],
+             v3 = x4[i + 3 * stride];
+    f(i, v0);
+    f(i + stride, v1);
+    f(i + 2 * stride, v2);
+    f(i + 3 * stride, v3);
+  }
+  for (; i < n4; i += stride) f(i, x4[i]);
+}
+
 __global__ __launch_bounds__(kRedThreads) void k_range(
     const float* __restrict__ x, uint64_t n, float* pmin, float* pmax,
     uint32_t* status) {
   __shared__ float smin[kRedThreads], smax[kRedThreads];
   float lo = INFINITY, hi = -INFINITY;
   bool bad = false;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    float v = x[i];
+  auto take = [&](float v) {
     bad |= !isfinite(v);
     lo = fminf(lo, v);
     hi = fmaxf(hi, v);
-  }
+  };
+  for_each4(x, n, [&](uint64_t, const Q4& v) {
+    take(v.a);
+    take(v.b);
+    take(v.c);
+    take(v.d);
+  });
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < n % 4) take(x[n / 4 * 4 + gid]);
   smin[threadIdx.x] = lo;
   smax[threadIdx.x] = hi;
   __syncthreads();
@@ -70,12 +102,21 @@ __global__ __launch_bounds__(kRedThreads) void k_sse_max(
     double* psse, double* pmax) {
   __shared__ double ss[kRedThreads], sm[kRedThreads];
   double acc = 0.0, mx = 0.0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    double d = (double)x[i] - (double)y[i];
+  const Q4* y4 = reinterpret_cast<const Q4*>(y);
+  auto take = [&](float a, float b) {
+    const double d = (double)a - (double)b;
     acc += d * d;
     mx = fmax(mx, fabs(d));
-  }
+  };
+  for_each4(x, n, [&](uint64_t i, const Q4& v) {
+    const Q4 w = y4[i];
+    take(v.a, w.a);
+    take(v.b, w.b);
+    take(v.c, w.c);
+    take(v.d, w.d);
+  });
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < n % 4) take(x[n / 4 * 4 + gid], y[n / 4 * 4 + gid]);
   ss[threadIdx.x] = acc;
   sm[threadIdx.x] = mx;
   __syncthreads();
