@@ -136,6 +136,10 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     }
   }
   const uint64_t n_used = usym.size();
+  /* an encoder table entry holds the code above an 8-bit length; a code
+   * longer than 56 bits needs more than Fib(58) ~ 5.9e11 coded points */
+  for (uint64_t i = 0; i < n_used; ++i)
+    if (ulen[i] > 56) return fail(QOZ_EINVAL, "Huffman code longer than 56 bits");
   std::vector<uint64_t> ucode(n_used);
   canonical_codes_sparse(usym.data(), ulen.data(), (uint32_t)n_used,
                          ucode.data());
@@ -166,11 +170,12 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                           (uint32_t*)c->chunk_zeros.p, nch,
                           (uint64_t*)c->coff.p, (uint32_t*)c->upre.p, totals,
                           s)));
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus + 64), totals, 16,
+  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus + 64), totals, 24,
                          hipMemcpyDeviceToHost, s));
   QOZ_TRY(sync_checked(s));
   const uint64_t n_words = ((uint64_t*)pin(c, kPinStatus + 64))[0];
   const uint64_t n_unpred = ((uint64_t*)pin(c, kPinStatus + 64))[1];
+  const uint64_t max_chunk_words = ((uint64_t*)pin(c, kPinStatus + 64))[2];
   const Layout lay = layout_of(P.n_anchor, n_used, nch, n_unpred, n_words);
   if (!d_out || lay.total > cap) {
     *out_bytes = lay.total;
@@ -207,7 +212,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                           (uint16_t*)(out + lay.segs),
                           (uint32_t*)(out + lay.payload),
                           (cap - lay.payload) / 4, (float*)(out + lay.unpred),
-                          d_x, P.g, tbl, st, s));
+                          d_x, P.g, tbl, (uint32_t)max_chunk_words, st, s));
   QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
                          s));
   QOZ_TRY(sync_checked(s));

@@ -194,6 +194,7 @@ __global__ __launch_bounds__(kScanThreads) void k_chunk_scan(
   __shared__ uint64_t ww[kScanThreads / 64], wz[kScanThreads / 64];
   const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
   uint64_t run_w = 0, run_z = 0;
+  uint32_t wmax = 0;
   for (uint64_t base = 0; base < n; base += kScanTile) {
     const uint32_t cnt = (uint32_t)(n - base < kScanTile ? n - base : kScanTile);
     for (uint32_t i = t; i < kScanTile; i += kScanThreads) {
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(kScanThreads) void k_chunk_scan(
     for (uint32_t k = 0; k < kScanPer; ++k) {
       sw += tw[t * kScanPer + k];
       sz += tz[t * kScanPer + k];
+      wmax = wmax > tw[t * kScanPer + k] ? wmax : tw[t * kScanPer + k];
     }
     const uint64_t iw = wave_incl_scan_u64(sw), iz = wave_incl_scan_u64(sz);
     if (lane == 63) {
@@ -235,11 +237,20 @@ __global__ __launch_bounds__(kScanThreads) void k_chunk_scan(
     run_z += tot_z;
     __syncthreads();
   }
+  for (uint32_t o = 32; o > 0; o >>= 1) {
+    const uint32_t v = __shfl_xor(wmax, o, 64);
+    wmax = wmax > v ? wmax : v;
+  }
+  if (lane == 0) ww[wave] = wmax;
+  __syncthreads();
   if (t == 0) {
+    uint64_t m = 0;
+    for (uint32_t w = 0; w < kScanThreads / 64; ++w) m = m > ww[w] ? m : ww[w];
     coff[n] = run_w;
     upre[n] = (uint32_t)run_z;
     totals[0] = run_w;
     totals[1] = run_z;
+    totals[2] = m;
   }
 }
 
@@ -308,30 +319,40 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
                      chunk_bits, chunk_zeros, n_chunks, coff, upre, totals);
 }
 
-constexpr uint32_t kEncMaxWords = kChunk * kMaxCodeLen / 32 + 2;
-
-__device__ __forceinline__ void put_bits(uint32_t* words, uint32_t pos,
-                                         uint64_t code, uint32_t len) {
-  /* MSB-first: bit q of the chunk is bit (31 - q % 32) of word q / 32 */
-  while (len) {
-    uint32_t o = pos & 31;
-    uint32_t take = 32 - o < len ? 32 - o : len;
-    uint32_t part = (uint32_t)((code >> (len - take)) &
-                               ((take == 32) ? 0xffffffffull
-                                             : ((1ull << take) - 1)));
-    atomicOr(&words[pos >> 5], part << (32 - o - take));
-    pos += take;
-    len -= take;
-  }
-}
+/* words of a chunk: at most 56 bits per bin (the encoder table's limit) */
+constexpr uint32_t kEncMaxWords = kChunk * 56 / 32;
 
 /* Segment-major packing: segment j holds the chunk's bins j, j + 8, ....
  * The chunk's bins are staged in LDS by segment (cbin[j * 512 + k] = bin
  * 8k + j), lane t packs bins k in [16 (t mod 32), +16) of segment t / 32,
- * so the thread-order scan of bit counts is the payload order.
- * Unpredictable values are gathered in bin order: the staging lanes count
- * the zero bins of their two 8-bin groups (rounds 0 and 1, packed in one
- * scan word) and rank them in bin order. */
+ * so the thread-order scan of bit counts is the payload order.  A lane
+ * builds its bits in a register and writes whole words it alone covers
+ * with plain LDS stores, the (at most two) words it shares with its
+ * neighbours with atomic ORs.  Unpredictable values are gathered in bin
+ * order: the staging lanes count the zero bins of their two 8-bin groups
+ * (rounds 0 and 1, packed in one scan word) and rank them in bin order.
+ * The word buffer is dynamic LDS sized for the largest chunk. */
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
+                                                    uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(x, o, 64);
+    x += lane >= o ? t : 0u;
+  }
+  if (lane == 63) ws[wave] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kEncThreads / 64; ++w) {
+    pre += w < wave ? ws[w] : 0u;
+    tot += ws[w];
+  }
+  *total = tot;
+  return pre + x - v;
+}
+
 __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
     const uint16_t* __restrict__ codes, uint64_t n,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
@@ -342,9 +363,10 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
     uint32_t* status) {
   constexpr uint32_t kRounds = kChunk / (8 * kEncThreads); /* 2 */
   constexpr uint32_t kSegBins = kChunk / kSegPerChunk;      /* 512 */
-  __shared__ uint32_t words[kEncMaxWords];
+  extern __shared__ uint32_t words[];
   __shared__ __align__(16) uint16_t cbin[kChunk];
-  __shared__ uint32_t sbits[kEncThreads], szero[kEncThreads];
+  __shared__ uint32_t ws[2][kEncThreads / 64];
+  __shared__ uint32_t seg_end[kSegPerChunk];
   const uint32_t c = blockIdx.x;
   const uint64_t base = (uint64_t)c * kChunk;
   const uint32_t nsym = (uint32_t)(n - base < kChunk ? n - base : kChunk);
@@ -395,35 +417,47 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
       bits += (uint32_t)(ent[k] & 0xff);
     }
   }
-  sbits[threadIdx.x] = bits;
-  szero[threadIdx.x] = zpack;
+  uint32_t tot_bits, tot_z;
+  const uint32_t pos0 = block_excl_scan(bits, ws[0], &tot_bits);
+  const uint32_t zex = block_excl_scan(zpack, ws[1], &tot_z);
+  /* payload bits of segments 0..6: the last lane of each segment knows
+   * where the segment ends */
+  if (threadIdx.x % kLanesPerSeg == kLanesPerSeg - 1) seg_end[j] = pos0 + bits;
   __syncthreads();
-  for (uint32_t o = 1; o < kEncThreads; o <<= 1) {
-    uint32_t vb = threadIdx.x >= o ? sbits[threadIdx.x - o] : 0;
-    uint32_t vz = threadIdx.x >= o ? szero[threadIdx.x - o] : 0;
-    __syncthreads();
-    sbits[threadIdx.x] += vb;
-    szero[threadIdx.x] += vz;
-    __syncthreads();
-  }
-  uint32_t pos = sbits[threadIdx.x] - bits;
-  const uint32_t zex = szero[threadIdx.x] - zpack;
-  const uint32_t ztot0 = szero[kEncThreads - 1] & 0xffffu;
-  uint32_t zr[kRounds] = {upre[c] + (zex & 0xffffu),
-                          upre[c] + ztot0 + (zex >> 16)};
-  /* payload bits of segments 0..6: the last lane of each segment holds the
-   * inclusive bit count at the segment's end */
-  if (threadIdx.x % kLanesPerSeg == kLanesPerSeg - 1 && j + 1 < kSegPerChunk) {
-    const uint32_t before = j ? sbits[j * kLanesPerSeg - 1] : 0u;
-    segs[(uint64_t)c * (kSegPerChunk - 1) + j] =
-        (uint16_t)(sbits[threadIdx.x] - before);
-  }
+  if (threadIdx.x < kSegPerChunk - 1)
+    segs[(uint64_t)c * (kSegPerChunk - 1) + threadIdx.x] = (uint16_t)(
+        seg_end[threadIdx.x] - (threadIdx.x ? seg_end[threadIdx.x - 1] : 0u));
+  /* this lane's bits [pos0, pos0 + bits) */
+  {
+    uint64_t acc = 0;
+    uint32_t nacc = pos0 & 31u, wi = pos0 >> 5;
+    auto emit = [&](uint32_t word) {
+      if (wi * 32 >= pos0) /* covered by this lane alone */
+        words[wi] = word;
+      else
+        atomicOr(&words[wi], word);
+      ++wi;
+    };
 #pragma unroll
-  for (uint32_t k = 0; k < kEncPerThread; ++k) {
-    const uint32_t len = (uint32_t)(ent[k] & 0xff);
-    if (len) put_bits(words, pos, ent[k] >> 8, len);
-    pos += len;
+    for (uint32_t k = 0; k < kEncPerThread; ++k) {
+      uint32_t len = (uint32_t)(ent[k] & 0xff);
+      const uint64_t code = ent[k] >> 8;
+      while (len) {
+        const uint32_t take = len < 32 ? len : 32u;
+        const uint64_t part = (code >> (len - take)) & ((1ull << take) - 1);
+        acc = (acc << take) | part;
+        nacc += take;
+        len -= take;
+        if (nacc >= 32) {
+          nacc -= 32;
+          emit((uint32_t)(acc >> nacc));
+        }
+      }
+    }
+    if (nacc) atomicOr(&words[wi], (uint32_t)(acc << (32 - nacc)));
   }
+  uint32_t zr[kRounds] = {upre[c] + (zex & 0xffffu),
+                          upre[c] + (tot_z & 0xffffu) + (zex >> 16)};
 #pragma unroll
   for (uint32_t r = 0; r < kRounds; ++r) {
     const uint32_t m = threadIdx.x + r * kEncThreads;
@@ -452,11 +486,17 @@ void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         uint32_t* payload,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
-                        uint32_t* status, hipStream_t s) {
+                        uint32_t max_chunk_words, uint32_t* status,
+                        hipStream_t s) {
   uint64_t chunks = (n_codes + kChunk - 1) / kChunk;
   if (!chunks) return;
+  /* every chunk's word count is at most the largest one, which is at
+   * most kEncMaxWords (codes of at most 56 bits) */
+  const uint32_t mw = max_chunk_words < kEncMaxWords ? max_chunk_words
+                                                     : kEncMaxWords;
+  const size_t lds = 4 * ((size_t)mw + 1);
   hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)chunks), dim3(kEncThreads),
-                     0, s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
+                     lds, s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
                      coff, upre, segs, payload, payload_cap_words, unpred, x,
                      g, st, status);
 }

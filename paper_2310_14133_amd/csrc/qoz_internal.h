@@ -286,7 +286,8 @@ void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         uint32_t* payload,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
-                        uint32_t* status, hipStream_t s);
+                        uint32_t max_chunk_words, uint32_t* status,
+                        hipStream_t s);
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
                         const uint16_t* segs, uint64_t n_chunks, uint64_t n_codes,
