@@ -18,6 +18,7 @@ rest of the step runs uninstrumented.  cpu_baseline times the
 single-threaded CPU oracle on the same field.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -141,11 +142,23 @@ def main():
     q.qoz_ctx_set_timing_mask(ctx, 1 << dom_kind)
     print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    # the collector's full passes over torch's object graph take several ms
+    # and would land on whichever step triggers them (as timeit does, the
+    # collector is off while timing)
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     t0 = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
         p, nb = step()
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
+    step_ms = [(b - a) * 1e3 for a, b in zip([t0] + marks[:-1], marks)]
+    print("bench: step ms " + " ".join(f"{v:.3f}" for v in step_ms),
+          file=sys.stderr, flush=True)
     q.qoz_ctx_set_timing(ctx, False)
     timed = q.timing_table(ctx)[dom]
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -173,6 +186,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "step_ms": {"min": round(min(step_ms), 4),
+                    "median": round(sorted(step_ms)[len(step_ms) // 2], 4),
+                    "max": round(max(step_ms), 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

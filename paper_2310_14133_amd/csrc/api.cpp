@@ -93,10 +93,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   QOZ_TRY(ensure(c->hsort, 8 * (kSortCap + 1)));
   launch_hist_sort(hist, 1, (uint64_t*)c->hsort.p, s);
   uint64_t* hk = (uint64_t*)pin(c, kPinHist);
-  QOZ_HIP(hipMemcpyAsync(hk, c->hsort.p, 8 * (kSortCap + 1),
-                         hipMemcpyDeviceToHost, s));
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
-                         s));
+  QOZ_TRY(to_host(c, hk, c->hsort.p, 8 * (kSortCap + 1), s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
   QOZ_TRY(sync_checked(s));
   if (((uint32_t*)pin(c, kPinStatus))[0] & kStNonFinite)
     return fail(QOZ_EINVAL, "input contains NaN or Inf");
@@ -113,7 +111,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
       keys.assign(hk + 1, hk + 1 + n_keys);
     } else { /* too many used symbols for the device sort */
       uint32_t* h = (uint32_t*)pin(c, kPinTable);
-      QOZ_HIP(hipMemcpyAsync(h, hist, 4 * kNSym, hipMemcpyDeviceToHost, s));
+      QOZ_TRY(to_host(c, h, hist, 4 * kNSym, s));
       QOZ_TRY(sync_checked(s));
       for (uint32_t sy = 0; sy < kNSym; ++sy)
         if (h[sy]) keys.push_back(((uint64_t)h[sy] << 16) | sy);
@@ -159,8 +157,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   for (uint64_t i = 0; i < n_used; ++i)
     if (usym[i]) tab[usym[i] - lo] = (ucode[i] << 8) | ulen[i];
   if (tab_n)
-    QOZ_HIP(hipMemcpyAsync(c->enc_table.p, tab, 8ull * tab_n,
-                           hipMemcpyHostToDevice, s));
+    QOZ_TRY(to_device(c, c->enc_table.p, tab, 8ull * tab_n, s));
   const uint64_t* dtab = (const uint64_t*)c->enc_table.p;
   PROF(PK_HUFF_LEN, 2.0 * P.n_codes + 8.0 * nch,
        (launch_huff_len(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
@@ -170,8 +167,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                           (uint32_t*)c->chunk_zeros.p, nch,
                           (uint64_t*)c->coff.p, (uint32_t*)c->upre.p, totals,
                           s)));
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus + 64), totals, 24,
-                         hipMemcpyDeviceToHost, s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus + 64), totals, 24, s));
   QOZ_TRY(sync_checked(s));
   const uint64_t n_words = ((uint64_t*)pin(c, kPinStatus + 64))[0];
   const uint64_t n_unpred = ((uint64_t*)pin(c, kPinStatus + 64))[1];
@@ -187,14 +183,13 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   launch_zero_u32((uint32_t*)out, lay.payload / 4, s);
   uint8_t* hs = pin(c, kPinStage);
   write_header(hs, P, n_unpred, n_used, n_words);
-  QOZ_HIP(hipMemcpyAsync(out, hs, kHeaderBytes, hipMemcpyHostToDevice, s));
+  QOZ_TRY(to_device(c, out, hs, kHeaderBytes, s));
   uint8_t* cb = pin(c, kPinStage + 256);
   const size_t cb_bytes = lay.coff - lay.syms;
   std::memset(cb, 0, cb_bytes);
   std::memcpy(cb, usym.data(), 2 * n_used);
   std::memcpy(cb + (lay.lens - lay.syms), ulen.data(), n_used);
-  QOZ_HIP(hipMemcpyAsync(out + lay.syms, cb, cb_bytes, hipMemcpyHostToDevice,
-                         s));
+  QOZ_TRY(to_device(c, out + lay.syms, cb, cb_bytes, s));
   if (P.n_anchor)
     QOZ_HIP(hipMemcpyAsync(out + lay.anchors, c->anchors.p, 4 * P.n_anchor,
                            hipMemcpyDeviceToDevice, s));
@@ -213,8 +208,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                           (uint32_t*)(out + lay.payload),
                           (cap - lay.payload) / 4, (float*)(out + lay.unpred),
                           d_x, P.g, tbl, (uint32_t)max_chunk_words, st, s));
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
-                         s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
   QOZ_TRY(sync_checked(s));
   prof_collect(c);
   if (((uint32_t*)pin(c, kPinStatus))[0] & kStOverflow) {
@@ -311,7 +305,7 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   QOZ_TRY(ensure_pinned(c, kPinBase));
   if (in_bytes < kHeaderBytes) return fail(QOZ_EFORMAT, "stream too short");
   uint8_t* hs = pin(c, kPinStage);
-  QOZ_HIP(hipMemcpyAsync(hs, d_in, kHeaderBytes, hipMemcpyDeviceToHost, s));
+  QOZ_TRY(to_host(c, hs, d_in, kHeaderBytes, s));
   QOZ_TRY(sync_checked(s));
   Plan P;
   uint64_t nu, nused, nw;
@@ -323,8 +317,7 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   const Layout lay = layout_of(P.n_anchor, nused, nch, nu, nw);
   const uint8_t* in = (const uint8_t*)d_in;
   uint8_t* cb = pin(c, kPinStage + 256);
-  QOZ_HIP(hipMemcpyAsync(cb, in + lay.syms, lay.coff - lay.syms,
-                         hipMemcpyDeviceToHost, s));
+  QOZ_TRY(to_host(c, cb, in + lay.syms, lay.coff - lay.syms, s));
   QOZ_TRY(sync_checked(s));
   DecTables* dt = (DecTables*)pin(c, kPinTable);
   std::vector<uint32_t> sorted;
@@ -338,10 +331,9 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   QOZ_TRY(ensure(c->dec_syms, 4 * kNSym));
   QOZ_TRY(ensure(c->codes, 2 * (P.n_codes + 16)));
   QOZ_TRY(ensure(c->status, 256));
-  QOZ_HIP(hipMemcpyAsync(c->dec_tables.p, dt, sizeof(DecTables),
-                         hipMemcpyHostToDevice, s));
-  QOZ_HIP(hipMemcpyAsync(c->dec_syms.p, pin(c, kPinTable + syms_off),
-                         4 * sorted.size(), hipMemcpyHostToDevice, s));
+  QOZ_TRY(to_device(c, c->dec_tables.p, dt, sizeof(DecTables), s));
+  QOZ_TRY(to_device(c, c->dec_syms.p, pin(c, kPinTable + syms_off),
+                    4 * sorted.size(), s));
   QOZ_TRY(ensure(c->upos, 4 * (nu + 1)));
   uint32_t* st = (uint32_t*)c->status.p;
   uint16_t* codes = (uint16_t*)c->codes.p;
@@ -378,8 +370,7 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
          (double)sw.count * 10.0,
          launch_sweep_decomp(P.g, sw, d_y, codes, s));
   }
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
-                         s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
   QOZ_TRY(sync_checked(s));
   prof_collect(c);
   if (((uint32_t*)pin(c, kPinStatus))[0] & kStBadStream)
@@ -438,10 +429,8 @@ qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
   PROF(PK_CHECK, 4.0 * N, launch_range(d_x, N, pmin, pmax, st, rp, s));
   PROF(PK_REDUCE, 8.0 * N, launch_sse_max(d_x, d_y, N, psse, pmx, sp, s));
   const size_t part_bytes = 8 * (size_t)rp + 16 * (size_t)sp;
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinSmall), dp, part_bytes,
-                         hipMemcpyDeviceToHost, s));
-  QOZ_HIP(hipMemcpyAsync(pin(c, kPinStatus), st, 32, hipMemcpyDeviceToHost,
-                         s));
+  QOZ_TRY(to_host(c, pin(c, kPinSmall), dp, part_bytes, s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
   QOZ_TRY(sync_checked(s));
   const float* hmin = (const float*)pin(c, kPinSmall);
   const float* hmax = hmin + rp;
@@ -468,8 +457,7 @@ qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
     j.c2 = (0.03 * vrange) * (0.03 * vrange);
     double* parts = (double*)c->ssim_part.p;
     PROF(PK_SSIM, 8.0 * N, launch_ssim(j, d_x, d_y, parts, s));
-    QOZ_HIP(hipMemcpyAsync(pin(c, kPinSmall), parts, 8 * qp,
-                           hipMemcpyDeviceToHost, s));
+    QOZ_TRY(to_host(c, pin(c, kPinSmall), parts, 8 * qp, s));
     QOZ_TRY(sync_checked(s));
     const double* hp = (const double*)pin(c, kPinSmall);
     double tot = 0.0;

@@ -43,15 +43,50 @@ qoz_status ensure(DevBuf& b, size_t bytes) {
   return QOZ_OK;
 }
 
+/* The host staging buffer is coherent pinned memory that the device reads
+ * and writes directly: transfers to and from it are small kernels on the
+ * library's stream (no copy engine, whose first uses in a process can stall
+ * the stream for milliseconds). */
 qoz_status ensure_pinned(qoz_ctx* c, size_t bytes) {
   if (bytes <= c->pinned_bytes && c->pinned) return QOZ_OK;
   if (c->pinned) {
     QOZ_HIP(hipHostFree(c->pinned));
     c->pinned = nullptr;
+    c->pinned_dev = nullptr;
     c->pinned_bytes = 0;
   }
-  QOZ_HIP(hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+  QOZ_HIP(hipHostMalloc(&c->pinned, bytes,
+                        hipHostMallocMapped | hipHostMallocCoherent));
   c->pinned_bytes = bytes;
+  QOZ_HIP(hipHostGetDevicePointer(&c->pinned_dev, c->pinned, 0));
+  return QOZ_OK;
+}
+
+static qoz_status pinned_dev(qoz_ctx* c, const void* h, size_t bytes,
+                             void** d) {
+  const uint8_t* base = (const uint8_t*)c->pinned;
+  const uint8_t* p = (const uint8_t*)h;
+  if (!base || p < base || p + bytes > base + c->pinned_bytes)
+    return fail(QOZ_EDEVICE, "host transfer outside the staging buffer");
+  *d = (uint8_t*)c->pinned_dev + (p - base);
+  return QOZ_OK;
+}
+
+qoz_status to_host(qoz_ctx* c, void* h_dst, const void* d_src, size_t bytes,
+                   hipStream_t s) {
+  void* d = nullptr;
+  QOZ_TRY(pinned_dev(c, h_dst, bytes, &d));
+  launch_copy_bytes(d, d_src, bytes, s);
+  QOZ_HIP(hipGetLastError());
+  return QOZ_OK;
+}
+
+qoz_status to_device(qoz_ctx* c, void* d_dst, const void* h_src,
+                     size_t bytes, hipStream_t s) {
+  void* d = nullptr;
+  QOZ_TRY(pinned_dev(c, h_src, bytes, &d));
+  launch_copy_bytes(d_dst, d, bytes, s);
+  QOZ_HIP(hipGetLastError());
   return QOZ_OK;
 }
 

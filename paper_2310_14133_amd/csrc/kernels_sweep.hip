@@ -39,6 +39,34 @@ void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
                      n);
 }
 
+/* A plain copy: 16-byte words when both ends are 16-byte aligned, else
+ * bytes.  A system-scope fence makes writes to host memory visible before
+ * the kernel ends. */
+__global__ void k_copy_bytes(uint8_t* __restrict__ dst,
+                             const uint8_t* __restrict__ src, uint64_t n) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t done = 0;
+  if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
+    const uint64_t nq = n / 16;
+    for (uint64_t i = tid; i < nq; i += stride)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    done = nq * 16;
+  }
+  for (uint64_t i = done + tid; i < n; i += stride) dst[i] = src[i];
+  __threadfence_system();
+}
+
+void launch_copy_bytes(void* dst, const void* src, size_t bytes,
+                       hipStream_t s) {
+  if (!bytes) return;
+  uint64_t blocks = (bytes / 16 + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_copy_bytes, dim3((uint32_t)blocks), dim3(256), 0, s,
+                     (uint8_t*)dst, (const uint8_t*)src, (uint64_t)bytes);
+}
+
 /* Anchor grid (Sec. V-B): every point whose coordinates are all multiples
  * of s is stored verbatim, in row-major order of the anchor grid. */
 __global__ void k_anchor_copy(Geo g, uint32_t stride, uint32_t na0,

@@ -16,6 +16,24 @@
 
 namespace qoz {
 
+/* Division of t < tmax by a divisor shared by all lanes, as a
+ * multiply-high: m = ceil(2^32 / d) gives floor(t / d) exactly whenever
+ * t * d <= 2^32 (t = q d + r: t m / 2^32 = q + (r + t e / 2^32) / d with
+ * e = m d - 2^32 < d, and t e < 2^32 keeps the fraction below 1); larger
+ * ranges take the plain division. */
+struct FastDiv {
+  uint32_t d, m;
+  bool mul;
+  __device__ __forceinline__ FastDiv(uint32_t dv, uint32_t tmax)
+      : d(dv),
+        m(dv > 1 ? 0xffffffffu / dv + 1u : 0u), /* = ceil(2^32 / d) */
+        mul((uint64_t)tmax * dv <= (1ull << 32)) {}
+  __device__ __forceinline__ uint32_t div(uint32_t t) const {
+    if (d <= 1) return t;
+    return mul ? __umulhi(t, m) : t / d;
+  }
+};
+
 /* Interpolated value at a midpoint from a = f(-3h), b = f(-h), c = f(+h),
  * d = f(+3h).  Linear: mean of b and c.  Cubic: the 4-point midpoint rule
  * (-1, 9, 9, -1)/16, the one-sided 3-point rules (3, 6, -1)/8 and

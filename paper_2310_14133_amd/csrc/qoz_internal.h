@@ -167,6 +167,7 @@ struct qoz_ctx {
       hsort;
   /* pinned host staging */
   void* pinned = nullptr;
+  void* pinned_dev = nullptr; /* its device address */
   size_t pinned_bytes = 0;
   /* instrumentation */
   uint64_t timing_mask = 0; /* bit k: time launches of kind k */
@@ -197,6 +198,12 @@ void clear_error();
 /* ---- context helpers ------------------------------------------------- */
 qoz_status ensure(DevBuf& b, size_t bytes);
 qoz_status ensure_pinned(qoz_ctx* c, size_t bytes);
+/* stream-ordered transfers between device memory and the pinned staging
+ * buffer (the host pointer must lie inside it) */
+qoz_status to_host(qoz_ctx* c, void* h_dst, const void* d_src, size_t bytes,
+                   hipStream_t s);
+qoz_status to_device(qoz_ctx* c, void* d_dst, const void* h_src,
+                     size_t bytes, hipStream_t s);
 /* Instrumented launch bracket: call prof_begin before and prof_end after a
  * launch; resolved by prof_collect after the stream is synchronised. */
 hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s, int kind);
@@ -271,6 +278,9 @@ void launch_unpred_scatter(const Geo& g, const SweepTable& st,
 void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s);
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
+/* bytes from src to dst, either of which may be mapped host memory */
+void launch_copy_bytes(void* dst, const void* src, size_t bytes,
+                       hipStream_t s);
 void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
@@ -326,16 +336,24 @@ struct BlockGeo {
 void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
                           const uint32_t* origins_dev, float* xs,
                           hipStream_t s);
+/* whether Algorithm 1's level-l working copies fit in LDS on the current
+ * device (then no per-candidate copies in wt are made) */
+bool alg1_in_lds(const BlockGeo& bg, uint32_t l);
 void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
                        const float* wc, float* wt, uint32_t ncand,
                        const TrialDesc* cand_desc, double* l1_part,
-                       hipStream_t s);
-void launch_alg1_pick(const double* l1_part, uint32_t ncand, uint32_t nb,
-                      double count, uint32_t* pick, const float* wt,
-                      uint64_t bsz, float* wc, hipStream_t s);
+                       bool in_lds, hipStream_t s);
+/* the level's choice (first strict minimum) to *pick and its
+ * reconstruction committed to wc */
+void launch_alg1_pick(const BlockGeo& bg, uint32_t l, const float* xs,
+                      const TrialDesc* cand_desc, const double* l1_part,
+                      uint32_t ncand, double count, uint32_t* pick,
+                      const float* wt, float* wc, bool in_lds, hipStream_t s);
+/* keep_wt: leave each trial's reconstruction of each block in wt */
 void launch_trial(const BlockGeo& bg, const float* xs, float* wt,
                   uint32_t ntrial, const TrialDesc* desc, uint32_t* hist,
-                  double* sse_part, uint32_t* unpred_part, hipStream_t s);
+                  double* sse_part, uint32_t* unpred_part, bool keep_wt,
+                  hipStream_t s);
 
 }  // namespace qoz
 #endif

@@ -172,7 +172,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   QOZ_TRY(ensure(c->tune_desc,
                  sizeof(TrialDesc) * (nslots + adesc_n) + 4 * QOZ_MAX_LEVELS));
   QOZ_TRY(ensure(c->tune_l1, 8 * (size_t)nslots * bg.nb));
-  QOZ_TRY(ensure(c->tune_stats, 12 * (size_t)nslots * bg.nb));
+  QOZ_TRY(ensure(c->tune_stats, 24 * (size_t)nslots * bg.nb));
   QOZ_TRY(ensure(c->tune_hist, 4 * (size_t)kNSym * max_trials));
   SsimJob sj;
   std::memset(&sj, 0, sizeof(sj));
@@ -191,7 +191,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     QOZ_TRY(ensure(c->ssim_part, 8 * ssim_np));
   }
   const size_t pin_need = kPinTune + 4 * (size_t)kNSym * max_trials +
-                          12 * (size_t)nslots * bg.nb +
+                          24 * (size_t)nslots * bg.nb +
                           8 * (size_t)nslots * bg.nb + 8 * ssim_np +
                           sizeof(TrialDesc) * (nslots + adesc_n) + 8 * rp +
                           12 * (size_t)bg.nb + 4096;
@@ -199,9 +199,10 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   uint8_t* pbase = (uint8_t*)c->pinned + kPinTune;
   uint32_t* h_hist = (uint32_t*)pbase;
   double* h_sse = (double*)(pbase + 4 * (size_t)kNSym * max_trials);
-  uint32_t* h_un = (uint32_t*)(h_sse + (size_t)nslots * bg.nb);
+  /* per (trial, block) item: two partials (levels above 1, level 1) */
+  uint32_t* h_un = (uint32_t*)(h_sse + 2 * (size_t)nslots * bg.nb);
   double* h_l1 = (double*)(pbase + 4 * (size_t)kNSym * max_trials +
-                           12 * (size_t)nslots * bg.nb);
+                           24 * (size_t)nslots * bg.nb);
   double* h_ssim = h_l1 + (size_t)nslots * bg.nb;
   TrialDesc* h_desc = (TrialDesc*)(h_ssim + ssim_np);
   TrialDesc* h_adesc = h_desc + nslots;
@@ -216,7 +217,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   uint32_t* dpick = (uint32_t*)(dadesc + adesc_n);
   double* dl1 = (double*)c->tune_l1.p;
   double* dsse = (double*)c->tune_stats.p;
-  uint32_t* dun = (uint32_t*)(dsse + (size_t)nslots * bg.nb);
+  uint32_t* dun = (uint32_t*)(dsse + 2 * (size_t)nslots * bg.nb);
   uint32_t* dhist = (uint32_t*)c->tune_hist.p;
   uint32_t* st = (uint32_t*)c->status.p;
   float* pmin = (float*)c->partial.p;
@@ -230,12 +231,10 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     launch_range(d_x, N, pmin, pmax, st, rp, s);
     prof_end(c, s, ev, PK_CHECK, 4.0 * N);
   }
-  QOZ_HIP(hipMemcpyAsync(h_range, pmin, 8 * (size_t)rp,
-                         hipMemcpyDeviceToHost, s));
-  QOZ_HIP(hipMemcpyAsync(h_status, st, 16, hipMemcpyDeviceToHost, s));
+  QOZ_TRY(to_host(c, h_range, pmin, 8 * (size_t)rp, s));
+  QOZ_TRY(to_host(c, h_status, st, 16, s));
   std::memcpy(h_status + 8, origins.data(), 4 * origins.size());
-  QOZ_HIP(hipMemcpyAsync(dorig, h_status + 8, 4 * origins.size(),
-                         hipMemcpyHostToDevice, s));
+  QOZ_TRY(to_device(c, dorig, h_status + 8, 4 * origins.size(), s));
   {
     hipEvent_t ev = prof_begin(c, s, PK_TUNE_GATHER);
     launch_gather_blocks(d_x, g, bg, dorig, xs, s);
@@ -277,13 +276,14 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       for (int j = 0; j < 3; ++j)
         lv.order[j] = j < d ? cands[ci].order[j] + shift : 0;
     }
-  QOZ_HIP(hipMemcpyAsync(dadesc, h_adesc, sizeof(TrialDesc) * Lt * ncand,
-                         hipMemcpyHostToDevice, s));
+  QOZ_TRY(
+      to_device(c, dadesc, h_adesc, sizeof(TrialDesc) * Lt * ncand, s));
   for (uint32_t l = Lt; l >= 1; --l) {
+    const bool in_lds = alg1_in_lds(bg, l);
     {
       hipEvent_t ev = prof_begin(c, s, PK_TUNE_ALG1);
       launch_alg1_level(bg, l, xs, wc, wt, ncand, dadesc + (l - 1) * ncand,
-                        dl1, s);
+                        dl1, in_lds, s);
       prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
     }
     /* level-l targets: points of the 2^(l-1) grid off the 2^l grid */
@@ -293,11 +293,11 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
     }
     const double count = (double)(on_fine - on_coarse) * bg.nb;
-    launch_alg1_pick(dl1, ncand, bg.nb, count, dpick + (l - 1), wt, bsz, wc,
-                     s);
+    launch_alg1_pick(bg, l, xs, dadesc + (l - 1) * ncand, dl1, ncand, count,
+                     dpick + (l - 1), wt, wc, in_lds, s);
   }
   uint32_t* h_pick = h_status + 8 + 3 * (size_t)bg.nb; /* after origins */
-  QOZ_HIP(hipMemcpyAsync(h_pick, dpick, 4 * Lt, hipMemcpyDeviceToHost, s));
+  QOZ_TRY(to_host(c, h_pick, dpick, 4 * Lt, s));
   QOZ_HIP(hipGetLastError());
   QOZ_HIP(hipStreamSynchronize(s));
   for (uint32_t l = Lt; l >= 1; --l) {
@@ -350,12 +350,12 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       for (int j = 0; j < 3; ++j)
         lv.order[j] = j < d ? Is_order[l - 1][j] + shift : 0;
     }
-  QOZ_HIP(hipMemcpyAsync(ddesc, h_desc, sizeof(TrialDesc) * ntrial,
-                         hipMemcpyHostToDevice, s));
+  QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ntrial, s));
   launch_zero_u32(dhist, (uint64_t)kNSym * ntrial, s);
   {
     hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
-    launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun, s);
+    launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun,
+                 target == QOZ_TARGET_SSIM, s);
     prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ntrial);
   }
   if (target == QOZ_TARGET_SSIM) {
@@ -366,18 +366,15 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     hipEvent_t ev = prof_begin(c, s, PK_SSIM);
     launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
     prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
-    QOZ_HIP(hipMemcpyAsync(h_ssim, c->ssim_part.p, 8 * ssim_np,
-                           hipMemcpyDeviceToHost, s));
+    QOZ_TRY(to_host(c, h_ssim, c->ssim_part.p, 8 * ssim_np, s));
   }
   /* used symbols of every trial histogram, sorted on the device */
   QOZ_TRY(ensure(c->hsort, 8 * (size_t)(kSortCap + 1) * ntrial));
   launch_hist_sort(dhist, ntrial, (uint64_t*)c->hsort.p, s);
   uint64_t* h_keys = (uint64_t*)h_hist;
-  QOZ_HIP(hipMemcpyAsync(h_keys, c->hsort.p,
-                         8 * (size_t)(kSortCap + 1) * ntrial,
-                         hipMemcpyDeviceToHost, s));
-  QOZ_HIP(hipMemcpyAsync(h_sse, dsse, 12 * (size_t)nslots * bg.nb,
-                         hipMemcpyDeviceToHost, s));
+  QOZ_TRY(to_host(c, h_keys, c->hsort.p,
+                  8 * (size_t)(kSortCap + 1) * ntrial, s));
+  QOZ_TRY(to_host(c, h_sse, dsse, 24 * (size_t)nslots * bg.nb, s));
   QOZ_HIP(hipGetLastError());
   QOZ_HIP(hipStreamSynchronize(s));
   prof_collect(c);
@@ -401,8 +398,9 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     uint64_t U = 0;
     double sse = 0.0;
     for (uint32_t k = 0; k < bg.nb; ++k) {
-      U += h_un[(size_t)t * bg.nb + k];
-      sse += h_sse[(size_t)t * bg.nb + k];
+      const size_t it = 2 * ((size_t)t * bg.nb + k);
+      U += h_un[it] + h_un[it + 1];
+      sse += h_sse[it] + h_sse[it + 1];
     }
     B[t] = ((double)bits + 32.0 * (double)U) / npts;
     if (target == QOZ_TARGET_PSNR) {
