@@ -76,7 +76,7 @@ qoz_status to_host(qoz_ctx* c, void* h_dst, const void* d_src, size_t bytes,
                    hipStream_t s) {
   void* d = nullptr;
   QOZ_TRY(pinned_dev(c, h_dst, bytes, &d));
-  launch_copy_bytes(d, d_src, bytes, s);
+  launch_copy_host(d, d_src, bytes, true, s);
   QOZ_HIP(hipGetLastError());
   return QOZ_OK;
 }
@@ -85,7 +85,7 @@ qoz_status to_device(qoz_ctx* c, void* d_dst, const void* h_src,
                      size_t bytes, hipStream_t s) {
   void* d = nullptr;
   QOZ_TRY(pinned_dev(c, h_src, bytes, &d));
-  launch_copy_bytes(d_dst, d, bytes, s);
+  launch_copy_host(d_dst, d, bytes, false, s);
   QOZ_HIP(hipGetLastError());
   return QOZ_OK;
 }

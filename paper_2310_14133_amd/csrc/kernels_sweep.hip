@@ -39,32 +39,49 @@ void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
                      n);
 }
 
-/* A plain copy: 16-byte words when both ends are 16-byte aligned, else
- * bytes.  A system-scope fence makes writes to host memory visible before
- * the kernel ends. */
-__global__ void k_copy_bytes(uint8_t* __restrict__ dst,
-                             const uint8_t* __restrict__ src, uint64_t n) {
+/* Copies between device memory and coherent host memory.  The host side
+ * is accessed with system-scope (write-through, uncached) loads or stores,
+ * 4 bytes at a time when both ends and the size allow, else bytewise; the
+ * device side with plain accesses. */
+template <bool TO_HOST, typename T>
+__device__ __forceinline__ void copy_host_units(T* dst, const T* src,
+                                                uint64_t n) {
   const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t done = 0;
-  if ((((uintptr_t)dst | (uintptr_t)src) & 15) == 0) {
-    const uint64_t nq = n / 16;
-    for (uint64_t i = tid; i < nq; i += stride)
-      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
-    done = nq * 16;
+  for (uint64_t i = tid; i < n; i += stride) {
+    if (TO_HOST) {
+      __hip_atomic_store(dst + i, src[i], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+      dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
-  for (uint64_t i = done + tid; i < n; i += stride) dst[i] = src[i];
-  __threadfence_system();
 }
 
-void launch_copy_bytes(void* dst, const void* src, size_t bytes,
-                       hipStream_t s) {
+template <bool TO_HOST>
+__global__ void k_copy_host(uint8_t* dst, const uint8_t* src, uint64_t n) {
+  if ((((uintptr_t)dst | (uintptr_t)src | n) & 3) == 0)
+    copy_host_units<TO_HOST>(reinterpret_cast<uint32_t*>(dst),
+                             reinterpret_cast<const uint32_t*>(src), n / 4);
+  else
+    copy_host_units<TO_HOST>(dst, src, n);
+}
+
+void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
+                      hipStream_t s) {
   if (!bytes) return;
-  uint64_t blocks = (bytes / 16 + 255) / 256;
+  uint64_t blocks = (bytes / 4 + 255) / 256;
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_copy_bytes, dim3((uint32_t)blocks), dim3(256), 0, s,
-                     (uint8_t*)dst, (const uint8_t*)src, (uint64_t)bytes);
+  if (to_host)
+    hipLaunchKernelGGL(k_copy_host<true>, dim3((uint32_t)blocks), dim3(256),
+                       0, s, (uint8_t*)dst, (const uint8_t*)src,
+                       (uint64_t)bytes);
+  else
+    hipLaunchKernelGGL(k_copy_host<false>, dim3((uint32_t)blocks), dim3(256),
+                       0, s, (uint8_t*)dst, (const uint8_t*)src,
+                       (uint64_t)bytes);
 }
 
 /* Anchor grid (Sec. V-B): every point whose coordinates are all multiples

@@ -278,9 +278,9 @@ void launch_unpred_scatter(const Geo& g, const SweepTable& st,
 void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s);
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
-/* bytes from src to dst, either of which may be mapped host memory */
-void launch_copy_bytes(void* dst, const void* src, size_t bytes,
-                       hipStream_t s);
+/* bytes from device memory to coherent host memory (to_host) or back */
+void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
+                      hipStream_t s);
 void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
