@@ -279,15 +279,55 @@ __device__ __forceinline__ void load_span(const float* __restrict__ r,
   }
 }
 
+/* the n (<= 4) bins of a span at pos; one 8-byte access when vec and the
+ * span is full */
+__device__ __forceinline__ void load_bins4(const uint16_t* __restrict__ c,
+                                           uint64_t pos, bool vec,
+                                           uint32_t n, int32_t* b) {
+  if (vec && n == 4) {
+    const uint2 v = *reinterpret_cast<const uint2*>(c + pos);
+    b[0] = (int32_t)(v.x & 0xffffu);
+    b[1] = (int32_t)(v.x >> 16);
+    b[2] = (int32_t)(v.y & 0xffffu);
+    b[3] = (int32_t)(v.y >> 16);
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) b[k] = k < n ? (int32_t)c[pos + k] : 0;
+  }
+}
+
+__device__ __forceinline__ void store_bins4(uint16_t* __restrict__ c,
+                                            uint64_t pos, bool vec,
+                                            uint32_t n, const int32_t* b) {
+  if (vec && n == 4) {
+    *reinterpret_cast<uint2*>(c + pos) =
+        make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16),
+                   (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+  } else {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k)
+      if (k < n) c[pos + k] = (uint16_t)b[k];
+  }
+}
+
 struct RowCtx {
   uint32_t p0, p1, row, pa;
   bool hasA;
 };
 
+/* item it of a workgroup: row it / spans, span it mod spans */
+struct RowItems {
+  uint32_t spans;
+  FastDiv fs, fr;
+  __device__ __forceinline__ RowItems(uint32_t sp, uint32_t items,
+                                      uint32_t rows, uint32_t rcnt1)
+      : spans(sp), fs(sp, items), fr(rcnt1, rows) {}
+};
+
 __device__ __forceinline__ RowCtx row_ctx(const Geo& g, const RowJob& rj,
-                                          uint32_t r) {
+                                          const FastDiv& fr, uint32_t r) {
   RowCtx c;
-  const uint32_t i0 = r / rj.rcnt[1];
+  const uint32_t i0 = fr.div(r);
   const uint32_t i1 = r - i0 * rj.rcnt[1];
   c.p0 = i0 * rj.rstep[0];
   c.p1 = i1 * rj.rstep[1];
@@ -329,11 +369,12 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
   const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
   const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
   const uint32_t items = rj.rows_per_wg * spans;
+  const RowItems ri(spans, items, rows, rj.rcnt[1]);
   bool bad = false;
   for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = it / spans, u = it - rl * spans;
+    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
     if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
     const uint32_t p = u * kSpan;
     float* Er = E + rl * es;
     float xv[kSpan];
@@ -342,16 +383,19 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
       load_span(x + c.row, p, n2, xv);
       predict_span_A(g, rj, W, c, p, pred);
       const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
+      const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
+      int32_t bins[kSpan / 2];
 #pragma unroll
       for (uint32_t k = 0; k < kSpan / 2; ++k) {
-        if (p + 2 * k >= n2) break;
+        bins[k] = 0;
+        if (k >= nA) continue;
         float e;
-        const int32_t code =
+        bins[k] =
             quantize_bin(xv[2 * k], pred[k], rj.A.inv, rj.A.twoeb, rj.A.eb, &e);
-        codes[pos + k] = (uint16_t)code;
         bad |= !isfinite(xv[2 * k]);
         Er[p / 2 + k + 1] = e;
       }
+      store_bins4(codes, pos, rj.vecA, nA < 4 ? nA : 4u, bins);
     } else {
       float wv[kSpan];
       load_span(W + c.row, p, n2, wv);
@@ -362,31 +406,34 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
   }
   __syncthreads();
   for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = it / spans, u = it - rl * spans;
+    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
     if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
     const uint32_t p = u * kSpan;
     const float* Er = E + rl * es;
     float xv[kSpan], out[kSpan];
     load_span(x + c.row, p, n2, xv);
     const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
+    const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
+    int32_t bins[kSpan / 2];
 #pragma unroll
     for (uint32_t k = 0; k < kSpan / 2; ++k) {
       const uint32_t t = p / 2 + k, q = 2 * t + 1;
       out[2 * k] = Er[t + 1];
       out[2 * k + 1] = 0.0f;
+      bins[k] = 0;
       if (q >= n2) continue;
       const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
       const float pred =
           interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
                      hc ? Er[t + 2] : 0.0f, hd ? Er[t + 3] : 0.0f, ha, hc, hd);
       float rec;
-      const int32_t code =
+      bins[k] =
           quantize_bin(xv[2 * k + 1], pred, rj.B.inv, rj.B.twoeb, rj.B.eb, &rec);
-      codes[pos + k] = (uint16_t)code;
       bad |= !isfinite(xv[2 * k + 1]);
       out[2 * k + 1] = rec;
     }
+    store_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
     if (WRITE_W) {
       float* wr = W + c.row;
       if (p + kSpan <= n2) {
@@ -409,20 +456,24 @@ __global__ __launch_bounds__(kRowThreads) void k_row_decomp(
   const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
   const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
   const uint32_t items = rj.rows_per_wg * spans;
+  const RowItems ri(spans, items, rows, rj.rcnt[1]);
   for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = it / spans, u = it - rl * spans;
+    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
     if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
     const uint32_t p = u * kSpan;
     float* Er = E + rl * es;
     if (c.hasA) {
+      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
+      const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
+      int32_t bins[kSpan / 2];
+      load_bins4(codes, pos, rj.vecA, nA < 4 ? nA : 4u, bins);
       float pred[kSpan / 2];
       predict_span_A(g, rj, W, c, p, pred);
-      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
 #pragma unroll
       for (uint32_t k = 0; k < kSpan / 2; ++k) {
-        if (p + 2 * k >= n2) break;
-        const int32_t code = codes[pos + k];
+        if (k >= nA) break;
+        const int32_t code = bins[k];
         Er[p / 2 + k + 1] = code ? dequantize_bin(pred[k], code, rj.A.twoeb)
                                  : W[c.row + p + 2 * k];
       }
@@ -436,20 +487,23 @@ __global__ __launch_bounds__(kRowThreads) void k_row_decomp(
   }
   __syncthreads();
   for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = it / spans, u = it - rl * spans;
+    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
     if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, r0 + rl);
+    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
     const uint32_t p = u * kSpan;
     const float* Er = E + rl * es;
     float out[kSpan];
     const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
+    const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
+    int32_t bins[kSpan / 2];
+    load_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
 #pragma unroll
     for (uint32_t k = 0; k < kSpan / 2; ++k) {
       const uint32_t t = p / 2 + k, q = 2 * t + 1;
       out[2 * k] = Er[t + 1];
       out[2 * k + 1] = 0.0f;
       if (q >= n2) continue;
-      const int32_t code = codes[pos + k];
+      const int32_t code = bins[k];
       if (code) {
         const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
         const float pred = interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],

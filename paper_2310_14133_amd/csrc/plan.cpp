@@ -173,6 +173,8 @@ bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj) {
     rj->rstep[m] = rj->B.step[m];
     rj->rcnt[m] = rj->B.cnt[m];
   }
+  rj->vecA = jb > 0 && rj->A.code_off % 4 == 0 && rj->A.cnt[2] % 4 == 0;
+  rj->vecB = rj->B.code_off % 4 == 0 && rj->B.cnt[2] % 4 == 0;
   return true;
 }
 

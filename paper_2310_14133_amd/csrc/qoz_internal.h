@@ -61,6 +61,8 @@ struct RowJob {
   int32_t a;
   uint32_t rstep[2], rcnt[2];
   uint32_t rows_per_wg; /* set by the launcher */
+  /* the sweep's bins of a row start on a multiple of 4 (8-byte access) */
+  uint32_t vecA, vecB;
   Sweep A, B;
 };
 
