@@ -56,6 +56,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   QOZ_TRY(ensure(c->chunk_bits, 4 * nch));
   QOZ_TRY(ensure(c->chunk_zeros, 4 * nch));
   QOZ_TRY(ensure(c->coff, 8 * (nch + 1)));
+  QOZ_TRY(ensure(c->scan, chunk_scan_scratch(nch)));
   QOZ_TRY(ensure(c->upre, 4 * (nch + 1)));
   QOZ_TRY(ensure(c->enc_table, 8 * kNSym));
   float* W = (float*)c->W.p;
@@ -166,7 +167,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
         launch_chunk_scan((uint32_t*)c->chunk_bits.p,
                           (uint32_t*)c->chunk_zeros.p, nch,
                           (uint64_t*)c->coff.p, (uint32_t*)c->upre.p, totals,
-                          s)));
+                          (uint64_t*)c->scan.p, s)));
   QOZ_TRY(to_host(c, pin(c, kPinStatus + 64), totals, 24, s));
   QOZ_TRY(sync_checked(s));
   const uint64_t n_words = ((uint64_t*)pin(c, kPinStatus + 64))[0];

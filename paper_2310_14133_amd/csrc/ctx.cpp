@@ -177,7 +177,7 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->partial,    &c->tune_x,     &c->tune_wc,
                     &c->tune_wt,    &c->tune_desc,  &c->tune_hist,
                     &c->tune_stats, &c->tune_l1,    &c->ssim_part,
-                    &c->upos,       &c->hsort};
+                    &c->upos,       &c->hsort,      &c->scan};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -169,11 +169,14 @@ void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      chunk_bits, chunk_zeros);
 }
 
-/* Exclusive scans over chunks in one workgroup: tiles of 8192 chunk counts
- * are staged in LDS with coalesced loads, each lane scans a contiguous run
- * of 8, the lane sums are scanned with wave shuffles, and a running total
- * carries across tiles.  totals[0] = words, totals[1] = unpredictables. */
-constexpr uint32_t kScanThreads = 1024;
+/* Exclusive scans over chunks (words = ceil(bits / 32), unpredictable
+ * counts) in two launches: k_scan_tiles sums tiles of 2048 chunks (and
+ * finds the largest chunk in words); k_scan_apply adds the sums of the
+ * tiles before its own and scans its tile (8 consecutive chunks per lane,
+ * lane sums scanned with wave shuffles).  The last tile also writes
+ * coff[n], upre[n] and totals[0..2] = words, unpredictables, largest chunk
+ * in words. */
+constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanPer = 8;
 constexpr uint32_t kScanTile = kScanThreads * kScanPer;
 
@@ -187,69 +190,108 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
   return v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(
+template <typename T>
+__device__ __forceinline__ T scan_block_sum(T v, T* ws) {
+  for (uint32_t o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63u) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T t = 0;
+  for (uint32_t w = 0; w < kScanThreads / 64; ++w) t += ws[w];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(
     const uint32_t* __restrict__ bits, const uint32_t* __restrict__ zeros,
-    uint64_t n, uint64_t* coff, uint32_t* upre, uint64_t* totals) {
-  __shared__ uint32_t tw[kScanTile], tz[kScanTile];
-  __shared__ uint64_t ww[kScanThreads / 64], wz[kScanThreads / 64];
-  const uint32_t t = threadIdx.x, wave = t >> 6, lane = t & 63u;
-  uint64_t run_w = 0, run_z = 0;
-  uint32_t wmax = 0;
-  for (uint64_t base = 0; base < n; base += kScanTile) {
-    const uint32_t cnt = (uint32_t)(n - base < kScanTile ? n - base : kScanTile);
-    for (uint32_t i = t; i < kScanTile; i += kScanThreads) {
-      tw[i] = i < cnt ? (bits[base + i] + 31) / 32 : 0u;
-      tz[i] = i < cnt ? zeros[base + i] : 0u;
-    }
-    __syncthreads();
-    uint64_t sw = 0, sz = 0;
+    uint64_t n, uint64_t* __restrict__ tile_w, uint64_t* __restrict__ tile_z,
+    uint64_t* __restrict__ tile_max) {
+  __shared__ uint64_t ws[kScanThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint64_t sw = 0, sz = 0, mx = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < kScanPer; ++k) {
-      sw += tw[t * kScanPer + k];
-      sz += tz[t * kScanPer + k];
-      wmax = wmax > tw[t * kScanPer + k] ? wmax : tw[t * kScanPer + k];
+  for (uint32_t k = 0; k < kScanPer; ++k) {
+    const uint64_t i = base + threadIdx.x + k * kScanThreads;
+    if (i < n) {
+      const uint64_t w = (bits[i] + 31) / 32;
+      sw += w;
+      sz += zeros[i];
+      mx = mx > w ? mx : w;
     }
-    const uint64_t iw = wave_incl_scan_u64(sw), iz = wave_incl_scan_u64(sz);
-    if (lane == 63) {
-      ww[wave] = iw;
-      wz[wave] = iz;
-    }
-    __syncthreads();
-    uint64_t ow = run_w + iw - sw, oz = run_z + iz - sz;
-    uint64_t tot_w = 0, tot_z = 0;
-    for (uint32_t w = 0; w < kScanThreads / 64; ++w) {
-      ow += w < wave ? ww[w] : 0ull;
-      oz += w < wave ? wz[w] : 0ull;
-      tot_w += ww[w];
-      tot_z += wz[w];
-    }
-#pragma unroll
-    for (uint32_t k = 0; k < kScanPer; ++k) {
-      const uint32_t i = t * kScanPer + k;
-      if (i < cnt) {
-        coff[base + i] = ow;
-        upre[base + i] = (uint32_t)oz;
-      }
-      ow += tw[i];
-      oz += tz[i];
-    }
-    run_w += tot_w;
-    run_z += tot_z;
-    __syncthreads();
   }
   for (uint32_t o = 32; o > 0; o >>= 1) {
-    const uint32_t v = __shfl_xor(wmax, o, 64);
-    wmax = wmax > v ? wmax : v;
+    const uint64_t t = __shfl_xor(mx, o, 64);
+    mx = mx > t ? mx : t;
   }
-  if (lane == 0) ww[wave] = wmax;
-  __syncthreads();
-  if (t == 0) {
+  __shared__ uint64_t wm[kScanThreads / 64];
+  if ((threadIdx.x & 63u) == 0) wm[threadIdx.x >> 6] = mx;
+  sw = scan_block_sum(sw, ws);
+  sz = scan_block_sum(sz, ws);
+  if (threadIdx.x == 0) {
     uint64_t m = 0;
-    for (uint32_t w = 0; w < kScanThreads / 64; ++w) m = m > ww[w] ? m : ww[w];
-    coff[n] = run_w;
-    upre[n] = (uint32_t)run_z;
-    totals[0] = run_w;
-    totals[1] = run_z;
+    for (uint32_t w = 0; w < kScanThreads / 64; ++w) m = m > wm[w] ? m : wm[w];
+    tile_w[blockIdx.x] = sw;
+    tile_z[blockIdx.x] = sz;
+    tile_max[blockIdx.x] = m;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(
+    const uint32_t* __restrict__ bits, const uint32_t* __restrict__ zeros,
+    uint64_t n, const uint64_t* __restrict__ tile_w,
+    const uint64_t* __restrict__ tile_z, const uint64_t* __restrict__ tile_max,
+    uint64_t* coff, uint32_t* upre, uint64_t* totals) {
+  __shared__ uint64_t ws[kScanThreads / 64], wz[kScanThreads / 64];
+  const uint32_t b = blockIdx.x, lane = threadIdx.x & 63u,
+                 wave = threadIdx.x >> 6;
+  /* sums of the tiles before this one */
+  uint64_t ow = 0, oz = 0;
+  for (uint32_t t = threadIdx.x; t < b; t += kScanThreads) {
+    ow += tile_w[t];
+    oz += tile_z[t];
+  }
+  ow = scan_block_sum(ow, ws);
+  oz = scan_block_sum(oz, ws);
+  /* this lane's 8 consecutive chunks */
+  const uint64_t i0 = (uint64_t)b * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+  uint32_t w[kScanPer], z[kScanPer];
+  uint64_t sw = 0, sz = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kScanPer; ++k) {
+    const bool in = i0 + k < n;
+    w[k] = in ? (bits[i0 + k] + 31) / 32 : 0u;
+    z[k] = in ? zeros[i0 + k] : 0u;
+    sw += w[k];
+    sz += z[k];
+  }
+  const uint64_t iw = wave_incl_scan_u64(sw), iz = wave_incl_scan_u64(sz);
+  if (lane == 63) {
+    ws[wave] = iw;
+    wz[wave] = iz;
+  }
+  __syncthreads();
+  uint64_t pw = ow + iw - sw, pz = oz + iz - sz, tw = 0, tz = 0;
+  for (uint32_t v = 0; v < kScanThreads / 64; ++v) {
+    pw += v < wave ? ws[v] : 0ull;
+    pz += v < wave ? wz[v] : 0ull;
+    tw += ws[v];
+    tz += wz[v];
+  }
+#pragma unroll
+  for (uint32_t k = 0; k < kScanPer; ++k) {
+    if (i0 + k < n) {
+      coff[i0 + k] = pw;
+      upre[i0 + k] = (uint32_t)pz;
+    }
+    pw += w[k];
+    pz += z[k];
+  }
+  if (b + 1 == gridDim.x && threadIdx.x == 0) {
+    uint64_t m = 0;
+    for (uint32_t t = 0; t < gridDim.x; ++t) m = m > tile_max[t] ? m : tile_max[t];
+    coff[n] = ow + tw;
+    upre[n] = (uint32_t)(oz + tz);
+    totals[0] = ow + tw;
+    totals[1] = oz + tz;
     totals[2] = m;
   }
 }
@@ -264,19 +306,54 @@ constexpr uint32_t kSortThreads = 1024;
 
 __global__ __launch_bounds__(kSortThreads) void k_hist_sort(
     const uint32_t* __restrict__ hist, uint64_t* __restrict__ out) {
+  static_assert(kNSym % (4 * kSortThreads) == 0, "bins per lane");
   __shared__ uint64_t keys[kSortCap];
   __shared__ uint32_t n_used;
   const uint32_t* hh = hist + (uint64_t)blockIdx.x * kNSym;
   uint64_t* o = out + (uint64_t)blockIdx.x * (kSortCap + 1);
-  if (threadIdx.x == 0) n_used = 0;
-  __syncthreads();
-  for (uint32_t i = threadIdx.x; i < kNSym; i += kSortThreads) {
-    const uint32_t v = hh[i];
-    if (v) {
-      const uint32_t k = atomicAdd(&n_used, 1u);
-      if (k < kSortCap) keys[k] = ((uint64_t)v << 16) | i;
+  __shared__ uint32_t wcount[kSortThreads / 64];
+  /* lane t holds bins [64 t, 64 t + 64): sixteen 16-byte loads in flight,
+   * then the used ones are compacted in bin order by a block scan of the
+   * per-lane counts */
+  constexpr uint32_t kPer = kNSym / kSortThreads; /* 64 */
+  uint32_t v[kPer];
+  {
+    const uint4* h4 =
+        reinterpret_cast<const uint4*>(hh + (uint64_t)threadIdx.x * kPer);
+#pragma unroll
+    for (uint32_t q = 0; q < kPer / 4; ++q) {
+      const uint4 w = h4[q];
+      v[4 * q] = w.x;
+      v[4 * q + 1] = w.y;
+      v[4 * q + 2] = w.z;
+      v[4 * q + 3] = w.w;
     }
   }
+  uint32_t cnt = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) cnt += v[q] ? 1u : 0u;
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint32_t incl = cnt;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    incl += lane >= o ? t : 0u;
+  }
+  if (lane == 63) wcount[wave] = incl;
+  __syncthreads();
+  uint32_t k = incl - cnt, total = 0;
+  for (uint32_t w = 0; w < kSortThreads / 64; ++w) {
+    k += w < wave ? wcount[w] : 0u;
+    total += wcount[w];
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q)
+    if (v[q]) {
+      if (k < kSortCap)
+        keys[k] = ((uint64_t)v[q] << 16) | (threadIdx.x * kPer + q);
+      ++k;
+    }
+  if (threadIdx.x == 0) n_used = total;
   __syncthreads();
   const uint32_t n = n_used;
   const uint32_t m = n < kSortCap ? n : kSortCap;
@@ -311,12 +388,25 @@ void launch_hist_sort(const uint32_t* hist, uint32_t n_hist, uint64_t* out,
                      hist, out);
 }
 
+uint64_t chunk_scan_scratch(uint64_t n_chunks) {
+  return 24 * ((n_chunks + kScanTile - 1) / kScanTile + 1);
+}
+
 void launch_chunk_scan(const uint32_t* chunk_bits,
                        const uint32_t* chunk_zeros, uint64_t n_chunks,
                        uint64_t* coff, uint32_t* upre, uint64_t* totals,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, s,
-                     chunk_bits, chunk_zeros, n_chunks, coff, upre, totals);
+                       uint64_t* scratch, hipStream_t s) {
+  /* at least one tile, so that the totals are written for no chunks too */
+  const uint32_t tiles =
+      n_chunks ? (uint32_t)((n_chunks + kScanTile - 1) / kScanTile) : 1u;
+  uint64_t* tw = scratch;
+  uint64_t* tz = tw + tiles;
+  uint64_t* tm = tz + tiles;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, s,
+                     chunk_bits, chunk_zeros, n_chunks, tw, tz, tm);
+  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanThreads), 0, s,
+                     chunk_bits, chunk_zeros, n_chunks, tw, tz, tm, coff,
+                     upre, totals);
 }
 
 /* words of a chunk: at most 56 bits per bin (the encoder table's limit) */

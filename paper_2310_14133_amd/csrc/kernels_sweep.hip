@@ -370,6 +370,10 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
   const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
   const uint32_t items = rj.rows_per_wg * spans;
   const RowItems ri(spans, items, rows, rj.rcnt[1]);
+  /* one item per lane: the span's x values stay in registers between the
+   * phases */
+  const bool one = items <= kRowThreads;
+  float xv[kSpan];
   bool bad = false;
   for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
     const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
@@ -377,10 +381,9 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
     const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
     const uint32_t p = u * kSpan;
     float* Er = E + rl * es;
-    float xv[kSpan];
+    if (c.hasA || one) load_span(x + c.row, p, n2, xv);
     if (c.hasA) {
       float pred[kSpan / 2];
-      load_span(x + c.row, p, n2, xv);
       predict_span_A(g, rj, W, c, p, pred);
       const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
       const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
@@ -411,8 +414,8 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
     const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
     const uint32_t p = u * kSpan;
     const float* Er = E + rl * es;
-    float xv[kSpan], out[kSpan];
-    load_span(x + c.row, p, n2, xv);
+    float out[kSpan];
+    if (!one) load_span(x + c.row, p, n2, xv);
     const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
     const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
     int32_t bins[kSpan / 2];

@@ -166,7 +166,7 @@ struct qoz_ctx {
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
-      hsort;
+      hsort, scan;
   /* pinned host staging */
   void* pinned = nullptr;
   void* pinned_dev = nullptr; /* its device address */
@@ -287,10 +287,12 @@ void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
                      uint32_t* chunk_zeros, hipStream_t s);
+/* scratch bytes launch_chunk_scan needs */
+uint64_t chunk_scan_scratch(uint64_t n_chunks);
 void launch_chunk_scan(const uint32_t* chunk_bits,
                        const uint32_t* chunk_zeros, uint64_t n_chunks,
                        uint64_t* coff, uint32_t* upre, uint64_t* totals,
-                       hipStream_t s);
+                       uint64_t* scratch, hipStream_t s);
 void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
