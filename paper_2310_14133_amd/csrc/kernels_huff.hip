@@ -31,16 +31,26 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(
   const uint64_t b0 = (uint64_t)blockIdx.x * kHistPerBlock;
   const uint64_t b1 = b0 + kHistPerBlock < n ? b0 + kHistPerBlock : n;
   uint32_t center = 0;
-  /* eight 16-bit bins per 16-byte load */
+  /* eight 16-bit bins per 16-byte load, four loads in flight per lane */
+  constexpr uint32_t kU = 4;
   const uint64_t nvec = (b1 - b0) / 8;
   const uint4* v4 = reinterpret_cast<const uint4*>(codes + b0);
-  for (uint64_t i = threadIdx.x; i < nvec; i += blockDim.x) {
-    const uint4 q = v4[i];
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+  for (uint64_t i0 = threadIdx.x; i0 < nvec; i0 += kU * kHistThreads) {
+    uint4 q[kU];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      hist_add(lh, hist, (int32_t)(w[k] & 0xffffu), center);
-      hist_add(lh, hist, (int32_t)(w[k] >> 16), center);
+    for (uint32_t u = 0; u < kU; ++u) {
+      const uint64_t i = i0 + u * kHistThreads;
+      q[u] = i < nvec ? v4[i] : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) {
+      if (i0 + u * kHistThreads >= nvec) break;
+      const uint32_t w[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        hist_add(lh, hist, (int32_t)(w[k] & 0xffffu), center);
+        hist_add(lh, hist, (int32_t)(w[k] >> 16), center);
+      }
     }
   }
   for (uint64_t i = b0 + nvec * 8 + threadIdx.x; i < b1; i += blockDim.x)

@@ -33,25 +33,28 @@ struct __attribute__((aligned(4))) Q4 {
   float a, b, c, d;
 };
 
-/* Grid-stride over 4-float groups with four groups in flight per lane; the
- * last n mod 4 values go to the first lanes. */
+/* Each workgroup reads a contiguous range of 4-float groups, four 16-byte
+ * loads in flight per lane (contiguous ranges per workgroup stream better
+ * than a grid-wide stride); the last n mod 4 values go to the first lanes
+ * of the grid. */
 template <class F>
 __device__ __forceinline__ void for_each4(const float* __restrict__ x,
                                           uint64_t n, F&& f) {
+  constexpr uint32_t kU = 4;
   const uint64_t n4 = n / 4;
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t per = (n4 + gridDim.x - 1) / gridDim.x;
+  const uint64_t b0 = (uint64_t)blockIdx.x * per;
+  const uint64_t b1 = b0 + per < n4 ? b0 + per : n4;
   const Q4* x4 = reinterpret_cast<const Q4*>(x);
-  uint64_t i = gid;
-  for (; i + 3 * stride < n4; i += 4 * stride) {
-    const Q4 v0 = x4[i], v1 = x4[i + stride], v2 = x4[i + 2 * stride],
-             v3 = x4[i + 3 * stride];
-    f(i, v0);
-    f(i + stride, v1);
-    f(i + 2 * stride, v2);
-    f(i + 3 * stride, v3);
+  uint64_t i = b0 + threadIdx.x;
+  for (; i + (kU - 1) * kRedThreads < b1; i += kU * kRedThreads) {
+    Q4 v[kU];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) v[u] = x4[i + u * kRedThreads];
+#pragma unroll
+    for (uint32_t u = 0; u < kU; ++u) f(i + u * kRedThreads, v[u]);
   }
-  for (; i < n4; i += stride) f(i, x4[i]);
+  for (; i < b1; i += kRedThreads) f(i, x4[i]);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_range(
