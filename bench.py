@@ -14,8 +14,11 @@ library's stream (per-kind table `kernels_warmup`, per step); the kind with
 the largest summed time there is the roofline kernel, and in the timed
 region only its launches carry events, so `roofline.achieved` is its
 algorithmic bytes over its average launch duration measured live while the
-rest of the step runs uninstrumented.  cpu_baseline times the
-single-threaded CPU oracle on the same field.
+rest of the step runs uninstrumented.  `roofline.cold_copy_TBps` is the
+rate of a plain device copy of field-sized buffers that miss the last-level
+cache (read + write bytes): the practical streaming ceiling next to the
+8 TB/s peak.  cpu_baseline times the single-threaded CPU oracle on the same
+field.
 """
 import argparse
 import gc
@@ -30,6 +33,32 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_KINDS_EXCLUDED = ()
+
+
+def cold_copy_tbps(numel, nbuf=6, reps=12):
+    """Device-to-device copy rate (read + write bytes per second) of
+    field-sized buffers, rotating over nbuf of them so that no copy finds
+    its data in the 256 MB last-level cache: the practical HBM streaming
+    ceiling the kernels are compared with."""
+    import torch
+    bufs = [torch.empty(numel, dtype=torch.float32, device="cuda")
+            for _ in range(nbuf)]
+    for i, b in enumerate(bufs):
+        b.fill_(float(i))
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+        enable_timing=True)
+    ms = 0.0
+    for k in range(reps):
+        src, dst = bufs[k % nbuf], bufs[(k + nbuf // 2) % nbuf]
+        a.record()
+        dst.copy_(src)
+        z.record()
+        z.synchronize()
+        if k >= nbuf:  # the first pass touches every buffer once
+            ms += a.elapsed_time(z)
+    del bufs
+    torch.cuda.empty_cache()
+    return 2 * numel * 4 / (ms / (reps - nbuf) / 1e3) / 1e12
 
 
 def main():
@@ -56,7 +85,7 @@ def main():
                          "(the reference for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU; there is no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -119,6 +148,8 @@ def main():
             record["comp"].append(ev[1].elapsed_time(ev[2]))
             record["decomp"].append(ev[2].elapsed_time(ev[3]))
         return p, nb
+
+    hbm_copy = cold_copy_tbps(x.numel())
 
     # warmup with every kernel kind timed: the per-kind table and the
     # dominant kind (one extra untimed step when there is no warmup)
@@ -222,6 +253,7 @@ def main():
             "traffic": traffic,
             "avg_launch_ms": round(tot_ms / launches, 5),
             "algo_bytes_per_launch": algo_bytes / launches,
+            "cold_copy_TBps": round(hbm_copy, 3),
         },
         "kernels_warmup": {k: {"launches": v[0] / nwarm,
                                "ms": round(v[1] / nwarm, 4),
