@@ -27,6 +27,20 @@ namespace qoz {
 
 constexpr uint32_t kTuneThreads = 256;
 
+/* (candidate or trial, block) of a workgroup of a (gridDim.x, gridDim.y)
+ * grid, ordered so that each of the 8 XCDs (dispatched round-robin, each
+ * with its own L2) takes consecutive items: the candidates of one block
+ * then read its samples from the same L2. */
+struct Item {
+  uint32_t c, blk;
+};
+__device__ __forceinline__ Item xcd_item() {
+  const uint32_t total = gridDim.x * gridDim.y;
+  uint32_t id = blockIdx.x + gridDim.x * blockIdx.y;
+  if (total % 8 == 0) id = (id % 8) * (total / 8) + id / 8;
+  return Item{id % gridDim.x, id / gridDim.x};
+}
+
 __device__ __forceinline__ void block_subgrid(const Geo& g,
                                               const uint32_t* order,
                                               uint32_t d, uint32_t j,
@@ -291,7 +305,8 @@ __global__ __launch_bounds__(NT) void k_alg1_lds(
     const TrialDesc* __restrict__ desc, double* l1_part) {
   extern __shared__ float Ws[];
   __shared__ double red[NT / 64];
-  const uint32_t c = blockIdx.x, blk = blockIdx.y;
+  const Item item = xcd_item();
+  const uint32_t c = item.c, blk = item.blk;
   const uint32_t h = 1u << (l - 1);
   const Geo& g = bg.g;
   const Geo cg = compact_geo(g, h);
@@ -557,7 +572,8 @@ __global__ __launch_bounds__(kHiThreads) void k_trial_hi(
   __shared__ uint32_t lh[kHistWin];
   __shared__ double red[kHiThreads / 64];
   __shared__ uint32_t ured[kHiThreads / 64];
-  const uint32_t tr = blockIdx.x, blk = blockIdx.y;
+  const Item xi = xcd_item();
+  const uint32_t tr = xi.c, blk = xi.blk;
   const uint64_t item = (uint64_t)tr * bg.nb + blk;
   const Geo& g = bg.g;
   const Geo cg = compact_geo(g, 2);
@@ -617,7 +633,8 @@ __global__ __launch_bounds__(kLdsThreads) void k_trial_l1(
   __shared__ uint32_t lh[kHistWin];
   __shared__ double red[kLdsThreads / 64];
   __shared__ uint32_t ured[kLdsThreads / 64];
-  const uint32_t tr = blockIdx.x, blk = blockIdx.y;
+  const Item xi = xcd_item();
+  const uint32_t tr = xi.c, blk = xi.blk;
   const uint64_t item = (uint64_t)tr * bg.nb + blk;
   const Geo& g = bg.g;
   const float* X = xs + (uint64_t)blk * bg.size;
