@@ -32,7 +32,7 @@ enum { QREF_TARGET_CR = 0, QREF_TARGET_PSNR = 1, QREF_TARGET_SSIM = 2 };
 
 #define QREF_MAX_LEVELS 16
 #define QREF_RADIUS 32768
-#define QREF_CHUNK 4096
+#define QREF_CHUNK 4096 /* level-1 chunk; coarser levels halve it */
 #define QREF_SEG 512 /* bins per segment: a chunk holds 8 */
 #define QREF_MAX_CAND 12
 #define QREF_NPAIRS 20

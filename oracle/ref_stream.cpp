@@ -2,13 +2,15 @@
  * Oracle: the compressed stream Z = C(X) and X' = D(Z) (Sec. III).
  * Test infrastructure only.
  *
- * Reading (the paper fixes no container): a 184-byte little-endian header,
+ * Reading (the paper fixes no container): a 200-byte little-endian header,
  * then 8-byte-aligned sections: anchors f32[A]; codebook symbols u16[U_s]
  * (ascending) and lengths u8[U_s]; chunk word offsets u64[C+1]; number of
  * unpredictable values before each chunk u32[C+1]; segment bit lengths
  * u16[7 C]; unpredictable values f32[U]; Huffman payload u32[W], each chunk
- * of 4096 bins starting on a word boundary and packed most-significant bit
- * first.  A chunk is cut into eight interleaved segments: segment j holds
+ * starting on a word boundary and packed most-significant bit first.
+ * Level l's bins form chunks of max(4096 >> (l - 1), 1024) bins (level
+ * boundaries rounded up to 64 bins, a level's last chunk possibly
+ * shorter).  A chunk is cut into eight interleaved segments: segment j holds
  * the chunk's bins j, j + 8, j + 16, ... and the payload stores segment 0,
  * then segment 1, and so on; the stream keeps the payload bits of segments
  * 0..6 (0 for an empty segment), so each segment can be decoded on its own.
@@ -25,11 +27,49 @@ using namespace qref;
 
 namespace {
 
-const size_t kHeader = 184;
+const size_t kHeader = 200;
 
 struct Counts {
   uint64_t n_anchor, n_codes, n_unpred, n_used, n_chunks, n_words;
 };
+
+/* Chunking of the bin stream by level: level l (levels L..1 in stream
+ * order) is cut into chunks of max(4096 >> (l - 1), 1024) bins (4096 on
+ * level 1, 2048 on level 2, 1024 above: coarser levels' bins carry more
+ * long codes); level boundaries are rounded up to a multiple of 64 bins (at
+ * most all bins), and the last chunk of a level may be shorter. */
+struct Regions {
+  int n;                                 /* one per level, level L first */
+  uint64_t start[QREF_MAX_LEVELS + 1];   /* first bin; start[n] = bins */
+  uint64_t size[QREF_MAX_LEVELS];        /* chunk size */
+  uint64_t first[QREF_MAX_LEVELS + 1];   /* first chunk; first[n] = all */
+};
+
+Regions regions_of(const Grid& g, int L, uint64_t n_codes) {
+  Regions R;
+  R.n = L;
+  R.start[0] = 0;
+  R.first[0] = 0;
+  uint64_t t = 0;
+  for (int r = 0; r < L; ++r) {
+    const int l = L - r;
+    t += (uint64_t)(count_anchors(g, (int64_t)1 << (l - 1)) -
+                    count_anchors(g, (int64_t)1 << l));
+    const uint64_t end = r + 1 == L ? n_codes : (t + 63) / 64 * 64;
+    R.start[r + 1] = std::min<uint64_t>(end, n_codes);
+    R.size[r] = std::max<uint64_t>((uint64_t)QREF_CHUNK >> (l - 1), 1024);
+    const uint64_t bins = R.start[r + 1] - R.start[r];
+    R.first[r + 1] = R.first[r] + (bins + R.size[r] - 1) / R.size[r];
+  }
+  return R;
+}
+
+void chunk_range(const Regions& R, uint64_t ch, uint64_t* lo, uint64_t* hi) {
+  int r = 0;
+  while (r + 1 < R.n && ch >= R.first[r + 1]) ++r;
+  *lo = R.start[r] + (ch - R.first[r]) * R.size[r];
+  *hi = std::min<uint64_t>(*lo + R.size[r], R.start[r + 1]);
+}
 
 struct Layout {
   size_t anchors, syms, lens, coff, upre, segs, unpred, payload, total;
@@ -88,7 +128,7 @@ extern "C" int qref_compress_bound(qref_shape shape, uint32_t anchor_stride,
   Grid g;
   if (!bytes || !shape_to_grid(shape, &g)) return QREF_EINVAL;
   uint64_t N = (uint64_t)g.N;
-  uint64_t cmax = (N + QREF_CHUNK - 1) / QREF_CHUNK;
+  uint64_t cmax = (N + 1023) / 1024 + QREF_MAX_LEVELS;
   uint64_t wmax = (N + 1) / 2 + cmax;
   size_t b = kHeader + 4 * N + 8 + al8(2 * 65536) + al8(65536) +
              8 * (cmax + 1) + al8(4 * (cmax + 1)) +
@@ -141,7 +181,8 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   c.n_unpred = n_unpred;
   c.n_used = 0;
   for (uint32_t s = 0; s < nsym; ++s) c.n_used += len[s] ? 1 : 0;
-  c.n_chunks = (n_codes + QREF_CHUNK - 1) / QREF_CHUNK;
+  const Regions R = regions_of(g, L, n_codes);
+  c.n_chunks = R.first[R.n];
 
   /* chunked MSB-first packing */
   std::vector<uint64_t> coff(c.n_chunks + 1);
@@ -152,8 +193,8 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   for (uint64_t ch = 0; ch < c.n_chunks; ++ch) {
     coff[ch] = words.size();
     upre[ch] = (uint32_t)zeros;
-    uint64_t lo = ch * QREF_CHUNK;
-    uint64_t hi = std::min<uint64_t>(lo + QREF_CHUNK, n_codes);
+    uint64_t lo, hi;
+    chunk_range(R, ch, &lo, &hi);
     uint64_t bitpos = 0;
     size_t base = words.size();
     for (uint64_t i = lo; i < hi; ++i)
@@ -186,7 +227,7 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   uint8_t* o = (uint8_t*)out;
   std::memset(o, 0, lay.total);
   std::memcpy(o, "QOZ1", 4);
-  put<uint16_t>(o, 4, 3);
+  put<uint16_t>(o, 4, 4);
   put<uint8_t>(o, 6, (uint8_t)g.d);
   put<uint8_t>(o, 7, (uint8_t)kSegLog2);
   for (int i = 0; i < 3; ++i)
@@ -210,6 +251,8 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   put<uint64_t>(o, 160, c.n_used);
   put<uint64_t>(o, 168, c.n_chunks);
   put<uint64_t>(o, 176, c.n_words);
+  put<uint64_t>(o, 184, R.start[R.n - 1]); /* bins before level 1 */
+  put<uint32_t>(o, 192, 1024);            /* smallest chunk size */
   std::memcpy(o + lay.anchors, anchors.data(), 4 * n_anchor);
   uint64_t k = 0;
   for (uint32_t s = 0; s < nsym; ++s)
@@ -238,13 +281,14 @@ struct Parsed {
   int L;
   double e;
   Counts c;
+  Regions R;
   Layout lay;
 };
 
 int parse(const uint8_t* in, size_t n, Parsed* P) {
   if (!in || n < kHeader) return QREF_EFORMAT;
   if (std::memcmp(in, "QOZ1", 4) != 0) return QREF_EFORMAT;
-  if (get<uint16_t>(in, 4) != 3) return QREF_EFORMAT;
+  if (get<uint16_t>(in, 4) != 4) return QREF_EFORMAT;
   if (get<uint8_t>(in, 7) != kSegLog2) return QREF_EFORMAT;
   qref_shape sh;
   std::memset(&sh, 0, sizeof(sh));
@@ -256,7 +300,8 @@ int parse(const uint8_t* in, size_t n, Parsed* P) {
   P->e = get<double>(in, 32);
   if (!(P->e > 0.0) || !std::isfinite(P->e)) return QREF_EFORMAT;
   if (get<uint32_t>(in, 40) != QREF_RADIUS) return QREF_EFORMAT;
-  if (get<uint32_t>(in, 52) != QREF_CHUNK) return QREF_EFORMAT;
+  if (get<uint32_t>(in, 52) != QREF_CHUNK || get<uint32_t>(in, 192) != 1024)
+    return QREF_EFORMAT;
   std::memset(&P->p, 0, sizeof(P->p));
   P->p.anchor_stride = get<uint32_t>(in, 44);
   P->p.alpha = get<double>(in, 56);
@@ -280,8 +325,9 @@ int parse(const uint8_t* in, size_t n, Parsed* P) {
   if (c.n_codes != (uint64_t)P->g.N - (uint64_t)A) return QREF_EFORMAT;
   if (c.n_unpred > c.n_codes) return QREF_EFORMAT;
   if (c.n_used < 1 || c.n_used > 2 * QREF_RADIUS) return QREF_EFORMAT;
-  if (c.n_chunks != (c.n_codes + QREF_CHUNK - 1) / QREF_CHUNK)
-    return QREF_EFORMAT;
+  P->R = regions_of(P->g, P->L, c.n_codes);
+  if (get<uint64_t>(in, 184) != P->R.start[P->R.n - 1]) return QREF_EFORMAT;
+  if (c.n_chunks != P->R.first[P->R.n]) return QREF_EFORMAT;
   if (c.n_words > 2 * c.n_codes + c.n_chunks) return QREF_EFORMAT;
   P->lay = layout_of(c);
   if (P->lay.total > n) return QREF_EFORMAT;
@@ -365,8 +411,8 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
     if (ch == 0 && w0 != 0) return QREF_EFORMAT;
     uint64_t nbits = (w1 - w0) * 32;
     uint64_t bitpos = 0;
-    uint64_t lo = ch * QREF_CHUNK;
-    uint64_t hi = std::min<uint64_t>(lo + QREF_CHUNK, c.n_codes);
+    uint64_t lo, hi;
+    chunk_range(P.R, ch, &lo, &hi);
     /* segment j (bins j, j + 8, ...) must start where the bit lengths of
      * segments 0..j-1 say; an empty segment has length 0; a segment with a
      * stored length must end exactly there, the last one inside the

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libqoz.so")
 QOZ_OK, QOZ_EINVAL, QOZ_ENOSPACE, QOZ_EFORMAT, QOZ_EDEVICE, QOZ_ENOMEM = range(6)
 TARGETS = {"cr": 0, "psnr": 1, "ssim": 2}
 MAX_LEVELS = 16
+HEADER_BYTES = 200  # stream header (format version 4)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOSPACE", 3: "EFORMAT",
                 4: "EDEVICE", 5: "ENOMEM"}
 
@@ -316,9 +317,9 @@ class Codec:
                             out.numel(), self._stream())
 
     def decompress(self, buf, out=None):
-        head = buf[:184].cpu().numpy()
-        sh, _, _ = qoz_inspect(head.tobytes() + bytes(0)) \
-            if buf.numel() >= 184 else (None, None, None)
+        head = buf[:HEADER_BYTES].cpu().numpy()
+        sh, _, _ = qoz_inspect(head.tobytes()) \
+            if buf.numel() >= HEADER_BYTES else (None, None, None)
         if sh is None:
             raise QozError(QOZ_EFORMAT, "decompress", "stream too short")
         dims = tuple(int(sh.dims[i]) for i in range(sh.ndim))

@@ -161,7 +161,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     QOZ_TRY(to_device(c, c->enc_table.p, tab, 8ull * tab_n, s));
   const uint64_t* dtab = (const uint64_t*)c->enc_table.p;
   PROF(PK_HUFF_LEN, 2.0 * P.n_codes + 8.0 * nch,
-       (launch_huff_len(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
+       (launch_huff_len(codes, P.chunks, dtab, lo, tab_n, zero_entry,
                         (uint32_t*)c->chunk_bits.p,
                         (uint32_t*)c->chunk_zeros.p, s),
         launch_chunk_scan((uint32_t*)c->chunk_bits.p,
@@ -202,7 +202,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   fill_sweep_table(P, &tbl);
   PROF(PK_HUFF_ENC,
        2.0 * P.n_codes + 4.0 * n_words + 8.0 * n_unpred + 26.0 * nch,
-       launch_huff_encode(codes, P.n_codes, dtab, lo, tab_n, zero_entry,
+       launch_huff_encode(codes, P.chunks, dtab, lo, tab_n, zero_entry,
                           (const uint64_t*)c->coff.p,
                           (const uint32_t*)c->upre.p,
                           (uint16_t*)(out + lay.segs),
@@ -235,7 +235,7 @@ qoz_status qoz_compress_bound(qoz_shape shape, size_t* bytes) {
   for (int i = 0; i < d; ++i) N *= n[i];
   /* every point a bin (no anchors): <= 16 bits each plus a padding word per
    * chunk, every bin possibly unpredictable, all 65536 symbols used */
-  uint64_t chunks = (N + kChunk - 1) / kChunk;
+  uint64_t chunks = (N + kMinChunk - 1) / kMinChunk + QOZ_MAX_LEVELS;
   Layout lay = layout_of(0, kNSym, chunks, N, (N + 1) / 2 + chunks);
   *bytes = lay.total + 64;
   return QOZ_OK;
@@ -344,7 +344,7 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
        launch_huff_decode((const uint32_t*)(in + lay.payload), nw,
                           (const uint64_t*)(in + lay.coff),
                           (const uint32_t*)(in + lay.upre),
-                          (const uint16_t*)(in + lay.segs), nch, P.n_codes, nu,
+                          (const uint16_t*)(in + lay.segs), P.chunks, nu,
                           (const DecTables*)c->dec_tables.p,
                           (const uint32_t*)c->dec_syms.p, codes, upos, st, s));
   SweepTable tbl;

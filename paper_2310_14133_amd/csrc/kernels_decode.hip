@@ -29,9 +29,9 @@
 
 namespace qoz {
 
-constexpr uint32_t kDecWG = 256; /* 4 waves: 32 chunks */
+constexpr uint32_t kDecWG = 640; /* 10 waves: 80 chunks */
 constexpr uint32_t kChunksPerWG = kDecWG / kSegPerChunk;
-constexpr uint32_t kRegMax = 27; /* longest code sized from registers */
+constexpr uint32_t kRegMax = 20; /* longest code sized from registers */
 constexpr uint32_t kMaxChunkWords = kChunk * kMaxCodeLen / 32 + 2;
 constexpr uint32_t kSortedLds = 1024; /* canonical symbols kept in LDS */
 constexpr uint32_t kRing = 16;        /* payload words per lane in LDS */
@@ -108,13 +108,21 @@ struct Reader {
                                        uint32_t p) {
     pos = p;
     const uint32_t wi = p >> 5, o = p & 31;
-    uint32_t v[kRing];
-    W.block<kRing / 4>(wi, v);
+    /* four words at a time (few registers: seeks are rare) */
+    uint32_t v0 = 0, v1 = 0;
+#pragma unroll 1
+    for (uint32_t k = 0; k < kRing; k += 4) {
+      uint32_t v[4];
+      W.block<1>(wi + k, v);
+      for (uint32_t i = 0; i < 4; ++i)
+        sh.ring[(wi + k + i) % kRing][threadIdx.x] = v[i];
+      if (k == 0) {
+        v0 = v[0];
+        v1 = v[1];
+      }
+    }
     W.block<kHalf / 4>(wi + kRing, pf);
-#pragma unroll
-    for (uint32_t k = 0; k < kRing; ++k)
-      sh.ring[(wi + k) % kRing][threadIdx.x] = v[k];
-    buf = (((uint64_t)v[0] << 32) | v[1]) << o;
+    buf = (((uint64_t)v0 << 32) | v1) << o;
     nb = 64 - (int)o;
     wp = wi + 2;
     B = wi;
@@ -196,7 +204,7 @@ __device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, uint32_t j) {
 __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     const uint32_t* __restrict__ payload, uint64_t n_words,
     const uint64_t* __restrict__ coff, const uint32_t* __restrict__ upre,
-    const uint16_t* __restrict__ segs, uint64_t n_chunks, uint64_t n_codes,
+    const uint16_t* __restrict__ segs, Chunks ch,
     uint64_t n_unpred, const DecTables* __restrict__ tabs,
     const uint32_t* __restrict__ syms, uint16_t* __restrict__ codes,
     uint32_t* __restrict__ upos, uint32_t* status) {
@@ -232,6 +240,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
   const uint32_t j = threadIdx.x % kSegPerChunk;
   const uint64_t c = (uint64_t)blockIdx.x * kChunksPerWG +
                      threadIdx.x / kSegPerChunk;
+  const uint64_t n_chunks = ch.count();
   const bool have = c < n_chunks;
   bool bad = false;
   uint64_t w0 = 0, w1 = 0;
@@ -245,8 +254,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     bad = w0 > w1 || w1 > n_words || (c == 0 && (w0 != 0 || u0 != 0)) ||
           u0 > u1 || u1 > n_unpred || w1 - w0 > kMaxChunkWords || w1 == w0 ||
           (last && (w1 != n_words || u1 != n_unpred));
-    const uint64_t base = c * kChunk;
-    nsym = (uint32_t)(n_codes - base < kChunk ? n_codes - base : kChunk);
+    nsym = (uint32_t)(ch.end(c) - ch.begin(c));
     d = j + 1 < kSegPerChunk ? segs[c * (kSegPerChunk - 1) + j] : 0u;
   }
   /* segment starts: exclusive scan of the stored lengths over the chunk */
@@ -261,7 +269,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
   /* decode */
   const Words W{payload + w0, chunk_ok ? nw : 0u,
                 chunk_ok ? (uint32_t)(n_words - w0) : 0u};
-  const uint64_t base = c * kChunk;
+  const uint64_t base = have ? ch.begin(c) : 0;
   bool inv = false;
   Reader rd;
   rd.seek(sh, W, start);
@@ -370,16 +378,16 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
 
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
-                        const uint16_t* segs, uint64_t n_chunks,
-                        uint64_t n_codes, uint64_t n_unpred,
-                        const DecTables* tabs, const uint32_t* syms,
-                        uint16_t* codes, uint32_t* upos, uint32_t* status,
-                        hipStream_t s) {
+                        const uint16_t* segs, const Chunks& chunks,
+                        uint64_t n_unpred, const DecTables* tabs,
+                        const uint32_t* syms, uint16_t* codes,
+                        uint32_t* upos, uint32_t* status, hipStream_t s) {
+  const uint64_t n_chunks = chunks.count();
   if (!n_chunks) return;
   const uint64_t blocks = (n_chunks + kChunksPerWG - 1) / kChunksPerWG;
   hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecWG), 0,
-                     s, payload, n_words, coff, upre, segs, n_chunks, n_codes,
-                     n_unpred, tabs, syms, codes, upos, status);
+                     s, payload, n_words, coff, upre, segs, chunks, n_unpred,
+                     tabs, syms, codes, upos, status);
 }
 
 }  // namespace qoz

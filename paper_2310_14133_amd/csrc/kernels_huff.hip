@@ -106,76 +106,77 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v,
 constexpr uint32_t kLenLds = 16384;
 
 __global__ __launch_bounds__(kEncThreads) void k_huff_len(
-    const uint16_t* __restrict__ codes, uint64_t n,
+    const uint16_t* __restrict__ codes, Chunks ch,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, uint32_t* chunk_bits, uint32_t* chunk_zeros) {
   __shared__ uint8_t lens[kLenLds];
-  __shared__ uint32_t wsum[2][kEncThreads / 64];
   const bool in_lds = tn <= kLenLds;
   if (in_lds)
     for (uint32_t i = threadIdx.x; i < tn; i += kEncThreads)
       lens[i] = (uint8_t)(tab[i] & 0xff);
   __syncthreads();
   const uint32_t zlen = (uint32_t)(zero_entry & 0xff);
-  const uint64_t n_chunks = (n + kChunk - 1) / kChunk;
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-  for (uint64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
-    const uint64_t b0 = c * kChunk + (uint64_t)threadIdx.x * kEncPerThread;
-    uint32_t sym[kEncPerThread];
-    if (b0 + kEncPerThread <= n) {
-      const uint4* p = reinterpret_cast<const uint4*>(codes + b0);
-      const uint4 q0 = p[0], q1 = p[1];
-      const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-      for (uint32_t k = 0; k < kEncPerThread; ++k)
-        sym[k] = (w[k >> 1] >> (16 * (k & 1))) & 0xffffu;
-    } else {
-#pragma unroll
-      for (uint32_t k = 0; k < kEncPerThread; ++k)
-        sym[k] = b0 + k < n ? codes[b0 + k] : 0xffffffffu;
+  const uint64_t n_chunks = ch.count();
+  const uint32_t lane = threadIdx.x & 63u;
+  auto bin_len = [&](uint32_t s, uint32_t& bits, uint32_t& zeros) {
+    if (s == 0) {
+      bits += zlen;
+      ++zeros;
+      return;
     }
+    const uint32_t o = s - (uint32_t)lo;
+    bits += o < tn ? (in_lds ? lens[o] : (uint32_t)(tab[o] & 0xff)) : 0u;
+  };
+  /* one wave per chunk: lane t takes 8-bin groups t, t + 64, ...; chunks
+   * start on a multiple of 64 bins, so full groups are 16-byte loads */
+  constexpr uint32_t kU = 4;
+  const uint64_t waves = (uint64_t)gridDim.x * (kEncThreads / 64);
+  for (uint64_t c = (uint64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6);
+       c < n_chunks; c += waves) {
+    const uint64_t b = ch.begin(c), e = ch.end(c);
     uint32_t bits = 0, zeros = 0;
+    for (uint64_t g0 = b + 8 * (uint64_t)lane; g0 < e; g0 += 8 * 64 * kU) {
+      uint4 q[kU];
 #pragma unroll
-    for (uint32_t k = 0; k < kEncPerThread; ++k) {
-      const uint32_t s = sym[k];
-      if (s == 0xffffffffu) continue;
-      if (s == 0) {
-        bits += zlen;
-        ++zeros;
-        continue;
+      for (uint32_t u = 0; u < kU; ++u) {
+        const uint64_t g = g0 + 8 * 64 * u;
+        q[u] = g + 8 <= e ? *reinterpret_cast<const uint4*>(codes + g)
+                          : make_uint4(0, 0, 0, 0);
       }
-      const uint32_t o = s - (uint32_t)lo;
-      bits += o < tn ? (in_lds ? lens[o] : (uint32_t)(tab[o] & 0xff)) : 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) {
+        const uint64_t g = g0 + 8 * 64 * u;
+        if (g >= e) break;
+        if (g + 8 <= e) {
+          const uint32_t w[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+          for (uint32_t k = 0; k < 8; ++k)
+            bin_len((w[k >> 1] >> (16 * (k & 1))) & 0xffffu, bits, zeros);
+        } else {
+          for (uint64_t i = g; i < e; ++i) bin_len(codes[i], bits, zeros);
+        }
+      }
     }
     bits = wave_sum_u32(bits);
     zeros = wave_sum_u32(zeros);
     if (lane == 0) {
-      wsum[0][wave] = bits;
-      wsum[1][wave] = zeros;
+      chunk_bits[c] = bits;
+      chunk_zeros[c] = zeros;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t tb = 0, tz = 0;
-      for (uint32_t w = 0; w < kEncThreads / 64; ++w) {
-        tb += wsum[0][w];
-        tz += wsum[1][w];
-      }
-      chunk_bits[c] = tb;
-      chunk_zeros[c] = tz;
-    }
-    __syncthreads();
   }
 }
 
-void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
+void launch_huff_len(const uint16_t* codes, const Chunks& chunks,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
                      uint32_t* chunk_zeros, hipStream_t s) {
-  uint64_t chunks = (n_codes + kChunk - 1) / kChunk;
-  if (!chunks) return;
-  const uint32_t blocks = chunks < 2048 ? (uint32_t)chunks : 2048u;
+  const uint64_t nch = chunks.count();
+  if (!nch) return;
+  const uint64_t per = kEncThreads / 64; /* chunks in flight per workgroup */
+  const uint32_t blocks =
+      (nch + per - 1) / per < 2048 ? (uint32_t)((nch + per - 1) / per) : 2048u;
   hipLaunchKernelGGL(k_huff_len, dim3(blocks), dim3(kEncThreads), 0, s,
-                     codes, n_codes, table, tab_lo, tab_n, zero_entry,
+                     codes, chunks, table, tab_lo, tab_n, zero_entry,
                      chunk_bits, chunk_zeros);
 }
 
@@ -454,7 +455,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
 }
 
 __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
-    const uint16_t* __restrict__ codes, uint64_t n,
+    const uint16_t* __restrict__ codes, Chunks ch,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, const uint64_t* __restrict__ coff,
     const uint32_t* __restrict__ upre, uint16_t* __restrict__ segs,
@@ -468,8 +469,8 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
   __shared__ uint32_t ws[2][kEncThreads / 64];
   __shared__ uint32_t seg_end[kSegPerChunk];
   const uint32_t c = blockIdx.x;
-  const uint64_t base = (uint64_t)c * kChunk;
-  const uint32_t nsym = (uint32_t)(n - base < kChunk ? n - base : kChunk);
+  const uint64_t base = ch.begin(c);
+  const uint32_t nsym = (uint32_t)(ch.end(c) - base);
   const uint64_t w0 = coff[c];
   const uint32_t nw = (uint32_t)(coff[c + 1] - w0);
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) words[i] = 0;
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
   if (over) atomicOr(status, kStOverflow);
 }
 
-void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
+void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
                         const uint32_t* upre, uint16_t* segs,
@@ -588,15 +589,15 @@ void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         const float* x, const Geo& g, const SweepTable& st,
                         uint32_t max_chunk_words, uint32_t* status,
                         hipStream_t s) {
-  uint64_t chunks = (n_codes + kChunk - 1) / kChunk;
-  if (!chunks) return;
+  const uint64_t nch = chunks.count();
+  if (!nch) return;
   /* every chunk's word count is at most the largest one, which is at
    * most kEncMaxWords (codes of at most 56 bits) */
   const uint32_t mw = max_chunk_words < kEncMaxWords ? max_chunk_words
                                                      : kEncMaxWords;
   const size_t lds = 4 * ((size_t)mw + 1);
-  hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)chunks), dim3(kEncThreads),
-                     lds, s, codes, n_codes, table, tab_lo, tab_n, zero_entry,
+  hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)nch), dim3(kEncThreads),
+                     lds, s, codes, chunks, table, tab_lo, tab_n, zero_entry,
                      coff, upre, segs, payload, payload_cap_words, unpred, x,
                      g, st, status);
 }

@@ -144,7 +144,27 @@ qoz_status make_plan(const qoz_shape& sh, double e, const qoz_params& p_in,
     }
   }
   P.n_codes = off;
-  P.n_chunks = (off + kChunk - 1) / kChunk;
+  /* chunking by level, level L first (as in the stream) */
+  {
+    Chunks& C = P.chunks;
+    C = Chunks();
+    C.n = L;
+    C.start[0] = 0;
+    C.first[0] = 0;
+    uint64_t t = 0;
+    for (uint32_t r = 0; r < L; ++r) {
+      const uint32_t l = L - r;
+      for (const Sweep& sw : P.sweeps)
+        if (sw.level == l) t += sw.count;
+      const uint64_t e = r + 1 == L ? off : (t + 63) / 64 * 64;
+      C.start[r + 1] = e < off ? e : off;
+      const uint32_t sz = kChunk >> (l - 1);
+      C.size[r] = sz > kMinChunk ? sz : kMinChunk;
+      C.first[r + 1] =
+          C.first[r] + (C.start[r + 1] - C.start[r] + C.size[r] - 1) / C.size[r];
+    }
+  }
+  P.n_chunks = P.chunks.count();
   if (P.n_codes + P.n_anchor != (uint64_t)P.g.n[0] * P.g.n[1] * P.g.n[2])
     return fail(QOZ_EINVAL, "internal: sweep schedule does not cover field");
   return QOZ_OK;
@@ -267,6 +287,8 @@ void write_header(uint8_t* h, const Plan& p, uint64_t n_unpred,
   wr<uint64_t>(h, 160, n_used);
   wr<uint64_t>(h, 168, p.n_chunks);
   wr<uint64_t>(h, 176, n_words);
+  wr<uint64_t>(h, 184, p.chunks.start[p.chunks.n - 1]); /* before level 1 */
+  wr<uint32_t>(h, 192, kMinChunk);
 }
 
 qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* plan,
@@ -283,7 +305,7 @@ qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* 
   for (int i = 0; i < 3; ++i) sh.dims[i] = rd<uint64_t>(h, 8 + 8 * i);
   if (sh.ndim == 2 && sh.dims[2] != 1) return fail(QOZ_EFORMAT, "bad dims");
   if (rd<uint32_t>(h, 40) != (uint32_t)kRadius ||
-      rd<uint32_t>(h, 52) != kChunk)
+      rd<uint32_t>(h, 52) != kChunk || rd<uint32_t>(h, 192) != kMinChunk)
     return fail(QOZ_EFORMAT, "unsupported radius or chunk size");
   qoz_params p;
   std::memset(&p, 0, sizeof(p));
@@ -308,6 +330,7 @@ qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* 
   uint64_t nu = rd<uint64_t>(h, 152), nused = rd<uint64_t>(h, 160);
   uint64_t nch = rd<uint64_t>(h, 168), nw = rd<uint64_t>(h, 176);
   if (na != plan->n_anchor || nc != plan->n_codes || nch != plan->n_chunks ||
+      rd<uint64_t>(h, 184) != plan->chunks.start[plan->chunks.n - 1] ||
       nu > nc || nused < 1 || nused > kNSym ||
       nw > 2 * nc + nch)
     return fail(QOZ_EFORMAT, "inconsistent counts in header");

@@ -20,12 +20,42 @@ namespace qoz {
 
 constexpr int32_t kRadius = 32768;         /* bins on each side of zero */
 constexpr uint32_t kNSym = 2 * kRadius;    /* Huffman alphabet */
-constexpr uint32_t kChunk = 4096;          /* bins per Huffman chunk */
+constexpr uint32_t kChunk = 4096;          /* bins per level-1 chunk */
 constexpr uint32_t kSegLog2 = 9;           /* a chunk holds 8 segments of */
 constexpr uint32_t kSeg = 1u << kSegLog2;  /* 512 bins, each decodable alone */
 constexpr uint32_t kSegPerChunk = kChunk / kSeg;
-constexpr size_t kHeaderBytes = 184;
-constexpr uint16_t kStreamVersion = 3;
+constexpr size_t kHeaderBytes = 200;
+constexpr uint16_t kStreamVersion = 4;
+
+/* Chunks of the bin stream, by level: level l (levels L..1 in stream
+ * order) is cut into chunks of max(kChunk >> (l - 1), kMinChunk) bins, level
+ * boundaries rounded up to a multiple of 64 bins (at most all bins), a
+ * level's last chunk possibly shorter.  Coarser levels carry more long
+ * codes per bin, so their segments are shorter, to decode in about the
+ * time of a level-1 segment; the rounding keeps chunk starts 128-byte
+ * aligned in the bin array. */
+constexpr uint32_t kMinChunk = 1024;
+struct Chunks {
+  uint32_t n = 0;                          /* regions: one per level */
+  uint32_t size[QOZ_MAX_LEVELS];           /* chunk size of region r */
+  uint64_t start[QOZ_MAX_LEVELS + 1];      /* first bin; start[n] = bins */
+  uint64_t first[QOZ_MAX_LEVELS + 1];      /* first chunk; first[n] = all */
+  __host__ __device__ uint32_t region(uint64_t c) const {
+    uint32_t r = 0;
+    while (r + 1 < n && c >= first[r + 1]) ++r;
+    return r;
+  }
+  __host__ __device__ uint64_t begin(uint64_t c) const {
+    const uint32_t r = region(c);
+    return start[r] + (c - first[r]) * size[r];
+  }
+  __host__ __device__ uint64_t end(uint64_t c) const {
+    const uint32_t r = region(c);
+    const uint64_t e = start[r] + (c - first[r] + 1) * size[r];
+    return e < start[r + 1] ? e : start[r + 1];
+  }
+  __host__ __device__ uint64_t count() const { return n ? first[n] : 0; }
+};
 constexpr int kLenBits = 13;               /* decoder length-table width */
 constexpr int kSymBits = 12;               /* decoder symbol-table width */
 constexpr int kMaxCodeLen = 63;
@@ -76,6 +106,7 @@ struct Plan {
   uint8_t order[QOZ_MAX_LEVELS][3]; /* real dimensions */
   uint32_t na[3];      /* anchors per grid dimension */
   uint64_t n_anchor = 0, n_codes = 0, n_chunks = 0;
+  Chunks chunks;
   std::vector<Sweep> sweeps;
 };
 
@@ -283,7 +314,7 @@ void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
 /* bytes from device memory to coherent host memory (to_host) or back */
 void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
                       hipStream_t s);
-void launch_huff_len(const uint16_t* codes, uint64_t n_codes,
+void launch_huff_len(const uint16_t* codes, const Chunks& chunks,
                      const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                      uint64_t zero_entry, uint32_t* chunk_bits,
                      uint32_t* chunk_zeros, hipStream_t s);
@@ -293,7 +324,7 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
                        const uint32_t* chunk_zeros, uint64_t n_chunks,
                        uint64_t* coff, uint32_t* upre, uint64_t* totals,
                        uint64_t* scratch, hipStream_t s);
-void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
+void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
                         const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
                         uint64_t zero_entry, const uint64_t* coff,
                         const uint32_t* upre, uint16_t* segs,
@@ -304,7 +335,7 @@ void launch_huff_encode(const uint16_t* codes, uint64_t n_codes,
                         hipStream_t s);
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
-                        const uint16_t* segs, uint64_t n_chunks, uint64_t n_codes,
+                        const uint16_t* segs, const Chunks& chunks,
                         uint64_t n_unpred, const DecTables* tabs,
                         const uint32_t* syms, uint16_t* codes,
                         uint32_t* upos, uint32_t* status, hipStream_t s);

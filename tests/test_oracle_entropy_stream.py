@@ -95,6 +95,27 @@ CASES = [
 ]
 
 
+def chunk_sizes(shape, s, n_codes):
+    """Bins per chunk.  Level l (levels L..1 in stream order, L = log2 s)
+    holds the points on the stride-2^(l-1) grid that are not on the
+    stride-2^l grid; its bins form chunks of max(4096 >> (l - 1), 1024),
+    level boundaries rounded up to 64 bins, the last chunk of a level
+    possibly shorter.  Returns (bins before level 1, sizes)."""
+    L = int(s).bit_length() - 1
+    on = lambda h: int(np.prod([(n - 1) // h + 1 for n in shape]))
+    sizes, t, start = [], 0, 0
+    for l in range(L, 0, -1):
+        t += on(2 ** (l - 1)) - on(2 ** l)
+        end = n_codes if l == 1 else min(-(-t // 64) * 64, n_codes)
+        if l == 1:
+            before_l1 = start
+        c = max(4096 >> (l - 1), 1024)
+        m = end - start
+        sizes += [c] * (m // c) + ([m % c] if m % c else [])
+        start = end
+    return before_l1, sizes
+
+
 @pytest.mark.parametrize("name,make,rel,s", CASES)
 def test_stream_roundtrip(ref, name, make, rel, s):
     x = make()
@@ -115,7 +136,10 @@ def test_stream_roundtrip(ref, name, make, rel, s):
     hist = np.bincount(codes, minlength=2 * 32768).astype(np.uint64)
     ln = ref.huffman_lengths(hist)
     bits = int(np.sum(hist * ln))
-    nchunks = -(-codes.size // 4096)
+    stride = s or (64 if x.ndim == 2 else 32)
+    _, sizes = chunk_sizes(x.shape, stride, codes.size)
+    nchunks = len(sizes)
+    assert int(np.frombuffer(z[168:176].tobytes(), np.uint64)[0]) == nchunks
     n_words = int(np.frombuffer(z[176:184].tobytes(), np.uint64)[0])
     assert bits <= 32 * n_words < bits + 32 * nchunks
     assert int(np.frombuffer(z[152:160].tobytes(), np.uint64)[0]) == unpred.size
@@ -127,8 +151,8 @@ def test_stream_header_fields(ref):
                         1.5, 3.0, anchor_stride=8)
     z = ref.compress(x, 0.01, p)
     assert bytes(z[:4]) == b"QOZ1"
-    hdr = z[:184].tobytes()
-    assert int(np.frombuffer(hdr[4:6], np.uint16)[0]) == 3  # version
+    hdr = z[:200].tobytes()
+    assert int(np.frombuffer(hdr[4:6], np.uint16)[0]) == 4  # version
     assert hdr[7] == 9                               # log2 segment size
     u64 = lambda o: int(np.frombuffer(hdr[o:o + 8], np.uint64)[0])
     u32 = lambda o: int(np.frombuffer(hdr[o:o + 4], np.uint32)[0])
@@ -139,6 +163,10 @@ def test_stream_header_fields(ref):
     assert list(hdr[88:94]) == [1, 0, 0, 0, 1, 0]  # 3 bytes per level
     n_anchor = u64(136)
     assert n_anchor == 3 * 4 and u64(144) == 600 - 12
+    # bins before level 1: level 3 (5 x 8 points of stride 4 minus the
+    # 3 x 4 anchors = 28, rounded up to 64) and level 2 (10 x 15 - 5 x 8 =
+    # 110; 64 + 110 = 174, rounded up to 192)
+    assert u64(184) == 192 and u32(192) == 1024
 
 
 def test_corrupt_streams_rejected(ref):
@@ -151,7 +179,7 @@ def test_corrupt_streams_rejected(ref):
     assert ref.decompress_status(bad) == ref.EFORMAT
     assert ref.decompress_status(z[:100]) == ref.EFORMAT
     assert ref.decompress_status(z[:-8]) == ref.EFORMAT
-    for off in (136, 144, 160, 168, 176):            # counts
+    for off in (136, 144, 160, 168, 176, 184, 192):  # counts, chunking
         bad = z.copy(); bad[off] ^= 0x01
         assert ref.decompress_status(bad) == ref.EFORMAT, off
     bad = z.copy(); bad[40] ^= 0x01                  # radius
@@ -168,7 +196,7 @@ def test_payload_bitflips_never_crash(ref):
     rng = np.random.default_rng(0)
     for _ in range(30):
         bad = z.copy()
-        pos = int(rng.integers(184, z.size))
+        pos = int(rng.integers(200, z.size))
         bad[pos] ^= 1 << int(rng.integers(8))
         assert ref.decompress_status(bad) in (ref.OK, ref.EFORMAT)
 
@@ -196,7 +224,7 @@ def _segs_section(z):
     u64 = lambda o: int(np.frombuffer(z[o:o + 8].tobytes(), np.uint64)[0])
     al8 = lambda v: (v + 7) // 8 * 8
     n_anchor, n_used, n_chunks = u64(136), u64(160), u64(168)
-    off = al8(184 + 4 * n_anchor)
+    off = al8(200 + 4 * n_anchor)
     off = al8(off + 2 * n_used)
     off = al8(off + n_used)
     off = al8(off + 8 * (n_chunks + 1))
@@ -221,9 +249,14 @@ def test_segment_table(ref, shape, rel):
     segs = np.frombuffer(z[off:off + 14 * n_chunks].tobytes(), np.uint16)
     segs = segs.reshape(n_chunks, 7).astype(np.int64)
     per_bin = ln[codes]
-    pad = np.zeros(n_chunks * 4096, np.int64)
-    pad[:per_bin.size] = per_bin
-    want = pad.reshape(n_chunks, 512, 8).sum(axis=1)[:, :7]
+    _, sizes = chunk_sizes(x.shape, 64 if x.ndim == 2 else 32, codes.size)
+    assert len(sizes) == n_chunks and sum(sizes) == codes.size
+    want = np.zeros((n_chunks, 7), np.int64)
+    lo = 0
+    for c, m in enumerate(sizes):
+        for j in range(7):
+            want[c, j] = per_bin[lo + j:lo + m:8].sum()
+        lo += m
     assert n_chunks >= 2 and codes.size % 4096 != 0
     assert np.array_equal(segs, want)
     # a wrong length is rejected
@@ -231,7 +264,7 @@ def test_segment_table(ref, shape, rel):
     bad[off + 2] ^= 0x01
     assert ref.decompress_status(bad) == ref.EFORMAT
     # so is a nonzero length for an empty segment
-    tail = codes.size - (n_chunks - 1) * 4096
+    tail = sizes[-1]
     if tail < 7:
         assert np.all(segs[-1, tail:] == 0)
         bad = z.copy()
