@@ -28,7 +28,12 @@ enum {
   QREF_EFORMAT = 3   /* malformed compressed stream */
 };
 
-enum { QREF_TARGET_CR = 0, QREF_TARGET_PSNR = 1, QREF_TARGET_SSIM = 2 };
+enum {
+  QREF_TARGET_CR = 0,
+  QREF_TARGET_PSNR = 1,
+  QREF_TARGET_SSIM = 2,
+  QREF_TARGET_AC = 3 /* lag-1 error autocorrelation (Eq. 4) */
+};
 
 #define QREF_MAX_LEVELS 16
 #define QREF_RADIUS 32768
@@ -87,6 +92,7 @@ typedef struct {
   double ssim_sum;   /* sum of window SSIMs over windows inside blocks */
   uint64_t n_windows;
   double B;          /* (payload_bits + 32 * n_unpred) / n_points */
+  double ac;         /* lag-1 error autocorrelation over the blocks' rows */
 } qref_trial_result;
 
 /* ---- level plan (Eq. 5) ------------------------------------------------ */
@@ -139,6 +145,11 @@ int qref_inspect(const void* in, size_t in_bytes, qref_shape* shape,
 int qref_metrics(const float* x, const float* y, qref_shape shape,
                  uint32_t ssim_window, double* psnr, double* ssim,
                  double* max_abs_err);
+/* Lag-1 autocorrelation of the errors x - y along the fastest dimension
+ * (Eq. 4): mean and population variance over all points, lagged products
+ * over all adjacent pairs of a row; 0 when the errors are constant. */
+int qref_error_ac(const float* x, const float* y, qref_shape shape,
+                  double* ac);
 /* Window sums of SSIM over all windows fully inside the field, with c1, c2
  * from vrange; direct (O(N w^d)) and separable (O(N w d)) variants. */
 int qref_ssim_direct(const float* x, const float* y, qref_shape shape,
@@ -155,10 +166,11 @@ int qref_sample_plan(qref_shape shape, uint32_t anchor_stride,
                      const qref_tune_config* cfg, uint32_t* b, uint32_t* S,
                      uint32_t* Lt, uint64_t* nblocks, uint64_t* block_dims,
                      uint64_t* origins, uint64_t origins_cap);
-/* One trial: theta at bound e_trial over the sampled blocks. */
+/* One trial: theta at bound e_trial over the sampled blocks; want: bit 0
+ * the SSIM sums, bit 1 the error autocorrelation. */
 int qref_trial(const float* x, qref_shape shape, double e_trial,
                const qref_params* theta, const qref_tune_config* cfg,
-               double vrange, uint32_t want_ssim, qref_trial_result* res);
+               double vrange, uint32_t want, qref_trial_result* res);
 /* Table-I case of (B_I, M_I) vs (B_II, M_II): 1..4. */
 int qref_table1_case(double BI, double MI, double BII, double MII);
 /* Line test of Table I cases 3/4: 1 if II is better, 0 if I stays. */

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqoz_ref.so")
 
 OK, EINVAL, ENOSPACE, EFORMAT = 0, 1, 2, 3
-TARGETS = {"cr": 0, "psnr": 1, "ssim": 2}
+TARGETS = {"cr": 0, "psnr": 1, "ssim": 2, "ac": 3}
 MAX_LEVELS = 16
 RADIUS = 32768
 CHUNK = 4096
@@ -53,7 +53,8 @@ class TrialResult(C.Structure):
     _fields_ = [("payload_bits", C.c_uint64), ("n_unpred", C.c_uint64),
                 ("n_points", C.c_uint64), ("n_codes", C.c_uint64),
                 ("sse", C.c_double), ("ssim_sum", C.c_double),
-                ("n_windows", C.c_uint64), ("B", C.c_double)]
+                ("n_windows", C.c_uint64), ("B", C.c_double),
+                ("ac", C.c_double)]
 
 
 class OracleError(RuntimeError):
@@ -278,6 +279,17 @@ def metrics(x, y, ssim_window=7):
     return ps.value, ss.value, me.value
 
 
+def error_ac(x, y):
+    """Lag-1 autocorrelation of the errors x - y along the fastest
+    dimension (Eq. 4)."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    ac = C.c_double()
+    _chk(lib().qref_error_ac(_ptr(x), _ptr(y), shape_of(x.shape),
+                             C.byref(ac)), "error_ac")
+    return ac.value
+
+
 def ssim_sums(x, y, w, vrange, direct=False):
     x = np.ascontiguousarray(x, np.float32)
     y = np.ascontiguousarray(y, np.float32)
@@ -304,7 +316,8 @@ def sample_plan(dims, anchor_stride=0, cfg=None):
             "origins": org[:nb.value * d].reshape(-1, d)}
 
 
-def trial(x, e_trial, theta, cfg=None, vrange=None, want_ssim=False):
+def trial(x, e_trial, theta, cfg=None, vrange=None, want_ssim=False,
+          want_ac=False):
     x = np.ascontiguousarray(x, np.float32)
     if vrange is None:
         vrange = float(x.max()) - float(x.min())
@@ -312,7 +325,8 @@ def trial(x, e_trial, theta, cfg=None, vrange=None, want_ssim=False):
     _chk(lib().qref_trial(_ptr(x), shape_of(x.shape), C.c_double(e_trial),
                           C.byref(theta),
                           C.byref(cfg) if cfg is not None else None,
-                          C.c_double(vrange), C.c_uint32(int(want_ssim)),
+                          C.c_double(vrange),
+                          C.c_uint32(int(want_ssim) | 2 * int(want_ac)),
                           C.byref(r)), "trial")
     return r
 

@@ -18,6 +18,8 @@ struct Grid {
   int64_t stride[3] = {0, 0, 0};
   int64_t N = 0;
 };
+/* Lag-1 autocorrelation of e over nrows rows of len values (Eq. 4). */
+double ac_of_rows(const double* e, int64_t nrows, int64_t len);
 Grid make_grid(int d, const int64_t* n);
 bool shape_to_grid(const qref_shape& s, Grid* g); /* validates dims */
 

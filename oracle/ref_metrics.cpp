@@ -9,6 +9,7 @@
  * c1 = (0.01 vrange)^2, c2 = (0.03 vrange)^2 with the range of X.
  */
 #include <cmath>
+#include <vector>
 #include <cstring>
 #include <limits>
 
@@ -167,6 +168,37 @@ extern "C" int qref_ssim_separable(const float* x, const float* y,
 }
 
 /* Eq. 1: PSNR = 20 log10(vrange / sqrt(mse)), vrange = max(X) - min(X). */
+/* Eq. 4 with lag k = 1 along the fastest dimension: the mean and the
+ * population variance of the errors over all points; the lagged moment
+ * over every pair of neighbours in a row. */
+double qref::ac_of_rows(const double* e, int64_t nrows, int64_t len) {
+  const int64_t n = nrows * len;
+  double mu = 0.0;
+  for (int64_t i = 0; i < n; ++i) mu += e[i];
+  mu /= (double)n;
+  double var = 0.0;
+  for (int64_t i = 0; i < n; ++i) var += (e[i] - mu) * (e[i] - mu);
+  var /= (double)n;
+  if (!(var > 0.0) || len < 2) return 0.0;
+  double lag = 0.0;
+  for (int64_t r = 0; r < nrows; ++r)
+    for (int64_t k = 0; k + 1 < len; ++k)
+      lag += (e[r * len + k] - mu) * (e[r * len + k + 1] - mu);
+  lag /= (double)(nrows * (len - 1));
+  return lag / var;
+}
+
+extern "C" int qref_error_ac(const float* x, const float* y, qref_shape shape,
+                             double* ac) {
+  Grid g;
+  if (!x || !y || !ac || !shape_to_grid(shape, &g)) return QREF_EINVAL;
+  std::vector<double> e((size_t)g.N);
+  for (int64_t i = 0; i < g.N; ++i) e[(size_t)i] = (double)x[i] - (double)y[i];
+  const int64_t len = g.n[g.d - 1];
+  *ac = ac_of_rows(e.data(), g.N / len, len);
+  return QREF_OK;
+}
+
 extern "C" int qref_metrics(const float* x, const float* y, qref_shape shape,
                             uint32_t ssim_window, double* psnr, double* ssim,
                             double* max_abs_err) {

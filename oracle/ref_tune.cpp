@@ -25,6 +25,10 @@
  *    that brackets B_I between B_II and B'_II).  On the line or with a
  *    degenerate line I is kept.  In ratio mode M is 0 for every trial.
  *  - PSNR of a trial uses the global value range of X.
+ *  - AC target (Eq. 4): lag 1 along the fastest dimension; a trial's AC
+ *    takes the mean and variance over all block points and the lagged
+ *    moment over the blocks' rows; M = -|AC| (the paper prefers errors as
+ *    uncorrelated as possible).
  */
 #include <algorithm>
 #include <cmath>
@@ -143,12 +147,14 @@ std::vector<Cand> candidates(int d, bool all_orders) {
 
 /* Trial compression of every sampled block with one parameter set. */
 void run_trial(const Sample& sp, const LevelPlan& plan, const LevelBounds& lb,
-               double vrange, bool want_ssim, int w, qref_trial_result* res) {
+               double vrange, bool want_ssim, bool want_ac, int w,
+               qref_trial_result* res) {
   const uint32_t nsym = 2 * QREF_RADIUS;
   std::vector<uint64_t> hist(nsym, 0);
   std::memset(res, 0, sizeof(*res));
   int64_t st = (int64_t)1 << sp.Lt;
   std::vector<float> W((size_t)sp.bg.N);
+  std::vector<double> errs; /* every block's errors, block after block */
   for (const auto& blk : sp.blocks) {
     std::fill(W.begin(), W.end(), std::numeric_limits<float>::quiet_NaN());
     place_anchors(blk.data(), sp.bg, st, W.data(), nullptr);
@@ -161,6 +167,7 @@ void run_trial(const Sample& sp, const LevelPlan& plan, const LevelBounds& lb,
     for (int64_t i = 0; i < sp.bg.N; ++i) {
       double d = (double)blk[(size_t)i] - (double)W[(size_t)i];
       res->sse += d * d;
+      if (want_ac) errs.push_back(d);
     }
     res->n_points += (uint64_t)sp.bg.N;
     if (want_ssim) {
@@ -170,6 +177,11 @@ void run_trial(const Sample& sp, const LevelPlan& plan, const LevelBounds& lb,
       res->ssim_sum += s;
       res->n_windows += nw;
     }
+  }
+  if (want_ac) {
+    /* the blocks' rows (along the fastest dimension) together */
+    const int64_t rl = sp.bg.n[sp.bg.d - 1];
+    res->ac = ac_of_rows(errs.data(), (int64_t)errs.size() / rl, rl);
   }
   std::vector<uint8_t> len(nsym);
   huffman_lengths(hist.data(), nsym, len.data());
@@ -184,6 +196,8 @@ double metric_of(const qref_trial_result& r, int target, double vrange) {
     return 20.0 * std::log10(vrange / std::sqrt(r.sse / (double)r.n_points));
   }
   if (target == QREF_TARGET_SSIM) return r.ssim_sum / (double)r.n_windows;
+  /* errors closest to uncorrelated are best (Eq. 4) */
+  if (target == QREF_TARGET_AC) return -std::fabs(r.ac);
   return 0.0;
 }
 
@@ -238,7 +252,7 @@ extern "C" int qref_sample_plan(qref_shape shape, uint32_t anchor_stride,
 extern "C" int qref_trial(const float* x, qref_shape shape, double e_trial,
                           const qref_params* theta,
                           const qref_tune_config* cfg, double vrange,
-                          uint32_t want_ssim, qref_trial_result* res) {
+                          uint32_t want, qref_trial_result* res) {
   Grid g;
   if (!x || !theta || !res || !shape_to_grid(shape, &g)) return QREF_EINVAL;
   int L;
@@ -252,7 +266,8 @@ extern "C" int qref_trial(const float* x, qref_shape shape, double e_trial,
   LevelBounds lb;
   bounds_eq5(e_trial, theta->alpha, theta->beta, (int)sp.Lt, &lb);
   int w = (cfg && cfg->ssim_window) ? (int)cfg->ssim_window : 7;
-  run_trial(sp, plan, lb, vrange, want_ssim != 0, w, res);
+  run_trial(sp, plan, lb, vrange, (want & 1u) != 0, (want & 2u) != 0, w,
+            res);
   return QREF_OK;
 }
 
@@ -262,7 +277,7 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
   Grid g;
   if (!x || !out || !shape_to_grid(shape, &g)) return QREF_EINVAL;
   if (!(e > 0.0) || !std::isfinite(e)) return QREF_EINVAL;
-  if (target < QREF_TARGET_CR || target > QREF_TARGET_SSIM) return QREF_EINVAL;
+  if (target < QREF_TARGET_CR || target > QREF_TARGET_AC) return QREF_EINVAL;
   if (!all_finite(x, g.N)) return QREF_EINVAL;
   uint32_t s = out->anchor_stride ? out->anchor_stride : (g.d == 2 ? 64u : 32u);
   if (s < 2 || (s & (s - 1)) != 0) return QREF_EINVAL;
@@ -332,12 +347,13 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
 
   /* (alpha, beta) search with Table I */
   bool want_ssim = target == QREF_TARGET_SSIM;
+  bool want_ac = target == QREF_TARGET_AC;
   double B[QREF_NPAIRS], M[QREF_NPAIRS];
   for (int i = 0; i < QREF_NPAIRS; ++i) {
     LevelBounds lb;
     bounds_eq5(e, kAlphas[i / 4], kBetas[i % 4], Lt, &lb);
     qref_trial_result r;
-    run_trial(sp, Is, lb, vrange, want_ssim, w, &r);
+    run_trial(sp, Is, lb, vrange, want_ssim, want_ac, w, &r);
     B[i] = r.B;
     M[i] = metric_of(r, target, vrange);
     if (trace) {
@@ -362,7 +378,7 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
     LevelBounds lb;
     bounds_eq5(ep, kAlphas[i / 4], kBetas[i % 4], Lt, &lb);
     qref_trial_result r;
-    run_trial(sp, Is, lb, vrange, want_ssim, w, &r);
+    run_trial(sp, Is, lb, vrange, want_ssim, want_ac, w, &r);
     double Bp = r.B, Mp = metric_of(r, target, vrange);
     if (trace) {
       trace->Bp[i] = Bp;

@@ -1,4 +1,5 @@
-"""Oracle pins: PSNR (Eq. 1) and windowed SSIM (Eq. 2-3).  CPU only."""
+"""Oracle pins: PSNR (Eq. 1), windowed SSIM (Eq. 2-3) and the lag-1
+autocorrelation of errors (Eq. 4).  CPU only."""
 import math
 
 import numpy as np
@@ -89,3 +90,41 @@ def test_ssim_hand_example(ref):
         ((1.5 ** 2 + 2 ** 2 + c1) * (1.25 + 3.5 + c2))
     s, n = ref.ssim_sums(x, y, 7, 3.0)
     assert n == 1 and abs(s - want) < 1e-15
+
+
+def _with_errors(e):
+    """x = 0, y = -e, so x - y = e exactly (e holds powers of two and small
+    integers)."""
+    e = np.asarray(e, np.float32)
+    return np.zeros_like(e), -e
+
+
+def test_ac_alternating_errors_is_minus_one(ref):
+    """Errors +d, -d, +d, ... along every row: the lagged products are all
+    -d^2 around a zero mean, so AC = -1 exactly."""
+    e = np.tile(np.where(np.arange(10) % 2 == 0, 0.5, -0.5), (6, 7, 1))
+    assert ref.error_ac(*_with_errors(e)) == -1.0
+
+
+def test_ac_axis_is_the_fastest_dimension(ref):
+    """Errors alternating along dimension 0 but constant along each row:
+    neighbours in a row carry equal errors, so AC = +1 (it would be -1 along
+    dimension 0)."""
+    e = np.broadcast_to(np.where(np.arange(6) % 2 == 0, 0.25, -0.25)[:, None,
+                                                                      None],
+                        (6, 5, 8))
+    assert ref.error_ac(*_with_errors(e)) == 1.0
+
+
+def test_ac_constant_error_is_zero(ref):
+    e = np.full((9, 11), 0.125, np.float32)
+    assert ref.error_ac(*_with_errors(e)) == 0.0
+
+
+@pytest.mark.parametrize("n", [5, 9, 33])
+def test_ac_ramp_closed_form(ref, n):
+    """Errors 0, 1, ..., n-1 in every row: mean (n-1)/2, variance
+    (n^2-1)/12, lagged moment (n-3)(n+1)/12, so AC = (n-3)/(n-1)."""
+    e = np.tile(np.arange(n, dtype=np.float32), (4, 1))
+    got = ref.error_ac(*_with_errors(e))
+    assert abs(got - (n - 3) / (n - 1)) <= 1e-15

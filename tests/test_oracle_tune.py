@@ -154,6 +154,7 @@ def trial_blockwise(ref, blocks, d, Lt, interp, order, alpha, beta, e,
     U = npts = 0
     sse = 0.0
     ssim_s, ssim_n = 0.0, 0
+    errs = []
     for b in blocks:
         codes, recon, unpred, _ = ref.predict_quantize(b, e, p)
         hist += np.bincount(codes, minlength=hist.size).astype(np.uint64)
@@ -161,6 +162,7 @@ def trial_blockwise(ref, blocks, d, Lt, interp, order, alpha, beta, e,
         npts += b.size
         dd = b.astype(np.float64) - recon
         sse += float((dd * dd).sum())
+        errs.append(dd.reshape(-1, b.shape[-1]))
         if target == "ssim":
             s, n = ref.ssim_sums(b, recon, w, vrange)
             ssim_s += s
@@ -171,6 +173,13 @@ def trial_blockwise(ref, blocks, d, Lt, interp, order, alpha, beta, e,
         M = math.inf if sse == 0 else 20 * math.log10(vrange / math.sqrt(sse / npts))
     elif target == "ssim":
         M = ssim_s / ssim_n
+    elif target == "ac":
+        # lag 1 along rows; mean and variance over all block points
+        r = np.concatenate(errs)
+        mu = r.mean()
+        var = ((r - mu) ** 2).mean()
+        lag = ((r[:, :-1] - mu) * (r[:, 1:] - mu)).mean()
+        M = -abs(lag / var) if var > 0 else 0.0
     else:
         M = 0.0
     return B, M, bits, U
@@ -196,6 +205,10 @@ CASES = [
      dict(block=32, sample_rate=0.2), "cr", 1e-3),
     ("2d_psnr_case3", lambda: fields.bumps_and_waves(200, 6, noise=1e-4),
      None, 32, dict(block=32, sample_rate=0.2), "psnr", 1e-3),
+    ("2d_ac", lambda: fields.grf((96, 100), 36), None, 16,
+     dict(block=16, sample_rate=0.15), "ac", 1e-3),
+    ("3d_ac_all", lambda: fields.multiscale((34, 36, 40), 37), None, 8,
+     dict(block=8, sample_rate=0.2, all_orders=1), "ac", 1e-3),
 ]
 
 
@@ -236,7 +249,7 @@ def test_tuner_bruteforce(ref, name, make, _, s, cfgkw, target, rel):
         B.append(bi)
         M.append(mi)
         assert bi == tr.B[i]
-        assert (mi == tr.M[i]) or abs(mi - tr.M[i]) <= 1e-11 * abs(mi)
+        assert (mi == tr.M[i]) or abs(mi - tr.M[i]) <= 1e-11 * max(abs(mi), 1e-3)
 
     def rerun(i, f):
         a, b = pairs[i]
@@ -281,6 +294,9 @@ def test_single_block_trial_equals_real_compression(ref):
     psnr, _, _ = ref.metrics(x, y)
     trial_psnr = 20 * math.log10(vr / math.sqrt(r.sse / r.n_points))
     assert abs(trial_psnr - psnr) < 1e-9
+    # ... and the trial's error autocorrelation is the real one
+    ra = ref.trial(x, e, p, cfg, vr, want_ac=True)
+    assert ra.ac == ref.error_ac(x, y)
 
 
 def test_duplicate_bound_vectors_give_identical_trials(ref):
