@@ -50,11 +50,14 @@ typedef enum {
 } qoz_status;
 
 /* Quality target of the tuner (Sec. III): the ratio at the fixed bound,
- * PSNR (Eq. 1) or SSIM (Eq. 2-3). */
+ * PSNR (Eq. 1), SSIM (Eq. 2-3), or the lag-1 autocorrelation of the errors
+ * (Eq. 4; the AC-preferred mode of Sec. VII), where the tuner prefers the
+ * smallest |AC|. */
 typedef enum {
   QOZ_TARGET_CR = 0,
   QOZ_TARGET_PSNR = 1,
-  QOZ_TARGET_SSIM = 2
+  QOZ_TARGET_SSIM = 2,
+  QOZ_TARGET_AC = 3
 } qoz_target;
 
 typedef struct {
@@ -140,6 +143,14 @@ qoz_status qoz_inspect(const void* h_in, size_t in_bytes, qoz_shape* shape,
 qoz_status qoz_metrics(qoz_ctx* ctx, const float* d_x, const float* d_y,
                        qoz_shape shape, uint32_t ssim_window, double* psnr,
                        double* ssim, double* max_abs_err, hipStream_t stream);
+
+/* Lag-1 autocorrelation of the errors e = d_x - d_y (Eq. 4) along the
+ * fastest (last) dimension: the mean and population variance of e over all
+ * points, the lagged moment over every pair of neighbours in a row; 0 when
+ * the errors are constant.  Sums in FP64.  Errors: EINVAL, EDEVICE,
+ * ENOMEM. */
+qoz_status qoz_error_ac(qoz_ctx* ctx, const float* d_x, const float* d_y,
+                        qoz_shape shape, double* ac, hipStream_t stream);
 
 /* Message describing the calling thread's last error ("" if none). */
 const char* qoz_last_error(void);

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqoz.so")
 
 QOZ_OK, QOZ_EINVAL, QOZ_ENOSPACE, QOZ_EFORMAT, QOZ_EDEVICE, QOZ_ENOMEM = range(6)
-TARGETS = {"cr": 0, "psnr": 1, "ssim": 2}
+TARGETS = {"cr": 0, "psnr": 1, "ssim": 2, "ac": 3}
 MAX_LEVELS = 16
 HEADER_BYTES = 200  # stream header (format version 4)
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOSPACE", 3: "EFORMAT",
@@ -77,6 +77,7 @@ def lib():
                                   C.POINTER(dbl), C.POINTER(Params)]
         L.qoz_metrics.argtypes = [vp, vp, vp, Shape, u32, C.POINTER(dbl),
                                   C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.qoz_error_ac.argtypes = [vp, vp, vp, Shape, C.POINTER(dbl), vp]
         L.qoz_last_error.restype = C.c_char_p
         L.qoz_ctx_set_timing.argtypes = [vp, C.c_int]
         L.qoz_ctx_set_timing_mask.argtypes = [vp, C.c_uint64]
@@ -86,7 +87,7 @@ def lib():
                                          C.POINTER(dbl), C.POINTER(dbl)]
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
-                   "qoz_metrics", "qoz_ctx_set_timing",
+                   "qoz_metrics", "qoz_error_ac", "qoz_ctx_set_timing",
                    "qoz_ctx_set_timing_mask",
                    "qoz_ctx_reset_timing", "qoz_ctx_get_timing"):
             getattr(L, fn).restype = C.c_int
@@ -219,6 +220,14 @@ def qoz_metrics(ctx, d_x, d_y, shape, ssim_window, stream, want_ssim=True):
     return ps.value, (ss.value if want_ssim else None), me.value
 
 
+def qoz_error_ac(ctx, d_x, d_y, shape, stream):
+    ac = C.c_double()
+    _check(lib().qoz_error_ac(ctx, C.c_void_p(d_x), C.c_void_p(d_y), shape,
+                              C.byref(ac), C.c_void_p(stream)),
+           "qoz_error_ac")
+    return ac.value
+
+
 def qoz_last_error():
     m = lib().qoz_last_error()
     return m.decode() if m else ""
@@ -334,6 +343,14 @@ class Codec:
         sh = self._field(x)
         return qoz_metrics(self.ctx, x.data_ptr(), y.data_ptr(), sh,
                            ssim_window, self._stream(), want_ssim)
+
+    def error_ac(self, x, y):
+        """Lag-1 autocorrelation of the errors x - y (Eq. 4)."""
+        sh = self._field(x)
+        if self._field(y) is not None and tuple(y.shape) != tuple(x.shape):
+            raise ValueError("x and y must have the same shape")
+        return qoz_error_ac(self.ctx, x.data_ptr(), y.data_ptr(), sh,
+                            self._stream())
 
 
 def rel_to_abs(vmin, vmax, eps):

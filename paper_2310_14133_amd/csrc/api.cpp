@@ -471,4 +471,38 @@ qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
   return QOZ_OK;
 }
 
+qoz_status qoz_error_ac(qoz_ctx* c, const float* d_x, const float* d_y,
+                        qoz_shape shape, double* ac, hipStream_t s) {
+  clear_error();
+  if (!c || !d_x || !d_y || !ac) return fail(QOZ_EINVAL, "NULL argument");
+  int d;
+  uint64_t n[3] = {1, 1, 1};
+  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  QOZ_TRY(set_device(c));
+  const Geo g = make_geo(d, n);
+  const uint32_t len = g.n[2];
+  const uint64_t nrows = (uint64_t)g.n[0] * g.n[1];
+  uint64_t per;
+  const uint32_t np = ac_parts(nrows, len, &per);
+  const size_t bytes = 24 * (size_t)np;
+  QOZ_TRY(ensure_pinned(c, kPinSmall + bytes));
+  QOZ_TRY(ensure(c->partial, bytes));
+  double* p0 = (double*)c->partial.p;
+  double* p1 = p0 + np;
+  PROF(PK_REDUCE, 8.0 * nrows * len,
+       launch_ac_field(d_x, d_y, nrows, len, p0, p1, s));
+  QOZ_TRY(to_host(c, pin(c, kPinSmall), p1, 16 * (size_t)np, s));
+  QOZ_TRY(sync_checked(s));
+  const double* hp = (const double*)pin(c, kPinSmall);
+  double ss = 0.0, lag = 0.0;
+  for (uint32_t i = 0; i < np; ++i) {
+    ss += hp[2 * i];
+    lag += hp[2 * i + 1];
+  }
+  *ac = ac_from_sums(ss, lag, (double)nrows * len,
+                     (double)nrows * (len > 0 ? len - 1 : 0));
+  prof_collect(c);
+  return QOZ_OK;
+}
+
 }  // extern "C"

@@ -1,7 +1,8 @@
 /*
  * Quality metrics of Sec. III on gfx950: value range (for Eq. 1 and the
  * value-range-relative bound), FP64 squared-error and max-error reductions
- * (Eq. 1), and windowed SSIM (Eq. 2-3).
+ * (Eq. 1), windowed SSIM (Eq. 2-3) and the error moments of the lag-1
+ * autocorrelation (Eq. 4).
  *
  * Reductions write one partial per workgroup in a fixed assignment; the
  * host adds the partials in index order, so results are identical from run
@@ -14,6 +15,7 @@
  * (row, column) plane and streams through a range of planes, keeping the
  * last w planes of 2D window sums in an LDS ring.
  */
+#include "qoz_device.h"
 #include "qoz_internal.h"
 
 namespace qoz {
@@ -98,6 +100,113 @@ void launch_range(const float* x, uint64_t n, float* part_min,
                   hipStream_t s) {
   hipLaunchKernelGGL(k_range, dim3(nparts), dim3(kRedThreads), 0, s, x, n,
                      part_min, part_max, status);
+}
+
+/* Error moments of the lag-1 autocorrelation (Eq. 4) over cnt points of
+ * rows of len values starting at x, y, in two passes as the definition
+ * reads.  Pass 0: out[0] = sum e.  Pass 1, with the mean mu of e over the
+ * whole set: out[0] = sum (e - mu)^2, out[1] = sum over the pairs of
+ * neighbours in a row of (e_i - mu)(e_(i+1) - mu). */
+__device__ void ac_moments(const float* __restrict__ x,
+                           const float* __restrict__ y, uint32_t cnt,
+                           uint32_t len, int pass, double mu, double* out) {
+  __shared__ double red[2][kRedThreads / 64];
+  const FastDiv fl(len, cnt);
+  double m0 = 0.0, m1 = 0.0;
+  for (uint32_t t = threadIdx.x; t < cnt; t += kRedThreads) {
+    const double e = (double)x[t] - (double)y[t];
+    if (pass == 0) {
+      m0 += e;
+      continue;
+    }
+    const double d = e - mu;
+    m0 += d * d;
+    const uint32_t col = t - fl.div(t) * len;
+    if (col + 1 < len) m1 += d * (((double)x[t + 1] - (double)y[t + 1]) - mu);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    m0 += __shfl_xor(m0, o, 64);
+    m1 += __shfl_xor(m1, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = m0;
+    red[1][threadIdx.x >> 6] = m1;
+  }
+  __syncthreads();
+  if (threadIdx.x < (pass == 0 ? 1u : 2u)) {
+    double t = 0.0;
+    for (uint32_t w = 0; w < kRedThreads / 64; ++w) t += red[threadIdx.x][w];
+    out[threadIdx.x] = t;
+  }
+}
+
+/* mean of a set from its pass-0 partials p[0..np) over n points */
+__device__ __forceinline__ double ac_mean(const double* __restrict__ p,
+                                          uint32_t np, double n) {
+  double s = 0.0;
+  for (uint32_t i = 0; i < np; ++i) s += p[i];
+  return s / n;
+}
+
+/* the field: workgroup w takes rows [w rows_per_wg, +rows_per_wg); pass 1
+ * reads the pass-0 partials p0 of all nparts workgroups */
+__global__ __launch_bounds__(kRedThreads) void k_ac_field(
+    const float* __restrict__ x, const float* __restrict__ y, uint64_t nrows,
+    uint32_t len, uint64_t rows_per_wg, int pass, const double* p0,
+    double* part) {
+  const uint64_t r0 = (uint64_t)blockIdx.x * rows_per_wg;
+  const uint64_t r1 = r0 + rows_per_wg < nrows ? r0 + rows_per_wg : nrows;
+  const uint32_t cnt = r0 < r1 ? (uint32_t)((r1 - r0) * len) : 0u;
+  const double mu =
+      pass == 0 ? 0.0 : ac_mean(p0, gridDim.x, (double)nrows * (double)len);
+  ac_moments(x + r0 * len, y + r0 * len, cnt, len, pass, mu,
+             part + (pass == 0 ? 1 : 2) * (uint64_t)blockIdx.x);
+}
+
+uint32_t ac_parts(uint64_t nrows, uint32_t len, uint64_t* rows_per_wg) {
+  uint64_t parts = nrows < 2048 ? nrows : 2048;
+  if (parts < 1) parts = 1;
+  uint64_t per = (nrows + parts - 1) / parts;
+  /* a workgroup's points must index in 32 bits */
+  const uint64_t cap = (1ull << 31) / (len ? len : 1);
+  if (per > cap) per = cap;
+  if (per < 1) per = 1;
+  *rows_per_wg = per;
+  return (uint32_t)((nrows + per - 1) / per);
+}
+
+void launch_ac_field(const float* x, const float* y, uint64_t nrows,
+                     uint32_t len, double* p0, double* p1, hipStream_t s) {
+  uint64_t per;
+  const uint32_t parts = ac_parts(nrows, len, &per);
+  hipLaunchKernelGGL(k_ac_field, dim3(parts), dim3(kRedThreads), 0, s, x, y,
+                     nrows, len, per, 0, (const double*)nullptr, p0);
+  hipLaunchKernelGGL(k_ac_field, dim3(parts), dim3(kRedThreads), 0, s, x, y,
+                     nrows, len, per, 1, (const double*)p0, p1);
+}
+
+/* the tuner's items: block blockIdx.y of xs against trial blockIdx.x's
+ * reconstruction in wt (stride `size` floats per item); the mean of pass 1
+ * is that of the trial's nb blocks together */
+__global__ __launch_bounds__(kRedThreads) void k_ac_items(
+    const float* __restrict__ xs, const float* __restrict__ wt, uint32_t nb,
+    uint32_t size, uint32_t len, int pass, const double* p0, double* part) {
+  const uint64_t item = (uint64_t)blockIdx.x * nb + blockIdx.y;
+  const double mu =
+      pass == 0 ? 0.0
+                : ac_mean(p0 + (uint64_t)blockIdx.x * nb, nb,
+                          (double)nb * (double)size);
+  ac_moments(xs + (uint64_t)blockIdx.y * size, wt + item * size, size, len,
+             pass, mu, part + (pass == 0 ? 1 : 2) * item);
+}
+
+void launch_ac_items(const float* xs, const float* wt, uint32_t ntrial,
+                     uint32_t nb, uint32_t size, uint32_t len, double* p0,
+                     double* p1, hipStream_t s) {
+  hipLaunchKernelGGL(k_ac_items, dim3(ntrial, nb), dim3(kRedThreads), 0, s,
+                     xs, wt, nb, size, len, 0, (const double*)nullptr, p0);
+  hipLaunchKernelGGL(k_ac_items, dim3(ntrial, nb), dim3(kRedThreads), 0, s,
+                     xs, wt, nb, size, len, 1, (const double*)p0, p1);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_sse_max(

@@ -347,6 +347,21 @@ void launch_sse_max(const float* x, const float* y, uint64_t n,
                     double* part_sse, double* part_max, uint32_t nparts,
                     hipStream_t s);
 uint32_t sse_parts(uint64_t n);
+/* lag-1 error autocorrelation (Eq. 4): pass-0 partials p0 hold sum e (one
+ * double per part), pass-1 partials p1 the centred sum of squares and the
+ * centred lagged sum (two per part) */
+uint32_t ac_parts(uint64_t nrows, uint32_t len, uint64_t* rows_per_wg);
+void launch_ac_field(const float* x, const float* y, uint64_t nrows,
+                     uint32_t len, double* p0, double* p1, hipStream_t s);
+void launch_ac_items(const float* xs, const float* wt, uint32_t ntrial,
+                     uint32_t nb, uint32_t size, uint32_t len, double* p0,
+                     double* p1, hipStream_t s);
+/* AC from the summed centred moments: n points, p neighbour pairs */
+inline double ac_from_sums(double ss, double lag, double n, double p) {
+  const double var = ss / n;
+  if (!(var > 0.0) || !(p > 0.0)) return 0.0;
+  return (lag / p) / var;
+}
 /* SSIM sums over a batch of equally shaped fields */
 struct SsimJob {
   uint32_t P, Rn, Cn;  /* field extents (2D: P = 1) */

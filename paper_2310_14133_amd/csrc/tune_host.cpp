@@ -70,7 +70,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                                hipStream_t s) {
   clear_error();
   if (!c || !d_x || !out) return fail(QOZ_EINVAL, "NULL argument");
-  if (target < QOZ_TARGET_CR || target > QOZ_TARGET_SSIM)
+  if (target < QOZ_TARGET_CR || target > QOZ_TARGET_AC)
     return fail(QOZ_EINVAL, "bad target");
   if (!(e > 0.0) || !std::isfinite(e))
     return fail(QOZ_EINVAL, "error bound must be finite and > 0");
@@ -188,6 +188,10 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     sj.batch = max_trials * bg.nb;
     sj.x_mod = bg.nb;
     ssim_np = ssim_parts(sj);
+    QOZ_TRY(ensure(c->ssim_part, 8 * ssim_np));
+  } else if (target == QOZ_TARGET_AC) {
+    /* AC moments: one pass-0 and two pass-1 doubles per (trial, block) */
+    ssim_np = 3 * (uint64_t)max_trials * bg.nb;
     QOZ_TRY(ensure(c->ssim_part, 8 * ssim_np));
   }
   const size_t pin_need = kPinTune + 4 * (size_t)kNSym * max_trials +
@@ -355,7 +359,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   {
     hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
     launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun,
-                 target == QOZ_TARGET_SSIM, s);
+                 target == QOZ_TARGET_SSIM || target == QOZ_TARGET_AC, s);
     prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ntrial);
   }
   if (target == QOZ_TARGET_SSIM) {
@@ -367,6 +371,13 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
     prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
     QOZ_TRY(to_host(c, h_ssim, c->ssim_part.p, 8 * ssim_np, s));
+  } else if (target == QOZ_TARGET_AC) {
+    double* p0 = (double*)c->ssim_part.p;
+    double* p1 = p0 + (size_t)ntrial * bg.nb;
+    hipEvent_t ev = prof_begin(c, s, PK_REDUCE);
+    launch_ac_items(xs, wt, ntrial, bg.nb, bg.size, bg.g.n[2], p0, p1, s);
+    prof_end(c, s, ev, PK_REDUCE, 16.0 * bsz * ntrial);
+    QOZ_TRY(to_host(c, h_ssim, p1, 16 * (size_t)ntrial * bg.nb, s));
   }
   /* used symbols of every trial histogram, sorted on the device */
   QOZ_TRY(ensure(c->hsort, 8 * (size_t)(kSortCap + 1) * ntrial));
@@ -411,6 +422,16 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       for (uint64_t q = 0; q < per_item * bg.nb; ++q)
         sum += h_ssim[(uint64_t)t * bg.nb * per_item + q];
       M[t] = sum / nwin;
+    } else if (target == QOZ_TARGET_AC) {
+      /* the blocks' rows together; errors nearest uncorrelated are best */
+      double ss = 0.0, lag = 0.0;
+      for (uint32_t k = 0; k < bg.nb; ++k) {
+        const size_t it = 2 * ((size_t)t * bg.nb + k);
+        ss += h_ssim[it];
+        lag += h_ssim[it + 1];
+      }
+      const double len = (double)bg.g.n[2];
+      M[t] = -std::fabs(ac_from_sums(ss, lag, npts, npts / len * (len - 1)));
     }
   }
   int inc = 0;

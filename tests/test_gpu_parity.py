@@ -180,6 +180,31 @@ def test_metrics_parity(codec, ref):
         assert me == mr
 
 
+def test_error_ac_parity(codec, ref):
+    # several rows per workgroup (3000 rows), rows of two points, errors
+    # with and without lag-1 structure, and a real reconstruction
+    rng = np.random.default_rng(4)
+    cases = []
+    for shape in [(200, 150), (40, 50, 60), (5, 30), (3000, 20), (64, 2),
+                  (2, 333)]:
+        x = fields.grf(shape, 16) if min(shape) > 2 else \
+            rng.normal(size=shape).astype(np.float32)
+        white = rng.normal(0, 1e-2, shape)
+        smooth = np.cumsum(white, axis=-1) * 0.1
+        cases.append((x, (x + white).astype(np.float32)))
+        cases.append((x, (x + smooth).astype(np.float32)))
+    x = fields.bumps_and_waves(128, 5)
+    e = 1e-2 * (float(x.max()) - float(x.min()))
+    p = ref.make_params(2, "cubic", (0, 1), 1.0, 1.0)
+    cases.append((x, ref.decompress(ref.compress(x, e, p))))
+    cases.append((x, x.copy()))  # no error at all: AC = 0
+    for x, y in cases:
+        print(f"error_ac shape={x.shape}", flush=True)
+        g = codec.error_ac(to_dev(x), to_dev(np.ascontiguousarray(y)))
+        r = ref.error_ac(x, y)
+        assert abs(g - r) <= 1e-9, (x.shape, g, r)
+
+
 def near_tie(vals, chosen, rel=1e-9):
     """Another candidate within `rel` of the chosen one but not equal to it.
     Exact ties (identical predictions, e.g. linear and cubic where only two
@@ -205,6 +230,10 @@ TUNE_CASES = [
      dict(block=8, sample_rate=0.2), "ssim", 1e-2),
     ("3d_default", lambda: fields.grf((96, 100, 90), 35), 0, {}, "psnr",
      1e-3),
+    ("2d_ac", lambda: fields.bumps_and_waves(128, 5), 32,
+     dict(block=32, sample_rate=0.2), "ac", 1e-2),
+    ("3d_ac_all", lambda: fields.grf((36, 36, 36), 34), 8,
+     dict(block=8, sample_rate=0.15, all_orders=1), "ac", 1e-3),
 ]
 
 
@@ -230,7 +259,7 @@ def test_tune_parity(codec, ref, name, make, s, cfgkw, target, rel):
             for l in range(rp.levels))
     if not same:
         Ms = [tr.M[i] for i in range(20)]
-        assert near_tie(Ms, tr.best_pair) or target == "ssim" and \
+        assert near_tie(Ms, tr.best_pair) or target in ("ssim", "ac") and \
             near_tie(Ms, tr.best_pair, 1e-7), \
             (q.params_dict(gp, d), ref.params_to_dict(rp, d))
     # downstream: the GPU's parameters give the oracle's stream
