@@ -152,6 +152,85 @@ qoz_status qoz_metrics(qoz_ctx* ctx, const float* d_x, const float* d_y,
 qoz_status qoz_error_ac(qoz_ctx* ctx, const float* d_x, const float* d_y,
                         qoz_shape shape, double* ac, hipStream_t stream);
 
+/* ---- Learned tuner ------------------------------------------------------
+ * A stand-in for the trial search of Sec. VI: a small network maps
+ * features of the sampled blocks to the search's choices (one interpolation
+ * type for every level, alpha and beta of Eq. 5), with the search itself as
+ * the fallback when the network is unsure.
+ *
+ * Parameters are one float32 blob of QOZ_MLP_NPARAM entries: input shift
+ * mu[32] and scale sg[32] (x = (f - mu) / sg, not trained), then W1[128][32],
+ * b1[128], W2[128][128], b2[128], W3[11][128], b3[11] (row-major, output
+ * index first).  Outputs 0-1 score linear / cubic, 2-6 alpha in {1, 1.25,
+ * 1.5, 1.75, 2}, 7-10 beta in {1.5, 2, 3, 4}.  Products take bfloat16
+ * operands (round to nearest even) with FP32 accumulation; the loss is the
+ * batch mean of the three heads' summed softmax cross-entropies. */
+#define QOZ_MLP_NFEAT 32
+#define QOZ_MLP_HIDDEN 128
+#define QOZ_MLP_NOUT 11
+#define QOZ_MLP_NPARAM 22219
+
+/* Features of a 3D field for the learned tuner: the blocks of b = 32
+ * (33^3 points) sampled as in Sec. VI-A at cfg's rate and stride (rate 0
+ * -> 0.01; cfg->block is ignored), 32 float32 features each (level-wise
+ * linear / cubic residual statistics of the original values, gradient
+ * deciles, block and field value ranges, all relative to abs_eb), and
+ * their mean over the blocks into d_mean[32].  d_block (may be NULL)
+ * receives the per-block rows, *nblocks (may be NULL) their count; with
+ * d_block non-NULL, block_cap is its capacity in rows.  Every dimension
+ * must be >= 33.  Errors: EINVAL (shape, bound, cfg, non-finite input,
+ * block_cap too small), EDEVICE, ENOMEM. */
+qoz_status qoz_learned_features(qoz_ctx* ctx, const float* d_x,
+                                qoz_shape shape, double abs_eb,
+                                const qoz_tune_config* cfg, float* d_mean,
+                                float* d_block, uint64_t block_cap,
+                                uint64_t* nblocks, hipStream_t stream);
+
+/* Logits d_logits[batch][11] of feature rows d_feat[batch][32].
+ * Asynchronous on `stream`.  Errors: EINVAL, EDEVICE, ENOMEM. */
+qoz_status qoz_mlp_forward(qoz_ctx* ctx, const float* d_params,
+                           const float* d_feat, uint32_t batch,
+                           float* d_logits, hipStream_t stream);
+
+/* Gradient of the batch loss with respect to every blob entry (0 for mu
+ * and sg) into d_grad[QOZ_MLP_NPARAM] and the loss into *d_loss (device
+ * double).  The batch is rows d_index[0..batch) of d_feat[n_rows][32] and
+ * d_labels[n_rows][3] (interpolation, alpha index, beta index), or rows
+ * 0..batch-1 when d_index is NULL; rows >= n_rows contribute nothing (the
+ * mean still divides by batch) and labels outside their head's range are
+ * clamped into it.  d_index must hold batch entries.  Asynchronous.
+ * Errors: EINVAL, EDEVICE, ENOMEM. */
+qoz_status qoz_mlp_grad(qoz_ctx* ctx, const float* d_params,
+                        const float* d_feat, const int32_t* d_labels,
+                        const uint32_t* d_index, uint32_t n_rows,
+                        uint32_t batch, float* d_grad, double* d_loss,
+                        hipStream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected at step
+ * t >= 1) of learning rate lr on the trained entries of d_params, with the
+ * moment blobs d_m and d_v (same layout; start at zero), on the batch as in
+ * qoz_mlp_grad.  d_loss (device double, may be NULL) receives the loss
+ * before the step.  Asynchronous.  Errors: EINVAL, EDEVICE, ENOMEM. */
+qoz_status qoz_mlp_train_step(qoz_ctx* ctx, float* d_params, float* d_m,
+                              float* d_v, const float* d_feat,
+                              const int32_t* d_labels, const uint32_t* d_index,
+                              uint32_t n_rows, uint32_t batch, float lr,
+                              uint32_t t, double* d_loss, hipStream_t stream);
+
+/* Learned tuning: features of d_x, one forward pass, and per head the class
+ * of highest score.  When the smallest of the three heads' softmax
+ * probabilities is below min_confidence, or the field is not 3D with every
+ * dimension >= 33, the online tuner (qoz_tune with `fallback_target` and
+ * cfg) decides instead and *used_fallback (may be NULL) is set to 1, else
+ * 0.  The network's parameters use every level's interpolation type from
+ * its first head and the identity dimension order.  On input
+ * out->anchor_stride selects s.  Errors: as qoz_tune. */
+qoz_status qoz_tune_learned(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
+                            double abs_eb, const float* d_params,
+                            double min_confidence, qoz_target fallback_target,
+                            const qoz_tune_config* cfg, qoz_params* out,
+                            int* used_fallback, hipStream_t stream);
+
 /* Message describing the calling thread's last error ("" if none). */
 const char* qoz_last_error(void);
 

@@ -78,6 +78,17 @@ def lib():
         L.qoz_metrics.argtypes = [vp, vp, vp, Shape, u32, C.POINTER(dbl),
                                   C.POINTER(dbl), C.POINTER(dbl), vp]
         L.qoz_error_ac.argtypes = [vp, vp, vp, Shape, C.POINTER(dbl), vp]
+        L.qoz_learned_features.argtypes = [vp, vp, Shape, dbl,
+                                           C.POINTER(TuneConfig), vp, vp,
+                                           u64, C.POINTER(u64), vp]
+        L.qoz_mlp_forward.argtypes = [vp, vp, vp, u32, vp, vp]
+        L.qoz_mlp_grad.argtypes = [vp, vp, vp, vp, vp, u32, u32, vp, vp, vp]
+        L.qoz_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, u32,
+                                         u32, C.c_float, u32, vp, vp]
+        L.qoz_tune_learned.argtypes = [vp, vp, Shape, dbl, vp, dbl, C.c_int,
+                                       C.POINTER(TuneConfig),
+                                       C.POINTER(Params), C.POINTER(C.c_int),
+                                       vp]
         L.qoz_last_error.restype = C.c_char_p
         L.qoz_ctx_set_timing.argtypes = [vp, C.c_int]
         L.qoz_ctx_set_timing_mask.argtypes = [vp, C.c_uint64]
@@ -87,7 +98,9 @@ def lib():
                                          C.POINTER(dbl), C.POINTER(dbl)]
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
-                   "qoz_metrics", "qoz_error_ac", "qoz_ctx_set_timing",
+                   "qoz_metrics", "qoz_error_ac", "qoz_learned_features",
+                   "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
+                   "qoz_tune_learned", "qoz_ctx_set_timing",
                    "qoz_ctx_set_timing_mask",
                    "qoz_ctx_reset_timing", "qoz_ctx_get_timing"):
             getattr(L, fn).restype = C.c_int
@@ -228,6 +241,62 @@ def qoz_error_ac(ctx, d_x, d_y, shape, stream):
     return ac.value
 
 
+MLP_NFEAT, MLP_NOUT, MLP_NPARAM = 32, 11, 22219
+MLP_HEADS = (2, 5, 4)
+ALPHAS = (1.0, 1.25, 1.5, 1.75, 2.0)
+BETAS = (1.5, 2.0, 3.0, 4.0)
+
+
+def qoz_learned_features(ctx, d_x, shape, abs_eb, cfg, d_mean, d_block,
+                         block_cap, stream):
+    nb = C.c_uint64()
+    _check(lib().qoz_learned_features(
+        ctx, C.c_void_p(d_x), shape, C.c_double(abs_eb),
+        C.byref(cfg) if cfg else None, C.c_void_p(d_mean),
+        C.c_void_p(d_block), C.c_uint64(block_cap), C.byref(nb),
+        C.c_void_p(stream)), "qoz_learned_features")
+    return nb.value
+
+
+def qoz_mlp_forward(ctx, d_params, d_feat, batch, d_logits, stream):
+    _check(lib().qoz_mlp_forward(ctx, C.c_void_p(d_params),
+                                 C.c_void_p(d_feat), C.c_uint32(batch),
+                                 C.c_void_p(d_logits), C.c_void_p(stream)),
+           "qoz_mlp_forward")
+
+
+def qoz_mlp_grad(ctx, d_params, d_feat, d_labels, d_index, n_rows, batch,
+                 d_grad, d_loss, stream):
+    _check(lib().qoz_mlp_grad(ctx, C.c_void_p(d_params), C.c_void_p(d_feat),
+                              C.c_void_p(d_labels), C.c_void_p(d_index),
+                              C.c_uint32(n_rows), C.c_uint32(batch),
+                              C.c_void_p(d_grad), C.c_void_p(d_loss),
+                              C.c_void_p(stream)), "qoz_mlp_grad")
+
+
+def qoz_mlp_train_step(ctx, d_params, d_m, d_v, d_feat, d_labels, d_index,
+                       n_rows, batch, lr, t, d_loss, stream):
+    _check(lib().qoz_mlp_train_step(
+        ctx, C.c_void_p(d_params), C.c_void_p(d_m), C.c_void_p(d_v),
+        C.c_void_p(d_feat), C.c_void_p(d_labels), C.c_void_p(d_index),
+        C.c_uint32(n_rows), C.c_uint32(batch), C.c_float(lr), C.c_uint32(t),
+        C.c_void_p(d_loss), C.c_void_p(stream)), "qoz_mlp_train_step")
+
+
+def qoz_tune_learned(ctx, d_x, shape, abs_eb, d_params, min_confidence,
+                     fallback_target, cfg, params, stream):
+    """params: in (anchor_stride) / out; returns (params, used_fallback)."""
+    fb = C.c_int(0)
+    _check(lib().qoz_tune_learned(ctx, C.c_void_p(d_x), shape,
+                                  C.c_double(abs_eb), C.c_void_p(d_params),
+                                  C.c_double(min_confidence),
+                                  int(fallback_target),
+                                  C.byref(cfg) if cfg else None,
+                                  C.byref(params), C.byref(fb),
+                                  C.c_void_p(stream)), "qoz_tune_learned")
+    return params, bool(fb.value)
+
+
 def qoz_last_error():
     m = lib().qoz_last_error()
     return m.decode() if m else ""
@@ -343,6 +412,93 @@ class Codec:
         sh = self._field(x)
         return qoz_metrics(self.ctx, x.data_ptr(), y.data_ptr(), sh,
                            ssim_window, self._stream(), want_ssim)
+
+    # ---- learned tuner -------------------------------------------------
+    def learned_features(self, x, abs_eb, cfg=None, per_block=False):
+        """Mean block features (32 float32) of a 3D field; with per_block
+        also the (nblocks, 32) rows."""
+        torch = self.torch
+        sh = self._field(x)
+        mean = torch.empty(MLP_NFEAT, dtype=torch.float32, device=self.device)
+        blk = None
+        cap = 0
+        if per_block:
+            cap = 1 << 16
+            blk = torch.empty((cap, MLP_NFEAT), dtype=torch.float32,
+                              device=self.device)
+        nb = qoz_learned_features(self.ctx, x.data_ptr(), sh, abs_eb, cfg,
+                                  mean.data_ptr(),
+                                  blk.data_ptr() if per_block else None,
+                                  cap, self._stream())
+        return (mean, blk[:nb]) if per_block else mean
+
+    def _dev(self, t, dtype, shape=None):
+        torch = self.torch
+        if t.device != self.device or t.dtype != dtype or \
+                not t.is_contiguous() or (shape and tuple(t.shape) != shape):
+            raise ValueError(f"need a contiguous {dtype} tensor on "
+                             f"{self.device}" + (f" of shape {shape}"
+                                                 if shape else ""))
+        return t
+
+    def mlp_forward(self, params, feat):
+        torch = self.torch
+        self._dev(params, torch.float32, (MLP_NPARAM,))
+        feat = self._dev(feat, torch.float32).reshape(-1, MLP_NFEAT)
+        out = torch.empty((feat.shape[0], MLP_NOUT), dtype=torch.float32,
+                          device=self.device)
+        qoz_mlp_forward(self.ctx, params.data_ptr(), feat.data_ptr(),
+                        feat.shape[0], out.data_ptr(), self._stream())
+        return out
+
+    def mlp_grad(self, params, feat, labels, index=None, batch=None):
+        torch = self.torch
+        self._dev(params, torch.float32, (MLP_NPARAM,))
+        self._dev(feat, torch.float32)
+        self._dev(labels, torch.int32, (feat.shape[0], 3))
+        if index is not None:
+            self._dev(index, torch.int32)
+        B = batch or (index.numel() if index is not None else feat.shape[0])
+        if B > (index.numel() if index is not None else feat.shape[0]):
+            raise ValueError("batch larger than the index / feature rows")
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32,
+                           device=self.device)
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        qoz_mlp_grad(self.ctx, params.data_ptr(), feat.data_ptr(),
+                     labels.data_ptr(),
+                     index.data_ptr() if index is not None else None,
+                     feat.shape[0], B, grad.data_ptr(), loss.data_ptr(),
+                     self._stream())
+        return grad, loss
+
+    def mlp_train_step(self, params, m, v, feat, labels, index, lr, t,
+                       loss=None):
+        torch = self.torch
+        for a in (params, m, v):
+            self._dev(a, torch.float32, (MLP_NPARAM,))
+        self._dev(feat, torch.float32)
+        self._dev(labels, torch.int32, (feat.shape[0], 3))
+        if index is not None:
+            self._dev(index, torch.int32)
+        B = index.numel() if index is not None else feat.shape[0]
+        qoz_mlp_train_step(self.ctx, params.data_ptr(), m.data_ptr(),
+                           v.data_ptr(), feat.data_ptr(), labels.data_ptr(),
+                           index.data_ptr() if index is not None else None,
+                           feat.shape[0], B, lr, t,
+                           loss.data_ptr() if loss is not None else None,
+                           self._stream())
+
+    def tune_learned(self, x, abs_eb, params, min_confidence=0.0,
+                     fallback_target="psnr", cfg=None, anchor_stride=0):
+        """Learned tuning; returns (Params, used_fallback)."""
+        sh = self._field(x)
+        self._dev(params, self.torch.float32, (MLP_NPARAM,))
+        p = Params()
+        p.anchor_stride = anchor_stride
+        return qoz_tune_learned(self.ctx, x.data_ptr(), sh, abs_eb,
+                                params.data_ptr(), min_confidence,
+                                TARGETS[fallback_target], cfg, p,
+                                self._stream())
 
     def error_ac(self, x, y):
         """Lag-1 autocorrelation of the errors x - y (Eq. 4)."""

@@ -139,7 +139,8 @@ static const char* kProfNames[PK_COUNT] = {
     "huffman_encode",  "huffman_decode",  "sweep_decomp_level1",
     "sweep_decomp",    "tune_gather",     "tune_alg1",
     "tune_trial",      "ssim",            "reduce",
-    "row_comp_level1", "row_decomp_level1"};
+    "row_comp_level1", "row_decomp_level1", "learned_features",
+    "mlp"};
 
 }  // namespace qoz
 
@@ -177,7 +178,9 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->partial,    &c->tune_x,     &c->tune_wc,
                     &c->tune_wt,    &c->tune_desc,  &c->tune_hist,
                     &c->tune_stats, &c->tune_l1,    &c->ssim_part,
-                    &c->upos,       &c->hsort,      &c->scan};
+                    &c->upos,       &c->hsort,      &c->scan,
+                    &c->feat,       &c->mlp_io,     &c->mlp_part,
+                    &c->mlp_loss};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -1,0 +1,289 @@
+/*
+ * Learned tuner entry points: block features, network forward pass,
+ * gradient and Adam step, and learned tuning with the online tuner of
+ * Sec. VI as the fallback.
+ *
+ * Sampling of the feature blocks follows Sec. VI-A with b = 32: blocks of
+ * 33 points per dimension at origins k*S, S = round(32 r^(-1/3)), every
+ * origin with k*S + 32 <= n - 1.
+ */
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "qoz_internal.h"
+
+namespace qoz {
+
+static const double kAlphaL[5] = {1.0, 1.25, 1.5, 1.75, 2.0};
+static const double kBetaL[4] = {1.5, 2.0, 3.0, 4.0};
+
+static qoz_status learned_origins(int d, const uint64_t n[3],
+                                  const qoz_tune_config* cfg,
+                                  std::vector<uint32_t>* origins) {
+  if (d != 3) return fail(QOZ_EINVAL, "learned features need a 3D field");
+  for (int i = 0; i < 3; ++i)
+    if (n[i] < 33)
+      return fail(QOZ_EINVAL, "learned features need every dimension >= 33");
+  const double r =
+      (cfg && cfg->sample_rate > 0.0) ? cfg->sample_rate : 0.01;
+  if (!(r > 0.0 && r <= 1.0)) return fail(QOZ_EINVAL, "bad sample rate");
+  uint32_t S = (cfg && cfg->sample_stride)
+                   ? cfg->sample_stride
+                   : (uint32_t)std::llround(32.0 * std::pow(r, -1.0 / 3.0));
+  if (S < 1) S = 1;
+  uint64_t m[3];
+  for (int i = 0; i < 3; ++i) {
+    m[i] = 0;
+    while (m[i] * S + 32 <= n[i] - 1) ++m[i];
+  }
+  origins->clear();
+  for (uint64_t a = 0; a < m[0]; ++a)
+    for (uint64_t b = 0; b < m[1]; ++b)
+      for (uint64_t k = 0; k < m[2]; ++k) {
+        origins->push_back((uint32_t)(a * S));
+        origins->push_back((uint32_t)(b * S));
+        origins->push_back((uint32_t)(k * S));
+      }
+  if (origins->size() / 3 > (1u << 20))
+    return fail(QOZ_EINVAL, "too many sampled blocks");
+  return QOZ_OK;
+}
+
+/* Enqueue the range check and the features; the status word is copied to
+ * the pinned staging at *h_status (checked by the caller after a sync). */
+static qoz_status enqueue_features(qoz_ctx* c, const float* d_x, int d,
+                                   const uint64_t n[3], double e,
+                                   const qoz_tune_config* cfg, float* d_mean,
+                                   float* d_block, uint64_t block_cap,
+                                   uint32_t* nb_out, uint32_t** h_status,
+                                   hipStream_t s) {
+  std::vector<uint32_t> org;
+  QOZ_TRY(learned_origins(d, n, cfg, &org));
+  const uint32_t nb = (uint32_t)(org.size() / 3);
+  if (d_block && block_cap < nb)
+    return fail(QOZ_EINVAL, "block feature buffer too small");
+  if (!block_features_fit())
+    return fail(QOZ_EDEVICE, "block features do not fit in LDS");
+  const Geo g = make_geo(d, n);
+  const uint64_t N = (uint64_t)g.n[0] * g.n[1] * g.n[2];
+  const uint32_t rp = range_parts(N);
+  QOZ_TRY(ensure(c->partial, 8 * (size_t)rp + 4 * org.size() + 64));
+  QOZ_TRY(ensure(c->status, 256));
+  if (!d_block) QOZ_TRY(ensure(c->feat, 4 * (size_t)kMlpFeat * nb));
+  /* pinned: status [0, 16), logits [16, 60), origins from 64 */
+  QOZ_TRY(ensure_pinned(c, 4 * org.size() + 4096));
+  float* pmin = (float*)c->partial.p;
+  float* pmax = pmin + rp;
+  uint32_t* dorig = (uint32_t*)(pmax + rp);
+  uint32_t* st = (uint32_t*)c->status.p;
+  uint8_t* hp = (uint8_t*)c->pinned;
+  std::memcpy(hp + 64, org.data(), 4 * org.size());
+  launch_init_status(st, s);
+  {
+    hipEvent_t ev = prof_begin(c, s, PK_CHECK);
+    launch_range(d_x, N, pmin, pmax, st, rp, s);
+    prof_end(c, s, ev, PK_CHECK, 4.0 * N);
+  }
+  QOZ_TRY(to_device(c, dorig, hp + 64, 4 * org.size(), s));
+  {
+    hipEvent_t ev = prof_begin(c, s, PK_LEARN_FEAT);
+    launch_block_features(d_x, g, dorig, nb, pmin, pmax, rp, e,
+                          d_block ? d_block : (float*)c->feat.p, d_mean, s);
+    prof_end(c, s, ev, PK_LEARN_FEAT, 4.0 * 35937.0 * nb);
+  }
+  QOZ_TRY(to_host(c, hp, st, 16, s));
+  *nb_out = nb;
+  *h_status = (uint32_t*)hp;
+  return QOZ_OK;
+}
+
+}  // namespace qoz
+
+using namespace qoz;
+
+extern "C" qoz_status qoz_learned_features(qoz_ctx* c, const float* d_x,
+                                           qoz_shape shape, double e,
+                                           const qoz_tune_config* cfg,
+                                           float* d_mean, float* d_block,
+                                           uint64_t block_cap,
+                                           uint64_t* nblocks, hipStream_t s) {
+  clear_error();
+  if (!c || !d_x || !d_mean) return fail(QOZ_EINVAL, "NULL argument");
+  if (!(e > 0.0) || !std::isfinite(e))
+    return fail(QOZ_EINVAL, "error bound must be finite and > 0");
+  int d;
+  uint64_t n[3] = {1, 1, 1};
+  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  QOZ_TRY(set_device(c));
+  uint32_t nb = 0;
+  uint32_t* hst = nullptr;
+  QOZ_TRY(enqueue_features(c, d_x, d, n, e, cfg, d_mean, d_block, block_cap,
+                           &nb, &hst, s));
+  QOZ_HIP(hipGetLastError());
+  QOZ_HIP(hipStreamSynchronize(s));
+  prof_collect(c);
+  if (hst[0] & kStNonFinite) return fail(QOZ_EINVAL, "input contains NaN or Inf");
+  if (nblocks) *nblocks = nb;
+  return QOZ_OK;
+}
+
+extern "C" qoz_status qoz_mlp_forward(qoz_ctx* c, const float* d_params,
+                                      const float* d_feat, uint32_t batch,
+                                      float* d_logits, hipStream_t s) {
+  clear_error();
+  if (!c || !d_params || !d_feat || !d_logits)
+    return fail(QOZ_EINVAL, "NULL argument");
+  if (batch == 0) return fail(QOZ_EINVAL, "empty batch");
+  QOZ_TRY(set_device(c));
+  if (!mlp_fit()) return fail(QOZ_EDEVICE, "network does not fit in LDS");
+  {
+    hipEvent_t ev = prof_begin(c, s, PK_MLP);
+    launch_mlp_forward(d_params, d_feat, batch, d_logits, s);
+    prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams + 4.0 * 43 * batch);
+  }
+  QOZ_HIP(hipGetLastError());
+  return QOZ_OK;
+}
+
+static qoz_status mlp_backward(qoz_ctx* c, float* P, float* m, float* v,
+                               const float* X, const int32_t* labels,
+                               const uint32_t* index, uint32_t n_rows,
+                               uint32_t B, float* grad, float lr, uint32_t t,
+                               bool adam, double* loss, hipStream_t s) {
+  if (B == 0) return fail(QOZ_EINVAL, "empty batch");
+  if (!mlp_fit()) return fail(QOZ_EDEVICE, "network does not fit in LDS");
+  const uint32_t nw = mlp_tiles(B);
+  QOZ_TRY(ensure(c->mlp_part, 4 * (size_t)kMlpParams * nw));
+  QOZ_TRY(ensure(c->mlp_loss, 8 * (size_t)nw));
+  float* part = (float*)c->mlp_part.p;
+  double* lp = (double*)c->mlp_loss.p;
+  float bc1 = 1.0f, bc2 = 1.0f;
+  if (adam) {
+    bc1 = (float)(1.0 - std::pow((double)kAdamB1, (double)t));
+    bc2 = (float)(1.0 - std::pow((double)kAdamB2, (double)t));
+  }
+  hipEvent_t ev = prof_begin(c, s, PK_MLP);
+  launch_mlp_grad(P, X, labels, index, n_rows, B, part, lp, s);
+  launch_mlp_reduce(part, nw, grad, P, m, v, lr, bc1, bc2, adam, lp, B, loss,
+                    s);
+  prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams * (2.0 * nw + 4.0));
+  QOZ_HIP(hipGetLastError());
+  return QOZ_OK;
+}
+
+extern "C" qoz_status qoz_mlp_grad(qoz_ctx* c, const float* d_params,
+                                   const float* d_feat,
+                                   const int32_t* d_labels,
+                                   const uint32_t* d_index, uint32_t n_rows,
+                                   uint32_t batch, float* d_grad,
+                                   double* d_loss, hipStream_t s) {
+  clear_error();
+  if (!c || !d_params || !d_feat || !d_labels || !d_grad || !d_loss)
+    return fail(QOZ_EINVAL, "NULL argument");
+  QOZ_TRY(set_device(c));
+  return mlp_backward(c, const_cast<float*>(d_params), nullptr, nullptr,
+                      d_feat, d_labels, d_index, n_rows, batch, d_grad, 0.0f,
+                      0, false, d_loss, s);
+}
+
+extern "C" qoz_status qoz_mlp_train_step(
+    qoz_ctx* c, float* d_params, float* d_m, float* d_v, const float* d_feat,
+    const int32_t* d_labels, const uint32_t* d_index, uint32_t n_rows,
+    uint32_t batch, float lr, uint32_t t, double* d_loss, hipStream_t s) {
+  clear_error();
+  if (!c || !d_params || !d_m || !d_v || !d_feat || !d_labels)
+    return fail(QOZ_EINVAL, "NULL argument");
+  if (t < 1) return fail(QOZ_EINVAL, "Adam step must be >= 1");
+  if (!(lr > 0.0f) || !std::isfinite(lr))
+    return fail(QOZ_EINVAL, "learning rate must be finite and > 0");
+  QOZ_TRY(set_device(c));
+  return mlp_backward(c, d_params, d_m, d_v, d_feat, d_labels, d_index,
+                      n_rows, batch, nullptr, lr, t, true, d_loss, s);
+}
+
+extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
+                                       qoz_shape shape, double e,
+                                       const float* d_params,
+                                       double min_confidence,
+                                       qoz_target fallback_target,
+                                       const qoz_tune_config* cfg,
+                                       qoz_params* out, int* used_fallback,
+                                       hipStream_t s) {
+  clear_error();
+  if (!c || !d_x || !d_params || !out) return fail(QOZ_EINVAL, "NULL argument");
+  if (!(e > 0.0) || !std::isfinite(e))
+    return fail(QOZ_EINVAL, "error bound must be finite and > 0");
+  if (!(min_confidence >= 0.0 && min_confidence <= 1.0))
+    return fail(QOZ_EINVAL, "min_confidence must be in [0, 1]");
+  int d;
+  uint64_t n[3] = {1, 1, 1};
+  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  QOZ_TRY(set_device(c));
+  const uint32_t sa = out->anchor_stride ? out->anchor_stride
+                                         : (d == 2 ? 64u : 32u);
+  if (sa < 2 || (sa & (sa - 1))) return fail(QOZ_EINVAL, "bad anchor stride");
+  uint32_t L = 0;
+  while ((2u << L) <= sa) ++L;
+  if (L > QOZ_MAX_LEVELS) return fail(QOZ_EINVAL, "anchor stride too large");
+
+  bool supported = d == 3 && n[0] >= 33 && n[1] >= 33 && n[2] >= 33;
+  double conf = 0.0;
+  uint32_t pick[3] = {0, 0, 0};
+  if (supported) {
+    if (!mlp_fit()) return fail(QOZ_EDEVICE, "network does not fit in LDS");
+    QOZ_TRY(ensure(c->mlp_io, 4 * 64));
+    float* d_mean = (float*)c->mlp_io.p;
+    float* d_logit = d_mean + kMlpFeat;
+    uint32_t nb = 0;
+    uint32_t* hst = nullptr;
+    QOZ_TRY(enqueue_features(c, d_x, d, n, e, cfg, d_mean, nullptr, 0, &nb,
+                             &hst, s));
+    {
+      hipEvent_t ev = prof_begin(c, s, PK_MLP);
+      launch_mlp_forward(d_params, d_mean, 1, d_logit, s);
+      prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams);
+    }
+    float* hz = (float*)((uint8_t*)hst + 16); /* status is 16 bytes */
+    QOZ_TRY(to_host(c, hz, d_logit, 4 * kMlpOut, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    prof_collect(c);
+    if (hst[0] & kStNonFinite)
+      return fail(QOZ_EINVAL, "input contains NaN or Inf");
+    /* per head: first maximum and its softmax probability */
+    const uint32_t heads[3] = {kHeadInterp, kHeadAlpha, kHeadBeta};
+    conf = 1.0;
+    uint32_t o = 0;
+    for (int h = 0; h < 3; ++h) {
+      uint32_t best = 0;
+      for (uint32_t k = 1; k < heads[h]; ++k)
+        if (hz[o + k] > hz[o + best]) best = k;
+      double sum = 0.0;
+      for (uint32_t k = 0; k < heads[h]; ++k)
+        sum += std::exp((double)hz[o + k] - (double)hz[o + best]);
+      const double p = 1.0 / sum;
+      if (!(p >= 0.0)) conf = 0.0; /* NaN logits: untrusted */
+      conf = std::fmin(conf, p);
+      pick[h] = best;
+      o += heads[h];
+    }
+  }
+  if (!supported || conf < min_confidence) {
+    if (used_fallback) *used_fallback = 1;
+    return qoz_tune(c, d_x, shape, e, fallback_target, cfg, out, s);
+  }
+  qoz_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.anchor_stride = sa;
+  p.levels = L;
+  for (uint32_t l = 0; l < L; ++l) {
+    p.interp[l] = (uint8_t)pick[0];
+    for (int j = 0; j < 3; ++j) p.order[l][j] = (uint8_t)(j < d ? j : 0);
+  }
+  p.alpha = kAlphaL[pick[1]];
+  p.beta = kBetaL[pick[2]];
+  *out = p;
+  if (used_fallback) *used_fallback = 0;
+  return QOZ_OK;
+}

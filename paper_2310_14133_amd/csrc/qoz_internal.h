@@ -174,6 +174,8 @@ enum ProfKind {
   PK_REDUCE,
   PK_ROW_COMP_L1,
   PK_ROW_DEC_L1,
+  PK_LEARN_FEAT,
+  PK_MLP,
   PK_COUNT
 };
 
@@ -197,7 +199,7 @@ struct qoz_ctx {
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
-      hsort, scan;
+      hsort, scan, feat, mlp_io, mlp_part, mlp_loss;
   /* pinned host staging */
   void* pinned = nullptr;
   void* pinned_dev = nullptr; /* its device address */
@@ -347,6 +349,40 @@ void launch_sse_max(const float* x, const float* y, uint64_t n,
                     double* part_sse, double* part_max, uint32_t nparts,
                     hipStream_t s);
 uint32_t sse_parts(uint64_t n);
+/* learned tuner: network shape and parameter blob offsets */
+constexpr uint32_t kMlpFeat = QOZ_MLP_NFEAT;
+constexpr uint32_t kMlpHidden = QOZ_MLP_HIDDEN;
+constexpr uint32_t kMlpOut = QOZ_MLP_NOUT;
+constexpr uint32_t kHeadInterp = 2, kHeadAlpha = 5, kHeadBeta = 4;
+constexpr uint32_t kOffMu = 0;
+constexpr uint32_t kOffSg = kOffMu + kMlpFeat;
+constexpr uint32_t kOffW1 = kOffSg + kMlpFeat;
+constexpr uint32_t kOffB1 = kOffW1 + kMlpHidden * kMlpFeat;
+constexpr uint32_t kOffW2 = kOffB1 + kMlpHidden;
+constexpr uint32_t kOffB2 = kOffW2 + kMlpHidden * kMlpHidden;
+constexpr uint32_t kOffW3 = kOffB2 + kMlpHidden;
+constexpr uint32_t kOffB3 = kOffW3 + kMlpOut * kMlpHidden;
+constexpr uint32_t kMlpParams = kOffB3 + kMlpOut;
+static_assert(kMlpParams == QOZ_MLP_NPARAM, "parameter blob size");
+static_assert(kHeadInterp + kHeadAlpha + kHeadBeta == kMlpOut, "heads");
+constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
+bool block_features_fit();
+void launch_block_features(const float* x, const Geo& g,
+                           const uint32_t* origins, uint32_t nb,
+                           const float* pmin, const float* pmax, uint32_t rp,
+                           double e, float* feat, float* mean, hipStream_t s);
+uint32_t mlp_tiles(uint32_t B);
+bool mlp_fit();
+void launch_mlp_forward(const float* P, const float* X, uint32_t B,
+                        float* logits, hipStream_t s);
+void launch_mlp_grad(const float* P, const float* X, const int32_t* labels,
+                     const uint32_t* index, uint32_t n_rows, uint32_t B,
+                     float* part, double* loss_part, hipStream_t s);
+void launch_mlp_reduce(const float* part, uint32_t nw, float* grad, float* P,
+                       float* m, float* v, float lr, float bc1, float bc2,
+                       bool adam, const double* loss_part, uint32_t B,
+                       double* loss, hipStream_t s);
+
 /* lag-1 error autocorrelation (Eq. 4): pass-0 partials p0 hold sum e (one
  * double per part), pass-1 partials p1 the centred sum of squares and the
  * centred lagged sum (two per part) */

@@ -1,0 +1,251 @@
+"""GPU parity of the learned tuner's kernels against the oracle
+(oracle/ref_learned.py), through the C ABI.
+
+Features: the residuals and gradients that decide them are float32 in the
+same order on both sides and the deciles are selected elements, so only
+the FP64 sums differ in order: 1e-6 relative.  Network: bf16 operands on
+both sides, FP32 accumulation on the GPU against FP64 in the oracle; a
+bf16 rounding of an activation can land on the other side of a tie, which
+moves one product by up to 2^-8 of itself, so logits and gradients are
+compared with a tolerance on the whole tensor (norm) and a looser one per
+element."""
+import numpy as np
+import pytest
+
+from paper_2310_14133_amd import fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def codec():
+    import torch
+    import paper_2310_14133_amd as q
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = q.Codec(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def rl():
+    from oracle import ref_learned
+    return ref_learned
+
+
+def to_dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def random_blob(rl, seed):
+    rng = np.random.default_rng(seed)
+    P = rl.init_params(seed, mu=rng.normal(0, 1, 32).astype(np.float32),
+                       sg=rng.uniform(0.5, 2, 32).astype(np.float32))
+    P[rl.OFF_B1:rl.OFF_W2] = rng.normal(0, 0.1, 128)
+    P[rl.OFF_B2:rl.OFF_W3] = rng.normal(0, 0.1, 128)
+    P[rl.OFF_B3:] = rng.normal(0, 0.1, 11)
+    return P
+
+
+FEATURE_CASES = [
+    ("grf_multi_block", lambda: fields.grf((70, 66, 80), 7), 1e-3, 0.5),
+    ("single_block", lambda: fields.grf((33, 33, 33), 8), 1e-2, 0.0),
+    ("lognormal_ragged", lambda: fields.grf((40, 129, 35), 9,
+                                            log_normal=True), 1e-4, 0.3),
+    ("multiscale", lambda: fields.multiscale((64, 72, 96), 10), 1e-3, 0.2),
+]
+
+
+@pytest.mark.parametrize("name,make,rel,rate", FEATURE_CASES)
+def test_features_parity(codec, rl, name, make, rel, rate):
+    import paper_2310_14133_amd as q
+    from oracle import ref
+    x = make()
+    e = rel * (float(x.max()) - float(x.min()))
+    print(f"features case {name} shape={x.shape}", flush=True)
+    plan = ref.sample_plan(x.shape, cfg=ref.tune_config(
+        block=32, sample_rate=rate if rate else 0.01))
+    assert plan["block_dims"] == (33, 33, 33)
+    per_r, mean_r = rl.field_features(x, e, plan["origins"])
+    mean_g, per_g = codec.learned_features(
+        to_dev(x), e, q.make_tune_config(sample_rate=rate), per_block=True)
+    per_g = per_g.cpu().numpy()
+    assert per_g.shape == per_r.shape
+    assert np.allclose(per_g, per_r, rtol=1e-6, atol=1e-6), \
+        np.abs(per_g - per_r).max()
+    assert np.allclose(mean_g.cpu().numpy(), mean_r, rtol=1e-6, atol=1e-6)
+
+
+def test_features_errors(codec):
+    import torch
+    import paper_2310_14133_amd as q
+    with pytest.raises(q.QozError):
+        codec.learned_features(to_dev(fields.grf((64, 64), 1)), 1e-3)
+    with pytest.raises(q.QozError):
+        codec.learned_features(to_dev(fields.grf((64, 32, 64), 1)), 1e-3)
+    x = fields.grf((40, 40, 40), 2)
+    x[3, 4, 5] = np.nan
+    with pytest.raises(q.QozError) as err:
+        codec.learned_features(to_dev(x), 1e-3)
+    assert err.value.status == q.QOZ_EINVAL
+    torch.cuda.synchronize()
+
+
+def close_tensor(g, r, norm_tol, elem_tol):
+    g = np.asarray(g, np.float64)
+    r = np.asarray(r, np.float64)
+    assert np.linalg.norm(g - r) <= norm_tol * max(np.linalg.norm(r), 1e-30), \
+        (np.linalg.norm(g - r), np.linalg.norm(r))
+    scale = np.abs(r).max()
+    assert np.abs(g - r).max() <= elem_tol * scale, \
+        (np.abs(g - r).max(), scale)
+
+
+@pytest.mark.parametrize("B", [1, 5, 64, 130])
+def test_forward_parity(codec, rl, B):
+    rng = np.random.default_rng(B)
+    P = random_blob(rl, 11 + B)
+    feat = rng.normal(0, 2, (B, 32)).astype(np.float32)
+    print(f"forward batch={B}", flush=True)
+    zg = codec.mlp_forward(to_dev(P), to_dev(feat)).cpu().numpy()
+    zr, _ = rl.forward(P, feat)
+    assert zg.shape == (B, 11)
+    close_tensor(zg, zr, 2e-3, 1e-2)
+    # most entries agree to FP32 accumulation error
+    assert np.median(np.abs(zg - zr)) <= 1e-5 * max(np.abs(zr).max(), 1)
+
+
+@pytest.mark.parametrize("B,nrows,use_index", [(100, 100, False),
+                                               (64, 300, True),
+                                               (7, 7, False)])
+def test_gradient_parity(codec, rl, B, nrows, use_index):
+    import torch
+    rng = np.random.default_rng(B + nrows)
+    P = random_blob(rl, 3 + B)
+    feat = rng.normal(0, 2, (nrows, 32)).astype(np.float32)
+    lab = np.stack([rng.integers(0, k, nrows) for k in rl.HEADS],
+                   axis=1).astype(np.int32)
+    idx = rng.permutation(nrows)[:B].astype(np.int32) if use_index else None
+    print(f"gradient batch={B} rows={nrows}", flush=True)
+    g, loss = codec.mlp_grad(to_dev(P), to_dev(feat), to_dev(lab),
+                             to_dev(idx) if use_index else None, batch=B)
+    torch.cuda.synchronize()
+    rows = idx if use_index else np.arange(B)
+    lr_, gr = rl.loss_and_grad(P, feat[rows], lab[rows])
+    assert abs(float(loss.item()) - lr_) <= 1e-5 * abs(lr_)
+    g = g.cpu().numpy()
+    assert np.all(g[:rl.OFF_W1] == 0.0)
+    for lo, hi in [(rl.OFF_W1, rl.OFF_B1), (rl.OFF_B1, rl.OFF_W2),
+                   (rl.OFF_W2, rl.OFF_B2), (rl.OFF_B2, rl.OFF_W3),
+                   (rl.OFF_W3, rl.OFF_B3), (rl.OFF_B3, rl.NPARAM)]:
+        close_tensor(g[lo:hi], gr[lo:hi], 5e-3, 3e-2)
+
+
+def test_adam_step_parity(codec, rl):
+    import torch
+    rng = np.random.default_rng(21)
+    P = random_blob(rl, 21)
+    feat = rng.normal(0, 2, (96, 32)).astype(np.float32)
+    lab = np.stack([rng.integers(0, k, 96) for k in rl.HEADS],
+                   axis=1).astype(np.int32)
+    lr = 1e-3
+    Pd = to_dev(P)
+    m = torch.zeros_like(Pd)
+    v = torch.zeros_like(Pd)
+    loss = torch.zeros(1, dtype=torch.float64, device=Pd.device)
+    codec.mlp_train_step(Pd, m, v, to_dev(feat), to_dev(lab), None, lr, 1,
+                         loss)
+    torch.cuda.synchronize()
+    l_r, g_r = rl.loss_and_grad(P, feat, lab)
+    P1_r, m_r, v_r = rl.adam(P, np.zeros(rl.NPARAM), np.zeros(rl.NPARAM),
+                             g_r, lr, 1)
+    assert abs(float(loss.item()) - l_r) <= 1e-5 * abs(l_r)
+    P1 = Pd.cpu().numpy().astype(np.float64)
+    s = slice(rl.OFF_W1, None)
+    close_tensor(m.cpu().numpy()[s], m_r[s], 5e-3, 3e-2)
+    assert np.array_equal(P1[:rl.OFF_W1], P[:rl.OFF_W1].astype(np.float64))
+    # every step is at most lr; where the gradient is well above its own
+    # error the step equals the oracle's
+    step = np.abs(P1[s] - P[s].astype(np.float64))
+    assert np.all(step <= lr * (1 + 1e-5) + 1e-7 * np.abs(P[s]))
+    big = np.abs(g_r[s]) >= 0.05 * np.abs(g_r[s]).max()
+    assert big.sum() > 100
+    assert np.allclose(P1[s][big], P1_r[s][big], rtol=0,
+                       atol=2e-3 * lr + 1e-7)
+
+
+def test_training_fits_separable_toy(codec, rl):
+    import torch
+    rng = np.random.default_rng(6)
+    feat = rng.normal(0, 1, (256, 32)).astype(np.float32)
+    lab = np.stack([(feat[:, 0] > 0), (feat[:, 1] > 0) * 4,
+                    (feat[:, 2] > 0) * 3], axis=1).astype(np.int32)
+    P = to_dev(rl.init_params(6))
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    F, Lb = to_dev(feat), to_dev(lab)
+    loss = torch.zeros(1, dtype=torch.float64, device=P.device)
+    codec.mlp_train_step(P, m, v, F, Lb, None, 3e-3, 1, loss)
+    l0 = float(loss.item())
+    for t in range(2, 301):
+        idx = to_dev(rng.permutation(256)[:64].astype(np.int32))
+        codec.mlp_train_step(P, m, v, F, Lb, idx, 3e-3, t)
+    _, lend = codec.mlp_grad(P, F, Lb)
+    assert float(lend.item()) < 0.1 * l0, (float(lend.item()), l0)
+
+
+def test_tune_learned_follows_the_network(codec, rl):
+    import paper_2310_14133_amd as q
+    from oracle import ref
+    x = fields.grf((70, 66, 80), 12)
+    e = 1e-3 * (float(x.max()) - float(x.min()))
+    cfg_r = ref.tune_config(block=32, sample_rate=0.5)
+    cfg_g = q.make_tune_config(sample_rate=0.5)
+    plan = ref.sample_plan(x.shape, cfg=cfg_r)
+    _, mean_r = rl.field_features(x, e, plan["origins"])
+    checked = 0
+    for seed in range(6):
+        P = random_blob(rl, 40 + seed)
+        z, _ = rl.forward(P, mean_r.reshape(1, 32))
+        z = z[0]
+        o, near = 0, False
+        for k in rl.HEADS:
+            top = np.sort(z[o:o + k])[::-1]
+            near |= top[0] - top[1] < 1e-2 * max(1.0, abs(top[0]))
+            o += k
+        if near:
+            continue
+        pred = rl.predict(P, mean_r)
+        gp, fb = codec.tune_learned(to_dev(x), e, to_dev(P), 0.0, "psnr",
+                                    cfg_g)
+        assert not fb
+        assert gp.interp[0] == pred[0][0]
+        assert all(gp.interp[l] == pred[0][0] for l in range(gp.levels))
+        assert all(tuple(gp.order[l][j] for j in range(3)) == (0, 1, 2)
+                   for l in range(gp.levels))
+        assert gp.alpha == q.ALPHAS[pred[1][0]]
+        assert gp.beta == q.BETAS[pred[2][0]]
+        checked += 1
+    assert checked >= 3
+
+
+def test_tune_learned_fallback(codec, rl):
+    import paper_2310_14133_amd as q
+    P = to_dev(random_blob(rl, 50))
+    x = fields.grf((48, 40, 44), 13)
+    e = 1e-3 * (float(x.max()) - float(x.min()))
+    cfg = q.make_tune_config(block=8, sample_rate=0.2)
+    # confidence 1 can never be met: the online tuner decides
+    gp, fb = codec.tune_learned(to_dev(x), e, P, 1.0, "psnr", cfg)
+    assert fb
+    tp = codec.tune(to_dev(x), e, "psnr", cfg)
+    assert q.params_dict(gp, 3) == q.params_dict(tp, 3)
+    # 2D fields are outside the network's domain
+    x2 = fields.bumps_and_waves(96, 3)
+    e2 = 1e-3 * (float(x2.max()) - float(x2.min()))
+    gp2, fb2 = codec.tune_learned(to_dev(x2), e2, P, 0.0, "cr", None)
+    assert fb2
+    assert q.params_dict(gp2, 2) == q.params_dict(
+        codec.tune(to_dev(x2), e2, "cr", None), 2)
