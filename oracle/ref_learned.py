@@ -33,7 +33,9 @@ e the absolute bound, all logs base 2:
       g2 = (dx*dx + dy*dy) + dz*dz (float32) at points with all
       coordinates in [0, 31];
   f[30] = log(1 + (max - min of the block) / e);
-  f[31] = log(1 + (max - min of the field) / e).
+  f[31] = log(1 + (max - min over all sampled blocks together) / e), so
+      that the features read the sampled blocks only, as the search of
+      Sec. VI-A does.
 The field's features are the mean over its sampled blocks (FP64 sum in
 block order, then float32).
 """
@@ -114,13 +116,14 @@ def block_features(blk, e, vrange):
 def field_features(x, e, origins):
     """Per-block features and their mean (float32) for the blocks of a 3D
     float32 field at the given origins (Sec. VI-A sampling)."""
-    vrange = float(x.max()) - float(x.min())
-    rows = []
+    blocks = []
     for o in origins:
         i, j, k = (int(v) for v in o)
-        blk = np.ascontiguousarray(
-            x[i:i + BLOCK + 1, j:j + BLOCK + 1, k:k + BLOCK + 1])
-        rows.append(block_features(blk, e, vrange))
+        blocks.append(np.ascontiguousarray(
+            x[i:i + BLOCK + 1, j:j + BLOCK + 1, k:k + BLOCK + 1]))
+    vrange = (max(float(b.max()) for b in blocks) -
+              min(float(b.min()) for b in blocks))
+    rows = [block_features(b, e, vrange) for b in blocks]
     per = np.stack(rows)
     acc = np.zeros(NFEAT, np.float64)
     for r in per:

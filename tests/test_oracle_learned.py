@@ -94,12 +94,14 @@ def test_field_features_mean_over_sampled_blocks():
     per, mean = rl.field_features(x, 1e-3, plan["origins"])
     assert per.shape == (plan["nblocks"], 32)
     assert np.allclose(mean, per.astype(np.float64).mean(axis=0), rtol=1e-7)
-    # each block on its own
-    o = plan["origins"][-1]
-    blk = np.ascontiguousarray(x[o[0]:o[0] + 33, o[1]:o[1] + 33,
-                                 o[2]:o[2] + 33])
-    vr = float(x.max()) - float(x.min())
-    assert np.array_equal(per[-1], rl.block_features(blk, 1e-3, vr))
+    # each block on its own; the range feature spans all sampled blocks
+    blks = [np.ascontiguousarray(x[o[0]:o[0] + 33, o[1]:o[1] + 33,
+                                   o[2]:o[2] + 33]) for o in plan["origins"]]
+    lo = min(float(b.min()) for b in blks)
+    hi = max(float(b.max()) for b in blks)
+    assert hi - lo < float(x.max()) - float(x.min())  # not the field's
+    assert np.array_equal(per[-1], rl.block_features(blks[-1], 1e-3, hi - lo))
+    assert np.all(per[:, 31] == per[0, 31])
 
 
 # --------------------------------------------------------------------- MLP
