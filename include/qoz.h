@@ -174,12 +174,13 @@ qoz_status qoz_error_ac(qoz_ctx* ctx, const float* d_x, const float* d_y,
  * (33^3 points) sampled as in Sec. VI-A at cfg's rate and stride (rate 0
  * -> 0.01; cfg->block is ignored), 32 float32 features each (level-wise
  * linear / cubic residual statistics of the original values, gradient
- * deciles, block and field value ranges, all relative to abs_eb), and
- * their mean over the blocks into d_mean[32].  d_block (may be NULL)
+ * deciles, the block's value range and the range over all sampled
+ * blocks, all relative to abs_eb), and their mean over the blocks into
+ * d_mean[32].  Only the sampled blocks are read.  d_block (may be NULL)
  * receives the per-block rows, *nblocks (may be NULL) their count; with
  * d_block non-NULL, block_cap is its capacity in rows.  Every dimension
- * must be >= 33.  Errors: EINVAL (shape, bound, cfg, non-finite input,
- * block_cap too small), EDEVICE, ENOMEM. */
+ * must be >= 33.  Errors: EINVAL (shape, bound, cfg, NaN or Inf in a
+ * sampled block, block_cap too small), EDEVICE, ENOMEM. */
 qoz_status qoz_learned_features(qoz_ctx* ctx, const float* d_x,
                                 qoz_shape shape, double abs_eb,
                                 const qoz_tune_config* cfg, float* d_mean,
@@ -224,7 +225,9 @@ qoz_status qoz_mlp_train_step(qoz_ctx* ctx, float* d_params, float* d_m,
  * cfg) decides instead and *used_fallback (may be NULL) is set to 1, else
  * 0.  The network's parameters use every level's interpolation type from
  * its first head and the identity dimension order.  On input
- * out->anchor_stride selects s.  Errors: as qoz_tune. */
+ * out->anchor_stride selects s.  The network path reads only the sampled
+ * blocks (NaN or Inf elsewhere is left to qoz_compress to reject).
+ * Errors: as qoz_tune. */
 qoz_status qoz_tune_learned(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
                             double abs_eb, const float* d_params,
                             double min_confidence, qoz_target fallback_target,

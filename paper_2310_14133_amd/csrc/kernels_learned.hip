@@ -12,8 +12,9 @@
  * else linear); the ten nearest-rank deciles of the squared forward-
  * difference gradient (dx*dx + dy*dy) + dz*dz over the 32^3 points with
  * every coordinate below 32, as log2(1 + sqrt(g2) / e); log2(1 + block
- * range / e) and log2(1 + field range / e).  Residuals and gradients are
- * float32 in the order written; sums and logs are FP64.
+ * range / e) and log2(1 + range over all sampled blocks / e).  Residuals
+ * and gradients are float32 in the order written; sums and logs are FP64.
+ * Only the sampled blocks are read.
  *
  * One workgroup of 1024 lanes per block: the block sits in LDS (143.7 KB),
  * each level's residual sums are block reductions, and the 32768 squared
@@ -62,13 +63,14 @@ __device__ void block_sum(double (&v)[N], double (*red)[kFeatThreads / 64]) {
 }
 }  // namespace
 
+/* feat[b][0..30] of block b; aux[b] = (min, max, non-finite flag) for the
+ * pooling kernel, which fills feat[b][31] */
 __global__ __launch_bounds__(kFeatThreads) void k_block_features(
     const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
-    const float* __restrict__ pmin, const float* __restrict__ pmax,
-    uint32_t rp, double e, float* __restrict__ feat) {
+    double e, float* __restrict__ feat, float* __restrict__ aux) {
   extern __shared__ float blk[];
   __shared__ double red[4][kFeatThreads / 64];
-  __shared__ float mred[2][kFeatThreads / 64];
+  __shared__ float mred[3][kFeatThreads / 64];
   __shared__ double stat[20];
   const uint32_t tid = threadIdx.x;
   const uint32_t* o = origins + 3 * blockIdx.x;
@@ -81,19 +83,24 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
     blk[t] = x[base + (uint64_t)i * g.st[0] + (uint64_t)j * g.st[1] + k];
   }
   __syncthreads();
-  /* block range */
+  /* block range and finiteness */
   float lo = blk[tid], hi = blk[tid];
+  uint32_t bad = 0;
   for (uint32_t t = tid; t < kBlockPts; t += kFeatThreads) {
-    lo = fminf(lo, blk[t]);
-    hi = fmaxf(hi, blk[t]);
+    const float v = blk[t];
+    lo = fminf(lo, v);
+    hi = fmaxf(hi, v);
+    bad |= (__float_as_uint(v) & 0x7f800000u) == 0x7f800000u;
   }
   for (int s = 32; s > 0; s >>= 1) {
     lo = fminf(lo, __shfl_xor(lo, s, 64));
     hi = fmaxf(hi, __shfl_xor(hi, s, 64));
+    bad |= __shfl_xor(bad, s, 64);
   }
   if ((tid & 63) == 0) {
     mred[0][tid >> 6] = lo;
     mred[1][tid >> 6] = hi;
+    mred[2][tid >> 6] = bad ? 1.0f : 0.0f;
   }
   /* level-wise residual sums: lin |r|, lin r^2, cubic |r|, cubic r^2 */
   for (uint32_t l = 1; l <= 5; ++l) {
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
       }
       __syncthreads();
     }
-  if (tid < 32) {
+  if (tid < 31) {
     double f;
     if (tid < 20) {
       f = stat[tid];
@@ -172,32 +179,48 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
       const uint32_t q = tid - 19;
       const uint32_t idx = (q * kNG + 9) / 10 - 1;
       f = log2(1.0 + sqrt((double)__uint_as_float(key[idx])) / e);
-    } else if (tid == 30) {
-      float l2 = mred[0][0], h2 = mred[1][0];
+    } else {
+      float l2 = mred[0][0], h2 = mred[1][0], b2 = mred[2][0];
       for (uint32_t w = 1; w < kFeatThreads / 64; ++w) {
         l2 = fminf(l2, mred[0][w]);
         h2 = fmaxf(h2, mred[1][w]);
+        b2 = fmaxf(b2, mred[2][w]);
       }
       f = log2(1.0 + ((double)h2 - (double)l2) / e);
-    } else {
-      float l2 = pmin[0], h2 = pmax[0];
-      for (uint32_t w = 1; w < rp; ++w) {
-        l2 = fminf(l2, pmin[w]);
-        h2 = fmaxf(h2, pmax[w]);
+      if (tid == 30) {
+        aux[3 * (uint64_t)blockIdx.x + 0] = l2;
+        aux[3 * (uint64_t)blockIdx.x + 1] = h2;
+        aux[3 * (uint64_t)blockIdx.x + 2] = b2;
       }
-      f = log2(1.0 + ((double)h2 - (double)l2) / e);
     }
     feat[32 * (uint64_t)blockIdx.x + tid] = (float)f;
   }
 }
 
-__global__ void k_feat_mean(const float* __restrict__ feat, uint32_t nb,
-                            float* __restrict__ out) {
+/* Range over all blocks into every row's feature 31, the mean of each
+ * feature over the blocks into out[32], and the non-finite flag into
+ * status[0]. */
+__global__ void k_feat_pool(float* __restrict__ feat,
+                            const float* __restrict__ aux, uint32_t nb,
+                            double e, float* __restrict__ out,
+                            uint32_t* __restrict__ status) {
   const uint32_t i = threadIdx.x;
-  if (i >= 32) return;
-  double s = 0.0;
-  for (uint32_t b = 0; b < nb; ++b) s += (double)feat[32 * (uint64_t)b + i];
-  out[i] = (float)(s / (double)nb);
+  float lo = aux[0], hi = aux[1], bad = aux[2];
+  for (uint32_t b = 1; b < nb; ++b) {
+    lo = fminf(lo, aux[3 * (uint64_t)b]);
+    hi = fmaxf(hi, aux[3 * (uint64_t)b + 1]);
+    bad = fmaxf(bad, aux[3 * (uint64_t)b + 2]);
+  }
+  const float f31 = (float)log2(1.0 + ((double)hi - (double)lo) / e);
+  for (uint32_t b = i; b < nb; b += blockDim.x) feat[32 * (uint64_t)b + 31] = f31;
+  if (i == 0) status[0] = bad != 0.0f ? kStNonFinite : 0u;
+  if (i < 31) {
+    double s = 0.0;
+    for (uint32_t b = 0; b < nb; ++b) s += (double)feat[32 * (uint64_t)b + i];
+    out[i] = (float)(s / (double)nb);
+  } else if (i == 31) {
+    out[31] = f31;
+  }
 }
 
 size_t block_features_lds() { return 4 * (size_t)kBlockPts; }
@@ -208,7 +231,7 @@ bool block_features_fit() {
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                             dev) != hipSuccess)
     return false;
-  const size_t stat_bytes = 8 * 4 * 16 + 4 * 2 * 16 + 8 * 20;
+  const size_t stat_bytes = 8 * 4 * 16 + 4 * 3 * 16 + 8 * 20;
   if (block_features_lds() + stat_bytes > (size_t)max_lds) return false;
   return hipFuncSetAttribute(
              reinterpret_cast<const void*>(&k_block_features),
@@ -217,14 +240,13 @@ bool block_features_fit() {
 }
 
 void launch_block_features(const float* x, const Geo& g,
-                           const uint32_t* origins, uint32_t nb,
-                           const float* pmin, const float* pmax, uint32_t rp,
-                           double e, float* feat, float* mean,
-                           hipStream_t s) {
+                           const uint32_t* origins, uint32_t nb, double e,
+                           float* feat, float* aux, float* mean,
+                           uint32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(k_block_features, dim3(nb), dim3(kFeatThreads),
-                     block_features_lds(), s, x, g, origins, pmin, pmax, rp,
-                     e, feat);
-  hipLaunchKernelGGL(k_feat_mean, dim3(1), dim3(64), 0, s, feat, nb, mean);
+                     block_features_lds(), s, x, g, origins, e, feat, aux);
+  hipLaunchKernelGGL(k_feat_pool, dim3(1), dim3(64), 0, s, feat,
+                     (const float*)aux, nb, e, mean, status);
 }
 
 /* ----------------------------------------------------------------- MLP */

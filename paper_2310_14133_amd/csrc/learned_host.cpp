@@ -50,8 +50,8 @@ static qoz_status learned_origins(int d, const uint64_t n[3],
   return QOZ_OK;
 }
 
-/* Enqueue the range check and the features; the status word is copied to
- * the pinned staging at *h_status (checked by the caller after a sync). */
+/* Enqueue the features; the status word is copied to the pinned staging
+ * at *h_status (checked by the caller after a sync). */
 static qoz_status enqueue_features(qoz_ctx* c, const float* d_x, int d,
                                    const uint64_t n[3], double e,
                                    const qoz_tune_config* cfg, float* d_mean,
@@ -66,30 +66,23 @@ static qoz_status enqueue_features(qoz_ctx* c, const float* d_x, int d,
   if (!block_features_fit())
     return fail(QOZ_EDEVICE, "block features do not fit in LDS");
   const Geo g = make_geo(d, n);
-  const uint64_t N = (uint64_t)g.n[0] * g.n[1] * g.n[2];
-  const uint32_t rp = range_parts(N);
-  QOZ_TRY(ensure(c->partial, 8 * (size_t)rp + 4 * org.size() + 64));
+  /* partial: origins (3 per block), then aux (3 per block) */
+  QOZ_TRY(ensure(c->partial, 4 * 6 * (size_t)nb + 64));
   QOZ_TRY(ensure(c->status, 256));
   if (!d_block) QOZ_TRY(ensure(c->feat, 4 * (size_t)kMlpFeat * nb));
   /* pinned: status [0, 16), logits [16, 60), origins from 64 */
   QOZ_TRY(ensure_pinned(c, 4 * org.size() + 4096));
-  float* pmin = (float*)c->partial.p;
-  float* pmax = pmin + rp;
-  uint32_t* dorig = (uint32_t*)(pmax + rp);
+  uint32_t* dorig = (uint32_t*)c->partial.p;
+  float* aux = (float*)(dorig + org.size());
   uint32_t* st = (uint32_t*)c->status.p;
   uint8_t* hp = (uint8_t*)c->pinned;
   std::memcpy(hp + 64, org.data(), 4 * org.size());
-  launch_init_status(st, s);
-  {
-    hipEvent_t ev = prof_begin(c, s, PK_CHECK);
-    launch_range(d_x, N, pmin, pmax, st, rp, s);
-    prof_end(c, s, ev, PK_CHECK, 4.0 * N);
-  }
   QOZ_TRY(to_device(c, dorig, hp + 64, 4 * org.size(), s));
   {
     hipEvent_t ev = prof_begin(c, s, PK_LEARN_FEAT);
-    launch_block_features(d_x, g, dorig, nb, pmin, pmax, rp, e,
-                          d_block ? d_block : (float*)c->feat.p, d_mean, s);
+    launch_block_features(d_x, g, dorig, nb, e,
+                          d_block ? d_block : (float*)c->feat.p, aux, d_mean,
+                          st, s);
     prof_end(c, s, ev, PK_LEARN_FEAT, 4.0 * 35937.0 * nb);
   }
   QOZ_TRY(to_host(c, hp, st, 16, s));
@@ -123,7 +116,8 @@ extern "C" qoz_status qoz_learned_features(qoz_ctx* c, const float* d_x,
   QOZ_HIP(hipGetLastError());
   QOZ_HIP(hipStreamSynchronize(s));
   prof_collect(c);
-  if (hst[0] & kStNonFinite) return fail(QOZ_EINVAL, "input contains NaN or Inf");
+  if (hst[0] & kStNonFinite)
+    return fail(QOZ_EINVAL, "sampled blocks contain NaN or Inf");
   if (nblocks) *nblocks = nb;
   return QOZ_OK;
 }
@@ -250,7 +244,7 @@ extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
     QOZ_HIP(hipStreamSynchronize(s));
     prof_collect(c);
     if (hst[0] & kStNonFinite)
-      return fail(QOZ_EINVAL, "input contains NaN or Inf");
+      return fail(QOZ_EINVAL, "sampled blocks contain NaN or Inf");
     /* per head: first maximum and its softmax probability */
     const uint32_t heads[3] = {kHeadInterp, kHeadAlpha, kHeadBeta};
     conf = 1.0;

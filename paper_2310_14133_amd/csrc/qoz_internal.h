@@ -367,10 +367,13 @@ static_assert(kMlpParams == QOZ_MLP_NPARAM, "parameter blob size");
 static_assert(kHeadInterp + kHeadAlpha + kHeadBeta == kMlpOut, "heads");
 constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
 bool block_features_fit();
+/* features of nb sampled 33^3 blocks into feat[nb][32] (aux: 3 floats per
+ * block), their mean into mean[32], kStNonFinite into status[0] when a
+ * sampled value is NaN or Inf */
 void launch_block_features(const float* x, const Geo& g,
-                           const uint32_t* origins, uint32_t nb,
-                           const float* pmin, const float* pmax, uint32_t rp,
-                           double e, float* feat, float* mean, hipStream_t s);
+                           const uint32_t* origins, uint32_t nb, double e,
+                           float* feat, float* aux, float* mean,
+                           uint32_t* status, hipStream_t s);
 uint32_t mlp_tiles(uint32_t B);
 bool mlp_fit();
 void launch_mlp_forward(const float* P, const float* X, uint32_t B,

@@ -71,6 +71,33 @@ def grf_torch(shape, seed, slope=-3.0, log_normal=False, device="cuda"):
     return g.contiguous()
 
 
+def tuner_training_field(seed, device="cuda", shape=None):
+    """One field of the learned tuner's workload: a k^slope random field
+    (slope U[-4, -2]) plus white noise of relative std 10^U[-4, -2], shape
+    U{64..256}^3 unless given, all drawn from `seed` (torch on `device`).
+    Without a given shape the field is the corner of a periodic 256^3 field
+    (one FFT size for every field), standardised again.
+    Returns (field, recipe)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    crop = shape is None
+    if crop:
+        shape = tuple(int(v) for v in rng.integers(64, 257, 3))
+    slope = float(rng.uniform(-4.0, -2.0))
+    noise = float(10.0 ** rng.uniform(-4.0, -2.0))
+    if crop:
+        g = grf_torch((256, 256, 256), seed, slope=slope, device=device)
+        g = g[:shape[0], :shape[1], :shape[2]]
+        g = ((g - g.mean()) / g.std()).contiguous()
+    else:
+        g = grf_torch(shape, seed, slope=slope, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed) + 104729)
+    g += noise * torch.randn(shape, generator=gen, device=device,
+                             dtype=torch.float32)
+    return g.contiguous(), {"shape": shape, "slope": slope, "noise": noise}
+
+
 def bumps_and_waves(n=256, seed=1, n_bumps=8, n_waves=3, noise=1e-3,
                     dtype=np.float32):
     """2D field: Gaussian bumps + plane waves + white noise.
