@@ -164,7 +164,8 @@ qoz_status qoz_error_ac(qoz_ctx* ctx, const float* d_x, const float* d_y,
  * index first).  Outputs 0-1 score linear / cubic, 2-6 alpha in {1, 1.25,
  * 1.5, 1.75, 2}, 7-10 beta in {1.5, 2, 3, 4}.  Products take bfloat16
  * operands (round to nearest even) with FP32 accumulation; the loss is the
- * batch mean of the three heads' summed softmax cross-entropies. */
+ * batch mean of the three heads' summed softmax cross-entropies.  Every
+ * d_params passed below must be 16-byte aligned (EINVAL otherwise). */
 #define QOZ_MLP_NFEAT 32
 #define QOZ_MLP_HIDDEN 128
 #define QOZ_MLP_NOUT 11

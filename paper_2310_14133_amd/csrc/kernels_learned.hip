@@ -18,8 +18,10 @@
  *
  * One workgroup of 1024 lanes per block: the block sits in LDS (143.7 KB),
  * each level's residual sums are block reductions, and the 32768 squared
- * gradients, kept in registers while the block is still needed, are then
- * written over it and bitonic-sorted in LDS for the deciles.
+ * gradients stay in registers (32 per lane) while an exact radix select
+ * finds the ten deciles: four passes of 8 bits, each an LDS histogram per
+ * distinct prefix still in play, a wave per decile scanning its histogram
+ * to fix the next byte of its value and its rank below it.
  *
  * The network multiplies bfloat16 operands on the matrix cores
  * (v_mfma_f32_16x16x16_bf16, FP32 accumulate); biases, activations, the
@@ -43,6 +45,11 @@ constexpr uint32_t kPlane = kB1 * kB1; /* 1089 */
 constexpr uint32_t kBlockPts = kB1 * kPlane;
 constexpr uint32_t kNG = 32 * 32 * 32; /* gradient points */
 constexpr uint32_t kGPer = kNG / kFeatThreads;
+constexpr uint32_t kLoadBatch = 12;
+constexpr uint32_t kLoadPer =
+    (kBlockPts + kFeatThreads * kLoadBatch - 1) / (kFeatThreads * kLoadBatch) *
+    kLoadBatch;
+constexpr uint32_t kNone = 0xffffffffu;
 
 template <int N>
 __device__ void block_sum(double (&v)[N], double (*red)[kFeatThreads / 64]) {
@@ -72,15 +79,29 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
   __shared__ double red[4][kFeatThreads / 64];
   __shared__ float mred[3][kFeatThreads / 64];
   __shared__ double stat[20];
+  __shared__ uint32_t rhist[10][256];
+  __shared__ uint32_t rpre[10], rrank[10], dpre[10], dmap[10], ndist;
   const uint32_t tid = threadIdx.x;
   const uint32_t* o = origins + 3 * blockIdx.x;
   const uint64_t base = (uint64_t)o[0] * g.st[0] + (uint64_t)o[1] * g.st[1] +
                         (uint64_t)o[2] * g.st[2];
-  /* the block, row by row */
-  for (uint32_t t = tid; t < kBlockPts; t += kFeatThreads) {
-    const uint32_t i = t / kPlane, r = t - i * kPlane, j = r / kB1,
-                   k = r - j * kB1;
-    blk[t] = x[base + (uint64_t)i * g.st[0] + (uint64_t)j * g.st[1] + k];
+  /* the block, 12 loads in flight per lane */
+  for (uint32_t u0 = 0; u0 < kLoadPer; u0 += kLoadBatch) {
+    float v[kLoadBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kLoadBatch; ++u) {
+      const uint32_t t = tid + (u0 + u) * kFeatThreads;
+      if (t < kBlockPts) {
+        const uint32_t i = t / kPlane, r = t - i * kPlane, j = r / kB1,
+                       k = r - j * kB1;
+        v[u] = x[base + (uint64_t)i * g.st[0] + (uint64_t)j * g.st[1] + k];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kLoadBatch; ++u) {
+      const uint32_t t = tid + (u0 + u) * kFeatThreads;
+      if (t < kBlockPts) blk[t] = v[u];
+    }
   }
   __syncthreads();
   /* block range and finiteness */
@@ -103,6 +124,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
     mred[2][tid >> 6] = bad ? 1.0f : 0.0f;
   }
   /* level-wise residual sums: lin |r|, lin r^2, cubic |r|, cubic r^2 */
+#pragma unroll
   for (uint32_t l = 1; l <= 5; ++l) {
     const uint32_t h = 1u << (l - 1), m = 32 / h + 1, nodd = 16 / h;
     const uint32_t per_dim = nodd * m * m;
@@ -140,7 +162,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
       stat[4 * (l - 1) + 3] = log2(1.0 + sqrt(acc[3] / n) / e);
     }
   }
-  /* squared gradients into registers, then over the block */
+  /* squared gradients, kept in registers */
   uint32_t g2[kGPer];
 #pragma unroll
   for (uint32_t s = 0; s < kGPer; ++s) {
@@ -152,33 +174,94 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
                 dz = blk[p + 1] - v;
     g2[s] = __float_as_uint((dx * dx + dy * dy) + dz * dz);
   }
+  /* exact radix select of the deciles (non-negative floats order as their
+   * bits): rank of decile q is ceil(q n / 10) - 1 */
+  if (tid < 10) {
+    rrank[tid] = ((tid + 1) * kNG + 9) / 10 - 1;
+    rpre[tid] = 0;
+    dmap[tid] = 0;
+  }
+  if (tid == 0) {
+    dpre[0] = 0;
+    ndist = 1;
+  }
   __syncthreads();
-  uint32_t* key = reinterpret_cast<uint32_t*>(blk);
-#pragma unroll
-  for (uint32_t s = 0; s < kGPer; ++s) key[tid + s * kFeatThreads] = g2[s];
-  __syncthreads();
-  /* bitonic sort, ascending (non-negative floats order as their bits) */
-  for (uint32_t k = 2; k <= kNG; k <<= 1)
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t q = tid; q < kNG / 2; q += kFeatThreads) {
-        const uint32_t i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
-        const uint32_t a = key[i], b = key[i | j];
-        const bool up = (i & k) == 0;
-        if ((a > b) == up) {
-          key[i] = b;
-          key[i | j] = a;
-        }
+  const uint32_t lane = tid & 63, wv = tid >> 6;
+  uint32_t* flat = &rhist[0][0];
+  for (uint32_t pass = 0; pass < 4; ++pass) {
+    const uint32_t shift = 24 - 8 * pass;
+    const uint32_t nd = ndist;
+    for (uint32_t i = tid; i < nd * 256; i += kFeatThreads) flat[i] = 0;
+    __syncthreads();
+#pragma unroll 4
+    for (uint32_t s = 0; s < kGPer; ++s) {
+      const uint32_t key = g2[s];
+      uint32_t d = pass == 0 ? 0u : kNone;
+      if (pass != 0) {
+        const uint32_t hi = key >> (shift + 8);
+        for (uint32_t dd = 0; dd < nd; ++dd)
+          if (dpre[dd] == hi) d = dd;
       }
-      __syncthreads();
+      const uint32_t addr = d == kNone ? kNone : d * 256 + ((key >> shift) & 255);
+      /* a wave whose lanes all hit one bin adds once */
+      const uint32_t first = __builtin_amdgcn_readfirstlane(addr);
+      if (__all(addr == first)) {
+        if (lane == 0 && first != kNone) atomicAdd(&flat[first], 64u);
+      } else if (addr != kNone) {
+        atomicAdd(&flat[addr], 1u);
+      }
     }
+    __syncthreads();
+    if (wv < 10) {
+      const uint32_t* hq = rhist[dmap[wv]];
+      const uint32_t c0 = hq[4 * lane], c1 = hq[4 * lane + 1],
+                     c2 = hq[4 * lane + 2], c3 = hq[4 * lane + 3];
+      const uint32_t sum = c0 + c1 + c2 + c3;
+      uint32_t incl = sum;
+      for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
+      }
+      const uint32_t excl = incl - sum, r = rrank[wv];
+      if (r >= excl && r < incl) {
+        uint32_t b = 4 * lane, before = excl;
+        if (r >= before + c0) {
+          before += c0;
+          ++b;
+          if (r >= before + c1) {
+            before += c1;
+            ++b;
+            if (r >= before + c2) {
+              before += c2;
+              ++b;
+            }
+          }
+        }
+        rpre[wv] |= b << shift;
+        rrank[wv] = r - before;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) { /* distinct known prefixes for the next pass */
+      uint32_t n = 0;
+      for (uint32_t q = 0; q < 10; ++q) {
+        const uint32_t hi = rpre[q] >> shift;
+        uint32_t f = n;
+        for (uint32_t dd = 0; dd < n; ++dd)
+          if (dpre[dd] == hi) f = dd;
+        if (f == n) dpre[n++] = hi;
+        dmap[q] = f;
+      }
+      ndist = n;
+    }
+    __syncthreads();
+  }
   if (tid < 31) {
     double f;
     if (tid < 20) {
       f = stat[tid];
     } else if (tid < 30) {
-      const uint32_t q = tid - 19;
-      const uint32_t idx = (q * kNG + 9) / 10 - 1;
-      f = log2(1.0 + sqrt((double)__uint_as_float(key[idx])) / e);
+      f = log2(1.0 + sqrt((double)__uint_as_float(rpre[tid - 20])) / e);
     } else {
       float l2 = mred[0][0], h2 = mred[1][0], b2 = mred[2][0];
       for (uint32_t w = 1; w < kFeatThreads / 64; ++w) {
@@ -206,21 +289,23 @@ __global__ void k_feat_pool(float* __restrict__ feat,
                             uint32_t* __restrict__ status) {
   const uint32_t i = threadIdx.x;
   float lo = aux[0], hi = aux[1], bad = aux[2];
+#pragma unroll 8
   for (uint32_t b = 1; b < nb; ++b) {
     lo = fminf(lo, aux[3 * (uint64_t)b]);
     hi = fmaxf(hi, aux[3 * (uint64_t)b + 1]);
     bad = fmaxf(bad, aux[3 * (uint64_t)b + 2]);
   }
   const float f31 = (float)log2(1.0 + ((double)hi - (double)lo) / e);
-  for (uint32_t b = i; b < nb; b += blockDim.x) feat[32 * (uint64_t)b + 31] = f31;
   if (i == 0) status[0] = bad != 0.0f ? kStNonFinite : 0u;
   if (i < 31) {
     double s = 0.0;
+#pragma unroll 8
     for (uint32_t b = 0; b < nb; ++b) s += (double)feat[32 * (uint64_t)b + i];
     out[i] = (float)(s / (double)nb);
   } else if (i == 31) {
     out[31] = f31;
   }
+  for (uint32_t b = i; b < nb; b += blockDim.x) feat[32 * (uint64_t)b + 31] = f31;
 }
 
 size_t block_features_lds() { return 4 * (size_t)kBlockPts; }
@@ -231,7 +316,8 @@ bool block_features_fit() {
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                             dev) != hipSuccess)
     return false;
-  const size_t stat_bytes = 8 * 4 * 16 + 4 * 3 * 16 + 8 * 20;
+  const size_t stat_bytes = 8 * 4 * 16 + 4 * 3 * 16 + 8 * 20 + 4 * 10 * 256 +
+                            4 * 41;
   if (block_features_lds() + stat_bytes > (size_t)max_lds) return false;
   return hipFuncSetAttribute(
              reinterpret_cast<const void*>(&k_block_features),
@@ -286,13 +372,54 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
 }
 
+/* n4 float4 of a 16-byte aligned src to bf16 in dst, lane-strided, PER
+ * per lane (PER * kMlpThreads >= n4) */
+template <uint32_t PER>
+__device__ __forceinline__ void stage_bf16(const float* __restrict__ src,
+                                           uint32_t n4, uint16_t* dst) {
+  const float4* s4 = reinterpret_cast<const float4*>(src);
+  float4 v[PER];
+#pragma unroll
+  for (uint32_t u = 0; u < PER; ++u) {
+    const uint32_t i = threadIdx.x + u * kMlpThreads;
+    if (i < n4) v[u] = s4[i];
+  }
+#pragma unroll
+  for (uint32_t u = 0; u < PER; ++u) {
+    const uint32_t i = threadIdx.x + u * kMlpThreads;
+    if (i < n4) {
+      uint2 w;
+      w.x = (uint32_t)to_bf16(v[u].x) | ((uint32_t)to_bf16(v[u].y) << 16);
+      w.y = (uint32_t)to_bf16(v[u].z) | ((uint32_t)to_bf16(v[u].w) << 16);
+      reinterpret_cast<uint2*>(dst)[i] = w;
+    }
+  }
+}
+
+/* Operand fragments of four consecutive k: from a matrix whose k runs
+ * along a row (one 8-byte LDS read) or down a column (four reads). */
+__device__ __forceinline__ bf16x4 frag_row(const uint16_t* base,
+                                           uint32_t stride, uint32_t r,
+                                           uint32_t k0) {
+  return *reinterpret_cast<const bf16x4*>(base + r * stride + k0);
+}
+__device__ __forceinline__ bf16x4 frag_col(const uint16_t* base,
+                                           uint32_t stride, uint32_t k0,
+                                           uint32_t c) {
+  bf16x4 v;
+#pragma unroll
+  for (uint32_t j = 0; j < 4; ++j) v[j] = (short)base[(k0 + j) * stride + c];
+  return v;
+}
+
 /* C[M x N] = sum_k A(m, k) B(k, n) on 16x16x16 bf16 MFMA tiles, tiles
- * spread over the workgroup's waves.  Operand lane layout: A row = lane %
- * 16, k = 4 (lane / 16) + j; B k = 4 (lane / 16) + j, column = lane % 16;
- * result row = 4 (lane / 16) + j, column = lane % 16. */
+ * spread over the workgroup's waves.  fa(m, k0) gives A(m, k0..k0+3),
+ * fb(k0, n) gives B(k0..k0+3, n).  Lane layout: A row = lane % 16 and
+ * k0 = 4 (lane / 16); B column = lane % 16, same k0; result row =
+ * 4 (lane / 16) + j, column = lane % 16. */
 template <class FA, class FB, class FC>
 __device__ __forceinline__ void wave_mm(uint32_t M, uint32_t N, uint32_t K,
-                                        FA a, FB b, FC c) {
+                                        FA fa, FB fb, FC c) {
   const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t r = lane & 15, q = lane >> 4;
@@ -301,12 +428,8 @@ __device__ __forceinline__ void wave_mm(uint32_t M, uint32_t N, uint32_t K,
     const uint32_t m0 = (t / tn) << 4, n0 = (t % tn) << 4;
     f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     for (uint32_t k0 = 0; k0 < K; k0 += 16) {
-      bf16x4 av, bv;
-#pragma unroll
-      for (uint32_t j = 0; j < 4; ++j) {
-        av[j] = (short)a(m0 + r, k0 + 4 * q + j);
-        bv[j] = (short)b(k0 + 4 * q + j, n0 + r);
-      }
+      const bf16x4 av = fa(m0 + r, k0 + 4 * q);
+      const bf16x4 bv = fb(k0 + 4 * q, n0 + r);
       acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
@@ -340,12 +463,12 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
   const uint32_t tid = threadIdx.x;
   const uint32_t s0 = blockIdx.x * kTile;
 
-  for (uint32_t i = tid; i < NH * NF; i += kMlpThreads)
-    W1b[i] = to_bf16(P[kOffW1 + i]);
-  for (uint32_t i = tid; i < NH * NH; i += kMlpThreads)
-    W2b[i] = to_bf16(P[kOffW2 + i]);
-  for (uint32_t i = tid; i < NOP * NH; i += kMlpThreads)
-    W3b[i] = i < NO * NH ? to_bf16(P[kOffW3 + i]) : (uint16_t)0;
+  /* weights to bf16 in LDS: float4 loads, all of a matrix in flight */
+  stage_bf16<NH * NF / 4 / kMlpThreads>(P + kOffW1, NH * NF / 4, W1b);
+  stage_bf16<NH * NH / 4 / kMlpThreads>(P + kOffW2, NH * NH / 4, W2b);
+  stage_bf16<(NOP * NH / 4 + kMlpThreads - 1) / kMlpThreads>(
+      P + kOffW3, NO * NH / 4, W3b);
+  for (uint32_t i = NO * NH + tid; i < NOP * NH; i += kMlpThreads) W3b[i] = 0;
   for (uint32_t i = tid; i < NH; i += kMlpThreads) {
     b1[i] = P[kOffB1 + i];
     b2[i] = P[kOffB2 + i];
@@ -371,21 +494,24 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
   }
   __syncthreads();
 
-  wave_mm(kTile, NH, NF, [&](uint32_t m, uint32_t k) { return Xb[m * NF + k]; },
-          [&](uint32_t k, uint32_t n) { return W1b[n * NF + k]; },
+  /* forward rows: the whole tile when training, else the valid rows */
+  const uint32_t live = B - s0 < kTile ? B - s0 : kTile;
+  const uint32_t MF = TRAIN ? kTile : (live + 15) / 16 * 16;
+  wave_mm(MF, NH, NF, [&](uint32_t m, uint32_t k) { return frag_row(Xb, NF, m, k); },
+          [&](uint32_t k, uint32_t n) { return frag_row(W1b, NF, n, k); },
           [&](uint32_t m, uint32_t n, float v) {
             H1b[m * NH + n] = to_bf16(fmaxf(v + b1[n], 0.0f));
           });
   __syncthreads();
-  wave_mm(kTile, NH, NH, [&](uint32_t m, uint32_t k) { return H1b[m * NH + k]; },
-          [&](uint32_t k, uint32_t n) { return W2b[n * NH + k]; },
+  wave_mm(MF, NH, NH, [&](uint32_t m, uint32_t k) { return frag_row(H1b, NH, m, k); },
+          [&](uint32_t k, uint32_t n) { return frag_row(W2b, NH, n, k); },
           [&](uint32_t m, uint32_t n, float v) {
             H2b[m * NH + n] = to_bf16(fmaxf(v + b2[n], 0.0f));
           });
   __syncthreads();
-  wave_mm(kTile, NOP, NH,
-          [&](uint32_t m, uint32_t k) { return H2b[m * NH + k]; },
-          [&](uint32_t k, uint32_t n) { return W3b[n * NH + k]; },
+  wave_mm(MF, NOP, NH,
+          [&](uint32_t m, uint32_t k) { return frag_row(H2b, NH, m, k); },
+          [&](uint32_t k, uint32_t n) { return frag_row(W3b, NH, n, k); },
           [&](uint32_t m, uint32_t n, float v) { Zs[m * NOP + n] = v + b3[n]; });
   __syncthreads();
 
@@ -444,8 +570,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
   if (tid < 2 * NF) gp[tid] = 0.0f; /* input shift and scale: not trained */
   /* output layer */
   wave_mm(NOP, NH, kTile,
-          [&](uint32_t m, uint32_t k) { return dZb[k * NOP + m]; },
-          [&](uint32_t k, uint32_t n) { return H2b[k * NH + n]; },
+          [&](uint32_t m, uint32_t k) { return frag_col(dZb, NOP, k, m); },
+          [&](uint32_t k, uint32_t n) { return frag_col(H2b, NH, k, n); },
           [&](uint32_t m, uint32_t n, float v) {
             if (m < NO) gp[kOffW3 + m * NH + n] = v;
           });
@@ -455,8 +581,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
     gp[kOffB3 + tid] = t;
   }
   wave_mm(kTile, NH, NOP,
-          [&](uint32_t m, uint32_t k) { return dZb[m * NOP + k]; },
-          [&](uint32_t k, uint32_t n) { return W3b[k * NH + n]; },
+          [&](uint32_t m, uint32_t k) { return frag_row(dZb, NOP, m, k); },
+          [&](uint32_t k, uint32_t n) { return frag_col(W3b, NH, k, n); },
           [&](uint32_t m, uint32_t n, float v) {
             const float d = from_bf16(H2b[m * NH + n]) > 0.0f ? v : 0.0f;
             dHf[m * NH + n] = d;
@@ -465,8 +591,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
   __syncthreads();
   /* second layer */
   wave_mm(NH, NH, kTile,
-          [&](uint32_t m, uint32_t k) { return dH2b[k * NH + m]; },
-          [&](uint32_t k, uint32_t n) { return H1b[k * NH + n]; },
+          [&](uint32_t m, uint32_t k) { return frag_col(dH2b, NH, k, m); },
+          [&](uint32_t k, uint32_t n) { return frag_col(H1b, NH, k, n); },
           [&](uint32_t m, uint32_t n, float v) { gp[kOffW2 + m * NH + n] = v; });
   if (tid < NH) {
     float t = 0.0f;
@@ -475,8 +601,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
   }
   __syncthreads();
   wave_mm(kTile, NH, NH,
-          [&](uint32_t m, uint32_t k) { return dH2b[m * NH + k]; },
-          [&](uint32_t k, uint32_t n) { return W2b[k * NH + n]; },
+          [&](uint32_t m, uint32_t k) { return frag_row(dH2b, NH, m, k); },
+          [&](uint32_t k, uint32_t n) { return frag_col(W2b, NH, k, n); },
           [&](uint32_t m, uint32_t n, float v) {
             const float d = from_bf16(H1b[m * NH + n]) > 0.0f ? v : 0.0f;
             dHf[m * NH + n] = d;
@@ -485,8 +611,8 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp(
   __syncthreads();
   /* first layer */
   wave_mm(NH, NF, kTile,
-          [&](uint32_t m, uint32_t k) { return dH1b[k * NH + m]; },
-          [&](uint32_t k, uint32_t n) { return Xb[k * NF + n]; },
+          [&](uint32_t m, uint32_t k) { return frag_col(dH1b, NH, k, m); },
+          [&](uint32_t k, uint32_t n) { return frag_col(Xb, NF, k, n); },
           [&](uint32_t m, uint32_t n, float v) { gp[kOffW1 + m * NF + n] = v; });
   if (tid < NH) {
     float t = 0.0f;

@@ -122,12 +122,16 @@ extern "C" qoz_status qoz_learned_features(qoz_ctx* c, const float* d_x,
   return QOZ_OK;
 }
 
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 extern "C" qoz_status qoz_mlp_forward(qoz_ctx* c, const float* d_params,
                                       const float* d_feat, uint32_t batch,
                                       float* d_logits, hipStream_t s) {
   clear_error();
   if (!c || !d_params || !d_feat || !d_logits)
     return fail(QOZ_EINVAL, "NULL argument");
+  if (!aligned16(d_params))
+    return fail(QOZ_EINVAL, "d_params must be 16-byte aligned");
   if (batch == 0) return fail(QOZ_EINVAL, "empty batch");
   QOZ_TRY(set_device(c));
   if (!mlp_fit()) return fail(QOZ_EDEVICE, "network does not fit in LDS");
@@ -146,6 +150,7 @@ static qoz_status mlp_backward(qoz_ctx* c, float* P, float* m, float* v,
                                uint32_t B, float* grad, float lr, uint32_t t,
                                bool adam, double* loss, hipStream_t s) {
   if (B == 0) return fail(QOZ_EINVAL, "empty batch");
+  if (!aligned16(P)) return fail(QOZ_EINVAL, "d_params must be 16-byte aligned");
   if (!mlp_fit()) return fail(QOZ_EDEVICE, "network does not fit in LDS");
   const uint32_t nw = mlp_tiles(B);
   QOZ_TRY(ensure(c->mlp_part, 4 * (size_t)kMlpParams * nw));
@@ -206,6 +211,8 @@ extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
                                        hipStream_t s) {
   clear_error();
   if (!c || !d_x || !d_params || !out) return fail(QOZ_EINVAL, "NULL argument");
+  if (!aligned16(d_params))
+    return fail(QOZ_EINVAL, "d_params must be 16-byte aligned");
   if (!(e > 0.0) || !std::isfinite(e))
     return fail(QOZ_EINVAL, "error bound must be finite and > 0");
   if (!(min_confidence >= 0.0 && min_confidence <= 1.0))
