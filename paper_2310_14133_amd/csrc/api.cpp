@@ -108,9 +108,22 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     const uint64_t n_keys = hk[0];
     std::vector<uint8_t> klen;
     std::vector<uint64_t> keys;
+    bool have = false;
     if (n_keys <= kSortCap) {
       keys.assign(hk + 1, hk + 1 + n_keys);
-    } else { /* too many used symbols for the device sort */
+      have = true;
+    } else if (n_keys <= kSortCapBig && hist_sort_big_fits()) {
+      /* a second device sort with room for kSortCapBig symbols; its keys
+       * (128 KB) land in the table region of the pinned staging */
+      QOZ_TRY(ensure(c->hsort, 8 * (kSortCapBig + 1)));
+      launch_hist_sort_big(hist, nullptr, 1, (uint64_t*)c->hsort.p, s);
+      uint64_t* hb = (uint64_t*)pin(c, kPinTable);
+      QOZ_TRY(to_host(c, hb, c->hsort.p, 8 * (n_keys + 1), s));
+      QOZ_TRY(sync_checked(s));
+      keys.assign(hb + 1, hb + 1 + n_keys);
+      have = true;
+    }
+    if (!have) { /* too many used symbols for the device sort */
       uint32_t* h = (uint32_t*)pin(c, kPinTable);
       QOZ_TRY(to_host(c, h, hist, 4 * kNSym, s));
       QOZ_TRY(sync_checked(s));

@@ -180,7 +180,7 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->tune_stats, &c->tune_l1,    &c->ssim_part,
                     &c->upos,       &c->hsort,      &c->scan,
                     &c->feat,       &c->mlp_io,     &c->mlp_part,
-                    &c->mlp_loss};
+                    &c->mlp_loss,   &c->hsort_ids};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

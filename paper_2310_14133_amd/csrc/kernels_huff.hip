@@ -316,12 +316,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(
 constexpr uint32_t kSortThreads = 1024;
 
 __global__ __launch_bounds__(kSortThreads) void k_hist_sort(
-    const uint32_t* __restrict__ hist, uint64_t* __restrict__ out) {
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ ids,
+    uint32_t cap, uint64_t* __restrict__ out) {
   static_assert(kNSym % (4 * kSortThreads) == 0, "bins per lane");
-  __shared__ uint64_t keys[kSortCap];
+  extern __shared__ uint64_t keys[]; /* cap entries, cap a power of two */
   __shared__ uint32_t n_used;
-  const uint32_t* hh = hist + (uint64_t)blockIdx.x * kNSym;
-  uint64_t* o = out + (uint64_t)blockIdx.x * (kSortCap + 1);
+  const uint32_t hid = ids ? ids[blockIdx.x] : blockIdx.x;
+  const uint32_t* hh = hist + (uint64_t)hid * kNSym;
+  uint64_t* o = out + (uint64_t)blockIdx.x * (cap + 1);
   __shared__ uint32_t wcount[kSortThreads / 64];
   /* lane t holds bins [64 t, 64 t + 64): sixteen 16-byte loads in flight,
    * then the used ones are compacted in bin order by a block scan of the
@@ -360,14 +362,14 @@ __global__ __launch_bounds__(kSortThreads) void k_hist_sort(
 #pragma unroll
   for (uint32_t q = 0; q < kPer; ++q)
     if (v[q]) {
-      if (k < kSortCap)
+      if (k < cap)
         keys[k] = ((uint64_t)v[q] << 16) | (threadIdx.x * kPer + q);
       ++k;
     }
   if (threadIdx.x == 0) n_used = total;
   __syncthreads();
   const uint32_t n = n_used;
-  const uint32_t m = n < kSortCap ? n : kSortCap;
+  const uint32_t m = n < cap ? n : cap;
   uint32_t p2 = 2;
   while (p2 < m) p2 <<= 1;
   for (uint32_t i = m + threadIdx.x; i < p2; i += kSortThreads)
@@ -395,8 +397,28 @@ __global__ __launch_bounds__(kSortThreads) void k_hist_sort(
 void launch_hist_sort(const uint32_t* hist, uint32_t n_hist, uint64_t* out,
                       hipStream_t s) {
   if (!n_hist) return;
-  hipLaunchKernelGGL(k_hist_sort, dim3(n_hist), dim3(kSortThreads), 0, s,
-                     hist, out);
+  hipLaunchKernelGGL(k_hist_sort, dim3(n_hist), dim3(kSortThreads),
+                     8 * kSortCap, s, hist, (const uint32_t*)nullptr,
+                     kSortCap, out);
+}
+
+bool hist_sort_big_fits() {
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                            dev) != hipSuccess)
+    return false;
+  if (8 * (size_t)kSortCapBig + 256 > (size_t)max_lds) return false;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hist_sort),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(8 * kSortCapBig)) == hipSuccess;
+}
+
+void launch_hist_sort_big(const uint32_t* hist, const uint32_t* ids,
+                          uint32_t n, uint64_t* out, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_hist_sort, dim3(n), dim3(kSortThreads),
+                     8 * kSortCapBig, s, hist, ids, kSortCapBig, out);
 }
 
 uint64_t chunk_scan_scratch(uint64_t n_chunks) {

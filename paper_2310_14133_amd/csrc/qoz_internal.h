@@ -199,7 +199,7 @@ struct qoz_ctx {
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
-      hsort, scan, feat, mlp_io, mlp_part, mlp_loss;
+      hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids;
   /* pinned host staging */
   void* pinned = nullptr;
   void* pinned_dev = nullptr; /* its device address */
@@ -276,11 +276,17 @@ bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);
 /* Used symbols sorted on the device: keys (count << 16) | symbol in
  * ascending order; lengths per key, or the total code bits. */
 constexpr uint32_t kSortCap = 4096;
+constexpr uint32_t kSortCapBig = 16384; /* second pass, 128 KB of LDS */
 bool huffman_lengths_sorted(const uint64_t* keys, uint32_t n, uint8_t* len);
 uint64_t huffman_cost_sorted(const uint64_t* keys, uint32_t n);
 /* Canonical codes for ascending symbols syms[0..n) with lengths lens. */
 void canonical_codes_sparse(const uint16_t* syms, const uint8_t* lens,
                             uint32_t n, uint64_t* codes);
+/* histograms ids[0..n) sorted with up to kSortCapBig used symbols each
+ * (output stride kSortCapBig + 1); hist_sort_big_fits() first */
+bool hist_sort_big_fits();
+void launch_hist_sort_big(const uint32_t* hist, const uint32_t* ids,
+                          uint32_t n, uint64_t* out, hipStream_t s);
 void launch_hist_sort(const uint32_t* hist, uint32_t n_hist, uint64_t* out,
                       hipStream_t s);
 void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code);

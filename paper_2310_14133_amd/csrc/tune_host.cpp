@@ -395,17 +395,14 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   const double nwin = (double)(sj.P - sj.wp + 1) * (double)(sj.Rn - sj.wr + 1) *
                       (double)(sj.Cn - sj.wc + 1) * bg.nb;
   std::vector<double> B(ntrial), M(ntrial, 0.0);
+  std::vector<uint64_t> bits(ntrial, 0), Us(ntrial, 0);
+  std::vector<uint32_t> over; /* trials with more used symbols than kSortCap */
   for (uint32_t t = 0; t < ntrial; ++t) {
     const uint64_t* kt = h_keys + (size_t)t * (kSortCap + 1);
-    uint64_t bits;
-    if (kt[0] <= kSortCap) {
-      bits = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
-    } else { /* too many used symbols for the device sort */
-      std::vector<uint32_t> hh(kNSym);
-      QOZ_HIP(hipMemcpy(hh.data(), dhist + (size_t)t * kNSym, 4 * kNSym,
-                        hipMemcpyDeviceToHost));
-      bits = huffman_cost(hh.data(), kNSym);
-    }
+    if (kt[0] <= kSortCap)
+      bits[t] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
+    else
+      over.push_back(t);
     uint64_t U = 0;
     double sse = 0.0;
     for (uint32_t k = 0; k < bg.nb; ++k) {
@@ -413,7 +410,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       U += h_un[it] + h_un[it + 1];
       sse += h_sse[it] + h_sse[it + 1];
     }
-    B[t] = ((double)bits + 32.0 * (double)U) / npts;
+    Us[t] = U;
     if (target == QOZ_TARGET_PSNR) {
       M[t] = sse == 0.0 ? std::numeric_limits<double>::infinity()
                         : 20.0 * std::log10(vrange / std::sqrt(sse / npts));
@@ -434,6 +431,53 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       M[t] = -std::fabs(ac_from_sums(ss, lag, npts, npts / len * (len - 1)));
     }
   }
+  /* trials with many used symbols: a second device sort of up to
+   * kSortCapBig symbols, then whole histograms for any still larger; the
+   * pinned staging may move here, so nothing above reads it any more */
+  if (!over.empty()) {
+    const uint32_t no = (uint32_t)over.size();
+    std::vector<uint32_t> full;
+    if (hist_sort_big_fits()) {
+      const size_t kb = 8 * (size_t)(kSortCapBig + 1);
+      QOZ_TRY(ensure(c->hsort, kb * no));
+      QOZ_TRY(ensure(c->hsort_ids, 4 * (size_t)no));
+      QOZ_TRY(ensure_pinned(c, kb * no + 4 * (size_t)no + 64));
+      uint8_t* hp = (uint8_t*)c->pinned;
+      std::memcpy(hp, over.data(), 4 * (size_t)no);
+      QOZ_TRY(to_device(c, c->hsort_ids.p, hp, 4 * (size_t)no, s));
+      launch_hist_sort_big(dhist, (const uint32_t*)c->hsort_ids.p, no,
+                           (uint64_t*)c->hsort.p, s);
+      uint64_t* hk = (uint64_t*)(hp + ((4 * (size_t)no + 63) / 64) * 64);
+      QOZ_TRY(to_host(c, hk, c->hsort.p, kb * no, s));
+      QOZ_HIP(hipGetLastError());
+      QOZ_HIP(hipStreamSynchronize(s));
+      for (uint32_t i = 0; i < no; ++i) {
+        const uint64_t* kt = hk + (size_t)i * (kSortCapBig + 1);
+        if (kt[0] <= kSortCapBig)
+          bits[over[i]] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
+        else
+          full.push_back(over[i]);
+      }
+    } else {
+      full = over;
+    }
+    if (!full.empty()) {
+      const size_t hb = 4 * (size_t)kNSym;
+      QOZ_TRY(ensure_pinned(c, hb * full.size()));
+      uint8_t* hp = (uint8_t*)c->pinned;
+      for (size_t i = 0; i < full.size(); ++i)
+        QOZ_TRY(to_host(c, hp + i * hb, dhist + (size_t)full[i] * kNSym, hb,
+                        s));
+      QOZ_HIP(hipGetLastError());
+      QOZ_HIP(hipStreamSynchronize(s));
+      for (size_t i = 0; i < full.size(); ++i)
+        bits[full[i]] =
+            huffman_cost((const uint32_t*)(hp + i * hb), kNSym);
+    }
+  }
+  for (uint32_t t = 0; t < ntrial; ++t)
+    B[t] = ((double)bits[t] + 32.0 * (double)Us[t]) / npts;
+
   int inc = 0;
   for (int i = 1; i < 20; ++i) {
     const int tI = trial_of[0][inc], tII = trial_of[0][i];

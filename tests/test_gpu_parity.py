@@ -96,6 +96,10 @@ CASES = [
      1.0, 1.5),
     ("multi_chunk", lambda: fields.grf((3, 2500, 7), 11), 1e-4, 8, "cubic",
      None, 1.25, 3.0),
+    # about 4700 used symbols: the second, larger device sort
+    ("noise_big_sort", lambda: np.random.default_rng(5).normal(
+        size=(48, 40, 44)).astype(np.float32), 1e-4, 8, "cubic", None, 1.0,
+     1.5),
 ]
 
 
@@ -234,6 +238,14 @@ TUNE_CASES = [
      dict(block=32, sample_rate=0.2), "ac", 1e-2),
     ("3d_ac_all", lambda: fields.grf((36, 36, 36), 34), 8,
      dict(block=8, sample_rate=0.15, all_orders=1), "ac", 1e-3),
+    # trials with thousands of used symbols (second device sort) and with
+    # more than the device sorts hold (whole histograms)
+    ("3d_noise_many_symbols", lambda: np.random.default_rng(7).normal(
+        size=(48, 40, 44)).astype(np.float32), 16,
+     dict(block=16, sample_rate=0.5), "psnr", 3e-5),
+    ("3d_noise_huge_alphabet", lambda: np.random.default_rng(8).normal(
+        size=(48, 40, 44)).astype(np.float32), 16,
+     dict(block=16, sample_rate=0.5), "psnr", 4e-6),
 ]
 
 
