@@ -262,6 +262,24 @@ def main():
                            for k, v in kinds.items()},
     }
 
+    # the learned tuner on the same field (network trained on the online
+    # tuner's PSNR-mode choices), for reference next to tune_ms
+    wpath = os.path.join(ROOT, "paper_2310_14133_amd", "tuner_mlp.bin")
+    if os.path.exists(wpath):
+        from paper_2310_14133_amd import learned
+        Pw = learned.load_weights(wpath)
+        cfg_l = q.make_tune_config(sample_rate=learned.SAMPLE_RATE)
+        lt = []
+        for _ in range(6):
+            ev[0].record(stream)
+            pl, fb = codec.tune_learned(x, e, Pw, 0.5, "psnr", cfg_l)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            lt.append(ev[0].elapsed_time(ev[1]))
+        line["learned_tune_ms"] = round(sorted(lt[1:])[len(lt[1:]) // 2], 4)
+        line["learned_params"] = q.params_dict(pl, 3)
+        line["learned_fallback"] = bool(fb)
+
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, e, args)
     print(json.dumps(line), flush=True)
