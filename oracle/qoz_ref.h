@@ -65,7 +65,12 @@ typedef struct {
   double sample_rate;     /* r; 0 -> 0.01 (2D) / 0.005 (3D) */
   uint32_t all_orders;    /* 0: increasing + decreasing orders; 1: all d! */
   uint32_t ssim_window;   /* 0 -> 7 */
+  uint32_t ablation;      /* QREF_ABLATE_* switches (ablation of Sec. VII) */
 } qref_tune_config;
+
+/* Ablation switches: components of the method left out one at a time. */
+#define QREF_ABLATE_AB 1u        /* no (alpha, beta) search: alpha = 1 */
+#define QREF_ABLATE_LEVELWISE 2u /* one interpolator for every level */
 
 /* Record of one tuner run, for tests. */
 typedef struct {

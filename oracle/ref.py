@@ -35,7 +35,7 @@ class Params(C.Structure):
 class TuneConfig(C.Structure):
     _fields_ = [("block", C.c_uint32), ("sample_stride", C.c_uint32),
                 ("sample_rate", C.c_double), ("all_orders", C.c_uint32),
-                ("ssim_window", C.c_uint32)]
+                ("ssim_window", C.c_uint32), ("ablation", C.c_uint32)]
 
 
 class TuneTrace(C.Structure):
@@ -122,11 +122,14 @@ def params_to_dict(p, ndim):
             "alpha": p.alpha, "beta": p.beta}
 
 
+ABLATE_AB, ABLATE_LEVELWISE = 1, 2
+
+
 def tune_config(block=0, sample_stride=0, sample_rate=0.0, all_orders=0,
-                ssim_window=0):
+                ssim_window=0, ablation=0):
     c = TuneConfig()
     c.block, c.sample_stride, c.sample_rate = block, sample_stride, sample_rate
-    c.all_orders, c.ssim_window = all_orders, ssim_window
+    c.all_orders, c.ssim_window, c.ablation = all_orders, ssim_window, ablation
     return c
 
 

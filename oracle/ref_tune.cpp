@@ -278,6 +278,8 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
   if (!x || !out || !shape_to_grid(shape, &g)) return QREF_EINVAL;
   if (!(e > 0.0) || !std::isfinite(e)) return QREF_EINVAL;
   if (target < QREF_TARGET_CR || target > QREF_TARGET_AC) return QREF_EINVAL;
+  if (cfg && (cfg->ablation & ~(QREF_ABLATE_AB | QREF_ABLATE_LEVELWISE)))
+    return QREF_EINVAL;
   if (!all_finite(x, g.N)) return QREF_EINVAL;
   uint32_t s = out->anchor_stride ? out->anchor_stride : (g.d == 2 ? 64u : 32u);
   if (s < 2 || (s & (s - 1)) != 0) return QREF_EINVAL;
@@ -300,6 +302,7 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
     trace->block_points = sp.blocks.size() * (uint64_t)sp.bg.N;
   }
 
+  const uint32_t abl = cfg ? cfg->ablation : 0u;
   /* Algorithm 1 */
   LevelPlan Is;
   for (int l = 0; l < QREF_MAX_LEVELS; ++l) {
@@ -310,7 +313,33 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
   bounds_uniform(e, Lt, &ub);
   int64_t st = (int64_t)1 << Lt;
   std::vector<float> W((size_t)sp.bg.N);
-  for (int l = Lt; l >= 1; --l) {
+  if (abl & QREF_ABLATE_LEVELWISE) {
+    /* one interpolator for the whole field: the candidate whose trial
+     * compression of the sampled blocks (every level, uniform bound e)
+     * has the lowest bit rate, the first on ties */
+    double best = std::numeric_limits<double>::infinity();
+    int ib = 0;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      LevelPlan pl;
+      for (int l = 0; l < QREF_MAX_LEVELS; ++l) {
+        pl.interp[l] = cands[ci].interp;
+        for (int j = 0; j < 3; ++j) pl.order[l][j] = cands[ci].order[j];
+      }
+      qref_trial_result r;
+      run_trial(sp, pl, ub, vrange, false, false, w, &r);
+      if (trace) trace->alg1_err[0][ci] = r.B;
+      if (r.B < best) {
+        best = r.B;
+        ib = (int)ci;
+      }
+    }
+    for (int l = 0; l < QREF_MAX_LEVELS; ++l) {
+      Is.interp[l] = cands[ib].interp;
+      for (int j = 0; j < 3; ++j) Is.order[l][j] = cands[ib].order[j];
+      if (trace && l < Lt) trace->alg1_choice[l] = (uint32_t)ib;
+    }
+  }
+  for (int l = (abl & QREF_ABLATE_LEVELWISE) ? 0 : Lt; l >= 1; --l) {
     double best = std::numeric_limits<double>::infinity();
     int ib = 0;
     for (size_t ci = 0; ci < cands.size(); ++ci) {
@@ -345,11 +374,13 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
     for (int j = 0; j < 3; ++j) Is.order[l - 1][j] = Is.order[Lt - 1][j];
   }
 
-  /* (alpha, beta) search with Table I */
+  /* (alpha, beta) search with Table I; without it the first pair, whose
+   * alpha = 1 gives every level the bound e */
+  const int npairs = (abl & QREF_ABLATE_AB) ? 1 : QREF_NPAIRS;
   bool want_ssim = target == QREF_TARGET_SSIM;
   bool want_ac = target == QREF_TARGET_AC;
   double B[QREF_NPAIRS], M[QREF_NPAIRS];
-  for (int i = 0; i < QREF_NPAIRS; ++i) {
+  for (int i = 0; i < npairs; ++i) {
     LevelBounds lb;
     bounds_eq5(e, kAlphas[i / 4], kBetas[i % 4], Lt, &lb);
     qref_trial_result r;
@@ -365,7 +396,7 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
     }
   }
   int inc = 0;
-  for (int i = 1; i < QREF_NPAIRS; ++i) {
+  for (int i = 1; i < npairs; ++i) {
     int cs = qref_table1_case(B[inc], M[inc], B[i], M[i]);
     if (trace) trace->cmp_case[i] = cs;
     if (cs == 1) continue;

@@ -39,7 +39,7 @@ class Params(C.Structure):
 class TuneConfig(C.Structure):
     _fields_ = [("block", C.c_uint32), ("sample_stride", C.c_uint32),
                 ("sample_rate", C.c_double), ("all_orders", C.c_uint32),
-                ("ssim_window", C.c_uint32)]
+                ("ssim_window", C.c_uint32), ("ablation", C.c_uint32)]
 
 
 class QozError(RuntimeError):
@@ -142,12 +142,25 @@ def make_params(ndim, interp="cubic", order=None, alpha=1.0, beta=1.0,
     return p
 
 
+ABLATE_AB, ABLATE_LEVELWISE = 1, 2
+
+
 def make_tune_config(block=0, sample_stride=0, sample_rate=0.0, all_orders=0,
-                     ssim_window=0):
+                     ssim_window=0, ablation=0):
     c = TuneConfig()
     c.block, c.sample_stride, c.sample_rate = block, sample_stride, sample_rate
-    c.all_orders, c.ssim_window = all_orders, ssim_window
+    c.all_orders, c.ssim_window, c.ablation = all_orders, ssim_window, ablation
     return c
+
+
+def sz3_anchor_stride(shape):
+    """Anchor stride that leaves the origin as the only anchor: levels up to
+    ceil(log2(max dimension)), the level structure without anchor points
+    that the ablation of Sec. VII starts from."""
+    s = 2
+    while s < max(shape):
+        s *= 2
+    return s
 
 
 def params_dict(p, ndim):

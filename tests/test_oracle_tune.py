@@ -319,3 +319,90 @@ def test_candidate_counts_follow_paper():
     assert ["".join(map(str, o)) for _, o in c[:6]] == g["permutations"]
     assert ["".join(map(str, o)) for _, o in candidates(3, False)[:2]] == \
         PV["tested_orders"]["3"]
+
+
+# ---- ablation switches (the component study of Sec. VII) ----
+ABL_CASES = [
+    ("2d", lambda: fields.grf((80, 90), 31), 16, dict(block=16,
+                                                     sample_rate=0.1), 1e-3),
+    ("3d_all", lambda: fields.grf((40, 36, 44), 32, log_normal=True), 8,
+     dict(block=8, sample_rate=0.2, all_orders=1), 1e-3),
+]
+
+
+@pytest.mark.parametrize("name,make,s,cfgkw,rel", ABL_CASES)
+def test_ablation_one_interpolator(ref, name, make, s, cfgkw, rel):
+    # every candidate applied to all levels, trial-compressed block by
+    # block at the uniform bound; the lowest bit rate (first on ties) wins
+    x = make()
+    d = x.ndim
+    vr = float(x.max()) - float(x.min())
+    e = rel * vr
+    cfg = ref.tune_config(**cfgkw, ablation=ref.ABLATE_LEVELWISE)
+    p, tr = ref.tune(x, e, "psnr", cfg, anchor_stride=s)
+    plan = ref.sample_plan(x.shape, s, cfg)
+    Lt = plan["Lt"]
+    blocks = extract_blocks(x, plan)
+    cands = candidates(d, bool(cfgkw.get("all_orders", 0)))
+    Bs = []
+    for t, o in cands:
+        b, _, _, _ = trial_blockwise(ref, blocks, d, Lt, [t] * 16, [o] * 16,
+                                     1.0, 1.5, e, vr, "cr")
+        Bs.append(b)
+    best = int(np.argmin(Bs))
+    assert [tr.alg1_err[0][c] for c in range(len(cands))] == Bs
+    L = int(math.log2(s))
+    for l in range(L):
+        assert p.interp[l] == cands[best][0]
+        assert tuple(p.order[l][j] for j in range(d)) == tuple(cands[best][1])
+    # the (alpha, beta) search still runs on top of the single choice
+    full = ref.tune(x, e, "psnr", ref.tune_config(
+        **cfgkw, ablation=ref.ABLATE_LEVELWISE | ref.ABLATE_AB),
+        anchor_stride=s)[0]
+    assert (full.alpha, full.beta) == (1.0, 1.5)
+    assert [full.interp[l] for l in range(L)] == [p.interp[l]
+                                                   for l in range(L)]
+
+
+@pytest.mark.parametrize("name,make,s,cfgkw,rel", ABL_CASES)
+def test_ablation_no_alpha_beta(ref, name, make, s, cfgkw, rel):
+    # Algorithm 1 unchanged; alpha = 1 (uniform bounds), the first pair
+    x = make()
+    d = x.ndim
+    e = rel * (float(x.max()) - float(x.min()))
+    p_full, tr_full = ref.tune(x, e, "psnr", ref.tune_config(**cfgkw),
+                               anchor_stride=s)
+    p, tr = ref.tune(x, e, "psnr", ref.tune_config(
+        **cfgkw, ablation=ref.ABLATE_AB), anchor_stride=s)
+    assert (p.alpha, p.beta) == (1.0, 1.5)
+    L = int(math.log2(s))
+    for l in range(L):
+        assert p.interp[l] == p_full.interp[l]
+        assert all(p.order[l][j] == p_full.order[l][j] for j in range(d))
+    assert tr.best_pair == 0
+    el, _, _ = ref.level_bounds(e, 1.0, 1.5, L)
+    assert np.all(el == e)
+
+
+def test_ablation_rejects_unknown_switches(ref):
+    x = fields.grf((40, 40), 3)
+    with pytest.raises(ref.OracleError):
+        ref.tune(x, 1e-3, "cr", ref.tune_config(ablation=4))
+
+
+@pytest.mark.parametrize("shape", [(70, 45), (33, 65, 17)])
+def test_anchorless_level_structure(ref, shape):
+    # the SZ3-style structure: one anchor at the origin and
+    # ceil(log2(max n)) levels; still within the bound
+    import paper_2310_14133_amd as q
+    x = fields.grf(shape, 4)
+    s = q.sz3_anchor_stride(shape)
+    assert s == 1 << math.ceil(math.log2(max(shape)))
+    e = 1e-3 * (float(x.max()) - float(x.min()))
+    p = ref.make_params(len(shape), "cubic", None, 1.0, 1.5, anchor_stride=s)
+    codes, recon, unpred, anchors = ref.predict_quantize(x, e, p)
+    assert anchors.size == 1 and anchors[0] == x.flat[0]
+    assert codes.size + unpred.size * 0 == x.size - 1
+    z = ref.compress(x, e, p)
+    assert ref.inspect(z)[2].levels == int(math.log2(s))
+    assert np.abs(x.astype(np.float64) - ref.decompress(z)).max() <= e
