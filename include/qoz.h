@@ -86,7 +86,18 @@ typedef struct {
   uint32_t all_orders;    /* 0: increasing and decreasing dimension orders
                              (Sec. VI-B); 1: all ndim! orders */
   uint32_t ssim_window;   /* 0 -> 7 */
+  uint32_t ablation;      /* QOZ_ABLATE_* switches; 0 = the whole method */
 } qoz_tune_config;
+
+/* Ablation switches (the component study of Sec. VII), each leaving one
+ * part of the tuner out.  QOZ_ABLATE_AB: no (alpha, beta) search, alpha = 1
+ * (every level at the bound).  QOZ_ABLATE_LEVELWISE: instead of Algorithm 1,
+ * one interpolator (type and dimension order) for every level, the
+ * candidate whose trial compression of the sampled blocks at the uniform
+ * bound has the lowest bit rate.  The anchor-less level structure is an
+ * anchor stride of the next power of two >= the largest dimension. */
+#define QOZ_ABLATE_AB 1u
+#define QOZ_ABLATE_LEVELWISE 2u
 
 typedef struct qoz_ctx qoz_ctx;
 

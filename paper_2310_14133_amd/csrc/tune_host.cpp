@@ -60,6 +60,53 @@ static uint32_t log2_floor(uint32_t v) {
   return l;
 }
 
+/* Huffman bits of the trials listed in `over`, whose used symbols
+ * overflowed the first device sort: a second device sort of up to
+ * kSortCapBig symbols, then whole histograms for any still larger.  May
+ * move the pinned staging. */
+static qoz_status overflow_bits(qoz_ctx* c, const std::vector<uint32_t>& over,
+                                const uint32_t* dhist,
+                                std::vector<uint64_t>& bits, hipStream_t s) {
+  const uint32_t no = (uint32_t)over.size();
+  std::vector<uint32_t> full;
+  if (hist_sort_big_fits()) {
+    const size_t kb = 8 * (size_t)(kSortCapBig + 1);
+    QOZ_TRY(ensure(c->hsort, kb * no));
+    QOZ_TRY(ensure(c->hsort_ids, 4 * (size_t)no));
+    QOZ_TRY(ensure_pinned(c, kb * no + 4 * (size_t)no + 64));
+    uint8_t* hp = (uint8_t*)c->pinned;
+    std::memcpy(hp, over.data(), 4 * (size_t)no);
+    QOZ_TRY(to_device(c, c->hsort_ids.p, hp, 4 * (size_t)no, s));
+    launch_hist_sort_big(dhist, (const uint32_t*)c->hsort_ids.p, no,
+                         (uint64_t*)c->hsort.p, s);
+    uint64_t* hk = (uint64_t*)(hp + ((4 * (size_t)no + 63) / 64) * 64);
+    QOZ_TRY(to_host(c, hk, c->hsort.p, kb * no, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < no; ++i) {
+      const uint64_t* kt = hk + (size_t)i * (kSortCapBig + 1);
+      if (kt[0] <= kSortCapBig)
+        bits[over[i]] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
+      else
+        full.push_back(over[i]);
+    }
+  } else {
+    full = over;
+  }
+  if (!full.empty()) {
+    const size_t hb = 4 * (size_t)kNSym;
+    QOZ_TRY(ensure_pinned(c, hb * full.size()));
+    uint8_t* hp = (uint8_t*)c->pinned;
+    for (size_t i = 0; i < full.size(); ++i)
+      QOZ_TRY(to_host(c, hp + i * hb, dhist + (size_t)full[i] * kNSym, hb, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < full.size(); ++i)
+      bits[full[i]] = huffman_cost((const uint32_t*)(hp + i * hb), kNSym);
+  }
+  return QOZ_OK;
+}
+
 }  // namespace qoz
 
 using namespace qoz;
@@ -98,6 +145,9 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   if (S < 1) S = 1;
   const uint32_t Lt = log2_floor(b < sa ? b : sa);
   const bool all_orders = cfg && cfg->all_orders;
+  const uint32_t abl = cfg ? cfg->ablation : 0u;
+  if (abl & ~(QOZ_ABLATE_AB | QOZ_ABLATE_LEVELWISE))
+    return fail(QOZ_EINVAL, "unknown ablation switch");
   const uint32_t w = (cfg && cfg->ssim_window) ? cfg->ssim_window : 7;
   if (w > 11) return fail(QOZ_EINVAL, "ssim_window must be <= 11");
   uint64_t m[3] = {1, 1, 1};
@@ -200,18 +250,27 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                           sizeof(TrialDesc) * (nslots + adesc_n) + 8 * rp +
                           12 * (size_t)bg.nb + 4096;
   QOZ_TRY(ensure_pinned(c, pin_need));
-  uint8_t* pbase = (uint8_t*)c->pinned + kPinTune;
-  uint32_t* h_hist = (uint32_t*)pbase;
-  double* h_sse = (double*)(pbase + 4 * (size_t)kNSym * max_trials);
-  /* per (trial, block) item: two partials (levels above 1, level 1) */
-  uint32_t* h_un = (uint32_t*)(h_sse + 2 * (size_t)nslots * bg.nb);
-  double* h_l1 = (double*)(pbase + 4 * (size_t)kNSym * max_trials +
-                           24 * (size_t)nslots * bg.nb);
-  double* h_ssim = h_l1 + (size_t)nslots * bg.nb;
-  TrialDesc* h_desc = (TrialDesc*)(h_ssim + ssim_np);
-  TrialDesc* h_adesc = h_desc + nslots;
-  float* h_range = (float*)(h_adesc + adesc_n);
-  uint32_t* h_status = (uint32_t*)(h_range + 2 * rp);
+  uint8_t* pbase;
+  uint32_t *h_hist, *h_un, *h_status;
+  double *h_sse, *h_l1, *h_ssim;
+  TrialDesc *h_desc, *h_adesc;
+  float* h_range;
+  /* regions of the pinned staging (again after anything that may move it) */
+  auto bind_pinned = [&]() {
+    pbase = (uint8_t*)c->pinned + kPinTune;
+    h_hist = (uint32_t*)pbase;
+    h_sse = (double*)(pbase + 4 * (size_t)kNSym * max_trials);
+    /* per (trial, block) item: two partials (levels above 1, level 1) */
+    h_un = (uint32_t*)(h_sse + 2 * (size_t)nslots * bg.nb);
+    h_l1 = (double*)(pbase + 4 * (size_t)kNSym * max_trials +
+                     24 * (size_t)nslots * bg.nb);
+    h_ssim = h_l1 + (size_t)nslots * bg.nb;
+    h_desc = (TrialDesc*)(h_ssim + ssim_np);
+    h_adesc = h_desc + nslots;
+    h_range = (float*)(h_adesc + adesc_n);
+    h_status = (uint32_t*)(h_range + 2 * rp);
+  };
+  bind_pinned();
 
   float* xs = (float*)c->tune_x.p;
   float* wc = (float*)c->tune_wc.p;
@@ -266,232 +325,257 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   double ueb[QOZ_MAX_LEVELS];
   float utw[QOZ_MAX_LEVELS], uiv[QOZ_MAX_LEVELS];
   level_bounds(e, 1.0, 1.0, Lt, ueb, utw, uiv);
-  /* every level's candidates go up at once; each level's choice and the
-   * commit of its working copy happen on the device, so the levels run
-   * back to back and the host reads the choices once */
-  std::memset(h_adesc, 0, sizeof(TrialDesc) * adesc_n);
-  for (uint32_t l = Lt; l >= 1; --l)
-    for (uint32_t ci = 0; ci < ncand; ++ci) {
-      TrialLevel& lv = h_adesc[(l - 1) * ncand + ci].lv[l - 1];
-      lv.twoeb = utw[l - 1];
-      lv.inv = uiv[l - 1];
-      lv.eb = ueb[l - 1];
-      lv.cubic = cands[ci].interp;
-      for (int j = 0; j < 3; ++j)
-        lv.order[j] = j < d ? cands[ci].order[j] + shift : 0;
-    }
-  QOZ_TRY(
-      to_device(c, dadesc, h_adesc, sizeof(TrialDesc) * Lt * ncand, s));
-  for (uint32_t l = Lt; l >= 1; --l) {
-    const bool in_lds = alg1_in_lds(bg, l);
-    {
-      hipEvent_t ev = prof_begin(c, s, PK_TUNE_ALG1);
-      launch_alg1_level(bg, l, xs, wc, wt, ncand, dadesc + (l - 1) * ncand,
-                        dl1, in_lds, s);
-      prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
-    }
-    /* level-l targets: points of the 2^(l-1) grid off the 2^l grid */
-    uint64_t on_fine = 1, on_coarse = 1;
-    for (int i = 0; i < 3; ++i) {
-      on_fine *= (bg.g.n[i] - 1) / (1u << (l - 1)) + 1;
-      on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
-    }
-    const double count = (double)(on_fine - on_coarse) * bg.nb;
-    launch_alg1_pick(bg, l, xs, dadesc + (l - 1) * ncand, dl1, ncand, count,
-                     dpick + (l - 1), wt, wc, in_lds, s);
-  }
-  uint32_t* h_pick = h_status + 8 + 3 * (size_t)bg.nb; /* after origins */
-  QOZ_TRY(to_host(c, h_pick, dpick, 4 * Lt, s));
-  QOZ_HIP(hipGetLastError());
-  QOZ_HIP(hipStreamSynchronize(s));
-  for (uint32_t l = Lt; l >= 1; --l) {
-    const uint32_t ib = h_pick[l - 1];
-    if (ib >= ncand) return fail(QOZ_EDEVICE, "bad tuner choice");
-    Is_interp[l - 1] = cands[ib].interp;
-    std::memcpy(Is_order[l - 1], cands[ib].order, 3);
-  }
-  for (uint32_t l = Lt + 1; l <= L; ++l) {
-    Is_interp[l - 1] = Is_interp[Lt - 1];
-    std::memcpy(Is_order[l - 1], Is_order[Lt - 1], 3);
-  }
-
-  /* ---- (alpha, beta) trials, deduplicated by level-bound vector ---- */
-  const int nf = target == QOZ_TARGET_CR ? 1 : 3;
-  const double factors[3] = {1.0, 0.8, 1.2};
-  struct Vec {
-    double eb[QOZ_MAX_LEVELS];
-    float tw[QOZ_MAX_LEVELS], iv[QOZ_MAX_LEVELS];
-  };
-  std::vector<Vec> vecs;
-  int trial_of[3][20];
-  for (int f = 0; f < nf; ++f)
-    for (int i = 0; i < 20; ++i) {
-      Vec v;
-      std::memset(&v, 0, sizeof(v));
-      const double ef = f == 0 ? e : e * factors[f];
-      level_bounds(ef, kAlpha[i / 4], kBeta[i % 4], Lt, v.eb, v.tw, v.iv);
-      int found = -1;
-      for (size_t k = 0; k < vecs.size(); ++k)
-        if (std::memcmp(&vecs[k], &v, sizeof(Vec)) == 0) {
-          found = (int)k;
-          break;
-        }
-      if (found < 0) {
-        found = (int)vecs.size();
-        vecs.push_back(v);
-      }
-      trial_of[f][i] = found;
-    }
-  const uint32_t ntrial = (uint32_t)vecs.size();
-  std::memset(h_desc, 0, sizeof(TrialDesc) * ntrial);
-  for (uint32_t t = 0; t < ntrial; ++t)
-    for (uint32_t l = 1; l <= Lt; ++l) {
-      TrialLevel& lv = h_desc[t].lv[l - 1];
-      lv.twoeb = vecs[t].tw[l - 1];
-      lv.inv = vecs[t].iv[l - 1];
-      lv.eb = vecs[t].eb[l - 1];
-      lv.cubic = Is_interp[l - 1];
-      for (int j = 0; j < 3; ++j)
-        lv.order[j] = j < d ? Is_order[l - 1][j] + shift : 0;
-    }
-  QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ntrial, s));
-  launch_zero_u32(dhist, (uint64_t)kNSym * ntrial, s);
-  {
-    hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
-    launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun,
-                 target == QOZ_TARGET_SSIM || target == QOZ_TARGET_AC, s);
-    prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ntrial);
-  }
-  if (target == QOZ_TARGET_SSIM) {
-    sj.batch = ntrial * bg.nb;
-    sj.c1 = (0.01 * vrange) * (0.01 * vrange);
-    sj.c2 = (0.03 * vrange) * (0.03 * vrange);
-    ssim_np = ssim_parts(sj);
-    hipEvent_t ev = prof_begin(c, s, PK_SSIM);
-    launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
-    prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
-    QOZ_TRY(to_host(c, h_ssim, c->ssim_part.p, 8 * ssim_np, s));
-  } else if (target == QOZ_TARGET_AC) {
-    double* p0 = (double*)c->ssim_part.p;
-    double* p1 = p0 + (size_t)ntrial * bg.nb;
-    hipEvent_t ev = prof_begin(c, s, PK_REDUCE);
-    launch_ac_items(xs, wt, ntrial, bg.nb, bg.size, bg.g.n[2], p0, p1, s);
-    prof_end(c, s, ev, PK_REDUCE, 16.0 * bsz * ntrial);
-    QOZ_TRY(to_host(c, h_ssim, p1, 16 * (size_t)ntrial * bg.nb, s));
-  }
-  /* used symbols of every trial histogram, sorted on the device */
-  QOZ_TRY(ensure(c->hsort, 8 * (size_t)(kSortCap + 1) * ntrial));
-  launch_hist_sort(dhist, ntrial, (uint64_t*)c->hsort.p, s);
-  uint64_t* h_keys = (uint64_t*)h_hist;
-  QOZ_TRY(to_host(c, h_keys, c->hsort.p,
-                  8 * (size_t)(kSortCap + 1) * ntrial, s));
-  QOZ_TRY(to_host(c, h_sse, dsse, 24 * (size_t)nslots * bg.nb, s));
-  QOZ_HIP(hipGetLastError());
-  QOZ_HIP(hipStreamSynchronize(s));
-  prof_collect(c);
-
   const double npts = (double)bg.size * bg.nb;
-  const uint64_t per_item = sj.batch ? ssim_np / sj.batch : 0;
-  const double nwin = (double)(sj.P - sj.wp + 1) * (double)(sj.Rn - sj.wr + 1) *
-                      (double)(sj.Cn - sj.wc + 1) * bg.nb;
-  std::vector<double> B(ntrial), M(ntrial, 0.0);
-  std::vector<uint64_t> bits(ntrial, 0), Us(ntrial, 0);
-  std::vector<uint32_t> over; /* trials with more used symbols than kSortCap */
-  for (uint32_t t = 0; t < ntrial; ++t) {
-    const uint64_t* kt = h_keys + (size_t)t * (kSortCap + 1);
-    if (kt[0] <= kSortCap)
-      bits[t] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
-    else
-      over.push_back(t);
-    uint64_t U = 0;
-    double sse = 0.0;
-    for (uint32_t k = 0; k < bg.nb; ++k) {
-      const size_t it = 2 * ((size_t)t * bg.nb + k);
-      U += h_un[it] + h_un[it + 1];
-      sse += h_sse[it] + h_sse[it + 1];
+  if (abl & QOZ_ABLATE_LEVELWISE) {
+    /* one interpolator for every level: each candidate trial-compresses
+     * the sampled blocks at the uniform bound; the lowest bit rate wins,
+     * the first on ties */
+    std::memset(h_desc, 0, sizeof(TrialDesc) * ncand);
+    for (uint32_t ci = 0; ci < ncand; ++ci)
+      for (uint32_t l = 1; l <= Lt; ++l) {
+        TrialLevel& lv = h_desc[ci].lv[l - 1];
+        lv.twoeb = utw[l - 1];
+        lv.inv = uiv[l - 1];
+        lv.eb = ueb[l - 1];
+        lv.cubic = cands[ci].interp;
+        for (int j = 0; j < 3; ++j)
+          lv.order[j] = j < d ? cands[ci].order[j] + shift : 0;
+      }
+    QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ncand, s));
+    launch_zero_u32(dhist, (uint64_t)kNSym * ncand, s);
+    {
+      hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
+      launch_trial(bg, xs, wt, ncand, ddesc, dhist, dsse, dun, false, s);
+      prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ncand);
     }
-    Us[t] = U;
-    if (target == QOZ_TARGET_PSNR) {
-      M[t] = sse == 0.0 ? std::numeric_limits<double>::infinity()
-                        : 20.0 * std::log10(vrange / std::sqrt(sse / npts));
-    } else if (target == QOZ_TARGET_SSIM) {
-      double sum = 0.0;
-      for (uint64_t q = 0; q < per_item * bg.nb; ++q)
-        sum += h_ssim[(uint64_t)t * bg.nb * per_item + q];
-      M[t] = sum / nwin;
+    QOZ_TRY(ensure(c->hsort, 8 * (size_t)(kSortCap + 1) * ncand));
+    launch_hist_sort(dhist, ncand, (uint64_t*)c->hsort.p, s);
+    uint64_t* hk = (uint64_t*)h_hist;
+    QOZ_TRY(to_host(c, hk, c->hsort.p, 8 * (size_t)(kSortCap + 1) * ncand,
+                    s));
+    QOZ_TRY(to_host(c, h_sse, dsse, 24 * (size_t)nslots * bg.nb, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    std::vector<uint64_t> cbits(ncand, 0), cU(ncand, 0);
+    std::vector<uint32_t> cover;
+    for (uint32_t ci = 0; ci < ncand; ++ci) {
+      const uint64_t* kt = hk + (size_t)ci * (kSortCap + 1);
+      if (kt[0] <= kSortCap)
+        cbits[ci] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
+      else
+        cover.push_back(ci);
+      for (uint32_t k = 0; k < bg.nb; ++k) {
+        const size_t it = 2 * ((size_t)ci * bg.nb + k);
+        cU[ci] += h_un[it] + h_un[it + 1];
+      }
+    }
+    if (!cover.empty()) QOZ_TRY(overflow_bits(c, cover, dhist, cbits, s));
+    bind_pinned();
+    double best = std::numeric_limits<double>::infinity();
+    uint32_t ib = 0;
+    for (uint32_t ci = 0; ci < ncand; ++ci) {
+      const double Bc = ((double)cbits[ci] + 32.0 * (double)cU[ci]) / npts;
+      if (Bc < best) {
+        best = Bc;
+        ib = ci;
+      }
+    }
+    for (uint32_t l = 0; l < QOZ_MAX_LEVELS; ++l) {
+      Is_interp[l] = cands[ib].interp;
+      std::memcpy(Is_order[l], cands[ib].order, 3);
+    }
+  }
+  if (!(abl & QOZ_ABLATE_LEVELWISE)) {
+    /* every level's candidates go up at once; each level's choice and the
+     * commit of its working copy happen on the device, so the levels run
+     * back to back and the host reads the choices once */
+    std::memset(h_adesc, 0, sizeof(TrialDesc) * adesc_n);
+    for (uint32_t l = Lt; l >= 1; --l)
+      for (uint32_t ci = 0; ci < ncand; ++ci) {
+        TrialLevel& lv = h_adesc[(l - 1) * ncand + ci].lv[l - 1];
+        lv.twoeb = utw[l - 1];
+        lv.inv = uiv[l - 1];
+        lv.eb = ueb[l - 1];
+        lv.cubic = cands[ci].interp;
+        for (int j = 0; j < 3; ++j)
+          lv.order[j] = j < d ? cands[ci].order[j] + shift : 0;
+      }
+    QOZ_TRY(
+        to_device(c, dadesc, h_adesc, sizeof(TrialDesc) * Lt * ncand, s));
+    for (uint32_t l = Lt; l >= 1; --l) {
+      const bool in_lds = alg1_in_lds(bg, l);
+      {
+        hipEvent_t ev = prof_begin(c, s, PK_TUNE_ALG1);
+        launch_alg1_level(bg, l, xs, wc, wt, ncand, dadesc + (l - 1) * ncand,
+                          dl1, in_lds, s);
+        prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
+      }
+      /* level-l targets: points of the 2^(l-1) grid off the 2^l grid */
+      uint64_t on_fine = 1, on_coarse = 1;
+      for (int i = 0; i < 3; ++i) {
+        on_fine *= (bg.g.n[i] - 1) / (1u << (l - 1)) + 1;
+        on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
+      }
+      const double count = (double)(on_fine - on_coarse) * bg.nb;
+      launch_alg1_pick(bg, l, xs, dadesc + (l - 1) * ncand, dl1, ncand, count,
+                       dpick + (l - 1), wt, wc, in_lds, s);
+    }
+    uint32_t* h_pick = h_status + 8 + 3 * (size_t)bg.nb; /* after origins */
+    QOZ_TRY(to_host(c, h_pick, dpick, 4 * Lt, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    for (uint32_t l = Lt; l >= 1; --l) {
+      const uint32_t ib = h_pick[l - 1];
+      if (ib >= ncand) return fail(QOZ_EDEVICE, "bad tuner choice");
+      Is_interp[l - 1] = cands[ib].interp;
+      std::memcpy(Is_order[l - 1], cands[ib].order, 3);
+    }
+    for (uint32_t l = Lt + 1; l <= L; ++l) {
+      Is_interp[l - 1] = Is_interp[Lt - 1];
+      std::memcpy(Is_order[l - 1], Is_order[Lt - 1], 3);
+    }
+  }
+
+  /* (alpha, beta); without the search the first pair, alpha = 1 */
+  int inc = 0;
+  if (!(abl & QOZ_ABLATE_AB)) {
+    /* ---- (alpha, beta) trials, deduplicated by level-bound vector ---- */
+    const int nf = target == QOZ_TARGET_CR ? 1 : 3;
+    const double factors[3] = {1.0, 0.8, 1.2};
+    struct Vec {
+      double eb[QOZ_MAX_LEVELS];
+      float tw[QOZ_MAX_LEVELS], iv[QOZ_MAX_LEVELS];
+    };
+    std::vector<Vec> vecs;
+    int trial_of[3][20];
+    for (int f = 0; f < nf; ++f)
+      for (int i = 0; i < 20; ++i) {
+        Vec v;
+        std::memset(&v, 0, sizeof(v));
+        const double ef = f == 0 ? e : e * factors[f];
+        level_bounds(ef, kAlpha[i / 4], kBeta[i % 4], Lt, v.eb, v.tw, v.iv);
+        int found = -1;
+        for (size_t k = 0; k < vecs.size(); ++k)
+          if (std::memcmp(&vecs[k], &v, sizeof(Vec)) == 0) {
+            found = (int)k;
+            break;
+          }
+        if (found < 0) {
+          found = (int)vecs.size();
+          vecs.push_back(v);
+        }
+        trial_of[f][i] = found;
+      }
+    const uint32_t ntrial = (uint32_t)vecs.size();
+    std::memset(h_desc, 0, sizeof(TrialDesc) * ntrial);
+    for (uint32_t t = 0; t < ntrial; ++t)
+      for (uint32_t l = 1; l <= Lt; ++l) {
+        TrialLevel& lv = h_desc[t].lv[l - 1];
+        lv.twoeb = vecs[t].tw[l - 1];
+        lv.inv = vecs[t].iv[l - 1];
+        lv.eb = vecs[t].eb[l - 1];
+        lv.cubic = Is_interp[l - 1];
+        for (int j = 0; j < 3; ++j)
+          lv.order[j] = j < d ? Is_order[l - 1][j] + shift : 0;
+      }
+    QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ntrial, s));
+    launch_zero_u32(dhist, (uint64_t)kNSym * ntrial, s);
+    {
+      hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
+      launch_trial(bg, xs, wt, ntrial, ddesc, dhist, dsse, dun,
+                   target == QOZ_TARGET_SSIM || target == QOZ_TARGET_AC, s);
+      prof_end(c, s, ev, PK_TUNE_TRIAL, 16.0 * bsz * ntrial);
+    }
+    if (target == QOZ_TARGET_SSIM) {
+      sj.batch = ntrial * bg.nb;
+      sj.c1 = (0.01 * vrange) * (0.01 * vrange);
+      sj.c2 = (0.03 * vrange) * (0.03 * vrange);
+      ssim_np = ssim_parts(sj);
+      hipEvent_t ev = prof_begin(c, s, PK_SSIM);
+      launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
+      prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
+      QOZ_TRY(to_host(c, h_ssim, c->ssim_part.p, 8 * ssim_np, s));
     } else if (target == QOZ_TARGET_AC) {
-      /* the blocks' rows together; errors nearest uncorrelated are best */
-      double ss = 0.0, lag = 0.0;
+      double* p0 = (double*)c->ssim_part.p;
+      double* p1 = p0 + (size_t)ntrial * bg.nb;
+      hipEvent_t ev = prof_begin(c, s, PK_REDUCE);
+      launch_ac_items(xs, wt, ntrial, bg.nb, bg.size, bg.g.n[2], p0, p1, s);
+      prof_end(c, s, ev, PK_REDUCE, 16.0 * bsz * ntrial);
+      QOZ_TRY(to_host(c, h_ssim, p1, 16 * (size_t)ntrial * bg.nb, s));
+    }
+    /* used symbols of every trial histogram, sorted on the device */
+    QOZ_TRY(ensure(c->hsort, 8 * (size_t)(kSortCap + 1) * ntrial));
+    launch_hist_sort(dhist, ntrial, (uint64_t*)c->hsort.p, s);
+    uint64_t* h_keys = (uint64_t*)h_hist;
+    QOZ_TRY(to_host(c, h_keys, c->hsort.p,
+                    8 * (size_t)(kSortCap + 1) * ntrial, s));
+    QOZ_TRY(to_host(c, h_sse, dsse, 24 * (size_t)nslots * bg.nb, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    prof_collect(c);
+
+    const uint64_t per_item = sj.batch ? ssim_np / sj.batch : 0;
+    const double nwin = (double)(sj.P - sj.wp + 1) *
+                        (double)(sj.Rn - sj.wr + 1) *
+                        (double)(sj.Cn - sj.wc + 1) * bg.nb;
+    std::vector<double> B(ntrial), M(ntrial, 0.0);
+    std::vector<uint64_t> bits(ntrial, 0), Us(ntrial, 0);
+    std::vector<uint32_t> over; /* more used symbols than kSortCap */
+    for (uint32_t t = 0; t < ntrial; ++t) {
+      const uint64_t* kt = h_keys + (size_t)t * (kSortCap + 1);
+      if (kt[0] <= kSortCap)
+        bits[t] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
+      else
+        over.push_back(t);
+      uint64_t U = 0;
+      double sse = 0.0;
       for (uint32_t k = 0; k < bg.nb; ++k) {
         const size_t it = 2 * ((size_t)t * bg.nb + k);
-        ss += h_ssim[it];
-        lag += h_ssim[it + 1];
+        U += h_un[it] + h_un[it + 1];
+        sse += h_sse[it] + h_sse[it + 1];
       }
-      const double len = (double)bg.g.n[2];
-      M[t] = -std::fabs(ac_from_sums(ss, lag, npts, npts / len * (len - 1)));
-    }
-  }
-  /* trials with many used symbols: a second device sort of up to
-   * kSortCapBig symbols, then whole histograms for any still larger; the
-   * pinned staging may move here, so nothing above reads it any more */
-  if (!over.empty()) {
-    const uint32_t no = (uint32_t)over.size();
-    std::vector<uint32_t> full;
-    if (hist_sort_big_fits()) {
-      const size_t kb = 8 * (size_t)(kSortCapBig + 1);
-      QOZ_TRY(ensure(c->hsort, kb * no));
-      QOZ_TRY(ensure(c->hsort_ids, 4 * (size_t)no));
-      QOZ_TRY(ensure_pinned(c, kb * no + 4 * (size_t)no + 64));
-      uint8_t* hp = (uint8_t*)c->pinned;
-      std::memcpy(hp, over.data(), 4 * (size_t)no);
-      QOZ_TRY(to_device(c, c->hsort_ids.p, hp, 4 * (size_t)no, s));
-      launch_hist_sort_big(dhist, (const uint32_t*)c->hsort_ids.p, no,
-                           (uint64_t*)c->hsort.p, s);
-      uint64_t* hk = (uint64_t*)(hp + ((4 * (size_t)no + 63) / 64) * 64);
-      QOZ_TRY(to_host(c, hk, c->hsort.p, kb * no, s));
-      QOZ_HIP(hipGetLastError());
-      QOZ_HIP(hipStreamSynchronize(s));
-      for (uint32_t i = 0; i < no; ++i) {
-        const uint64_t* kt = hk + (size_t)i * (kSortCapBig + 1);
-        if (kt[0] <= kSortCapBig)
-          bits[over[i]] = huffman_cost_sorted(kt + 1, (uint32_t)kt[0]);
-        else
-          full.push_back(over[i]);
+      Us[t] = U;
+      if (target == QOZ_TARGET_PSNR) {
+        M[t] = sse == 0.0 ? std::numeric_limits<double>::infinity()
+                          : 20.0 * std::log10(vrange / std::sqrt(sse / npts));
+      } else if (target == QOZ_TARGET_SSIM) {
+        double sum = 0.0;
+        for (uint64_t q = 0; q < per_item * bg.nb; ++q)
+          sum += h_ssim[(uint64_t)t * bg.nb * per_item + q];
+        M[t] = sum / nwin;
+      } else if (target == QOZ_TARGET_AC) {
+        /* the blocks' rows together; errors nearest uncorrelated are best */
+        double ss = 0.0, lag = 0.0;
+        for (uint32_t k = 0; k < bg.nb; ++k) {
+          const size_t it = 2 * ((size_t)t * bg.nb + k);
+          ss += h_ssim[it];
+          lag += h_ssim[it + 1];
+        }
+        const double len = (double)bg.g.n[2];
+        M[t] = -std::fabs(ac_from_sums(ss, lag, npts, npts / len * (len - 1)));
       }
-    } else {
-      full = over;
     }
-    if (!full.empty()) {
-      const size_t hb = 4 * (size_t)kNSym;
-      QOZ_TRY(ensure_pinned(c, hb * full.size()));
-      uint8_t* hp = (uint8_t*)c->pinned;
-      for (size_t i = 0; i < full.size(); ++i)
-        QOZ_TRY(to_host(c, hp + i * hb, dhist + (size_t)full[i] * kNSym, hb,
-                        s));
-      QOZ_HIP(hipGetLastError());
-      QOZ_HIP(hipStreamSynchronize(s));
-      for (size_t i = 0; i < full.size(); ++i)
-        bits[full[i]] =
-            huffman_cost((const uint32_t*)(hp + i * hb), kNSym);
-    }
-  }
-  for (uint32_t t = 0; t < ntrial; ++t)
-    B[t] = ((double)bits[t] + 32.0 * (double)Us[t]) / npts;
+    /* trials with many used symbols (may move the pinned staging: nothing
+     * below reads it) */
+    if (!over.empty()) QOZ_TRY(overflow_bits(c, over, dhist, bits, s));
+    for (uint32_t t = 0; t < ntrial; ++t)
+      B[t] = ((double)bits[t] + 32.0 * (double)Us[t]) / npts;
 
-  int inc = 0;
-  for (int i = 1; i < 20; ++i) {
-    const int tI = trial_of[0][inc], tII = trial_of[0][i];
-    const int cs = table1_case(B[tI], M[tI], B[tII], M[tII]);
-    if (cs == 1) continue;
-    if (cs == 2) {
-      inc = i;
-      continue;
+    for (int i = 1; i < 20; ++i) {
+      const int tI = trial_of[0][inc], tII = trial_of[0][i];
+      const int cs = table1_case(B[tI], M[tI], B[tII], M[tII]);
+      if (cs == 1) continue;
+      if (cs == 2) {
+        inc = i;
+        continue;
+      }
+      const int tp = trial_of[cs == 3 ? 1 : 2][i];
+      if (table1_line_prefers_II(B[tI], M[tI], B[tII], M[tII], B[tp], M[tp]))
+        inc = i;
     }
-    const int tp = trial_of[cs == 3 ? 1 : 2][i];
-    if (table1_line_prefers_II(B[tI], M[tI], B[tII], M[tII], B[tp], M[tp]))
-      inc = i;
   }
 
+  prof_collect(c);
   qoz_params p;
   std::memset(&p, 0, sizeof(p));
   p.anchor_stride = sa;

@@ -96,6 +96,11 @@ CASES = [
      1.0, 1.5),
     ("multi_chunk", lambda: fields.grf((3, 2500, 7), 11), 1e-4, 8, "cubic",
      None, 1.25, 3.0),
+    # anchor-less level structure (only the origin is an anchor)
+    ("anchorless_3d", lambda: fields.grf((40, 36, 44), 12), 1e-3, 64,
+     "cubic", None, 1.0, 1.5),
+    ("anchorless_2d", lambda: fields.grf((70, 45), 13), 1e-3, 128, "linear",
+     None, 1.5, 2.0),
     # about 4700 used symbols: the second, larger device sort
     ("noise_big_sort", lambda: np.random.default_rng(5).normal(
         size=(48, 40, 44)).astype(np.float32), 1e-4, 8, "cubic", None, 1.0,
@@ -276,6 +281,59 @@ def test_tune_parity(codec, ref, name, make, s, cfgkw, target, rel):
             (q.params_dict(gp, d), ref.params_to_dict(rp, d))
     # downstream: the GPU's parameters give the oracle's stream
     roundtrip_check(codec, ref, x, e, rp)
+
+
+ABLATION_CASES = [
+    ("2d_levelwise", lambda: fields.grf((80, 90), 31), 16,
+     dict(block=16, sample_rate=0.1), "psnr", 1e-3, 2),
+    ("3d_all_levelwise", lambda: fields.grf((40, 36, 44), 32,
+                                           log_normal=True), 8,
+     dict(block=8, sample_rate=0.2, all_orders=1), "psnr", 1e-3, 2),
+    ("3d_no_ab", lambda: fields.grf((40, 36, 44), 32), 8,
+     dict(block=8, sample_rate=0.2), "ssim", 1e-3, 1),
+    # the anchor-less structure with neither switch's part: the baseline
+    ("3d_sz3_like", lambda: fields.grf((40, 36, 44), 33), 64,
+     dict(block=16, sample_rate=0.3), "cr", 1e-3, 3),
+]
+
+
+@pytest.mark.parametrize("name,make,s,cfgkw,target,rel,abl", ABLATION_CASES)
+def test_tune_ablation_parity(codec, ref, name, make, s, cfgkw, target, rel,
+                              abl):
+    import paper_2310_14133_amd as q
+    x = make()
+    e = rel * (float(x.max()) - float(x.min()))
+    print(f"ablation case {name} switches {abl}", flush=True)
+    rp, tr = ref.tune(x, e, target, ref.tune_config(**cfgkw, ablation=abl),
+                      anchor_stride=s)
+    gp = codec.tune(to_dev(x), e, target,
+                    q.make_tune_config(**cfgkw, ablation=abl),
+                    anchor_stride=s)
+    d = x.ndim
+    if not abl & 2:
+        for l in range(tr.Lt, 0, -1):
+            errs = [tr.alg1_err[l - 1][c] for c in range(tr.ncand)]
+            if near_tie(errs, tr.alg1_choice[l - 1]):
+                pytest.skip(f"near tie in Algorithm 1 at level {l}")
+    if not abl & 1:
+        Ms = [tr.M[i] for i in range(20)]
+        if near_tie(Ms, tr.best_pair, 1e-7):
+            pytest.skip("near tie in the (alpha, beta) walk")
+    assert q.params_dict(gp, d) == ref.params_to_dict(rp, d)
+    if abl & 1:
+        assert (gp.alpha, gp.beta) == (1.0, 1.5)
+    if abl & 2:
+        assert len({(gp.interp[l], tuple(gp.order[l][j] for j in range(d)))
+                    for l in range(gp.levels)}) == 1
+    roundtrip_check(codec, ref, x, e, rp)
+
+
+def test_tune_ablation_rejects_unknown(codec):
+    import paper_2310_14133_amd as q
+    x = to_dev(fields.grf((40, 40), 3))
+    with pytest.raises(q.QozError) as err:
+        codec.tune(x, 1e-3, "cr", q.make_tune_config(ablation=4))
+    assert err.value.status == q.QOZ_EINVAL
 
 
 @pytest.mark.parametrize("n_syms", [12, 28])
