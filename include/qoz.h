@@ -163,6 +163,54 @@ qoz_status qoz_metrics(qoz_ctx* ctx, const float* d_x, const float* d_y,
 qoz_status qoz_error_ac(qoz_ctx* ctx, const float* d_x, const float* d_y,
                         qoz_shape shape, double* ac, hipStream_t stream);
 
+/* ---- Batches -------------------------------------------------------------
+ * Many fields of uneven shapes and bounds in one call.  Worker threads,
+ * each with a context and stream of its own (created on first use, kept
+ * with ctx), take fields from a shared queue, largest first, so one
+ * field's host steps (Huffman code, tuner decisions) overlap other fields'
+ * kernels.  Every field's result is the single-field call's, byte for
+ * byte.  The call first waits for `stream` (inputs written there are
+ * ready) and returns when every output is complete.  Different items must
+ * not share outputs. */
+typedef struct {
+  const float* d_x;          /* in: field (device) */
+  qoz_shape shape;           /* in */
+  double abs_eb;             /* in */
+  const qoz_params* params;  /* in: NULL = tune with the batch's target */
+  void* d_out;               /* in: stream buffer (device) */
+  size_t cap;                /* in: its capacity in bytes */
+  size_t out_bytes;          /* out: stream size (or size needed) */
+  qoz_status status;         /* out: the field's own status */
+  double ms;                 /* out: wall time of the field's call */
+  double done_ms;            /* out: completion time after the batch start */
+} qoz_batch_item;
+
+/* Compression of items[0..n): as qoz_compress for each (target and cfg
+ * apply to items without params).  workers: threads (0 = 4; at most 64).
+ * Returns QOZ_OK when every item succeeded, else the status of the first
+ * failing item in index order (each item keeps its own status).
+ * Errors: EINVAL (arguments), EDEVICE, ENOMEM, or an item's status. */
+qoz_status qoz_compress_batch(qoz_ctx* ctx, qoz_batch_item* items, uint32_t n,
+                              qoz_target target, const qoz_tune_config* cfg,
+                              uint32_t workers, hipStream_t stream);
+
+typedef struct {
+  const void* d_in;   /* in: stream (device) */
+  size_t in_bytes;    /* in */
+  float* d_y;         /* in: output field (device) */
+  size_t y_cap_elems; /* in */
+  qoz_shape shape;    /* out */
+  qoz_status status;  /* out */
+  double ms;          /* out */
+  double done_ms;     /* out */
+} qoz_batch_dec_item;
+
+/* Decompression of items[0..n): as qoz_decompress for each; workers and
+ * status as qoz_compress_batch. */
+qoz_status qoz_decompress_batch(qoz_ctx* ctx, qoz_batch_dec_item* items,
+                                uint32_t n, uint32_t workers,
+                                hipStream_t stream);
+
 /* ---- Learned tuner ------------------------------------------------------
  * A stand-in for the trial search of Sec. VI: a small network maps
  * features of the sampled blocks to the search's choices (one interpolation

@@ -42,6 +42,21 @@ class TuneConfig(C.Structure):
                 ("ssim_window", C.c_uint32), ("ablation", C.c_uint32)]
 
 
+class BatchItem(C.Structure):
+    _fields_ = [("d_x", C.c_void_p), ("shape", Shape), ("abs_eb", C.c_double),
+                ("params", C.c_void_p), ("d_out", C.c_void_p),
+                ("cap", C.c_size_t), ("out_bytes", C.c_size_t),
+                ("status", C.c_int), ("ms", C.c_double),
+                ("done_ms", C.c_double)]
+
+
+class BatchDecItem(C.Structure):
+    _fields_ = [("d_in", C.c_void_p), ("in_bytes", C.c_size_t),
+                ("d_y", C.c_void_p), ("y_cap_elems", C.c_size_t),
+                ("shape", Shape), ("status", C.c_int), ("ms", C.c_double),
+                ("done_ms", C.c_double)]
+
+
 class QozError(RuntimeError):
     def __init__(self, status, what, message=""):
         super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}"
@@ -78,6 +93,9 @@ def lib():
         L.qoz_metrics.argtypes = [vp, vp, vp, Shape, u32, C.POINTER(dbl),
                                   C.POINTER(dbl), C.POINTER(dbl), vp]
         L.qoz_error_ac.argtypes = [vp, vp, vp, Shape, C.POINTER(dbl), vp]
+        L.qoz_compress_batch.argtypes = [vp, vp, u32, C.c_int,
+                                         C.POINTER(TuneConfig), u32, vp]
+        L.qoz_decompress_batch.argtypes = [vp, vp, u32, u32, vp]
         L.qoz_learned_features.argtypes = [vp, vp, Shape, dbl,
                                            C.POINTER(TuneConfig), vp, vp,
                                            u64, C.POINTER(u64), vp]
@@ -98,7 +116,8 @@ def lib():
                                          C.POINTER(dbl), C.POINTER(dbl)]
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
-                   "qoz_metrics", "qoz_error_ac", "qoz_learned_features",
+                   "qoz_metrics", "qoz_error_ac", "qoz_compress_batch",
+                   "qoz_decompress_batch", "qoz_learned_features",
                    "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
                    "qoz_tune_learned", "qoz_ctx_set_timing",
                    "qoz_ctx_set_timing_mask",
@@ -252,6 +271,21 @@ def qoz_error_ac(ctx, d_x, d_y, shape, stream):
                               C.byref(ac), C.c_void_p(stream)),
            "qoz_error_ac")
     return ac.value
+
+
+def qoz_compress_batch(ctx, items, target, cfg, workers, stream):
+    """items: a ctypes array of BatchItem; returns the batch status
+    without raising (each item carries its own)."""
+    return lib().qoz_compress_batch(ctx, C.cast(items, C.c_void_p),
+                                    len(items), int(target),
+                                    C.byref(cfg) if cfg else None,
+                                    int(workers), C.c_void_p(stream))
+
+
+def qoz_decompress_batch(ctx, items, workers, stream):
+    return lib().qoz_decompress_batch(ctx, C.cast(items, C.c_void_p),
+                                      len(items), int(workers),
+                                      C.c_void_p(stream))
 
 
 MLP_NFEAT, MLP_NOUT, MLP_NPARAM = 32, 11, 22219
@@ -425,6 +459,61 @@ class Codec:
         sh = self._field(x)
         return qoz_metrics(self.ctx, x.data_ptr(), y.data_ptr(), sh,
                            ssim_window, self._stream(), want_ssim)
+
+    # ---- batches -------------------------------------------------------
+    def compress_batch(self, xs, abs_ebs, params=None, target="cr", cfg=None,
+                       workers=4):
+        """Compress a list of fields in one call.  params: None (tune each)
+        or a list of Params.  Returns (streams, items): uint8 tensors cut to
+        size, and the BatchItem array (status, ms, done_ms per field)."""
+        torch = self.torch
+        n = len(xs)
+        items = (BatchItem * n)()
+        outs = []
+        keep = []
+        for i, x in enumerate(xs):
+            sh = self._field(x)
+            cap = qoz_compress_bound(sh)
+            out = torch.empty(cap, dtype=torch.uint8, device=self.device)
+            outs.append(out)
+            it = items[i]
+            it.d_x, it.shape, it.abs_eb = x.data_ptr(), sh, float(abs_ebs[i])
+            if params is not None:
+                keep.append(params[i])
+                it.params = C.cast(C.pointer(params[i]), C.c_void_p)
+            it.d_out, it.cap = out.data_ptr(), cap
+        st = qoz_compress_batch(self.ctx, items, TARGETS[target], cfg,
+                                workers, self._stream())
+        if st != QOZ_OK:
+            bad = [i for i in range(n) if items[i].status != QOZ_OK]
+            raise QozError(st, f"qoz_compress_batch (fields {bad[:8]})",
+                           qoz_last_error())
+        return [outs[i][:items[i].out_bytes] for i in range(n)], items
+
+    def decompress_batch(self, zs, workers=4):
+        """Decompress a list of streams; returns (fields, items)."""
+        torch = self.torch
+        n = len(zs)
+        items = (BatchDecItem * n)()
+        ys = []
+        for i, z in enumerate(zs):
+            zc = z.contiguous()
+            if zc.numel() < HEADER_BYTES:
+                raise QozError(QOZ_EFORMAT, "decompress_batch",
+                               f"stream {i} too short")
+            sh, _, _ = qoz_inspect(zc[:HEADER_BYTES].cpu().numpy().tobytes())
+            dims = tuple(int(sh.dims[j]) for j in range(sh.ndim))
+            y = torch.empty(dims, dtype=torch.float32, device=self.device)
+            ys.append((zc, y))
+            it = items[i]
+            it.d_in, it.in_bytes = zc.data_ptr(), zc.numel()
+            it.d_y, it.y_cap_elems = y.data_ptr(), y.numel()
+        st = qoz_decompress_batch(self.ctx, items, workers, self._stream())
+        if st != QOZ_OK:
+            bad = [i for i in range(n) if items[i].status != QOZ_OK]
+            raise QozError(st, f"qoz_decompress_batch (fields {bad[:8]})",
+                           qoz_last_error())
+        return [y for _, y in ys], items
 
     # ---- learned tuner -------------------------------------------------
     def learned_features(self, x, abs_eb, cfg=None, per_block=False):

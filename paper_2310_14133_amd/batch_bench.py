@@ -1,0 +1,121 @@
+"""Batch workload: many fields of uneven shapes and bounds, compressed
+(tuned per field) and decompressed one call at a time and as batches.
+
+Workload (from one seed): 64 fields; one third 2D with sides U{256..2048},
+the rest 3D between 64^3 and 384 x 384 x 256 (each side U{64..its cap}),
+k^-3 random fields cut from the corner of one periodic field per shape
+family (one FFT size), value-range-relative bounds log-uniform in
+[1e-5, 1e-2].  Reports aggregate GB/s of input and p50 / p99 per-field
+latency for the loop and for batches of 4 and 8 workers.
+
+    python -m paper_2310_14133_amd.batch_bench --fields 64
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def workload(n_fields, seed, device="cuda"):
+    import torch
+    from paper_2310_14133_amd import fields
+    rng = np.random.default_rng(seed)
+    big3 = fields.grf_torch((384, 384, 256), seed, device=device)
+    big2 = fields.grf_torch((2048, 2048), seed + 1, device=device)
+    xs, ebs = [], []
+    for i in range(n_fields):
+        if i % 3 == 2:
+            sh = (int(rng.integers(256, 2049)), int(rng.integers(256, 2049)))
+            src = big2
+        else:
+            sh = (int(rng.integers(64, 385)), int(rng.integers(64, 385)),
+                  int(rng.integers(64, 257)))
+            src = big3
+        x = src[tuple(slice(0, v) for v in sh)].contiguous()
+        x = (x - x.mean()) / x.std()
+        xs.append(x.contiguous())
+        vr = float((x.max() - x.min()).item())
+        ebs.append(vr * 10.0 ** rng.uniform(-5.0, -2.0))
+    del big3, big2
+    torch.cuda.synchronize()
+    return xs, ebs
+
+
+def pct(v, p):
+    return float(np.percentile(np.asarray(v), p))
+
+
+def main(argv=None):
+    import torch
+    import paper_2310_14133_amd as q
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fields", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=400)
+    ap.add_argument("--workers", type=int, nargs="+", default=[4, 8])
+    ap.add_argument("--report", default="")
+    args = ap.parse_args(argv)
+    if not torch.cuda.is_available():
+        sys.exit("the batch bench runs on the GPU")
+    codec = q.Codec(0)
+    xs, ebs = workload(args.fields, args.seed)
+    total = sum(x.numel() * 4 for x in xs)
+    print(f"batch: {len(xs)} fields, {total / 1e9:.3f} GB", flush=True)
+    res = {"fields": len(xs), "bytes": total, "seed": args.seed}
+
+    def loop():
+        lat_c, lat_d, zs = [], [], []
+        t0 = time.perf_counter()
+        for x, e in zip(xs, ebs):
+            t = time.perf_counter()
+            z = codec.compress(x, e)
+            torch.cuda.synchronize()
+            lat_c.append((time.perf_counter() - t) * 1e3)
+            zs.append(z)
+        tc = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for z in zs:
+            t = time.perf_counter()
+            codec.decompress(z)
+            torch.cuda.synchronize()
+            lat_d.append((time.perf_counter() - t) * 1e3)
+        td = time.perf_counter() - t0
+        return tc, td, lat_c, lat_d, zs
+
+    loop()  # warm-up: scratch allocations, code objects
+    tc, td, lc, ld, zs_loop = loop()
+    res["loop"] = {"compress_GBps": total / tc / 1e9,
+                   "decompress_GBps": total / td / 1e9,
+                   "compress_p50_ms": pct(lc, 50), "compress_p99_ms": pct(lc, 99),
+                   "decompress_p50_ms": pct(ld, 50),
+                   "decompress_p99_ms": pct(ld, 99)}
+    print("batch: loop", json.dumps(res["loop"]), flush=True)
+    for w in args.workers:
+        codec.compress_batch(xs, ebs, workers=w)  # warm-up of the workers
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        zs, it = codec.compress_batch(xs, ebs, workers=w)
+        tc = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ys, dit = codec.decompress_batch(zs, workers=w)
+        td = time.perf_counter() - t0
+        same = all(torch.equal(a, b) for a, b in zip(zs, zs_loop))
+        r = {"compress_GBps": total / tc / 1e9,
+             "decompress_GBps": total / td / 1e9,
+             "compress_p50_ms": pct([i.ms for i in it], 50),
+             "compress_p99_ms": pct([i.ms for i in it], 99),
+             "decompress_p50_ms": pct([i.ms for i in dit], 50),
+             "decompress_p99_ms": pct([i.ms for i in dit], 99),
+             "streams_equal_loop": same}
+        res[f"batch_w{w}"] = r
+        print(f"batch: workers {w}", json.dumps(r), flush=True)
+        del ys
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(res, f, indent=1)
+    codec.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -51,8 +51,8 @@ def build(verbose=False, jobs=8):
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o",
-           LIB + ".tmp"] + objs
+    cmd = ["hipcc", "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}",
+           "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -170,7 +170,9 @@ qoz_status qoz_ctx_create(int hip_device, qoz_ctx** out) {
 
 void qoz_ctx_destroy(qoz_ctx* c) {
   if (!c) return;
+  for (qoz_ctx* w : c->workers) qoz_ctx_destroy(w);
   (void)hipSetDevice(c->device);
+  for (hipStream_t st : c->worker_streams) (void)hipStreamDestroy(st);
   DevBuf* bufs[] = {&c->W,          &c->codes,      &c->hist,
                     &c->chunk_bits, &c->chunk_zeros, &c->coff,
                     &c->upre,       &c->status,     &c->enc_table,

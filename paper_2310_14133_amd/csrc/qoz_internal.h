@@ -200,6 +200,9 @@ struct qoz_ctx {
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
       hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids;
+  /* batch workers: their contexts and streams */
+  std::vector<qoz_ctx*> workers;
+  std::vector<hipStream_t> worker_streams;
   /* pinned host staging */
   void* pinned = nullptr;
   void* pinned_dev = nullptr; /* its device address */
