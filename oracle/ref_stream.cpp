@@ -15,7 +15,20 @@
  * then segment 1, and so on; the stream keeps the payload bits of segments
  * 0..6 (0 for an empty segment), so each segment can be decoded on its own.
  * Unpredictable values stay in bin order.  No dictionary (zstd) stage
- * follows the Huffman stage.
+ * follows the Huffman stage; a lossless zero-word packing may (below).
+ *
+ * Zero-word packing (format version 5; version 4 streams are unpacked):
+ * runs of the zero bin, whose canonical code is all zero bits when it is
+ * the most frequent symbol, leave whole payload words at zero.  Chunk c
+ * of n_c raw words with z_c nonzero words is stored as a bitmap of
+ * ceil(n_c / 32) words (bit i of bitmap word k, least significant first,
+ * set when raw word 32 k + i is nonzero) followed by its nonzero words in
+ * order, when that is shorter than n_c words; otherwise raw.  The stream
+ * is packed only when the packed payload is at most 97 % of the raw one;
+ * byte 196 of the header then holds the packed word count W_p, the
+ * payload section holds W_p words, and an 8-aligned section of packed
+ * chunk word offsets u64[C+1] follows it (a chunk is raw exactly when its
+ * packed and raw word counts agree).
  */
 #include <cmath>
 #include <cstring>
@@ -31,6 +44,7 @@ const size_t kHeader = 200;
 
 struct Counts {
   uint64_t n_anchor, n_codes, n_unpred, n_used, n_chunks, n_words;
+  uint64_t n_packed; /* packed payload words; 0 for an unpacked stream */
 };
 
 /* Chunking of the bin stream by level: level l (levels L..1 in stream
@@ -72,7 +86,7 @@ void chunk_range(const Regions& R, uint64_t ch, uint64_t* lo, uint64_t* hi) {
 }
 
 struct Layout {
-  size_t anchors, syms, lens, coff, upre, segs, unpred, payload, total;
+  size_t anchors, syms, lens, coff, upre, segs, unpred, payload, pcoff, total;
 };
 
 const uint32_t kSegPerChunk = QREF_CHUNK / QREF_SEG;
@@ -99,9 +113,47 @@ Layout layout_of(const Counts& c) {
   l.unpred = off;
   off = al8(off + 4 * c.n_unpred);
   l.payload = off;
-  off = off + 4 * c.n_words;
+  if (c.n_packed) {
+    off = al8(off + 4 * c.n_packed);
+    l.pcoff = off;
+    off = off + 8 * (c.n_chunks + 1);
+  } else {
+    off = off + 4 * c.n_words;
+    l.pcoff = 0;
+  }
   l.total = off;
   return l;
+}
+
+/* Zero-word packing of the chunked payload (raw word offsets coff):
+ * packed words and packed offsets pcoff; returns whether the stream is
+ * worth packing (packed <= 97 % of raw). */
+bool pack_payload(const std::vector<uint32_t>& words,
+                  const std::vector<uint64_t>& coff, uint64_t n_chunks,
+                  std::vector<uint32_t>* packed,
+                  std::vector<uint64_t>* pcoff) {
+  packed->clear();
+  pcoff->assign(n_chunks + 1, 0);
+  for (uint64_t ch = 0; ch < n_chunks; ++ch) {
+    (*pcoff)[ch] = packed->size();
+    const uint64_t w0 = coff[ch], n = coff[ch + 1] - coff[ch];
+    uint64_t nz = 0;
+    for (uint64_t i = 0; i < n; ++i) nz += words[w0 + i] != 0;
+    const uint64_t nbm = (n + 31) / 32;
+    if (nbm + nz < n) {
+      std::vector<uint32_t> bm(nbm, 0);
+      for (uint64_t i = 0; i < n; ++i)
+        if (words[w0 + i]) bm[i / 32] |= 1u << (i % 32);
+      packed->insert(packed->end(), bm.begin(), bm.end());
+      for (uint64_t i = 0; i < n; ++i)
+        if (words[w0 + i]) packed->push_back(words[w0 + i]);
+    } else {
+      packed->insert(packed->end(), words.begin() + w0,
+                     words.begin() + w0 + n);
+    }
+  }
+  (*pcoff)[n_chunks] = packed->size();
+  return !words.empty() && 100 * packed->size() <= 97 * words.size();
 }
 
 template <class T>
@@ -218,6 +270,10 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   coff[c.n_chunks] = words.size();
   upre[c.n_chunks] = (uint32_t)zeros;
   c.n_words = words.size();
+  std::vector<uint32_t> pwords;
+  std::vector<uint64_t> pcoff;
+  const bool packed = pack_payload(words, coff, c.n_chunks, &pwords, &pcoff);
+  c.n_packed = packed ? pwords.size() : 0;
 
   Layout lay = layout_of(c);
   if (cap < lay.total || !out) {
@@ -227,7 +283,7 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   uint8_t* o = (uint8_t*)out;
   std::memset(o, 0, lay.total);
   std::memcpy(o, "QOZ1", 4);
-  put<uint16_t>(o, 4, 4);
+  put<uint16_t>(o, 4, packed ? 5 : 4);
   put<uint8_t>(o, 6, (uint8_t)g.d);
   put<uint8_t>(o, 7, (uint8_t)kSegLog2);
   for (int i = 0; i < 3; ++i)
@@ -253,6 +309,7 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   put<uint64_t>(o, 176, c.n_words);
   put<uint64_t>(o, 184, R.start[R.n - 1]); /* bins before level 1 */
   put<uint32_t>(o, 192, 1024);            /* smallest chunk size */
+  put<uint32_t>(o, 196, (uint32_t)c.n_packed);
   std::memcpy(o + lay.anchors, anchors.data(), 4 * n_anchor);
   uint64_t k = 0;
   for (uint32_t s = 0; s < nsym; ++s)
@@ -268,7 +325,13 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   for (size_t k = 0; k < segs.size(); ++k)
     put<uint16_t>(o, lay.segs + 2 * k, segs[k]);
   std::memcpy(o + lay.unpred, unpred.data(), 4 * n_unpred);
-  std::memcpy(o + lay.payload, words.data(), 4 * c.n_words);
+  if (packed) {
+    std::memcpy(o + lay.payload, pwords.data(), 4 * c.n_packed);
+    for (uint64_t ch = 0; ch <= c.n_chunks; ++ch)
+      put<uint64_t>(o, lay.pcoff + 8 * ch, pcoff[ch]);
+  } else {
+    std::memcpy(o + lay.payload, words.data(), 4 * c.n_words);
+  }
   *out_bytes = lay.total;
   return QREF_OK;
 }
@@ -288,7 +351,8 @@ struct Parsed {
 int parse(const uint8_t* in, size_t n, Parsed* P) {
   if (!in || n < kHeader) return QREF_EFORMAT;
   if (std::memcmp(in, "QOZ1", 4) != 0) return QREF_EFORMAT;
-  if (get<uint16_t>(in, 4) != 4) return QREF_EFORMAT;
+  const uint16_t ver = get<uint16_t>(in, 4);
+  if (ver != 4 && ver != 5) return QREF_EFORMAT;
   if (get<uint8_t>(in, 7) != kSegLog2) return QREF_EFORMAT;
   qref_shape sh;
   std::memset(&sh, 0, sizeof(sh));
@@ -320,6 +384,9 @@ int parse(const uint8_t* in, size_t n, Parsed* P) {
   c.n_used = get<uint64_t>(in, 160);
   c.n_chunks = get<uint64_t>(in, 168);
   c.n_words = get<uint64_t>(in, 176);
+  c.n_packed = get<uint32_t>(in, 196);
+  if ((ver == 5) != (c.n_packed != 0)) return QREF_EFORMAT;
+  if (100 * c.n_packed > 97 * c.n_words) return QREF_EFORMAT;
   int64_t A = count_anchors(P->g, P->p.anchor_stride);
   if (c.n_anchor != (uint64_t)A) return QREF_EFORMAT;
   if (c.n_codes != (uint64_t)P->g.N - (uint64_t)A) return QREF_EFORMAT;
@@ -399,6 +466,45 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
     }
   }
 
+  /* the raw payload: as stored, or expanded from its zero-word packing */
+  std::vector<uint32_t> raw((size_t)c.n_words, 0);
+  if (!c.n_packed) {
+    std::memcpy(raw.data(), in + lay.payload, 4 * c.n_words);
+  } else {
+    uint64_t prev_p = 0;
+    for (uint64_t ch = 0; ch <= c.n_chunks; ++ch) {
+      const uint64_t pc = get<uint64_t>(in, lay.pcoff + 8 * ch);
+      if ((ch == 0 && pc != 0) || pc < prev_p) return QREF_EFORMAT;
+      prev_p = pc;
+    }
+    if (prev_p != c.n_packed) return QREF_EFORMAT;
+    for (uint64_t ch = 0; ch < c.n_chunks; ++ch) {
+      const uint64_t w0 = get<uint64_t>(in, lay.coff + 8 * ch);
+      const uint64_t w1 = get<uint64_t>(in, lay.coff + 8 * (ch + 1));
+      const uint64_t p0 = get<uint64_t>(in, lay.pcoff + 8 * ch);
+      const uint64_t p1 = get<uint64_t>(in, lay.pcoff + 8 * (ch + 1));
+      if (w1 < w0 || w1 > c.n_words) return QREF_EFORMAT;
+      const uint64_t n = w1 - w0, np = p1 - p0;
+      if (np > n) return QREF_EFORMAT;
+      const size_t pw = lay.payload + 4 * p0;
+      if (np == n) {
+        std::memcpy(raw.data() + w0, in + pw, 4 * n);
+        continue;
+      }
+      const uint64_t nbm = (n + 31) / 32;
+      if (np < nbm) return QREF_EFORMAT;
+      uint64_t k = nbm;
+      for (uint64_t i = 0; i < 32 * nbm; ++i) {
+        const uint32_t bm = get<uint32_t>(in, pw + 4 * (i / 32));
+        if (!((bm >> (i % 32)) & 1u)) continue;
+        if (i >= n || k >= np) return QREF_EFORMAT;
+        raw[w0 + i] = get<uint32_t>(in, pw + 4 * k);
+        ++k;
+      }
+      if (k != np) return QREF_EFORMAT;
+    }
+  }
+
   /* decode each chunk bit by bit */
   std::vector<int32_t> codes((size_t)c.n_codes);
   uint64_t zeros = 0;
@@ -434,8 +540,7 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
         int l = 0;
         for (;;) {
           if (bitpos >= nbits) return QREF_EFORMAT;
-          uint32_t word =
-              get<uint32_t>(in, lay.payload + 4 * (w0 + bitpos / 32));
+          uint32_t word = raw[w0 + bitpos / 32];
           uint32_t bit = (word >> (31 - (bitpos % 32))) & 1u;
           ++bitpos;
           v = (v << 1) | bit;

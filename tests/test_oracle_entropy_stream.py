@@ -270,3 +270,148 @@ def test_segment_table(ref, shape, rel):
         bad = z.copy()
         bad[off + 2 * (7 * (n_chunks - 1) + 6)] = 1
         assert ref.decompress_status(bad) == ref.EFORMAT
+
+
+# ---- zero-word packing (format version 5) ----
+def _sections(z):
+    """Offsets of the payload and of the packed offsets, and the counts."""
+    u64 = lambda o: int(np.frombuffer(z[o:o + 8].tobytes(), np.uint64)[0])
+    u32 = lambda o: int(np.frombuffer(z[o:o + 4].tobytes(), np.uint32)[0])
+    al8 = lambda v: (v + 7) // 8 * 8
+    n_anchor, n_unpred = u64(136), u64(152)
+    n_used, n_chunks, n_words = u64(160), u64(168), u64(176)
+    off = al8(200 + 4 * n_anchor)
+    off = al8(off + 2 * n_used)
+    off = al8(off + n_used)
+    coff_at = off
+    off = al8(off + 8 * (n_chunks + 1))
+    off = al8(off + 4 * (n_chunks + 1))
+    off = al8(off + 14 * n_chunks)
+    payload = al8(off + 4 * n_unpred)
+    wp = u32(196)
+    coff = np.frombuffer(z[coff_at:coff_at + 8 * (n_chunks + 1)].tobytes(),
+                         np.uint64).astype(np.int64)
+    return payload, wp, n_words, n_chunks, coff
+
+
+def _raw_payload(ref, x, e, p, s):
+    """The chunked MSB-first Huffman payload re-derived from the bins and
+    the canonical code, chunk by chunk, segment by segment."""
+    codes, _, _, _ = ref.predict_quantize(x, e, p)
+    hist = np.bincount(codes, minlength=65536).astype(np.uint64)
+    ln = ref.huffman_lengths(hist).astype(np.int64)
+    cd = ref.huffman_codes(ln.astype(np.uint8)).astype(np.uint64)
+    _, sizes = chunk_sizes(x.shape, s, codes.size)
+    words, coff, lo = [], [0], 0
+    for m in sizes:
+        bits = []
+        for j in range(8):
+            for sym in codes[lo + j:lo + m:8]:
+                L = int(ln[sym])
+                v = int(cd[sym])
+                bits.extend((v >> (L - 1 - b)) & 1 for b in range(L))
+        bits += [0] * (-len(bits) % 32)
+        for k in range(0, len(bits), 32):
+            w = 0
+            for b in bits[k:k + 32]:
+                w = (w << 1) | b
+            words.append(w)
+        coff.append(len(words))
+        lo += m
+    return np.array(words, np.uint64), np.array(coff, np.int64)
+
+
+def _pack(words, coff):
+    """Bitmap + nonzero words per chunk when shorter than the raw chunk."""
+    out, pcoff = [], [0]
+    for c in range(len(coff) - 1):
+        w = words[coff[c]:coff[c + 1]]
+        n = len(w)
+        nz = int(np.count_nonzero(w))
+        nbm = -(-n // 32)
+        if nbm + nz < n:
+            bm = [0] * nbm
+            for i in np.nonzero(w)[0]:
+                bm[i // 32] |= 1 << (i % 32)
+            out += bm + [int(v) for v in w if v]
+        else:
+            out += [int(v) for v in w]
+        pcoff.append(len(out))
+    return np.array(out, np.uint64), np.array(pcoff, np.int64)
+
+
+def test_zero_word_packing_layout(ref):
+    # a smooth field at a loose bound: mostly the zero bin, whose code is
+    # all zero bits, so whole payload words vanish
+    x = fields.bumps_and_waves(160, 2)
+    e = 1e-2 * (float(x.max()) - float(x.min()))
+    s = 64
+    p = ref.make_params(2, "cubic", None, 1.0, 1.5, anchor_stride=s)
+    z = ref.compress(x, e, p)
+    assert int(np.frombuffer(z[4:6].tobytes(), np.uint16)[0]) == 5
+    payload, wp, n_words, n_chunks, coff = _sections(z)
+    raw, coff_r = _raw_payload(ref, x, e, p, s)
+    assert raw.size == n_words and np.array_equal(coff, coff_r)
+    packed, pcoff = _pack(raw, coff_r)
+    assert packed.size == wp and 100 * wp <= 97 * n_words
+    got = np.frombuffer(z[payload:payload + 4 * wp].tobytes(), np.uint32)
+    assert np.array_equal(got.astype(np.uint64), packed)
+    pc_at = (payload + 4 * wp + 7) // 8 * 8
+    got_pc = np.frombuffer(z[pc_at:pc_at + 8 * (n_chunks + 1)].tobytes(),
+                           np.uint64).astype(np.int64)
+    assert np.array_equal(got_pc, pcoff) and z.size == pc_at + 8 * (n_chunks + 1)
+    # and it decodes to the predictor's reconstruction
+    _, recon, _, _ = ref.predict_quantize(x, e, p)
+    assert np.array_equal(ref.decompress(z), recon)
+
+
+def test_rough_field_stays_unpacked(ref):
+    x = fields.grf((50, 60, 40), 3)
+    e = 1e-3 * (float(x.max()) - float(x.min()))
+    z = ref.compress(x, e, ref.make_params(3, "cubic", None, 1.0, 1.5))
+    assert int(np.frombuffer(z[4:6].tobytes(), np.uint16)[0]) == 4
+    assert int(np.frombuffer(z[196:200].tobytes(), np.uint32)[0]) == 0
+
+
+def test_packing_lifts_the_one_bit_floor(ref):
+    # without packing every bin costs at least one bit (ratio <= 32)
+    x = fields.bumps_and_waves(256, 1)
+    e = 1e-2 * (float(x.max()) - float(x.min()))
+    z = ref.compress(x, e, ref.make_params(2, "cubic", None, 1.0, 1.5))
+    assert x.nbytes / z.size > 32
+
+
+def test_packed_stream_corruptions(ref):
+    x = fields.bumps_and_waves(160, 2)
+    e = 1e-2 * (float(x.max()) - float(x.min()))
+    p = ref.make_params(2, "cubic", None, 1.0, 1.5, anchor_stride=64)
+    z = ref.compress(x, e, p)
+    payload, wp, n_words, n_chunks, coff = _sections(z)
+    pc_at = (payload + 4 * wp + 7) // 8 * 8
+
+    def status(b):
+        return ref.decompress_status(b)
+
+    bad = z.copy()
+    bad[4] = 4  # version 4 with a packed count
+    assert status(bad) == ref.EFORMAT
+    bad = z.copy()
+    bad[pc_at + 8:pc_at + 16] = np.frombuffer(
+        np.array([wp + 5], np.uint64).tobytes(), np.uint8)
+    assert status(bad) == ref.EFORMAT
+    # a bitmap bit past the chunk's last word
+    pcs = np.frombuffer(z[pc_at:pc_at + 8 * (n_chunks + 1)].tobytes(),
+                        np.uint64).astype(np.int64)
+    for c in range(n_chunks):
+        n = coff[c + 1] - coff[c]
+        if pcs[c + 1] - pcs[c] < n and n % 32:
+            nbm = -(-n // 32)
+            at = payload + 4 * (pcs[c] + nbm - 1)
+            w = int(np.frombuffer(z[at:at + 4].tobytes(), np.uint32)[0])
+            bad = z.copy()
+            bad[at:at + 4] = np.frombuffer(
+                np.array([w | (1 << 31)], np.uint32).tobytes(), np.uint8)
+            assert status(bad) == ref.EFORMAT
+            break
+    else:
+        pytest.fail("no packed chunk with a partial bitmap word")
