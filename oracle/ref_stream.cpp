@@ -24,7 +24,9 @@
  * ceil(n_c / 32) words (bit i of bitmap word k, least significant first,
  * set when raw word 32 k + i is nonzero) followed by its nonzero words in
  * order, when that is shorter than n_c words; otherwise raw.  The stream
- * is packed only when the packed payload is at most 97 % of the raw one;
+ * is packed only when the packed payload and its offset section together
+ * take at most 97 % of the raw payload's bytes (the stage never grows a
+ * stream);
  * byte 196 of the header then holds the packed word count W_p, the
  * payload section holds W_p words, and an 8-aligned section of packed
  * chunk word offsets u64[C+1] follows it (a chunk is raw exactly when its
@@ -127,7 +129,7 @@ Layout layout_of(const Counts& c) {
 
 /* Zero-word packing of the chunked payload (raw word offsets coff):
  * packed words and packed offsets pcoff; returns whether the stream is
- * worth packing (packed <= 97 % of raw). */
+ * worth packing (packed words + offsets <= 97 % of the raw bytes). */
 bool pack_payload(const std::vector<uint32_t>& words,
                   const std::vector<uint64_t>& coff, uint64_t n_chunks,
                   std::vector<uint32_t>* packed,
@@ -153,7 +155,8 @@ bool pack_payload(const std::vector<uint32_t>& words,
     }
   }
   (*pcoff)[n_chunks] = packed->size();
-  return !words.empty() && 100 * packed->size() <= 97 * words.size();
+  return !words.empty() &&
+         100 * (packed->size() + 2 * (n_chunks + 1)) <= 97 * words.size();
 }
 
 template <class T>
@@ -386,7 +389,8 @@ int parse(const uint8_t* in, size_t n, Parsed* P) {
   c.n_words = get<uint64_t>(in, 176);
   c.n_packed = get<uint32_t>(in, 196);
   if ((ver == 5) != (c.n_packed != 0)) return QREF_EFORMAT;
-  if (100 * c.n_packed > 97 * c.n_words) return QREF_EFORMAT;
+  if (c.n_packed && 100 * (c.n_packed + 2 * (c.n_chunks + 1)) > 97 * c.n_words)
+    return QREF_EFORMAT;
   int64_t A = count_anchors(P->g, P->p.anchor_stride);
   if (c.n_anchor != (uint64_t)A) return QREF_EFORMAT;
   if (c.n_codes != (uint64_t)P->g.N - (uint64_t)A) return QREF_EFORMAT;
