@@ -58,6 +58,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   QOZ_TRY(ensure(c->coff, 8 * (nch + 1)));
   QOZ_TRY(ensure(c->scan, chunk_scan_scratch(nch)));
   QOZ_TRY(ensure(c->upre, 4 * (nch + 1)));
+  QOZ_TRY(ensure(c->pcoff, 8 * (nch + 1)));
   QOZ_TRY(ensure(c->enc_table, 8 * kNSym));
   float* W = (float*)c->W.p;
   uint16_t* codes = (uint16_t*)c->codes.p;
@@ -221,14 +222,56 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
                           (uint16_t*)(out + lay.segs),
                           (uint32_t*)(out + lay.payload),
                           (cap - lay.payload) / 4, (float*)(out + lay.unpred),
-                          d_x, P.g, tbl, (uint32_t)max_chunk_words, st, s));
+                          d_x, P.g, tbl, (uint32_t)max_chunk_words, st,
+                          (uint32_t*)c->chunk_bits.p, s));
+  /* each chunk's size under zero-word packing (from the encoder, in
+   * chunk_bits, free again after the first scan), scanned into the packed
+   * offsets and total; upre and chunk_zeros are spent by now */
+  uint64_t* pcoff = (uint64_t*)c->pcoff.p;
+  PROF(PK_PACK, 8.0 * nch,
+       launch_chunk_scan((uint32_t*)c->chunk_bits.p,
+                         (uint32_t*)c->chunk_zeros.p, nch, pcoff,
+                         (uint32_t*)c->upre.p, totals, (uint64_t*)c->scan.p,
+                         s));
   QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus + 64), totals, 24, s));
   QOZ_TRY(sync_checked(s));
-  prof_collect(c);
   if (((uint32_t*)pin(c, kPinStatus))[0] & kStOverflow) {
+    prof_collect(c);
     *out_bytes = lay.total;
     return fail(QOZ_ENOSPACE, "output capacity too small");
   }
+  /* zero-word packing, when the packed payload and its offsets take at
+   * most kPackPercent % of the raw payload's bytes */
+  const uint64_t n_packed = ((const uint64_t*)pin(c, kPinStatus + 64))[0];
+  if (n_words &&
+      100 * (n_packed + 2 * (nch + 1)) <= (uint64_t)kPackPercent * n_words) {
+    const Layout lp =
+        layout_of(P.n_anchor, n_used, nch, n_unpred, n_words, n_packed);
+    QOZ_TRY(ensure(c->ptmp, 4 * n_packed + 4));
+    uint32_t* raw = (uint32_t*)(out + lay.payload);
+    PROF(PK_PACK, 4.0 * n_words + 4.0 * n_packed + 8.0 * nch,
+         launch_pack_write(raw, (const uint64_t*)c->coff.p, pcoff, nch,
+                           (uint32_t*)c->ptmp.p, s));
+    QOZ_HIP(hipMemcpyAsync(raw, c->ptmp.p, 4 * n_packed,
+                           hipMemcpyDeviceToDevice, s));
+    /* the padding word before the offsets reads as zero */
+    if (lp.pcoff > lay.payload + 4 * n_packed)
+      launch_zero_u32((uint32_t*)(out + lay.payload + 4 * n_packed),
+                      (lp.pcoff - lay.payload - 4 * n_packed) / 4, s);
+    QOZ_HIP(hipMemcpyAsync(out + lp.pcoff, pcoff, 8 * (nch + 1),
+                           hipMemcpyDeviceToDevice, s));
+    const uint16_t ver = kStreamVersionPacked;
+    const uint32_t npk = (uint32_t)n_packed;
+    std::memcpy(hs + 4, &ver, 2);
+    std::memcpy(hs + 196, &npk, 4);
+    QOZ_TRY(to_device(c, out, hs, kHeaderBytes, s));
+    QOZ_TRY(sync_checked(s));
+    prof_collect(c);
+    *out_bytes = lp.total;
+    return QOZ_OK;
+  }
+  prof_collect(c);
   *out_bytes = lay.total;
   return QOZ_OK;
 }
@@ -282,8 +325,9 @@ qoz_status qoz_inspect(const void* h_in, size_t in_bytes, qoz_shape* shape,
   if (!h_in) return fail(QOZ_EFORMAT, "NULL stream");
   Plan P;
   uint64_t nu, nused, nw;
+  uint64_t npk_unused;
   QOZ_TRY(parse_header((const uint8_t*)h_in, in_bytes, false, &P, &nu, &nused,
-                       &nw));
+                       &nw, &npk_unused));
   if (shape) {
     std::memset(shape, 0, sizeof(*shape));
     shape->ndim = (uint32_t)P.d;
@@ -323,12 +367,13 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   QOZ_TRY(sync_checked(s));
   Plan P;
   uint64_t nu, nused, nw;
-  QOZ_TRY(parse_header(hs, in_bytes, true, &P, &nu, &nused, &nw));
+  uint64_t npk;
+  QOZ_TRY(parse_header(hs, in_bytes, true, &P, &nu, &nused, &nw, &npk));
   const uint64_t N = (uint64_t)P.g.n[0] * P.g.n[1] * P.g.n[2];
   if (!d_y || y_cap_elems < N)
     return fail(QOZ_ENOSPACE, "output field too small");
   const uint64_t nch = P.n_chunks;
-  const Layout lay = layout_of(P.n_anchor, nused, nch, nu, nw);
+  const Layout lay = layout_of(P.n_anchor, nused, nch, nu, nw, npk);
   const uint8_t* in = (const uint8_t*)d_in;
   uint8_t* cb = pin(c, kPinStage + 256);
   QOZ_TRY(to_host(c, cb, in + lay.syms, lay.coff - lay.syms, s));
@@ -353,8 +398,18 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   uint16_t* codes = (uint16_t*)c->codes.p;
   uint32_t* upos = (uint32_t*)c->upos.p;
   launch_init_status(st, s);
+  /* a packed payload is expanded into scratch first */
+  const uint32_t* payload = (const uint32_t*)(in + lay.payload);
+  if (npk) {
+    QOZ_TRY(ensure(c->ptmp, 4 * nw + 4));
+    PROF(PK_PACK, 4.0 * npk + 4.0 * nw + 16.0 * nch,
+         launch_unpack(payload, npk, (const uint64_t*)(in + lay.coff),
+                       (const uint64_t*)(in + lay.pcoff), nch, nw,
+                       (uint32_t*)c->ptmp.p, st, s));
+    payload = (const uint32_t*)c->ptmp.p;
+  }
   PROF(PK_HUFF_DEC, 4.0 * nw + 2.0 * P.n_codes + 4.0 * nu + 26.0 * nch,
-       launch_huff_decode((const uint32_t*)(in + lay.payload), nw,
+       launch_huff_decode(payload, nw,
                           (const uint64_t*)(in + lay.coff),
                           (const uint32_t*)(in + lay.upre),
                           (const uint16_t*)(in + lay.segs), P.chunks, nu,

@@ -140,7 +140,7 @@ static const char* kProfNames[PK_COUNT] = {
     "sweep_decomp",    "tune_gather",     "tune_alg1",
     "tune_trial",      "ssim",            "reduce",
     "row_comp_level1", "row_decomp_level1", "learned_features",
-    "mlp"};
+    "mlp",             "zero_word_pack"};
 
 }  // namespace qoz
 
@@ -182,7 +182,8 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->tune_stats, &c->tune_l1,    &c->ssim_part,
                     &c->upos,       &c->hsort,      &c->scan,
                     &c->feat,       &c->mlp_io,     &c->mlp_part,
-                    &c->mlp_loss,   &c->hsort_ids};
+                    &c->mlp_loss,   &c->hsort_ids,  &c->pcoff,
+                    &c->ptmp};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

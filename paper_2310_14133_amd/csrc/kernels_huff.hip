@@ -476,14 +476,16 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
   return pre + x - v;
 }
 
-__global__ __launch_bounds__(kEncThreads) void k_huff_encode(
+/* at least 6 waves per SIMD (80 VGPRs): one register more costs a sixth
+ * of the occupancy and about 15 % of the kernel's time */
+__global__ __launch_bounds__(kEncThreads, 6) void k_huff_encode(
     const uint16_t* __restrict__ codes, Chunks ch,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
     uint64_t zero_entry, const uint64_t* __restrict__ coff,
     const uint32_t* __restrict__ upre, uint16_t* __restrict__ segs,
     uint32_t* payload, uint64_t cap_words,
     float* unpred, const float* __restrict__ x, Geo g, SweepTable st,
-    uint32_t* status) {
+    uint32_t* status, uint32_t* __restrict__ pack_bits) {
   constexpr uint32_t kRounds = kChunk / (8 * kEncThreads); /* 2 */
   constexpr uint32_t kSegBins = kChunk / kSegPerChunk;      /* 512 */
   extern __shared__ uint32_t words[];
@@ -591,7 +593,22 @@ __global__ __launch_bounds__(kEncThreads) void k_huff_encode(
         ++zr[r];
       }
   }
+  __shared__ uint32_t nz_words;
+  if (threadIdx.x == 0) nz_words = 0;
   __syncthreads();
+  /* the chunk's size under zero-word packing (bitmap + nonzero words
+   * when shorter, else raw), scanned afterwards for the packing decision
+   * and the packed offsets; counted in LDS before the stores, so that no
+   * barrier waits on them */
+  uint32_t nz = 0;
+  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) nz += words[i] != 0u;
+  for (uint32_t o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o, 64);
+  if ((threadIdx.x & 63u) == 0) atomicAdd(&nz_words, nz);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t nbm = (nw + 31) / 32;
+    pack_bits[c] = 32 * (nbm + nz_words < nw ? nbm + nz_words : nw);
+  }
   bool over = false;
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
     if (w0 + i < cap_words)
@@ -610,7 +627,7 @@ void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
                         uint32_t max_chunk_words, uint32_t* status,
-                        hipStream_t s) {
+                        uint32_t* pack_bits, hipStream_t s) {
   const uint64_t nch = chunks.count();
   if (!nch) return;
   /* every chunk's word count is at most the largest one, which is at
@@ -621,7 +638,7 @@ void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
   hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)nch), dim3(kEncThreads),
                      lds, s, codes, chunks, table, tab_lo, tab_n, zero_entry,
                      coff, upre, segs, payload, payload_cap_words, unpred, x,
-                     g, st, status);
+                     g, st, status, pack_bits);
 }
 
 }  // namespace qoz

@@ -222,7 +222,7 @@ void fill_sweep_table(const Plan& p, SweepTable* t) {
 static uint64_t up8(uint64_t v) { return (v + 7) / 8 * 8; }
 
 Layout layout_of(uint64_t n_anchor, uint64_t n_used, uint64_t n_chunks,
-                 uint64_t n_unpred, uint64_t n_words) {
+                 uint64_t n_unpred, uint64_t n_words, uint64_t n_packed) {
   Layout L;
   uint64_t o = kHeaderBytes;
   L.anchors = o;
@@ -240,7 +240,13 @@ Layout layout_of(uint64_t n_anchor, uint64_t n_used, uint64_t n_chunks,
   L.unpred = o;
   o = up8(o + 4 * n_unpred);
   L.payload = o;
-  L.total = o + 4 * n_words;
+  if (n_packed) { /* packed payload, then the packed chunk offsets */
+    L.pcoff = up8(o + 4 * n_packed);
+    L.total = L.pcoff + 8 * (n_chunks + 1);
+  } else {
+    L.pcoff = 0;
+    L.total = o + 4 * n_words;
+  }
   return L;
 }
 
@@ -293,10 +299,11 @@ void write_header(uint8_t* h, const Plan& p, uint64_t n_unpred,
 
 qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* plan,
                         uint64_t* n_unpred, uint64_t* n_used,
-                        uint64_t* n_words) {
+                        uint64_t* n_words, uint64_t* n_packed) {
   if (in_bytes < kHeaderBytes) return fail(QOZ_EFORMAT, "stream too short");
   if (std::memcmp(h, "QOZ1", 4) != 0) return fail(QOZ_EFORMAT, "bad magic");
-  if (rd<uint16_t>(h, 4) != kStreamVersion)
+  const uint16_t ver = rd<uint16_t>(h, 4);
+  if (ver != kStreamVersion && ver != kStreamVersionPacked)
     return fail(QOZ_EFORMAT, "bad version");
   if (h[7] != kSegLog2) return fail(QOZ_EFORMAT, "unsupported segment size");
   qoz_shape sh;
@@ -334,12 +341,17 @@ qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* 
       nu > nc || nused < 1 || nused > kNSym ||
       nw > 2 * nc + nch)
     return fail(QOZ_EFORMAT, "inconsistent counts in header");
-  Layout lay = layout_of(na, nused, nch, nu, nw);
+  const uint64_t npk = rd<uint32_t>(h, 196);
+  if ((ver == kStreamVersionPacked) != (npk != 0) ||
+      100 * npk > (uint64_t)kPackPercent * nw)
+    return fail(QOZ_EFORMAT, "inconsistent packed payload size");
+  Layout lay = layout_of(na, nused, nch, nu, nw, npk);
   if (need_all && lay.total > in_bytes)
     return fail(QOZ_EFORMAT, "stream truncated");
   *n_unpred = nu;
   *n_used = nused;
   *n_words = nw;
+  *n_packed = npk;
   return QOZ_OK;
 }
 

@@ -25,7 +25,9 @@ constexpr uint32_t kSegLog2 = 9;           /* a chunk holds 8 segments of */
 constexpr uint32_t kSeg = 1u << kSegLog2;  /* 512 bins, each decodable alone */
 constexpr uint32_t kSegPerChunk = kChunk / kSeg;
 constexpr size_t kHeaderBytes = 200;
-constexpr uint16_t kStreamVersion = 4;
+constexpr uint16_t kStreamVersion = 4;       /* unpacked payload */
+constexpr uint16_t kStreamVersionPacked = 5; /* zero-word packed payload */
+constexpr uint32_t kPackPercent = 97; /* pack when packed <= 97 % of raw */
 
 /* Chunks of the bin stream, by level: level l (levels L..1 in stream
  * order) is cut into chunks of max(kChunk >> (l - 1), kMinChunk) bins, level
@@ -112,7 +114,8 @@ struct Plan {
 
 /* Byte offsets of the stream sections (see the stream layout notes). */
 struct Layout {
-  uint64_t anchors, syms, lens, coff, upre, segs, unpred, payload, total;
+  uint64_t anchors, syms, lens, coff, upre, segs, unpred, payload, pcoff,
+      total;
 };
 
 /* Sweep table used by kernels that map a stream position back to a point. */
@@ -176,6 +179,7 @@ enum ProfKind {
   PK_ROW_DEC_L1,
   PK_LEARN_FEAT,
   PK_MLP,
+  PK_PACK,
   PK_COUNT
 };
 
@@ -199,7 +203,7 @@ struct qoz_ctx {
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
-      hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids;
+      hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp;
   /* batch workers: their contexts and streams */
   std::vector<qoz_ctx*> workers;
   std::vector<hipStream_t> worker_streams;
@@ -261,13 +265,14 @@ qoz_status make_plan(const qoz_shape& sh, double e, const qoz_params& p,
 /* target sub-grid of sweep j of level l over geometry g (grid dims) */
 void sweep_grid(const Geo& g, const uint32_t* order_grid, int d, int j,
                 uint32_t h, uint32_t* start, uint32_t* step, uint32_t* cnt);
+/* n_packed: packed payload words of a format-5 stream, 0 for format 4 */
 Layout layout_of(uint64_t n_anchor, uint64_t n_used, uint64_t n_chunks,
-                 uint64_t n_unpred, uint64_t n_words);
+                 uint64_t n_unpred, uint64_t n_words, uint64_t n_packed = 0);
 void write_header(uint8_t* h, const Plan& p, uint64_t n_unpred,
                   uint64_t n_used, uint64_t n_words);
 qoz_status parse_header(const uint8_t* h, size_t in_bytes, bool need_all, Plan* plan,
                         uint64_t* n_unpred, uint64_t* n_used,
-                        uint64_t* n_words);
+                        uint64_t* n_words, uint64_t* n_packed);
 void fill_sweep_table(const Plan& p, SweepTable* t);
 /* Level-1 row fusion: indices of sweeps A (SIZE_MAX if none) and B and the
  * job; false when the level has no sweep along the contiguous dimension or
@@ -343,7 +348,16 @@ void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
                         uint32_t max_chunk_words, uint32_t* status,
-                        hipStream_t s);
+                        uint32_t* pack_bits, hipStream_t s);
+/* zero-word packing of the payload (stream format 5): pack_bits[c] from
+ * the encoder is 32 x the chunk's packed word count, scanned into pcoff */
+void launch_pack_write(const uint32_t* raw, const uint64_t* coff,
+                       const uint64_t* pcoff, uint64_t n_chunks,
+                       uint32_t* dst, hipStream_t s);
+void launch_unpack(const uint32_t* src, uint64_t n_packed,
+                   const uint64_t* coff, const uint64_t* pcoff,
+                   uint64_t n_chunks, uint64_t n_words, uint32_t* raw,
+                   uint32_t* status, hipStream_t s);
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
                         const uint16_t* segs, const Chunks& chunks,

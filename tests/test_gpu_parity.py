@@ -101,6 +101,11 @@ CASES = [
      "cubic", None, 1.0, 1.5),
     ("anchorless_2d", lambda: fields.grf((70, 45), 13), 1e-3, 128, "linear",
      None, 1.5, 2.0),
+    # zero-word packed payloads (stream format 5)
+    ("packed_2d", lambda: fields.bumps_and_waves(160, 2), 1e-2, 64, "cubic",
+     None, 1.0, 1.5),
+    ("packed_3d", lambda: fields.multiscale((48, 40, 56), 14), 1e-2, 16,
+     "linear", None, 1.25, 2.0),
     # about 4700 used symbols: the second, larger device sort
     ("noise_big_sort", lambda: np.random.default_rng(5).normal(
         size=(48, 40, 44)).astype(np.float32), 1e-4, 8, "cubic", None, 1.0,
@@ -281,6 +286,31 @@ def test_tune_parity(codec, ref, name, make, s, cfgkw, target, rel):
             (q.params_dict(gp, d), ref.params_to_dict(rp, d))
     # downstream: the GPU's parameters give the oracle's stream
     roundtrip_check(codec, ref, x, e, rp)
+
+
+def test_packed_stream_corruption(codec, ref):
+    import paper_2310_14133_amd as q
+    x = fields.bumps_and_waves(160, 2)
+    e = 1e-2 * (float(x.max()) - float(x.min()))
+    rp = ref.make_params(2, "cubic", None, 1.0, 1.5, anchor_stride=64)
+    z = ref.compress(x, e, rp)
+    assert int(np.frombuffer(z[4:6].tobytes(), np.uint16)[0]) == 5
+    y = codec.decompress(to_dev(z))
+    assert np.array_equal(y.cpu().numpy().view(np.uint32),
+                          ref.decompress(z).view(np.uint32))
+    wp = int(np.frombuffer(z[196:200].tobytes(), np.uint32)[0])
+    n_chunks = int(np.frombuffer(z[168:176].tobytes(), np.uint64)[0])
+    pc_at = z.size - 8 * (n_chunks + 1)
+    for name, at, val in [("offset past the payload", pc_at + 8, wp + 9),
+                          ("first offset not zero", pc_at, 1)]:
+        bad = z.copy()
+        bad[at:at + 8] = np.frombuffer(np.array([val], np.uint64).tobytes(),
+                                       np.uint8)
+        print(f"packed corruption: {name}", flush=True)
+        assert ref.decompress_status(bad) == ref.EFORMAT
+        with pytest.raises(q.QozError) as err:
+            codec.decompress(to_dev(bad))
+        assert err.value.status == q.QOZ_EFORMAT
 
 
 ABLATION_CASES = [
