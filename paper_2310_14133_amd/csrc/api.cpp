@@ -205,13 +205,12 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   std::memcpy(cb, usym.data(), 2 * n_used);
   std::memcpy(cb + (lay.lens - lay.syms), ulen.data(), n_used);
   QOZ_TRY(to_device(c, out + lay.syms, cb, cb_bytes, s));
-  if (P.n_anchor)
-    QOZ_HIP(hipMemcpyAsync(out + lay.anchors, c->anchors.p, 4 * P.n_anchor,
-                           hipMemcpyDeviceToDevice, s));
-  QOZ_HIP(hipMemcpyAsync(out + lay.coff, c->coff.p, 8 * (nch + 1),
-                         hipMemcpyDeviceToDevice, s));
-  QOZ_HIP(hipMemcpyAsync(out + lay.upre, c->upre.p, 4 * (nch + 1),
-                         hipMemcpyDeviceToDevice, s));
+  {
+    void* dst[3] = {out + lay.anchors, out + lay.coff, out + lay.upre};
+    const void* src[3] = {c->anchors.p, c->coff.p, c->upre.p};
+    const uint64_t bytes[3] = {4 * P.n_anchor, 8 * (nch + 1), 4 * (nch + 1)};
+    launch_copy_regions(dst, src, bytes, 3, s);
+  }
   SweepTable tbl;
   fill_sweep_table(P, &tbl);
   PROF(PK_HUFF_ENC,
@@ -253,14 +252,16 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     PROF(PK_PACK, 4.0 * n_words + 4.0 * n_packed + 8.0 * nch,
          launch_pack_write(raw, (const uint64_t*)c->coff.p, pcoff, nch,
                            (uint32_t*)c->ptmp.p, s));
-    QOZ_HIP(hipMemcpyAsync(raw, c->ptmp.p, 4 * n_packed,
-                           hipMemcpyDeviceToDevice, s));
+    {
+      void* dst[2] = {raw, out + lp.pcoff};
+      const void* src[2] = {c->ptmp.p, pcoff};
+      const uint64_t bytes[2] = {4 * n_packed, 8 * (nch + 1)};
+      launch_copy_regions(dst, src, bytes, 2, s);
+    }
     /* the padding word before the offsets reads as zero */
     if (lp.pcoff > lay.payload + 4 * n_packed)
       launch_zero_u32((uint32_t*)(out + lay.payload + 4 * n_packed),
                       (lp.pcoff - lay.payload - 4 * n_packed) / 4, s);
-    QOZ_HIP(hipMemcpyAsync(out + lp.pcoff, pcoff, 8 * (nch + 1),
-                           hipMemcpyDeviceToDevice, s));
     const uint16_t ver = kStreamVersionPacked;
     const uint32_t npk = (uint32_t)n_packed;
     std::memcpy(hs + 4, &ver, 2);

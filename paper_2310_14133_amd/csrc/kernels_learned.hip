@@ -16,9 +16,11 @@
  * and gradients are float32 in the order written; sums and logs are FP64.
  * Only the sampled blocks are read.
  *
- * One workgroup of 1024 lanes per block: the block sits in LDS (143.7 KB),
- * each level's residual sums are block reductions, and the 32768 squared
- * gradients stay in registers (32 per lane) while an exact radix select
+ * Three workgroups of 1024 lanes per block, each with the block in LDS
+ * (143.7 KB): level 1's residual sums; levels 2..5 and the value range;
+ * the gradient deciles.  The residual sums are block reductions, and the
+ * 32768 squared gradients stay in registers (32 per lane) while an exact
+ * radix select
  * finds the ten deciles: four passes of 8 bits, each an LDS histogram per
  * distinct prefix still in play, a wave per decile scanning its histogram
  * to fix the next byte of its value and its rank below it.
@@ -70,8 +72,8 @@ __device__ void block_sum(double (&v)[N], double (*red)[kFeatThreads / 64]) {
 }
 }  // namespace
 
-/* feat[b][0..30] of block b; aux[b] = (min, max, non-finite flag) for the
- * pooling kernel, which fills feat[b][31] */
+/* feat[b][0..30] of block b (blockIdx.y picks the part); aux[b] = (min,
+ * max, non-finite flag) for the pooling kernel, which fills feat[b][31] */
 __global__ __launch_bounds__(kFeatThreads) void k_block_features(
     const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
     double e, float* __restrict__ feat, float* __restrict__ aux) {
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
   __shared__ double stat[20];
   __shared__ uint32_t rhist[10][256];
   __shared__ uint32_t rpre[10], rrank[10], dpre[10], dmap[10], ndist;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, part = blockIdx.y;
   const uint32_t* o = origins + 3 * blockIdx.x;
   const uint64_t base = (uint64_t)o[0] * g.st[0] + (uint64_t)o[1] * g.st[1] +
                         (uint64_t)o[2] * g.st[2];
@@ -105,27 +107,30 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
   }
   __syncthreads();
   /* block range and finiteness */
-  float lo = blk[tid], hi = blk[tid];
-  uint32_t bad = 0;
-  for (uint32_t t = tid; t < kBlockPts; t += kFeatThreads) {
-    const float v = blk[t];
-    lo = fminf(lo, v);
-    hi = fmaxf(hi, v);
-    bad |= (__float_as_uint(v) & 0x7f800000u) == 0x7f800000u;
-  }
-  for (int s = 32; s > 0; s >>= 1) {
-    lo = fminf(lo, __shfl_xor(lo, s, 64));
-    hi = fmaxf(hi, __shfl_xor(hi, s, 64));
-    bad |= __shfl_xor(bad, s, 64);
-  }
-  if ((tid & 63) == 0) {
-    mred[0][tid >> 6] = lo;
-    mred[1][tid >> 6] = hi;
-    mred[2][tid >> 6] = bad ? 1.0f : 0.0f;
+  if (part == 1) {
+    float lo = blk[tid], hi = blk[tid];
+    uint32_t bad = 0;
+    for (uint32_t t = tid; t < kBlockPts; t += kFeatThreads) {
+      const float v = blk[t];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+      bad |= (__float_as_uint(v) & 0x7f800000u) == 0x7f800000u;
+    }
+    for (int s = 32; s > 0; s >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, s, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, s, 64));
+      bad |= __shfl_xor(bad, s, 64);
+    }
+    if ((tid & 63) == 0) {
+      mred[0][tid >> 6] = lo;
+      mred[1][tid >> 6] = hi;
+      mred[2][tid >> 6] = bad ? 1.0f : 0.0f;
+    }
   }
   /* level-wise residual sums: lin |r|, lin r^2, cubic |r|, cubic r^2 */
 #pragma unroll
   for (uint32_t l = 1; l <= 5; ++l) {
+    if (part == 2 || (part == 0) != (l == 1)) continue;
     const uint32_t h = 1u << (l - 1), m = 32 / h + 1, nodd = 16 / h;
     const uint32_t per_dim = nodd * m * m;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -161,6 +166,29 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
       stat[4 * (l - 1) + 2] = log2(1.0 + (acc[2] / n) / e);
       stat[4 * (l - 1) + 3] = log2(1.0 + sqrt(acc[3] / n) / e);
     }
+  }
+  if (part != 2) {
+    __syncthreads(); /* stat[] and mred[] complete */
+    if (tid < 31 &&
+        (part == 0 ? tid < 4 : (tid >= 4 && tid < 20) || tid == 30)) {
+      double f;
+      if (tid < 20) {
+        f = stat[tid];
+      } else {
+        float l2 = mred[0][0], h2 = mred[1][0], b2 = mred[2][0];
+        for (uint32_t w = 1; w < kFeatThreads / 64; ++w) {
+          l2 = fminf(l2, mred[0][w]);
+          h2 = fmaxf(h2, mred[1][w]);
+          b2 = fmaxf(b2, mred[2][w]);
+        }
+        f = log2(1.0 + ((double)h2 - (double)l2) / e);
+        aux[3 * (uint64_t)blockIdx.x + 0] = l2;
+        aux[3 * (uint64_t)blockIdx.x + 1] = h2;
+        aux[3 * (uint64_t)blockIdx.x + 2] = b2;
+      }
+      feat[32 * (uint64_t)blockIdx.x + tid] = (float)f;
+    }
+    return;
   }
   /* squared gradients, kept in registers */
   uint32_t g2[kGPer];
@@ -256,28 +284,9 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
     }
     __syncthreads();
   }
-  if (tid < 31) {
-    double f;
-    if (tid < 20) {
-      f = stat[tid];
-    } else if (tid < 30) {
-      f = log2(1.0 + sqrt((double)__uint_as_float(rpre[tid - 20])) / e);
-    } else {
-      float l2 = mred[0][0], h2 = mred[1][0], b2 = mred[2][0];
-      for (uint32_t w = 1; w < kFeatThreads / 64; ++w) {
-        l2 = fminf(l2, mred[0][w]);
-        h2 = fmaxf(h2, mred[1][w]);
-        b2 = fmaxf(b2, mred[2][w]);
-      }
-      f = log2(1.0 + ((double)h2 - (double)l2) / e);
-      if (tid == 30) {
-        aux[3 * (uint64_t)blockIdx.x + 0] = l2;
-        aux[3 * (uint64_t)blockIdx.x + 1] = h2;
-        aux[3 * (uint64_t)blockIdx.x + 2] = b2;
-      }
-    }
-    feat[32 * (uint64_t)blockIdx.x + tid] = (float)f;
-  }
+  if (tid >= 20 && tid < 30)
+    feat[32 * (uint64_t)blockIdx.x + tid] = (float)log2(
+        1.0 + sqrt((double)__uint_as_float(rpre[tid - 20])) / e);
 }
 
 /* Range over all blocks into every row's feature 31, the mean of each
@@ -329,7 +338,7 @@ void launch_block_features(const float* x, const Geo& g,
                            const uint32_t* origins, uint32_t nb, double e,
                            float* feat, float* aux, float* mean,
                            uint32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_block_features, dim3(nb), dim3(kFeatThreads),
+  hipLaunchKernelGGL(k_block_features, dim3(nb, 3), dim3(kFeatThreads),
                      block_features_lds(), s, x, g, origins, e, feat, aux);
   hipLaunchKernelGGL(k_feat_pool, dim3(1), dim3(64), 0, s, feat,
                      (const float*)aux, nb, e, mean, status);

@@ -68,6 +68,52 @@ __global__ void k_copy_host(uint8_t* dst, const uint8_t* src, uint64_t n) {
     copy_host_units<TO_HOST>(dst, src, n);
 }
 
+/* Up to four device-to-device copies in one launch (blockIdx.y picks
+ * the region), 16 bytes per lane where both ends allow it; the runtime's
+ * copy takes tens of microseconds per call for these small sections. */
+struct CopyRegions {
+  const uint8_t* src[4];
+  uint8_t* dst[4];
+  uint64_t bytes[4];
+};
+
+__global__ __launch_bounds__(256) void k_copy_regions(CopyRegions r) {
+  const uint32_t k = blockIdx.y;
+  const uint8_t* src = r.src[k];
+  uint8_t* dst = r.dst[k];
+  const uint64_t n = r.bytes[k];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
+    const uint64_t n16 = n / 16;
+    for (uint64_t i = t; i < n16; i += stride)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (uint64_t i = n16 * 16 + t; i < n; i += stride) dst[i] = src[i];
+  } else {
+    for (uint64_t i = t; i < n; i += stride) dst[i] = src[i];
+  }
+}
+
+void launch_copy_regions(void* const* dst, const void* const* src,
+                         const uint64_t* bytes, uint32_t n, hipStream_t s) {
+  CopyRegions r;
+  uint64_t most = 0;
+  uint32_t m = 0;
+  for (uint32_t k = 0; k < n && m < 4; ++k) {
+    if (!bytes[k]) continue;
+    r.src[m] = (const uint8_t*)src[k];
+    r.dst[m] = (uint8_t*)dst[k];
+    r.bytes[m] = bytes[k];
+    most = bytes[k] > most ? bytes[k] : most;
+    ++m;
+  }
+  if (!m) return;
+  uint64_t blocks = (most / 16 + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+  hipLaunchKernelGGL(k_copy_regions, dim3((uint32_t)blocks, m), dim3(256), 0,
+                     s, r);
+}
+
 void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
                       hipStream_t s) {
   if (!bytes) return;

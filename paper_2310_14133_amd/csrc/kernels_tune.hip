@@ -85,31 +85,52 @@ __device__ __forceinline__ void copy_grid(const Geo& g, uint32_t lg,
   }
 }
 
-/* One wave per row of a block (rows of blockIdx.x * 4 + wave, block
- * blockIdx.y), lanes along the contiguous dimension. */
-__global__ __launch_bounds__(256) void k_gather_blocks(
+/* The sampled blocks into xs and its committed copy wc: workgroup
+ * (blockIdx.x, blockIdx.y) takes points [2048 blockIdx.x, +2048) of block
+ * blockIdx.y in row-major order, eight per lane with all loads in flight;
+ * the stores are contiguous, the loads rows of the field. */
+constexpr uint32_t kGatherThreads = 256;
+constexpr uint32_t kGatherPer = 8;
+
+__global__ __launch_bounds__(kGatherThreads) void k_gather_blocks(
     const float* __restrict__ x, Geo g, BlockGeo bg,
-    const uint32_t* __restrict__ origins, float* __restrict__ xs) {
+    const uint32_t* __restrict__ origins, float* __restrict__ xs,
+    float* __restrict__ wc) {
   const uint32_t blk = blockIdx.y;
-  const uint32_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const uint32_t n0 = bg.g.n[0], n1 = bg.g.n[1], n2 = bg.g.n[2];
-  if (row >= n0 * n1) return;
-  const uint32_t i0 = row / n1, i1 = row - i0 * n1;
+  const uint32_t n1 = bg.g.n[1], n2 = bg.g.n[2], size = bg.size;
+  const FastDiv f2(n2, size), f1(n1, size);
   const uint32_t* o = origins + 3 * blk;
-  const uint64_t src = (uint64_t)(o[0] + i0) * g.st[0] +
-                       (uint64_t)(o[1] + i1) * g.st[1] + o[2];
-  float* dst = xs + (uint64_t)blk * bg.size + (uint64_t)row * n2;
-  for (uint32_t i2 = threadIdx.x & 63u; i2 < n2; i2 += 64)
-    dst[i2] = x[src + i2];
+  const uint32_t t0 = blockIdx.x * kGatherThreads * kGatherPer + threadIdx.x;
+  float v[kGatherPer];
+#pragma unroll
+  for (uint32_t u = 0; u < kGatherPer; ++u) {
+    const uint32_t t = t0 + u * kGatherThreads;
+    if (t < size) {
+      const uint32_t r = f2.div(t), i2 = t - r * n2;
+      const uint32_t i0 = f1.div(r), i1 = r - i0 * n1;
+      v[u] = x[(uint64_t)(o[0] + i0) * g.st[0] +
+               (uint64_t)(o[1] + i1) * g.st[1] + o[2] + i2];
+    }
+  }
+  const uint64_t base = (uint64_t)blk * size;
+#pragma unroll
+  for (uint32_t u = 0; u < kGatherPer; ++u) {
+    const uint32_t t = t0 + u * kGatherThreads;
+    if (t < size) {
+      xs[base + t] = v[u];
+      wc[base + t] = v[u];
+    }
+  }
 }
 
 void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
-                          const uint32_t* origins_dev, float* xs,
+                          const uint32_t* origins_dev, float* xs, float* wc,
                           hipStream_t s) {
-  const uint32_t rows = bg.g.n[0] * bg.g.n[1];
-  if (!rows || !bg.nb) return;
-  hipLaunchKernelGGL(k_gather_blocks, dim3((rows + 3) / 4, bg.nb), dim3(256),
-                     0, s, x, g, bg, origins_dev, xs);
+  if (!bg.size || !bg.nb) return;
+  const uint32_t per = kGatherThreads * kGatherPer;
+  hipLaunchKernelGGL(k_gather_blocks, dim3((bg.size + per - 1) / per, bg.nb),
+                     dim3(kGatherThreads), 0, s, x, g, bg, origins_dev, xs,
+                     wc);
 }
 
 __global__ __launch_bounds__(kTuneThreads) void k_alg1_level(

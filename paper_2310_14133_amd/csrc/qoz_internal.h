@@ -328,6 +328,9 @@ void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s);
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
 /* bytes from device memory to coherent host memory (to_host) or back */
+/* device-to-device copies of up to four regions (n <= 4) in one launch */
+void launch_copy_regions(void* const* dst, const void* const* src,
+                         const uint64_t* bytes, uint32_t n, hipStream_t s);
 void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
                       hipStream_t s);
 void launch_huff_len(const uint16_t* codes, const Chunks& chunks,
@@ -445,8 +448,9 @@ struct BlockGeo {
   uint32_t Lt;
   uint32_t d;
 };
+/* the sampled blocks into xs and a second copy into wc */
 void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
-                          const uint32_t* origins_dev, float* xs,
+                          const uint32_t* origins_dev, float* xs, float* wc,
                           hipStream_t s);
 /* whether Algorithm 1's level-l working copies fit in LDS on the current
  * device (then no per-candidate copies in wt are made) */

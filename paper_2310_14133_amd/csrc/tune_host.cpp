@@ -300,10 +300,9 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   QOZ_TRY(to_device(c, dorig, h_status + 8, 4 * origins.size(), s));
   {
     hipEvent_t ev = prof_begin(c, s, PK_TUNE_GATHER);
-    launch_gather_blocks(d_x, g, bg, dorig, xs, s);
-    prof_end(c, s, ev, PK_TUNE_GATHER, 8.0 * bsz);
+    launch_gather_blocks(d_x, g, bg, dorig, xs, wc, s);
+    prof_end(c, s, ev, PK_TUNE_GATHER, 12.0 * bsz);
   }
-  QOZ_HIP(hipMemcpyAsync(wc, xs, 4 * bsz, hipMemcpyDeviceToDevice, s));
   QOZ_HIP(hipGetLastError());
   QOZ_HIP(hipStreamSynchronize(s));
   if (h_status[0] & kStNonFinite) {
