@@ -143,6 +143,24 @@ void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code) {
   }
 }
 
+/* Total code bits of a whole histogram: the used symbols' counts sorted
+ * by two 16-bit radix passes, then the two-queue merge above. */
+uint64_t huffman_cost_hist(const uint32_t* hist, uint32_t nsym) {
+  std::vector<uint64_t> a, b;
+  a.reserve(4096);
+  for (uint32_t s = 0; s < nsym; ++s)
+    if (hist[s]) a.push_back(((uint64_t)hist[s] << 16) | s);
+  b.resize(a.size());
+  for (int shift = 16; shift < 48; shift += 16) {
+    uint32_t cnt[65537] = {0};
+    for (uint64_t k : a) cnt[((k >> shift) & 0xffffu) + 1]++;
+    for (uint32_t d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
+    for (uint64_t k : a) b[cnt[(k >> shift) & 0xffffu]++] = k;
+    a.swap(b);
+  }
+  return huffman_cost_sorted(a.data(), (uint32_t)a.size());
+}
+
 uint64_t huffman_cost(const uint32_t* hist, uint32_t nsym) {
   std::vector<uint8_t> len(nsym);
   if (!huffman_lengths(hist, nsym, len.data())) return ~0ull;

@@ -302,6 +302,7 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
                       uint32_t n_used, DecTables* t,
                       std::vector<uint32_t>* sorted_syms);
 uint64_t huffman_cost(const uint32_t* hist, uint32_t nsym);
+uint64_t huffman_cost_hist(const uint32_t* hist, uint32_t nsym);
 
 /* ---- launchers (kernels_*.hip) -------------------------------------- */
 void launch_init_status(uint32_t* status, hipStream_t s);

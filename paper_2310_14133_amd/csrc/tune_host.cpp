@@ -20,9 +20,11 @@
  * keep the incumbent; ratio mode compares bit rates only.
  */
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <thread>
 
 #include "qoz_internal.h"
 
@@ -101,8 +103,18 @@ static qoz_status overflow_bits(qoz_ctx* c, const std::vector<uint32_t>& over,
       QOZ_TRY(to_host(c, hp + i * hb, dhist + (size_t)full[i] * kNSym, hb, s));
     QOZ_HIP(hipGetLastError());
     QOZ_HIP(hipStreamSynchronize(s));
-    for (size_t i = 0; i < full.size(); ++i)
-      bits[full[i]] = huffman_cost((const uint32_t*)(hp + i * hb), kNSym);
+    /* one host thread per histogram, at most 16 */
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+      for (size_t i; (i = next.fetch_add(1)) < full.size();)
+        bits[full[i]] =
+            huffman_cost_hist((const uint32_t*)(hp + i * hb), kNSym);
+    };
+    const size_t nt = std::min<size_t>(full.size(), 16);
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < nt; ++t) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
   }
   return QOZ_OK;
 }
