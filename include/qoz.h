@@ -163,6 +163,22 @@ qoz_status qoz_metrics(qoz_ctx* ctx, const float* d_x, const float* d_y,
 qoz_status qoz_error_ac(qoz_ctx* ctx, const float* d_x, const float* d_y,
                         qoz_shape shape, double* ac, hipStream_t stream);
 
+/* Tile autotuning of the interpolation sweeps: for the plan of `shape`
+ * and `params` (anchor stride, levels, orders), times every sweep of
+ * compression and decompression on scratch data with each candidate
+ * launch tile (rows per workgroup 1..16, rows per lane 1..4) and keeps the
+ * fastest per sweep in ctx; later qoz_compress / qoz_decompress calls with
+ * the same sweep geometry use them (results are the same for any tile).
+ * *n_sweeps (may be NULL) receives the number of sweeps tuned;
+ * *ms_default and *ms_tuned (may be NULL) the summed time of those sweeps,
+ * compression and decompression, with the default tile (4 rows per
+ * workgroup, 1 per lane) and with the chosen ones (each the fastest of its
+ * repetitions).  Synchronous.  Errors: EINVAL, EDEVICE, ENOMEM. */
+qoz_status qoz_autotune_tiles(qoz_ctx* ctx, qoz_shape shape,
+                              const qoz_params* params, uint32_t* n_sweeps,
+                              float* ms_default, float* ms_tuned,
+                              hipStream_t stream);
+
 /* ---- Batches -------------------------------------------------------------
  * Many fields of uneven shapes and bounds in one call.  Worker threads,
  * each with a context and stream of its own (created on first use, kept

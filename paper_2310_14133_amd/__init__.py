@@ -93,6 +93,10 @@ def lib():
         L.qoz_metrics.argtypes = [vp, vp, vp, Shape, u32, C.POINTER(dbl),
                                   C.POINTER(dbl), C.POINTER(dbl), vp]
         L.qoz_error_ac.argtypes = [vp, vp, vp, Shape, C.POINTER(dbl), vp]
+        L.qoz_autotune_tiles.argtypes = [vp, Shape, C.POINTER(Params),
+                                         C.POINTER(u32),
+                                         C.POINTER(C.c_float),
+                                         C.POINTER(C.c_float), vp]
         L.qoz_compress_batch.argtypes = [vp, vp, u32, C.c_int,
                                          C.POINTER(TuneConfig), u32, vp]
         L.qoz_decompress_batch.argtypes = [vp, vp, u32, u32, vp]
@@ -116,7 +120,8 @@ def lib():
                                          C.POINTER(dbl), C.POINTER(dbl)]
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
-                   "qoz_metrics", "qoz_error_ac", "qoz_compress_batch",
+                   "qoz_metrics", "qoz_error_ac", "qoz_autotune_tiles",
+                   "qoz_compress_batch",
                    "qoz_decompress_batch", "qoz_learned_features",
                    "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
                    "qoz_tune_learned", "qoz_ctx_set_timing",
@@ -271,6 +276,17 @@ def qoz_error_ac(ctx, d_x, d_y, shape, stream):
                               C.byref(ac), C.c_void_p(stream)),
            "qoz_error_ac")
     return ac.value
+
+
+def qoz_autotune_tiles(ctx, shape, params, stream):
+    """Times the sweep launch tiles for this shape and parameters; returns
+    (sweeps tuned, ms with the default tiles, ms with the chosen ones)."""
+    n = C.c_uint32()
+    t0, t1 = C.c_float(), C.c_float()
+    _check(lib().qoz_autotune_tiles(ctx, shape, C.byref(params), C.byref(n),
+                                    C.byref(t0), C.byref(t1),
+                                    C.c_void_p(stream)), "qoz_autotune_tiles")
+    return n.value, t0.value, t1.value
 
 
 def qoz_compress_batch(ctx, items, target, cfg, workers, stream):
@@ -459,6 +475,12 @@ class Codec:
         sh = self._field(x)
         return qoz_metrics(self.ctx, x.data_ptr(), y.data_ptr(), sh,
                            ssim_window, self._stream(), want_ssim)
+
+    def autotune_tiles(self, shape, params):
+        """Sweep launch tiles for fields of `shape` compressed with
+        `params`, kept in this codec's context."""
+        return qoz_autotune_tiles(self.ctx, make_shape(tuple(shape)), params,
+                                  self._stream())
 
     # ---- batches -------------------------------------------------------
     def compress_batch(self, xs, abs_ebs, params=None, target="cr", cfg=None,

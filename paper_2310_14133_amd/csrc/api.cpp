@@ -74,6 +74,11 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   size_t fa = SIZE_MAX, fb = SIZE_MAX;
   RowJob rj;
   const bool fuse = level1_rows(P, &fa, &fb, &rj);
+  const std::vector<SweepTile>* tiles = nullptr;
+  {
+    auto it = c->tiles_comp.find(tile_key(P));
+    if (it != c->tiles_comp.end()) tiles = &it->second;
+  }
   for (size_t i = 0; i < P.sweeps.size(); ++i) {
     const Sweep& sw = P.sweeps[i];
     if (fuse && (i == fa || i == fb)) {
@@ -88,7 +93,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     const bool last = i + 1 == P.sweeps.size();
     PROF(sw.level == 1 ? PK_SWEEP_COMP_L1 : PK_SWEEP_COMP,
          (double)sw.count * (last ? 10.0 : 14.0),
-         launch_sweep_comp(P.g, sw, d_x, W, codes, !last, st, s));
+         launch_sweep_comp(P.g, sw, d_x, W, codes, !last, st, s,
+                           tiles ? (*tiles)[i] : SweepTile()));
   }
   PROF(PK_HIST, 2.0 * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
   /* used symbols sorted on the device; the tree is built on the host */
@@ -426,6 +432,11 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   size_t fa = SIZE_MAX, fb = SIZE_MAX;
   RowJob rj;
   const bool fuse = level1_rows(P, &fa, &fb, &rj);
+  const std::vector<SweepTile>* tiles = nullptr;
+  {
+    auto it = c->tiles_decomp.find(tile_key(P));
+    if (it != c->tiles_decomp.end()) tiles = &it->second;
+  }
   for (size_t i = 0; i < P.sweeps.size(); ++i) {
     const Sweep& sw = P.sweeps[i];
     if (fuse && (i == fa || i == fb)) {
@@ -438,7 +449,8 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
     }
     PROF(sw.level == 1 ? PK_SWEEP_DEC_L1 : PK_SWEEP_DEC,
          (double)sw.count * 10.0,
-         launch_sweep_decomp(P.g, sw, d_y, codes, s));
+         launch_sweep_decomp(P.g, sw, d_y, codes, s,
+                             tiles ? (*tiles)[i] : SweepTile()));
   }
   QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
   QOZ_TRY(sync_checked(s));

@@ -198,7 +198,7 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t id, uint32_t total) {
 }
 
 constexpr uint32_t kSweepTX = 64;
-constexpr uint32_t kSweepTY = 4;
+constexpr uint32_t kSweepTYMax = 16; /* rows per workgroup: blockDim.y */
 constexpr uint32_t kMaxGridY = 65535;
 
 struct SweepPoint {
@@ -223,7 +223,7 @@ __device__ __forceinline__ SweepPoint sweep_point(const Geo& g,
 }
 
 template <bool WRITE_W>
-__global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_comp(
+__global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_comp(
     Geo g, Sweep s, const float* __restrict__ x, float* W,
     uint16_t* __restrict__ codes, uint32_t* status) {
   const uint32_t lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y,
@@ -235,8 +235,8 @@ __global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_comp(
   const uint32_t sk = g.st[s.k];
   const uint32_t nk = g.n[s.k];
   bool bad = false;
-  for (uint32_t r = by * kSweepTY + threadIdx.y; r < rows;
-       r += gridDim.y * kSweepTY) {
+  const uint32_t ty = blockDim.y;
+  for (uint32_t r = by * ty + threadIdx.y; r < rows; r += gridDim.y * ty) {
     SweepPoint sp = sweep_point(g, s, r, i2);
     float pred = predict_at(W, sp.idx, sp.pk, sk, nk, s.h, s.cubic);
     float xv = x[sp.idx];
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_comp(
 /* Decompression: bins >= 1 reconstruct pred + (bin - R) * 2e_l with the
  * same two roundings as the compressor.  Bin 0 (unpredictable) is skipped:
  * its exact value was scattered into W before the sweeps. */
-__global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_decomp(
+__global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_decomp(
     Geo g, Sweep s, float* W, const uint16_t* __restrict__ codes) {
   const uint32_t lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y,
                                 gridDim.x * gridDim.y);
@@ -262,8 +262,8 @@ __global__ __launch_bounds__(kSweepTX * kSweepTY) void k_sweep_decomp(
   const uint32_t rows = s.cnt[0] * s.cnt[1];
   const uint32_t sk = g.st[s.k];
   const uint32_t nk = g.n[s.k];
-  for (uint32_t r = by * kSweepTY + threadIdx.y; r < rows;
-       r += gridDim.y * kSweepTY) {
+  const uint32_t ty = blockDim.y;
+  for (uint32_t r = by * ty + threadIdx.y; r < rows; r += gridDim.y * ty) {
     SweepPoint sp = sweep_point(g, s, r, i2);
     const int32_t code = codes[sp.pos];
     if (code == 0) continue;
@@ -626,19 +626,31 @@ void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
                      rj, W, codes);
 }
 
-static dim3 sweep_grid_dim(const Sweep& sw) {
+/* Launch shape of a sweep: x covers 64 consecutive targets of a row, y
+ * covers rows (flattened over the two outer sub-grid dimensions), ty rows
+ * per workgroup and rpt rows per lane (a grid-stride loop), the grid's y
+ * extent capped at 65535. */
+static dim3 sweep_grid_dim(const Sweep& sw, SweepTile t) {
   uint32_t gx = (sw.cnt[2] + kSweepTX - 1) / kSweepTX;
   uint64_t rows = (uint64_t)sw.cnt[0] * sw.cnt[1];
-  uint64_t gy = (rows + kSweepTY - 1) / kSweepTY;
+  uint64_t per = (uint64_t)t.ty * t.rpt;
+  uint64_t gy = (rows + per - 1) / per;
   if (gy > kMaxGridY) gy = kMaxGridY;
+  if (gy < 1) gy = 1;
   return dim3(gx, (uint32_t)gy);
+}
+
+bool sweep_tile_ok(SweepTile t) {
+  return t.ty >= 1 && t.ty <= kSweepTYMax && (t.ty & (t.ty - 1)) == 0 &&
+         t.rpt >= 1 && t.rpt <= 64;
 }
 
 void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
                        float* W, uint16_t* codes, bool write_w,
-                       uint32_t* status, hipStream_t s) {
+                       uint32_t* status, hipStream_t s, SweepTile t) {
   if (sw.count == 0) return;
-  dim3 grid = sweep_grid_dim(sw), block(kSweepTX, kSweepTY);
+  if (!sweep_tile_ok(t)) t = SweepTile();
+  dim3 grid = sweep_grid_dim(sw, t), block(kSweepTX, t.ty);
   if (write_w)
     hipLaunchKernelGGL(k_sweep_comp<true>, grid, block, 0, s, g, sw, x, W,
                        codes, status);
@@ -648,9 +660,10 @@ void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
 }
 
 void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
-                         const uint16_t* codes, hipStream_t s) {
+                         const uint16_t* codes, hipStream_t s, SweepTile t) {
   if (sw.count == 0) return;
-  dim3 grid = sweep_grid_dim(sw), block(kSweepTX, kSweepTY);
+  if (!sweep_tile_ok(t)) t = SweepTile();
+  dim3 grid = sweep_grid_dim(sw, t), block(kSweepTX, t.ty);
   hipLaunchKernelGGL(k_sweep_decomp, grid, block, 0, s, g, sw, W, codes);
 }
 

@@ -261,6 +261,21 @@ static T rd(const uint8_t* b, size_t o) {
   return v;
 }
 
+std::vector<uint32_t> tile_key(const Plan& p) {
+  std::vector<uint32_t> k = {p.g.n[0], p.g.n[1], p.g.n[2],
+                             (uint32_t)p.sweeps.size()};
+  for (const Sweep& sw : p.sweeps) {
+    k.push_back(sw.k);
+    k.push_back(sw.h);
+    for (int i = 0; i < 3; ++i) {
+      k.push_back(sw.start[i]);
+      k.push_back(sw.step[i]);
+      k.push_back(sw.cnt[i]);
+    }
+  }
+  return k;
+}
+
 void write_header(uint8_t* h, const Plan& p, uint64_t n_unpred,
                   uint64_t n_used, uint64_t n_words) {
   std::memset(h, 0, kHeaderBytes);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -183,6 +184,12 @@ enum ProfKind {
   PK_COUNT
 };
 
+/* Sweep launch tile: ty rows of 64 targets per workgroup (a power of two
+ * up to 16), rpt rows per lane; the default is (4, 1). */
+struct SweepTile {
+  uint8_t ty = 4, rpt = 1;
+};
+
 /* Growable device buffer. */
 struct DevBuf {
   void* p = nullptr;
@@ -204,6 +211,9 @@ struct qoz_ctx {
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
       hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp;
+  /* sweep launch tiles chosen by qoz_autotune_tiles, per plan signature */
+  std::map<std::vector<uint32_t>, std::vector<qoz::SweepTile>> tiles_comp,
+      tiles_decomp;
   /* batch workers: their contexts and streams */
   std::vector<qoz_ctx*> workers;
   std::vector<hipStream_t> worker_streams;
@@ -262,6 +272,8 @@ void level_bounds(double e, double alpha, double beta, uint32_t L,
                   double* eb, float* twoeb, float* inv);
 qoz_status make_plan(const qoz_shape& sh, double e, const qoz_params& p,
                      Plan* plan);
+/* key of a plan's sweep geometry for the tile tables */
+std::vector<uint32_t> tile_key(const Plan& p);
 /* target sub-grid of sweep j of level l over geometry g (grid dims) */
 void sweep_grid(const Geo& g, const uint32_t* order_grid, int d, int j,
                 uint32_t h, uint32_t* start, uint32_t* step, uint32_t* cnt);
@@ -311,16 +323,19 @@ void launch_anchor_copy(const Geo& g, uint32_t stride, const uint32_t na[3],
                         hipStream_t s);
 void launch_anchor_scatter(const Geo& g, uint32_t stride, const uint32_t na[3],
                            const float* in, float* W, hipStream_t s);
+bool sweep_tile_ok(SweepTile t);
 void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
                        float* W, uint16_t* codes, bool write_w,
-                       uint32_t* status, hipStream_t s);
+                       uint32_t* status, hipStream_t s,
+                       SweepTile t = SweepTile());
+void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
+                         const uint16_t* codes, hipStream_t s,
+                         SweepTile t = SweepTile());
 void launch_row_comp(const Geo& g, const RowJob& rj, const float* x, float* W,
                      uint16_t* codes, bool write_w, uint32_t* status,
                      hipStream_t s);
 void launch_row_decomp(const Geo& g, const RowJob& rj, float* W,
                        const uint16_t* codes, hipStream_t s);
-void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
-                         const uint16_t* codes, hipStream_t s);
 void launch_unpred_scatter(const Geo& g, const SweepTable& st,
                            const uint32_t* upos, const float* vals,
                            uint64_t n_unpred, uint64_t n_codes, float* W,

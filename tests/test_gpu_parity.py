@@ -288,6 +288,22 @@ def test_tune_parity(codec, ref, name, make, s, cfgkw, target, rel):
     roundtrip_check(codec, ref, x, e, rp)
 
 
+@pytest.mark.parametrize("shape,s,rel", [((40, 41, 42), 8, 1e-3),
+                                         ((130, 129), 16, 1e-4),
+                                         ((3, 200, 70), 32, 1e-2)])
+def test_autotuned_tiles_keep_streams(codec, ref, shape, s, rel):
+    # any launch tile gives the same bins: streams still equal the oracle's
+    import paper_2310_14133_amd as q
+    x = fields.grf(shape, 61)
+    e = rel * (float(x.max()) - float(x.min()))
+    rp = ref.make_params(x.ndim, "cubic", None, 1.25, 2.0, anchor_stride=s)
+    n, t_def, t_best = codec.autotune_tiles(x.shape, qparams(q, rp, x.ndim))
+    print(f"autotuned {n} sweeps for {shape}: {t_def:.4f} -> {t_best:.4f} ms",
+          flush=True)
+    assert n >= 1 and 0.0 < t_best <= t_def
+    roundtrip_check(codec, ref, x, e, rp)
+
+
 def test_packed_stream_corruption(codec, ref):
     import paper_2310_14133_amd as q
     x = fields.bumps_and_waves(160, 2)
