@@ -227,6 +227,24 @@ qoz_status qoz_decompress_batch(qoz_ctx* ctx, qoz_batch_dec_item* items,
                                 uint32_t n, uint32_t workers,
                                 hipStream_t stream);
 
+/* Decompression of items[0..n) (at most 65536) on `stream` through device
+ * work queues, in a number of launches that does not grow with n: the
+ * headers and codebooks of all streams are read back together, one launch
+ * decodes every stream's Huffman chunks, and each round of inverse sweeps
+ * (the r-th sweep, or fused level-1 row pair, of every stream) is one
+ * launch, as is the placing of every stream's exact values (anchors,
+ * unpredictable bins); a workgroup finds its stream from the queue's
+ * running count of workgroups.  A packed payload takes one more launch of
+ * its own.  Outputs equal qoz_decompress's bit for
+ * bit; sweeps use the default launch tiles.  Items must not share
+ * outputs.  ms and done_ms of every item are the call's duration.  Returns
+ * as qoz_compress_batch; a stream that fails its checks leaves the others
+ * decoded.  Scratch: the field's codes, unpredictable positions and (when
+ * packed) the expanded payload of every stream at once, kept in ctx.
+ * Errors: EINVAL, EDEVICE, ENOMEM, or an item's status. */
+qoz_status qoz_decompress_queue(qoz_ctx* ctx, qoz_batch_dec_item* items,
+                                uint32_t n, hipStream_t stream);
+
 /* ---- Learned tuner ------------------------------------------------------
  * A stand-in for the trial search of Sec. VI: a small network maps
  * features of the sampled blocks to the search's choices (one interpolation

@@ -100,6 +100,7 @@ def lib():
         L.qoz_compress_batch.argtypes = [vp, vp, u32, C.c_int,
                                          C.POINTER(TuneConfig), u32, vp]
         L.qoz_decompress_batch.argtypes = [vp, vp, u32, u32, vp]
+        L.qoz_decompress_queue.argtypes = [vp, vp, u32, vp]
         L.qoz_learned_features.argtypes = [vp, vp, Shape, dbl,
                                            C.POINTER(TuneConfig), vp, vp,
                                            u64, C.POINTER(u64), vp]
@@ -122,7 +123,8 @@ def lib():
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
                    "qoz_metrics", "qoz_error_ac", "qoz_autotune_tiles",
                    "qoz_compress_batch",
-                   "qoz_decompress_batch", "qoz_learned_features",
+                   "qoz_decompress_batch", "qoz_decompress_queue",
+                   "qoz_learned_features",
                    "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
                    "qoz_tune_learned", "qoz_ctx_set_timing",
                    "qoz_ctx_set_timing_mask",
@@ -296,6 +298,13 @@ def qoz_compress_batch(ctx, items, target, cfg, workers, stream):
                                     len(items), int(target),
                                     C.byref(cfg) if cfg else None,
                                     int(workers), C.c_void_p(stream))
+
+
+def qoz_decompress_queue(ctx, items, stream):
+    """items: a ctypes array of BatchDecItem; returns the status without
+    raising."""
+    return lib().qoz_decompress_queue(ctx, C.cast(items, C.c_void_p),
+                                      len(items), C.c_void_p(stream))
 
 
 def qoz_decompress_batch(ctx, items, workers, stream):
@@ -512,30 +521,52 @@ class Codec:
                            qoz_last_error())
         return [outs[i][:items[i].out_bytes] for i in range(n)], items
 
-    def decompress_batch(self, zs, workers=4):
-        """Decompress a list of streams; returns (fields, items)."""
+    def _dec_items(self, zs, out):
         torch = self.torch
         n = len(zs)
         items = (BatchDecItem * n)()
-        ys = []
+        keep = []
         for i, z in enumerate(zs):
             zc = z.contiguous()
-            if zc.numel() < HEADER_BYTES:
-                raise QozError(QOZ_EFORMAT, "decompress_batch",
-                               f"stream {i} too short")
-            sh, _, _ = qoz_inspect(zc[:HEADER_BYTES].cpu().numpy().tobytes())
-            dims = tuple(int(sh.dims[j]) for j in range(sh.ndim))
-            y = torch.empty(dims, dtype=torch.float32, device=self.device)
-            ys.append((zc, y))
+            if out is not None:
+                y = out[i]
+            else:
+                if zc.numel() < HEADER_BYTES:
+                    raise QozError(QOZ_EFORMAT, "decompress_batch",
+                                   f"stream {i} too short")
+                sh, _, _ = qoz_inspect(
+                    zc[:HEADER_BYTES].cpu().numpy().tobytes())
+                dims = tuple(int(sh.dims[j]) for j in range(sh.ndim))
+                y = torch.empty(dims, dtype=torch.float32, device=self.device)
+            keep.append((zc, y))
             it = items[i]
             it.d_in, it.in_bytes = zc.data_ptr(), zc.numel()
             it.d_y, it.y_cap_elems = y.data_ptr(), y.numel()
+        return items, keep
+
+    def decompress_batch(self, zs, workers=4, out=None):
+        """Decompress a list of streams on worker threads; returns (fields,
+        items).  out: preallocated float32 fields (else sized from the
+        headers)."""
+        items, keep = self._dec_items(zs, out)
         st = qoz_decompress_batch(self.ctx, items, workers, self._stream())
         if st != QOZ_OK:
-            bad = [i for i in range(n) if items[i].status != QOZ_OK]
+            bad = [i for i in range(len(zs)) if items[i].status != QOZ_OK]
             raise QozError(st, f"qoz_decompress_batch (fields {bad[:8]})",
                            qoz_last_error())
-        return [y for _, y in ys], items
+        return [y for _, y in keep], items
+
+    def decompress_queue(self, zs, out=None, check=True):
+        """Decompress a list of streams through the device work queues;
+        returns (fields, items).  With check=False a failing stream does
+        not raise (its item carries the status)."""
+        items, keep = self._dec_items(zs, out)
+        st = qoz_decompress_queue(self.ctx, items, self._stream())
+        if st != QOZ_OK and check:
+            bad = [i for i in range(len(zs)) if items[i].status != QOZ_OK]
+            raise QozError(st, f"qoz_decompress_queue (fields {bad[:8]})",
+                           qoz_last_error())
+        return [y for _, y in keep], items
 
     # ---- learned tuner -------------------------------------------------
     def learned_features(self, x, abs_eb, cfg=None, per_block=False):

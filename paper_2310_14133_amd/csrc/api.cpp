@@ -23,7 +23,7 @@ constexpr size_t kPinTable = 256u << 10;       /* 512 KB */
 constexpr size_t kPinStage = 768u << 10;       /* 256 KB */
 constexpr size_t kPinStatus = 1024u << 10;     /* 4 KB */
 constexpr size_t kPinSmall = (1024u << 10) + 4096;
-constexpr size_t kPinBase = 2u << 20;
+constexpr size_t kPinBase = kPinSingleBytes;
 
 static inline uint8_t* pin(qoz_ctx* c, size_t off) {
   return (uint8_t*)c->pinned + off;

@@ -81,6 +81,18 @@ qoz_status to_host(qoz_ctx* c, void* h_dst, const void* d_src, size_t bytes,
   return QOZ_OK;
 }
 
+qoz_status gather_to_host(qoz_ctx* c, HostCopy* copies, uint32_t n,
+                          hipStream_t s) {
+  if (!n) return QOZ_OK;
+  for (uint32_t i = 0; i < n; ++i)
+    QOZ_TRY(pinned_dev(c, copies[i].dst, copies[i].bytes, &copies[i].dst));
+  void* list = nullptr;
+  QOZ_TRY(pinned_dev(c, copies, sizeof(HostCopy) * n, &list));
+  launch_gather_host((const HostCopy*)list, n, s);
+  QOZ_HIP(hipGetLastError());
+  return QOZ_OK;
+}
+
 qoz_status to_device(qoz_ctx* c, void* d_dst, const void* h_src,
                      size_t bytes, hipStream_t s) {
   void* d = nullptr;
@@ -183,7 +195,7 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->upos,       &c->hsort,      &c->scan,
                     &c->feat,       &c->mlp_io,     &c->mlp_part,
                     &c->mlp_loss,   &c->hsort_ids,  &c->pcoff,
-                    &c->ptmp};
+                    &c->ptmp,       &c->queue};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

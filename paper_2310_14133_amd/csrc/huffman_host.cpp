@@ -173,27 +173,26 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
                       uint32_t n_used, DecTables* t,
                       std::vector<uint32_t>* sorted) {
   std::memset(t, 0, sizeof(*t));
-  std::vector<uint8_t> len(kNSym, 0);
+  uint64_t per_len[kMaxCodeLen + 2] = {0};
   int prev = -1;
   for (uint32_t i = 0; i < n_used; ++i) {
     if ((int)syms[i] <= prev) return false;
     if (lens[i] < 1 || lens[i] > kMaxCodeLen) return false;
     prev = syms[i];
-    len[syms[i]] = lens[i];
+    per_len[lens[i]]++;
   }
   /* Kraft sum must not exceed one */
   unsigned __int128 kraft = 0;
   for (uint32_t i = 0; i < n_used; ++i)
     kraft += (unsigned __int128)1 << (kMaxCodeLen - lens[i]);
   if (kraft > ((unsigned __int128)1 << kMaxCodeLen)) return false;
-  std::vector<uint64_t> code(kNSym);
-  canonical_codes(len.data(), kNSym, code.data());
+  /* code[i] of symbol syms[i] (ascending symbols) */
+  std::vector<uint64_t> code(n_used ? n_used : 1);
+  canonical_codes_sparse(syms, lens, n_used, code.data());
   t->n_used = n_used;
-  t->zlen = len[0];
-  t->zcode = len[0] ? code[0] : 0;
+  t->zlen = n_used && syms[0] == 0 ? lens[0] : 0;
+  t->zcode = t->zlen ? code[0] : 0;
   {
-    uint64_t per_len[kMaxCodeLen + 2] = {0};
-    for (uint32_t i = 0; i < n_used; ++i) per_len[lens[i]]++;
     uint64_t c = 0; /* first canonical code of length L */
     t->lim_half[0] = 0;
     for (int L = 1; L <= kMaxCodeLen; ++L) {
@@ -201,16 +200,21 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
       t->lim_half[L] = (c + per_len[L]) << (63 - L);
     }
   }
-  sorted->clear();
+  /* symbols in canonical order (length, then symbol): a counting sort */
+  sorted->assign(n_used, 0u);
+  uint32_t pos[kMaxCodeLen + 2] = {0};
+  uint32_t acc = 0;
   for (int l = 1; l <= kMaxCodeLen; ++l) {
-    t->off[l] = (uint32_t)sorted->size();
-    for (uint32_t i = 0; i < n_used; ++i)
-      if (lens[i] == l) {
-        if (t->cnt[l] == 0) t->first[l] = code[syms[i]];
-        t->cnt[l]++;
-        sorted->push_back(syms[i]);
-      }
-    if (t->cnt[l]) t->maxlen = (uint32_t)l;
+    t->off[l] = acc;
+    pos[l] = acc;
+    t->cnt[l] = (uint32_t)per_len[l];
+    acc += (uint32_t)per_len[l];
+    if (per_len[l]) t->maxlen = (uint32_t)l;
+  }
+  for (uint32_t i = 0; i < n_used; ++i) {
+    const uint32_t l = lens[i];
+    if (pos[l] == t->off[l]) t->first[l] = code[i];
+    (*sorted)[pos[l]++] = syms[i];
   }
   /* Fast tables: a code of length l fills the 2^(width - l) entries that
    * start with it (l <= width); entries of longer (or invalid) codes stay 0
@@ -218,7 +222,7 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
   for (uint32_t i = 0; i < n_used; ++i) {
     const uint32_t l = lens[i];
     if (l > (uint32_t)kLenBits) continue;
-    const uint64_t cv = code[syms[i]];
+    const uint64_t cv = code[i];
     const uint8_t e = (uint8_t)(l | (syms[i] == 0 ? 0x80u : 0u));
     const uint32_t base = (uint32_t)(cv << (kLenBits - l));
     for (uint32_t k = 0; k < (1u << (kLenBits - l)); ++k) t->lz[base + k] = e;

@@ -25,6 +25,7 @@
  * words), a codeword is invalid, or a chunk's symbol-0 count disagrees with
  * the chunk table.
  */
+#include "qoz_device.h"
 #include "qoz_internal.h"
 
 namespace qoz {
@@ -201,14 +202,14 @@ __device__ __forceinline__ uint32_t group_incl_scan(uint32_t v, uint32_t j) {
   return v;
 }
 
-__global__ __launch_bounds__(kDecWG) void k_huff_decode(
-    const uint32_t* __restrict__ payload, uint64_t n_words,
+/* Workgroup wg of a stream's decoding: its chunks wg * kChunksPerWG on. */
+__device__ __forceinline__ void decode_wg(
+    DecShared& sh, const uint32_t* __restrict__ payload, uint64_t n_words,
     const uint64_t* __restrict__ coff, const uint32_t* __restrict__ upre,
-    const uint16_t* __restrict__ segs, Chunks ch,
+    const uint16_t* __restrict__ segs, const Chunks& ch,
     uint64_t n_unpred, const DecTables* __restrict__ tabs,
     const uint32_t* __restrict__ syms, uint16_t* __restrict__ codes,
-    uint32_t* __restrict__ upos, uint32_t* status) {
-  __shared__ DecShared sh;
+    uint32_t* __restrict__ upos, uint32_t* status, uint32_t wg) {
   {
     const uint4* src = reinterpret_cast<const uint4*>(tabs->lz);
     uint4* dst = reinterpret_cast<uint4*>(sh.lz);
@@ -238,8 +239,7 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
 
   /* this lane's chunk and segment */
   const uint32_t j = threadIdx.x % kSegPerChunk;
-  const uint64_t c = (uint64_t)blockIdx.x * kChunksPerWG +
-                     threadIdx.x / kSegPerChunk;
+  const uint64_t c = (uint64_t)wg * kChunksPerWG + threadIdx.x / kSegPerChunk;
   const uint64_t n_chunks = ch.count();
   const bool have = c < n_chunks;
   bool bad = false;
@@ -374,6 +374,42 @@ __global__ __launch_bounds__(kDecWG) void k_huff_decode(
     if (zacc != u1 - u0) bad = true;
   }
   if (have && bad) atomicOr(status, kStBadStream);
+}
+
+__global__ __launch_bounds__(kDecWG) void k_huff_decode(
+    const uint32_t* __restrict__ payload, uint64_t n_words,
+    const uint64_t* __restrict__ coff, const uint32_t* __restrict__ upre,
+    const uint16_t* __restrict__ segs, Chunks ch,
+    uint64_t n_unpred, const DecTables* __restrict__ tabs,
+    const uint32_t* __restrict__ syms, uint16_t* __restrict__ codes,
+    uint32_t* __restrict__ upos, uint32_t* status) {
+  __shared__ DecShared sh;
+  decode_wg(sh, payload, n_words, coff, upre, segs, ch, n_unpred, tabs, syms,
+            codes, upos, status, blockIdx.x);
+}
+
+/* Every stream of a batch in one launch: a workgroup decodes chunks of the
+ * stream its queue entry names. */
+__global__ __launch_bounds__(kDecWG) void k_huff_decode_q(
+    const DecJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  __shared__ DecShared sh;
+  const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
+  const DecJob& a = jobs[j];
+  decode_wg(sh, a.payload, a.n_words, a.coff, a.upre, a.segs, a.ch,
+            a.n_unpred, a.tabs, a.syms, a.codes, a.upos, a.status,
+            blockIdx.x - wg0[j]);
+}
+
+uint32_t decode_workgroups(uint64_t n_chunks) {
+  return (uint32_t)((n_chunks + kChunksPerWG - 1) / kChunksPerWG);
+}
+
+void launch_huff_decode_q(const DecJob* jobs, const uint32_t* wg0,
+                          uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_huff_decode_q, dim3(total_wg), dim3(kDecWG), 0, s,
+                     jobs, wg0, n_jobs);
 }
 
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,

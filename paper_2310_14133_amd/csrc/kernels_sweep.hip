@@ -114,6 +114,85 @@ void launch_copy_regions(void* const* dst, const void* const* src,
                      s, r);
 }
 
+/* Many device-to-host copies in one launch, a workgroup per copy; the
+ * copy list itself lies in coherent host memory. */
+__global__ __launch_bounds__(256) void k_gather_host(
+    const HostCopy* __restrict__ list) {
+  const HostCopy* h = list + blockIdx.x;
+  const uint8_t* src = (const uint8_t*)__hip_atomic_load(
+      (const uint64_t*)&h->src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  uint8_t* dst = (uint8_t*)__hip_atomic_load(
+      (const uint64_t*)&h->dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  const uint64_t n = __hip_atomic_load(&h->bytes, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+  if ((((uintptr_t)dst | (uintptr_t)src | n) & 3) == 0) {
+    const uint32_t* s4 = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d4 = reinterpret_cast<uint32_t*>(dst);
+    for (uint64_t i = threadIdx.x; i < n / 4; i += blockDim.x)
+      __hip_atomic_store(d4 + i, s4[i], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+  } else {
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x)
+      __hip_atomic_store(dst + i, src[i], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+void launch_gather_host(const HostCopy* list, uint32_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_gather_host, dim3(n), dim3(256), 0, s, list);
+}
+
+/* The exact values of a batch of streams: per job (one stream) the anchor
+ * grid (first wg_anchor workgroups, one anchor per lane) and then the
+ * unpredictable values (a grid-stride loop over the remaining ones). */
+__global__ __launch_bounds__(256) void k_exact_q(
+    const ExactJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
+  const ExactJob& a = jobs[j];
+  const uint32_t lid = blockIdx.x - wg0[j];
+  if (lid < a.wg_anchor) {
+    const uint32_t t = lid * blockDim.x + threadIdx.x;
+    const uint32_t total = a.na[0] * a.na[1] * a.na[2];
+    if (t >= total) return;
+    const uint32_t a2 = t % a.na[2];
+    const uint32_t r = t / a.na[2];
+    const uint32_t a1 = r % a.na[1];
+    const uint32_t a0 = r / a.na[1];
+    a.W[a0 * a.stride * a.g.st[0] + a1 * a.stride * a.g.st[1] +
+        a2 * a.stride] = a.anchors[t];
+    return;
+  }
+  const uint32_t wgu = wg0[j + 1] - wg0[j] - a.wg_anchor;
+  bool bad = false;
+  for (uint64_t r = (uint64_t)(lid - a.wg_anchor) * blockDim.x + threadIdx.x;
+       r < a.n_unpred; r += (uint64_t)wgu * blockDim.x) {
+    const uint32_t pos = a.upos[r];
+    if (pos >= a.n_codes) {
+      bad = true;
+      continue;
+    }
+    a.W[point_of(*a.st, a.g, pos)] = a.vals[r];
+  }
+  if (bad) atomicOr(a.status, kStBadStream);
+}
+
+uint32_t exact_job_workgroups(ExactJob* j) {
+  const uint64_t total = (uint64_t)j->na[0] * j->na[1] * j->na[2];
+  j->wg_anchor = (uint32_t)((total + 255) / 256);
+  uint64_t wu = (j->n_unpred + 255) / 256;
+  if (wu > 4096) wu = 4096;
+  return j->wg_anchor + (uint32_t)wu;
+}
+
+void launch_exact_q(const ExactJob* jobs, const uint32_t* wg0,
+                    uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_exact_q, dim3(total_wg), dim3(256), 0, s, jobs, wg0,
+                     n_jobs);
+}
+
 void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
                       hipStream_t s) {
   if (!bytes) return;
@@ -252,24 +331,32 @@ __global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_comp(
 /* Decompression: bins >= 1 reconstruct pred + (bin - R) * 2e_l with the
  * same two roundings as the compressor.  Bin 0 (unpredictable) is skipped:
  * its exact value was scattered into W before the sweeps. */
-__global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_decomp(
-    Geo g, Sweep s, float* W, const uint16_t* __restrict__ codes) {
-  const uint32_t lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y,
-                                gridDim.x * gridDim.y);
-  const uint32_t bx = lb % gridDim.x, by = lb / gridDim.x;
-  const uint32_t i2 = bx * kSweepTX + threadIdx.x;
+/* Workgroup (bx, by) of a sweep's gx x gy grid of ty-row tiles; this lane
+ * is target tx of row tyi of the tile. */
+__device__ __forceinline__ void sweep_decomp_wg(
+    const Geo& g, const Sweep& s, float* W, const uint16_t* __restrict__ codes,
+    uint32_t bx, uint32_t by, uint32_t gy, uint32_t tx, uint32_t tyi,
+    uint32_t ty) {
+  const uint32_t i2 = bx * kSweepTX + tx;
   if (i2 >= s.cnt[2]) return;
   const uint32_t rows = s.cnt[0] * s.cnt[1];
   const uint32_t sk = g.st[s.k];
   const uint32_t nk = g.n[s.k];
-  const uint32_t ty = blockDim.y;
-  for (uint32_t r = by * ty + threadIdx.y; r < rows; r += gridDim.y * ty) {
+  for (uint32_t r = by * ty + tyi; r < rows; r += gy * ty) {
     SweepPoint sp = sweep_point(g, s, r, i2);
     const int32_t code = codes[sp.pos];
     if (code == 0) continue;
     float pred = predict_at(W, sp.idx, sp.pk, sk, nk, s.h, s.cubic);
     W[sp.idx] = dequantize_bin(pred, code, s.twoeb);
   }
+}
+
+__global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_decomp(
+    Geo g, Sweep s, float* W, const uint16_t* __restrict__ codes) {
+  const uint32_t lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y,
+                                gridDim.x * gridDim.y);
+  sweep_decomp_wg(g, s, W, codes, lb % gridDim.x, lb / gridDim.x, gridDim.y,
+                  threadIdx.x, threadIdx.y, blockDim.y);
 }
 
 /* Unpredictable values to their points: upos[r] is the stream position of
@@ -515,14 +602,15 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
   if (bad) atomicOr(status, kStNonFinite);
 }
 
-/* Decompression: bin 0 keeps the exact value already scattered into W. */
-__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
-    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
-  extern __shared__ float E[];
+/* Decompression: bin 0 keeps the exact value already scattered into W.
+ * Workgroup wg of the job (kRowThreads lanes, E its LDS rows). */
+__device__ __forceinline__ void row_decomp_wg(
+    const Geo& g, const RowJob& rj, float* W,
+    const uint16_t* __restrict__ codes, uint32_t wg, float* E) {
   const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
   const uint32_t spans = (n2 + kSpan - 1) / kSpan;
   const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
-  const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
+  const uint32_t r0 = wg * rj.rows_per_wg;
   const uint32_t items = rj.rows_per_wg * spans;
   const RowItems ri(spans, items, rows, rj.rcnt[1]);
   for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
@@ -592,6 +680,12 @@ __global__ __launch_bounds__(kRowThreads) void k_row_decomp(
   }
 }
 
+__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
+    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
+  extern __shared__ float E[];
+  row_decomp_wg(g, rj, W, codes, blockIdx.x, E);
+}
+
 static uint32_t row_blocks(const Geo& g, RowJob* rj, size_t* lds) {
   const uint32_t rows = rj->rcnt[0] * rj->rcnt[1];
   const uint32_t spans = (g.n[2] + kSpan - 1) / kSpan;
@@ -626,6 +720,27 @@ void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
                      rj, W, codes);
 }
 
+/* One round of a batch's inverse sweeps: each job is one sweep (64 x 4
+ * lane tiles) or one fused level-1 row pair of a different field, so the
+ * jobs of a round are independent of each other. */
+__global__ __launch_bounds__(kRowThreads) void k_sweep_round_q(
+    const SweepJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  extern __shared__ float E[];
+  const uint32_t gid = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t j = find_job(wg0, n_jobs, gid);
+  const SweepJob& a = jobs[j];
+  const uint32_t lid = gid - wg0[j];
+  if (a.rows)
+    row_decomp_wg(a.g, a.rj, a.W, a.codes, lid, E);
+  else
+    sweep_decomp_wg(a.g, a.s, a.W, a.codes, lid % a.gx, lid / a.gx, a.gy,
+                    threadIdx.x % kSweepTX, threadIdx.x / kSweepTX,
+                    kRowThreads / kSweepTX);
+}
+
+static_assert(kRowThreads % kSweepTX == 0, "queued sweep tiles");
+
 /* Launch shape of a sweep: x covers 64 consecutive targets of a row, y
  * covers rows (flattened over the two outer sub-grid dimensions), ty rows
  * per workgroup and rpt rows per lane (a grid-stride loop), the grid's y
@@ -657,6 +772,30 @@ void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
   else
     hipLaunchKernelGGL(k_sweep_comp<false>, grid, block, 0, s, g, sw, x, W,
                        codes, status);
+}
+
+uint32_t sweep_job_prepare(SweepJob* j, size_t* lds) {
+  *lds = 0;
+  if (j->rows) {
+    if (!j->rj.rcnt[0] || !j->rj.rcnt[1]) return 0;
+    return row_blocks(j->g, &j->rj, lds);
+  }
+  if (j->s.count == 0) return 0;
+  SweepTile t;
+  t.ty = kRowThreads / kSweepTX;
+  t.rpt = 1;
+  const dim3 grid = sweep_grid_dim(j->s, t);
+  j->gx = grid.x;
+  j->gy = grid.y;
+  return grid.x * grid.y;
+}
+
+void launch_sweep_round_q(const SweepJob* jobs, const uint32_t* wg0,
+                          uint32_t n_jobs, uint32_t total_wg, size_t lds,
+                          hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_sweep_round_q, dim3(total_wg), dim3(kRowThreads), lds,
+                     s, jobs, wg0, n_jobs);
 }
 
 void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,

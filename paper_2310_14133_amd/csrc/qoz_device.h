@@ -152,5 +152,22 @@ __device__ __forceinline__ uint32_t point_of(const SweepTable& t, const Geo& g, 
   return p0 * g.st[0] + p1 * g.st[1] + p2;
 }
 
+/* Work queues of several fields in one launch: job j owns the launch's
+ * workgroups [wg0[j], wg0[j + 1]) (wg0[0] = 0, nondecreasing).  Returns
+ * the job of workgroup wg, the last j with wg0[j] <= wg, counted with one
+ * ballot per 64 jobs; the same on every lane.  Every lane of the wave must
+ * be active. */
+__device__ __forceinline__ uint32_t find_job(const uint32_t* __restrict__ wg0,
+                                             uint32_t n_jobs, uint32_t wg) {
+  const uint32_t lane = __lane_id();
+  uint32_t cnt = 0;
+  for (uint32_t b = 0; b < n_jobs; b += 64) {
+    const uint32_t i = b + lane;
+    const bool le = i < n_jobs && wg0[i] <= wg;
+    cnt += (uint32_t)__popcll(__ballot(le));
+  }
+  return __builtin_amdgcn_readfirstlane(cnt - 1);
+}
+
 }  // namespace qoz
 #endif

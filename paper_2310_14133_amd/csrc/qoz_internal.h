@@ -26,6 +26,9 @@ constexpr uint32_t kSegLog2 = 9;           /* a chunk holds 8 segments of */
 constexpr uint32_t kSeg = 1u << kSegLog2;  /* 512 bins, each decodable alone */
 constexpr uint32_t kSegPerChunk = kChunk / kSeg;
 constexpr size_t kHeaderBytes = 200;
+/* pinned staging bytes of the single-field calls; the batched
+ * decompression stages past them */
+constexpr size_t kPinSingleBytes = 2u << 20;
 constexpr uint16_t kStreamVersion = 4;       /* unpacked payload */
 constexpr uint16_t kStreamVersionPacked = 5; /* zero-word packed payload */
 constexpr uint32_t kPackPercent = 97; /* pack when packed <= 97 % of raw */
@@ -210,7 +213,8 @@ struct qoz_ctx {
   qoz::DevBuf W, codes, hist, chunk_bits, chunk_zeros, coff, upre, status,
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
-      hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp;
+      hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp,
+      queue;
   /* sweep launch tiles chosen by qoz_autotune_tiles, per plan signature */
   std::map<std::vector<uint32_t>, std::vector<qoz::SweepTile>> tiles_comp,
       tiles_decomp;
@@ -377,6 +381,68 @@ void launch_unpack(const uint32_t* src, uint64_t n_packed,
                    const uint64_t* coff, const uint64_t* pcoff,
                    uint64_t n_chunks, uint64_t n_words, uint32_t* raw,
                    uint32_t* status, hipStream_t s);
+/* Work queues of the batched decompression: one entry per field (decode)
+ * or per field and round (sweeps); entry j owns the launch's workgroups
+ * [wg0[j], wg0[j + 1]). */
+struct DecJob {
+  const uint32_t* payload;
+  uint64_t n_words;
+  const uint64_t* coff;
+  const uint32_t* upre;
+  const uint16_t* segs;
+  Chunks ch;
+  uint64_t n_unpred;
+  const DecTables* tabs;
+  const uint32_t* syms;
+  uint16_t* codes;
+  uint32_t* upos;
+  uint32_t* status;
+};
+struct SweepJob {
+  Geo g;
+  uint32_t rows;   /* 0: sweep s; 1: fused level-1 rows rj */
+  uint32_t gx, gy; /* sweep grid (set by sweep_job_prepare) */
+  Sweep s;
+  RowJob rj;
+  float* W;
+  const uint16_t* codes;
+};
+/* anchors and unpredictable values of one stream */
+struct ExactJob {
+  Geo g;
+  uint32_t stride, na[3];
+  uint32_t wg_anchor; /* set by exact_job_workgroups */
+  const float* anchors;
+  const SweepTable* st; /* device copy */
+  const uint32_t* upos;
+  const float* vals;
+  uint64_t n_unpred, n_codes;
+  float* W;
+  uint32_t* status;
+};
+/* a device-to-host copy; dst is the device address of pinned staging */
+struct HostCopy {
+  const void* src;
+  void* dst;
+  uint64_t bytes;
+};
+void launch_gather_host(const HostCopy* list, uint32_t n, hipStream_t s);
+/* copies[0..n), an array inside the pinned staging whose dst fields hold
+ * host addresses inside it, in one launch */
+qoz_status gather_to_host(qoz_ctx* c, HostCopy* copies, uint32_t n,
+                          hipStream_t s);
+uint32_t exact_job_workgroups(ExactJob* j);
+void launch_exact_q(const ExactJob* jobs, const uint32_t* wg0,
+                    uint32_t n_jobs, uint32_t total_wg, hipStream_t s);
+uint32_t decode_workgroups(uint64_t n_chunks);
+void launch_huff_decode_q(const DecJob* jobs, const uint32_t* wg0,
+                          uint32_t n_jobs, uint32_t total_wg, hipStream_t s);
+/* workgroups of the job and its LDS bytes; sets its grid or rows per
+ * workgroup */
+uint32_t sweep_job_prepare(SweepJob* j, size_t* lds);
+void launch_sweep_round_q(const SweepJob* jobs, const uint32_t* wg0,
+                          uint32_t n_jobs, uint32_t total_wg, size_t lds,
+                          hipStream_t s);
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
                         const uint64_t* coff, const uint32_t* upre,
                         const uint16_t* segs, const Chunks& chunks,

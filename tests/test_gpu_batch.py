@@ -110,3 +110,106 @@ def test_batch_failing_field_fails_alone(codec, ref):
     for k, i in enumerate(keep):
         assert np.array_equal(zs[k].cpu().numpy(),
                               ref.compress(fs[i][0], fs[i][1], rps[i]))
+
+
+def queue_cases(ref):
+    """Streams of uneven shapes and parameters from the oracle: 2D and 3D,
+    level-1 orders that end on the contiguous dimension (fused row kernels)
+    and ones that do not, a packed payload, an anchor-free plan and a field
+    too small for any sweep."""
+    rng = np.random.default_rng(7)
+    out = []
+    for i, (x, e) in enumerate(batch_fields()):
+        order = None
+        if x.ndim == 3 and i % 2:
+            order = [(2, 0, 1)] * 16  # level 1 ends off the contiguous axis
+        rp = ref.make_params(x.ndim, ["linear", "cubic"][i % 2], order,
+                             [1.0, 1.25, 2.0][i % 3], [1.5, 4.0][i % 2],
+                             anchor_stride=[4, 8, 16, 32][rng.integers(0, 4)])
+        out.append((f"grf{x.shape}", x, e, rp))
+    x = fields.bumps_and_waves(160, 2)
+    out.append(("packed 160^2", x, 1e-2 * float(x.max() - x.min()),
+                ref.make_params(2, "cubic", None, 1.0, 1.5, anchor_stride=64)))
+    x = fields.grf((96, 100, 90), 140)
+    out.append(("grf 96x100x90", x, 1e-4 * float(x.max() - x.min()),
+                ref.make_params(3, "cubic", None, 1.5, 2.0, anchor_stride=32)))
+    x = fields.grf((1000, 700), 141, log_normal=True)
+    out.append(("grf 1000x700", x, 1e-3 * float(x.max() - x.min()),
+                ref.make_params(2, "linear", None, 1.0, 1.5,
+                                anchor_stride=1024)))
+    return out
+
+
+def test_queue_outputs_equal_oracle(codec, ref):
+    import paper_2310_14133_amd as q
+    cases = queue_cases(ref)
+    zs, yrs = [], []
+    for name, x, e, rp in cases:
+        z = ref.compress(x, e, rp)
+        zs.append(to_dev(z))
+        yrs.append(ref.decompress(z))
+    assert any(int(np.frombuffer(z[4:6].cpu().numpy().tobytes(),
+                                 np.uint16)[0]) == 5 for z in zs)
+    print(f"queue of {len(zs)} streams", flush=True)
+    for rep in range(2):  # the second call reuses the context's buffers
+        ys, items = codec.decompress_queue(zs)
+        for i, (name, x, e, rp) in enumerate(cases):
+            assert items[i].status == q.QOZ_OK, name
+            assert tuple(items[i].shape.dims[:x.ndim]) == x.shape, name
+            assert np.array_equal(ys[i].cpu().numpy().view(np.uint32),
+                                  yrs[i].view(np.uint32)), (name, rep)
+    # a batch of one, and an empty batch
+    ys, items = codec.decompress_queue(zs[-2:-1])
+    assert np.array_equal(ys[0].cpu().numpy().view(np.uint32),
+                          yrs[-2].view(np.uint32))
+    ys, items = codec.decompress_queue([])
+    assert ys == [] and len(items) == 0
+
+
+def test_queue_equals_single_calls_tuned(codec):
+    # tuned streams of the library itself: queue output == qoz_decompress
+    import paper_2310_14133_amd as q
+    fs = [f for f in batch_fields() if min(f[0].shape) >= 9]
+    cfg = q.make_tune_config(sample_rate=0.2)
+    zs = [codec.compress(to_dev(x), e, None, "psnr", cfg) for x, e in fs]
+    ys, items = codec.decompress_queue(zs)
+    for i, z in enumerate(zs):
+        y1 = codec.decompress(z)
+        assert np.array_equal(ys[i].cpu().numpy().view(np.uint32),
+                              y1.cpu().numpy().view(np.uint32)), i
+
+
+def test_queue_bad_streams_fail_alone(codec, ref):
+    import paper_2310_14133_amd as q
+    cases = queue_cases(ref)
+    zh = [ref.compress(x, e, rp) for _, x, e, rp in cases]
+    packed = [i for i, z in enumerate(zh)
+              if int(np.frombuffer(z[4:6].tobytes(), np.uint16)[0]) == 5][0]
+    # a packed chunk offset past the payload: found by the device
+    z = zh[packed].copy()
+    wp = int(np.frombuffer(z[196:200].tobytes(), np.uint32)[0])
+    n_chunks = int(np.frombuffer(z[168:176].tobytes(), np.uint64)[0])
+    at = z.size - 8 * n_chunks
+    z[at:at + 8] = np.frombuffer(np.array([wp + 9], np.uint64).tobytes(),
+                                 np.uint8)
+    assert ref.decompress_status(z) == ref.EFORMAT
+    zs = [to_dev(v) for v in zh]
+    zs[packed] = to_dev(z)
+    # a stream cut short: found by the header check on the host
+    cut = 2
+    zs[cut] = zs[cut][:-8].clone()
+    import torch
+    outs = [torch.empty(x.shape, dtype=torch.float32, device="cuda")
+            for _, x, _, _ in cases]
+    print(f"queue with bad streams {packed} and {cut}", flush=True)
+    ys, items = codec.decompress_queue(zs, out=outs, check=False)
+    for i, (name, x, e, rp) in enumerate(cases):
+        if i in (packed, cut):
+            assert items[i].status == q.QOZ_EFORMAT, name
+            continue
+        assert items[i].status == q.QOZ_OK, name
+        assert np.array_equal(ys[i].cpu().numpy().view(np.uint32),
+                              ref.decompress(zh[i]).view(np.uint32)), name
+    with pytest.raises(q.QozError) as err:
+        codec.decompress_queue(zs, out=outs)
+    assert err.value.status == q.QOZ_EFORMAT
