@@ -603,7 +603,87 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
 }
 
 /* Decompression: bin 0 keeps the exact value already scattered into W.
- * Workgroup wg of the job (kRowThreads lanes, E its LDS rows). */
+ * The single-stream kernel keeps its own copy of the body of row_decomp_wg
+ * below: calling the shared inline body compiled to a schedule that ran
+ * 6 % slower at 512^3. */
+__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
+    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
+  extern __shared__ float E[];
+  const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
+  const uint32_t spans = (n2 + kSpan - 1) / kSpan;
+  const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
+  const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
+  const uint32_t items = rj.rows_per_wg * spans;
+  const RowItems ri(spans, items, rows, rj.rcnt[1]);
+  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
+    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
+    if (r0 + rl >= rows) break;
+    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
+    const uint32_t p = u * kSpan;
+    float* Er = E + rl * es;
+    if (c.hasA) {
+      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
+      const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
+      int32_t bins[kSpan / 2];
+      load_bins4(codes, pos, rj.vecA, nA < 4 ? nA : 4u, bins);
+      float pred[kSpan / 2];
+      predict_span_A(g, rj, W, c, p, pred);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k) {
+        if (k >= nA) break;
+        const int32_t code = bins[k];
+        Er[p / 2 + k + 1] = code ? dequantize_bin(pred[k], code, rj.A.twoeb)
+                                 : W[c.row + p + 2 * k];
+      }
+    } else {
+      float wv[kSpan];
+      load_span(W + c.row, p, n2, wv);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k)
+        if (p + 2 * k < n2) Er[p / 2 + k + 1] = wv[2 * k];
+    }
+  }
+  __syncthreads();
+  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
+    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
+    if (r0 + rl >= rows) break;
+    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
+    const uint32_t p = u * kSpan;
+    const float* Er = E + rl * es;
+    float out[kSpan];
+    const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
+    const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
+    int32_t bins[kSpan / 2];
+    load_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
+#pragma unroll
+    for (uint32_t k = 0; k < kSpan / 2; ++k) {
+      const uint32_t t = p / 2 + k, q = 2 * t + 1;
+      out[2 * k] = Er[t + 1];
+      out[2 * k + 1] = 0.0f;
+      if (q >= n2) continue;
+      const int32_t code = bins[k];
+      if (code) {
+        const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
+        const float pred = interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
+                                      hc ? Er[t + 2] : 0.0f,
+                                      hd ? Er[t + 3] : 0.0f, ha, hc, hd);
+        out[2 * k + 1] = dequantize_bin(pred, code, rj.B.twoeb);
+      } else {
+        out[2 * k + 1] = W[c.row + q];
+      }
+    }
+    float* wr = W + c.row;
+    if (p + kSpan <= n2) {
+      *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
+      *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
+    } else {
+      for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+    }
+  }
+}
+
+/* The same for workgroup wg of a queued job (kRowThreads lanes, E its
+ * LDS rows). */
 __device__ __forceinline__ void row_decomp_wg(
     const Geo& g, const RowJob& rj, float* W,
     const uint16_t* __restrict__ codes, uint32_t wg, float* E) {
@@ -680,11 +760,6 @@ __device__ __forceinline__ void row_decomp_wg(
   }
 }
 
-__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
-    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
-  extern __shared__ float E[];
-  row_decomp_wg(g, rj, W, codes, blockIdx.x, E);
-}
 
 static uint32_t row_blocks(const Geo& g, RowJob* rj, size_t* lds) {
   const uint32_t rows = rj->rcnt[0] * rj->rcnt[1];
