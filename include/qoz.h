@@ -245,6 +245,16 @@ qoz_status qoz_decompress_batch(qoz_ctx* ctx, qoz_batch_dec_item* items,
 qoz_status qoz_decompress_queue(qoz_ctx* ctx, qoz_batch_dec_item* items,
                                 uint32_t n, hipStream_t stream);
 
+/* With enable != 0, qoz_decompress_queue keeps its device work (upload,
+ * launches, status read-back) as a HIP graph: a call whose launch
+ * signature (grids, queue layout, scratch addresses, packed payloads)
+ * equals the previous call's captures it once on an internal stream, and
+ * later calls with that signature launch the graph on their stream.  In
+ * practice that is the same batch layout again (equal shapes, codebook
+ * sizes and packing).  Off by default; turning it off frees the graph.
+ * Errors: EINVAL, EDEVICE. */
+qoz_status qoz_ctx_set_queue_graphs(qoz_ctx* ctx, int enable);
+
 /* ---- Learned tuner ------------------------------------------------------
  * A stand-in for the trial search of Sec. VI: a small network maps
  * features of the sampled blocks to the search's choices (one interpolation

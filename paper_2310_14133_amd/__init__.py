@@ -101,6 +101,7 @@ def lib():
                                          C.POINTER(TuneConfig), u32, vp]
         L.qoz_decompress_batch.argtypes = [vp, vp, u32, u32, vp]
         L.qoz_decompress_queue.argtypes = [vp, vp, u32, vp]
+        L.qoz_ctx_set_queue_graphs.argtypes = [vp, C.c_int]
         L.qoz_learned_features.argtypes = [vp, vp, Shape, dbl,
                                            C.POINTER(TuneConfig), vp, vp,
                                            u64, C.POINTER(u64), vp]
@@ -124,6 +125,7 @@ def lib():
                    "qoz_metrics", "qoz_error_ac", "qoz_autotune_tiles",
                    "qoz_compress_batch",
                    "qoz_decompress_batch", "qoz_decompress_queue",
+                   "qoz_ctx_set_queue_graphs",
                    "qoz_learned_features",
                    "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
                    "qoz_tune_learned", "qoz_ctx_set_timing",
@@ -298,6 +300,11 @@ def qoz_compress_batch(ctx, items, target, cfg, workers, stream):
                                     len(items), int(target),
                                     C.byref(cfg) if cfg else None,
                                     int(workers), C.c_void_p(stream))
+
+
+def qoz_ctx_set_queue_graphs(ctx, enable):
+    _check(lib().qoz_ctx_set_queue_graphs(ctx, int(bool(enable))),
+           "qoz_ctx_set_queue_graphs")
 
 
 def qoz_decompress_queue(ctx, items, stream):
@@ -555,6 +562,11 @@ class Codec:
             raise QozError(st, f"qoz_decompress_batch (fields {bad[:8]})",
                            qoz_last_error())
         return [y for _, y in keep], items
+
+    def set_queue_graphs(self, enable):
+        """Replay the work-queue decompression's device work as a HIP graph
+        when a call repeats the previous call's launch signature."""
+        qoz_ctx_set_queue_graphs(self.ctx, enable)
 
     def decompress_queue(self, zs, out=None, check=True):
         """Decompress a list of streams through the device work queues;

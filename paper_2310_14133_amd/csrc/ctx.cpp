@@ -185,6 +185,8 @@ void qoz_ctx_destroy(qoz_ctx* c) {
   for (qoz_ctx* w : c->workers) qoz_ctx_destroy(w);
   (void)hipSetDevice(c->device);
   for (hipStream_t st : c->worker_streams) (void)hipStreamDestroy(st);
+  if (c->qgraph_exec) (void)hipGraphExecDestroy(c->qgraph_exec);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   DevBuf* bufs[] = {&c->W,          &c->codes,      &c->hist,
                     &c->chunk_bits, &c->chunk_zeros, &c->coff,
                     &c->upre,       &c->status,     &c->enc_table,

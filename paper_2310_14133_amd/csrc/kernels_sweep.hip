@@ -181,7 +181,11 @@ __global__ __launch_bounds__(256) void k_exact_q(
 uint32_t exact_job_workgroups(ExactJob* j) {
   const uint64_t total = (uint64_t)j->na[0] * j->na[1] * j->na[2];
   j->wg_anchor = (uint32_t)((total + 255) / 256);
-  uint64_t wu = (j->n_unpred + 255) / 256;
+  /* the unpredictable values' grid-stride loop is sized by the number of
+   * bins, not of unpredictable values, so that streams of the same shapes
+   * give the same launch grid */
+  uint64_t wu = (j->n_codes + 16383) / 16384;
+  if (wu < 1) wu = 1;
   if (wu > 4096) wu = 4096;
   return j->wg_anchor + (uint32_t)wu;
 }

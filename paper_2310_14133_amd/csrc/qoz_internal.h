@@ -218,6 +218,11 @@ struct qoz_ctx {
   /* sweep launch tiles chosen by qoz_autotune_tiles, per plan signature */
   std::map<std::vector<uint32_t>, std::vector<qoz::SweepTile>> tiles_comp,
       tiles_decomp;
+  /* work-queue decompression replayed as a graph (queue_host.cpp) */
+  bool queue_graphs = false;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t qgraph_exec = nullptr;
+  std::vector<uint64_t> qgraph_sig, qgraph_last;
   /* batch workers: their contexts and streams */
   std::vector<qoz_ctx*> workers;
   std::vector<hipStream_t> worker_streams;

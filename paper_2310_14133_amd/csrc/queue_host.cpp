@@ -19,6 +19,11 @@
  * Every target is computed by the single-stream kernels' code, so each
  * output equals qoz_decompress's bit for bit.  The sweeps use the default
  * launch tiles (4 rows of 64 targets per workgroup).
+ *
+ * Steps 2-5 read everything that changes from call to call (streams,
+ * outputs, tables) from the uploaded queues, so with graphs enabled a batch
+ * with the same launch signature (grids, queue layout, scratch addresses,
+ * packed payloads) as the call before replays them as one HIP graph.
  */
 #include <atomic>
 #include <chrono>
@@ -68,10 +73,67 @@ void write_shape(const Plan& P, qoz_shape* out) {
   }
 }
 
+/* The device work of a call as a HIP graph (when enabled): a call whose
+ * signature equals
+ * the previous call's captures its sequence once (on the context's capture
+ * stream, where nothing runs) and launches the graph on s; later calls with
+ * the same signature launch it again.  Other calls issue the sequence on s
+ * directly and remember their signature. */
+template <class Issue>
+qoz_status run_queue_graph(qoz_ctx* c, const std::vector<uint64_t>& sig,
+                           Issue issue, hipStream_t s) {
+  if (!c->queue_graphs) return issue(s);
+  if (c->qgraph_exec && sig == c->qgraph_sig) {
+    QOZ_HIP(hipGraphLaunch(c->qgraph_exec, s));
+    return QOZ_OK;
+  }
+  if (sig != c->qgraph_last) {
+    c->qgraph_last = sig;
+    return issue(s);
+  }
+  if (!c->capture_stream)
+    QOZ_HIP(hipStreamCreateWithFlags(&c->capture_stream,
+                                     hipStreamNonBlocking));
+  QOZ_HIP(hipStreamBeginCapture(c->capture_stream,
+                                hipStreamCaptureModeThreadLocal));
+  const qoz_status st = issue(c->capture_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(c->capture_stream, &g);
+  if (st != QOZ_OK || ee != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    c->qgraph_last.clear();
+    return st != QOZ_OK ? st : hip_fail(ee, "hipStreamEndCapture");
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate");
+  if (c->qgraph_exec) (void)hipGraphExecDestroy(c->qgraph_exec);
+  c->qgraph_exec = ex;
+  c->qgraph_sig = sig;
+  QOZ_HIP(hipGraphLaunch(c->qgraph_exec, s));
+  return QOZ_OK;
+}
+
 }  // namespace
 }  // namespace qoz
 
 using namespace qoz;
+
+extern "C" qoz_status qoz_ctx_set_queue_graphs(qoz_ctx* c, int enable) {
+  clear_error();
+  if (!c) return fail(QOZ_EINVAL, "NULL argument");
+  QOZ_TRY(set_device(c));
+  c->queue_graphs = enable != 0;
+  if (!c->queue_graphs && c->qgraph_exec) {
+    QOZ_HIP(hipGraphExecDestroy(c->qgraph_exec));
+    c->qgraph_exec = nullptr;
+  }
+  c->qgraph_sig.clear();
+  c->qgraph_last.clear();
+  return QOZ_OK;
+}
 
 extern "C" qoz_status qoz_decompress_queue(qoz_ctx* c,
                                            qoz_batch_dec_item* items,
@@ -314,30 +376,53 @@ extern "C" qoz_status qoz_decompress_queue(qoz_ctx* c,
     r_total[r] = tot;
   }
 
-  /* 3. launches */
-  QOZ_TRY(to_device(c, dq, hu, upload, s));
+  /* 3. device work: upload, launches, status read-back.  Everything a
+   * launch reads from the call (streams, outputs, tables) goes through the
+   * uploaded queues, except the expansion of packed payloads, so the same
+   * sequence serves any batch with the same signature below. */
+  uint32_t* hs = (uint32_t*)(pin + hdr + upload);
+  auto issue = [&](hipStream_t q) -> qoz_status {
+    QOZ_TRY(to_device(c, dq, hu, upload, q));
+    for (uint32_t k = 0; k < nf; ++k) {
+      const QField& f = G[k];
+      if (!f.npk) continue;
+      const uint8_t* in = (const uint8_t*)items[f.item].d_in;
+      launch_unpack((const uint32_t*)(in + f.lay.payload), f.npk,
+                    (const uint64_t*)(in + f.lay.coff),
+                    (const uint64_t*)(in + f.lay.pcoff), f.P.n_chunks, f.nw,
+                    (uint32_t*)(dq + f.ptmp_off),
+                    (uint32_t*)(dq + st_off) + k, q);
+    }
+    launch_huff_decode_q((const DecJob*)(dq + dec_jobs),
+                         (const uint32_t*)(dq + dec_wg0), nf, dec_total, q);
+    launch_exact_q((const ExactJob*)(dq + ex_jobs),
+                   (const uint32_t*)(dq + ex_wg0), nf, ex_total, q);
+    for (size_t r = 0; r < rounds; ++r)
+      launch_sweep_round_q((const SweepJob*)(dq + rj_off[r]),
+                           (const uint32_t*)(dq + rw_off[r]), r_jobs[r],
+                           r_total[r], r_lds[r], q);
+    QOZ_TRY(to_host(c, hs, dq + st_off, 4 * (nf ? nf : 1), q));
+    return QOZ_OK;
+  };
+  /* the signature: every value the sequence passes to the device */
+  std::vector<uint64_t> sig = {(uintptr_t)dq, (uintptr_t)c->pinned, hdr,
+                               upload, st_off, nf, dec_jobs, dec_wg0,
+                               dec_total, ex_jobs, ex_wg0, ex_total, rounds};
+  for (size_t r = 0; r < rounds; ++r) {
+    sig.push_back(rj_off[r]);
+    sig.push_back(rw_off[r]);
+    sig.push_back(r_jobs[r]);
+    sig.push_back(r_total[r]);
+    sig.push_back(r_lds[r]);
+  }
   for (uint32_t k = 0; k < nf; ++k) {
     const QField& f = G[k];
     if (!f.npk) continue;
-    const uint8_t* in = (const uint8_t*)items[f.item].d_in;
-    launch_unpack((const uint32_t*)(in + f.lay.payload), f.npk,
-                  (const uint64_t*)(in + f.lay.coff),
-                  (const uint64_t*)(in + f.lay.pcoff), f.P.n_chunks, f.nw,
-                  (uint32_t*)(dq + f.ptmp_off),
-                  (uint32_t*)(dq + st_off) + k, s);
+    sig.insert(sig.end(), {k, (uintptr_t)items[f.item].d_in, f.lay.payload,
+                           f.lay.coff, f.lay.pcoff, f.npk, f.P.n_chunks, f.nw,
+                           f.ptmp_off});
   }
-  launch_huff_decode_q((const DecJob*)(dq + dec_jobs),
-                       (const uint32_t*)(dq + dec_wg0), nf, dec_total, s);
-  launch_exact_q((const ExactJob*)(dq + ex_jobs),
-                 (const uint32_t*)(dq + ex_wg0), nf, ex_total, s);
-  for (size_t r = 0; r < rounds; ++r)
-    launch_sweep_round_q((const SweepJob*)(dq + rj_off[r]),
-                         (const uint32_t*)(dq + rw_off[r]), r_jobs[r],
-                         r_total[r], r_lds[r], s);
-
-  /* 4. status */
-  uint32_t* hs = (uint32_t*)(pin + hdr + upload);
-  QOZ_TRY(to_host(c, hs, dq + st_off, 4 * (nf ? nf : 1), s));
+  QOZ_TRY(run_queue_graph(c, sig, issue, s));
   QOZ_TRY(sync_stream(s));
   const double ms = std::chrono::duration<double, std::milli>(
                         std::chrono::steady_clock::now() - t0)

@@ -151,7 +151,16 @@ def test_queue_outputs_equal_oracle(codec, ref):
     assert any(int(np.frombuffer(z[4:6].cpu().numpy().tobytes(),
                                  np.uint16)[0]) == 5 for z in zs)
     print(f"queue of {len(zs)} streams", flush=True)
-    for rep in range(2):  # the second call reuses the context's buffers
+    import torch
+    # with graphs on: call 1 runs the device work directly, call 2 (same
+    # signature) captures it as a graph, calls 3 and 4 replay the graph;
+    # eager work in between; call 5 with graphs off again
+    codec.set_queue_graphs(True)
+    for rep in range(5):
+        if rep == 4:
+            codec.set_queue_graphs(False)
+        junk = torch.full((1 << 20,), float(rep), device="cuda")
+        assert float(junk.mul_(3.0).sum().item()) == 3.0 * rep * (1 << 20)
         ys, items = codec.decompress_queue(zs)
         for i, (name, x, e, rp) in enumerate(cases):
             assert items[i].status == q.QOZ_OK, name
@@ -213,3 +222,29 @@ def test_queue_bad_streams_fail_alone(codec, ref):
     with pytest.raises(q.QozError) as err:
         codec.decompress_queue(zs, out=outs)
     assert err.value.status == q.QOZ_EFORMAT
+
+
+def test_queue_many_small_streams(codec, ref):
+    # more streams than one 64-lane ballot covers: every queue's workgroup
+    # lookup runs over several ballots
+    import paper_2310_14133_amd as q
+    rng = np.random.default_rng(11)
+    zs, yrs, shapes = [], [], []
+    for i in range(150):
+        sh = ((int(rng.integers(5, 40)), int(rng.integers(5, 40)))
+              if i % 2 else tuple(int(v) for v in rng.integers(3, 14, 3)))
+        x = fields.grf(sh, 500 + i, log_normal=(i % 5 == 0))
+        e = [1e-2, 1e-3, 1e-4][i % 3] * (float(x.max()) - float(x.min()))
+        rp = ref.make_params(x.ndim, ["linear", "cubic"][i % 2], None,
+                             1.25, 2.0, anchor_stride=[4, 8, 16][i % 3])
+        z = ref.compress(x, e, rp)
+        zs.append(to_dev(z))
+        yrs.append(ref.decompress(z))
+        shapes.append(sh)
+    print(f"queue of {len(zs)} small streams", flush=True)
+    ys, items = codec.decompress_queue(zs)
+    for i in range(len(zs)):
+        assert items[i].status == q.QOZ_OK, i
+        assert ys[i].shape == shapes[i]
+        assert np.array_equal(ys[i].cpu().numpy().view(np.uint32),
+                              yrs[i].view(np.uint32)), i
