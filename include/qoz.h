@@ -338,6 +338,31 @@ qoz_status qoz_tune_learned(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
                             const qoz_tune_config* cfg, qoz_params* out,
                             int* used_fallback, hipStream_t stream);
 
+/* Learned tuning of many fields: the features of every supported field
+ * (3D, every dimension >= 33), one forward pass over all of them, then the
+ * online tuner, one field at a time in item order, for the fields that are
+ * unsupported or below min_confidence.  Each item's params and
+ * used_fallback equal what qoz_tune_learned gives for it alone.
+ * params.anchor_stride is read on input (0 = default).  Synchronous.
+ * Returns QOZ_OK when every item succeeded, else the status of the first
+ * failing item in index order (each item keeps its own).
+ * Errors: EINVAL, EDEVICE, ENOMEM, or an item's status. */
+typedef struct {
+  const float* d_x;   /* in: field (device) */
+  qoz_shape shape;    /* in */
+  double abs_eb;      /* in */
+  qoz_params params;  /* in: anchor_stride; out: parameters */
+  int used_fallback;  /* out */
+  qoz_status status;  /* out */
+} qoz_learned_item;
+
+qoz_status qoz_tune_learned_batch(qoz_ctx* ctx, qoz_learned_item* items,
+                                  uint32_t n, const float* d_params,
+                                  double min_confidence,
+                                  qoz_target fallback_target,
+                                  const qoz_tune_config* cfg,
+                                  hipStream_t stream);
+
 /* Message describing the calling thread's last error ("" if none). */
 const char* qoz_last_error(void);
 

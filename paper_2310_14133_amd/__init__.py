@@ -57,6 +57,12 @@ class BatchDecItem(C.Structure):
                 ("done_ms", C.c_double)]
 
 
+class LearnedItem(C.Structure):
+    _fields_ = [("d_x", C.c_void_p), ("shape", Shape),
+                ("abs_eb", C.c_double), ("params", Params),
+                ("used_fallback", C.c_int), ("status", C.c_int)]
+
+
 class QozError(RuntimeError):
     def __init__(self, status, what, message=""):
         super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}"
@@ -102,6 +108,8 @@ def lib():
         L.qoz_decompress_batch.argtypes = [vp, vp, u32, u32, vp]
         L.qoz_decompress_queue.argtypes = [vp, vp, u32, vp]
         L.qoz_ctx_set_queue_graphs.argtypes = [vp, C.c_int]
+        L.qoz_tune_learned_batch.argtypes = [vp, vp, u32, vp, dbl, C.c_int,
+                                             C.POINTER(TuneConfig), vp]
         L.qoz_learned_features.argtypes = [vp, vp, Shape, dbl,
                                            C.POINTER(TuneConfig), vp, vp,
                                            u64, C.POINTER(u64), vp]
@@ -125,7 +133,7 @@ def lib():
                    "qoz_metrics", "qoz_error_ac", "qoz_autotune_tiles",
                    "qoz_compress_batch",
                    "qoz_decompress_batch", "qoz_decompress_queue",
-                   "qoz_ctx_set_queue_graphs",
+                   "qoz_ctx_set_queue_graphs", "qoz_tune_learned_batch",
                    "qoz_learned_features",
                    "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
                    "qoz_tune_learned", "qoz_ctx_set_timing",
@@ -374,6 +382,18 @@ def qoz_tune_learned(ctx, d_x, shape, abs_eb, d_params, min_confidence,
                                   C.byref(params), C.byref(fb),
                                   C.c_void_p(stream)), "qoz_tune_learned")
     return params, bool(fb.value)
+
+
+def qoz_tune_learned_batch(ctx, items, d_params, min_confidence,
+                           fallback_target, cfg, stream):
+    """items: a ctypes array of LearnedItem; returns the status without
+    raising (each item carries its own)."""
+    return lib().qoz_tune_learned_batch(ctx, C.cast(items, C.c_void_p),
+                                        len(items), C.c_void_p(d_params),
+                                        C.c_double(min_confidence),
+                                        int(fallback_target),
+                                        C.byref(cfg) if cfg else None,
+                                        C.c_void_p(stream))
 
 
 def qoz_last_error():
@@ -666,6 +686,27 @@ class Codec:
                                 params.data_ptr(), min_confidence,
                                 TARGETS[fallback_target], cfg, p,
                                 self._stream())
+
+    def tune_learned_batch(self, xs, abs_ebs, params, min_confidence=0.0,
+                           fallback_target="psnr", cfg=None,
+                           anchor_stride=0):
+        """Learned tuning of a list of fields; returns the items
+        (.params, .used_fallback, .status)."""
+        self._dev(params, self.torch.float32, (MLP_NPARAM,))
+        items = (LearnedItem * len(xs))()
+        for i, (x, e) in enumerate(zip(xs, abs_ebs)):
+            items[i].d_x = x.data_ptr()
+            items[i].shape = self._field(x)
+            items[i].abs_eb = float(e)
+            items[i].params.anchor_stride = anchor_stride
+        st = qoz_tune_learned_batch(self.ctx, items, params.data_ptr(),
+                                    min_confidence, TARGETS[fallback_target],
+                                    cfg, self._stream())
+        if st != QOZ_OK:
+            bad = [i for i in range(len(xs)) if items[i].status != QOZ_OK]
+            raise QozError(st, f"qoz_tune_learned_batch (fields {bad[:8]})",
+                           qoz_last_error())
+        return items
 
     def error_ac(self, x, y):
         """Lag-1 autocorrelation of the errors x - y (Eq. 4)."""

@@ -197,7 +197,7 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->upos,       &c->hsort,      &c->scan,
                     &c->feat,       &c->mlp_io,     &c->mlp_part,
                     &c->mlp_loss,   &c->hsort_ids,  &c->pcoff,
-                    &c->ptmp,       &c->queue};
+                    &c->ptmp,       &c->queue,      &c->lbatch};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

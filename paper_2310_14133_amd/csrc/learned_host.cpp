@@ -11,6 +11,8 @@
 #include <cstring>
 #include <vector>
 
+#include <algorithm>
+
 #include "qoz_internal.h"
 
 namespace qoz {
@@ -124,6 +126,54 @@ extern "C" qoz_status qoz_learned_features(qoz_ctx* c, const float* d_x,
 
 static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
+/* One row of logits: per head the first maximum; returns the smallest of
+ * the heads' softmax probabilities of their picks (0 for NaN logits). */
+static double decide(const float* hz, uint32_t pick[3]) {
+  const uint32_t heads[3] = {kHeadInterp, kHeadAlpha, kHeadBeta};
+  double conf = 1.0;
+  uint32_t o = 0;
+  for (int h = 0; h < 3; ++h) {
+    uint32_t best = 0;
+    for (uint32_t k = 1; k < heads[h]; ++k)
+      if (hz[o + k] > hz[o + best]) best = k;
+    double sum = 0.0;
+    for (uint32_t k = 0; k < heads[h]; ++k)
+      sum += std::exp((double)hz[o + k] - (double)hz[o + best]);
+    const double p = 1.0 / sum;
+    if (!(p >= 0.0)) conf = 0.0; /* NaN logits: untrusted */
+    conf = std::fmin(conf, p);
+    pick[h] = best;
+    o += heads[h];
+  }
+  return conf;
+}
+
+/* The network's picks as parameters: one interpolation type for every
+ * level, the identity dimension order. */
+static qoz_params learned_params(const uint32_t pick[3], uint32_t sa,
+                                 uint32_t L, int d) {
+  qoz_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.anchor_stride = sa;
+  p.levels = L;
+  for (uint32_t l = 0; l < L; ++l) {
+    p.interp[l] = (uint8_t)pick[0];
+    for (int j = 0; j < 3; ++j) p.order[l][j] = (uint8_t)(j < d ? j : 0);
+  }
+  p.alpha = kAlphaL[pick[1]];
+  p.beta = kBetaL[pick[2]];
+  return p;
+}
+
+/* Anchor stride (0 = the default of the dimensionality) and level count. */
+static bool stride_levels(uint32_t want, int d, uint32_t* sa, uint32_t* L) {
+  *sa = want ? want : (d == 2 ? 64u : 32u);
+  if (*sa < 2 || (*sa & (*sa - 1))) return false;
+  *L = 0;
+  while ((2u << *L) <= *sa) ++*L;
+  return *L <= QOZ_MAX_LEVELS;
+}
+
 extern "C" qoz_status qoz_mlp_forward(qoz_ctx* c, const float* d_params,
                                       const float* d_feat, uint32_t batch,
                                       float* d_logits, hipStream_t s) {
@@ -221,12 +271,9 @@ extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
   uint64_t n[3] = {1, 1, 1};
   if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
   QOZ_TRY(set_device(c));
-  const uint32_t sa = out->anchor_stride ? out->anchor_stride
-                                         : (d == 2 ? 64u : 32u);
-  if (sa < 2 || (sa & (sa - 1))) return fail(QOZ_EINVAL, "bad anchor stride");
-  uint32_t L = 0;
-  while ((2u << L) <= sa) ++L;
-  if (L > QOZ_MAX_LEVELS) return fail(QOZ_EINVAL, "anchor stride too large");
+  uint32_t sa = 0, L = 0;
+  if (!stride_levels(out->anchor_stride, d, &sa, &L))
+    return fail(QOZ_EINVAL, "bad anchor stride");
 
   bool supported = d == 3 && n[0] >= 33 && n[1] >= 33 && n[2] >= 33;
   double conf = 0.0;
@@ -252,39 +299,141 @@ extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
     prof_collect(c);
     if (hst[0] & kStNonFinite)
       return fail(QOZ_EINVAL, "sampled blocks contain NaN or Inf");
-    /* per head: first maximum and its softmax probability */
-    const uint32_t heads[3] = {kHeadInterp, kHeadAlpha, kHeadBeta};
-    conf = 1.0;
-    uint32_t o = 0;
-    for (int h = 0; h < 3; ++h) {
-      uint32_t best = 0;
-      for (uint32_t k = 1; k < heads[h]; ++k)
-        if (hz[o + k] > hz[o + best]) best = k;
-      double sum = 0.0;
-      for (uint32_t k = 0; k < heads[h]; ++k)
-        sum += std::exp((double)hz[o + k] - (double)hz[o + best]);
-      const double p = 1.0 / sum;
-      if (!(p >= 0.0)) conf = 0.0; /* NaN logits: untrusted */
-      conf = std::fmin(conf, p);
-      pick[h] = best;
-      o += heads[h];
-    }
+    conf = decide(hz, pick);
   }
   if (!supported || conf < min_confidence) {
     if (used_fallback) *used_fallback = 1;
     return qoz_tune(c, d_x, shape, e, fallback_target, cfg, out, s);
   }
-  qoz_params p;
-  std::memset(&p, 0, sizeof(p));
-  p.anchor_stride = sa;
-  p.levels = L;
-  for (uint32_t l = 0; l < L; ++l) {
-    p.interp[l] = (uint8_t)pick[0];
-    for (int j = 0; j < 3; ++j) p.order[l][j] = (uint8_t)(j < d ? j : 0);
-  }
-  p.alpha = kAlphaL[pick[1]];
-  p.beta = kBetaL[pick[2]];
-  *out = p;
+  *out = learned_params(pick, sa, L, d);
   if (used_fallback) *used_fallback = 0;
+  return QOZ_OK;
+}
+
+extern "C" qoz_status qoz_tune_learned_batch(
+    qoz_ctx* c, qoz_learned_item* items, uint32_t n, const float* d_params,
+    double min_confidence, qoz_target fallback_target,
+    const qoz_tune_config* cfg, hipStream_t s) {
+  clear_error();
+  if (!c || (n && !items) || !d_params)
+    return fail(QOZ_EINVAL, "NULL argument");
+  if (!aligned16(d_params))
+    return fail(QOZ_EINVAL, "d_params must be 16-byte aligned");
+  if (!(min_confidence >= 0.0 && min_confidence <= 1.0))
+    return fail(QOZ_EINVAL, "min_confidence must be in [0, 1]");
+  QOZ_TRY(set_device(c));
+  if (!n) return QOZ_OK;
+  if (!mlp_fit()) return fail(QOZ_EDEVICE, "network does not fit in LDS");
+  if (!block_features_fit())
+    return fail(QOZ_EDEVICE, "block features do not fit in LDS");
+  struct Job {
+    uint32_t item, nb;
+    int d;
+    uint64_t n[3];
+    uint32_t sa, L;
+    size_t org; /* first origin (in u32) */
+    size_t blk; /* first block */
+  };
+  std::vector<Job> jobs;
+  std::vector<uint32_t> fall; /* items for the online tuner */
+  std::vector<uint32_t> org_all;
+  size_t blocks = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    qoz_learned_item& it = items[i];
+    it.status = QOZ_OK;
+    it.used_fallback = 0;
+    Job j{};
+    j.item = i;
+    if (!it.d_x || !(it.abs_eb > 0.0) || !std::isfinite(it.abs_eb) ||
+        !shape_ok(it.shape, &j.d, j.n) ||
+        !stride_levels(it.params.anchor_stride, j.d, &j.sa, &j.L)) {
+      it.status = QOZ_EINVAL;
+      continue;
+    }
+    const bool sup =
+        j.d == 3 && j.n[0] >= 33 && j.n[1] >= 33 && j.n[2] >= 33;
+    if (!sup) {
+      fall.push_back(i);
+      continue;
+    }
+    std::vector<uint32_t> org;
+    QOZ_TRY(learned_origins(j.d, j.n, cfg, &org));
+    j.nb = (uint32_t)(org.size() / 3);
+    j.org = org_all.size();
+    j.blk = blocks;
+    org_all.insert(org_all.end(), org.begin(), org.end());
+    blocks += j.nb;
+    jobs.push_back(j);
+  }
+  const uint32_t m = (uint32_t)jobs.size();
+  if (m) {
+    /* device: origins, aux (3 per block), features (32 per block), means
+     * (32 per field), logits (11 per field), status (4 words per field) */
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t o_org = 0;
+    const size_t o_aux = al(o_org + 4 * org_all.size());
+    const size_t o_feat = al(o_aux + 4 * 3 * blocks);
+    const size_t o_mean = al(o_feat + 4 * (size_t)kMlpFeat * blocks);
+    const size_t o_logit = al(o_mean + 4 * (size_t)kMlpFeat * m);
+    const size_t o_st = al(o_logit + 4 * (size_t)kMlpOut * m);
+    QOZ_TRY(ensure(c->lbatch, o_st + 16 * (size_t)m));
+    uint8_t* D = (uint8_t*)c->lbatch.p;
+    const size_t pin_org = kPinSingleBytes;
+    const size_t pin_back = pin_org + (4 * org_all.size() + 255) / 256 * 256;
+    QOZ_TRY(ensure_pinned(c, pin_back + 4 * (size_t)kMlpOut * m + 16 * m));
+    uint8_t* hp = (uint8_t*)c->pinned;
+    std::memcpy(hp + pin_org, org_all.data(), 4 * org_all.size());
+    QOZ_TRY(to_device(c, D + o_org, hp + pin_org, 4 * org_all.size(), s));
+    for (uint32_t k = 0; k < m; ++k) {
+      const Job& j = jobs[k];
+      hipEvent_t ev = prof_begin(c, s, PK_LEARN_FEAT);
+      launch_block_features(items[j.item].d_x, make_geo(j.d, j.n),
+                            (const uint32_t*)(D + o_org) + j.org, j.nb,
+                            items[j.item].abs_eb,
+                            (float*)(D + o_feat) + (size_t)kMlpFeat * j.blk,
+                            (float*)(D + o_aux) + 3 * j.blk,
+                            (float*)(D + o_mean) + (size_t)kMlpFeat * k,
+                            (uint32_t*)(D + o_st) + 4 * k, s);
+      prof_end(c, s, ev, PK_LEARN_FEAT, 4.0 * 35937.0 * j.nb);
+    }
+    {
+      hipEvent_t ev = prof_begin(c, s, PK_MLP);
+      launch_mlp_forward(d_params, (const float*)(D + o_mean), m,
+                         (float*)(D + o_logit), s);
+      prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams + 4.0 * 43 * m);
+    }
+    float* hz = (float*)(hp + pin_back);
+    uint32_t* hs = (uint32_t*)(hz + (size_t)kMlpOut * m);
+    QOZ_TRY(to_host(c, hz, D + o_logit, 4 * (size_t)kMlpOut * m, s));
+    QOZ_TRY(to_host(c, hs, D + o_st, 16 * (size_t)m, s));
+    QOZ_HIP(hipGetLastError());
+    QOZ_HIP(hipStreamSynchronize(s));
+    prof_collect(c);
+    for (uint32_t k = 0; k < m; ++k) {
+      const Job& j = jobs[k];
+      qoz_learned_item& it = items[j.item];
+      if (hs[4 * k] & kStNonFinite) {
+        it.status = QOZ_EINVAL;
+        continue;
+      }
+      uint32_t pick[3];
+      if (decide(hz + (size_t)kMlpOut * k, pick) < min_confidence) {
+        fall.push_back(j.item);
+        continue;
+      }
+      it.params = learned_params(pick, j.sa, j.L, j.d);
+    }
+  }
+  /* the online tuner for the rest, in item order */
+  std::sort(fall.begin(), fall.end());
+  for (uint32_t i : fall) {
+    qoz_learned_item& it = items[i];
+    it.used_fallback = 1;
+    it.status = qoz_tune(c, it.d_x, it.shape, it.abs_eb, fallback_target, cfg,
+                         &it.params, s);
+  }
+  for (uint32_t i = 0; i < n; ++i)
+    if (items[i].status != QOZ_OK)
+      return fail(items[i].status, "a field of the batch failed");
   return QOZ_OK;
 }

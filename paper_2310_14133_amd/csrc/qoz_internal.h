@@ -214,7 +214,7 @@ struct qoz_ctx {
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
       hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp,
-      queue;
+      queue, lbatch;
   /* sweep launch tiles chosen by qoz_autotune_tiles, per plan signature */
   std::map<std::vector<uint32_t>, std::vector<qoz::SweepTile>> tiles_comp,
       tiles_decomp;

@@ -283,3 +283,55 @@ def test_trained_network_gain(codec):
               f"learned {tl:.3f} ms cr {cr_l:.4f} psnr {ps_l:.3f}", flush=True)
         assert te / tl >= 4.0, (te, tl)
         assert (32.0 / bits_eq) / cr_e >= 0.98
+
+
+def test_tune_learned_batch_equals_single_calls(codec):
+    import time
+    import torch
+    import paper_2310_14133_amd as q
+    from paper_2310_14133_amd import learned
+    P = learned.load_weights()
+    cfg = q.make_tune_config(block=32, sample_rate=0.05)
+    shapes = [(64, 70, 66), (40, 48, 56), (96, 64, 64), (33, 33, 33),
+              (20, 40, 40), (130, 129), (80, 72, 90), (128, 128, 128)]
+    xs, es = [], []
+    for i, sh in enumerate(shapes):
+        x = fields.grf(sh, 700 + i, log_normal=(i % 3 == 2))
+        es.append([1e-2, 1e-3, 1e-4][i % 3] * (float(x.max()) - float(x.min())))
+        xs.append(to_dev(x))
+    for conf in (0.0, 0.6):
+        items = codec.tune_learned_batch(xs, es, P, conf, "psnr", cfg)
+        n_fb = 0
+        for i, x in enumerate(xs):
+            p1, fb1 = codec.tune_learned(x, es[i], P, conf, "psnr", cfg)
+            it = items[i]
+            assert it.status == q.QOZ_OK, i
+            assert bool(it.used_fallback) == fb1, (i, conf)
+            assert q.params_dict(it.params, x.dim()) == \
+                q.params_dict(p1, x.dim()), (i, conf)
+            n_fb += fb1
+        print(f"learned batch, min confidence {conf}: {n_fb} of {len(xs)} "
+              "fields to the online tuner", flush=True)
+        assert n_fb >= 2  # the 2D field and the small 3D one
+    # a field with NaN in a sampled block fails alone
+    bad = xs[0].clone()
+    bad[0, 0, 0] = float("nan")
+    xs3 = [xs[1], bad, xs[2]]
+    es3 = [es[1], es[0], es[2]]
+    with pytest.raises(q.QozError) as err:
+        codec.tune_learned_batch(xs3, es3, P, 0.0, "psnr", cfg)
+    assert err.value.status == q.QOZ_EINVAL
+    # a batch of 16 supported fields against one call per field
+    big = [to_dev(fields.grf((128, 128, 128), 720 + i)) for i in range(16)]
+    eb = [1e-3 * float((b.max() - b.min()).item()) for b in big]
+    codec.tune_learned_batch(big, eb, P, 0.0, "psnr", cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    codec.tune_learned_batch(big, eb, P, 0.0, "psnr", cfg)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for b, e in zip(big, eb):
+        codec.tune_learned(b, e, P, 0.0, "psnr", cfg)
+    tl = time.perf_counter() - t0
+    print(f"learned tuning of 16 fields of 128^3: batch {tb * 1e3:.3f} ms, "
+          f"one call each {tl * 1e3:.3f} ms", flush=True)
