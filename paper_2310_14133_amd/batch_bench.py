@@ -8,7 +8,8 @@ family (one FFT size), value-range-relative bounds log-uniform in
 [1e-5, 1e-2].  Reports aggregate GB/s of input and p50 / p99 per-field
 latency for the loop and for batches of 4 and 8 workers, and the
 decompression of the whole batch through the device work queues (the
-batch calls write into preallocated fields).
+batch calls write into preallocated fields), and PSNR-mode tuning of the
+batch by the online tuner and by the batched learned tuner.
 
     python -m paper_2310_14133_amd.batch_bench --fields 64
 """
@@ -149,10 +150,50 @@ def main(argv=None):
          "outputs_equal_loop": same}
     res["queue_graph"] = r
     print("batch: queue, graph replays", json.dumps(r), flush=True)
+    res["tuning"] = tuning(codec, xs, ebs, total)
+    print("batch: tuning", json.dumps(res["tuning"]), flush=True)
     if args.report:
         with open(args.report, "w") as f:
             json.dump(res, f, indent=1)
     codec.close()
+
+
+def tuning(codec, xs, ebs, total):
+    """PSNR-mode tuning of the whole batch: the online tuner one field at a
+    time against the batched learned tuner (2D and small fields fall back
+    to the online tuner), and the ratio each one's parameters give."""
+    import torch
+    import paper_2310_14133_amd as q
+    from paper_2310_14133_amd import learned
+    P = learned.load_weights()
+    cfg = q.make_tune_config(block=32, sample_rate=learned.SAMPLE_RATE)
+
+    def online():
+        return [codec.tune(x, e, "psnr", cfg) for x, e in zip(xs, ebs)]
+
+    def batch():
+        its = codec.tune_learned_batch(xs, ebs, P, 0.5, "psnr", cfg)
+        return [it.params for it in its], sum(it.used_fallback for it in its)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3
+
+    po, to = timed(online)
+    (pl, n_fb), tl = timed(batch)
+
+    def stream_bytes(ps):
+        return sum(int(codec.compress(x, e, p).numel())
+                   for x, e, p in zip(xs, ebs, ps))
+
+    return {"online_ms": to, "learned_batch_ms": tl,
+            "learned_fallbacks": int(n_fb), "fields": len(xs),
+            "cr_online": total / stream_bytes(po),
+            "cr_learned": total / stream_bytes(pl)}
 
 
 if __name__ == "__main__":
