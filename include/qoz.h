@@ -227,7 +227,7 @@ qoz_status qoz_decompress_batch(qoz_ctx* ctx, qoz_batch_dec_item* items,
                                 uint32_t n, uint32_t workers,
                                 hipStream_t stream);
 
-/* Decompression of items[0..n) (at most 65536) on `stream` through device
+/* Decompression of items[0..n) (at most 16384) on `stream` through device
  * work queues, in a number of launches that does not grow with n: the
  * headers and codebooks of all streams are read back together, one launch
  * decodes every stream's Huffman chunks, and each round of inverse sweeps

@@ -37,7 +37,8 @@ namespace qoz {
 namespace {
 
 constexpr size_t kAl = 256;
-constexpr uint32_t kMaxQueueFields = 1u << 16;
+/* the host keeps each stream's decoding tables (about 18 KB) for the call */
+constexpr uint32_t kMaxQueueFields = 1u << 14;
 constexpr size_t kTableThreads = 16;
 
 inline size_t al(size_t v) { return (v + kAl - 1) / kAl * kAl; }
