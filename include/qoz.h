@@ -122,6 +122,46 @@ qoz_status qoz_tune(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
                     const qoz_tune_config* cfg, qoz_params* out,
                     hipStream_t stream);
 
+/* Record of one tuning, for checking the tuner's intermediate values
+ * (Algorithm 1 of Sec. VI-B; the (alpha, beta) walk of Sec. VI-C, Table I).
+ * alg1_err[l-1][c]: mean absolute prediction error of interpolator
+ * candidate c (interpolation type outer, dimension order inner) on level l
+ * of the sampled blocks at the uniform bound; alg1_choice[l-1]: the first
+ * strict minimum.  Under QOZ_ABLATE_LEVELWISE, alg1_err[0][c] is candidate
+ * c's trial bit rate over every level and every alg1_choice[l-1] (l <= Lt)
+ * the one chosen.  Pair i is (alpha, beta) = ({1, 1.25, 1.5, 1.75, 2}[i/4],
+ * {1.5, 2, 3, 4}[i%4]); B[i] its trial bit rate (Huffman bits of the bins
+ * aggregated over the blocks plus 32 per unpredictable value, per block
+ * point) and M[i] its metric (PSNR, SSIM, -|AC|; 0 for the ratio target)
+ * at bound e; where the walk re-ran pair i at e' = eprime[i] * e (Table I
+ * cases 3 and 4), Bp[i] and Mp[i] (else NaN, eprime 0); cmp_case[i] the
+ * Table-I case when pair i (i >= 1) challenged the incumbent; best_pair
+ * the pair chosen.  Under QOZ_ABLATE_AB no pair is tried and the pair
+ * fields stay 0. */
+#define QOZ_MAX_CAND 12
+#define QOZ_NPAIRS 20
+typedef struct {
+  uint32_t Lt;           /* levels covered by the sampled blocks */
+  uint32_t ncand;        /* interpolator candidates per level */
+  uint64_t nblocks;      /* sampled blocks */
+  uint64_t block_points; /* points in all sampled blocks */
+  double alg1_err[QOZ_MAX_LEVELS][QOZ_MAX_CAND];
+  uint32_t alg1_choice[QOZ_MAX_LEVELS];
+  double B[QOZ_NPAIRS], M[QOZ_NPAIRS];
+  double Bp[QOZ_NPAIRS], Mp[QOZ_NPAIRS];
+  double eprime[QOZ_NPAIRS];
+  int32_t cmp_case[QOZ_NPAIRS];
+  uint32_t best_pair;
+} qoz_tune_trace;
+
+/* qoz_tune that also fills *trace (not NULL).  Same decisions and errors
+ * as qoz_tune; the per-level error sums of Algorithm 1 are read back, one
+ * small copy per level. */
+qoz_status qoz_tune_traced(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
+                           double abs_eb, qoz_target target,
+                           const qoz_tune_config* cfg, qoz_params* out,
+                           qoz_tune_trace* trace, hipStream_t stream);
+
 /* Compression Z = C_theta(X) (Sec. III) into d_out[0..cap).  params == NULL
  * runs qoz_tune(target, cfg) first.  On QOZ_OK *out_bytes is the stream
  * size; on QOZ_ENOSPACE it is the size needed.  The stream is

@@ -42,6 +42,20 @@ class TuneConfig(C.Structure):
                 ("ssim_window", C.c_uint32), ("ablation", C.c_uint32)]
 
 
+MAX_CAND, NPAIRS = 12, 20
+
+
+class TuneTrace(C.Structure):
+    _fields_ = [("Lt", C.c_uint32), ("ncand", C.c_uint32),
+                ("nblocks", C.c_uint64), ("block_points", C.c_uint64),
+                ("alg1_err", (C.c_double * MAX_CAND) * MAX_LEVELS),
+                ("alg1_choice", C.c_uint32 * MAX_LEVELS),
+                ("B", C.c_double * NPAIRS), ("M", C.c_double * NPAIRS),
+                ("Bp", C.c_double * NPAIRS), ("Mp", C.c_double * NPAIRS),
+                ("eprime", C.c_double * NPAIRS),
+                ("cmp_case", C.c_int32 * NPAIRS), ("best_pair", C.c_uint32)]
+
+
 class BatchItem(C.Structure):
     _fields_ = [("d_x", C.c_void_p), ("shape", Shape), ("abs_eb", C.c_double),
                 ("params", C.c_void_p), ("d_out", C.c_void_p),
@@ -90,6 +104,10 @@ def lib():
         L.qoz_compress_bound.argtypes = [Shape, C.POINTER(sz)]
         L.qoz_tune.argtypes = [vp, vp, Shape, dbl, C.c_int,
                                C.POINTER(TuneConfig), C.POINTER(Params), vp]
+        L.qoz_tune_traced.argtypes = [vp, vp, Shape, dbl, C.c_int,
+                                      C.POINTER(TuneConfig),
+                                      C.POINTER(Params),
+                                      C.POINTER(TuneTrace), vp]
         L.qoz_compress.argtypes = [vp, vp, Shape, dbl, C.POINTER(Params),
                                    C.c_int, C.POINTER(TuneConfig), vp, sz,
                                    C.POINTER(sz), vp]
@@ -129,6 +147,7 @@ def lib():
         L.qoz_ctx_get_timing.argtypes = [vp, C.c_int, C.POINTER(u64),
                                          C.POINTER(dbl), C.POINTER(dbl)]
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
+                   "qoz_tune_traced",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
                    "qoz_metrics", "qoz_error_ac", "qoz_autotune_tiles",
                    "qoz_compress_batch",
@@ -232,6 +251,17 @@ def qoz_tune(ctx, d_x, shape, abs_eb, target, cfg, params, stream):
                           int(target), C.byref(cfg) if cfg else None,
                           C.byref(params), C.c_void_p(stream)), "qoz_tune")
     return params
+
+
+def qoz_tune_traced(ctx, d_x, shape, abs_eb, target, cfg, params, trace,
+                    stream):
+    """As qoz_tune; also fills the TuneTrace `trace`."""
+    _check(lib().qoz_tune_traced(ctx, C.c_void_p(d_x), shape,
+                                 C.c_double(abs_eb), int(target),
+                                 C.byref(cfg) if cfg else None,
+                                 C.byref(params), C.byref(trace),
+                                 C.c_void_p(stream)), "qoz_tune_traced")
+    return params, trace
 
 
 def qoz_compress(ctx, d_x, shape, abs_eb, params, target, cfg, d_out, cap,
@@ -477,6 +507,15 @@ class Codec:
         p.anchor_stride = anchor_stride
         return qoz_tune(self.ctx, x.data_ptr(), sh, abs_eb, TARGETS[target],
                         cfg, p, self._stream())
+
+    def tune_traced(self, x, abs_eb, target="cr", cfg=None, anchor_stride=0):
+        """(params, TuneTrace) of one tuning."""
+        sh = self._field(x)
+        p = Params()
+        p.anchor_stride = anchor_stride
+        return qoz_tune_traced(self.ctx, x.data_ptr(), sh, abs_eb,
+                               TARGETS[target], cfg, p, TuneTrace(),
+                               self._stream())
 
     def compress(self, x, abs_eb, params=None, target="cr", cfg=None):
         sh = self._field(x)

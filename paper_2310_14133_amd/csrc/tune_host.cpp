@@ -123,10 +123,10 @@ static qoz_status overflow_bits(qoz_ctx* c, const std::vector<uint32_t>& over,
 
 using namespace qoz;
 
-extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
-                               double e, qoz_target target,
-                               const qoz_tune_config* cfg, qoz_params* out,
-                               hipStream_t s) {
+static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
+                            double e, qoz_target target,
+                            const qoz_tune_config* cfg, qoz_params* out,
+                            qoz_tune_trace* tr, hipStream_t s) {
   clear_error();
   if (!c || !d_x || !out) return fail(QOZ_EINVAL, "NULL argument");
   if (target < QOZ_TARGET_CR || target > QOZ_TARGET_AC)
@@ -218,6 +218,13 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
       }
   }
   const uint32_t ncand = (uint32_t)cands.size();
+  if (tr) {
+    std::memset(tr, 0, sizeof(*tr));
+    tr->Lt = Lt;
+    tr->ncand = ncand;
+    tr->nblocks = bg.nb;
+    tr->block_points = (uint64_t)bg.nb * bg.size;
+  }
   const uint32_t shift = d == 2 ? 1 : 0;
   const uint32_t max_trials = 60;
   const uint32_t nslots = std::max(ncand, max_trials);
@@ -260,13 +267,16 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                           24 * (size_t)nslots * bg.nb +
                           8 * (size_t)nslots * bg.nb + 8 * ssim_np +
                           sizeof(TrialDesc) * (nslots + adesc_n) + 8 * rp +
-                          12 * (size_t)bg.nb + 4096;
+                          12 * (size_t)bg.nb + 4096 +
+                          (tr ? 8 * (size_t)QOZ_MAX_LEVELS * ncand * bg.nb
+                              : 0);
   QOZ_TRY(ensure_pinned(c, pin_need));
   uint8_t* pbase;
   uint32_t *h_hist, *h_un, *h_status;
   double *h_sse, *h_l1, *h_ssim;
   TrialDesc *h_desc, *h_adesc;
   float* h_range;
+  double* h_tl1; /* traced runs: Algorithm 1's per-block sums, per level */
   /* regions of the pinned staging (again after anything that may move it) */
   auto bind_pinned = [&]() {
     pbase = (uint8_t*)c->pinned + kPinTune;
@@ -281,6 +291,10 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     h_adesc = h_desc + nslots;
     h_range = (float*)(h_adesc + adesc_n);
     h_status = (uint32_t*)(h_range + 2 * rp);
+    h_tl1 = (double*)(((uintptr_t)(h_status + 8 + 3 * (size_t)bg.nb +
+                                   QOZ_MAX_LEVELS) +
+                       7) &
+                      ~(uintptr_t)7);
   };
   bind_pinned();
 
@@ -386,6 +400,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     uint32_t ib = 0;
     for (uint32_t ci = 0; ci < ncand; ++ci) {
       const double Bc = ((double)cbits[ci] + 32.0 * (double)cU[ci]) / npts;
+      if (tr) tr->alg1_err[0][ci] = Bc;
       if (Bc < best) {
         best = Bc;
         ib = ci;
@@ -394,6 +409,7 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     for (uint32_t l = 0; l < QOZ_MAX_LEVELS; ++l) {
       Is_interp[l] = cands[ib].interp;
       std::memcpy(Is_order[l], cands[ib].order, 3);
+      if (tr && l < Lt) tr->alg1_choice[l] = ib;
     }
   }
   if (!(abl & QOZ_ABLATE_LEVELWISE)) {
@@ -421,6 +437,9 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
                           dl1, in_lds, s);
         prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
       }
+      if (tr)
+        QOZ_TRY(to_host(c, h_tl1 + (size_t)(l - 1) * ncand * bg.nb, dl1,
+                        8 * (size_t)ncand * bg.nb, s));
       /* level-l targets: points of the 2^(l-1) grid off the 2^l grid */
       uint64_t on_fine = 1, on_coarse = 1;
       for (int i = 0; i < 3; ++i) {
@@ -438,6 +457,23 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     for (uint32_t l = Lt; l >= 1; --l) {
       const uint32_t ib = h_pick[l - 1];
       if (ib >= ncand) return fail(QOZ_EDEVICE, "bad tuner choice");
+      if (tr) {
+        /* each candidate's mean as the device forms it: block sums in
+         * block order over the level's target count */
+        uint64_t on_fine = 1, on_coarse = 1;
+        for (int i = 0; i < 3; ++i) {
+          on_fine *= (bg.g.n[i] - 1) / (1u << (l - 1)) + 1;
+          on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
+        }
+        const double count = (double)(on_fine - on_coarse) * bg.nb;
+        const double* lp = h_tl1 + (size_t)(l - 1) * ncand * bg.nb;
+        for (uint32_t ci = 0; ci < ncand; ++ci) {
+          double sum = 0.0;
+          for (uint32_t k = 0; k < bg.nb; ++k) sum += lp[(size_t)ci * bg.nb + k];
+          tr->alg1_err[l - 1][ci] = count > 0 ? sum / count : 0.0;
+        }
+        tr->alg1_choice[l - 1] = ib;
+      }
       Is_interp[l - 1] = cands[ib].interp;
       std::memcpy(Is_order[l - 1], cands[ib].order, 3);
     }
@@ -572,19 +608,32 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
     for (uint32_t t = 0; t < ntrial; ++t)
       B[t] = ((double)bits[t] + 32.0 * (double)Us[t]) / npts;
 
+    if (tr)
+      for (int i = 0; i < 20; ++i) {
+        tr->B[i] = B[trial_of[0][i]];
+        tr->M[i] = M[trial_of[0][i]];
+        tr->Bp[i] = tr->Mp[i] = std::numeric_limits<double>::quiet_NaN();
+      }
     for (int i = 1; i < 20; ++i) {
       const int tI = trial_of[0][inc], tII = trial_of[0][i];
       const int cs = table1_case(B[tI], M[tI], B[tII], M[tII]);
+      if (tr) tr->cmp_case[i] = cs;
       if (cs == 1) continue;
       if (cs == 2) {
         inc = i;
         continue;
       }
       const int tp = trial_of[cs == 3 ? 1 : 2][i];
+      if (tr) {
+        tr->Bp[i] = B[tp];
+        tr->Mp[i] = M[tp];
+        tr->eprime[i] = factors[cs == 3 ? 1 : 2];
+      }
       if (table1_line_prefers_II(B[tI], M[tI], B[tII], M[tII], B[tp], M[tp]))
         inc = i;
     }
   }
+  if (tr) tr->best_pair = (uint32_t)inc;
 
   prof_collect(c);
   qoz_params p;
@@ -599,4 +648,21 @@ extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
   p.beta = kBeta[inc % 4];
   *out = p;
   return QOZ_OK;
+}
+
+extern "C" qoz_status qoz_tune(qoz_ctx* c, const float* d_x, qoz_shape shape,
+                               double e, qoz_target target,
+                               const qoz_tune_config* cfg, qoz_params* out,
+                               hipStream_t s) {
+  return tune_impl(c, d_x, shape, e, target, cfg, out, nullptr, s);
+}
+
+extern "C" qoz_status qoz_tune_traced(qoz_ctx* c, const float* d_x,
+                                      qoz_shape shape, double e,
+                                      qoz_target target,
+                                      const qoz_tune_config* cfg,
+                                      qoz_params* out, qoz_tune_trace* trace,
+                                      hipStream_t s) {
+  if (!trace) return fail(QOZ_EINVAL, "trace is NULL");
+  return tune_impl(c, d_x, shape, e, target, cfg, out, trace, s);
 }

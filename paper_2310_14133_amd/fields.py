@@ -148,6 +148,34 @@ def multiscale(shape, seed, n_bumps=16, dtype=np.float32):
     return np.ascontiguousarray(base.astype(dtype))
 
 
+def multiscale_torch(shape, seed, n_bumps=16, device="cuda"):
+    """Same recipe as multiscale() computed with torch on `device` (fast at
+    the paper's shapes, e.g. 1008x1008x352): the k^-3 field of grf_torch
+    (standardised) plus n_bumps Gaussian bumps, centres uniform in the box,
+    widths U[0.02, 0.1] * min(shape), amplitudes N(0,1), drawn from
+    `seed`.  Its bytes differ from multiscale()'s; whatever it returns is
+    handed unchanged to every consumer."""
+    import torch
+    g = grf_torch(shape, seed, slope=-3.0, device=device)
+    rng = np.random.default_rng(seed + 7919)
+    m = min(shape)
+    axes = [torch.arange(n, device=device, dtype=torch.float32)
+            for n in shape]
+    for _ in range(n_bumps):
+        c = [rng.uniform(0, n) for n in shape]
+        w = rng.uniform(0.02, 0.1) * m
+        a = float(rng.normal())
+        bump = None
+        for i, (ax, ci) in enumerate(zip(axes, c)):
+            t = torch.exp(-((ax - ci) ** 2) / (2.0 * w * w))
+            view = [1] * len(shape)
+            view[i] = shape[i]
+            t = t.view(view)
+            bump = t if bump is None else bump * t
+        g += a * bump
+    return g.contiguous()
+
+
 def polynomial(shape, degree, seed=0, max_coef=3, dtype=np.float32):
     """Integer-coefficient polynomial of total degree <= `degree` in the
     grid coordinates; values are integers (exact in FP32 for small fields)."""

@@ -1,15 +1,22 @@
 """GPU parity at the benchmark's full size: a 512^3 float32 k^-3 Gaussian
-random field, value-range-relative bound, tuner with 32^3 blocks at 1% and
-all dimension orders (ratio target), in the launch configuration bench.py
-times.  The oracle runs the whole field (about 15 s of CPU)."""
+random field (and its exp transform), value-range-relative bounds 1e-2,
+1e-3 and 1e-4, tuner with 32^3 blocks at 1% and all dimension orders (ratio
+target), in the launch configuration bench.py times; at 1e-3 also PSNR and
+SSIM of the reconstruction.  The oracle runs the whole field (about 15 s of
+CPU per case)."""
 import numpy as np
 import pytest
+
+from parity_helpers import check_trace
 
 pytestmark = pytest.mark.gpu
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("seed,log_normal,eps", [(20, False, 1e-3),
-                                                 (21, True, 1e-2)])
+                                                 (21, True, 1e-2),
+                                                 (22, False, 1e-2),
+                                                 (24, False, 1e-4)])
 def test_512_cube_tuned_bitexact(ref, seed, log_normal, eps):
     import torch
 
@@ -24,9 +31,11 @@ def test_512_cube_tuned_bitexact(ref, seed, log_normal, eps):
     e = eps * (float(xh.max()) - float(xh.min()))
     codec = q.Codec(0)
     try:
-        gp = codec.tune(x, e, "cr", q.make_tune_config(32, 0, 0.01, 1))
+        gp, gt = codec.tune_traced(x, e, "cr",
+                                   q.make_tune_config(32, 0, 0.01, 1))
         rp, tr = ref.tune(xh, e, "cr", ref.tune_config(32, 0, 0.01, 1))
         assert tr.nblocks == 64
+        assert check_trace(gt, tr, "cr") is None
         for l in range(rp.levels):
             assert gp.interp[l] == rp.interp[l], l
             assert tuple(gp.order[l]) == tuple(rp.order[l]), l
@@ -39,5 +48,12 @@ def test_512_cube_tuned_bitexact(ref, seed, log_normal, eps):
         yr = ref.decompress(zr)
         assert np.array_equal(y.cpu().numpy(), yr)
         assert np.abs(xh.astype(np.float64) - yr).max() <= e
+        if seed == 20:
+            # PSNR and SSIM (Eq. 1-3) of the reconstruction at full size
+            ps, ss, me = codec.metrics(x, y)
+            pr, sr, mr = ref.metrics(xh, yr)
+            assert abs(ps - pr) <= 1e-9 * abs(pr), (ps, pr)
+            assert abs(ss - sr) <= 1e-9 * abs(sr), (ss, sr)
+            assert me == mr
     finally:
         codec.close()
