@@ -101,13 +101,26 @@ typedef struct {
 
 typedef struct qoz_ctx qoz_ctx;
 
-/* Create a context on HIP device `hip_device`.  Errors: EINVAL (bad
- * device), EDEVICE. */
+/* Context of the compressor C, decompressor D and tuner of Sec. III: the
+ * device scratch that their steps (the level sweeps of Sec. V-B, the
+ * Huffman stage of Sec. VI-A, the sampled-block trials of Sec. VI) reuse
+ * from call to call, grown on first use and freed by qoz_ctx_destroy.  The
+ * paper's single-core compressor has no counterpart; the context only
+ * holds memory and never changes a result.  Create one on HIP device
+ * `hip_device`; *out receives it.  Errors: EINVAL (NULL out, bad device),
+ * EDEVICE, ENOMEM.  qoz_ctx_destroy(NULL) does nothing; destroying frees
+ * every allocation of the context (and its batch workers). */
 qoz_status qoz_ctx_create(int hip_device, qoz_ctx** out);
 void qoz_ctx_destroy(qoz_ctx* ctx);
 
-/* Worst-case size in bytes of a compressed stream of this shape (any
- * parameters).  Errors: EINVAL. */
+/* Worst-case size in bytes of a compressed stream Z (Sec. III) of this
+ * shape, for any parameters and bound: the fixed header, the anchor grid
+ * of Sec. V-B stored raw, the largest codebook of the bins, the per-chunk
+ * tables, a Huffman payload (Sec. VI-A) of at most 16 bits per bin (an
+ * optimal prefix code is never longer in total than the fixed 16-bit
+ * code of the 65536 bins) plus one word of padding per chunk, and every
+ * non-anchor value unpredictable (raw float32).  *bytes receives it.
+ * Errors: EINVAL (bad shape, NULL bytes). */
 qoz_status qoz_compress_bound(qoz_shape shape, size_t* bytes);
 
 /* Online tuning (Sec. VI): sample blocks of d_x, choose per-level
@@ -181,8 +194,12 @@ qoz_status qoz_decompress(qoz_ctx* ctx, const void* d_in, size_t in_bytes,
                           float* d_y, size_t y_cap_elems,
                           qoz_shape* out_shape, hipStream_t stream);
 
-/* Parse a stream header held in host memory.  Any output may be NULL.
- * Errors: EFORMAT. */
+/* Read the self-describing header of a stream Z held in host memory: the
+ * field's shape, the absolute bound e and the parameter set theta of
+ * Sec. III (anchor stride and levels, per-level interpolation type and
+ * dimension order of Sec. V-B, alpha and beta of Eq. 5).  h_in[0..in_bytes)
+ * is only read.  Any output may be NULL.  Errors: EFORMAT (too short, bad
+ * magic or version, inconsistent counts). */
 qoz_status qoz_inspect(const void* h_in, size_t in_bytes, qoz_shape* shape,
                        double* abs_eb, qoz_params* params);
 
@@ -403,7 +420,10 @@ qoz_status qoz_tune_learned_batch(qoz_ctx* ctx, qoz_learned_item* items,
                                   const qoz_tune_config* cfg,
                                   hipStream_t stream);
 
-/* Message describing the calling thread's last error ("" if none). */
+/* Message describing the calling thread's last failed call ("" if none);
+ * the text is owned by the library and stays valid until the thread's next
+ * call into it.  It states which check of the entry point failed (a bound
+ * of Sec. III, a shape rule, a stream check, a HIP error). */
 const char* qoz_last_error(void);
 
 /* ---- instrumentation ----------------------------------------------------

@@ -538,7 +538,9 @@ qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
     j.c1 = (0.01 * vrange) * (0.01 * vrange);
     j.c2 = (0.03 * vrange) * (0.03 * vrange);
     double* parts = (double*)c->ssim_part.p;
-    PROF(PK_SSIM, 8.0 * N, launch_ssim(j, d_x, d_y, parts, s));
+    bool launched = false;
+    PROF(PK_SSIM, 8.0 * N, launched = launch_ssim(j, d_x, d_y, parts, s));
+    if (!launched) return fail(QOZ_EDEVICE, "SSIM window ring does not fit LDS");
     QOZ_TRY(to_host(c, pin(c, kPinSmall), parts, 8 * qp, s));
     QOZ_TRY(sync_checked(s));
     const double* hp = (const double*)pin(c, kPinSmall);

@@ -15,10 +15,14 @@
  * (row, column) plane and streams through a range of planes, keeping the
  * last w planes of 2D window sums in an LDS ring.
  */
+#include <mutex>
+
 #include "qoz_device.h"
 #include "qoz_internal.h"
 
 namespace qoz {
+
+constexpr int kSsimLdsMax = 150 * 1024; /* largest dynamic LDS of k_ssim */
 
 constexpr uint32_t kRedThreads = 256;
 
@@ -366,18 +370,31 @@ __global__ __launch_bounds__(kSsThreads) void k_ssim(
   }
 }
 
-void launch_ssim(const SsimJob& j, const float* x, const float* y,
+/* The SSIM ring needs more dynamic LDS than the default limit.  The
+ * attribute is set once per device under a per-device once-flag (batch
+ * workers launch this from several threads) and its status is kept. */
+bool launch_ssim(const SsimJob& j, const float* x, const float* y,
                  double* parts, hipStream_t s) {
-  static bool attr_set = false;
-  size_t lds = ssim_lds(j);
-  if (!attr_set) {
-    (void)hipFuncSetAttribute((const void*)k_ssim,
-                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                              150 * 1024);
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_ssim, ssim_grid(j), dim3(kSsThreads), lds, s, j, x, y,
-                     parts);
+  constexpr int kMaxDev = 64;
+  static std::once_flag once[kMaxDev];
+  static bool ok[kMaxDev];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev)
+    return false;
+  std::call_once(once[dev], [dev] {
+    int max_lds = 0;
+    ok[dev] = hipDeviceGetAttribute(&max_lds,
+                                    hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                    dev) == hipSuccess &&
+              max_lds >= kSsimLdsMax &&
+              hipFuncSetAttribute((const void*)k_ssim,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kSsimLdsMax) == hipSuccess;
+  });
+  if (!ok[dev] || ssim_lds(j) > (size_t)kSsimLdsMax) return false;
+  hipLaunchKernelGGL(k_ssim, ssim_grid(j), dim3(kSsThreads), ssim_lds(j), s,
+                     j, x, y, parts);
+  return true;
 }
 
 }  // namespace qoz

@@ -524,7 +524,8 @@ struct SsimJob {
   double c1, c2;
 };
 uint64_t ssim_parts(const SsimJob& j);
-void launch_ssim(const SsimJob& j, const float* x, const float* y,
+/* false when the device cannot give the window ring its LDS */
+bool launch_ssim(const SsimJob& j, const float* x, const float* y,
                  double* parts, hipStream_t s);
 
 /* tuner kernels (kernels_tune.hip) */

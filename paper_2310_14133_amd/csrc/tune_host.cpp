@@ -539,8 +539,11 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
       sj.c2 = (0.03 * vrange) * (0.03 * vrange);
       ssim_np = ssim_parts(sj);
       hipEvent_t ev = prof_begin(c, s, PK_SSIM);
-      launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
+      const bool launched =
+          launch_ssim(sj, xs, wt, (double*)c->ssim_part.p, s);
       prof_end(c, s, ev, PK_SSIM, 8.0 * bsz * ntrial);
+      if (!launched)
+        return fail(QOZ_EDEVICE, "SSIM window ring does not fit LDS");
       QOZ_TRY(to_host(c, h_ssim, c->ssim_part.p, 8 * ssim_np, s));
     } else if (target == QOZ_TARGET_AC) {
       double* p0 = (double*)c->ssim_part.p;
