@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqoz_ref.so")
+# QOZ_REF_LIB selects another build of the same sources (the sanitizer
+# build of build.py)
+LIB_PATH = os.environ.get("QOZ_REF_LIB") or os.path.join(HERE, "libqoz_ref.so")
 
 OK, EINVAL, ENOSPACE, EFORMAT = 0, 1, 2, 3
 TARGETS = {"cr": 0, "psnr": 1, "ssim": 2, "ac": 3}

@@ -394,10 +394,10 @@ extern "C" int qref_predict_quantize(const float* x, qref_shape shape,
   sink.codes = &cd;
   sink.unpred = &un;
   compress_levels(x, g, L, 1, plan, lb, W.data(), &sink);
-  if (codes) std::memcpy(codes, cd.data(), cd.size() * sizeof(int32_t));
-  if (recon) std::memcpy(recon, W.data(), W.size() * sizeof(float));
-  if (unpred) std::memcpy(unpred, un.data(), un.size() * sizeof(float));
-  if (anchors) std::memcpy(anchors, anc.data(), anc.size() * sizeof(float));
+  if (codes) copy_bytes(codes, cd.data(), cd.size() * sizeof(int32_t));
+  if (recon) copy_bytes(recon, W.data(), W.size() * sizeof(float));
+  if (unpred) copy_bytes(unpred, un.data(), un.size() * sizeof(float));
+  if (anchors) copy_bytes(anchors, anc.data(), anc.size() * sizeof(float));
   *n_codes = cd.size();
   *n_unpred = un.size();
   *n_anchor = anc.size();
@@ -466,9 +466,9 @@ extern "C" int qref_target_trace(const float* x, qref_shape shape, double e,
   sink.preds = &pr;
   sink.codes = &cd;
   compress_levels(x, g, L, 1, plan, lb, W.data(), &sink);
-  if (idx) std::memcpy(idx, ti.data(), ti.size() * sizeof(uint32_t));
-  if (pred) std::memcpy(pred, pr.data(), pr.size() * sizeof(float));
-  if (codes) std::memcpy(codes, cd.data(), cd.size() * sizeof(int32_t));
+  if (idx) copy_bytes(idx, ti.data(), ti.size() * sizeof(uint32_t));
+  if (pred) copy_bytes(pred, pr.data(), pr.size() * sizeof(float));
+  if (codes) copy_bytes(codes, cd.data(), cd.size() * sizeof(int32_t));
   *n_codes = ti.size();
   return QREF_OK;
 }

@@ -5,11 +5,18 @@
 #ifndef QOZ_REF_INTERNAL_H
 #define QOZ_REF_INTERNAL_H
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "qoz_ref.h"
 
 namespace qref {
+
+/* memcpy that accepts an empty range (an empty vector's data() may be
+ * null, which memcpy does not allow even for zero bytes) */
+inline void copy_bytes(void* dst, const void* src, size_t n) {
+  if (n) std::memcpy(dst, src, n);
+}
 
 /* A d-dimensional row-major grid (dims[0] slowest). */
 struct Grid {

@@ -313,7 +313,7 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   put<uint64_t>(o, 184, R.start[R.n - 1]); /* bins before level 1 */
   put<uint32_t>(o, 192, 1024);            /* smallest chunk size */
   put<uint32_t>(o, 196, (uint32_t)c.n_packed);
-  std::memcpy(o + lay.anchors, anchors.data(), 4 * n_anchor);
+  copy_bytes(o + lay.anchors, anchors.data(), 4 * n_anchor);
   uint64_t k = 0;
   for (uint32_t s = 0; s < nsym; ++s)
     if (len[s]) {
@@ -327,13 +327,13 @@ extern "C" int qref_compress(const float* x, qref_shape shape, double e,
   }
   for (size_t k = 0; k < segs.size(); ++k)
     put<uint16_t>(o, lay.segs + 2 * k, segs[k]);
-  std::memcpy(o + lay.unpred, unpred.data(), 4 * n_unpred);
+  copy_bytes(o + lay.unpred, unpred.data(), 4 * n_unpred);
   if (packed) {
-    std::memcpy(o + lay.payload, pwords.data(), 4 * c.n_packed);
+    copy_bytes(o + lay.payload, pwords.data(), 4 * c.n_packed);
     for (uint64_t ch = 0; ch <= c.n_chunks; ++ch)
       put<uint64_t>(o, lay.pcoff + 8 * ch, pcoff[ch]);
   } else {
-    std::memcpy(o + lay.payload, words.data(), 4 * c.n_words);
+    copy_bytes(o + lay.payload, words.data(), 4 * c.n_words);
   }
   *out_bytes = lay.total;
   return QREF_OK;
@@ -473,7 +473,7 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
   /* the raw payload: as stored, or expanded from its zero-word packing */
   std::vector<uint32_t> raw((size_t)c.n_words, 0);
   if (!c.n_packed) {
-    std::memcpy(raw.data(), in + lay.payload, 4 * c.n_words);
+    copy_bytes(raw.data(), in + lay.payload, 4 * c.n_words);
   } else {
     uint64_t prev_p = 0;
     for (uint64_t ch = 0; ch <= c.n_chunks; ++ch) {
@@ -492,7 +492,7 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
       if (np > n) return QREF_EFORMAT;
       const size_t pw = lay.payload + 4 * p0;
       if (np == n) {
-        std::memcpy(raw.data() + w0, in + pw, 4 * n);
+        copy_bytes(raw.data() + w0, in + pw, 4 * n);
         continue;
       }
       const uint64_t nbm = (n + 31) / 32;
@@ -566,8 +566,8 @@ extern "C" int qref_decompress(const void* in_v, size_t in_bytes, float* y,
     return QREF_EFORMAT;
 
   std::vector<float> anchors(c.n_anchor), unpred(c.n_unpred);
-  std::memcpy(anchors.data(), in + lay.anchors, 4 * c.n_anchor);
-  std::memcpy(unpred.data(), in + lay.unpred, 4 * c.n_unpred);
+  copy_bytes(anchors.data(), in + lay.anchors, 4 * c.n_anchor);
+  copy_bytes(unpred.data(), in + lay.unpred, 4 * c.n_unpred);
   qref_shape sh;
   std::memset(&sh, 0, sizeof(sh));
   sh.ndim = (uint32_t)P.g.d;
