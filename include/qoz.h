@@ -212,6 +212,27 @@ qoz_status qoz_metrics(qoz_ctx* ctx, const float* d_x, const float* d_y,
                        qoz_shape shape, uint32_t ssim_window, double* psnr,
                        double* ssim, double* max_abs_err, hipStream_t stream);
 
+/* qoz_metrics for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same
+ * arguments and results, bit for bit, but no device or host allocation.
+ * Its device scratch is one fixed array of 4 MiB per device, held from
+ * the library's load until the process ends, whose address qoz_ctx_create
+ * looks up; the host side uses the context's pinned staging buffer, which
+ * qoz_ctx_create allocated.  The SSIM pass needs one partial sum per 64 x 4
+ * window origins of a row plane per slab of 32 planes; a shape needing
+ * more than (4 MiB - 64 KiB) / 8 = 516096 of them (3D fields up to about
+ * 4e9 points fit, e.g. 1600^3; 2D fields up to about 1.3e8 points) is
+ * rejected with EINVAL before any launch.  Every call on one device shares
+ * the array and it keeps the last call's contents (each call initialises
+ * what it reads): calls that overlap on one device (on any stream, from
+ * any context) race, so callers serialise them.
+ * Errors: EINVAL, EDEVICE. */
+qoz_status qoz_metrics_noalloc(qoz_ctx* ctx, const float* d_x,
+                               const float* d_y, qoz_shape shape,
+                               uint32_t ssim_window, double* psnr,
+                               double* ssim, double* max_abs_err,
+                               hipStream_t stream);
+
 /* Lag-1 autocorrelation of the errors e = d_x - d_y (Eq. 4) along the
  * fastest (last) dimension: the mean and population variance of e over all
  * points, the lagged moment over every pair of neighbours in a row; 0 when

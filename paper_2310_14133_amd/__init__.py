@@ -116,6 +116,9 @@ def lib():
                                   C.POINTER(dbl), C.POINTER(Params)]
         L.qoz_metrics.argtypes = [vp, vp, vp, Shape, u32, C.POINTER(dbl),
                                   C.POINTER(dbl), C.POINTER(dbl), vp]
+        L.qoz_metrics_noalloc.argtypes = [vp, vp, vp, Shape, u32,
+                                          C.POINTER(dbl), C.POINTER(dbl),
+                                          C.POINTER(dbl), vp]
         L.qoz_error_ac.argtypes = [vp, vp, vp, Shape, C.POINTER(dbl), vp]
         L.qoz_autotune_tiles.argtypes = [vp, Shape, C.POINTER(Params),
                                          C.POINTER(u32),
@@ -149,7 +152,8 @@ def lib():
         for fn in ("qoz_ctx_create", "qoz_compress_bound", "qoz_tune",
                    "qoz_tune_traced",
                    "qoz_compress", "qoz_decompress", "qoz_inspect",
-                   "qoz_metrics", "qoz_error_ac", "qoz_autotune_tiles",
+                   "qoz_metrics", "qoz_metrics_noalloc", "qoz_error_ac",
+                   "qoz_autotune_tiles",
                    "qoz_compress_batch",
                    "qoz_decompress_batch", "qoz_decompress_queue",
                    "qoz_ctx_set_queue_graphs", "qoz_tune_learned_batch",
@@ -309,6 +313,18 @@ def qoz_metrics(ctx, d_x, d_y, shape, ssim_window, stream, want_ssim=True):
                              C.c_uint32(ssim_window), C.byref(ps),
                              C.byref(ss) if want_ssim else None, C.byref(me),
                              C.c_void_p(stream)), "qoz_metrics")
+    return ps.value, (ss.value if want_ssim else None), me.value
+
+
+def qoz_metrics_noalloc(ctx, d_x, d_y, shape, ssim_window, stream,
+                        want_ssim=True):
+    ps, ss, me = C.c_double(), C.c_double(), C.c_double()
+    _check(lib().qoz_metrics_noalloc(ctx, C.c_void_p(d_x), C.c_void_p(d_y),
+                                     shape, C.c_uint32(ssim_window),
+                                     C.byref(ps),
+                                     C.byref(ss) if want_ssim else None,
+                                     C.byref(me), C.c_void_p(stream)),
+           "qoz_metrics_noalloc")
     return ps.value, (ss.value if want_ssim else None), me.value
 
 

@@ -471,48 +471,53 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   return QOZ_OK;
 }
 
-qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
-                       qoz_shape shape, uint32_t ssim_window, double* psnr,
-                       double* ssim, double* max_abs_err, hipStream_t s) {
-  clear_error();
-  if (!c || !d_x || !d_y) return fail(QOZ_EINVAL, "NULL argument");
-  int d;
-  uint64_t n[3] = {1, 1, 1};
-  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
-  if (ssim_window == 0) ssim_window = 7;
-  if (ssim_window > 11) return fail(QOZ_EINVAL, "ssim_window must be <= 11");
-  QOZ_TRY(set_device(c));
-  const Geo g = make_geo(d, n);
+}  // extern "C"
+
+namespace qoz {
+
+/* Device scratch of one metrics call: status words, the range and SSE
+ * partials, and the SSIM partials (at most ssim_cap of them).  `prof` says
+ * whether launches may be bracketed with timing events. */
+struct MetricsScratch {
+  uint32_t* status;
+  uint8_t* partial;
+  double* ssim;
+  uint64_t ssim_cap;
+  bool prof;
+};
+
+/* Partials go to the host through the context's pinned staging buffer in
+ * pieces of at most this many bytes. */
+constexpr size_t kMetricsPiece = 512u << 10;
+
+static qoz_status metrics_impl(qoz_ctx* c, const float* d_x,
+                               const float* d_y, const Geo& g,
+                               const SsimJob& j0, double* psnr, double* ssim,
+                               double* max_abs_err, const MetricsScratch& m,
+                               hipStream_t s) {
+  SsimJob j = j0;
   const uint64_t N = (uint64_t)g.n[0] * g.n[1] * g.n[2];
   const uint32_t rp = range_parts(N), sp = sse_parts(N);
-  SsimJob j;
-  j.P = g.n[0];
-  j.Rn = g.n[1];
-  j.Cn = g.n[2];
-  j.wp = g.n[0] < ssim_window ? g.n[0] : ssim_window;
-  j.wr = g.n[1] < ssim_window ? g.n[1] : ssim_window;
-  j.wc = g.n[2] < ssim_window ? g.n[2] : ssim_window;
-  j.field_stride = N;
-  j.batch = 1;
-  j.x_mod = 1;
   const uint64_t qp = ssim ? ssim_parts(j) : 0;
-  const size_t small = 8 * (2 * (size_t)rp + 2 * (size_t)sp + qp) + 1024;
-  QOZ_TRY(ensure_pinned(c, kPinSmall + small));
-  QOZ_TRY(ensure(c->partial, small));
-  QOZ_TRY(ensure(c->ssim_part, 8 * (qp + 1)));
-  QOZ_TRY(ensure(c->status, 256));
-  uint8_t* dp = (uint8_t*)c->partial.p;
-  float* pmin = (float*)dp;
+  if (qp > m.ssim_cap) return fail(QOZ_EINVAL, "too many SSIM partial sums");
+  if (c->pinned_bytes < kPinSmall + kMetricsPiece)
+    return fail(QOZ_EDEVICE, "staging buffer smaller than its minimum");
+  float* pmin = (float*)m.partial;
   float* pmax = pmin + rp;
-  double* psse = (double*)(dp + 8 * (size_t)rp);
+  double* psse = (double*)(m.partial + 8 * (size_t)rp);
   double* pmx = psse + sp;
-  uint32_t* st = (uint32_t*)c->status.p;
-  launch_init_status(st, s);
-  PROF(PK_CHECK, 4.0 * N, launch_range(d_x, N, pmin, pmax, st, rp, s));
-  PROF(PK_REDUCE, 8.0 * N, launch_sse_max(d_x, d_y, N, psse, pmx, sp, s));
+  launch_init_status(m.status, s);
+  if (m.prof) {
+    PROF(PK_CHECK, 4.0 * N, launch_range(d_x, N, pmin, pmax, m.status, rp, s));
+    PROF(PK_REDUCE, 8.0 * N,
+         launch_sse_max(d_x, d_y, N, psse, pmx, sp, s));
+  } else {
+    launch_range(d_x, N, pmin, pmax, m.status, rp, s);
+    launch_sse_max(d_x, d_y, N, psse, pmx, sp, s);
+  }
   const size_t part_bytes = 8 * (size_t)rp + 16 * (size_t)sp;
-  QOZ_TRY(to_host(c, pin(c, kPinSmall), dp, part_bytes, s));
-  QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
+  QOZ_TRY(to_host(c, pin(c, kPinSmall), m.partial, part_bytes, s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus), m.status, 32, s));
   QOZ_TRY(sync_checked(s));
   const float* hmin = (const float*)pin(c, kPinSmall);
   const float* hmax = hmin + rp;
@@ -537,21 +542,99 @@ qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
   if (ssim) {
     j.c1 = (0.01 * vrange) * (0.01 * vrange);
     j.c2 = (0.03 * vrange) * (0.03 * vrange);
-    double* parts = (double*)c->ssim_part.p;
     bool launched = false;
-    PROF(PK_SSIM, 8.0 * N, launched = launch_ssim(j, d_x, d_y, parts, s));
-    if (!launched) return fail(QOZ_EDEVICE, "SSIM window ring does not fit LDS");
-    QOZ_TRY(to_host(c, pin(c, kPinSmall), parts, 8 * qp, s));
-    QOZ_TRY(sync_checked(s));
-    const double* hp = (const double*)pin(c, kPinSmall);
+    if (m.prof) {
+      PROF(PK_SSIM, 8.0 * N, launched = launch_ssim(j, d_x, d_y, m.ssim, s));
+    } else {
+      launched = launch_ssim(j, d_x, d_y, m.ssim, s);
+    }
+    if (!launched)
+      return fail(QOZ_EDEVICE, "SSIM window ring does not fit LDS");
+    /* sequential sum in partial index order, piece by piece */
     double tot = 0.0;
-    for (uint64_t i = 0; i < qp; ++i) tot += hp[i];
+    const uint64_t per = kMetricsPiece / 8;
+    for (uint64_t i0 = 0; i0 < qp; i0 += per) {
+      const uint64_t k = std::min<uint64_t>(per, qp - i0);
+      QOZ_TRY(to_host(c, pin(c, kPinSmall), m.ssim + i0, 8 * k, s));
+      QOZ_TRY(sync_checked(s));
+      const double* hp = (const double*)pin(c, kPinSmall);
+      for (uint64_t i = 0; i < k; ++i) tot += hp[i];
+    }
     const double nwin = (double)(j.P - j.wp + 1) * (double)(j.Rn - j.wr + 1) *
                         (double)(j.Cn - j.wc + 1);
     *ssim = tot / nwin;
   }
-  prof_collect(c);
+  if (m.prof) prof_collect(c);
   return QOZ_OK;
+}
+
+/* Shape checks and the SSIM window job shared by both metrics calls. */
+static qoz_status metrics_setup(qoz_ctx* c, const float* d_x,
+                                const float* d_y, qoz_shape shape,
+                                uint32_t ssim_window, Geo* g, SsimJob* j) {
+  if (!c || !d_x || !d_y) return fail(QOZ_EINVAL, "NULL argument");
+  int d;
+  uint64_t n[3] = {1, 1, 1};
+  if (!shape_ok(shape, &d, n)) return fail(QOZ_EINVAL, "bad shape");
+  if (ssim_window == 0) ssim_window = 7;
+  if (ssim_window > 11) return fail(QOZ_EINVAL, "ssim_window must be <= 11");
+  *g = make_geo(d, n);
+  j->P = g->n[0];
+  j->Rn = g->n[1];
+  j->Cn = g->n[2];
+  j->wp = g->n[0] < ssim_window ? g->n[0] : ssim_window;
+  j->wr = g->n[1] < ssim_window ? g->n[1] : ssim_window;
+  j->wc = g->n[2] < ssim_window ? g->n[2] : ssim_window;
+  j->field_stride = (uint64_t)g->n[0] * g->n[1] * g->n[2];
+  j->batch = 1;
+  j->x_mod = 1;
+  j->c1 = j->c2 = 0.0;
+  return QOZ_OK;
+}
+
+}  // namespace qoz
+
+extern "C" {
+
+qoz_status qoz_metrics(qoz_ctx* c, const float* d_x, const float* d_y,
+                       qoz_shape shape, uint32_t ssim_window, double* psnr,
+                       double* ssim, double* max_abs_err, hipStream_t s) {
+  clear_error();
+  Geo g;
+  SsimJob j;
+  QOZ_TRY(metrics_setup(c, d_x, d_y, shape, ssim_window, &g, &j));
+  QOZ_TRY(set_device(c));
+  const uint64_t N = (uint64_t)g.n[0] * g.n[1] * g.n[2];
+  const uint32_t rp = range_parts(N), sp = sse_parts(N);
+  const uint64_t qp = ssim ? ssim_parts(j) : 0;
+  const size_t small = 8 * (2 * (size_t)rp + 2 * (size_t)sp) + 1024;
+  QOZ_TRY(ensure_pinned(c, kPinSmall + std::max(small, kMetricsPiece)));
+  QOZ_TRY(ensure(c->partial, small));
+  QOZ_TRY(ensure(c->ssim_part, 8 * (qp + 1)));
+  QOZ_TRY(ensure(c->status, 256));
+  MetricsScratch m{(uint32_t*)c->status.p, (uint8_t*)c->partial.p,
+                   (double*)c->ssim_part.p, qp, true};
+  return metrics_impl(c, d_x, d_y, g, j, psnr, ssim, max_abs_err, m, s);
+}
+
+qoz_status qoz_metrics_noalloc(qoz_ctx* c, const float* d_x,
+                               const float* d_y, qoz_shape shape,
+                               uint32_t ssim_window, double* psnr,
+                               double* ssim, double* max_abs_err,
+                               hipStream_t s) {
+  clear_error();
+  Geo g;
+  SsimJob j;
+  QOZ_TRY(metrics_setup(c, d_x, d_y, shape, ssim_window, &g, &j));
+  if (!c->fixed_scratch)
+    return fail(QOZ_EDEVICE, "fixed device scratch was not resolved");
+  QOZ_TRY(set_device(c));
+  uint8_t* base = (uint8_t*)c->fixed_scratch;
+  MetricsScratch m{(uint32_t*)(base + kFixedStatusOff),
+                   base + kFixedPartialOff,
+                   (double*)(base + kFixedSsimOff),
+                   (kFixedScratchBytes - kFixedSsimOff) / 8, false};
+  return metrics_impl(c, d_x, d_y, g, j, psnr, ssim, max_abs_err, m, s);
 }
 
 qoz_status qoz_error_ac(qoz_ctx* c, const float* d_x, const float* d_y,

@@ -171,6 +171,10 @@ qoz_status qoz_ctx_create(int hip_device, qoz_ctx** out) {
   if (!c) return fail(QOZ_ENOMEM, "context allocation failed");
   c->device = hip_device;
   qoz_status st = set_device(c);
+  if (st == QOZ_OK) {
+    const hipError_t e = fixed_scratch_addr(hip_device, &c->fixed_scratch);
+    if (e != hipSuccess) st = hip_fail(e, "hipGetSymbolAddress(scratch)");
+  }
   if (st == QOZ_OK) st = ensure_pinned(c, 2u << 20);
   if (st != QOZ_OK) {
     qoz_ctx_destroy(c);

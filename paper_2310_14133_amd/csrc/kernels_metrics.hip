@@ -24,6 +24,28 @@ namespace qoz {
 
 constexpr int kSsimLdsMax = 150 * 1024; /* largest dynamic LDS of k_ssim */
 
+/* Scratch of the metrics call that allocates nothing (qoz_metrics_noalloc):
+ * every device holds its own copy for the life of the process.  Host code
+ * never passes this name to a kernel; it uses the address that
+ * fixed_scratch_addr looks up on each device. */
+static __device__ __align__(256) uint8_t scratch[kFixedScratchBytes];
+static_assert(kFixedPartialOff + 8 * 2048 + 16 * 2048 <= kFixedSsimOff,
+              "range and SSE partial sums overlap the SSIM partial sums");
+
+hipError_t fixed_scratch_addr(int dev, void** out) {
+  constexpr int kMaxDev = 64;
+  static std::once_flag once[kMaxDev];
+  static void* addr[kMaxDev];
+  static hipError_t err[kMaxDev];
+  if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
+  std::call_once(once[dev], [dev] {
+    err[dev] = hipGetSymbolAddress(&addr[dev], HIP_SYMBOL(scratch));
+  });
+  if (err[dev] != hipSuccess) return err[dev];
+  *out = addr[dev];
+  return hipSuccess;
+}
+
 constexpr uint32_t kRedThreads = 256;
 
 uint32_t range_parts(uint64_t n) {

@@ -29,6 +29,13 @@ constexpr size_t kHeaderBytes = 200;
 /* pinned staging bytes of the single-field calls; the batched
  * decompression stages past them */
 constexpr size_t kPinSingleBytes = 2u << 20;
+/* Fixed device scratch of the calls that allocate nothing: a file-scope
+ * device array of this many bytes per device (status words, the range and
+ * SSE partial sums, then the SSIM partial sums). */
+constexpr size_t kFixedScratchBytes = 4u << 20;
+constexpr size_t kFixedStatusOff = 0;
+constexpr size_t kFixedPartialOff = 256;
+constexpr size_t kFixedSsimOff = 64u << 10;
 constexpr uint16_t kStreamVersion = 4;       /* unpacked payload */
 constexpr uint16_t kStreamVersionPacked = 5; /* zero-word packed payload */
 constexpr uint32_t kPackPercent = 97; /* pack when packed <= 97 % of raw */
@@ -226,6 +233,8 @@ struct qoz_ctx {
   /* batch workers: their contexts and streams */
   std::vector<qoz_ctx*> workers;
   std::vector<hipStream_t> worker_streams;
+  /* this device's copy of the fixed scratch array (its device address) */
+  void* fixed_scratch = nullptr;
   /* pinned host staging */
   void* pinned = nullptr;
   void* pinned_dev = nullptr; /* its device address */
@@ -524,6 +533,9 @@ struct SsimJob {
   double c1, c2;
 };
 uint64_t ssim_parts(const SsimJob& j);
+/* Device address of the fixed scratch array (kFixedScratchBytes) on device
+ * `dev`, which must be the current device; looked up once per device. */
+hipError_t fixed_scratch_addr(int dev, void** out);
 /* false when the device cannot give the window ring its LDS */
 bool launch_ssim(const SsimJob& j, const float* x, const float* y,
                  double* parts, hipStream_t s);
