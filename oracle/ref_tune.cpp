@@ -280,7 +280,11 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
   if (target < QREF_TARGET_CR || target > QREF_TARGET_AC) return QREF_EINVAL;
   if (cfg && (cfg->ablation & ~(QREF_ABLATE_AB | QREF_ABLATE_LEVELWISE)))
     return QREF_EINVAL;
-  if (!all_finite(x, g.N)) return QREF_EINVAL;
+  /* A ratio-target tuning reads only the sampled blocks (Sec. VI-A), so
+   * only their values must be finite; the quality targets also use the
+   * whole field's value range (Eq. 1-3) and check every value. */
+  const bool ratio = target == QREF_TARGET_CR;
+  if (!ratio && !all_finite(x, g.N)) return QREF_EINVAL;
   uint32_t s = out->anchor_stride ? out->anchor_stride : (g.d == 2 ? 64u : 32u);
   if (s < 2 || (s & (s - 1)) != 0) return QREF_EINVAL;
   int L = ilog2(s);
@@ -288,10 +292,13 @@ extern "C" int qref_tune(const float* x, qref_shape shape, double e,
   Sample sp;
   int rc = make_plan(g, s, cfg, &sp, true, x);
   if (rc != QREF_OK) return rc;
+  if (ratio)
+    for (const std::vector<float>& blk : sp.blocks)
+      if (!all_finite(blk.data(), (int64_t)blk.size())) return QREF_EINVAL;
   int Lt = (int)sp.Lt;
   int w = (cfg && cfg->ssim_window) ? (int)cfg->ssim_window : 7;
-  double vmin, vmax;
-  value_range(x, g.N, &vmin, &vmax);
+  double vmin = 0.0, vmax = 0.0; /* unused by the ratio target */
+  if (!ratio) value_range(x, g.N, &vmin, &vmax);
   double vrange = vmax - vmin;
   std::vector<Cand> cands = candidates(g.d, cfg && cfg->all_orders);
   if (trace) {

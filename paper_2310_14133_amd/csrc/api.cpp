@@ -25,6 +25,14 @@ constexpr size_t kPinStatus = 1024u << 10;     /* 4 KB */
 constexpr size_t kPinSmall = (1024u << 10) + 4096;
 constexpr size_t kPinBase = kPinSingleBytes;
 
+/* Algorithmic bytes per bin in the timing table: a bin counts as a 4-byte
+ * quantization code (the width of the integer codes in the cost model of
+ * the sweeps), although the kernels store bins as 2-byte values.  A
+ * compression sweep target moves x, its neighbour line, its code and (except
+ * in the last sweep) its reconstruction; a decompression target its code,
+ * its neighbour line and its value. */
+constexpr double kCodeBytes = 4.0;
+
 static inline uint8_t* pin(qoz_ctx* c, size_t off) {
   return (uint8_t*)c->pinned + off;
 }
@@ -85,18 +93,18 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
       if (i == fb) { /* sweep A (if any) and B as one row pass */
         const bool write_w = fb + 1 < P.sweeps.size();
         const double tg = (double)rj.B.count + (fa != SIZE_MAX ? rj.A.count : 0);
-        PROF(PK_ROW_COMP_L1, tg * (write_w ? 14.0 : 10.0),
+        PROF(PK_ROW_COMP_L1, tg * ((write_w ? 12.0 : 8.0) + kCodeBytes),
              launch_row_comp(P.g, rj, d_x, W, codes, write_w, st, s));
       }
       continue;
     }
     const bool last = i + 1 == P.sweeps.size();
     PROF(sw.level == 1 ? PK_SWEEP_COMP_L1 : PK_SWEEP_COMP,
-         (double)sw.count * (last ? 10.0 : 14.0),
+         (double)sw.count * ((last ? 8.0 : 12.0) + kCodeBytes),
          launch_sweep_comp(P.g, sw, d_x, W, codes, !last, st, s,
                            tiles ? (*tiles)[i] : SweepTile()));
   }
-  PROF(PK_HIST, 2.0 * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
+  PROF(PK_HIST, kCodeBytes * P.n_codes, launch_hist(codes, P.n_codes, hist, s));
   /* used symbols sorted on the device; the tree is built on the host */
   QOZ_TRY(ensure(c->hsort, 8 * (kSortCap + 1)));
   launch_hist_sort(hist, 1, (uint64_t*)c->hsort.p, s);
@@ -157,8 +165,11 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   const uint64_t n_used = usym.size();
   /* an encoder table entry holds the code above an 8-bit length; a code
    * longer than 56 bits needs more than Fib(58) ~ 5.9e11 coded points */
-  for (uint64_t i = 0; i < n_used; ++i)
+  uint32_t max_len = 0;
+  for (uint64_t i = 0; i < n_used; ++i) {
     if (ulen[i] > 56) return fail(QOZ_EINVAL, "Huffman code longer than 56 bits");
+    max_len = std::max<uint32_t>(max_len, ulen[i]);
+  }
   std::vector<uint64_t> ucode(n_used);
   canonical_codes_sparse(usym.data(), ulen.data(), (uint32_t)n_used,
                          ucode.data());
@@ -180,7 +191,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   if (tab_n)
     QOZ_TRY(to_device(c, c->enc_table.p, tab, 8ull * tab_n, s));
   const uint64_t* dtab = (const uint64_t*)c->enc_table.p;
-  PROF(PK_HUFF_LEN, 2.0 * P.n_codes + 8.0 * nch,
+  PROF(PK_HUFF_LEN, kCodeBytes * P.n_codes + 8.0 * nch,
        (launch_huff_len(codes, P.chunks, dtab, lo, tab_n, zero_entry,
                         (uint32_t*)c->chunk_bits.p,
                         (uint32_t*)c->chunk_zeros.p, s),
@@ -220,15 +231,15 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   SweepTable tbl;
   fill_sweep_table(P, &tbl);
   PROF(PK_HUFF_ENC,
-       2.0 * P.n_codes + 4.0 * n_words + 8.0 * n_unpred + 26.0 * nch,
+       kCodeBytes * P.n_codes + 4.0 * n_words + 8.0 * n_unpred + 26.0 * nch,
        launch_huff_encode(codes, P.chunks, dtab, lo, tab_n, zero_entry,
                           (const uint64_t*)c->coff.p,
                           (const uint32_t*)c->upre.p,
                           (uint16_t*)(out + lay.segs),
                           (uint32_t*)(out + lay.payload),
                           (cap - lay.payload) / 4, (float*)(out + lay.unpred),
-                          d_x, P.g, tbl, (uint32_t)max_chunk_words, st,
-                          (uint32_t*)c->chunk_bits.p, s));
+                          d_x, P.g, tbl, (uint32_t)max_chunk_words, max_len,
+                          st, (uint32_t*)c->chunk_bits.p, s));
   /* each chunk's size under zero-word packing (from the encoder, in
    * chunk_bits, free again after the first scan), scanned into the packed
    * offsets and total; upre and chunk_zeros are spent by now */
@@ -415,7 +426,7 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
                        (uint32_t*)c->ptmp.p, st, s));
     payload = (const uint32_t*)c->ptmp.p;
   }
-  PROF(PK_HUFF_DEC, 4.0 * nw + 2.0 * P.n_codes + 4.0 * nu + 26.0 * nch,
+  PROF(PK_HUFF_DEC, 4.0 * nw + kCodeBytes * P.n_codes + 4.0 * nu + 26.0 * nch,
        launch_huff_decode(payload, nw,
                           (const uint64_t*)(in + lay.coff),
                           (const uint32_t*)(in + lay.upre),
@@ -442,13 +453,13 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
     if (fuse && (i == fa || i == fb)) {
       if (i == fb) {
         const double tg = (double)rj.B.count + (fa != SIZE_MAX ? rj.A.count : 0);
-        PROF(PK_ROW_DEC_L1, tg * 10.0,
+        PROF(PK_ROW_DEC_L1, tg * (8.0 + kCodeBytes),
              launch_row_decomp(P.g, rj, d_y, codes, s));
       }
       continue;
     }
     PROF(sw.level == 1 ? PK_SWEEP_DEC_L1 : PK_SWEEP_DEC,
-         (double)sw.count * 10.0,
+         (double)sw.count * (8.0 + kCodeBytes),
          launch_sweep_decomp(P.g, sw, d_y, codes, s,
                              tiles ? (*tiles)[i] : SweepTile()));
   }

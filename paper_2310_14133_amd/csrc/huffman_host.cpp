@@ -216,20 +216,16 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
     if (pos[l] == t->off[l]) t->first[l] = code[i];
     (*sorted)[pos[l]++] = syms[i];
   }
-  /* Fast tables: a code of length l fills the 2^(width - l) entries that
-   * start with it (l <= width); entries of longer (or invalid) codes stay 0
-   * in the length table. */
+  /* Fast table: a code of length l <= kSymBits fills the 2^(kSymBits - l)
+   * entries that start with it; entries of longer (or invalid) codes stay
+   * 0. */
   for (uint32_t i = 0; i < n_used; ++i) {
     const uint32_t l = lens[i];
-    if (l > (uint32_t)kLenBits) continue;
-    const uint64_t cv = code[i];
-    const uint8_t e = (uint8_t)(l | (syms[i] == 0 ? 0x80u : 0u));
-    const uint32_t base = (uint32_t)(cv << (kLenBits - l));
-    for (uint32_t k = 0; k < (1u << (kLenBits - l)); ++k) t->lz[base + k] = e;
     if (l > (uint32_t)kSymBits) continue;
-    const uint32_t sbase = (uint32_t)(cv << (kSymBits - l));
-    for (uint32_t k = 0; k < (1u << (kSymBits - l)); ++k)
-      t->sym[sbase + k] = syms[i];
+    const uint32_t e = l | (syms[i] == 0 ? 0x40u : 0u) |
+                       ((uint32_t)syms[i] << 16);
+    const uint32_t base = (uint32_t)(code[i] << (kSymBits - l));
+    for (uint32_t k = 0; k < (1u << (kSymBits - l)); ++k) t->ent[base + k] = e;
   }
   return true;
 }

@@ -7,17 +7,21 @@
  * per segment, eight lanes per chunk, a wave covers eight consecutive
  * chunks.  Each lane keeps its next payload words in a 16-word ring in LDS
  * (word k of every lane's ring in one LDS row, so a wave's reads fall in
- * distinct banks) and a 64-bit bit buffer refilled from it; global loads
- * happen only at the ends of 8-bin groups, where a lane that has used half
- * its ring fetches the next eight words into registers and, one group
- * later, writes them over the used half.  Codewords are looked up in a
- * 13-bit length table and a 12-bit symbol table in LDS; longer codes are
- * sized by comparing the top 32 bits of the buffer with the canonical
- * code's per-length limits (held in registers) and mapped to their symbol
- * through the canonical order.  Bins are written eight at a time (16-byte
- * stores).  Symbol-0 bins (unpredictable values) are counted per segment;
- * a scan over the chunk's eight lanes ranks them and their stream positions
- * go to `upos`, so the exact values can be placed before the inverse sweeps.
+ * distinct banks) and the two words under its read position in registers:
+ * the next 32 bits of the segment are one funnel shift of that pair.  Each
+ * codeword costs one lookup in a 12-bit table in LDS that gives its length,
+ * its symbol and whether it is symbol 0; when the position crosses a word,
+ * the pair advances by the ring word read alongside the lookup.  Global
+ * loads happen only at the ends of 8-bin groups, where a lane that has used
+ * half its ring fetches the next eight words into registers and, one group
+ * later, writes them over the used half.  Codes longer than 12 bits are
+ * sized by comparing the 32-bit window with the canonical code's
+ * per-length limits (held in registers) and mapped to their symbol through
+ * the canonical order.  Bins are written eight at a time (16-byte stores).
+ * Symbol-0 bins (unpredictable values) are ranked by a scan over the
+ * chunk's eight lanes, only in groups where a lane of the wave met one, and
+ * their stream positions go to `upos`, so the exact values can be placed
+ * before the inverse sweeps.
  *
  * Every payload read is bounded by the chunk's words (zero beyond).  The
  * stream is rejected if a chunk table entry is inconsistent, a segment does
@@ -38,13 +42,13 @@ constexpr uint32_t kSortedLds = 1024; /* canonical symbols kept in LDS */
 constexpr uint32_t kRing = 16;        /* payload words per lane in LDS */
 constexpr uint32_t kHalf = kRing / 2;
 constexpr uint32_t kInvalid = 0xffffffffu;
+constexpr uint32_t kEntZero = 0x40u; /* DecTables::ent: symbol 0's code */
 
 struct DecShared {
   uint32_t ring[kRing][kDecWG];
   /* per chunk, the 64 bins of the group being decoded, in bin order */
   __align__(16) uint16_t tb[kChunksPerWG][64];
-  uint8_t lz[1u << kLenBits];
-  uint16_t sym[1u << kSymBits];
+  uint32_t ent[1u << kSymBits]; /* DecTables::ent */
   uint16_t sorted[kSortedLds];
   uint64_t first[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
@@ -73,6 +77,25 @@ struct Words {
   __device__ __forceinline__ uint32_t operator()(uint32_t i) const {
     return i < nw ? w[i] : 0u;
   }
+  /* words i .. i + 4n - 1 into v, unmasked: words at or past nw are
+   * whatever follows the chunk (the caller masks them when it uses them,
+   * so the loads stay in flight until then) */
+  template <uint32_t n>
+  __device__ __forceinline__ void raw_block(uint32_t i, uint32_t* v) const {
+    if (i + 4 * n <= room) {
+#pragma unroll
+      for (uint32_t k = 0; k < n; ++k) {
+        const Quad q = *reinterpret_cast<const Quad*>(w + i + 4 * k);
+        v[4 * k] = q.x;
+        v[4 * k + 1] = q.y;
+        v[4 * k + 2] = q.z;
+        v[4 * k + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (uint32_t k = 0; k < 4 * n; ++k) v[k] = (*this)(i + k);
+    }
+  }
   /* words i .. i + 4n - 1 into v */
   template <uint32_t n>
   __device__ __forceinline__ void block(uint32_t i, uint32_t* v) const {
@@ -92,22 +115,27 @@ struct Words {
   }
 };
 
-/* One lane's reader: buf holds nb >= 33 valid bits from pos on; the ring
- * holds words [B, B + kRing); wp is the next word to append to buf; pf
- * holds words [B + kRing, B + kRing + kHalf), always in flight.  A step
- * appends at most one word, and the group end slides the ring whenever
- * wp - B >= kHalf, so wp - B <= 7 when a group starts and every ring read
- * in its eight steps is of a word the ring holds. */
+/* One lane's reader.  a and b are words wp - 2 and wp - 1 of the chunk;
+ * the next 32 bits of the segment are ((a:b) >> so)[31:0] (so in [0, 31]),
+ * i.e. the read position is 32 (wp - 1) - so.  The ring holds words
+ * [B, B + kRing); pf holds words [B + kRing, B + kRing + kHalf), always in
+ * flight.  Consuming up to 32 bits takes at most one word from the ring
+ * (word wp), and the group end slides the ring whenever wp - B >= kHalf, so
+ * wp - B <= 7 when a group starts and every ring read in its eight steps
+ * is of a word the ring holds.  The prefetched words are masked to the
+ * chunk only when they enter the ring, so their loads overlap the groups
+ * decoded meanwhile instead of stalling the wave at issue. */
 struct Reader {
-  uint64_t buf;
-  int nb;
-  uint32_t pos, wp, B;
+  uint32_t a, b, so, wp, B;
   bool pending;
   uint32_t pf[kHalf];
 
+  __device__ __forceinline__ uint32_t pos() const { return (wp - 1) * 32 - so; }
+  __device__ __forceinline__ uint32_t window() const {
+    return __builtin_amdgcn_alignbit(a, b, so);
+  }
   __device__ __forceinline__ void seek(DecShared& sh, const Words& W,
                                        uint32_t p) {
-    pos = p;
     const uint32_t wi = p >> 5, o = p & 31;
     /* four words at a time (few registers: seeks are rare) */
     uint32_t v0 = 0, v1 = 0;
@@ -122,64 +150,84 @@ struct Reader {
         v1 = v[1];
       }
     }
-    W.block<kHalf / 4>(wi + kRing, pf);
-    buf = (((uint64_t)v0 << 32) | v1) << o;
-    nb = 64 - (int)o;
-    wp = wi + 2;
+    W.raw_block<kHalf / 4>(wi + kRing, pf);
+    if (o) { /* position o of word wi: the pair (wi, wi + 1) */
+      a = v0;
+      b = v1;
+      wp = wi + 2;
+      so = 32 - o;
+    } else { /* the start of word wi: the pair (wi - 1, wi) */
+      a = 0;
+      b = v0;
+      wp = wi + 1;
+      so = 0;
+    }
     B = wi;
     pending = true;
   }
-  /* the 64 bits at pos, from memory */
-  __device__ __forceinline__ uint64_t window(const Words& W) const {
-    const uint32_t wi = pos >> 5, o = pos & 31;
-    const uint64_t a = W(wi), b = W(wi + 1), c = W(wi + 2);
-    return (((a << 32) | b) << o) | (o ? c >> (32 - o) : 0);
+  /* the 64 bits at the read position, from memory */
+  __device__ __forceinline__ uint64_t window64(const Words& W) const {
+    const uint32_t p = pos(), wi = p >> 5, o = p & 31;
+    const uint64_t x = W(wi), y = W(wi + 1), z = W(wi + 2);
+    return (((x << 32) | y) << o) | (o ? z >> (32 - o) : 0);
+  }
+  /* move the read position by len <= 32 bits; nx is word wp */
+  __device__ __forceinline__ void advance(uint32_t len, uint32_t nx) {
+    const int t = (int)so - (int)len;
+    const bool need = t < 0;
+    a = need ? b : a;
+    b = need ? nx : b;
+    wp += need ? 1u : 0u;
+    so = (uint32_t)t & 31u;
   }
   /* end of an 8-bin group: once the first half of the ring is used, move
    * the fetched words over it; keep the next half always in flight */
   __device__ __forceinline__ void group_end(DecShared& sh, const Words& W) {
     if (pending && wp >= B + kHalf) {
+      /* pf holds words B + kRing + k, loaded unmasked: zero past the
+       * chunk's words here, where the loads are first needed */
 #pragma unroll
       for (uint32_t k = 0; k < kHalf; ++k)
-        sh.ring[(B + k) % kRing][threadIdx.x] = pf[k];
+        sh.ring[(B + k) % kRing][threadIdx.x] =
+            B + kRing + k < W.nw ? pf[k] : 0u;
       B += kHalf;
       pending = false;
     }
     if (!pending) {
-      W.block<kHalf / 4>(B + kRing, pf);
+      W.raw_block<kHalf / 4>(B + kRing, pf);
       pending = true;
     }
   }
 };
 
-/* Symbol and length of a codeword the fast tables do not resolve (longer
- * than kSymBits bits, or invalid): kInvalid if invalid. */
+/* Symbol and length of a codeword the table does not resolve (longer than
+ * kSymBits bits, or invalid): kInvalid if invalid.  top is the 32-bit
+ * window at the read position. */
 __device__ __forceinline__ uint32_t slow_symbol(
-    const Reader& rd, const Words& W, uint32_t len, const Limits& lim,
+    const Reader& rd, const Words& W, uint32_t top, const Limits& lim,
     const DecShared& sh, const DecTables* __restrict__ tabs,
     const uint32_t* __restrict__ syms, uint32_t maxlen, uint32_t* len_out) {
-  const uint32_t top = (uint32_t)(rd.buf >> 32);
-  uint64_t V = rd.buf;
-  if (len == 0) { /* longer than kLenBits */
-    len = kLenBits + 1;
+  uint32_t len = kSymBits + 1;
 #pragma unroll
-    for (uint32_t L = kLenBits + 1; L < kRegMax; ++L)
-      len += top >= lim.top[L] ? 1u : 0u;
-    if (len < kRegMax) {
-      len = len <= maxlen ? len : maxlen;
-    } else { /* a code of kRegMax bits or more, or a saturated limit */
-      V = rd.window(W);
-      const uint64_t h = V >> 1;
-      len = 0;
-      for (uint32_t L = kLenBits + 1; L <= maxlen; ++L)
-        if (h < tabs->lim_half[L]) {
-          len = sh.cnt[L] ? L : 0;
-          break;
-        }
-      if (!len) return kInvalid;
-    }
+  for (uint32_t L = kSymBits + 1; L < kRegMax; ++L)
+    len += top >= lim.top[L] ? 1u : 0u;
+  uint64_t r;
+  if (len < kRegMax) {
+    len = len <= maxlen ? len : maxlen;
+    r = (uint64_t)(top >> (32 - len));
+  } else { /* a code of kRegMax bits or more, or a saturated limit */
+    const uint64_t V = rd.window64(W);
+    const uint64_t h = V >> 1;
+    len = 0;
+    for (uint32_t L = kSymBits + 1; L <= maxlen; ++L)
+      if (h < tabs->lim_half[L]) {
+        len = sh.cnt[L] ? L : 0;
+        break;
+      }
+    if (!len) return kInvalid;
+    r = V >> (64 - len);
   }
-  const uint64_t r = (V >> (64 - len)) - sh.first[len];
+  r -= sh.first[len];
   if (r >= sh.cnt[len]) return kInvalid; /* past the last code */
   const uint32_t k = sh.off[len] + (uint32_t)r;
   *len_out = len;
@@ -211,13 +259,9 @@ __device__ __forceinline__ void decode_wg(
     const uint32_t* __restrict__ syms, uint16_t* __restrict__ codes,
     uint32_t* __restrict__ upos, uint32_t* status, uint32_t wg) {
   {
-    const uint4* src = reinterpret_cast<const uint4*>(tabs->lz);
-    uint4* dst = reinterpret_cast<uint4*>(sh.lz);
-    for (uint32_t i = threadIdx.x; i < sizeof(sh.lz) / 16; i += kDecWG)
-      dst[i] = src[i];
-    src = reinterpret_cast<const uint4*>(tabs->sym);
-    dst = reinterpret_cast<uint4*>(sh.sym);
-    for (uint32_t i = threadIdx.x; i < sizeof(sh.sym) / 16; i += kDecWG)
+    const uint4* src = reinterpret_cast<const uint4*>(tabs->ent);
+    uint4* dst = reinterpret_cast<uint4*>(sh.ent);
+    for (uint32_t i = threadIdx.x; i < sizeof(sh.ent) / 16; i += kDecWG)
       dst[i] = src[i];
   }
   const uint32_t n_used = tabs->n_used;
@@ -273,34 +317,31 @@ __device__ __forceinline__ void decode_wg(
   bool inv = false;
   Reader rd;
   rd.seek(sh, W, start);
+  /* symbol-0 flags of the group's steps (bit 6 of the table entries) */
+  uint32_t zor = 0;
   /* one codeword; an invalid one is flagged and skipped as one bit */
   auto step = [&]() -> uint32_t {
-    const uint32_t hi = (uint32_t)(rd.buf >> 32);
-    const uint32_t e = sh.lz[hi >> (32 - kLenBits)];
-    uint32_t s = sh.sym[hi >> (32 - kSymBits)];
-    uint32_t nx = sh.ring[rd.wp % kRing][threadIdx.x];
+    const uint32_t nx = sh.ring[rd.wp % kRing][threadIdx.x];
+    const uint32_t top = rd.window();
+    const uint32_t e = sh.ent[top >> (32 - kSymBits)];
     uint32_t len = e & 0x3fu;
-    if (__builtin_expect(len == 0 || len > (uint32_t)kSymBits, 0)) {
-      s = slow_symbol(rd, W, len, lim, sh, tabs, syms, maxlen, &len);
+    uint32_t s = e >> 16;
+    zor |= e;
+    if (__builtin_expect(len == 0, 0)) {
+      s = slow_symbol(rd, W, top, lim, sh, tabs, syms, maxlen, &len);
       if (s == kInvalid) {
         inv = true;
         s = 1;
         len = 1;
       }
-      /* a code longer than the buffer's guaranteed bits: seek past it */
+      zor |= s == 0 ? kEntZero : 0u;
+      /* a code longer than the pair's guaranteed bits: seek past it */
       if (len > 32) {
-        rd.seek(sh, W, rd.pos + len);
+        rd.seek(sh, W, rd.pos() + len);
         len = 0;
-        nx = 0;
       }
     }
-    rd.buf <<= len;
-    rd.nb -= (int)len;
-    rd.pos += len;
-    const bool need = rd.nb <= 32;
-    rd.buf |= (uint64_t)(need ? nx : 0u) << ((uint32_t)(32 - rd.nb) & 31u);
-    rd.wp += need ? 1u : 0u;
-    rd.nb += need ? 32 : 0;
+    rd.advance(len, nx);
     return s;
   };
   /* Group g: step u of lane j is bin 64 g + 8 u + j.  The chunk's eight
@@ -322,13 +363,13 @@ __device__ __forceinline__ void decode_wg(
     const uint32_t nat = 64 * g + 8 * j; /* first bin of this lane's run */
     const uint32_t nval = nat < nsym ? (nsym - nat < 8 ? nsym - nat : 8) : 0;
     const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-    uint32_t zm = 0;
+    if (__any((zor & kEntZero) != 0)) {
+      uint32_t zm = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < 8; ++i)
-      zm |= (i < nval && ((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) == 0)
-                ? 1u << i
-                : 0u;
-    if (__any(zm != 0)) {
+      for (uint32_t i = 0; i < 8; ++i)
+        zm |= (i < nval && ((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) == 0)
+                  ? 1u << i
+                  : 0u;
       const uint32_t zc = __popc(zm);
       const uint32_t zi = group_incl_scan(zc, j);
       uint32_t r = u0 + zacc + zi - zc;
@@ -341,6 +382,7 @@ __device__ __forceinline__ void decode_wg(
       }
       zacc += __shfl(zi, kSegPerChunk - 1, kSegPerChunk);
     }
+    zor = 0;
     if (nval == 8) {
       *reinterpret_cast<uint4*>(codes + base + nat) = q;
     } else {
@@ -369,7 +411,8 @@ __device__ __forceinline__ void decode_wg(
   }
   if (chunk_ok) {
     const uint32_t end = j + 1 < kSegPerChunk ? start + d : nbits;
-    if (inv || zbad || (j + 1 < kSegPerChunk ? rd.pos != end : rd.pos > end))
+    const uint32_t pend = rd.pos();
+    if (inv || zbad || (j + 1 < kSegPerChunk ? pend != end : pend > end))
       bad = true;
     if (zacc != u1 - u0) bad = true;
   }

@@ -478,6 +478,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
 
 /* at least 6 waves per SIMD (80 VGPRs): one register more costs a sixth
  * of the occupancy and about 15 % of the kernel's time */
+template <bool kLong> /* kLong: some code is longer than 32 bits */
 __global__ __launch_bounds__(kEncThreads, 6) void k_huff_encode(
     const uint16_t* __restrict__ codes, Chunks ch,
     const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
@@ -498,14 +499,23 @@ __global__ __launch_bounds__(kEncThreads, 6) void k_huff_encode(
   const uint64_t w0 = coff[c];
   const uint32_t nw = (uint32_t)(coff[c + 1] - w0);
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) words[i] = 0;
-  /* staging: lane t takes the 8-bin groups m = t + 256 r */
+  /* staging: lane t takes the 8-bin groups m = t + 256 r; the full
+   * groups' loads of both rounds are issued before either is used */
   uint32_t v[kRounds][8];
   uint32_t zpack = 0;
+  uint4 qr[kRounds];
+#pragma unroll
+  for (uint32_t r = 0; r < kRounds; ++r) {
+    const uint32_t m = threadIdx.x + r * kEncThreads;
+    qr[r] = 8 * m + 8 <= nsym
+                ? *reinterpret_cast<const uint4*>(codes + base + 8 * m)
+                : make_uint4(0, 0, 0, 0);
+  }
 #pragma unroll
   for (uint32_t r = 0; r < kRounds; ++r) {
     const uint32_t m = threadIdx.x + r * kEncThreads;
     if (8 * m + 8 <= nsym) {
-      const uint4 q = *reinterpret_cast<const uint4*>(codes + base + 8 * m);
+      const uint4 q = qr[r];
       const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i) v[r][i] = (w[i / 2] >> (16 * (i & 1))) & 0xffffu;
@@ -552,31 +562,32 @@ __global__ __launch_bounds__(kEncThreads, 6) void k_huff_encode(
   if (threadIdx.x < kSegPerChunk - 1)
     segs[(uint64_t)c * (kSegPerChunk - 1) + threadIdx.x] = (uint16_t)(
         seg_end[threadIdx.x] - (threadIdx.x ? seg_end[threadIdx.x - 1] : 0u));
-  /* this lane's bits [pos0, pos0 + bits) */
+  /* This lane's bits [pos0, pos0 + bits), MSB-first.  acc holds the bits
+   * not yet written in its low nacc (< 32) bits (above them: bits already
+   * written, shifted out as codes come in); every complete word is ORed
+   * into the zeroed chunk words (a lane's first and last words are shared
+   * with its neighbours), and a code that completes no word ORs 0 into
+   * the current word, so the stores need no branch. */
   {
     uint64_t acc = 0;
     uint32_t nacc = pos0 & 31u, wi = pos0 >> 5;
-    auto emit = [&](uint32_t word) {
-      if (wi * 32 >= pos0) /* covered by this lane alone */
-        words[wi] = word;
-      else
-        atomicOr(&words[wi], word);
-      ++wi;
+    auto put = [&](uint32_t code, uint32_t len) { /* len <= 32 */
+      acc = (acc << len) | code;
+      nacc += len;
+      const bool full = nacc >= 32;
+      nacc -= full ? 32u : 0u;
+      atomicOr(&words[wi], full ? (uint32_t)(acc >> nacc) : 0u);
+      wi += full ? 1u : 0u;
     };
 #pragma unroll
     for (uint32_t k = 0; k < kEncPerThread; ++k) {
-      uint32_t len = (uint32_t)(ent[k] & 0xff);
+      const uint32_t len = (uint32_t)(ent[k] & 0xff);
       const uint64_t code = ent[k] >> 8;
-      while (len) {
-        const uint32_t take = len < 32 ? len : 32u;
-        const uint64_t part = (code >> (len - take)) & ((1ull << take) - 1);
-        acc = (acc << take) | part;
-        nacc += take;
-        len -= take;
-        if (nacc >= 32) {
-          nacc -= 32;
-          emit((uint32_t)(acc >> nacc));
-        }
+      if (kLong && len > 32) {
+        put((uint32_t)(code >> 32), len - 32);
+        put((uint32_t)code, 32);
+      } else {
+        put((uint32_t)code, len);
       }
     }
     if (nacc) atomicOr(&words[wi], (uint32_t)(acc << (32 - nacc)));
@@ -626,8 +637,8 @@ void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
                         uint32_t* payload,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
-                        uint32_t max_chunk_words, uint32_t* status,
-                        uint32_t* pack_bits, hipStream_t s) {
+                        uint32_t max_chunk_words, uint32_t max_len,
+                        uint32_t* status, uint32_t* pack_bits, hipStream_t s) {
   const uint64_t nch = chunks.count();
   if (!nch) return;
   /* every chunk's word count is at most the largest one, which is at
@@ -635,10 +646,16 @@ void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
   const uint32_t mw = max_chunk_words < kEncMaxWords ? max_chunk_words
                                                      : kEncMaxWords;
   const size_t lds = 4 * ((size_t)mw + 1);
-  hipLaunchKernelGGL(k_huff_encode, dim3((uint32_t)nch), dim3(kEncThreads),
-                     lds, s, codes, chunks, table, tab_lo, tab_n, zero_entry,
-                     coff, upre, segs, payload, payload_cap_words, unpred, x,
-                     g, st, status, pack_bits);
+  if (max_len > 32)
+    hipLaunchKernelGGL(k_huff_encode<true>, dim3((uint32_t)nch),
+                       dim3(kEncThreads), lds, s, codes, chunks, table, tab_lo,
+                       tab_n, zero_entry, coff, upre, segs, payload,
+                       payload_cap_words, unpred, x, g, st, status, pack_bits);
+  else
+    hipLaunchKernelGGL(k_huff_encode<false>, dim3((uint32_t)nch),
+                       dim3(kEncThreads), lds, s, codes, chunks, table, tab_lo,
+                       tab_n, zero_entry, coff, upre, segs, payload,
+                       payload_cap_words, unpred, x, g, st, status, pack_bits);
 }
 
 }  // namespace qoz

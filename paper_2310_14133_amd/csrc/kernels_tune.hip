@@ -95,7 +95,7 @@ constexpr uint32_t kGatherPer = 8;
 __global__ __launch_bounds__(kGatherThreads) void k_gather_blocks(
     const float* __restrict__ x, Geo g, BlockGeo bg,
     const uint32_t* __restrict__ origins, float* __restrict__ xs,
-    float* __restrict__ wc) {
+    float* __restrict__ wc, uint32_t* status) {
   const uint32_t blk = blockIdx.y;
   const uint32_t n1 = bg.g.n[1], n2 = bg.g.n[2], size = bg.size;
   const FastDiv f2(n2, size), f1(n1, size);
@@ -113,24 +113,28 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_blocks(
     }
   }
   const uint64_t base = (uint64_t)blk * size;
+  bool bad = false;
 #pragma unroll
   for (uint32_t u = 0; u < kGatherPer; ++u) {
     const uint32_t t = t0 + u * kGatherThreads;
     if (t < size) {
       xs[base + t] = v[u];
       wc[base + t] = v[u];
+      bad |= !isfinite(v[u]);
     }
   }
+  /* non-finite sampled values (the ratio target reads nothing else) */
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, kStNonFinite);
 }
 
 void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
                           const uint32_t* origins_dev, float* xs, float* wc,
-                          hipStream_t s) {
+                          uint32_t* status, hipStream_t s) {
   if (!bg.size || !bg.nb) return;
   const uint32_t per = kGatherThreads * kGatherPer;
   hipLaunchKernelGGL(k_gather_blocks, dim3((bg.size + per - 1) / per, bg.nb),
                      dim3(kGatherThreads), 0, s, x, g, bg, origins_dev, xs,
-                     wc);
+                     wc, status);
 }
 
 __global__ __launch_bounds__(kTuneThreads) void k_alg1_level(

@@ -69,8 +69,7 @@ struct Chunks {
   }
   __host__ __device__ uint64_t count() const { return n ? first[n] : 0; }
 };
-constexpr int kLenBits = 13;               /* decoder length-table width */
-constexpr int kSymBits = 12;               /* decoder symbol-table width */
+constexpr int kSymBits = 12;               /* decoder table width */
 constexpr int kMaxCodeLen = 63;
 
 /* status word bits reported by kernels */
@@ -140,11 +139,10 @@ struct SweepTable {
 
 /* Canonical-Huffman decoding tables (device copy). */
 struct DecTables {
-  /* indexed by the next kLenBits bits: code length | 0x80 if the code is
-   * symbol 0's; 0 for a longer (or invalid) code */
-  uint8_t lz[1u << kLenBits];
-  /* indexed by the next kSymBits bits: the symbol of codes that short */
-  uint16_t sym[1u << kSymBits];
+  /* indexed by the next kSymBits bits: for a code of at most kSymBits bits
+   * its length (bits 0-5), 0x40 if it is symbol 0's code, and its symbol
+   * (bits 16-31); 0 for a longer (or invalid) code */
+  uint32_t ent[1u << kSymBits];
   uint64_t first[kMaxCodeLen + 1];
   uint32_t cnt[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
@@ -384,8 +382,8 @@ void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
                         uint32_t* payload,
                         uint64_t payload_cap_words, float* unpred,
                         const float* x, const Geo& g, const SweepTable& st,
-                        uint32_t max_chunk_words, uint32_t* status,
-                        uint32_t* pack_bits, hipStream_t s);
+                        uint32_t max_chunk_words, uint32_t max_len,
+                        uint32_t* status, uint32_t* pack_bits, hipStream_t s);
 /* zero-word packing of the payload (stream format 5): pack_bits[c] from
  * the encoder is 32 x the chunk's packed word count, scanned into pcoff */
 void launch_pack_write(const uint32_t* raw, const uint64_t* coff,
@@ -548,10 +546,11 @@ struct BlockGeo {
   uint32_t Lt;
   uint32_t d;
 };
-/* the sampled blocks into xs and a second copy into wc */
+/* the sampled blocks into xs and a second copy into wc; kStNonFinite into
+ * status[0] when a sampled value is NaN or Inf */
 void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
                           const uint32_t* origins_dev, float* xs, float* wc,
-                          hipStream_t s);
+                          uint32_t* status, hipStream_t s);
 /* whether Algorithm 1's level-l working copies fit in LDS on the current
  * device (then no per-candidate copies in wt are made) */
 bool alg1_in_lds(const BlockGeo& bg, uint32_t l);

@@ -313,34 +313,40 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
   float* pmax = pmin + rp;
   uint32_t* dorig = (uint32_t*)(pmax + rp);
 
-  /* value range and finiteness of the whole field */
+  /* The ratio target reads only the sampled blocks (Sec. VI-A), checked
+   * for finiteness as they are gathered; the quality targets also need the
+   * whole field's value range (Eq. 1-3) and check every value. */
+  const bool need_range = target != QOZ_TARGET_CR;
   launch_init_status(st, s);
-  {
+  if (need_range) {
     hipEvent_t ev = prof_begin(c, s, PK_CHECK);
     launch_range(d_x, N, pmin, pmax, st, rp, s);
     prof_end(c, s, ev, PK_CHECK, 4.0 * N);
+    QOZ_TRY(to_host(c, h_range, pmin, 8 * (size_t)rp, s));
   }
-  QOZ_TRY(to_host(c, h_range, pmin, 8 * (size_t)rp, s));
-  QOZ_TRY(to_host(c, h_status, st, 16, s));
   std::memcpy(h_status + 8, origins.data(), 4 * origins.size());
   QOZ_TRY(to_device(c, dorig, h_status + 8, 4 * origins.size(), s));
   {
     hipEvent_t ev = prof_begin(c, s, PK_TUNE_GATHER);
-    launch_gather_blocks(d_x, g, bg, dorig, xs, wc, s);
+    launch_gather_blocks(d_x, g, bg, dorig, xs, wc, st, s);
     prof_end(c, s, ev, PK_TUNE_GATHER, 12.0 * bsz);
   }
+  QOZ_TRY(to_host(c, h_status, st, 16, s));
   QOZ_HIP(hipGetLastError());
   QOZ_HIP(hipStreamSynchronize(s));
   if (h_status[0] & kStNonFinite) {
     prof_collect(c);
     return fail(QOZ_EINVAL, "input contains NaN or Inf");
   }
-  float lo = h_range[0], hi = h_range[rp];
-  for (uint32_t i = 1; i < rp; ++i) {
-    lo = std::fmin(lo, h_range[i]);
-    hi = std::fmax(hi, h_range[rp + i]);
+  double vrange = 0.0; /* unused by the ratio target */
+  if (need_range) {
+    float lo = h_range[0], hi = h_range[rp];
+    for (uint32_t i = 1; i < rp; ++i) {
+      lo = std::fmin(lo, h_range[i]);
+      hi = std::fmax(hi, h_range[rp + i]);
+    }
+    vrange = (double)hi - (double)lo;
   }
-  const double vrange = (double)hi - (double)lo;
 
   /* ---- Algorithm 1 ---- */
   uint8_t Is_interp[QOZ_MAX_LEVELS] = {0};
