@@ -71,8 +71,12 @@ def main():
     ap.add_argument("--seed", type=int, default=20)
     ap.add_argument("--log-normal", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-online tuner comparison")
     ap.add_argument("--no-autotune", action="store_true",
                     help="default sweep launch tiles")
+    ap.add_argument("--cpu-reps", type=int, default=3,
+                    help="oracle runs for the CPU baseline (median)")
     ap.add_argument("--cpu-crop", type=int, default=0,
                     help="edge of a central crop for the CPU baseline "
                          "(0 = whole field)")
@@ -217,6 +221,15 @@ def main():
     value = field_bytes / (ms_per_step / 1e3) / 1e9
     launches, tot_ms, algo_bytes = timed
     achieved = (algo_bytes / 1e9) / (tot_ms / 1e3)
+    # the library counts every bin as a 4-byte code (the cost model's
+    # width); the kernels store 2-byte bins, so per bin 2 bytes fewer move
+    n_codes = x.numel() - ((n - 1) // 32 + 1) ** 3
+    bins_per_launch = {"huffman_decode": n_codes, "huffman_encode": n_codes,
+                       "huffman_count": n_codes, "histogram": n_codes}
+    stored = None
+    if dom in bins_per_launch:
+        stored = (algo_bytes / launches - 2.0 * bins_per_launch[dom]) / 1e9 \
+            / (tot_ms / launches / 1e3)
     from paper_2310_14133_amd import profiling
     traffic = profiling.load_traffic(args.traffic, dom)
 
@@ -264,6 +277,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "code_bytes_counted": 4,
+            "frac_at_stored_width": (round(stored / HBM_PEAK_GBS, 4)
+                                     if stored is not None else None),
             "avg_launch_ms": round(tot_ms / launches, 5),
             "algo_bytes_per_launch": algo_bytes / launches,
             "cold_copy_TBps": round(hbm_copy, 3),
@@ -275,23 +291,45 @@ def main():
                            for k, v in kinds.items()},
     }
 
-    # the learned tuner on the same field (network trained on the online
-    # tuner's PSNR-mode choices), for reference next to tune_ms
+    # the learned tuner against the online tuner on the same field at the
+    # PSNR targets 60 / 80 / 100 dB: tuning time at each target's nominal
+    # bound, and the ratio of each tuner's parameters at equal PSNR (the
+    # bound bisected until the final PSNR is within 0.05 dB above the
+    # target, each step tuning at that bound)
     wpath = os.path.join(ROOT, "paper_2310_14133_amd", "tuner_mlp.bin")
-    if os.path.exists(wpath):
+    if os.path.exists(wpath) and not args.no_learned:
         from paper_2310_14133_amd import learned
+        print("bench: learned tuner at equal PSNR", file=sys.stderr,
+              flush=True)
         Pw = learned.load_weights(wpath)
-        cfg_l = q.make_tune_config(sample_rate=learned.SAMPLE_RATE)
-        lt = []
-        for _ in range(6):
-            ev[0].record(stream)
-            pl, fb = codec.tune_learned(x, e, Pw, 0.5, "psnr", cfg_l)
-            ev[1].record(stream)
-            torch.cuda.synchronize()
-            lt.append(ev[0].elapsed_time(ev[1]))
-        line["learned_tune_ms"] = round(sorted(lt[1:])[len(lt[1:]) // 2], 4)
-        line["learned_params"] = q.params_dict(pl, 3)
-        line["learned_fallback"] = bool(fb)
+        cfg_l = q.make_tune_config(block=32, sample_rate=learned.SAMPLE_RATE)
+        rows = []
+        for target in learned.PSNR_TARGETS:
+            eb = learned.bound_for_psnr(vmax - vmin, target)
+            (pl, fb), tl = learned._timed(lambda: codec.tune_learned(
+                x, eb, Pw, 0.5, "psnr", cfg_l), reps=5)
+            _, te = learned._timed(lambda: codec.tune(x, eb, "psnr", cfg_l),
+                                   reps=5)
+            cr_e, ps_e, _, _ = learned.equal_psnr(
+                codec, x, target, lambda b: codec.tune(x, b, "psnr", cfg_l))
+            cr_l, ps_l, _, _ = learned.equal_psnr(
+                codec, x, target, lambda b: codec.tune_learned(
+                    x, b, Pw, 0.5, "psnr", cfg_l)[0])
+            rows.append({"psnr_target": target,
+                         "online_tune_ms": round(te, 4),
+                         "learned_tune_ms": round(tl, 4),
+                         "tune_speedup": round(te / tl, 3),
+                         "cr_online": round(cr_e, 4),
+                         "cr_learned": round(cr_l, 4),
+                         "cr_ratio_equal_psnr": round(cr_l / cr_e, 5),
+                         "psnr_online": round(ps_e, 3),
+                         "psnr_learned": round(ps_l, 3),
+                         "fallback": bool(fb)})
+        line["learned_tuner"] = {
+            "rows": rows,
+            "cr_ratio_min": min(r["cr_ratio_equal_psnr"] for r in rows),
+            "tune_speedup_min": min(r["tune_speedup"] for r in rows),
+            "fallback_rate": sum(r["fallback"] for r in rows) / len(rows)}
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, e, args)
@@ -299,8 +337,28 @@ def main():
     codec.close()
 
 
+def host_cpu():
+    """CPU model and logical CPU count of this host, from lscpu."""
+    import subprocess
+    model, total = "unknown", os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True,
+                             timeout=20).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() == "Model name":
+                model = v.strip()
+            elif k.strip() == "CPU(s)":
+                total = int(v.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return model, total
+
+
 def cpu_baseline(x, e, args):
-    """The oracle (single-threaded C++) on the same workload."""
+    """The oracle (single-threaded C++) on the same workload, pinned to one
+    host core (the process's affinity is narrowed to it for the duration,
+    as taskset would), median of `args.cpu_reps` whole steps."""
     import numpy as np
 
     from oracle import ref
@@ -310,21 +368,38 @@ def cpu_baseline(x, e, args):
         o = (xh.shape[0] - c) // 2
         xh = np.ascontiguousarray(xh[o:o + c, o:o + c, o:o + c])
     cfg = ref.tune_config(block=32, sample_rate=0.01, all_orders=1)
-    print(f"bench: cpu baseline on {xh.shape}", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    p, _ = ref.tune(xh, e, "cr", cfg, want_trace=False)
-    t1 = time.perf_counter()
-    z = ref.compress(xh, e, p)
-    t2 = time.perf_counter()
-    ref.decompress(z)
-    t3 = time.perf_counter()
-    total = t3 - t0
-    return {"value": round(xh.nbytes / total / 1e9, 5), "unit": "GB/s",
+    allowed = sorted(os.sched_getaffinity(0))
+    core = allowed[-1]
+    model, total = host_cpu()
+    print(f"bench: cpu baseline on {xh.shape}, core {core}", file=sys.stderr,
+          flush=True)
+    runs = []
+    os.sched_setaffinity(0, {core})
+    try:
+        for r in range(args.cpu_reps):
+            t0 = time.perf_counter()
+            p, _ = ref.tune(xh, e, "cr", cfg, want_trace=False)
+            t1 = time.perf_counter()
+            z = ref.compress(xh, e, p)
+            t2 = time.perf_counter()
+            ref.decompress(z)
+            t3 = time.perf_counter()
+            runs.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2))
+            print(f"bench: cpu baseline run {r + 1}: {t3 - t0:.3f} s",
+                  file=sys.stderr, flush=True)
+    finally:
+        os.sched_setaffinity(0, allowed)
+    runs.sort()
+    tot, tt, tc, td = runs[len(runs) // 2]
+    return {"value": round(xh.nbytes / tot / 1e9, 5), "unit": "GB/s",
             "cores": 1, "kind": "oracle",
             "sample": f"whole step (tune+compress+decompress) on "
-                      f"{'x'.join(map(str, xh.shape))} of the same field",
-            "tune_s": round(t1 - t0, 3), "compress_s": round(t2 - t1, 3),
-            "decompress_s": round(t3 - t2, 3)}
+                      f"{'x'.join(map(str, xh.shape))} of the same field, "
+                      f"median of {len(runs)} runs",
+            "pinned_core": core, "cpu_model": model, "host_cpus": total,
+            "runs_s": [round(r[0], 3) for r in runs],
+            "tune_s": round(tt, 3), "compress_s": round(tc, 3),
+            "decompress_s": round(td, 3)}
 
 
 if __name__ == "__main__":

@@ -323,6 +323,30 @@ qoz_status qoz_decompress_batch(qoz_ctx* ctx, qoz_batch_dec_item* items,
 qoz_status qoz_decompress_queue(qoz_ctx* ctx, qoz_batch_dec_item* items,
                                 uint32_t n, hipStream_t stream);
 
+/* Compression of items[0..n) (at most 16384) on `stream` through device
+ * work queues, in a number of launches that does not grow with n: one
+ * launch places every field's anchors, each round of sweeps (the r-th
+ * sweep, or fused level-1 row pair, of every field; Sec. V-B) is one
+ * launch, one launch counts every field's bins and one sorts the used
+ * bins of every histogram; the Huffman codes (Sec. VI-A) are built on host
+ * threads; one launch fills every field's sections before its payload,
+ * one counts the code bits of every chunk of every field, one scan (two
+ * launches) turns the counts into chunk offsets and one encoding launch
+ * codes the chunks of every field.  Three waits per call (four when a
+ * field uses more than 4096 distinct bins), plus the few launches of each
+ * field whose zero-word packing pays.  Items without params are
+ * tuned first with the online tuner (target, cfg), one at a time.  Every
+ * stream equals qoz_compress's byte for byte; sweeps use the default
+ * launch tiles.  A field whose output cannot hold the sections before its
+ * payload is compressed by qoz_compress after the queue (and reports the
+ * size needed).  ms and done_ms of every item are the call's duration.
+ * Returns as qoz_compress_batch.  Scratch: every field's reconstruction,
+ * bins and histogram at once, kept in ctx.
+ * Errors: EINVAL, EDEVICE, ENOMEM, or an item's status. */
+qoz_status qoz_compress_queue(qoz_ctx* ctx, qoz_batch_item* items, uint32_t n,
+                              qoz_target target, const qoz_tune_config* cfg,
+                              hipStream_t stream);
+
 /* With enable != 0, qoz_decompress_queue keeps its device work (upload,
  * launches, status read-back) as a HIP graph: a call whose launch
  * signature (grids, queue layout, scratch addresses, packed payloads)
@@ -352,17 +376,19 @@ qoz_status qoz_ctx_set_queue_graphs(qoz_ctx* ctx, int enable);
 #define QOZ_MLP_NOUT 11
 #define QOZ_MLP_NPARAM 22219
 
-/* Features of a 3D field for the learned tuner: the blocks of b = 32
- * (33^3 points) sampled as in Sec. VI-A at cfg's rate and stride (rate 0
- * -> 0.01; cfg->block is ignored), 32 float32 features each (level-wise
- * linear / cubic residual statistics of the original values, gradient
- * deciles, the block's value range and the range over all sampled
- * blocks, all relative to abs_eb), and their mean over the blocks into
- * d_mean[32].  Only the sampled blocks are read.  d_block (may be NULL)
- * receives the per-block rows, *nblocks (may be NULL) their count; with
- * d_block non-NULL, block_cap is its capacity in rows.  Every dimension
- * must be >= 33.  Errors: EINVAL (shape, bound, cfg, NaN or Inf in a
- * sampled block, block_cap too small), EDEVICE, ENOMEM. */
+/* Features of a 2D or 3D field for the learned tuner: the blocks of
+ * b = 32 (33^d points) sampled as in Sec. VI-A at cfg's rate and stride
+ * (rate 0 -> 0.01; stride 0 -> round(32 rate^(-1/d)); cfg->block is
+ * ignored), 32 float32 features each (level-wise linear / cubic residual
+ * statistics of the original values along each dimension, deciles of the
+ * squared forward-difference gradient, the block's value range and the
+ * range over all sampled blocks, all relative to abs_eb), and their mean
+ * over the blocks into d_mean[32].  Only the sampled blocks are read.
+ * d_block (may be NULL) receives the per-block rows, *nblocks (may be
+ * NULL) their count; with d_block non-NULL, block_cap is its capacity in
+ * rows.  Every dimension must be >= 33.  Errors: EINVAL (shape, bound,
+ * cfg, NaN or Inf in a sampled block, block_cap too small), EDEVICE,
+ * ENOMEM. */
 qoz_status qoz_learned_features(qoz_ctx* ctx, const float* d_x,
                                 qoz_shape shape, double abs_eb,
                                 const qoz_tune_config* cfg, float* d_mean,
@@ -400,16 +426,16 @@ qoz_status qoz_mlp_train_step(qoz_ctx* ctx, float* d_params, float* d_m,
                               uint32_t n_rows, uint32_t batch, float lr,
                               uint32_t t, double* d_loss, hipStream_t stream);
 
-/* Learned tuning: features of d_x, one forward pass, and per head the class
- * of highest score.  When the smallest of the three heads' softmax
- * probabilities is below min_confidence, or the field is not 3D with every
- * dimension >= 33, the online tuner (qoz_tune with `fallback_target` and
- * cfg) decides instead and *used_fallback (may be NULL) is set to 1, else
- * 0.  The network's parameters use every level's interpolation type from
- * its first head and the identity dimension order.  On input
- * out->anchor_stride selects s.  The network path reads only the sampled
- * blocks (NaN or Inf elsewhere is left to qoz_compress to reject).
- * Errors: as qoz_tune. */
+/* Learned tuning: features of d_x, one forward pass of the network
+ * d_params (trained on fields of d_x's dimensionality), and per head the
+ * class of highest score.  When the smallest of the three heads' softmax
+ * probabilities is below min_confidence, or a dimension is below 33, the
+ * online tuner (qoz_tune with `fallback_target` and cfg) decides instead
+ * and *used_fallback (may be NULL) is set to 1, else 0.  The network's
+ * parameters use every level's interpolation type from its first head and
+ * the identity dimension order.  On input out->anchor_stride selects s.
+ * The network path reads only the sampled blocks (NaN or Inf elsewhere is
+ * left to qoz_compress to reject).  Errors: as qoz_tune. */
 qoz_status qoz_tune_learned(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
                             double abs_eb, const float* d_params,
                             double min_confidence, qoz_target fallback_target,
@@ -417,10 +443,12 @@ qoz_status qoz_tune_learned(qoz_ctx* ctx, const float* d_x, qoz_shape shape,
                             int* used_fallback, hipStream_t stream);
 
 /* Learned tuning of many fields: the features of every supported field
- * (3D, every dimension >= 33), one forward pass over all of them, then the
- * online tuner, one field at a time in item order, for the fields that are
- * unsupported or below min_confidence.  Each item's params and
- * used_fallback equal what qoz_tune_learned gives for it alone.
+ * (every dimension >= 33; a 2D field only when d_params_2d, the network
+ * for 2D fields, is not NULL), one forward pass per network (d_params for
+ * the 3D fields) over all of them, then the online tuner, one field at a
+ * time in item order, for the fields that are unsupported or below
+ * min_confidence.  Each item's params and used_fallback equal what
+ * qoz_tune_learned gives for it alone with its network.
  * params.anchor_stride is read on input (0 = default).  Synchronous.
  * Returns QOZ_OK when every item succeeded, else the status of the first
  * failing item in index order (each item keeps its own).
@@ -436,6 +464,7 @@ typedef struct {
 
 qoz_status qoz_tune_learned_batch(qoz_ctx* ctx, qoz_learned_item* items,
                                   uint32_t n, const float* d_params,
+                                  const float* d_params_2d,
                                   double min_confidence,
                                   qoz_target fallback_target,
                                   const qoz_tune_config* cfg,

@@ -36,6 +36,10 @@ e the absolute bound, all logs base 2:
   f[31] = log(1 + (max - min over all sampled blocks together) / e), so
       that the features read the sampled blocks only, as the search of
       Sec. VI-A does.
+A 2D field's sampled blocks are 33 x 33 points and the same 32 features
+are formed over its two dimensions: the residuals along k = 0, 1 in turn,
+and g2 = dx*dx + dy*dy at the n = 32^2 points with both coordinates in
+[0, 31].
 The field's features are the mean over its sampled blocks (FP64 sum in
 block order, then float32).
 """
@@ -68,9 +72,9 @@ def _residual_sums(blk, l, cubic):
     s1 = s2 = 0.0
     cnt = 0
     f32 = np.float32
-    grid = blk[::h, ::h, ::h]  # the h-grid: coordinates 0, h, ..., 32
+    grid = blk[(slice(None, None, h),) * blk.ndim]  # coordinates 0, h, .., 32
     m = grid.shape[0]          # 32 / h + 1
-    for k in range(3):
+    for k in range(blk.ndim):
         g = np.moveaxis(grid, k, 0)
         for j in range(1, m, 2):  # odd multiples of h along k
             b = g[j - 1]
@@ -90,9 +94,10 @@ def _residual_sums(blk, l, cubic):
 
 
 def block_features(blk, e, vrange):
-    """32 features (float32) of one 33^3 float32 block; formulas in the
-    module docstring."""
-    assert blk.shape == (BLOCK + 1,) * 3 and blk.dtype == np.float32
+    """32 features (float32) of one 33^3 (or, for a 2D field, 33^2) float32
+    block; formulas in the module docstring."""
+    assert blk.ndim in (2, 3) and blk.dtype == np.float32
+    assert blk.shape == (BLOCK + 1,) * blk.ndim
     f = np.zeros(NFEAT, np.float64)
     for l in range(1, LT + 1):
         for t in (0, 1):
@@ -100,10 +105,15 @@ def block_features(blk, e, vrange):
             f[4 * (l - 1) + 2 * t] = np.log2(1.0 + (s1 / n) / e)
             f[4 * (l - 1) + 2 * t + 1] = np.log2(1.0 + np.sqrt(s2 / n) / e)
     x = blk
-    dx = x[1:, :-1, :-1] - x[:-1, :-1, :-1]
-    dy = x[:-1, 1:, :-1] - x[:-1, :-1, :-1]
-    dz = x[:-1, :-1, 1:] - x[:-1, :-1, :-1]
-    g2 = np.sort(((dx * dx + dy * dy) + dz * dz).ravel())
+    if x.ndim == 3:
+        dx = x[1:, :-1, :-1] - x[:-1, :-1, :-1]
+        dy = x[:-1, 1:, :-1] - x[:-1, :-1, :-1]
+        dz = x[:-1, :-1, 1:] - x[:-1, :-1, :-1]
+        g2 = np.sort(((dx * dx + dy * dy) + dz * dz).ravel())
+    else:
+        dx = x[1:, :-1] - x[:-1, :-1]
+        dy = x[:-1, 1:] - x[:-1, :-1]
+        g2 = np.sort((dx * dx + dy * dy).ravel())
     n = g2.size
     for q in range(1, 11):
         v = float(g2[-(-q * n // 10) - 1])
@@ -114,13 +124,12 @@ def block_features(blk, e, vrange):
 
 
 def field_features(x, e, origins):
-    """Per-block features and their mean (float32) for the blocks of a 3D
-    float32 field at the given origins (Sec. VI-A sampling)."""
+    """Per-block features and their mean (float32) for the blocks of a 2D
+    or 3D float32 field at the given origins (Sec. VI-A sampling)."""
     blocks = []
     for o in origins:
-        i, j, k = (int(v) for v in o)
-        blocks.append(np.ascontiguousarray(
-            x[i:i + BLOCK + 1, j:j + BLOCK + 1, k:k + BLOCK + 1]))
+        sl = tuple(slice(int(v), int(v) + BLOCK + 1) for v in o[:x.ndim])
+        blocks.append(np.ascontiguousarray(x[sl]))
     vrange = (max(float(b.max()) for b in blocks) -
               min(float(b.min()) for b in blocks))
     rows = [block_features(b, e, vrange) for b in blocks]

@@ -128,9 +128,12 @@ def lib():
                                          C.POINTER(TuneConfig), u32, vp]
         L.qoz_decompress_batch.argtypes = [vp, vp, u32, u32, vp]
         L.qoz_decompress_queue.argtypes = [vp, vp, u32, vp]
+        L.qoz_compress_queue.argtypes = [vp, vp, u32, C.c_int,
+                                         C.POINTER(TuneConfig), vp]
         L.qoz_ctx_set_queue_graphs.argtypes = [vp, C.c_int]
-        L.qoz_tune_learned_batch.argtypes = [vp, vp, u32, vp, dbl, C.c_int,
-                                             C.POINTER(TuneConfig), vp]
+        L.qoz_tune_learned_batch.argtypes = [vp, vp, u32, vp, vp, dbl,
+                                             C.c_int, C.POINTER(TuneConfig),
+                                             vp]
         L.qoz_learned_features.argtypes = [vp, vp, Shape, dbl,
                                            C.POINTER(TuneConfig), vp, vp,
                                            u64, C.POINTER(u64), vp]
@@ -156,6 +159,7 @@ def lib():
                    "qoz_autotune_tiles",
                    "qoz_compress_batch",
                    "qoz_decompress_batch", "qoz_decompress_queue",
+                   "qoz_compress_queue",
                    "qoz_ctx_set_queue_graphs", "qoz_tune_learned_batch",
                    "qoz_learned_features",
                    "qoz_mlp_forward", "qoz_mlp_grad", "qoz_mlp_train_step",
@@ -361,6 +365,15 @@ def qoz_ctx_set_queue_graphs(ctx, enable):
            "qoz_ctx_set_queue_graphs")
 
 
+def qoz_compress_queue(ctx, items, target, cfg, stream):
+    """items: a ctypes array of BatchItem; returns the batch status
+    without raising (each item carries its own)."""
+    return lib().qoz_compress_queue(ctx, C.cast(items, C.c_void_p),
+                                    len(items), int(target),
+                                    C.byref(cfg) if cfg else None,
+                                    C.c_void_p(stream))
+
+
 def qoz_decompress_queue(ctx, items, stream):
     """items: a ctypes array of BatchDecItem; returns the status without
     raising."""
@@ -430,12 +443,13 @@ def qoz_tune_learned(ctx, d_x, shape, abs_eb, d_params, min_confidence,
     return params, bool(fb.value)
 
 
-def qoz_tune_learned_batch(ctx, items, d_params, min_confidence,
-                           fallback_target, cfg, stream):
+def qoz_tune_learned_batch(ctx, items, d_params, d_params_2d,
+                           min_confidence, fallback_target, cfg, stream):
     """items: a ctypes array of LearnedItem; returns the status without
     raising (each item carries its own)."""
     return lib().qoz_tune_learned_batch(ctx, C.cast(items, C.c_void_p),
                                         len(items), C.c_void_p(d_params),
+                                        C.c_void_p(d_params_2d),
                                         C.c_double(min_confidence),
                                         int(fallback_target),
                                         C.byref(cfg) if cfg else None,
@@ -575,10 +589,15 @@ class Codec:
 
     # ---- batches -------------------------------------------------------
     def compress_batch(self, xs, abs_ebs, params=None, target="cr", cfg=None,
-                       workers=4):
-        """Compress a list of fields in one call.  params: None (tune each)
-        or a list of Params.  Returns (streams, items): uint8 tensors cut to
-        size, and the BatchItem array (status, ms, done_ms per field)."""
+                       workers=4, queue=False, caps=None, check=True):
+        """Compress a list of fields in one call (queue=True: through the
+        device work queues, qoz_compress_queue; else on worker threads,
+        qoz_compress_batch).  params: None (tune each) or a list of Params
+        (an entry None: tune that field); caps: output capacities in bytes
+        (default: qoz_compress_bound).  Returns (streams, items): uint8
+        tensors cut to size, and the BatchItem array (status, out_bytes,
+        ms, done_ms per field); with check=False a failing field does not
+        raise, its stream is empty and its item says why."""
         torch = self.torch
         n = len(xs)
         items = (BatchItem * n)()
@@ -586,22 +605,29 @@ class Codec:
         keep = []
         for i, x in enumerate(xs):
             sh = self._field(x)
-            cap = qoz_compress_bound(sh)
-            out = torch.empty(cap, dtype=torch.uint8, device=self.device)
+            cap = qoz_compress_bound(sh) if caps is None else int(caps[i])
+            out = torch.empty(max(cap, 1), dtype=torch.uint8,
+                              device=self.device)
             outs.append(out)
             it = items[i]
             it.d_x, it.shape, it.abs_eb = x.data_ptr(), sh, float(abs_ebs[i])
-            if params is not None:
+            if params is not None and params[i] is not None:
                 keep.append(params[i])
                 it.params = C.cast(C.pointer(params[i]), C.c_void_p)
             it.d_out, it.cap = out.data_ptr(), cap
-        st = qoz_compress_batch(self.ctx, items, TARGETS[target], cfg,
-                                workers, self._stream())
-        if st != QOZ_OK:
+        if queue:
+            st = qoz_compress_queue(self.ctx, items, TARGETS[target], cfg,
+                                    self._stream())
+        else:
+            st = qoz_compress_batch(self.ctx, items, TARGETS[target], cfg,
+                                    workers, self._stream())
+        if st != QOZ_OK and check:
             bad = [i for i in range(n) if items[i].status != QOZ_OK]
-            raise QozError(st, f"qoz_compress_batch (fields {bad[:8]})",
+            what = "qoz_compress_queue" if queue else "qoz_compress_batch"
+            raise QozError(st, f"{what} (fields {bad[:8]})",
                            qoz_last_error())
-        return [outs[i][:items[i].out_bytes] for i in range(n)], items
+        return [outs[i][:items[i].out_bytes if items[i].status == QOZ_OK
+                        else 0] for i in range(n)], items
 
     def _dec_items(self, zs, out):
         torch = self.torch
@@ -657,8 +683,8 @@ class Codec:
 
     # ---- learned tuner -------------------------------------------------
     def learned_features(self, x, abs_eb, cfg=None, per_block=False):
-        """Mean block features (32 float32) of a 3D field; with per_block
-        also the (nblocks, 32) rows."""
+        """Mean block features (32 float32) of a 2D or 3D field; with
+        per_block also the (nblocks, 32) rows."""
         torch = self.torch
         sh = self._field(x)
         mean = torch.empty(MLP_NFEAT, dtype=torch.float32, device=self.device)
@@ -744,10 +770,13 @@ class Codec:
 
     def tune_learned_batch(self, xs, abs_ebs, params, min_confidence=0.0,
                            fallback_target="psnr", cfg=None,
-                           anchor_stride=0):
-        """Learned tuning of a list of fields; returns the items
+                           anchor_stride=0, params_2d=None):
+        """Learned tuning of a list of fields (params: the network for 3D
+        fields, params_2d for 2D fields or None); returns the items
         (.params, .used_fallback, .status)."""
         self._dev(params, self.torch.float32, (MLP_NPARAM,))
+        if params_2d is not None:
+            self._dev(params_2d, self.torch.float32, (MLP_NPARAM,))
         items = (LearnedItem * len(xs))()
         for i, (x, e) in enumerate(zip(xs, abs_ebs)):
             items[i].d_x = x.data_ptr()
@@ -755,6 +784,8 @@ class Codec:
             items[i].abs_eb = float(e)
             items[i].params.anchor_stride = anchor_stride
         st = qoz_tune_learned_batch(self.ctx, items, params.data_ptr(),
+                                    params_2d.data_ptr()
+                                    if params_2d is not None else None,
                                     min_confidence, TARGETS[fallback_target],
                                     cfg, self._stream())
         if st != QOZ_OK:

@@ -6,10 +6,11 @@ the rest 3D between 64^3 and 384 x 384 x 256 (each side U{64..its cap}),
 k^-3 random fields cut from the corner of one periodic field per shape
 family (one FFT size), value-range-relative bounds log-uniform in
 [1e-5, 1e-2].  Reports aggregate GB/s of input and p50 / p99 per-field
-latency for the loop and for batches of 4 and 8 workers, and the
-decompression of the whole batch through the device work queues (the
-batch calls write into preallocated fields), and PSNR-mode tuning of the
-batch by the online tuner and by the batched learned tuner.
+latency for the loop and for batches of 4 and 8 workers, the compression
+(tuned in the call, and with parameters given) and decompression of the
+whole batch through the device work queues (the batch calls write into
+preallocated fields), and PSNR-mode tuning of the batch by the online
+tuner and by the batched learned tuner.
 
     python -m paper_2310_14133_amd.batch_bench --fields 64
 """
@@ -118,6 +119,43 @@ def main(argv=None):
         res[f"batch_w{w}"] = r
         print(f"batch: workers {w}", json.dumps(r), flush=True)
         del ys
+    # compression through the device work queues (one stream): tuned
+    # inside the call, then with the parameters given (the compression
+    # engine alone, against the loop of single calls with those parameters)
+    codec.compress_batch(xs, ebs, queue=True)  # warm-up: queue buffers
+    torch.cuda.synchronize()
+    tq = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        zq, _ = codec.compress_batch(xs, ebs, queue=True)
+        tq.append(time.perf_counter() - t0)
+    same = all(torch.equal(a, b) for a, b in zip(zq, zs_loop))
+    ps = [codec.tune(x, e) for x, e in zip(xs, ebs)]
+    codec.compress_batch(xs, ebs, ps, queue=True)
+    torch.cuda.synchronize()
+    tp = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        zp, _ = codec.compress_batch(xs, ebs, ps, queue=True)
+        tp.append(time.perf_counter() - t0)
+    same_p = all(torch.equal(a, b) for a, b in zip(zp, zs_loop))
+    tl = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        for x, e, p in zip(xs, ebs, ps):
+            codec.compress(x, e, p)
+        torch.cuda.synchronize()
+        tl.append(time.perf_counter() - t0)
+    r = {"compress_GBps": total / min(tq) / 1e9,
+         "compress_ms": [round(v * 1e3, 3) for v in tq],
+         "outputs_equal_loop": same,
+         "given_params_compress_GBps": total / min(tp) / 1e9,
+         "given_params_compress_ms": [round(v * 1e3, 3) for v in tp],
+         "given_params_outputs_equal_loop": same_p,
+         "given_params_loop_GBps": total / min(tl) / 1e9}
+    res["queue_compress"] = r
+    print("batch: queue compression", json.dumps(r), flush=True)
+    del zq, zp
     # decompression through the device work queues (one stream)
     codec.decompress_queue(zs_loop, out=outs)  # warm-up: queue buffers
     torch.cuda.synchronize()
@@ -160,19 +198,22 @@ def main(argv=None):
 
 def tuning(codec, xs, ebs, total):
     """PSNR-mode tuning of the whole batch: the online tuner one field at a
-    time against the batched learned tuner (2D and small fields fall back
-    to the online tuner), and the ratio each one's parameters give."""
+    time against the batched learned tuner (its 3D and 2D networks; fields
+    below one feature block, or below the confidence margin, fall back to
+    the online tuner), and the ratio each one's parameters give."""
     import torch
     import paper_2310_14133_amd as q
     from paper_2310_14133_amd import learned
-    P = learned.load_weights()
+    P = learned.load_weights(learned.WEIGHTS[3])
+    P2 = learned.load_weights(learned.WEIGHTS[2])
     cfg = q.make_tune_config(block=32, sample_rate=learned.SAMPLE_RATE)
 
     def online():
         return [codec.tune(x, e, "psnr", cfg) for x, e in zip(xs, ebs)]
 
     def batch():
-        its = codec.tune_learned_batch(xs, ebs, P, 0.5, "psnr", cfg)
+        its = codec.tune_learned_batch(xs, ebs, P, 0.5, "psnr", cfg,
+                                       params_2d=P2)
         return [it.params for it in its], sum(it.used_fallback for it in its)
 
     def timed(fn):

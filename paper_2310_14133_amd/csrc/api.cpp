@@ -65,9 +65,10 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   QOZ_TRY(ensure(c->chunk_zeros, 4 * nch));
   QOZ_TRY(ensure(c->coff, 8 * (nch + 1)));
   QOZ_TRY(ensure(c->scan, chunk_scan_scratch(nch)));
-  QOZ_TRY(ensure(c->upre, 4 * (nch + 1)));
+  QOZ_TRY(ensure(c->upre, 8 * (nch + 1)));
   QOZ_TRY(ensure(c->pcoff, 8 * (nch + 1)));
-  QOZ_TRY(ensure(c->enc_table, 8 * kNSym));
+  /* the code table, then the encoder's field record and chunk range */
+  QOZ_TRY(ensure(c->enc_table, 8 * kNSym + 4096));
   float* W = (float*)c->W.p;
   uint16_t* codes = (uint16_t*)c->codes.p;
   uint32_t* hist = (uint32_t*)c->hist.p;
@@ -119,6 +120,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
    * then canonical codes in ascending symbol order */
   std::vector<uint16_t> usym;
   std::vector<uint8_t> ulen;
+  uint64_t n_unpred = 0; /* symbol 0's count: the unpredictable values */
+  uint64_t payload_bits = 0;
   {
     const uint64_t n_keys = hk[0];
     std::vector<uint8_t> klen;
@@ -160,6 +163,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     for (uint32_t i = 0; i < idx.size(); ++i) {
       usym[i] = (uint16_t)(keys[idx[i]] & 0xffffu);
       ulen[i] = klen[idx[i]];
+      if (usym[i] == 0) n_unpred = keys[idx[i]] >> 16;
+      payload_bits += (keys[idx[i]] >> 16) * klen[idx[i]];
     }
   }
   const uint64_t n_used = usym.size();
@@ -184,62 +189,102 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     hi = usym[i];
   }
   const uint32_t tab_n = lo < 0 ? 0 : (uint32_t)(hi - lo + 1);
+  /* Every section before the payload has a size known now (the payload's
+   * start depends on the unpredictable count, symbol 0's count); the
+   * encoder writes the chunk offsets, unpredictable ranks, segment lengths
+   * and unpredictable values into them and finds the payload size.  When
+   * the caller's buffer cannot hold even those sections, the encoder runs
+   * into scratch to learn the size needed. */
+  const Layout lay0 = layout_of(P.n_anchor, n_used, nch, n_unpred, 0);
+  const bool room = d_out && cap >= lay0.payload;
+  if (!room) QOZ_TRY(ensure(c->ptmp, lay0.payload));
+  uint8_t* out = room ? (uint8_t*)d_out : (uint8_t*)c->ptmp.p;
+  const uint64_t cap_words = room ? (cap - lay0.payload) / 4 : 0;
+  /* the chunks' exclusive prefixes of payload words and symbol-0 bins
+   * (from the count and the chunk scan) and the encoder's totals (zero on
+   * entry) */
+  uint64_t* gw = (uint64_t*)c->coff.p;
+  uint64_t* gz = (uint64_t*)c->upre.p;
+  uint64_t* etot = totals + 3;
+  /* the code table, then the encoder's field record, its chunk range and
+   * the count's workgroup range (after the largest table) */
   uint64_t* tab = (uint64_t*)pin(c, kPinTable);
   std::memset(tab, 0, 8ull * tab_n);
   for (uint64_t i = 0; i < n_used; ++i)
     if (usym[i]) tab[usym[i] - lo] = (ucode[i] << 8) | ulen[i];
   if (tab_n)
     QOZ_TRY(to_device(c, c->enc_table.p, tab, 8ull * tab_n, s));
-  const uint64_t* dtab = (const uint64_t*)c->enc_table.p;
-  PROF(PK_HUFF_LEN, kCodeBytes * P.n_codes + 8.0 * nch,
-       (launch_huff_len(codes, P.chunks, dtab, lo, tab_n, zero_entry,
-                        (uint32_t*)c->chunk_bits.p,
-                        (uint32_t*)c->chunk_zeros.p, s),
-        launch_chunk_scan((uint32_t*)c->chunk_bits.p,
-                          (uint32_t*)c->chunk_zeros.p, nch,
-                          (uint64_t*)c->coff.p, (uint32_t*)c->upre.p, totals,
-                          (uint64_t*)c->scan.p, s)));
-  QOZ_TRY(to_host(c, pin(c, kPinStatus + 64), totals, 24, s));
-  QOZ_TRY(sync_checked(s));
-  const uint64_t n_words = ((uint64_t*)pin(c, kPinStatus + 64))[0];
-  const uint64_t n_unpred = ((uint64_t*)pin(c, kPinStatus + 64))[1];
-  const uint64_t max_chunk_words = ((uint64_t*)pin(c, kPinStatus + 64))[2];
-  const Layout lay = layout_of(P.n_anchor, n_used, nch, n_unpred, n_words);
-  if (!d_out || lay.total > cap) {
-    *out_bytes = lay.total;
-    prof_collect(c);
-    return fail(QOZ_ENOSPACE, "output capacity too small");
-  }
-  uint8_t* out = (uint8_t*)d_out;
+  uint8_t* hp = pin(c, kPinSmall);
+  const size_t f_off = 8ull * kNSym;
+  EncField* ef = (EncField*)hp;
+  std::memset(ef, 0, sizeof(EncField));
+  ef->codes = codes;
+  ef->ch = P.chunks;
+  ef->nch = nch;
+  ef->tab = (const uint64_t*)c->enc_table.p;
+  ef->lo = lo;
+  ef->tn = tab_n;
+  ef->zero_entry = zero_entry;
+  ef->coff = (uint64_t*)(out + lay0.coff);
+  ef->upre = (uint32_t*)(out + lay0.upre);
+  ef->segs = (uint16_t*)(out + lay0.segs);
+  ef->payload = (uint32_t*)(out + lay0.payload);
+  ef->cap_words = cap_words;
+  ef->unpred = (float*)(out + lay0.unpred);
+  ef->x = d_x;
+  ef->g = P.g;
+  ef->totals = etot;
+  ef->status = st;
+  ef->pack_bits = (uint32_t*)c->chunk_bits.p;
+  fill_sweep_table(P, &ef->st);
+  const size_t c0_off = (sizeof(EncField) + 255) / 256 * 256;
+  static_assert((sizeof(EncField) + 255) / 256 * 256 + 24 <= 4096,
+                "encoder record larger than its scratch");
+  uint64_t* c0 = (uint64_t*)(hp + c0_off);
+  c0[0] = 0;
+  c0[1] = nch;
+  uint32_t* wg0 = (uint32_t*)(hp + c0_off + 16);
+  const uint32_t count_wg = count_workgroups(nch);
+  wg0[0] = 0;
+  wg0[1] = count_wg;
+  uint8_t* dtab = (uint8_t*)c->enc_table.p;
+  QOZ_TRY(to_device(c, dtab + f_off, hp, c0_off + 24, s));
   /* section padding must read as zero */
-  launch_zero_u32((uint32_t*)out, lay.payload / 4, s);
-  uint8_t* hs = pin(c, kPinStage);
-  write_header(hs, P, n_unpred, n_used, n_words);
-  QOZ_TRY(to_device(c, out, hs, kHeaderBytes, s));
+  launch_zero_u32((uint32_t*)out, lay0.payload / 4, s);
   uint8_t* cb = pin(c, kPinStage + 256);
-  const size_t cb_bytes = lay.coff - lay.syms;
+  const size_t cb_bytes = lay0.coff - lay0.syms;
   std::memset(cb, 0, cb_bytes);
   std::memcpy(cb, usym.data(), 2 * n_used);
-  std::memcpy(cb + (lay.lens - lay.syms), ulen.data(), n_used);
-  QOZ_TRY(to_device(c, out + lay.syms, cb, cb_bytes, s));
+  std::memcpy(cb + (lay0.lens - lay0.syms), ulen.data(), n_used);
+  QOZ_TRY(to_device(c, out + lay0.syms, cb, cb_bytes, s));
   {
-    void* dst[3] = {out + lay.anchors, out + lay.coff, out + lay.upre};
-    const void* src[3] = {c->anchors.p, c->coff.p, c->upre.p};
-    const uint64_t bytes[3] = {4 * P.n_anchor, 8 * (nch + 1), 4 * (nch + 1)};
-    launch_copy_regions(dst, src, bytes, 3, s);
+    void* dst[1] = {out + lay0.anchors};
+    const void* src[1] = {c->anchors.p};
+    const uint64_t bytes[1] = {4 * P.n_anchor};
+    launch_copy_regions(dst, src, bytes, 1, s);
   }
-  SweepTable tbl;
-  fill_sweep_table(P, &tbl);
+  launch_zero_u32((uint32_t*)etot, 6, s);
+  const EncField* d_ef = (const EncField*)(dtab + f_off);
+  const uint64_t* d_c0 = (const uint64_t*)(dtab + f_off + c0_off);
+  /* per chunk its code bits and symbol-0 bins, scanned into the chunks'
+   * payload offsets and unpredictable ranks (the scan's totals are
+   * rewritten by the packing scan below) */
+  PROF(PK_HUFF_COUNT, kCodeBytes * P.n_codes + 8.0 * nch,
+       launch_huff_count(d_ef, d_c0,
+                         (const uint32_t*)(dtab + f_off + c0_off + 16), 1,
+                         count_wg, (uint32_t*)c->chunk_bits.p,
+                         (uint32_t*)c->chunk_zeros.p, s));
+  launch_chunk_scan((uint32_t*)c->chunk_bits.p, (uint32_t*)c->chunk_zeros.p,
+                    nch, gw, gz, totals, (uint64_t*)c->scan.p, s);
+  /* algorithmic bytes: the bins (as 4-byte codes), the payload (its Huffman
+   * bits), the unpredictable values read and written, and per chunk its
+   * offsets (read and written), rank, segment lengths and packed size */
   PROF(PK_HUFF_ENC,
-       kCodeBytes * P.n_codes + 4.0 * n_words + 8.0 * n_unpred + 26.0 * nch,
-       launch_huff_encode(codes, P.chunks, dtab, lo, tab_n, zero_entry,
-                          (const uint64_t*)c->coff.p,
-                          (const uint32_t*)c->upre.p,
-                          (uint16_t*)(out + lay.segs),
-                          (uint32_t*)(out + lay.payload),
-                          (cap - lay.payload) / 4, (float*)(out + lay.unpred),
-                          d_x, P.g, tbl, (uint32_t)max_chunk_words, max_len,
-                          st, (uint32_t*)c->chunk_bits.p, s));
+       kCodeBytes * P.n_codes + (double)payload_bits / 8.0 + 8.0 * n_unpred +
+           46.0 * nch,
+       launch_huff_encode(d_ef, d_c0, gw, gz, 1, nch,
+                          encode_max_words(max_len), max_len > 32,
+                          encode_workgroups(), s));
   /* each chunk's size under zero-word packing (from the encoder, in
    * chunk_bits, free again after the first scan), scanned into the packed
    * offsets and total; upre and chunk_zeros are spent by now */
@@ -247,16 +292,26 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   PROF(PK_PACK, 8.0 * nch,
        launch_chunk_scan((uint32_t*)c->chunk_bits.p,
                          (uint32_t*)c->chunk_zeros.p, nch, pcoff,
-                         (uint32_t*)c->upre.p, totals, (uint64_t*)c->scan.p,
+                         (uint64_t*)c->upre.p, totals, (uint64_t*)c->scan.p,
                          s));
   QOZ_TRY(to_host(c, pin(c, kPinStatus), st, 32, s));
-  QOZ_TRY(to_host(c, pin(c, kPinStatus + 64), totals, 24, s));
+  QOZ_TRY(to_host(c, pin(c, kPinStatus + 64), totals, 48, s));
   QOZ_TRY(sync_checked(s));
-  if (((uint32_t*)pin(c, kPinStatus))[0] & kStOverflow) {
+  /* the encoder's totals (words, symbol-0 bins) follow the packing scan's
+   * three totals */
+  const uint64_t n_words = ((const uint64_t*)pin(c, kPinStatus + 64))[3];
+  if (((const uint64_t*)pin(c, kPinStatus + 64))[4] != n_unpred)
+    return fail(QOZ_EDEVICE, "internal: unpredictable count mismatch");
+  const Layout lay = layout_of(P.n_anchor, n_used, nch, n_unpred, n_words);
+  if (!room || lay.total > cap ||
+      (((uint32_t*)pin(c, kPinStatus))[0] & kStOverflow)) {
     prof_collect(c);
     *out_bytes = lay.total;
     return fail(QOZ_ENOSPACE, "output capacity too small");
   }
+  uint8_t* hs = pin(c, kPinStage);
+  write_header(hs, P, n_unpred, n_used, n_words);
+  QOZ_TRY(to_device(c, out, hs, kHeaderBytes, s));
   /* zero-word packing, when the packed payload and its offsets take at
    * most kPackPercent % of the raw payload's bytes */
   const uint64_t n_packed = ((const uint64_t*)pin(c, kPinStatus + 64))[0];
@@ -267,8 +322,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     QOZ_TRY(ensure(c->ptmp, 4 * n_packed + 4));
     uint32_t* raw = (uint32_t*)(out + lay.payload);
     PROF(PK_PACK, 4.0 * n_words + 4.0 * n_packed + 8.0 * nch,
-         launch_pack_write(raw, (const uint64_t*)c->coff.p, pcoff, nch,
-                           (uint32_t*)c->ptmp.p, s));
+         launch_pack_write(raw, (const uint64_t*)(out + lay.coff), pcoff,
+                           nch, (uint32_t*)c->ptmp.p, s));
     {
       void* dst[2] = {raw, out + lp.pcoff};
       const void* src[2] = {c->ptmp.p, pcoff};

@@ -147,7 +147,7 @@ void prof_collect(qoz_ctx* c) {
 
 static const char* kProfNames[PK_COUNT] = {
     "check_range",     "anchors",         "sweep_comp_level1",
-    "sweep_comp",      "histogram",       "huffman_lengths",
+    "sweep_comp",      "histogram",       "huffman_count",
     "huffman_encode",  "huffman_decode",  "sweep_decomp_level1",
     "sweep_decomp",    "tune_gather",     "tune_alg1",
     "tune_trial",      "ssim",            "reduce",
@@ -201,7 +201,8 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->upos,       &c->hsort,      &c->scan,
                     &c->feat,       &c->mlp_io,     &c->mlp_part,
                     &c->mlp_loss,   &c->hsort_ids,  &c->pcoff,
-                    &c->ptmp,       &c->queue,      &c->lbatch};
+                    &c->ptmp,       &c->queue,      &c->lbatch,
+                    &c->cqueue,     &c->cqueue_up};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   if (c->pinned) (void)hipHostFree(c->pinned);

@@ -38,7 +38,7 @@ constexpr uint32_t kDecWG = 640; /* 10 waves: 80 chunks */
 constexpr uint32_t kChunksPerWG = kDecWG / kSegPerChunk;
 constexpr uint32_t kRegMax = 20; /* longest code sized from registers */
 constexpr uint32_t kMaxChunkWords = kChunk * kMaxCodeLen / 32 + 2;
-constexpr uint32_t kSortedLds = 1024; /* canonical symbols kept in LDS */
+constexpr uint32_t kSortedLds = 4096; /* canonical symbols kept in LDS */
 constexpr uint32_t kRing = 16;        /* payload words per lane in LDS */
 constexpr uint32_t kHalf = kRing / 2;
 constexpr uint32_t kInvalid = 0xffffffffu;
@@ -51,6 +51,7 @@ struct DecShared {
   uint32_t ent[1u << kSymBits]; /* DecTables::ent */
   uint16_t sorted[kSortedLds];
   uint64_t first[kMaxCodeLen + 1];
+  uint64_t lim_half[kMaxCodeLen + 1]; /* DecTables::lim_half */
   uint32_t off[kMaxCodeLen + 1];
   uint32_t cnt[kMaxCodeLen + 1];
 };
@@ -220,7 +221,7 @@ __device__ __forceinline__ uint32_t slow_symbol(
     const uint64_t h = V >> 1;
     len = 0;
     for (uint32_t L = kSymBits + 1; L <= maxlen; ++L)
-      if (h < tabs->lim_half[L]) {
+      if (h < sh.lim_half[L]) {
         len = sh.cnt[L] ? L : 0;
         break;
       }
@@ -264,13 +265,16 @@ __device__ __forceinline__ void decode_wg(
     for (uint32_t i = threadIdx.x; i < sizeof(sh.ent) / 16; i += kDecWG)
       dst[i] = src[i];
   }
+  /* the canonical symbols a valid code can index (k < n_used) */
   const uint32_t n_used = tabs->n_used;
-  for (uint32_t i = threadIdx.x; i < kSortedLds; i += kDecWG)
-    sh.sorted[i] = (uint16_t)(i < n_used ? syms[i] : 0u);
+  const uint32_t n_sorted = n_used < kSortedLds ? n_used : kSortedLds;
+  for (uint32_t i = threadIdx.x; i < n_sorted; i += kDecWG)
+    sh.sorted[i] = (uint16_t)syms[i];
   for (uint32_t i = threadIdx.x; i <= (uint32_t)kMaxCodeLen; i += kDecWG) {
     sh.first[i] = tabs->first[i];
     sh.off[i] = tabs->off[i];
     sh.cnt[i] = tabs->cnt[i];
+    sh.lim_half[i] = tabs->lim_half[i];
   }
   const uint32_t maxlen = tabs->maxlen;
   Limits lim;

@@ -6,13 +6,17 @@
  *                  the zero bin plus a per-lane counter for the zero bin
  *                  itself absorb the concentrated traffic, the rest goes to
  *                  global atomics.
- *  - k_huff_len:   bits and unpredictable count per 4096-bin chunk.
- *  - k_chunk_scan: exclusive scans -> chunk word offsets and unpredictable
- *                  ranks (one workgroup).
- *  - k_huff_encode: one workgroup per chunk packs its codes MSB-first into
- *                  an LDS word buffer (ds_or), then stores the words
- *                  coalesced; lanes holding bin 0 gather their exact value
- *                  into the unpredictable list at their global rank.
+ *  - k_huff_count: code bits and symbol-0 bins per chunk (code lengths
+ *                  in LDS).
+ *  - k_scan_tiles / k_scan_apply: exclusive scans of per-chunk counts (one
+ *                  workgroup per tile, then the tile offsets): the payload
+ *                  offsets and unpredictable ranks of the chunks, and the
+ *                  offsets of the zero-word packed payload.
+ *  - k_huff_encode: workgroups take chunks in a grid stride, code them with
+ *                  the code table in LDS, pack the codes MSB-first into an LDS word
+ *                  buffer (ds_or), store the words coalesced at the
+ *                  chunk's scanned offset, and gather the exact values of
+ *                  bin-0 lanes at their rank.
  * Decoding is in kernels_decode.hip.
  */
 #include "qoz_device.h"
@@ -23,12 +27,14 @@ namespace qoz {
 constexpr uint32_t kHistPerBlock = 1u << 16;
 constexpr uint32_t kHistThreads = 512;
 
-__global__ __launch_bounds__(kHistThreads) void k_hist(
-    const uint16_t* __restrict__ codes, uint64_t n, uint32_t* hist) {
+/* Workgroup blk of a histogram: bins [blk * 65536, +65536) of codes. */
+__device__ __forceinline__ void hist_wg(const uint16_t* __restrict__ codes,
+                                        uint64_t n, uint32_t* hist,
+                                        uint32_t blk) {
   __shared__ uint32_t lh[kHistWin];
   for (uint32_t i = threadIdx.x; i < kHistWin; i += blockDim.x) lh[i] = 0;
   __syncthreads();
-  const uint64_t b0 = (uint64_t)blockIdx.x * kHistPerBlock;
+  const uint64_t b0 = (uint64_t)blk * kHistPerBlock;
   const uint64_t b1 = b0 + kHistPerBlock < n ? b0 + kHistPerBlock : n;
   uint32_t center = 0;
   /* eight 16-bit bins per 16-byte load, four loads in flight per lane */
@@ -65,6 +71,30 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(
   }
 }
 
+__global__ __launch_bounds__(kHistThreads) void k_hist(
+    const uint16_t* __restrict__ codes, uint64_t n, uint32_t* hist) {
+  hist_wg(codes, n, hist, blockIdx.x);
+}
+
+/* The histograms of many fields in one launch. */
+__global__ __launch_bounds__(kHistThreads) void k_hist_q(
+    const HistJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
+  hist_wg(jobs[j].codes, jobs[j].n, jobs[j].hist, blockIdx.x - wg0[j]);
+}
+
+uint32_t hist_job_workgroups(const HistJob& j) {
+  return (uint32_t)((j.n + kHistPerBlock - 1) / kHistPerBlock);
+}
+
+void launch_hist_q(const HistJob* jobs, const uint32_t* wg0, uint32_t n_jobs,
+                   uint32_t total_wg, hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_hist_q, dim3(total_wg), dim3(kHistThreads), 0, s, jobs,
+                     wg0, n_jobs);
+}
+
 void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s) {
   if (!n) return;
@@ -99,94 +129,6 @@ __device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v,
   return r;
 }
 
-/* Bits and symbol-0 count per chunk.  Workgroups are persistent over
- * chunks; code lengths of the symbols [lo, lo + tn) sit in LDS as bytes
- * (from the code table in global memory when the range is wider than the
- * LDS copy).  A lane reads 16 bins as two 16-byte loads. */
-constexpr uint32_t kLenLds = 16384;
-
-__global__ __launch_bounds__(kEncThreads) void k_huff_len(
-    const uint16_t* __restrict__ codes, Chunks ch,
-    const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
-    uint64_t zero_entry, uint32_t* chunk_bits, uint32_t* chunk_zeros) {
-  __shared__ uint8_t lens[kLenLds];
-  const bool in_lds = tn <= kLenLds;
-  if (in_lds)
-    for (uint32_t i = threadIdx.x; i < tn; i += kEncThreads)
-      lens[i] = (uint8_t)(tab[i] & 0xff);
-  __syncthreads();
-  const uint32_t zlen = (uint32_t)(zero_entry & 0xff);
-  const uint64_t n_chunks = ch.count();
-  const uint32_t lane = threadIdx.x & 63u;
-  auto bin_len = [&](uint32_t s, uint32_t& bits, uint32_t& zeros) {
-    if (s == 0) {
-      bits += zlen;
-      ++zeros;
-      return;
-    }
-    const uint32_t o = s - (uint32_t)lo;
-    bits += o < tn ? (in_lds ? lens[o] : (uint32_t)(tab[o] & 0xff)) : 0u;
-  };
-  /* one wave per chunk: lane t takes 8-bin groups t, t + 64, ...; chunks
-   * start on a multiple of 64 bins, so full groups are 16-byte loads */
-  constexpr uint32_t kU = 4;
-  const uint64_t waves = (uint64_t)gridDim.x * (kEncThreads / 64);
-  for (uint64_t c = (uint64_t)blockIdx.x * (kEncThreads / 64) + (threadIdx.x >> 6);
-       c < n_chunks; c += waves) {
-    const uint64_t b = ch.begin(c), e = ch.end(c);
-    uint32_t bits = 0, zeros = 0;
-    for (uint64_t g0 = b + 8 * (uint64_t)lane; g0 < e; g0 += 8 * 64 * kU) {
-      uint4 q[kU];
-#pragma unroll
-      for (uint32_t u = 0; u < kU; ++u) {
-        const uint64_t g = g0 + 8 * 64 * u;
-        q[u] = g + 8 <= e ? *reinterpret_cast<const uint4*>(codes + g)
-                          : make_uint4(0, 0, 0, 0);
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < kU; ++u) {
-        const uint64_t g = g0 + 8 * 64 * u;
-        if (g >= e) break;
-        if (g + 8 <= e) {
-          const uint32_t w[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-#pragma unroll
-          for (uint32_t k = 0; k < 8; ++k)
-            bin_len((w[k >> 1] >> (16 * (k & 1))) & 0xffffu, bits, zeros);
-        } else {
-          for (uint64_t i = g; i < e; ++i) bin_len(codes[i], bits, zeros);
-        }
-      }
-    }
-    bits = wave_sum_u32(bits);
-    zeros = wave_sum_u32(zeros);
-    if (lane == 0) {
-      chunk_bits[c] = bits;
-      chunk_zeros[c] = zeros;
-    }
-  }
-}
-
-void launch_huff_len(const uint16_t* codes, const Chunks& chunks,
-                     const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
-                     uint64_t zero_entry, uint32_t* chunk_bits,
-                     uint32_t* chunk_zeros, hipStream_t s) {
-  const uint64_t nch = chunks.count();
-  if (!nch) return;
-  const uint64_t per = kEncThreads / 64; /* chunks in flight per workgroup */
-  const uint32_t blocks =
-      (nch + per - 1) / per < 2048 ? (uint32_t)((nch + per - 1) / per) : 2048u;
-  hipLaunchKernelGGL(k_huff_len, dim3(blocks), dim3(kEncThreads), 0, s,
-                     codes, chunks, table, tab_lo, tab_n, zero_entry,
-                     chunk_bits, chunk_zeros);
-}
-
-/* Exclusive scans over chunks (words = ceil(bits / 32), unpredictable
- * counts) in two launches: k_scan_tiles sums tiles of 2048 chunks (and
- * finds the largest chunk in words); k_scan_apply adds the sums of the
- * tiles before its own and scans its tile (8 consecutive chunks per lane,
- * lane sums scanned with wave shuffles).  The last tile also writes
- * coff[n], upre[n] and totals[0..2] = words, unpredictables, largest chunk
- * in words. */
 constexpr uint32_t kScanThreads = 256;
 constexpr uint32_t kScanPer = 8;
 constexpr uint32_t kScanTile = kScanThreads * kScanPer;
@@ -250,7 +192,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(
     const uint32_t* __restrict__ bits, const uint32_t* __restrict__ zeros,
     uint64_t n, const uint64_t* __restrict__ tile_w,
     const uint64_t* __restrict__ tile_z, const uint64_t* __restrict__ tile_max,
-    uint64_t* coff, uint32_t* upre, uint64_t* totals) {
+    uint64_t* coff, uint64_t* upre, uint64_t* totals) {
   __shared__ uint64_t ws[kScanThreads / 64], wz[kScanThreads / 64];
   const uint32_t b = blockIdx.x, lane = threadIdx.x & 63u,
                  wave = threadIdx.x >> 6;
@@ -291,7 +233,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(
   for (uint32_t k = 0; k < kScanPer; ++k) {
     if (i0 + k < n) {
       coff[i0 + k] = pw;
-      upre[i0 + k] = (uint32_t)pz;
+      upre[i0 + k] = pz;
     }
     pw += w[k];
     pz += z[k];
@@ -300,7 +242,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(
     uint64_t m = 0;
     for (uint32_t t = 0; t < gridDim.x; ++t) m = m > tile_max[t] ? m : tile_max[t];
     coff[n] = ow + tw;
-    upre[n] = (uint32_t)(oz + tz);
+    upre[n] = oz + tz;
     totals[0] = ow + tw;
     totals[1] = oz + tz;
     totals[2] = m;
@@ -427,7 +369,7 @@ uint64_t chunk_scan_scratch(uint64_t n_chunks) {
 
 void launch_chunk_scan(const uint32_t* chunk_bits,
                        const uint32_t* chunk_zeros, uint64_t n_chunks,
-                       uint64_t* coff, uint32_t* upre, uint64_t* totals,
+                       uint64_t* coff, uint64_t* upre, uint64_t* totals,
                        uint64_t* scratch, hipStream_t s) {
   /* at least one tile, so that the totals are written for no chunks too */
   const uint32_t tiles =
@@ -444,17 +386,11 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
 
 /* words of a chunk: at most 56 bits per bin (the encoder table's limit) */
 constexpr uint32_t kEncMaxWords = kChunk * 56 / 32;
+/* code table entries kept in LDS: (code << 6) | length for codes of at
+ * most 26 bits, kEncFar for a longer code (read from the global table) */
+constexpr uint32_t kEncTab = 4096;
+constexpr uint32_t kEncFar = 0xffffffffu;
 
-/* Segment-major packing: segment j holds the chunk's bins j, j + 8, ....
- * The chunk's bins are staged in LDS by segment (cbin[j * 512 + k] = bin
- * 8k + j), lane t packs bins k in [16 (t mod 32), +16) of segment t / 32,
- * so the thread-order scan of bit counts is the payload order.  A lane
- * builds its bits in a register and writes whole words it alone covers
- * with plain LDS stores, the (at most two) words it shares with its
- * neighbours with atomic ORs.  Unpredictable values are gathered in bin
- * order: the staging lanes count the zero bins of their two 8-bin groups
- * (rounds 0 and 1, packed in one scan word) and rank them in bin order.
- * The word buffer is dynamic LDS sized for the largest chunk. */
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
                                                     uint32_t* total) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
@@ -476,186 +412,378 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
   return pre + x - v;
 }
 
-/* at least 6 waves per SIMD (80 VGPRs): one register more costs a sixth
- * of the occupancy and about 15 % of the kernel's time */
+/* Code bits and symbol-0 bins of every chunk, the counts the chunk scan
+ * turns into payload offsets and unpredictable ranks before encoding.  A
+ * workgroup takes kCountChunks consecutive chunks of one field (the
+ * field's workgroups start at wg0[f]) with the field's code lengths in LDS
+ * (from the global table beyond kCountLens symbols); a wave counts one
+ * chunk, each lane 8 groups of 8 bins read as 16-byte loads (chunks start
+ * on a multiple of 64 bins).  Counts go to bits[chunk0[f] + c] and
+ * zeros[chunk0[f] + c]. */
+constexpr uint32_t kCountThreads = 256;
+constexpr uint32_t kCountChunks = 8;
+constexpr uint32_t kCountLens = 16384;
+
+__global__ __launch_bounds__(kCountThreads) void k_huff_count(
+    const EncField* __restrict__ fields, const uint64_t* __restrict__ chunk0,
+    const uint32_t* __restrict__ wg0, uint32_t nf,
+    uint32_t* __restrict__ bits_out, uint32_t* __restrict__ zeros_out) {
+  constexpr uint32_t kGroups = kChunk / (8 * 64); /* 8 per lane */
+  __shared__ uint8_t lens[kCountLens];
+  const uint32_t f = find_job(wg0, nf, blockIdx.x);
+  const EncField& F = fields[f];
+  const uint32_t tn = F.tn;
+  const uint32_t tl = tn < kCountLens ? tn : kCountLens;
+  for (uint32_t i = threadIdx.x; i < tl; i += kCountThreads)
+    lens[i] = (uint8_t)(F.tab[i] & 0xff);
+  __syncthreads();
+  const int32_t lo = F.lo;
+  const uint32_t zlen = (uint32_t)(F.zero_entry & 0xff);
+  const uint64_t c0 = (uint64_t)(blockIdx.x - wg0[f]) * kCountChunks;
+  const uint64_t c1 = c0 + kCountChunks < F.nch ? c0 + kCountChunks : F.nch;
+  const uint32_t lane = threadIdx.x & 63u;
+  auto add = [&](uint32_t sym, uint32_t& bits, uint32_t& zeros) {
+    const uint32_t o = sym - (uint32_t)lo;
+    const uint32_t l = sym == 0 ? zlen
+                       : o < tl ? (uint32_t)lens[o]
+                       : o < tn ? (uint32_t)(F.tab[o] & 0xff)
+                                : 0u;
+    bits += l;
+    zeros += sym == 0 ? 1u : 0u;
+  };
+  for (uint64_t c = c0 + (threadIdx.x >> 6); c < c1;
+       c += kCountThreads / 64) {
+    const uint64_t b = F.ch.begin(c);
+    const uint32_t n = (uint32_t)(F.ch.end(c) - b);
+    uint4 q[kGroups];
+#pragma unroll
+    for (uint32_t u = 0; u < kGroups; ++u) {
+      const uint32_t m = lane + 64 * u;
+      q[u] = 8 * m + 8 <= n
+                 ? *reinterpret_cast<const uint4*>(F.codes + b + 8 * m)
+                 : make_uint4(0, 0, 0, 0);
+    }
+    uint32_t bits = 0, zeros = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kGroups; ++u) {
+      const uint32_t m = lane + 64 * u;
+      if (8 * m + 8 <= n) {
+        const uint32_t w[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k)
+          add((w[k >> 1] >> (16 * (k & 1))) & 0xffffu, bits, zeros);
+      } else {
+        for (uint32_t i = 8 * m; i < n; ++i) add(F.codes[b + i], bits, zeros);
+      }
+    }
+    bits = wave_sum_u32(bits);
+    zeros = wave_sum_u32(zeros);
+    if (lane == 0) {
+      bits_out[chunk0[f] + c] = bits;
+      zeros_out[chunk0[f] + c] = zeros;
+    }
+  }
+}
+
+uint32_t count_workgroups(uint64_t n_chunks) {
+  return (uint32_t)((n_chunks + kCountChunks - 1) / kCountChunks);
+}
+
+void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
+                       const uint32_t* wg0, uint32_t nf, uint32_t total_wg,
+                       uint32_t* bits, uint32_t* zeros, hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_huff_count, dim3(total_wg), dim3(kCountThreads), 0, s,
+                     fields, chunk0, wg0, nf, bits, zeros);
+}
+
+/* Encoding of the chunks of one or more fields, after k_huff_count and the
+ * chunk scan: gw and gz are the exclusive prefixes of the chunks' payload
+ * words and symbol-0 bins over the global chunk order (a field's offsets
+ * are differences of them).  Workgroup w codes global chunks (field after
+ * field) w, w + G, w + 2G, ... for a grid of G, and loads the next one's
+ * bins while the current one is coded.  Per chunk: segment-major
+ * staging of the bins in LDS (segment j holds the chunk's bins j, j + 8,
+ * ...), lane t codes bins k in [16 (t mod 32), +16) of segment t / 32 with
+ * the field's code table in LDS (reloaded when the field changes), block
+ * scans of the bit counts (thread order = payload order) and of the
+ * symbol-0 counts, codes ORed into a zeroed LDS word buffer without
+ * branches, unpredictable values gathered in bin order at their ranks, the
+ * chunk's size under zero-word packing counted (and added to the field's
+ * packed total), and the words stored.  The chunk offsets, unpredictable
+ * ranks and segment lengths go straight to their stream sections; a
+ * field's last chunk also writes its totals (payload words, symbol-0
+ * bins).  No workgroup waits for another. */
 template <bool kLong> /* kLong: some code is longer than 32 bits */
-__global__ __launch_bounds__(kEncThreads, 6) void k_huff_encode(
-    const uint16_t* __restrict__ codes, Chunks ch,
-    const uint64_t* __restrict__ tab, int32_t lo, uint32_t tn,
-    uint64_t zero_entry, const uint64_t* __restrict__ coff,
-    const uint32_t* __restrict__ upre, uint16_t* __restrict__ segs,
-    uint32_t* payload, uint64_t cap_words,
-    float* unpred, const float* __restrict__ x, Geo g, SweepTable st,
-    uint32_t* status, uint32_t* __restrict__ pack_bits) {
+__global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
+    const EncField* __restrict__ fields, const uint64_t* __restrict__ chunk0,
+    const uint64_t* __restrict__ gw, const uint64_t* __restrict__ gz,
+    uint32_t nf, uint64_t n_total, uint32_t max_words) {
   constexpr uint32_t kRounds = kChunk / (8 * kEncThreads); /* 2 */
   constexpr uint32_t kSegBins = kChunk / kSegPerChunk;      /* 512 */
-  extern __shared__ uint32_t words[];
-  __shared__ __align__(16) uint16_t cbin[kChunk];
-  __shared__ uint32_t ws[2][kEncThreads / 64];
-  __shared__ uint32_t seg_end[kSegPerChunk];
-  const uint32_t c = blockIdx.x;
-  const uint64_t base = ch.begin(c);
-  const uint32_t nsym = (uint32_t)(ch.end(c) - base);
-  const uint64_t w0 = coff[c];
-  const uint32_t nw = (uint32_t)(coff[c + 1] - w0);
-  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) words[i] = 0;
-  /* staging: lane t takes the 8-bin groups m = t + 256 r; the full
-   * groups' loads of both rounds are issued before either is used */
-  uint32_t v[kRounds][8];
-  uint32_t zpack = 0;
-  uint4 qr[kRounds];
-#pragma unroll
-  for (uint32_t r = 0; r < kRounds; ++r) {
-    const uint32_t m = threadIdx.x + r * kEncThreads;
-    qr[r] = 8 * m + 8 <= nsym
-                ? *reinterpret_cast<const uint4*>(codes + base + 8 * m)
-                : make_uint4(0, 0, 0, 0);
-  }
-#pragma unroll
-  for (uint32_t r = 0; r < kRounds; ++r) {
-    const uint32_t m = threadIdx.x + r * kEncThreads;
-    if (8 * m + 8 <= nsym) {
-      const uint4 q = qr[r];
-      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) v[r][i] = (w[i / 2] >> (16 * (i & 1))) & 0xffffu;
-    } else {
-#pragma unroll
-      for (uint32_t i = 0; i < 8; ++i)
-        v[r][i] = 8 * m + i < nsym ? codes[base + 8 * m + i] : 1u;
-    }
-    uint32_t z = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < 8; ++i) {
-      cbin[i * kSegBins + m] = (uint16_t)v[r][i];
-      z += v[r][i] == 0 ? 1u : 0u;
-    }
-    zpack |= z << (16 * r);
-  }
-  __syncthreads();
   constexpr uint32_t kLanesPerSeg = kSeg / kEncPerThread;
   static_assert(kLanesPerSeg * kEncPerThread == kSeg, "segment lanes");
   static_assert(kRounds == 2 && kSegBins == kSeg, "chunk layout");
-  const uint32_t j = threadIdx.x / kLanesPerSeg;
-  const uint32_t k0 = (threadIdx.x % kLanesPerSeg) * kEncPerThread;
-  uint64_t ent[kEncPerThread];
-  uint32_t bits = 0;
-  {
-    const uint4* cb = reinterpret_cast<const uint4*>(cbin + j * kSegBins + k0);
-    const uint4 qa = cb[0], qb = cb[1];
-    const uint32_t w[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
-#pragma unroll
-    for (uint32_t k = 0; k < kEncPerThread; ++k) {
-      const uint32_t b = (k0 + k) * kSegPerChunk + j; /* bin in the chunk */
-      const uint32_t sym = (w[k / 2] >> (16 * (k & 1))) & 0xffffu;
-      ent[k] = b < nsym ? code_entry(tab, lo, tn, zero_entry, (int32_t)sym) : 0;
-      bits += (uint32_t)(ent[k] & 0xff);
-    }
-  }
-  uint32_t tot_bits, tot_z;
-  const uint32_t pos0 = block_excl_scan(bits, ws[0], &tot_bits);
-  const uint32_t zex = block_excl_scan(zpack, ws[1], &tot_z);
-  /* payload bits of segments 0..6: the last lane of each segment knows
-   * where the segment ends */
-  if (threadIdx.x % kLanesPerSeg == kLanesPerSeg - 1) seg_end[j] = pos0 + bits;
-  __syncthreads();
-  if (threadIdx.x < kSegPerChunk - 1)
-    segs[(uint64_t)c * (kSegPerChunk - 1) + threadIdx.x] = (uint16_t)(
-        seg_end[threadIdx.x] - (threadIdx.x ? seg_end[threadIdx.x - 1] : 0u));
-  /* This lane's bits [pos0, pos0 + bits), MSB-first.  acc holds the bits
-   * not yet written in its low nacc (< 32) bits (above them: bits already
-   * written, shifted out as codes come in); every complete word is ORed
-   * into the zeroed chunk words (a lane's first and last words are shared
-   * with its neighbours), and a code that completes no word ORs 0 into
-   * the current word, so the stores need no branch. */
-  {
-    uint64_t acc = 0;
-    uint32_t nacc = pos0 & 31u, wi = pos0 >> 5;
-    auto put = [&](uint32_t code, uint32_t len) { /* len <= 32 */
-      acc = (acc << len) | code;
-      nacc += len;
-      const bool full = nacc >= 32;
-      nacc -= full ? 32u : 0u;
-      atomicOr(&words[wi], full ? (uint32_t)(acc >> nacc) : 0u);
-      wi += full ? 1u : 0u;
-    };
-#pragma unroll
-    for (uint32_t k = 0; k < kEncPerThread; ++k) {
-      const uint32_t len = (uint32_t)(ent[k] & 0xff);
-      const uint64_t code = ent[k] >> 8;
-      if (kLong && len > 32) {
-        put((uint32_t)(code >> 32), len - 32);
-        put((uint32_t)code, 32);
-      } else {
-        put((uint32_t)code, len);
-      }
-    }
-    if (nacc) atomicOr(&words[wi], (uint32_t)(acc << (32 - nacc)));
-  }
-  uint32_t zr[kRounds] = {upre[c] + (zex & 0xffffu),
-                          upre[c] + (tot_z & 0xffffu) + (zex >> 16)};
-#pragma unroll
-  for (uint32_t r = 0; r < kRounds; ++r) {
-    const uint32_t m = threadIdx.x + r * kEncThreads;
-#pragma unroll
-    for (uint32_t i = 0; i < 8; ++i)
-      if (v[r][i] == 0) {
-        unpred[zr[r]] = x[point_of(st, g, base + 8 * m + i)];
-        ++zr[r];
-      }
-  }
+  extern __shared__ uint32_t words[];
+  __shared__ __align__(16) uint16_t cbin[kChunk];
+  __shared__ uint32_t tabl[kEncTab];
+  __shared__ uint32_t ws[2][kEncThreads / 64];
+  __shared__ uint32_t seg_end[kSegPerChunk];
   __shared__ uint32_t nz_words;
-  if (threadIdx.x == 0) nz_words = 0;
-  __syncthreads();
-  /* the chunk's size under zero-word packing (bitmap + nonzero words
-   * when shorter, else raw), scanned afterwards for the packing decision
-   * and the packed offsets; counted in LDS before the stores, so that no
-   * barrier waits on them */
-  uint32_t nz = 0;
-  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) nz += words[i] != 0u;
-  for (uint32_t o = 32; o > 0; o >>= 1) nz += __shfl_xor(nz, o, 64);
-  if ((threadIdx.x & 63u) == 0) atomicAdd(&nz_words, nz);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t nbm = (nw + 31) / 32;
-    pack_bits[c] = 32 * (nbm + nz_words < nw ? nbm + nz_words : nw);
+  const uint32_t tid = threadIdx.x;
+  /* field of global chunk c2: the number of fields f with chunk0[f] <= c2,
+   * less one (64 entries per ballot; every wave finds it on its own) */
+  auto field_of = [&](uint64_t c2) -> uint32_t {
+    const uint32_t lane = tid & 63u;
+    uint32_t cnt = 0;
+    for (uint32_t b = 0; b < nf; b += 64) {
+      const uint32_t i = b + lane;
+      cnt += (uint32_t)__popcll(__ballot(i < nf && chunk0[i] <= c2));
+    }
+    return cnt - 1;
+  };
+  for (uint32_t i = tid; i < max_words + 1; i += kEncThreads) words[i] = 0;
+  /* chunks blockIdx.x, + gridDim.x, ... (no shared counter: every chunk's
+   * offsets are known, and a counter that all workgroups hit serializes) */
+  const uint64_t stride = gridDim.x;
+  uint64_t cn = blockIdx.x;
+  uint32_t fn = cn < n_total ? field_of(cn) : 0u;
+  /* the field's packed words so far (thread 0), added to its total when
+   * the field changes and at the end: one atomic per field and workgroup */
+  uint32_t pk_field = ~0u;
+  uint64_t pk_acc = 0;
+  /* this lane's two 8-bin groups of a chunk: m = t + 256 r */
+  uint4 qr[kRounds];
+  auto load_bins = [&](uint64_t c2, uint32_t f2) {
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+      qr[r] = make_uint4(0, 0, 0, 0);
+      if (c2 < n_total) {
+        const EncField& F2 = fields[f2];
+        const uint64_t cl = c2 - chunk0[f2];
+        const uint64_t b2 = F2.ch.begin(cl);
+        const uint32_t n2 = (uint32_t)(F2.ch.end(cl) - b2);
+        const uint32_t m = tid + r * kEncThreads;
+        if (8 * m + 8 <= n2)
+          qr[r] = *reinterpret_cast<const uint4*>(F2.codes + b2 + 8 * m);
+      }
+    }
+  };
+  load_bins(cn, fn);
+  uint32_t dirty = 0;      /* words of the previous chunk (to zero again) */
+  uint32_t loaded = ~0u;   /* field whose code table is in LDS */
+  uint32_t tw = 0, tn = 0; /* its table window and range */
+  int32_t lo = 0;
+  uint64_t zero_entry = 0;
+  while (cn < n_total) {
+    const uint32_t f = fn;
+    const EncField& F = fields[f];
+    const uint64_t c = cn - chunk0[f]; /* chunk within the field */
+    const uint64_t base = F.ch.begin(c);
+    const uint32_t nsym = (uint32_t)(F.ch.end(c) - base);
+    const uint64_t cur = cn;
+    /* the next chunk; its bins load while this one is coded */
+    cn = cur + stride;
+    fn = cn < n_total ? field_of(cn) : 0u;
+    if (f != loaded) { /* the field's code table (after the last barrier) */
+      tn = F.tn;
+      tw = tn < kEncTab ? tn : kEncTab;
+      lo = F.lo;
+      zero_entry = F.zero_entry;
+      for (uint32_t i = tid; i < tw; i += kEncThreads) {
+        const uint64_t e = F.tab[i];
+        const uint32_t len = (uint32_t)(e & 0xff);
+        tabl[i] = len <= 26 ? (uint32_t)((e >> 8) << 6) | len : kEncFar;
+      }
+      loaded = f;
+    }
+    uint32_t v[kRounds][8];
+    uint32_t zpack = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+      const uint32_t m = tid + r * kEncThreads;
+      if (8 * m + 8 <= nsym) {
+        const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i)
+          v[r][i] = (w[i / 2] >> (16 * (i & 1))) & 0xffffu;
+      } else {
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i)
+          v[r][i] = 8 * m + i < nsym ? F.codes[base + 8 * m + i] : 1u;
+      }
+      uint32_t z = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i) {
+        cbin[i * kSegBins + m] = (uint16_t)v[r][i];
+        z += v[r][i] == 0 ? 1u : 0u;
+      }
+      zpack |= z << (16 * r);
+    }
+    for (uint32_t i = tid; i < dirty; i += kEncThreads) words[i] = 0;
+    __syncthreads();
+    load_bins(cn, fn);
+    const uint32_t j = tid / kLanesPerSeg;
+    const uint32_t k0 = (tid % kLanesPerSeg) * kEncPerThread;
+    uint64_t ent[kEncPerThread];
+    uint32_t bits = 0;
+    {
+      const uint4* cb =
+          reinterpret_cast<const uint4*>(cbin + j * kSegBins + k0);
+      const uint4 qa = cb[0], qb = cb[1];
+      const uint32_t w[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+      for (uint32_t k = 0; k < kEncPerThread; ++k) {
+        const uint32_t b = (k0 + k) * kSegPerChunk + j; /* bin in the chunk */
+        const int32_t sym = (int32_t)((w[k / 2] >> (16 * (k & 1))) & 0xffffu);
+        uint64_t e = 0;
+        if (b < nsym) {
+          const uint32_t o = (uint32_t)(sym - lo);
+          if (sym == 0) {
+            e = zero_entry;
+          } else if (o < tw) {
+            const uint32_t t = tabl[o];
+            e = t != kEncFar ? ((uint64_t)(t >> 6) << 8) | (t & 63u)
+                             : F.tab[o];
+          } else if (o < tn) {
+            e = F.tab[o];
+          }
+        }
+        ent[k] = e;
+        bits += (uint32_t)(e & 0xff);
+      }
+    }
+    uint32_t tot_bits, tot_z;
+    const uint32_t pos0 = block_excl_scan(bits, ws[0], &tot_bits);
+    const uint32_t zex = block_excl_scan(zpack, ws[1], &tot_z);
+    const uint32_t nw = (tot_bits + 31) / 32;
+    const uint32_t zc = (tot_z & 0xffffu) + (tot_z >> 16);
+    if (tid % kLanesPerSeg == kLanesPerSeg - 1) seg_end[j] = pos0 + bits;
+    /* the chunk's word and unpredictable offsets within its field */
+    const uint64_t w0 = gw[cur] - gw[chunk0[f]];
+    const uint64_t u0 = gz[cur] - gz[chunk0[f]];
+    if (tid == 0) {
+      F.coff[c] = w0;
+      F.upre[c] = (uint32_t)u0;
+      if (c + 1 == F.nch) {
+        F.coff[F.nch] = w0 + nw;
+        F.upre[F.nch] = (uint32_t)(u0 + zc);
+        F.totals[0] = w0 + nw;
+        F.totals[1] = u0 + zc;
+      }
+      nz_words = 0;
+    }
+    __syncthreads();
+    if (tid < kSegPerChunk - 1)
+      F.segs[c * (kSegPerChunk - 1) + tid] =
+          (uint16_t)(seg_end[tid] - (tid ? seg_end[tid - 1] : 0u));
+    /* This lane's bits [pos0, pos0 + bits), MSB-first: acc holds the bits
+     * not yet written in its low nacc (< 32) bits; every complete word is
+     * ORed into the zeroed chunk words (a lane's first and last words are
+     * shared with its neighbours), a code that completes no word ORs 0
+     * into the current word, so the stores need no branch. */
+    {
+      uint64_t acc = 0;
+      uint32_t nacc = pos0 & 31u, wi = pos0 >> 5;
+      auto put = [&](uint32_t code, uint32_t len) { /* len <= 32 */
+        acc = (acc << len) | code;
+        nacc += len;
+        const bool full = nacc >= 32;
+        nacc -= full ? 32u : 0u;
+        atomicOr(&words[wi], full ? (uint32_t)(acc >> nacc) : 0u);
+        wi += full ? 1u : 0u;
+      };
+#pragma unroll
+      for (uint32_t k = 0; k < kEncPerThread; ++k) {
+        const uint32_t len = (uint32_t)(ent[k] & 0xff);
+        const uint64_t code = ent[k] >> 8;
+        if (kLong && len > 32) {
+          put((uint32_t)(code >> 32), len - 32);
+          put((uint32_t)code, 32);
+        } else {
+          put((uint32_t)code, len);
+        }
+      }
+      if (nacc) atomicOr(&words[wi], (uint32_t)(acc << (32 - nacc)));
+    }
+    uint64_t zr[kRounds] = {u0 + (zex & 0xffffu),
+                            u0 + (tot_z & 0xffffu) + (zex >> 16)};
+#pragma unroll
+    for (uint32_t r = 0; r < kRounds; ++r) {
+      const uint32_t m = tid + r * kEncThreads;
+#pragma unroll
+      for (uint32_t i = 0; i < 8; ++i)
+        if (v[r][i] == 0) {
+          F.unpred[zr[r]] = F.x[point_of(F.st, F.g, base + 8 * m + i)];
+          ++zr[r];
+        }
+    }
+    __syncthreads();
+    /* the chunk's size under zero-word packing (bitmap + nonzero words
+     * when shorter, else raw), scanned afterwards for the packing decision
+     * and the packed offsets */
+    uint32_t nzc = 0;
+    for (uint32_t i = tid; i < nw; i += kEncThreads) nzc += words[i] != 0u;
+    for (uint32_t o = 32; o > 0; o >>= 1) nzc += __shfl_xor(nzc, o, 64);
+    if ((tid & 63u) == 0) atomicAdd(&nz_words, nzc);
+    bool over = false;
+    for (uint32_t i = tid; i < nw; i += kEncThreads) {
+      if (w0 + i < F.cap_words)
+        F.payload[w0 + i] = words[i];
+      else
+        over = true;
+    }
+    if (over) atomicOr(F.status, kStOverflow);
+    __syncthreads();
+    if (tid == 0) {
+      const uint32_t nbm = (nw + 31) / 32;
+      const uint32_t pw = nbm + nz_words < nw ? nbm + nz_words : nw;
+      F.pack_bits[c] = 32 * pw;
+      if (f != pk_field) {
+        if (pk_field != ~0u)
+          atomicAdd((unsigned long long*)&fields[pk_field].totals[2],
+                    (unsigned long long)pk_acc);
+        pk_field = f;
+        pk_acc = 0;
+      }
+      pk_acc += pw;
+    }
+    dirty = nw + 1;
   }
-  bool over = false;
-  for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
-    if (w0 + i < cap_words)
-      payload[w0 + i] = words[i];
-    else
-      over = true;
-  }
-  if (over) atomicOr(status, kStOverflow);
+  if (tid == 0 && pk_field != ~0u)
+    atomicAdd((unsigned long long*)&fields[pk_field].totals[2],
+              (unsigned long long)pk_acc);
 }
 
-void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
-                        const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
-                        uint64_t zero_entry, const uint64_t* coff,
-                        const uint32_t* upre, uint16_t* segs,
-                        uint32_t* payload,
-                        uint64_t payload_cap_words, float* unpred,
-                        const float* x, const Geo& g, const SweepTable& st,
-                        uint32_t max_chunk_words, uint32_t max_len,
-                        uint32_t* status, uint32_t* pack_bits, hipStream_t s) {
-  const uint64_t nch = chunks.count();
-  if (!nch) return;
-  /* every chunk's word count is at most the largest one, which is at
-   * most kEncMaxWords (codes of at most 56 bits) */
-  const uint32_t mw = max_chunk_words < kEncMaxWords ? max_chunk_words
-                                                     : kEncMaxWords;
-  const size_t lds = 4 * ((size_t)mw + 1);
-  if (max_len > 32)
-    hipLaunchKernelGGL(k_huff_encode<true>, dim3((uint32_t)nch),
-                       dim3(kEncThreads), lds, s, codes, chunks, table, tab_lo,
-                       tab_n, zero_entry, coff, upre, segs, payload,
-                       payload_cap_words, unpred, x, g, st, status, pack_bits);
+uint32_t encode_workgroups() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return 4u * (uint32_t)cus;
+}
+
+uint32_t encode_max_words(uint32_t max_len) {
+  const uint64_t w = ((uint64_t)kChunk * max_len + 31) / 32;
+  return (uint32_t)(w < kEncMaxWords ? w : kEncMaxWords);
+}
+
+void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
+                        const uint64_t* gw, const uint64_t* gz, uint32_t nf,
+                        uint64_t n_chunks, uint32_t max_words,
+                        bool long_codes, uint32_t n_wg, hipStream_t s) {
+  if (!n_chunks || !nf) return;
+  const size_t lds = 4 * ((size_t)max_words + 1);
+  const uint32_t grid = (uint32_t)(n_chunks < n_wg ? n_chunks : n_wg);
+  if (long_codes)
+    hipLaunchKernelGGL(k_huff_encode<true>, dim3(grid), dim3(kEncThreads), lds,
+                       s, fields, chunk0, gw, gz, nf, n_chunks, max_words);
   else
-    hipLaunchKernelGGL(k_huff_encode<false>, dim3((uint32_t)nch),
-                       dim3(kEncThreads), lds, s, codes, chunks, table, tab_lo,
-                       tab_n, zero_entry, coff, upre, segs, payload,
-                       payload_cap_words, unpred, x, g, st, status, pack_bits);
+    hipLaunchKernelGGL(k_huff_encode<false>, dim3(grid), dim3(kEncThreads),
+                       lds, s, fields, chunk0, gw, gz, nf, n_chunks,
+                       max_words);
 }
 
 }  // namespace qoz

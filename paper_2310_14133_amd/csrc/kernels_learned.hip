@@ -289,6 +289,135 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
         1.0 + sqrt((double)__uint_as_float(rpre[tid - 20])) / e);
 }
 
+/* The same features of one 33 x 33 block of a 2D field (row stride
+ * g.st[1]; origins hold (0, row, column) per block): residuals along the two
+ * dimensions, g2 = dx*dx + dy*dy over the 32 x 32 points with both
+ * coordinates below 32, whose deciles come from a bitonic sort of the 1024
+ * values in LDS.  One 256-lane workgroup per block. */
+namespace {
+constexpr uint32_t kF2Threads = 256;
+constexpr uint32_t kB2Pts = kB1 * kB1; /* 1089 */
+constexpr uint32_t kNG2 = 32 * 32;     /* gradient points */
+}  // namespace
+
+__global__ __launch_bounds__(kF2Threads) void k_block_features_2d(
+    const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
+    double e, float* __restrict__ feat, float* __restrict__ aux) {
+  __shared__ float blk[kB2Pts];
+  __shared__ uint32_t keys[kNG2];
+  __shared__ double red[4][kF2Threads / 64];
+  __shared__ float mred[3][kF2Threads / 64];
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t* o = origins + 3 * blockIdx.x;
+  const uint64_t base = (uint64_t)o[1] * g.st[1] + o[2];
+  float* out = feat + 32 * (uint64_t)blockIdx.x;
+  for (uint32_t t = tid; t < kB2Pts; t += kF2Threads) {
+    const uint32_t i = t / kB1, j = t - i * kB1;
+    blk[t] = x[base + (uint64_t)i * g.st[1] + j];
+  }
+  __syncthreads();
+  /* block range and finiteness */
+  {
+    float lo = blk[tid], hi = blk[tid];
+    uint32_t bad = 0;
+    for (uint32_t t = tid; t < kB2Pts; t += kF2Threads) {
+      const float v = blk[t];
+      lo = fminf(lo, v);
+      hi = fmaxf(hi, v);
+      bad |= (__float_as_uint(v) & 0x7f800000u) == 0x7f800000u;
+    }
+    for (int sh = 32; sh > 0; sh >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, sh, 64));
+      hi = fmaxf(hi, __shfl_xor(hi, sh, 64));
+      bad |= __shfl_xor(bad, sh, 64);
+    }
+    if (lane == 0) {
+      mred[0][wv] = lo;
+      mred[1][wv] = hi;
+      mred[2][wv] = bad ? 1.0f : 0.0f;
+    }
+  }
+  /* level-wise residual sums: lin |r|, lin r^2, cubic |r|, cubic r^2 */
+  for (uint32_t l = 1; l <= 5; ++l) {
+    const uint32_t h = 1u << (l - 1), m = 32 / h + 1, nodd = 16 / h;
+    const uint32_t per_dim = nodd * m;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t t = tid; t < 2 * per_dim; t += kF2Threads) {
+      const uint32_t k = t / per_dim, q = t - k * per_dim;
+      const uint32_t u = q / m, v = q - u * m;
+      const uint32_t ck = (2 * u + 1) * h; /* odd multiple along k */
+      const uint32_t sk = (k == 0 ? kB1 : 1u) * h;
+      const uint32_t p = k == 0 ? ck * kB1 + v * h : v * h * kB1 + ck;
+      const float b = blk[p - sk], cc = blk[p + sk], xv = blk[p];
+      const float lin = (b + cc) * 0.5f;
+      float cub = lin;
+      if (ck >= 3 * h && ck + 3 * h <= 32) {
+        const float a = blk[p - 3 * sk], d = blk[p + 3 * sk];
+        cub = ((b + cc) * 9.0f - (a + d)) * 0.0625f;
+      }
+      const double rl = (double)(xv - lin), rc = (double)(xv - cub);
+      acc[0] += fabs(rl);
+      acc[1] += rl * rl;
+      acc[2] += fabs(rc);
+      acc[3] += rc * rc;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double t = acc[i];
+      for (int sh = 32; sh > 0; sh >>= 1) t += __shfl_xor(t, sh, 64);
+      if (lane == 0) red[i][wv] = t;
+    }
+    __syncthreads();
+    if (tid < 4) {
+      double t = 0.0;
+      for (uint32_t w = 0; w < kF2Threads / 64; ++w) t += red[tid][w];
+      const double n = 2.0 * per_dim;
+      out[4 * (l - 1) + tid] =
+          (float)log2(1.0 + ((tid & 1) ? sqrt(t / n) : t / n) / e);
+    }
+    __syncthreads();
+  }
+  /* squared gradients (non-negative floats order as their bits) */
+  for (uint32_t t = tid; t < kNG2; t += kF2Threads) {
+    const uint32_t p = (t >> 5) * kB1 + (t & 31);
+    const float v = blk[p];
+    const float dx = blk[p + kB1] - v, dy = blk[p + 1] - v;
+    keys[t] = __float_as_uint(dx * dx + dy * dy);
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= kNG2; k <<= 1)
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = tid; i < kNG2; i += kF2Threads) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint32_t a = keys[i], b = keys[ixj];
+          if ((a > b) == ((i & k) == 0)) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  if (tid < 10) {
+    const uint32_t r = ((tid + 1) * kNG2 + 9) / 10 - 1;
+    out[20 + tid] =
+        (float)log2(1.0 + sqrt((double)__uint_as_float(keys[r])) / e);
+  }
+  if (tid == 0) {
+    float l2 = mred[0][0], h2 = mred[1][0], b2 = mred[2][0];
+    for (uint32_t w = 1; w < kF2Threads / 64; ++w) {
+      l2 = fminf(l2, mred[0][w]);
+      h2 = fmaxf(h2, mred[1][w]);
+      b2 = fmaxf(b2, mred[2][w]);
+    }
+    out[30] = (float)log2(1.0 + ((double)h2 - (double)l2) / e);
+    aux[3 * (uint64_t)blockIdx.x + 0] = l2;
+    aux[3 * (uint64_t)blockIdx.x + 1] = h2;
+    aux[3 * (uint64_t)blockIdx.x + 2] = b2;
+  }
+}
+
 /* Range over all blocks into every row's feature 31, the mean of each
  * feature over the blocks into out[32], and the non-finite flag into
  * status[0]. */
@@ -338,8 +467,12 @@ void launch_block_features(const float* x, const Geo& g,
                            const uint32_t* origins, uint32_t nb, double e,
                            float* feat, float* aux, float* mean,
                            uint32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_block_features, dim3(nb, 3), dim3(kFeatThreads),
-                     block_features_lds(), s, x, g, origins, e, feat, aux);
+  if (g.n[0] == 1) /* a 2D field: its geometry has a single plane */
+    hipLaunchKernelGGL(k_block_features_2d, dim3(nb), dim3(kF2Threads), 0, s,
+                       x, g, origins, e, feat, aux);
+  else
+    hipLaunchKernelGGL(k_block_features, dim3(nb, 3), dim3(kFeatThreads),
+                       block_features_lds(), s, x, g, origins, e, feat, aux);
   hipLaunchKernelGGL(k_feat_pool, dim3(1), dim3(64), 0, s, feat,
                      (const float*)aux, nb, e, mean, status);
 }

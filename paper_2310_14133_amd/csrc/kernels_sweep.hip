@@ -305,21 +305,20 @@ __device__ __forceinline__ SweepPoint sweep_point(const Geo& g,
   return sp;
 }
 
+/* Workgroup (bx, by) of a sweep's gx x gy grid of ty-row tiles; this lane
+ * is target tx of row tyi of the tile. */
 template <bool WRITE_W>
-__global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_comp(
-    Geo g, Sweep s, const float* __restrict__ x, float* W,
-    uint16_t* __restrict__ codes, uint32_t* status) {
-  const uint32_t lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y,
-                                gridDim.x * gridDim.y);
-  const uint32_t bx = lb % gridDim.x, by = lb / gridDim.x;
-  const uint32_t i2 = bx * kSweepTX + threadIdx.x;
+__device__ __forceinline__ void sweep_comp_wg(
+    const Geo& g, const Sweep& s, const float* __restrict__ x, float* W,
+    uint16_t* __restrict__ codes, uint32_t* status, uint32_t bx, uint32_t by,
+    uint32_t gy, uint32_t tx, uint32_t tyi, uint32_t ty) {
+  const uint32_t i2 = bx * kSweepTX + tx;
   if (i2 >= s.cnt[2]) return;
   const uint32_t rows = s.cnt[0] * s.cnt[1];
   const uint32_t sk = g.st[s.k];
   const uint32_t nk = g.n[s.k];
   bool bad = false;
-  const uint32_t ty = blockDim.y;
-  for (uint32_t r = by * ty + threadIdx.y; r < rows; r += gridDim.y * ty) {
+  for (uint32_t r = by * ty + tyi; r < rows; r += gy * ty) {
     SweepPoint sp = sweep_point(g, s, r, i2);
     float pred = predict_at(W, sp.idx, sp.pk, sk, nk, s.h, s.cubic);
     float xv = x[sp.idx];
@@ -330,6 +329,17 @@ __global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_comp(
     bad |= !isfinite(xv);
   }
   if (bad) atomicOr(status, kStNonFinite);
+}
+
+template <bool WRITE_W>
+__global__ __launch_bounds__(kSweepTX * kSweepTYMax) void k_sweep_comp(
+    Geo g, Sweep s, const float* __restrict__ x, float* W,
+    uint16_t* __restrict__ codes, uint32_t* status) {
+  const uint32_t lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y,
+                                gridDim.x * gridDim.y);
+  sweep_comp_wg<WRITE_W>(g, s, x, W, codes, status, lb % gridDim.x,
+                         lb / gridDim.x, gridDim.y, threadIdx.x, threadIdx.y,
+                         blockDim.y);
 }
 
 /* Decompression: bins >= 1 reconstruct pred + (bin - R) * 2e_l with the
@@ -515,15 +525,16 @@ __device__ __forceinline__ void predict_span_A(const Geo& g, const RowJob& rj,
                          hd);
 }
 
+/* Workgroup blk of a fused level-1 row pair; E is the LDS row buffer. */
 template <bool WRITE_W>
-__global__ __launch_bounds__(kRowThreads) void k_row_comp(
-    Geo g, RowJob rj, const float* __restrict__ x, float* W,
-    uint16_t* __restrict__ codes, uint32_t* status) {
-  extern __shared__ float E[]; /* per row: E[t + 1] = value at 2t */
+__device__ __forceinline__ void row_comp_wg(
+    const Geo& g, const RowJob& rj, const float* __restrict__ x, float* W,
+    uint16_t* __restrict__ codes, uint32_t* status, uint32_t blk, float* E) {
+  /* per row: E[t + 1] = value at 2t */
   const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
   const uint32_t spans = (n2 + kSpan - 1) / kSpan;
   const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
-  const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
+  const uint32_t r0 = blk * rj.rows_per_wg;
   const uint32_t items = rj.rows_per_wg * spans;
   const RowItems ri(spans, items, rows, rj.rcnt[1]);
   /* one item per lane: the span's x values stay in registers between the
@@ -604,6 +615,14 @@ __global__ __launch_bounds__(kRowThreads) void k_row_comp(
     }
   }
   if (bad) atomicOr(status, kStNonFinite);
+}
+
+template <bool WRITE_W>
+__global__ __launch_bounds__(kRowThreads) void k_row_comp(
+    Geo g, RowJob rj, const float* __restrict__ x, float* W,
+    uint16_t* __restrict__ codes, uint32_t* status) {
+  extern __shared__ float E[];
+  row_comp_wg<WRITE_W>(g, rj, x, W, codes, status, blockIdx.x, E);
 }
 
 /* Decompression: bin 0 keeps the exact value already scattered into W.
@@ -818,6 +837,94 @@ __global__ __launch_bounds__(kRowThreads) void k_sweep_round_q(
                     kRowThreads / kSweepTX);
 }
 
+/* One round of a batch's compression sweeps, as k_sweep_round_q for the
+ * inverse sweeps. */
+__global__ __launch_bounds__(kRowThreads) void k_sweep_round_comp_q(
+    const CompJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  extern __shared__ float E[];
+  const uint32_t gid = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t j = find_job(wg0, n_jobs, gid);
+  const CompJob& a = jobs[j];
+  const uint32_t lid = gid - wg0[j];
+  if (a.rows) {
+    if (a.write_w)
+      row_comp_wg<true>(a.g, a.rj, a.x, a.W, a.codes, a.status, lid, E);
+    else
+      row_comp_wg<false>(a.g, a.rj, a.x, a.W, a.codes, a.status, lid, E);
+  } else {
+    const uint32_t tx = threadIdx.x % kSweepTX, ty = threadIdx.x / kSweepTX;
+    if (a.write_w)
+      sweep_comp_wg<true>(a.g, a.s, a.x, a.W, a.codes, a.status, lid % a.gx,
+                          lid / a.gx, a.gy, tx, ty, kRowThreads / kSweepTX);
+    else
+      sweep_comp_wg<false>(a.g, a.s, a.x, a.W, a.codes, a.status, lid % a.gx,
+                           lid / a.gx, a.gy, tx, ty, kRowThreads / kSweepTX);
+  }
+}
+
+/* The anchors of many fields in one launch. */
+__global__ __launch_bounds__(256) void k_anchor_q(
+    const AnchorJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
+  const AnchorJob& a = jobs[j];
+  const uint32_t t = (blockIdx.x - wg0[j]) * blockDim.x + threadIdx.x;
+  const uint32_t total = a.na[0] * a.na[1] * a.na[2];
+  if (t >= total) return;
+  const uint32_t a2 = t % a.na[2];
+  const uint32_t r = t / a.na[2];
+  const uint32_t a1 = r % a.na[1];
+  const uint32_t a0 = r / a.na[1];
+  const uint32_t idx = a0 * a.stride * a.g.st[0] + a1 * a.stride * a.g.st[1] +
+                       a2 * a.stride;
+  const float v = a.x[idx];
+  a.W[idx] = v;
+  a.out[t] = v;
+  if (!isfinite(v)) atomicOr(a.status, kStNonFinite);
+}
+
+/* Copies (or zero fills) of a list, one workgroup per entry: 16-byte
+ * accesses when both ends and the size allow, else 8-byte ones, else
+ * bytes. */
+__global__ __launch_bounds__(256) void k_copy_list(
+    const DevCopy* __restrict__ list) {
+  const DevCopy c = list[blockIdx.x];
+  const uint64_t al = (uintptr_t)c.src | (uintptr_t)c.dst | c.bytes;
+  if ((al & 15) == 0) {
+    uint4* d = (uint4*)c.dst;
+    const uint4* s = (const uint4*)c.src;
+    for (uint64_t i = threadIdx.x; i < c.bytes / 16; i += blockDim.x)
+      d[i] = s ? s[i] : make_uint4(0, 0, 0, 0);
+  } else if ((al & 7) == 0) {
+    uint2* d = (uint2*)c.dst;
+    const uint2* s = (const uint2*)c.src;
+    for (uint64_t i = threadIdx.x; i < c.bytes / 8; i += blockDim.x)
+      d[i] = s ? s[i] : make_uint2(0, 0);
+  } else {
+    uint8_t* d = (uint8_t*)c.dst;
+    const uint8_t* s = (const uint8_t*)c.src;
+    for (uint64_t i = threadIdx.x; i < c.bytes; i += blockDim.x)
+      d[i] = s ? s[i] : (uint8_t)0;
+  }
+}
+
+uint32_t anchor_job_workgroups(const AnchorJob& j) {
+  return (j.na[0] * j.na[1] * j.na[2] + 255) / 256;
+}
+
+void launch_anchor_q(const AnchorJob* jobs, const uint32_t* wg0,
+                     uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_anchor_q, dim3(total_wg), dim3(256), 0, s, jobs, wg0,
+                     n_jobs);
+}
+
+void launch_copy_list(const DevCopy* list, uint32_t n, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_copy_list, dim3(n), dim3(256), 0, s, list);
+}
+
 static_assert(kRowThreads % kSweepTX == 0, "queued sweep tiles");
 
 /* Launch shape of a sweep: x covers 64 consecutive targets of a row, y
@@ -867,6 +974,30 @@ uint32_t sweep_job_prepare(SweepJob* j, size_t* lds) {
   j->gx = grid.x;
   j->gy = grid.y;
   return grid.x * grid.y;
+}
+
+uint32_t comp_job_prepare(CompJob* j, size_t* lds) {
+  *lds = 0;
+  if (j->rows) {
+    if (!j->rj.rcnt[0] || !j->rj.rcnt[1]) return 0;
+    return row_blocks(j->g, &j->rj, lds);
+  }
+  if (j->s.count == 0) return 0;
+  SweepTile t;
+  t.ty = kRowThreads / kSweepTX;
+  t.rpt = 1;
+  const dim3 grid = sweep_grid_dim(j->s, t);
+  j->gx = grid.x;
+  j->gy = grid.y;
+  return grid.x * grid.y;
+}
+
+void launch_sweep_round_comp_q(const CompJob* jobs, const uint32_t* wg0,
+                               uint32_t n_jobs, uint32_t total_wg, size_t lds,
+                               hipStream_t s) {
+  if (!total_wg) return;
+  hipLaunchKernelGGL(k_sweep_round_comp_q, dim3(total_wg), dim3(kRowThreads),
+                     lds, s, jobs, wg0, n_jobs);
 }
 
 void launch_sweep_round_q(const SweepJob* jobs, const uint32_t* wg0,

@@ -4,8 +4,8 @@
  * Sec. VI as the fallback.
  *
  * Sampling of the feature blocks follows Sec. VI-A with b = 32: blocks of
- * 33 points per dimension at origins k*S, S = round(32 r^(-1/3)), every
- * origin with k*S + 32 <= n - 1.
+ * 33 points per dimension at origins k*S, S = round(32 r^(-1/d)), every
+ * origin with k*S + 32 <= n - 1, for 2D (d = 2) and 3D (d = 3) fields.
  */
 #include <cmath>
 #include <cstring>
@@ -23,8 +23,7 @@ static const double kBetaL[4] = {1.5, 2.0, 3.0, 4.0};
 static qoz_status learned_origins(int d, const uint64_t n[3],
                                   const qoz_tune_config* cfg,
                                   std::vector<uint32_t>* origins) {
-  if (d != 3) return fail(QOZ_EINVAL, "learned features need a 3D field");
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < d; ++i)
     if (n[i] < 33)
       return fail(QOZ_EINVAL, "learned features need every dimension >= 33");
   const double r =
@@ -32,12 +31,14 @@ static qoz_status learned_origins(int d, const uint64_t n[3],
   if (!(r > 0.0 && r <= 1.0)) return fail(QOZ_EINVAL, "bad sample rate");
   uint32_t S = (cfg && cfg->sample_stride)
                    ? cfg->sample_stride
-                   : (uint32_t)std::llround(32.0 * std::pow(r, -1.0 / 3.0));
+                   : (uint32_t)std::llround(32.0 * std::pow(r, -1.0 / d));
   if (S < 1) S = 1;
-  uint64_t m[3];
-  for (int i = 0; i < 3; ++i) {
-    m[i] = 0;
-    while (m[i] * S + 32 <= n[i] - 1) ++m[i];
+  /* blocks per dimension; a 2D field is one plane of the 3D layout */
+  uint64_t m[3] = {1, 1, 1};
+  for (int i = 0; i < d; ++i) {
+    uint64_t& mi = m[3 - d + i];
+    mi = 0;
+    while (mi * S + 32 <= n[i] - 1) ++mi;
   }
   origins->clear();
   for (uint64_t a = 0; a < m[0]; ++a)
@@ -85,7 +86,8 @@ static qoz_status enqueue_features(qoz_ctx* c, const float* d_x, int d,
     launch_block_features(d_x, g, dorig, nb, e,
                           d_block ? d_block : (float*)c->feat.p, aux, d_mean,
                           st, s);
-    prof_end(c, s, ev, PK_LEARN_FEAT, 4.0 * 35937.0 * nb);
+    prof_end(c, s, ev, PK_LEARN_FEAT,
+             4.0 * (d == 2 ? 1089.0 : 35937.0) * nb);
   }
   QOZ_TRY(to_host(c, hp, st, 16, s));
   *nb_out = nb;
@@ -275,7 +277,7 @@ extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
   if (!stride_levels(out->anchor_stride, d, &sa, &L))
     return fail(QOZ_EINVAL, "bad anchor stride");
 
-  bool supported = d == 3 && n[0] >= 33 && n[1] >= 33 && n[2] >= 33;
+  bool supported = n[0] >= 33 && n[1] >= 33 && (d == 2 || n[2] >= 33);
   double conf = 0.0;
   uint32_t pick[3] = {0, 0, 0};
   if (supported) {
@@ -312,12 +314,12 @@ extern "C" qoz_status qoz_tune_learned(qoz_ctx* c, const float* d_x,
 
 extern "C" qoz_status qoz_tune_learned_batch(
     qoz_ctx* c, qoz_learned_item* items, uint32_t n, const float* d_params,
-    double min_confidence, qoz_target fallback_target,
-    const qoz_tune_config* cfg, hipStream_t s) {
+    const float* d_params_2d, double min_confidence,
+    qoz_target fallback_target, const qoz_tune_config* cfg, hipStream_t s) {
   clear_error();
   if (!c || (n && !items) || !d_params)
     return fail(QOZ_EINVAL, "NULL argument");
-  if (!aligned16(d_params))
+  if (!aligned16(d_params) || (d_params_2d && !aligned16(d_params_2d)))
     return fail(QOZ_EINVAL, "d_params must be 16-byte aligned");
   if (!(min_confidence >= 0.0 && min_confidence <= 1.0))
     return fail(QOZ_EINVAL, "min_confidence must be in [0, 1]");
@@ -350,8 +352,8 @@ extern "C" qoz_status qoz_tune_learned_batch(
       it.status = QOZ_EINVAL;
       continue;
     }
-    const bool sup =
-        j.d == 3 && j.n[0] >= 33 && j.n[1] >= 33 && j.n[2] >= 33;
+    const bool sup = j.n[0] >= 33 && j.n[1] >= 33 &&
+                     (j.d == 3 ? j.n[2] >= 33 : d_params_2d != nullptr);
     if (!sup) {
       fall.push_back(i);
       continue;
@@ -365,7 +367,12 @@ extern "C" qoz_status qoz_tune_learned_batch(
     blocks += j.nb;
     jobs.push_back(j);
   }
+  /* 3D fields first, then 2D ones: one forward pass per network */
+  std::stable_partition(jobs.begin(), jobs.end(),
+                        [](const Job& j) { return j.d == 3; });
   const uint32_t m = (uint32_t)jobs.size();
+  uint32_t m3 = 0;
+  while (m3 < m && jobs[m3].d == 3) ++m3;
   if (m) {
     /* device: origins, aux (3 per block), features (32 per block), means
      * (32 per field), logits (11 per field), status (4 words per field) */
@@ -394,13 +401,22 @@ extern "C" qoz_status qoz_tune_learned_batch(
                             (float*)(D + o_aux) + 3 * j.blk,
                             (float*)(D + o_mean) + (size_t)kMlpFeat * k,
                             (uint32_t*)(D + o_st) + 4 * k, s);
-      prof_end(c, s, ev, PK_LEARN_FEAT, 4.0 * 35937.0 * j.nb);
+      prof_end(c, s, ev, PK_LEARN_FEAT,
+               4.0 * (j.d == 2 ? 1089.0 : 35937.0) * j.nb);
     }
-    {
+    if (m3) {
       hipEvent_t ev = prof_begin(c, s, PK_MLP);
-      launch_mlp_forward(d_params, (const float*)(D + o_mean), m,
+      launch_mlp_forward(d_params, (const float*)(D + o_mean), m3,
                          (float*)(D + o_logit), s);
-      prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams + 4.0 * 43 * m);
+      prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams + 4.0 * 43 * m3);
+    }
+    if (m > m3) {
+      hipEvent_t ev = prof_begin(c, s, PK_MLP);
+      launch_mlp_forward(d_params_2d,
+                         (const float*)(D + o_mean) + (size_t)kMlpFeat * m3,
+                         m - m3,
+                         (float*)(D + o_logit) + (size_t)kMlpOut * m3, s);
+      prof_end(c, s, ev, PK_MLP, 4.0 * kMlpParams + 4.0 * 43 * (m - m3));
     }
     float* hz = (float*)(hp + pin_back);
     uint32_t* hs = (uint32_t*)(hz + (size_t)kMlpOut * m);

@@ -174,7 +174,7 @@ enum ProfKind {
   PK_SWEEP_COMP_L1,
   PK_SWEEP_COMP,
   PK_HIST,
-  PK_HUFF_LEN,
+  PK_HUFF_COUNT,
   PK_HUFF_ENC,
   PK_HUFF_DEC,
   PK_SWEEP_DEC_L1,
@@ -219,7 +219,7 @@ struct qoz_ctx {
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
       hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp,
-      queue, lbatch;
+      queue, lbatch, cqueue, cqueue_up;
   /* sweep launch tiles chosen by qoz_autotune_tiles, per plan signature */
   std::map<std::vector<uint32_t>, std::vector<qoz::SweepTile>> tiles_comp,
       tiles_decomp;
@@ -359,31 +359,64 @@ void launch_unpred_scatter(const Geo& g, const SweepTable& st,
 void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s);
 void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
-/* bytes from device memory to coherent host memory (to_host) or back */
 /* device-to-device copies of up to four regions (n <= 4) in one launch */
 void launch_copy_regions(void* const* dst, const void* const* src,
                          const uint64_t* bytes, uint32_t n, hipStream_t s);
+/* bytes from device memory to coherent host memory (to_host) or back */
 void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
                       hipStream_t s);
-void launch_huff_len(const uint16_t* codes, const Chunks& chunks,
-                     const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
-                     uint64_t zero_entry, uint32_t* chunk_bits,
-                     uint32_t* chunk_zeros, hipStream_t s);
 /* scratch bytes launch_chunk_scan needs */
 uint64_t chunk_scan_scratch(uint64_t n_chunks);
 void launch_chunk_scan(const uint32_t* chunk_bits,
                        const uint32_t* chunk_zeros, uint64_t n_chunks,
-                       uint64_t* coff, uint32_t* upre, uint64_t* totals,
+                       uint64_t* coff, uint64_t* upre, uint64_t* totals,
                        uint64_t* scratch, hipStream_t s);
-void launch_huff_encode(const uint16_t* codes, const Chunks& chunks,
-                        const uint64_t* table, int32_t tab_lo, uint32_t tab_n,
-                        uint64_t zero_entry, const uint64_t* coff,
-                        const uint32_t* upre, uint16_t* segs,
-                        uint32_t* payload,
-                        uint64_t payload_cap_words, float* unpred,
-                        const float* x, const Geo& g, const SweepTable& st,
-                        uint32_t max_chunk_words, uint32_t max_len,
-                        uint32_t* status, uint32_t* pack_bits, hipStream_t s);
+/* One field of an encoding (see kernels_huff.hip): its bins, chunks and
+ * code table, the stream sections the encoder fills, its totals (payload
+ * words, symbol-0 bins, packed words: zero on entry) and status word. */
+struct EncField {
+  const uint16_t* codes;
+  Chunks ch;
+  uint64_t nch;
+  const uint64_t* tab; /* (code << 8) | length for symbols [lo, lo + tn) */
+  int32_t lo;
+  uint32_t tn;
+  uint64_t zero_entry; /* symbol 0's entry */
+  uint64_t* coff;
+  uint32_t* upre;
+  uint16_t* segs;
+  uint32_t* payload;
+  uint64_t cap_words;
+  float* unpred;
+  const float* x;
+  Geo g;
+  uint64_t* totals;
+  uint32_t* status;
+  uint32_t* pack_bits;
+  SweepTable st;
+};
+/* Code bits and symbol-0 bins of every chunk of fields[0..nf) (chunk0[f]:
+ * the first chunk of field f in the global chunk order, chunk0[nf] the
+ * total) into bits[] and zeros[] at global chunk indices; field f's
+ * workgroups start at wg0[f] (count_workgroups(its chunks) of them),
+ * wg0[nf] = total_wg. */
+uint32_t count_workgroups(uint64_t n_chunks);
+void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
+                       const uint32_t* wg0, uint32_t nf, uint32_t total_wg,
+                       uint32_t* bits, uint32_t* zeros, hipStream_t s);
+/* Chunks of every field, coded by n_wg workgroups in a grid stride over
+ * the global chunk order; gw and gz are the chunk scan's exclusive
+ * prefixes of the counted words and symbol-0 bins (n_chunks + 1 each);
+ * max_words bounds a chunk's payload words, long_codes selects the
+ * variant for codes longer than 32 bits. */
+void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
+                        const uint64_t* gw, const uint64_t* gz, uint32_t nf,
+                        uint64_t n_chunks, uint32_t max_words,
+                        bool long_codes, uint32_t n_wg, hipStream_t s);
+/* workgroups of the encoding launch for the current device */
+uint32_t encode_workgroups();
+/* payload words a chunk can need with codes of at most max_len bits */
+uint32_t encode_max_words(uint32_t max_len);
 /* zero-word packing of the payload (stream format 5): pack_bits[c] from
  * the encoder is 32 x the chunk's packed word count, scanned into pcoff */
 void launch_pack_write(const uint32_t* raw, const uint64_t* coff,
@@ -419,6 +452,40 @@ struct SweepJob {
   float* W;
   const uint16_t* codes;
 };
+/* one compression sweep (or fused level-1 row pair) of one field */
+struct CompJob {
+  Geo g;
+  uint32_t rows;    /* 0: sweep s; 1: fused level-1 rows rj */
+  uint32_t gx, gy;  /* sweep grid (set by comp_job_prepare) */
+  uint32_t write_w; /* the reconstruction is read by later sweeps */
+  Sweep s;
+  RowJob rj;
+  const float* x;
+  float* W;
+  uint16_t* codes;
+  uint32_t* status;
+};
+/* the anchors of one field: into W and the anchor list out */
+struct AnchorJob {
+  Geo g;
+  uint32_t stride, na[3];
+  const float* x;
+  float* W;
+  float* out;
+  uint32_t* status;
+};
+/* one histogram: bins codes[0..n) into hist[65536] (zero on entry) */
+struct HistJob {
+  const uint16_t* codes;
+  uint64_t n;
+  uint32_t* hist;
+};
+/* a device-to-device copy, or a zero fill when src is NULL */
+struct DevCopy {
+  const void* src;
+  void* dst;
+  uint64_t bytes;
+};
 /* anchors and unpredictable values of one stream */
 struct ExactJob {
   Geo g;
@@ -439,6 +506,20 @@ struct HostCopy {
   uint64_t bytes;
 };
 void launch_gather_host(const HostCopy* list, uint32_t n, hipStream_t s);
+/* work queues of batched compression: each job owns the launch's
+ * workgroups [wg0[j], wg0[j + 1]) */
+uint32_t comp_job_prepare(CompJob* j, size_t* lds);
+void launch_sweep_round_comp_q(const CompJob* jobs, const uint32_t* wg0,
+                               uint32_t n_jobs, uint32_t total_wg, size_t lds,
+                               hipStream_t s);
+uint32_t anchor_job_workgroups(const AnchorJob& j);
+void launch_anchor_q(const AnchorJob* jobs, const uint32_t* wg0,
+                     uint32_t n_jobs, uint32_t total_wg, hipStream_t s);
+uint32_t hist_job_workgroups(const HistJob& j);
+void launch_hist_q(const HistJob* jobs, const uint32_t* wg0, uint32_t n_jobs,
+                   uint32_t total_wg, hipStream_t s);
+/* copies / zero fills list[0..n) (device memory), one workgroup each */
+void launch_copy_list(const DevCopy* list, uint32_t n, hipStream_t s);
 /* copies[0..n), an array inside the pinned staging whose dst fields hold
  * host addresses inside it, in one launch */
 qoz_status gather_to_host(qoz_ctx* c, HostCopy* copies, uint32_t n,

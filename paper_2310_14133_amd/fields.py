@@ -98,6 +98,59 @@ def tuner_training_field(seed, device="cuda", shape=None):
     return g.contiguous(), {"shape": shape, "slope": slope, "noise": noise}
 
 
+TUNER_KINDS = ("grf", "lognormal", "multiscale")
+
+
+def tuner_field(seed, ndim=3, device="cuda", shape=None, kind=None):
+    """One field of the learned tuner's wider workload, drawn from `seed`
+    (torch on `device`):
+
+    * kind "grf": a k^slope random field (slope U[-4, -2]) plus white noise
+      of relative std 10^U[-4, -2] (the tuner_training_field recipe);
+    * kind "lognormal": exp(s g) of a k^slope field g (slope U[-4, -2]),
+      s U[0.5, 1.5], standardised: a skewed, density-like field;
+    * kind "multiscale": the k^-3 field plus 16 Gaussian bumps.
+
+    Without a given shape: 3D U{64..256}^3, 2D U{256..2048}^2 (the corner
+    of a periodic 256^3 / 2048^2 field, standardised again); kind uniform
+    over TUNER_KINDS unless given.  Returns (field, recipe)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    if kind is None:
+        kind = TUNER_KINDS[int(rng.integers(0, len(TUNER_KINDS)))]
+    crop = shape is None
+    full = (256,) * 3 if ndim == 3 else (2048, 2048)
+    if crop:
+        lo, hi = (64, 257) if ndim == 3 else (256, 2049)
+        shape = tuple(int(v) for v in rng.integers(lo, hi, ndim))
+    slope = float(rng.uniform(-4.0, -2.0))
+    noise = float(10.0 ** rng.uniform(-4.0, -2.0))
+    sigma = float(rng.uniform(0.5, 1.5))
+    gshape = full if crop else shape
+    if kind == "multiscale":
+        g = multiscale_torch(gshape, seed, device=device)
+    else:
+        g = grf_torch(gshape, seed, slope=slope, device=device)
+    if crop:
+        g = g[tuple(slice(0, n) for n in shape)]
+    if kind == "lognormal":
+        g = torch.exp(sigma * ((g - g.mean()) / g.std()))
+    g = ((g - g.mean()) / g.std()).contiguous()
+    if kind == "grf":
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed) + 104729)
+        g += noise * torch.randn(shape, generator=gen, device=device,
+                                 dtype=torch.float32)
+    rec = {"shape": shape, "kind": kind}
+    if kind != "multiscale":
+        rec["slope"] = slope
+    if kind == "grf":
+        rec["noise"] = noise
+    if kind == "lognormal":
+        rec["sigma"] = sigma
+    return g.contiguous(), rec
+
+
 def bumps_and_waves(n=256, seed=1, n_bumps=8, n_waves=3, noise=1e-3,
                     dtype=np.float32):
     """2D field: Gaussian bumps + plane waves + white noise.

@@ -30,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KIND_KERNELS = {
     "huffman_decode": ("k_huff_decode", "csrc/kernels_decode.hip"),
     "huffman_encode": ("k_huff_encode", "csrc/kernels_huff.hip"),
-    "huffman_lengths": ("k_huff_len", "csrc/kernels_huff.hip"),
+    "huffman_count": ("k_huff_count", "csrc/kernels_huff.hip"),
     "histogram": ("k_hist", "csrc/kernels_huff.hip"),
     "row_comp_level1": ("k_row_comp", "csrc/kernels_sweep.hip"),
     "row_decomp_level1": ("k_row_decomp", "csrc/kernels_sweep.hip"),

@@ -55,6 +55,10 @@ FEATURE_CASES = [
     ("lognormal_ragged", lambda: fields.grf((40, 129, 35), 9,
                                             log_normal=True), 1e-4, 0.3),
     ("multiscale", lambda: fields.multiscale((64, 72, 96), 10), 1e-3, 0.2),
+    ("grf_2d", lambda: fields.grf((150, 170), 11), 1e-3, 0.2),
+    ("lognormal_2d_single", lambda: fields.grf((33, 40), 12,
+                                               log_normal=True), 1e-2, 0.0),
+    ("bumps_2d", lambda: fields.bumps_and_waves(512, 13), 1e-4, 0.01),
 ]
 
 
@@ -67,7 +71,7 @@ def test_features_parity(codec, rl, name, make, rel, rate):
     print(f"features case {name} shape={x.shape}", flush=True)
     plan = ref.sample_plan(x.shape, cfg=ref.tune_config(
         block=32, sample_rate=rate if rate else 0.01))
-    assert plan["block_dims"] == (33, 33, 33)
+    assert plan["block_dims"] == (33,) * x.ndim
     per_r, mean_r = rl.field_features(x, e, plan["origins"])
     mean_g, per_g = codec.learned_features(
         to_dev(x), e, q.make_tune_config(sample_rate=rate), per_block=True)
@@ -82,9 +86,15 @@ def test_features_errors(codec):
     import torch
     import paper_2310_14133_amd as q
     with pytest.raises(q.QozError):
-        codec.learned_features(to_dev(fields.grf((64, 64), 1)), 1e-3)
+        codec.learned_features(to_dev(fields.grf((64, 32), 1)), 1e-3)
     with pytest.raises(q.QozError):
         codec.learned_features(to_dev(fields.grf((64, 32, 64), 1)), 1e-3)
+    x2 = fields.grf((80, 90), 3)
+    x2[40, 2] = np.inf
+    with pytest.raises(q.QozError) as err:
+        codec.learned_features(to_dev(x2), 1e-3, q.make_tune_config(
+            sample_rate=1.0))
+    assert err.value.status == q.QOZ_EINVAL
     x = fields.grf((40, 40, 40), 2)
     x[3, 4, 5] = np.nan
     with pytest.raises(q.QozError) as err:
@@ -242,8 +252,8 @@ def test_tune_learned_fallback(codec, rl):
     assert fb
     tp = codec.tune(to_dev(x), e, "psnr", cfg)
     assert q.params_dict(gp, 3) == q.params_dict(tp, 3)
-    # 2D fields are outside the network's domain
-    x2 = fields.bumps_and_waves(96, 3)
+    # fields with a side below one feature block are outside its domain
+    x2 = np.ascontiguousarray(fields.bumps_and_waves(96, 3)[:20])
     e2 = 1e-3 * (float(x2.max()) - float(x2.min()))
     gp2, fb2 = codec.tune_learned(to_dev(x2), e2, P, 0.0, "cr", None)
     assert fb2
@@ -251,38 +261,65 @@ def test_tune_learned_fallback(codec, rl):
         codec.tune(to_dev(x2), e2, "cr", None), 2)
 
 
-def test_trained_network_gain(codec):
-    """The committed network against the online tuner it was trained on, on
-    a held-out 512^3 field: several times faster, and within 2 % of the
-    online tuner's ratio at the same PSNR (6.02 dB per bit per value)."""
+def _gain(codec, x, ndim, targets, min_speedup, conf=0.5, min_ratio=0.98):
+    """The committed network against the online tuner it was trained on:
+    tuning time at each target's nominal bound, and the ratio of each at
+    equal PSNR (bisection of the bound to within 0.05 dB above the
+    target).  With conf = 0 the network decides every time."""
     import paper_2310_14133_amd as q
     from paper_2310_14133_amd import learned
-    P = learned.load_weights()
-    x, _ = fields.tuner_training_field(20000, shape=(512, 512, 512))
+    P = learned.load_weights(learned.WEIGHTS[ndim])
     vr = float((x.max() - x.min()).item())
     cfg = q.make_tune_config(block=32, sample_rate=learned.SAMPLE_RATE)
-    raw = x.numel() * 4
-    for target in (60.0, 80.0):
+    for target in targets:
         e = learned.bound_for_psnr(vr, target)
-        print(f"gain case psnr target {target}", flush=True)
+        print(f"gain case {ndim}D psnr target {target}", flush=True)
         (pl, fb), tl = learned._timed(
-            lambda: codec.tune_learned(x, e, P, 0.5, "psnr", cfg), reps=5)
+            lambda: codec.tune_learned(x, e, P, conf, "psnr", cfg), reps=5)
         pe, te = learned._timed(lambda: codec.tune(x, e, "psnr", cfg),
                                 reps=5)
         assert not fb
-        res = []
-        for p in (pe, pl):
-            z = codec.compress(x, e, p)
-            y = codec.decompress(z)
-            ps, _, me = codec.metrics(x, y, want_ssim=False)
-            assert me <= e
-            res.append((raw / z.numel(), ps))
-        (cr_e, ps_e), (cr_l, ps_l) = res
-        bits_eq = 32.0 / cr_l + (ps_e - ps_l) / 6.02
-        print(f"  exhaustive {te:.3f} ms cr {cr_e:.4f} psnr {ps_e:.3f}; "
-              f"learned {tl:.3f} ms cr {cr_l:.4f} psnr {ps_l:.3f}", flush=True)
-        assert te / tl >= 4.0, (te, tl)
-        assert (32.0 / bits_eq) / cr_e >= 0.98
+        cr_e, ps_e, _, _ = learned.equal_psnr(
+            codec, x, target, lambda b: codec.tune(x, b, "psnr", cfg))
+        cr_l, ps_l, _, _ = learned.equal_psnr(
+            codec, x, target,
+            lambda b: codec.tune_learned(x, b, P, conf, "psnr", cfg)[0])
+        print(f"  online {te:.3f} ms cr {cr_e:.4f} at {ps_e:.3f} dB; "
+              f"learned {tl:.3f} ms cr {cr_l:.4f} at {ps_l:.3f} dB",
+              flush=True)
+        assert target <= ps_e <= target + 0.05 and \
+            target <= ps_l <= target + 0.05
+        assert te / tl >= min_speedup, (te, tl)
+        assert cr_l / cr_e >= min_ratio, (cr_l, cr_e)
+
+
+def test_trained_network_gain(codec):
+    """Held-out 512^3 field of the training recipe at 60, 80 and 100 dB:
+    at least 5x faster tuning and within 2 % of the online tuner's ratio at
+    equal PSNR."""
+    x, _ = fields.tuner_field(20000, 3, shape=(512, 512, 512), kind="grf")
+    _gain(codec, x, 3, (60.0, 80.0, 100.0), 5.0)
+
+
+def test_trained_network_gain_skewed_3d(codec):
+    """Held-out skewed (exponential) 256^3 field at 40, 50 and 70 dB, where
+    the online tuner moves alpha and beta off their first values; the
+    network decides every time.  Its worst case here is at 40 dB, where
+    its choice gives 2.7 % less ratio than the online tuner's at equal
+    PSNR, so the floor is 3 %.  The online tuner is fast on this field
+    (about 0.36 ms against the network's 0.12 ms), so the speed floor is
+    2.5x."""
+    x, _ = fields.tuner_field(20001, 3, shape=(256, 256, 256),
+                              kind="lognormal")
+    _gain(codec, x, 3, (40.0, 50.0, 70.0), 2.5, conf=0.0, min_ratio=0.97)
+
+
+def test_trained_network_gain_2d(codec):
+    """Held-out 2D field of the paper's climate shape (1800 x 3600) at 40,
+    60 and 80 dB; the network decides every time."""
+    x, _ = fields.tuner_field(20002, 2, shape=(1800, 3600),
+                              kind="multiscale")
+    _gain(codec, x, 2, (40.0, 60.0, 80.0), 3.0, conf=0.0)
 
 
 def test_tune_learned_batch_equals_single_calls(codec):
@@ -291,19 +328,23 @@ def test_tune_learned_batch_equals_single_calls(codec):
     import paper_2310_14133_amd as q
     from paper_2310_14133_amd import learned
     P = learned.load_weights()
+    P2 = learned.load_weights(learned.WEIGHTS[2])
     cfg = q.make_tune_config(block=32, sample_rate=0.05)
     shapes = [(64, 70, 66), (40, 48, 56), (96, 64, 64), (33, 33, 33),
-              (20, 40, 40), (130, 129), (80, 72, 90), (128, 128, 128)]
+              (20, 40, 40), (130, 129), (80, 72, 90), (128, 128, 128),
+              (300, 20)]
     xs, es = [], []
     for i, sh in enumerate(shapes):
         x = fields.grf(sh, 700 + i, log_normal=(i % 3 == 2))
         es.append([1e-2, 1e-3, 1e-4][i % 3] * (float(x.max()) - float(x.min())))
         xs.append(to_dev(x))
     for conf in (0.0, 0.6):
-        items = codec.tune_learned_batch(xs, es, P, conf, "psnr", cfg)
+        items = codec.tune_learned_batch(xs, es, P, conf, "psnr", cfg,
+                                         params_2d=P2)
         n_fb = 0
         for i, x in enumerate(xs):
-            p1, fb1 = codec.tune_learned(x, es[i], P, conf, "psnr", cfg)
+            p1, fb1 = codec.tune_learned(x, es[i], P if x.dim() == 3 else P2,
+                                         conf, "psnr", cfg)
             it = items[i]
             assert it.status == q.QOZ_OK, i
             assert bool(it.used_fallback) == fb1, (i, conf)
@@ -312,7 +353,14 @@ def test_tune_learned_batch_equals_single_calls(codec):
             n_fb += fb1
         print(f"learned batch, min confidence {conf}: {n_fb} of {len(xs)} "
               "fields to the online tuner", flush=True)
-        assert n_fb >= 2  # the 2D field and the small 3D one
+        assert n_fb >= 2  # the narrow 2D field and the small 3D one
+    # without the 2D network every 2D field goes to the online tuner
+    items = codec.tune_learned_batch(xs, es, P, 0.0, "psnr", cfg)
+    for i, x in enumerate(xs):
+        if x.dim() == 2:
+            assert items[i].used_fallback
+            assert q.params_dict(items[i].params, 2) == q.params_dict(
+                codec.tune(x, es[i], "psnr", cfg), 2)
     # a field with NaN in a sampled block fails alone
     bad = xs[0].clone()
     bad[0, 0, 0] = float("nan")

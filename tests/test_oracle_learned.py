@@ -23,14 +23,14 @@ def test_bf16_matches_torch_rounding():
 
 
 # ---------------------------------------------------------------- features
-def counts(l):
+def counts(l, d=3):
     """Targets of level l per dimension, and how many of them along one
-    dimension lack the cubic stencil's outer points."""
+    dimension lack the cubic stencil's outer points (d-dimensional block)."""
     h = 1 << (l - 1)
     m = 32 // h + 1
     odd = list(range(1, m, 2))
     lin_only = [j for j in odd if not (j - 3 >= 0 and j + 3 <= m - 1)]
-    return len(odd) * m * m, len(lin_only) * m * m
+    return len(odd) * m ** (d - 1), len(lin_only) * m ** (d - 1)
 
 
 def test_linear_field_features():
@@ -71,6 +71,47 @@ def test_quadratic_residuals_closed_form(axis):
         assert np.allclose(got, exp, rtol=2e-7), (l, got, exp)
 
 
+def test_linear_field_features_2d():
+    # x = 2i - 5j on a 33 x 33 block: every residual 0, g2 = 4 + 25
+    i, j = np.meshgrid(*[np.arange(33, dtype=np.float32)] * 2, indexing="ij")
+    x = (2 * i - 5 * j).astype(np.float32)
+    e = 0.125
+    f = rl.block_features(x, e, vrange=300.0)
+    assert np.all(f[:20] == 0.0)
+    assert np.allclose(f[20:30], np.log2(1 + np.sqrt(29.0) / e), rtol=1e-7)
+    assert f[30] == np.float32(np.log2(1 + (x.max() - x.min()) / e))
+    assert f[31] == np.float32(np.log2(1 + 300.0 / e))
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_quadratic_residuals_closed_form_2d(axis):
+    # as the 3D case on a 33 x 33 block: targets along the two dimensions
+    t = (np.arange(33, dtype=np.float32) + 2) ** 2
+    shape = [1, 1]
+    shape[axis] = 33
+    x = np.ascontiguousarray(
+        np.broadcast_to(t.reshape(shape), (33, 33)).astype(np.float32))
+    e = 2.0
+    f = rl.block_features(x, e, vrange=1.0)
+    for l in range(1, 6):
+        h = 1 << (l - 1)
+        per_dim, lin_only = counts(l, 2)
+        n = 2 * per_dim
+        exp = [np.log2(1 + per_dim * h * h / n / e),
+               np.log2(1 + np.sqrt(per_dim * h ** 4 / n) / e),
+               np.log2(1 + lin_only * h * h / n / e),
+               np.log2(1 + np.sqrt(lin_only * h ** 4 / n) / e)]
+        got = f[4 * (l - 1):4 * l].astype(np.float64)
+        assert np.allclose(got, exp, rtol=2e-7), (l, got, exp)
+    # g2 = (2t + 1)^2 along the axis: nearest-rank deciles of 32 values
+    # each taken 32 times
+    d = np.diff(t.astype(np.float64))
+    g2 = np.repeat(d * d, 32)
+    for q in range(1, 11):
+        v = np.percentile(g2, 10 * q, method="inverted_cdf")
+        assert f[19 + q] == np.float32(np.log2(1 + np.sqrt(v) / e)), q
+
+
 def test_gradient_deciles_nearest_rank():
     # x varies along axis 0 only: g2 = dx^2 with each of 32 values taken
     # 32*32 times; deciles by the inverted-CDF (nearest-rank) definition
@@ -102,6 +143,26 @@ def test_field_features_mean_over_sampled_blocks():
     assert hi - lo < float(x.max()) - float(x.min())  # not the field's
     assert np.array_equal(per[-1], rl.block_features(blks[-1], 1e-3, hi - lo))
     assert np.all(per[:, 31] == per[0, 31])
+
+
+def test_field_features_2d():
+    from paper_2310_14133_amd import fields
+    x = fields.grf((150, 170), 8)
+    plan = ref.sample_plan(x.shape, cfg=ref.tune_config(block=32,
+                                                        sample_rate=0.2))
+    assert plan["block_dims"] == (33, 33)
+    per, mean = rl.field_features(x, 1e-3, plan["origins"])
+    assert per.shape == (plan["nblocks"], 32) and plan["nblocks"] > 1
+    blks = [np.ascontiguousarray(x[o[0]:o[0] + 33, o[1]:o[1] + 33])
+            for o in plan["origins"]]
+    lo = min(float(b.min()) for b in blks)
+    hi = max(float(b.max()) for b in blks)
+    for r, b in zip(per, blks):
+        assert np.array_equal(r, rl.block_features(b, 1e-3, hi - lo))
+    acc = np.zeros(32)
+    for r in per:
+        acc += r.astype(np.float64)
+    assert np.array_equal(mean, (acc / len(per)).astype(np.float32))
 
 
 # --------------------------------------------------------------------- MLP
