@@ -122,6 +122,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   std::vector<uint8_t> ulen;
   uint64_t n_unpred = 0; /* symbol 0's count: the unpredictable values */
   uint64_t payload_bits = 0;
+  uint32_t words_bound = 0; /* payload words of the longest chunk, at most */
   {
     const uint64_t n_keys = hk[0];
     std::vector<uint8_t> klen;
@@ -153,6 +154,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
     if (!huffman_lengths_sorted(keys.data(), (uint32_t)keys.size(),
                                 klen.data()))
       return fail(QOZ_EINVAL, "Huffman code longer than 63 bits");
+    words_bound = chunk_words_bound(keys.data(), klen.data(),
+                                    (uint32_t)keys.size(), kChunk);
     std::vector<uint32_t> idx(keys.size());
     for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
     std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
@@ -283,8 +286,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
        kCodeBytes * P.n_codes + (double)payload_bits / 8.0 + 8.0 * n_unpred +
            46.0 * nch,
        launch_huff_encode(d_ef, d_c0, gw, gz, 1, nch,
-                          encode_max_words(max_len), max_len > 32,
-                          encode_workgroups(), s));
+                          std::min(encode_max_words(max_len), words_bound),
+                          tab_n, max_len > 32, s));
   /* each chunk's size under zero-word packing (from the encoder, in
    * chunk_bits, free again after the first scan), scanned into the packed
    * offsets and total; upre and chunk_zeros are spent by now */

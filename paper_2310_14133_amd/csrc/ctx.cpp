@@ -102,31 +102,50 @@ qoz_status to_device(qoz_ctx* c, void* d_dst, const void* h_src,
   return QOZ_OK;
 }
 
-hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s, int kind) {
-  if (!((c->timing_mask >> kind) & 1u)) return nullptr;
-  hipEvent_t e;
+ProfSlot& prof_slot() {
+  static thread_local ProfSlot slot;
+  return slot;
+}
+
+static hipEvent_t pool_event(qoz_ctx* c) {
+  hipEvent_t e = nullptr;
   if (!c->event_pool.empty()) {
     e = c->event_pool.back();
     c->event_pool.pop_back();
   } else if (hipEventCreate(&e) != hipSuccess) {
+    e = nullptr;
+  }
+  return e;
+}
+
+hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s, int kind) {
+  (void)s;
+  if (!((c->timing_mask >> kind) & 1u)) return nullptr;
+  hipEvent_t a = pool_event(c);
+  if (!a) return nullptr;
+  hipEvent_t b = pool_event(c);
+  if (!b) {
+    c->event_pool.push_back(a);
     return nullptr;
   }
-  (void)hipEventRecord(e, s);
-  return e;
+  prof_slot() = ProfSlot{a, b};
+  return a;
 }
 
 void prof_end(qoz_ctx* c, hipStream_t s, hipEvent_t a, int kind,
               double bytes) {
+  (void)s;
   if (!a) return;
-  hipEvent_t b;
-  if (!c->event_pool.empty()) {
-    b = c->event_pool.back();
-    c->event_pool.pop_back();
-  } else if (hipEventCreate(&b) != hipSuccess) {
+  ProfSlot& slot = prof_slot();
+  const hipEvent_t b = slot.stop;
+  /* no launch took the start event: nothing ran, nothing is timed */
+  const bool launched = slot.start == nullptr;
+  slot = ProfSlot{};
+  if (!launched) {
     c->event_pool.push_back(a);
+    c->event_pool.push_back(b);
     return;
   }
-  (void)hipEventRecord(b, s);
   c->pending.push_back({kind, a, b, bytes});
 }
 

@@ -111,6 +111,21 @@ uint64_t huffman_cost_sorted(const uint64_t* keys, uint32_t n) {
   return cost;
 }
 
+uint32_t chunk_words_bound(const uint64_t* keys, const uint8_t* lens,
+                           uint32_t n, uint32_t chunk) {
+  /* the longest codes first, each as often as it occurs in the field,
+   * until a chunk's bins are used up */
+  uint64_t by_len[kMaxCodeLen + 1] = {0};
+  for (uint32_t i = 0; i < n; ++i) by_len[lens[i]] += keys[i] >> 16;
+  uint64_t left = chunk, bits = 0;
+  for (int l = kMaxCodeLen; l > 0 && left; --l) {
+    const uint64_t take = by_len[l] < left ? by_len[l] : left;
+    bits += take * (uint64_t)l;
+    left -= take;
+  }
+  return (uint32_t)((bits + 31) / 32);
+}
+
 void canonical_codes_sparse(const uint16_t* syms, const uint8_t* lens,
                             uint32_t n, uint64_t* codes) {
   uint64_t count[kMaxCodeLen + 2] = {0};
@@ -226,6 +241,46 @@ bool build_dec_tables(const uint16_t* syms, const uint8_t* lens,
                        ((uint32_t)syms[i] << 16);
     const uint32_t base = (uint32_t)(code[i] << (kSymBits - l));
     for (uint32_t k = 0; k < (1u << (kSymBits - l)); ++k) t->ent[base + k] = e;
+  }
+  /* Second level: a kSymBits-bit prefix of longer codes gets a table of
+   * 2^d entries indexed by the next d bits, d the depth of its deepest code
+   * beyond the prefix, at most kEnt2Depth, while kEnt2 entries last (a
+   * prefix without one, and codes deeper than its d, take the search by
+   * length).  A code of length l fills the 2^(d - (l - kSymBits)) entries
+   * that start with its last l - kSymBits bits. */
+  {
+    std::vector<uint32_t> depth(1u << kSymBits, 0), base2(1u << kSymBits, 0);
+    for (uint32_t i = 0; i < n_used; ++i) {
+      const uint32_t l = lens[i];
+      if (l <= (uint32_t)kSymBits) continue;
+      const uint32_t p = (uint32_t)(code[i] >> (l - kSymBits));
+      depth[p] = std::max<uint32_t>(depth[p], l - kSymBits);
+    }
+    uint32_t used2 = 0;
+    for (uint32_t p = 0; p < (1u << kSymBits); ++p) {
+      if (!depth[p]) continue;
+      const uint32_t d = std::min<uint32_t>(depth[p], kEnt2Depth);
+      if (used2 + (1u << d) > kEnt2) {
+        depth[p] = 0;
+        continue;
+      }
+      depth[p] = d;
+      base2[p] = used2;
+      t->ent[p] = 0x80u | (d << 8) | (used2 << 12);
+      used2 += 1u << d;
+    }
+    for (uint32_t i = 0; i < n_used; ++i) {
+      const uint32_t l = lens[i];
+      if (l <= (uint32_t)kSymBits) continue;
+      const uint32_t p = (uint32_t)(code[i] >> (l - kSymBits));
+      const uint32_t d = depth[p], x = l - kSymBits;
+      if (!d || x > d) continue;
+      const uint32_t e = l | (syms[i] == 0 ? 0x40u : 0u) |
+                         ((uint32_t)syms[i] << 16);
+      const uint32_t suffix = (uint32_t)(code[i] & ((1ull << x) - 1));
+      const uint32_t b = base2[p] + (suffix << (d - x));
+      for (uint32_t k = 0; k < (1u << (d - x)); ++k) t->ent2[b + k] = e;
+    }
   }
   return true;
 }

@@ -38,7 +38,7 @@ constexpr uint32_t kDecWG = 640; /* 10 waves: 80 chunks */
 constexpr uint32_t kChunksPerWG = kDecWG / kSegPerChunk;
 constexpr uint32_t kRegMax = 20; /* longest code sized from registers */
 constexpr uint32_t kMaxChunkWords = kChunk * kMaxCodeLen / 32 + 2;
-constexpr uint32_t kSortedLds = 4096; /* canonical symbols kept in LDS */
+constexpr uint32_t kSortedLds = 1024; /* canonical symbols kept in LDS */
 constexpr uint32_t kRing = 16;        /* payload words per lane in LDS */
 constexpr uint32_t kHalf = kRing / 2;
 constexpr uint32_t kInvalid = 0xffffffffu;
@@ -49,6 +49,7 @@ struct DecShared {
   /* per chunk, the 64 bins of the group being decoded, in bin order */
   __align__(16) uint16_t tb[kChunksPerWG][64];
   uint32_t ent[1u << kSymBits]; /* DecTables::ent */
+  uint32_t ent2[kEnt2];         /* DecTables::ent2 */
   uint16_t sorted[kSortedLds];
   uint64_t first[kMaxCodeLen + 1];
   uint64_t lim_half[kMaxCodeLen + 1]; /* DecTables::lim_half */
@@ -167,10 +168,12 @@ struct Reader {
     pending = true;
   }
   /* the 64 bits at the read position, from memory */
-  __device__ __forceinline__ uint64_t window64(const Words& W) const {
-    const uint32_t p = pos(), wi = p >> 5, o = p & 31;
-    const uint64_t x = W(wi), y = W(wi + 1), z = W(wi + 2);
-    return (((x << 32) | y) << o) | (o ? z >> (32 - o) : 0);
+  /* the 64 bits from the read position: the window and the 32 bits after
+   * it, from b and word wp (which the ring holds during a group) */
+  __device__ __forceinline__ uint64_t window64(const DecShared& sh) const {
+    const uint32_t c = sh.ring[wp % kRing][threadIdx.x];
+    return ((uint64_t)__builtin_amdgcn_alignbit(a, b, so) << 32) |
+           __builtin_amdgcn_alignbit(b, c, so);
   }
   /* move the read position by len <= 32 bits; nx is word wp */
   __device__ __forceinline__ void advance(uint32_t len, uint32_t nx) {
@@ -217,7 +220,7 @@ __device__ __forceinline__ uint32_t slow_symbol(
     len = len <= maxlen ? len : maxlen;
     r = (uint64_t)(top >> (32 - len));
   } else { /* a code of kRegMax bits or more, or a saturated limit */
-    const uint64_t V = rd.window64(W);
+    const uint64_t V = rd.window64(sh);
     const uint64_t h = V >> 1;
     len = 0;
     for (uint32_t L = kSymBits + 1; L <= maxlen; ++L)
@@ -264,6 +267,10 @@ __device__ __forceinline__ void decode_wg(
     uint4* dst = reinterpret_cast<uint4*>(sh.ent);
     for (uint32_t i = threadIdx.x; i < sizeof(sh.ent) / 16; i += kDecWG)
       dst[i] = src[i];
+    const uint4* src2 = reinterpret_cast<const uint4*>(tabs->ent2);
+    uint4* dst2 = reinterpret_cast<uint4*>(sh.ent2);
+    for (uint32_t i = threadIdx.x; i < sizeof(sh.ent2) / 16; i += kDecWG)
+      dst2[i] = src2[i];
   }
   /* the canonical symbols a valid code can index (k < n_used) */
   const uint32_t n_used = tabs->n_used;
@@ -331,6 +338,15 @@ __device__ __forceinline__ void decode_wg(
     uint32_t len = e & 0x3fu;
     uint32_t s = e >> 16;
     zor |= e;
+    /* a code of up to kEnt2Depth bits beyond a prefix with a second-level
+     * table: one more lookup with the bits after the prefix */
+    if (__builtin_expect(len == 0 && (e & 0x80u) != 0, 0)) {
+      const uint32_t d = (e >> 8) & 15u;
+      const uint32_t e2 = sh.ent2[(e >> 12) + ((top << kSymBits) >> (32 - d))];
+      len = e2 & 0x3fu;
+      s = e2 >> 16;
+      zor |= e2;
+    }
     if (__builtin_expect(len == 0, 0)) {
       s = slow_symbol(rd, W, top, lim, sh, tabs, syms, maxlen, &len);
       if (s == kInvalid) {
@@ -455,7 +471,7 @@ uint32_t decode_workgroups(uint64_t n_chunks) {
 void launch_huff_decode_q(const DecJob* jobs, const uint32_t* wg0,
                           uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_huff_decode_q, dim3(total_wg), dim3(kDecWG), 0, s,
+  QOZ_LAUNCH(k_huff_decode_q, dim3(total_wg), dim3(kDecWG), 0, s,
                      jobs, wg0, n_jobs);
 }
 
@@ -468,7 +484,7 @@ void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
   const uint64_t n_chunks = chunks.count();
   if (!n_chunks) return;
   const uint64_t blocks = (n_chunks + kChunksPerWG - 1) / kChunksPerWG;
-  hipLaunchKernelGGL(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecWG), 0,
+  QOZ_LAUNCH(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecWG), 0,
                      s, payload, n_words, coff, upre, segs, chunks, n_unpred,
                      tabs, syms, codes, upos, status);
 }

@@ -91,7 +91,7 @@ uint32_t hist_job_workgroups(const HistJob& j) {
 void launch_hist_q(const HistJob* jobs, const uint32_t* wg0, uint32_t n_jobs,
                    uint32_t total_wg, hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_hist_q, dim3(total_wg), dim3(kHistThreads), 0, s, jobs,
+  QOZ_LAUNCH(k_hist_q, dim3(total_wg), dim3(kHistThreads), 0, s, jobs,
                      wg0, n_jobs);
 }
 
@@ -99,34 +99,8 @@ void launch_hist(const uint16_t* codes, uint64_t n, uint32_t* hist,
                  hipStream_t s) {
   if (!n) return;
   uint64_t blocks = (n + kHistPerBlock - 1) / kHistPerBlock;
-  hipLaunchKernelGGL(k_hist, dim3((uint32_t)blocks), dim3(kHistThreads), 0, s,
+  QOZ_LAUNCH(k_hist, dim3((uint32_t)blocks), dim3(kHistThreads), 0, s,
                      codes, n, hist);
-}
-
-/* Code table: entry = (code << 8) | length for symbols in [lo, lo + tn);
- * symbol 0 (unpredictable) has its own entry. */
-__device__ __forceinline__ uint64_t code_entry(const uint64_t* tab,
-                                               int32_t lo, uint32_t tn,
-                                               uint64_t zero_entry,
-                                               int32_t sym) {
-  if (sym == 0) return zero_entry;
-  uint32_t o = (uint32_t)(sym - lo);
-  return o < tn ? tab[o] : 0;
-}
-
-constexpr uint32_t kEncThreads = 256;
-constexpr uint32_t kEncPerThread = kChunk / kEncThreads; /* 16 */
-
-__device__ __forceinline__ uint32_t block_reduce_u32(uint32_t v,
-                                                     uint32_t* sh) {
-  v = wave_sum_u32(v);
-  const uint32_t wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  uint32_t r = 0;
-  if (threadIdx.x == 0)
-    for (uint32_t w = 0; w < blockDim.x / 64; ++w) r += sh[w];
-  return r;
 }
 
 constexpr uint32_t kScanThreads = 256;
@@ -339,7 +313,7 @@ __global__ __launch_bounds__(kSortThreads) void k_hist_sort(
 void launch_hist_sort(const uint32_t* hist, uint32_t n_hist, uint64_t* out,
                       hipStream_t s) {
   if (!n_hist) return;
-  hipLaunchKernelGGL(k_hist_sort, dim3(n_hist), dim3(kSortThreads),
+  QOZ_LAUNCH(k_hist_sort, dim3(n_hist), dim3(kSortThreads),
                      8 * kSortCap, s, hist, (const uint32_t*)nullptr,
                      kSortCap, out);
 }
@@ -359,7 +333,7 @@ bool hist_sort_big_fits() {
 void launch_hist_sort_big(const uint32_t* hist, const uint32_t* ids,
                           uint32_t n, uint64_t* out, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_hist_sort, dim3(n), dim3(kSortThreads),
+  QOZ_LAUNCH(k_hist_sort, dim3(n), dim3(kSortThreads),
                      8 * kSortCapBig, s, hist, ids, kSortCapBig, out);
 }
 
@@ -377,46 +351,35 @@ void launch_chunk_scan(const uint32_t* chunk_bits,
   uint64_t* tw = scratch;
   uint64_t* tz = tw + tiles;
   uint64_t* tm = tz + tiles;
-  hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, s,
+  QOZ_LAUNCH(k_scan_tiles, dim3(tiles), dim3(kScanThreads), 0, s,
                      chunk_bits, chunk_zeros, n_chunks, tw, tz, tm);
-  hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kScanThreads), 0, s,
+  QOZ_LAUNCH(k_scan_apply, dim3(tiles), dim3(kScanThreads), 0, s,
                      chunk_bits, chunk_zeros, n_chunks, tw, tz, tm, coff,
                      upre, totals);
 }
 
 /* words of a chunk: at most 56 bits per bin (the encoder table's limit) */
 constexpr uint32_t kEncMaxWords = kChunk * 56 / 32;
-/* code table entries kept in LDS: (code << 6) | length for codes of at
- * most 26 bits, kEncFar for a longer code (read from the global table) */
+/* code table entries kept in LDS (a window of the field's table) */
 constexpr uint32_t kEncTab = 4096;
-constexpr uint32_t kEncFar = 0xffffffffu;
 
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
-                                                    uint32_t* total) {
-  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (uint32_t o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(x, o, 64);
-    x += lane >= o ? t : 0u;
-  }
-  if (lane == 63) ws[wave] = x;
-  __syncthreads();
-  uint32_t pre = 0, tot = 0;
-#pragma unroll
-  for (uint32_t w = 0; w < kEncThreads / 64; ++w) {
-    pre += w < wave ? ws[w] : 0u;
-    tot += ws[w];
-  }
-  *total = tot;
-  return pre + x - v;
+/* First table index of the LDS window of a code table over symbols
+ * [lo, lo + tn): the window of w entries is centred on the zero-residual
+ * symbol R, where the bins concentrate, and kept inside the table. */
+__device__ __forceinline__ uint32_t table_window(int32_t lo, uint32_t tn,
+                                                 uint32_t w) {
+  if (tn <= w) return 0;
+  const int32_t want = kRadius - (int32_t)(w / 2) - lo;
+  const int32_t top = (int32_t)(tn - w);
+  return (uint32_t)(want < 0 ? 0 : want > top ? top : want);
 }
 
 /* Code bits and symbol-0 bins of every chunk, the counts the chunk scan
  * turns into payload offsets and unpredictable ranks before encoding.  A
  * workgroup takes kCountChunks consecutive chunks of one field (the
  * field's workgroups start at wg0[f]) with the field's code lengths in LDS
- * (from the global table beyond kCountLens symbols); a wave counts one
+ * (a window of kCountLens symbols centred on the zero residual; the rest
+ * from the global table); a wave counts one
  * chunk, each lane 8 groups of 8 bins read as 16-byte loads (chunks start
  * on a multiple of 64 bins).  Counts go to bits[chunk0[f] + c] and
  * zeros[chunk0[f] + c]. */
@@ -434,10 +397,11 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
   const EncField& F = fields[f];
   const uint32_t tn = F.tn;
   const uint32_t tl = tn < kCountLens ? tn : kCountLens;
-  for (uint32_t i = threadIdx.x; i < tl; i += kCountThreads)
-    lens[i] = (uint8_t)(F.tab[i] & 0xff);
-  __syncthreads();
   const int32_t lo = F.lo;
+  const uint32_t wo = table_window(lo, tn, kCountLens);
+  for (uint32_t i = threadIdx.x; i < tl; i += kCountThreads)
+    lens[i] = (uint8_t)(F.tab[wo + i] & 0xff);
+  __syncthreads();
   const uint32_t zlen = (uint32_t)(F.zero_entry & 0xff);
   const uint64_t c0 = (uint64_t)(blockIdx.x - wg0[f]) * kCountChunks;
   const uint64_t c1 = c0 + kCountChunks < F.nch ? c0 + kCountChunks : F.nch;
@@ -445,7 +409,7 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
   auto add = [&](uint32_t sym, uint32_t& bits, uint32_t& zeros) {
     const uint32_t o = sym - (uint32_t)lo;
     const uint32_t l = sym == 0 ? zlen
-                       : o < tl ? (uint32_t)lens[o]
+                       : o - wo < tl ? (uint32_t)lens[o - wo]
                        : o < tn ? (uint32_t)(F.tab[o] & 0xff)
                                 : 0u;
     bits += l;
@@ -493,7 +457,7 @@ void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
                        const uint32_t* wg0, uint32_t nf, uint32_t total_wg,
                        uint32_t* bits, uint32_t* zeros, hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_huff_count, dim3(total_wg), dim3(kCountThreads), 0, s,
+  QOZ_LAUNCH(k_huff_count, dim3(total_wg), dim3(kCountThreads), 0, s,
                      fields, chunk0, wg0, nf, bits, zeros);
 }
 
@@ -501,200 +465,257 @@ void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
  * chunk scan: gw and gz are the exclusive prefixes of the chunks' payload
  * words and symbol-0 bins over the global chunk order (a field's offsets
  * are differences of them).  Workgroup w codes global chunks (field after
- * field) w, w + G, w + 2G, ... for a grid of G, and loads the next one's
- * bins while the current one is coded.  Per chunk: segment-major
- * staging of the bins in LDS (segment j holds the chunk's bins j, j + 8,
- * ...), lane t codes bins k in [16 (t mod 32), +16) of segment t / 32 with
- * the field's code table in LDS (reloaded when the field changes), block
- * scans of the bit counts (thread order = payload order) and of the
- * symbol-0 counts, codes ORed into a zeroed LDS word buffer without
- * branches, unpredictable values gathered in bin order at their ranks, the
- * chunk's size under zero-word packing counted (and added to the field's
- * packed total), and the words stored.  The chunk offsets, unpredictable
- * ranks and segment lengths go straight to their stream sections; a
- * field's last chunk also writes its totals (payload words, symbol-0
- * bins).  No workgroup waits for another. */
+ * field) w, w + G, w + 2G, ... for a grid of G as large as the device
+ * holds at once, and loads the next chunk's bins while it codes the
+ * current one.  Per chunk:
+ *   - segment-major staging of the bins in LDS (segment j holds the
+ *     chunk's bins j, j + 8, ...; bins past the chunk's end stage as 1);
+ *   - thread t codes bins [16 (t mod 32), +16) of segment t / 32 (thread
+ *     order is payload order) with the field's code table: a window of it
+ *     in LDS, reloaded when the field changes; a symbol outside the window
+ *     is read from the global table in a branch of its own;
+ *   - block scans of the bit counts and of the bin-0 counts;
+ *   - the codes packed MSB-first into an LDS word buffer: a completed word
+ *     is a plain store, the two words a thread may share with its
+ *     neighbours are ORed into the zeroed buffer;
+ *   - the chunk's size under zero-word packing counted (and added to the
+ *     field's packed total), the words stored at the chunk's offset, the
+ *     chunk offset, unpredictable rank and segment lengths written to
+ *     their stream sections, and the exact values of bin-0 bins gathered
+ *     in bin order at their ranks.
+ * A field's last chunk also writes its totals (payload words, symbol-0
+ * bins).  No workgroup waits for another.  The field records are read
+ * through the constant address space: they are not written while the
+ * kernel runs, so the reads are scalar loads, which neither wait for nor
+ * hold up the vector loads and stores in flight (a record read as a plain
+ * load is a vector load, whose wait would also wait for the next chunk's
+ * bins and for the stores). */
+#define QOZ_CONST __attribute__((address_space(4)))
+__device__ __forceinline__ uint64_t chunk_begin(const QOZ_CONST Chunks& ch,
+                                                uint64_t c) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t i = 1; i < QOZ_MAX_LEVELS; ++i)
+    r += (i < ch.n && c >= ch.first[i]) ? 1u : 0u;
+  return ch.start[r] + (c - ch.first[r]) * ch.size[r];
+}
+__device__ __forceinline__ uint32_t chunk_bins(const QOZ_CONST Chunks& ch,
+                                               uint64_t c) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t i = 1; i < QOZ_MAX_LEVELS; ++i)
+    r += (i < ch.n && c >= ch.first[i]) ? 1u : 0u;
+  const uint64_t b = ch.start[r] + (c - ch.first[r]) * ch.size[r];
+  const uint64_t e = b + ch.size[r];
+  return (uint32_t)((e < ch.start[r + 1] ? e : ch.start[r + 1]) - b);
+}
+
+constexpr uint32_t kEncThreads = 256;
+constexpr uint32_t kEncLaneBins = kChunk / kEncThreads;    /* 16 */
+constexpr uint32_t kEncRounds = kChunk / (8 * kEncThreads); /* 2 */
+constexpr uint32_t kEncLanesPerSeg = kSeg / kEncLaneBins;   /* 32 */
+static_assert(kEncLanesPerSeg * kEncLaneBins == kSeg, "segment lanes");
+static_assert(kEncRounds == 2 && kChunk / kSegPerChunk == kSeg,
+              "chunk layout");
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
+                                                    uint32_t* total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(x, o, 64);
+    x += lane >= o ? t : 0u;
+  }
+  if (lane == 63) ws[wave] = x;
+  __syncthreads();
+  uint32_t pre = 0, tot = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < kEncThreads / 64; ++w) {
+    pre += w < wave ? ws[w] : 0u;
+    tot += ws[w];
+  }
+  *total = tot;
+  return pre + x - v;
+}
+
 template <bool kLong> /* kLong: some code is longer than 32 bits */
 __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
     const EncField* __restrict__ fields, const uint64_t* __restrict__ chunk0,
     const uint64_t* __restrict__ gw, const uint64_t* __restrict__ gz,
-    uint32_t nf, uint64_t n_total, uint32_t max_words) {
-  constexpr uint32_t kRounds = kChunk / (8 * kEncThreads); /* 2 */
-  constexpr uint32_t kSegBins = kChunk / kSegPerChunk;      /* 512 */
-  constexpr uint32_t kLanesPerSeg = kSeg / kEncPerThread;
-  static_assert(kLanesPerSeg * kEncPerThread == kSeg, "segment lanes");
-  static_assert(kRounds == 2 && kSegBins == kSeg, "chunk layout");
-  extern __shared__ uint32_t words[];
+    uint32_t nf, uint64_t n_total, uint32_t tcap, uint32_t max_words) {
+  extern __shared__ uint64_t lds64[];
+  uint64_t* tabl = lds64;                                   /* tcap */
+  uint32_t* words = reinterpret_cast<uint32_t*>(lds64 + tcap); /* max_words + 1 */
   __shared__ __align__(16) uint16_t cbin[kChunk];
-  __shared__ uint32_t tabl[kEncTab];
   __shared__ uint32_t ws[2][kEncThreads / 64];
   __shared__ uint32_t seg_end[kSegPerChunk];
-  __shared__ uint32_t nz_words;
-  const uint32_t tid = threadIdx.x;
-  /* field of global chunk c2: the number of fields f with chunk0[f] <= c2,
-   * less one (64 entries per ballot; every wave finds it on its own) */
+  __shared__ uint32_t s_nz;
+  const QOZ_CONST EncField* cfields = (const QOZ_CONST EncField*)fields;
+  const uint32_t tid = threadIdx.x, lane = tid & 63u;
+  /* field of global chunk c2 (uniform, scalar) */
+  const uint64_t c0_lane = lane < nf ? chunk0[lane] : ~0ull;
   auto field_of = [&](uint64_t c2) -> uint32_t {
-    const uint32_t lane = tid & 63u;
+    if (nf <= 64) /* chunk0 in registers, one entry per lane */
+      return __builtin_amdgcn_readfirstlane(
+          (uint32_t)__popcll(__ballot(c0_lane <= c2)) - 1);
     uint32_t cnt = 0;
     for (uint32_t b = 0; b < nf; b += 64) {
       const uint32_t i = b + lane;
       cnt += (uint32_t)__popcll(__ballot(i < nf && chunk0[i] <= c2));
     }
-    return cnt - 1;
+    return __builtin_amdgcn_readfirstlane(cnt - 1);
   };
-  for (uint32_t i = tid; i < max_words + 1; i += kEncThreads) words[i] = 0;
-  /* chunks blockIdx.x, + gridDim.x, ... (no shared counter: every chunk's
-   * offsets are known, and a counter that all workgroups hit serializes) */
-  const uint64_t stride = gridDim.x;
-  uint64_t cn = blockIdx.x;
-  uint32_t fn = cn < n_total ? field_of(cn) : 0u;
-  /* the field's packed words so far (thread 0), added to its total when
-   * the field changes and at the end: one atomic per field and workgroup */
-  uint32_t pk_field = ~0u;
-  uint64_t pk_acc = 0;
-  /* this lane's two 8-bin groups of a chunk: m = t + 256 r */
-  uint4 qr[kRounds];
+  /* this thread's staging groups m = t + 256 r of a chunk */
+  uint4 qr[kEncRounds];
   auto load_bins = [&](uint64_t c2, uint32_t f2) {
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
-      qr[r] = make_uint4(0, 0, 0, 0);
-      if (c2 < n_total) {
-        const EncField& F2 = fields[f2];
-        const uint64_t cl = c2 - chunk0[f2];
-        const uint64_t b2 = F2.ch.begin(cl);
-        const uint32_t n2 = (uint32_t)(F2.ch.end(cl) - b2);
-        const uint32_t m = tid + r * kEncThreads;
-        if (8 * m + 8 <= n2)
-          qr[r] = *reinterpret_cast<const uint4*>(F2.codes + b2 + 8 * m);
-      }
+    for (uint32_t r = 0; r < kEncRounds; ++r) qr[r] = make_uint4(0, 0, 0, 0);
+    if (c2 >= n_total) return;
+    const QOZ_CONST EncField& F2 = cfields[f2];
+    const uint64_t cl = c2 - chunk0[f2];
+    const uint64_t b2 = chunk_begin(F2.ch, cl);
+    const uint32_t n2 = chunk_bins(F2.ch, cl);
+#pragma unroll
+    for (uint32_t r = 0; r < kEncRounds; ++r) {
+      const uint32_t m = tid + kEncThreads * r;
+      /* a group the chunk ends in reads up to 7 bins past it: the bins of
+       * the next chunk, or the 16 bins of padding after the last */
+      if (8 * m < n2) qr[r] = gload16(F2.codes + b2 + 8 * m);
     }
   };
-  load_bins(cn, fn);
-  uint32_t dirty = 0;      /* words of the previous chunk (to zero again) */
-  uint32_t loaded = ~0u;   /* field whose code table is in LDS */
-  uint32_t tw = 0, tn = 0; /* its table window and range */
-  int32_t lo = 0;
-  uint64_t zero_entry = 0;
-  while (cn < n_total) {
+  for (uint32_t i = tid; i <= max_words; i += kEncThreads) words[i] = 0;
+  if (tid == 0) s_nz = 0;
+  uint64_t g = blockIdx.x;
+  uint32_t fn = g < n_total ? field_of(g) : 0u;
+  load_bins(g, fn);
+  uint32_t loaded = ~0u; /* field whose table window is in LDS */
+  uint32_t tw = 0, wo = 0;
+  uint32_t dirty = 0;       /* words of the previous chunk (to zero again) */
+  uint32_t pk_field = ~0u;  /* thread 0: packed words of pk_field so far */
+  uint64_t pk_acc = 0;
+  const uint32_t j = tid / kEncLanesPerSeg;
+  const uint32_t k0 = (tid % kEncLanesPerSeg) * kEncLaneBins;
+  while (g < n_total) {
     const uint32_t f = fn;
-    const EncField& F = fields[f];
-    const uint64_t c = cn - chunk0[f]; /* chunk within the field */
-    const uint64_t base = F.ch.begin(c);
-    const uint32_t nsym = (uint32_t)(F.ch.end(c) - base);
-    const uint64_t cur = cn;
-    /* the next chunk; its bins load while this one is coded */
-    cn = cur + stride;
-    fn = cn < n_total ? field_of(cn) : 0u;
-    if (f != loaded) { /* the field's code table (after the last barrier) */
-      tn = F.tn;
-      tw = tn < kEncTab ? tn : kEncTab;
-      lo = F.lo;
-      zero_entry = F.zero_entry;
-      for (uint32_t i = tid; i < tw; i += kEncThreads) {
-        const uint64_t e = F.tab[i];
-        const uint32_t len = (uint32_t)(e & 0xff);
-        tabl[i] = len <= 26 ? (uint32_t)((e >> 8) << 6) | len : kEncFar;
-      }
+    const QOZ_CONST EncField& F = cfields[f];
+    const int32_t lo = F.lo;
+    const uint32_t tn = F.tn;
+    const uint64_t zero_entry = F.zero_entry;
+    if (f != loaded) { /* the last barrier ended every use of the old one */
+      tw = tn < tcap ? tn : tcap;
+      wo = table_window(lo, tn, tcap);
+      for (uint32_t i = tid; i < tw; i += kEncThreads)
+        tabl[i] = gptr(F.tab)[wo + i];
       loaded = f;
     }
-    uint32_t v[kRounds][8];
-    uint32_t zpack = 0;
+    const uint64_t c = g - chunk0[f]; /* chunk within the field */
+    const uint64_t base = chunk_begin(F.ch, c);
+    const uint32_t nsym = chunk_bins(F.ch, c);
+    /* the chunk's word and unpredictable offsets within its field */
+    const uint64_t w0 = gw[g] - gw[chunk0[f]];
+    const uint64_t u0 = gz[g] - gz[chunk0[f]];
+    /* a full chunk whose field's table lies in the LDS window needs no
+     * checks per bin (the common case) */
+    const bool fast = nsym == kChunk && tw == tn && f == loaded;
+    /* staging: bin 8 m + i to segment i, position m */
+    uint32_t zpack = 0; /* bin-0 count of round r in bits [16 r, +16) */
+    uint32_t zmask = 0; /* bit 8 r + i: bin 8 m + i of round r is 0 */
 #pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
-      const uint32_t m = tid + r * kEncThreads;
-      if (8 * m + 8 <= nsym) {
-        const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
-#pragma unroll
-        for (uint32_t i = 0; i < 8; ++i)
-          v[r][i] = (w[i / 2] >> (16 * (i & 1))) & 0xffffu;
-      } else {
-#pragma unroll
-        for (uint32_t i = 0; i < 8; ++i)
-          v[r][i] = 8 * m + i < nsym ? F.codes[base + 8 * m + i] : 1u;
-      }
+    for (uint32_t r = 0; r < kEncRounds; ++r) {
+      const uint32_t m = tid + kEncThreads * r;
+      const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
       uint32_t z = 0;
 #pragma unroll
       for (uint32_t i = 0; i < 8; ++i) {
-        cbin[i * kSegBins + m] = (uint16_t)v[r][i];
-        z += v[r][i] == 0 ? 1u : 0u;
+        const uint32_t v = fast || 8 * m + i < nsym
+                               ? (w[i / 2] >> (16 * (i & 1))) & 0xffffu
+                               : 1u;
+        cbin[i * kSeg + m] = (uint16_t)v;
+        z += v == 0 ? 1u : 0u;
+        zmask |= (v == 0 ? 1u : 0u) << (8 * r + i);
       }
       zpack |= z << (16 * r);
     }
     for (uint32_t i = tid; i < dirty; i += kEncThreads) words[i] = 0;
     __syncthreads();
-    load_bins(cn, fn);
-    const uint32_t j = tid / kLanesPerSeg;
-    const uint32_t k0 = (tid % kLanesPerSeg) * kEncPerThread;
-    uint64_t ent[kEncPerThread];
+    /* the next chunk's bins load while this one is coded */
+    const uint64_t gn = g + gridDim.x;
+    fn = gn < n_total ? field_of(gn) : 0u;
+    load_bins(gn, fn);
+    /* the thread's 16 code table entries ((code << 8) | length; 0 past the
+     * chunk's end); symbols outside the LDS window in a branch of their
+     * own, so that its wait (which would also wait for the bins in flight)
+     * stays off the common path */
+    uint64_t ent[kEncLaneBins];
     uint32_t bits = 0;
     {
-      const uint4* cb =
-          reinterpret_cast<const uint4*>(cbin + j * kSegBins + k0);
+      const uint4* cb = reinterpret_cast<const uint4*>(cbin + j * kSeg + k0);
       const uint4 qa = cb[0], qb = cb[1];
       const uint32_t w[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+      if (fast) {
 #pragma unroll
-      for (uint32_t k = 0; k < kEncPerThread; ++k) {
-        const uint32_t b = (k0 + k) * kSegPerChunk + j; /* bin in the chunk */
-        const int32_t sym = (int32_t)((w[k / 2] >> (16 * (k & 1))) & 0xffffu);
-        uint64_t e = 0;
-        if (b < nsym) {
-          const uint32_t o = (uint32_t)(sym - lo);
-          if (sym == 0) {
-            e = zero_entry;
-          } else if (o < tw) {
-            const uint32_t t = tabl[o];
-            e = t != kEncFar ? ((uint64_t)(t >> 6) << 8) | (t & 63u)
-                             : F.tab[o];
-          } else if (o < tn) {
-            e = F.tab[o];
-          }
+        for (uint32_t k = 0; k < kEncLaneBins; ++k) {
+          const uint32_t sym = (w[k / 2] >> (16 * (k & 1))) & 0xffffu;
+          ent[k] = sym == 0 ? zero_entry : tabl[sym - (uint32_t)lo];
+          bits += (uint32_t)(ent[k] & 0xff);
         }
-        ent[k] = e;
-        bits += (uint32_t)(e & 0xff);
+      } else {
+        uint32_t far = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kEncLaneBins; ++k) {
+          const uint32_t b = (k0 + k) * kSegPerChunk + j;
+          const uint32_t sym = (w[k / 2] >> (16 * (k & 1))) & 0xffffu;
+          const uint32_t o = sym - (uint32_t)lo;
+          const uint32_t ow = o - wo;
+          const bool in = b < nsym;
+          const bool near = f == loaded && ow < tw;
+          ent[k] = !in ? 0ull : sym == 0 ? zero_entry : near ? tabl[ow] : 0ull;
+          far |= (in && sym != 0 && !near && o < tn ? 1u : 0u) << k;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kEncLaneBins; ++k)
+          bits += (uint32_t)(ent[k] & 0xff);
+        if (far) {
+#pragma unroll
+          for (uint32_t k = 0; k < kEncLaneBins; ++k)
+            if ((far >> k) & 1u) {
+              const uint32_t sym = (w[k / 2] >> (16 * (k & 1))) & 0xffffu;
+              ent[k] = gptr(F.tab)[sym - (uint32_t)lo];
+              bits += (uint32_t)(ent[k] & 0xff);
+            }
+        }
       }
     }
     uint32_t tot_bits, tot_z;
     const uint32_t pos0 = block_excl_scan(bits, ws[0], &tot_bits);
     const uint32_t zex = block_excl_scan(zpack, ws[1], &tot_z);
     const uint32_t nw = (tot_bits + 31) / 32;
-    const uint32_t zc = (tot_z & 0xffffu) + (tot_z >> 16);
-    if (tid % kLanesPerSeg == kLanesPerSeg - 1) seg_end[j] = pos0 + bits;
-    /* the chunk's word and unpredictable offsets within its field */
-    const uint64_t w0 = gw[cur] - gw[chunk0[f]];
-    const uint64_t u0 = gz[cur] - gz[chunk0[f]];
-    if (tid == 0) {
-      F.coff[c] = w0;
-      F.upre[c] = (uint32_t)u0;
-      if (c + 1 == F.nch) {
-        F.coff[F.nch] = w0 + nw;
-        F.upre[F.nch] = (uint32_t)(u0 + zc);
-        F.totals[0] = w0 + nw;
-        F.totals[1] = u0 + zc;
-      }
-      nz_words = 0;
-    }
-    __syncthreads();
-    if (tid < kSegPerChunk - 1)
-      F.segs[c * (kSegPerChunk - 1) + tid] =
-          (uint16_t)(seg_end[tid] - (tid ? seg_end[tid - 1] : 0u));
-    /* This lane's bits [pos0, pos0 + bits), MSB-first: acc holds the bits
-     * not yet written in its low nacc (< 32) bits; every complete word is
-     * ORed into the zeroed chunk words (a lane's first and last words are
-     * shared with its neighbours), a code that completes no word ORs 0
-     * into the current word, so the stores need no branch. */
+    if (tid % kEncLanesPerSeg == kEncLanesPerSeg - 1) seg_end[j] = pos0 + bits;
     {
+      /* acc holds the bits not yet written in its low nacc (< 32) bits; a
+       * completed word is a plain store, except the thread's first word,
+       * which it may share with the threads before it: that one and the
+       * last partial word (shared with the threads after) are ORed in */
       uint64_t acc = 0;
-      uint32_t nacc = pos0 & 31u, wi = pos0 >> 5;
+      const uint32_t first = pos0 >> 5;
+      uint32_t nacc = pos0 & 31u, wi = first;
+      uint32_t firstw = 0;
       auto put = [&](uint32_t code, uint32_t len) { /* len <= 32 */
         acc = (acc << len) | code;
         nacc += len;
-        const bool full = nacc >= 32;
-        nacc -= full ? 32u : 0u;
-        atomicOr(&words[wi], full ? (uint32_t)(acc >> nacc) : 0u);
-        wi += full ? 1u : 0u;
+        if (nacc >= 32) {
+          nacc -= 32;
+          const uint32_t v = (uint32_t)(acc >> nacc);
+          if (wi == first)
+            firstw = v;
+          else
+            words[wi] = v;
+          ++wi;
+        }
       };
 #pragma unroll
-      for (uint32_t k = 0; k < kEncPerThread; ++k) {
+      for (uint32_t k = 0; k < kEncLaneBins; ++k) {
         const uint32_t len = (uint32_t)(ent[k] & 0xff);
         const uint64_t code = ent[k] >> 8;
         if (kLong && len > 32) {
@@ -704,41 +725,63 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
           put((uint32_t)code, len);
         }
       }
-      if (nacc) atomicOr(&words[wi], (uint32_t)(acc << (32 - nacc)));
-    }
-    uint64_t zr[kRounds] = {u0 + (zex & 0xffffu),
-                            u0 + (tot_z & 0xffffu) + (zex >> 16)};
-#pragma unroll
-    for (uint32_t r = 0; r < kRounds; ++r) {
-      const uint32_t m = tid + r * kEncThreads;
-#pragma unroll
-      for (uint32_t i = 0; i < 8; ++i)
-        if (v[r][i] == 0) {
-          F.unpred[zr[r]] = F.x[point_of(F.st, F.g, base + 8 * m + i)];
-          ++zr[r];
-        }
+      const uint32_t tail = nacc ? (uint32_t)(acc << (32 - nacc)) : 0u;
+      if (wi == first)
+        firstw |= tail; /* the thread's bits end in its first word */
+      else if (nacc)
+        atomicOr(&words[wi], tail);
+      if (bits) atomicOr(&words[first], firstw);
     }
     __syncthreads();
+    if (tid < kSegPerChunk - 1)
+      gptr(F.segs)[c * (kSegPerChunk - 1) + tid] =
+          (uint16_t)(seg_end[tid] - (tid ? seg_end[tid - 1] : 0u));
     /* the chunk's size under zero-word packing (bitmap + nonzero words
-     * when shorter, else raw), scanned afterwards for the packing decision
-     * and the packed offsets */
-    uint32_t nzc = 0;
-    for (uint32_t i = tid; i < nw; i += kEncThreads) nzc += words[i] != 0u;
-    for (uint32_t o = 32; o > 0; o >>= 1) nzc += __shfl_xor(nzc, o, 64);
-    if ((tid & 63u) == 0) atomicAdd(&nz_words, nzc);
-    bool over = false;
-    for (uint32_t i = tid; i < nw; i += kEncThreads) {
-      if (w0 + i < F.cap_words)
-        F.payload[w0 + i] = words[i];
-      else
-        over = true;
+     * when shorter, else raw), and the stores */
+    {
+      uint32_t nz = 0;
+      bool over = false;
+      for (uint32_t i = tid; i < nw; i += kEncThreads) {
+        const uint32_t v = words[i];
+        nz += v != 0u ? 1u : 0u;
+        if (w0 + i < F.cap_words)
+          gptr(F.payload)[w0 + i] = v;
+        else
+          over = true;
+      }
+      nz = wave_sum_u32(nz);
+      if (lane == 0 && nz) atomicAdd(&s_nz, nz);
+      if (__ballot(over) != 0 && lane == 0) atomicOr(F.status, kStOverflow);
     }
-    if (over) atomicOr(F.status, kStOverflow);
+    /* bin-0 values in bin order (ascending bits of zmask within each
+     * round), each round ranked from its own prefix */
+    if (zmask) {
+      uint64_t zr[kEncRounds] = {u0 + (zex & 0xffffu),
+                                 u0 + (tot_z & 0xffffu) + (zex >> 16)};
+      for (uint32_t zm = zmask; zm; zm &= zm - 1) {
+        const uint32_t k = (uint32_t)__ffs(zm) - 1;
+        const uint32_t r = k >> 3;
+        const uint64_t rank = r ? zr[1]++ : zr[0]++;
+        const uint32_t m = tid + kEncThreads * r;
+        gptr(F.unpred)[rank] = gptr(F.x)[point_of(
+            fields[f].st, fields[f].g, base + 8 * m + (k & 7))];
+      }
+    }
     __syncthreads();
     if (tid == 0) {
+      const uint32_t zc = (tot_z & 0xffffu) + (tot_z >> 16);
+      gptr(F.coff)[c] = w0;
+      gptr(F.upre)[c] = (uint32_t)u0;
+      if (c + 1 == F.nch) {
+        gptr(F.coff)[F.nch] = w0 + nw;
+        gptr(F.upre)[F.nch] = (uint32_t)(u0 + zc);
+        gptr(F.totals)[0] = w0 + nw;
+        gptr(F.totals)[1] = u0 + zc;
+      }
       const uint32_t nbm = (nw + 31) / 32;
-      const uint32_t pw = nbm + nz_words < nw ? nbm + nz_words : nw;
-      F.pack_bits[c] = 32 * pw;
+      const uint32_t pw = nbm + s_nz < nw ? nbm + s_nz : nw;
+      s_nz = 0;
+      gptr(F.pack_bits)[c] = 32 * pw;
       if (f != pk_field) {
         if (pk_field != ~0u)
           atomicAdd((unsigned long long*)&fields[pk_field].totals[2],
@@ -749,20 +792,11 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
       pk_acc += pw;
     }
     dirty = nw + 1;
+    g = gn;
   }
   if (tid == 0 && pk_field != ~0u)
     atomicAdd((unsigned long long*)&fields[pk_field].totals[2],
               (unsigned long long)pk_acc);
-}
-
-uint32_t encode_workgroups() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                            dev) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  return 4u * (uint32_t)cus;
 }
 
 uint32_t encode_max_words(uint32_t max_len) {
@@ -772,18 +806,35 @@ uint32_t encode_max_words(uint32_t max_len) {
 
 void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
                         const uint64_t* gw, const uint64_t* gz, uint32_t nf,
-                        uint64_t n_chunks, uint32_t max_words,
-                        bool long_codes, uint32_t n_wg, hipStream_t s) {
+                        uint64_t n_chunks, uint32_t max_words, uint32_t max_tn,
+                        bool long_codes, hipStream_t s) {
   if (!n_chunks || !nf) return;
-  const size_t lds = 4 * ((size_t)max_words + 1);
+  /* LDS: the table window, then the chunk's words */
+  const uint32_t tcap = max_tn < kEncTab ? (max_tn ? max_tn : 1u) : kEncTab;
+  const size_t lds = 8 * (size_t)tcap + 4 * ((size_t)max_words + 1);
+  /* as many workgroups as can be resident at once (each takes every
+   * grid-th chunk, so one that waits for a slot would finish last) */
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu,
+          long_codes ? reinterpret_cast<const void*>(k_huff_encode<true>)
+                     : reinterpret_cast<const void*>(k_huff_encode<false>),
+          kEncThreads, lds) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  const uint64_t n_wg = (uint64_t)cus * (uint64_t)per_cu;
   const uint32_t grid = (uint32_t)(n_chunks < n_wg ? n_chunks : n_wg);
   if (long_codes)
-    hipLaunchKernelGGL(k_huff_encode<true>, dim3(grid), dim3(kEncThreads), lds,
-                       s, fields, chunk0, gw, gz, nf, n_chunks, max_words);
+    QOZ_LAUNCH(k_huff_encode<true>, dim3(grid), dim3(kEncThreads), lds, s,
+               fields, chunk0, gw, gz, nf, n_chunks, tcap, max_words);
   else
-    hipLaunchKernelGGL(k_huff_encode<false>, dim3(grid), dim3(kEncThreads),
-                       lds, s, fields, chunk0, gw, gz, nf, n_chunks,
-                       max_words);
+    QOZ_LAUNCH(k_huff_encode<false>, dim3(grid), dim3(kEncThreads), lds, s,
+               fields, chunk0, gw, gz, nf, n_chunks, tcap, max_words);
 }
 
 }  // namespace qoz

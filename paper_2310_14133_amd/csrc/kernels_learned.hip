@@ -468,12 +468,12 @@ void launch_block_features(const float* x, const Geo& g,
                            float* feat, float* aux, float* mean,
                            uint32_t* status, hipStream_t s) {
   if (g.n[0] == 1) /* a 2D field: its geometry has a single plane */
-    hipLaunchKernelGGL(k_block_features_2d, dim3(nb), dim3(kF2Threads), 0, s,
+    QOZ_LAUNCH(k_block_features_2d, dim3(nb), dim3(kF2Threads), 0, s,
                        x, g, origins, e, feat, aux);
   else
-    hipLaunchKernelGGL(k_block_features, dim3(nb, 3), dim3(kFeatThreads),
+    QOZ_LAUNCH(k_block_features, dim3(nb, 3), dim3(kFeatThreads),
                        block_features_lds(), s, x, g, origins, e, feat, aux);
-  hipLaunchKernelGGL(k_feat_pool, dim3(1), dim3(64), 0, s, feat,
+  QOZ_LAUNCH(k_feat_pool, dim3(1), dim3(64), 0, s, feat,
                      (const float*)aux, nb, e, mean, status);
 }
 
@@ -811,7 +811,7 @@ bool mlp_fit() {
 
 void launch_mlp_forward(const float* P, const float* X, uint32_t B,
                         float* logits, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp<false>, dim3(mlp_tiles(B)), dim3(kMlpThreads),
+  QOZ_LAUNCH(k_mlp<false>, dim3(mlp_tiles(B)), dim3(kMlpThreads),
                      L_FWD_END, s, P, X, (const int32_t*)nullptr,
                      (const uint32_t*)nullptr, B, B, logits, (float*)nullptr,
                      (double*)nullptr);
@@ -820,7 +820,7 @@ void launch_mlp_forward(const float* P, const float* X, uint32_t B,
 void launch_mlp_grad(const float* P, const float* X, const int32_t* labels,
                      const uint32_t* index, uint32_t n_rows, uint32_t B,
                      float* part, double* loss_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp<true>, dim3(mlp_tiles(B)), dim3(kMlpThreads),
+  QOZ_LAUNCH(k_mlp<true>, dim3(mlp_tiles(B)), dim3(kMlpThreads),
                      L_END, s, P, X, labels, index, n_rows, B, (float*)nullptr,
                      part, loss_part);
 }
@@ -830,7 +830,7 @@ void launch_mlp_reduce(const float* part, uint32_t nw, float* grad, float* P,
                        bool adam, const double* loss_part, uint32_t B,
                        double* loss, hipStream_t s) {
   const uint32_t nt = 256, nb = (kMlpParams + nt - 1) / nt;
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(nb), dim3(nt), 0, s, part, nw, grad,
+  QOZ_LAUNCH(k_mlp_reduce, dim3(nb), dim3(nt), 0, s, part, nw, grad,
                      P, m, v, lr, bc1, bc2, adam ? 1 : 0, loss_part, B, loss);
 }
 

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kRedThreads) void k_range(
 void launch_range(const float* x, uint64_t n, float* part_min,
                   float* part_max, uint32_t* status, uint32_t nparts,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_range, dim3(nparts), dim3(kRedThreads), 0, s, x, n,
+  QOZ_LAUNCH(k_range, dim3(nparts), dim3(kRedThreads), 0, s, x, n,
                      part_min, part_max, status);
 }
 
@@ -205,9 +205,9 @@ void launch_ac_field(const float* x, const float* y, uint64_t nrows,
                      uint32_t len, double* p0, double* p1, hipStream_t s) {
   uint64_t per;
   const uint32_t parts = ac_parts(nrows, len, &per);
-  hipLaunchKernelGGL(k_ac_field, dim3(parts), dim3(kRedThreads), 0, s, x, y,
+  QOZ_LAUNCH(k_ac_field, dim3(parts), dim3(kRedThreads), 0, s, x, y,
                      nrows, len, per, 0, (const double*)nullptr, p0);
-  hipLaunchKernelGGL(k_ac_field, dim3(parts), dim3(kRedThreads), 0, s, x, y,
+  QOZ_LAUNCH(k_ac_field, dim3(parts), dim3(kRedThreads), 0, s, x, y,
                      nrows, len, per, 1, (const double*)p0, p1);
 }
 
@@ -229,9 +229,9 @@ __global__ __launch_bounds__(kRedThreads) void k_ac_items(
 void launch_ac_items(const float* xs, const float* wt, uint32_t ntrial,
                      uint32_t nb, uint32_t size, uint32_t len, double* p0,
                      double* p1, hipStream_t s) {
-  hipLaunchKernelGGL(k_ac_items, dim3(ntrial, nb), dim3(kRedThreads), 0, s,
+  QOZ_LAUNCH(k_ac_items, dim3(ntrial, nb), dim3(kRedThreads), 0, s,
                      xs, wt, nb, size, len, 0, (const double*)nullptr, p0);
-  hipLaunchKernelGGL(k_ac_items, dim3(ntrial, nb), dim3(kRedThreads), 0, s,
+  QOZ_LAUNCH(k_ac_items, dim3(ntrial, nb), dim3(kRedThreads), 0, s,
                      xs, wt, nb, size, len, 1, (const double*)p0, p1);
 }
 
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kRedThreads) void k_sse_max(
 void launch_sse_max(const float* x, const float* y, uint64_t n,
                     double* part_sse, double* part_max, uint32_t nparts,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_sse_max, dim3(nparts), dim3(kRedThreads), 0, s, x, y,
+  QOZ_LAUNCH(k_sse_max, dim3(nparts), dim3(kRedThreads), 0, s, x, y,
                      n, part_sse, part_max);
 }
 
@@ -414,7 +414,7 @@ bool launch_ssim(const SsimJob& j, const float* x, const float* y,
                                   kSsimLdsMax) == hipSuccess;
   });
   if (!ok[dev] || ssim_lds(j) > (size_t)kSsimLdsMax) return false;
-  hipLaunchKernelGGL(k_ssim, ssim_grid(j), dim3(kSsThreads), ssim_lds(j), s,
+  QOZ_LAUNCH(k_ssim, ssim_grid(j), dim3(kSsThreads), ssim_lds(j), s,
                      j, x, y, parts);
   return true;
 }

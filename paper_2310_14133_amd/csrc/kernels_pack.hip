@@ -109,7 +109,7 @@ void launch_pack_write(const uint32_t* raw, const uint64_t* coff,
                        uint32_t* dst, hipStream_t s) {
   if (!n_chunks) return;
   const uint64_t blocks = (n_chunks + kPackWaves - 1) / kPackWaves;
-  hipLaunchKernelGGL(k_pack_write, dim3((uint32_t)blocks), dim3(kPackThreads),
+  QOZ_LAUNCH(k_pack_write, dim3((uint32_t)blocks), dim3(kPackThreads),
                      0, s, raw, coff, pcoff, n_chunks, dst);
 }
 
@@ -119,7 +119,7 @@ void launch_unpack(const uint32_t* src, uint64_t n_packed,
                    uint32_t* status, hipStream_t s) {
   if (!n_chunks) return;
   const uint64_t blocks = (n_chunks + kPackWaves - 1) / kPackWaves;
-  hipLaunchKernelGGL(k_unpack, dim3((uint32_t)blocks), dim3(kPackThreads), 0,
+  QOZ_LAUNCH(k_unpack, dim3((uint32_t)blocks), dim3(kPackThreads), 0,
                      s, src, n_packed, coff, pcoff, n_chunks, n_words, raw,
                      status);
 }

@@ -22,7 +22,7 @@ __global__ void k_init_status(uint32_t* st) {
 }
 
 void launch_init_status(uint32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, s, status);
+  QOZ_LAUNCH(k_init_status, dim3(1), dim3(64), 0, s, status);
 }
 
 __global__ void k_zero_u32(uint32_t* p, uint64_t n) {
@@ -35,7 +35,7 @@ void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
   if (!n) return;
   uint64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_zero_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p,
+  QOZ_LAUNCH(k_zero_u32, dim3((uint32_t)blocks), dim3(256), 0, s, p,
                      n);
 }
 
@@ -110,7 +110,7 @@ void launch_copy_regions(void* const* dst, const void* const* src,
   if (!m) return;
   uint64_t blocks = (most / 16 + 255) / 256;
   blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
-  hipLaunchKernelGGL(k_copy_regions, dim3((uint32_t)blocks, m), dim3(256), 0,
+  QOZ_LAUNCH(k_copy_regions, dim3((uint32_t)blocks, m), dim3(256), 0,
                      s, r);
 }
 
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_gather_host(
 
 void launch_gather_host(const HostCopy* list, uint32_t n, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_gather_host, dim3(n), dim3(256), 0, s, list);
+  QOZ_LAUNCH(k_gather_host, dim3(n), dim3(256), 0, s, list);
 }
 
 /* The exact values of a batch of streams: per job (one stream) the anchor
@@ -193,7 +193,7 @@ uint32_t exact_job_workgroups(ExactJob* j) {
 void launch_exact_q(const ExactJob* jobs, const uint32_t* wg0,
                     uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_exact_q, dim3(total_wg), dim3(256), 0, s, jobs, wg0,
+  QOZ_LAUNCH(k_exact_q, dim3(total_wg), dim3(256), 0, s, jobs, wg0,
                      n_jobs);
 }
 
@@ -204,11 +204,11 @@ void launch_copy_host(void* dst, const void* src, size_t bytes, bool to_host,
   if (blocks < 1) blocks = 1;
   if (blocks > 1024) blocks = 1024;
   if (to_host)
-    hipLaunchKernelGGL(k_copy_host<true>, dim3((uint32_t)blocks), dim3(256),
+    QOZ_LAUNCH(k_copy_host<true>, dim3((uint32_t)blocks), dim3(256),
                        0, s, (uint8_t*)dst, (const uint8_t*)src,
                        (uint64_t)bytes);
   else
-    hipLaunchKernelGGL(k_copy_host<false>, dim3((uint32_t)blocks), dim3(256),
+    QOZ_LAUNCH(k_copy_host<false>, dim3((uint32_t)blocks), dim3(256),
                        0, s, (uint8_t*)dst, (const uint8_t*)src,
                        (uint64_t)bytes);
 }
@@ -253,14 +253,14 @@ void launch_anchor_copy(const Geo& g, uint32_t stride, const uint32_t na[3],
                         const float* x, float* W, float* out,
                         uint32_t* status, hipStream_t s) {
   uint32_t total = na[0] * na[1] * na[2];
-  hipLaunchKernelGGL(k_anchor_copy, dim3((total + 255) / 256), dim3(256), 0,
+  QOZ_LAUNCH(k_anchor_copy, dim3((total + 255) / 256), dim3(256), 0,
                      s, g, stride, na[0], na[1], na[2], x, W, out, status);
 }
 
 void launch_anchor_scatter(const Geo& g, uint32_t stride, const uint32_t na[3],
                            const float* in, float* W, hipStream_t s) {
   uint32_t total = na[0] * na[1] * na[2];
-  hipLaunchKernelGGL(k_anchor_scatter, dim3((total + 255) / 256), dim3(256),
+  QOZ_LAUNCH(k_anchor_scatter, dim3((total + 255) / 256), dim3(256),
                      0, s, g, stride, na[0], na[1], na[2], in, W);
 }
 
@@ -400,7 +400,7 @@ void launch_unpred_scatter(const Geo& g, const SweepTable& st,
   if (!n_unpred) return;
   uint64_t blocks = (n_unpred + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_unpred_scatter, dim3((uint32_t)blocks), dim3(256), 0,
+  QOZ_LAUNCH(k_unpred_scatter, dim3((uint32_t)blocks), dim3(256), 0,
                      s, g, st, upos, vals, n_unpred, n_codes, W, status);
 }
 
@@ -801,10 +801,10 @@ void launch_row_comp(const Geo& g, const RowJob& rj_in, const float* x,
   size_t lds;
   const uint32_t blocks = row_blocks(g, &rj, &lds);
   if (write_w)
-    hipLaunchKernelGGL(k_row_comp<true>, dim3(blocks), dim3(kRowThreads), lds,
+    QOZ_LAUNCH(k_row_comp<true>, dim3(blocks), dim3(kRowThreads), lds,
                        s, g, rj, x, W, codes, status);
   else
-    hipLaunchKernelGGL(k_row_comp<false>, dim3(blocks), dim3(kRowThreads),
+    QOZ_LAUNCH(k_row_comp<false>, dim3(blocks), dim3(kRowThreads),
                        lds, s, g, rj, x, W, codes, status);
 }
 
@@ -814,7 +814,7 @@ void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
   RowJob rj = rj_in;
   size_t lds;
   const uint32_t blocks = row_blocks(g, &rj, &lds);
-  hipLaunchKernelGGL(k_row_decomp, dim3(blocks), dim3(kRowThreads), lds, s, g,
+  QOZ_LAUNCH(k_row_decomp, dim3(blocks), dim3(kRowThreads), lds, s, g,
                      rj, W, codes);
 }
 
@@ -916,13 +916,13 @@ uint32_t anchor_job_workgroups(const AnchorJob& j) {
 void launch_anchor_q(const AnchorJob* jobs, const uint32_t* wg0,
                      uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_anchor_q, dim3(total_wg), dim3(256), 0, s, jobs, wg0,
+  QOZ_LAUNCH(k_anchor_q, dim3(total_wg), dim3(256), 0, s, jobs, wg0,
                      n_jobs);
 }
 
 void launch_copy_list(const DevCopy* list, uint32_t n, hipStream_t s) {
   if (!n) return;
-  hipLaunchKernelGGL(k_copy_list, dim3(n), dim3(256), 0, s, list);
+  QOZ_LAUNCH(k_copy_list, dim3(n), dim3(256), 0, s, list);
 }
 
 static_assert(kRowThreads % kSweepTX == 0, "queued sweep tiles");
@@ -953,10 +953,10 @@ void launch_sweep_comp(const Geo& g, const Sweep& sw, const float* x,
   if (!sweep_tile_ok(t)) t = SweepTile();
   dim3 grid = sweep_grid_dim(sw, t), block(kSweepTX, t.ty);
   if (write_w)
-    hipLaunchKernelGGL(k_sweep_comp<true>, grid, block, 0, s, g, sw, x, W,
+    QOZ_LAUNCH(k_sweep_comp<true>, grid, block, 0, s, g, sw, x, W,
                        codes, status);
   else
-    hipLaunchKernelGGL(k_sweep_comp<false>, grid, block, 0, s, g, sw, x, W,
+    QOZ_LAUNCH(k_sweep_comp<false>, grid, block, 0, s, g, sw, x, W,
                        codes, status);
 }
 
@@ -996,7 +996,7 @@ void launch_sweep_round_comp_q(const CompJob* jobs, const uint32_t* wg0,
                                uint32_t n_jobs, uint32_t total_wg, size_t lds,
                                hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_sweep_round_comp_q, dim3(total_wg), dim3(kRowThreads),
+  QOZ_LAUNCH(k_sweep_round_comp_q, dim3(total_wg), dim3(kRowThreads),
                      lds, s, jobs, wg0, n_jobs);
 }
 
@@ -1004,7 +1004,7 @@ void launch_sweep_round_q(const SweepJob* jobs, const uint32_t* wg0,
                           uint32_t n_jobs, uint32_t total_wg, size_t lds,
                           hipStream_t s) {
   if (!total_wg) return;
-  hipLaunchKernelGGL(k_sweep_round_q, dim3(total_wg), dim3(kRowThreads), lds,
+  QOZ_LAUNCH(k_sweep_round_q, dim3(total_wg), dim3(kRowThreads), lds,
                      s, jobs, wg0, n_jobs);
 }
 
@@ -1013,7 +1013,7 @@ void launch_sweep_decomp(const Geo& g, const Sweep& sw, float* W,
   if (sw.count == 0) return;
   if (!sweep_tile_ok(t)) t = SweepTile();
   dim3 grid = sweep_grid_dim(sw, t), block(kSweepTX, t.ty);
-  hipLaunchKernelGGL(k_sweep_decomp, grid, block, 0, s, g, sw, W, codes);
+  QOZ_LAUNCH(k_sweep_decomp, grid, block, 0, s, g, sw, W, codes);
 }
 
 }  // namespace qoz

@@ -132,7 +132,7 @@ void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
                           uint32_t* status, hipStream_t s) {
   if (!bg.size || !bg.nb) return;
   const uint32_t per = kGatherThreads * kGatherPer;
-  hipLaunchKernelGGL(k_gather_blocks, dim3((bg.size + per - 1) / per, bg.nb),
+  QOZ_LAUNCH(k_gather_blocks, dim3((bg.size + per - 1) / per, bg.nb),
                      dim3(kGatherThreads), 0, s, x, g, bg, origins_dev, xs,
                      wc, status);
 }
@@ -416,15 +416,15 @@ void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
   if (in_lds) {
     const size_t bytes = alg1_lds_bytes(bg, l);
     if (bytes <= kAlg1WideBytes)
-      hipLaunchKernelGGL(k_alg1_lds<256>, dim3(ncand, bg.nb), dim3(256),
+      QOZ_LAUNCH(k_alg1_lds<256>, dim3(ncand, bg.nb), dim3(256),
                          bytes, s, bg, l, xs, wc, wt, cand_desc, l1_part);
     else
-      hipLaunchKernelGGL(k_alg1_lds<kLdsThreads>, dim3(ncand, bg.nb),
+      QOZ_LAUNCH(k_alg1_lds<kLdsThreads>, dim3(ncand, bg.nb),
                          dim3(kLdsThreads), bytes, s, bg, l, xs, wc, wt,
                          cand_desc, l1_part);
     return;
   }
-  hipLaunchKernelGGL(k_alg1_level, dim3(ncand, bg.nb), dim3(kTuneThreads), 0,
+  QOZ_LAUNCH(k_alg1_level, dim3(ncand, bg.nb), dim3(kTuneThreads), 0,
                      s, bg, l, xs, wc, wt, cand_desc, l1_part);
 }
 
@@ -472,18 +472,18 @@ void launch_alg1_pick(const BlockGeo& bg, uint32_t l, const float* xs,
                       const float* wt, float* wc, bool in_lds,
                       hipStream_t s) {
   const uint32_t nb = bg.nb;
-  hipLaunchKernelGGL(k_alg1_pick, dim3(1), dim3(kPickThreads), 0, s, l1_part,
+  QOZ_LAUNCH(k_alg1_pick, dim3(1), dim3(kPickThreads), 0, s, l1_part,
                      ncand, nb, count, pick);
   if (in_lds) {
     const uint32_t total = (uint32_t)(alg1_lds_bytes(bg, l) / 4);
-    hipLaunchKernelGGL(k_alg1_commit, dim3((total + 255) / 256, nb),
+    QOZ_LAUNCH(k_alg1_commit, dim3((total + 255) / 256, nb),
                        dim3(256), 0, s, bg, l, wt, pick, wc);
     return;
   }
   const uint64_t bsz = (uint64_t)nb * bg.size;
   uint64_t blocks = (bsz + 255) / 256;
   if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(k_commit_copy, dim3((uint32_t)blocks), dim3(256), 0, s,
+  QOZ_LAUNCH(k_commit_copy, dim3((uint32_t)blocks), dim3(256), 0, s,
                      wt, pick, bsz, wc);
 }
 
@@ -714,15 +714,15 @@ void launch_trial(const BlockGeo& bg, const float* xs, float* wt,
                hi_stat) &&
       lds_fits(reinterpret_cast<const void*>(&k_trial_l1), l1_bytes,
                l1_stat)) {
-    hipLaunchKernelGGL(k_trial_hi, dim3(ntrial, bg.nb), dim3(kHiThreads),
+    QOZ_LAUNCH(k_trial_hi, dim3(ntrial, bg.nb), dim3(kHiThreads),
                        hi_bytes, s, bg, xs, wt, desc, hist, sse_part,
                        unpred_part);
-    hipLaunchKernelGGL(k_trial_l1, dim3(ntrial, bg.nb), dim3(kLdsThreads),
+    QOZ_LAUNCH(k_trial_l1, dim3(ntrial, bg.nb), dim3(kLdsThreads),
                        l1_bytes, s, bg, xs, wt, keep_wt ? 1u : 0u, desc,
                        hist, sse_part, unpred_part);
     return;
   }
-  hipLaunchKernelGGL(k_trial, dim3(ntrial, bg.nb), dim3(kTuneThreads), 0, s,
+  QOZ_LAUNCH(k_trial, dim3(ntrial, bg.nb), dim3(kTuneThreads), 0, s,
                      bg, xs, wt, desc, hist, sse_part, unpred_part);
 }
 

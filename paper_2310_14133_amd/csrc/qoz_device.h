@@ -157,6 +157,28 @@ __device__ __forceinline__ uint32_t point_of(const SweepTable& t, const Geo& g, 
  * the job of workgroup wg, the last j with wg0[j] <= wg, counted with one
  * ballot per 64 jobs; the same on every lane.  Every lane of the wave must
  * be active. */
+/* A global-memory pointer read from memory (a field of a job record) is a
+ * generic pointer to the compiler, which then emits flat accesses; flat
+ * accesses count against the LDS wait counter too, so every LDS wait and
+ * barrier after one also waits for it (a prefetch issued early is then
+ * waited for at the next barrier).  gptr makes such a pointer a global one. */
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(
+    const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+/* 16 bytes through a global pointer (uint4 has no assignment from a
+ * global-address-space object) */
+__device__ __forceinline__ uint4 gload16(const void* p) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = *gptr(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ uint32_t find_job(const uint32_t* __restrict__ wg0,
                                              uint32_t n_jobs, uint32_t wg) {
   const uint32_t lane = __lane_id();

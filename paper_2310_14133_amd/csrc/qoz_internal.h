@@ -8,6 +8,7 @@
  */
 #ifndef QOZ_INTERNAL_H
 #define QOZ_INTERNAL_H
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -53,9 +54,14 @@ struct Chunks {
   uint32_t size[QOZ_MAX_LEVELS];           /* chunk size of region r */
   uint64_t start[QOZ_MAX_LEVELS + 1];      /* first bin; start[n] = bins */
   uint64_t first[QOZ_MAX_LEVELS + 1];      /* first chunk; first[n] = all */
+  /* the regions whose first chunk is at or before c, less one (first[] is
+   * non-decreasing); unrolled, so that on the device the reads of a
+   * uniform c stay scalar loads outside any loop */
   __host__ __device__ uint32_t region(uint64_t c) const {
     uint32_t r = 0;
-    while (r + 1 < n && c >= first[r + 1]) ++r;
+#pragma unroll
+    for (uint32_t i = 1; i < QOZ_MAX_LEVELS; ++i)
+      r += (i < n && c >= first[i]) ? 1u : 0u;
     return r;
   }
   __host__ __device__ uint64_t begin(uint64_t c) const {
@@ -138,11 +144,19 @@ struct SweepTable {
 };
 
 /* Canonical-Huffman decoding tables (device copy). */
+/* second-level decoder entries (codes of kSymBits + 1 .. kSymBits + 8 bits) */
+constexpr uint32_t kEnt2 = 1024;
+constexpr uint32_t kEnt2Depth = 8;
 struct DecTables {
   /* indexed by the next kSymBits bits: for a code of at most kSymBits bits
    * its length (bits 0-5), 0x40 if it is symbol 0's code, and its symbol
-   * (bits 16-31); 0 for a longer (or invalid) code */
+   * (bits 16-31); for a prefix of longer codes that has a second-level
+   * table, 0x80 | (d << 8) | (offset << 12): the next d bits index
+   * ent2[offset ..]; 0 otherwise (a longer code without one, or invalid) */
   uint32_t ent[1u << kSymBits];
+  /* second level: entries as in ent for the codes of a prefix whose length
+   * exceeds kSymBits by at most the prefix's d; 0 for longer or invalid */
+  uint32_t ent2[kEnt2];
   uint64_t first[kMaxCodeLen + 1];
   uint32_t cnt[kMaxCodeLen + 1];
   uint32_t off[kMaxCodeLen + 1];
@@ -272,12 +286,30 @@ qoz_status to_host(qoz_ctx* c, void* h_dst, const void* d_src, size_t bytes,
                    hipStream_t s);
 qoz_status to_device(qoz_ctx* c, void* d_dst, const void* h_src,
                      size_t bytes, hipStream_t s);
-/* Instrumented launch bracket: call prof_begin before and prof_end after a
- * launch; resolved by prof_collect after the stream is synchronised. */
+/* Instrumented launch bracket: call prof_begin before and prof_end after
+ * the launches of one kind; resolved by prof_collect after the stream is
+ * synchronised.  The bracket's two events travel with the kernel launches
+ * themselves (QOZ_LAUNCH): the first launch inside takes the start event,
+ * every launch the stop event, so the time measured is from the first
+ * kernel's start to the last one's end, whatever the stream did before. */
 hipEvent_t prof_begin(qoz_ctx* c, hipStream_t s, int kind);
 void prof_end(qoz_ctx* c, hipStream_t s, hipEvent_t a, int kind,
               double bytes);
 void prof_collect(qoz_ctx* c);
+/* the calling thread's open bracket (null events outside one) */
+struct ProfSlot {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+ProfSlot& prof_slot();
+/* Every kernel launch of the library: hipLaunchKernelGGL's arguments. */
+#define QOZ_LAUNCH(kernel, grid, block, lds, stream, ...)                  \
+  do {                                                                     \
+    ::qoz::ProfSlot& slot_ = ::qoz::prof_slot();                          \
+    hipEvent_t start_ = slot_.start;                                       \
+    slot_.start = nullptr;                                                 \
+    hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, start_,        \
+                          slot_.stop, 0, __VA_ARGS__);                     \
+  } while (0)
 qoz_status set_device(qoz_ctx* c);
 
 /* ---- host planning (plan.cpp) --------------------------------------- */
@@ -315,6 +347,11 @@ constexpr uint32_t kSortCap = 4096;
 constexpr uint32_t kSortCapBig = 16384; /* second pass, 128 KB of LDS */
 bool huffman_lengths_sorted(const uint64_t* keys, uint32_t n, uint8_t* len);
 uint64_t huffman_cost_sorted(const uint64_t* keys, uint32_t n);
+/* An upper bound on the payload words of any chunk of at most `chunk`
+ * bins: the `chunk` longest code occurrences of the field (keys as above,
+ * lens[i] the length of keys[i]'s symbol). */
+uint32_t chunk_words_bound(const uint64_t* keys, const uint8_t* lens,
+                           uint32_t n, uint32_t chunk);
 /* Canonical codes for ascending symbols syms[0..n) with lengths lens. */
 void canonical_codes_sparse(const uint16_t* syms, const uint8_t* lens,
                             uint32_t n, uint64_t* codes);
@@ -404,17 +441,16 @@ uint32_t count_workgroups(uint64_t n_chunks);
 void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
                        const uint32_t* wg0, uint32_t nf, uint32_t total_wg,
                        uint32_t* bits, uint32_t* zeros, hipStream_t s);
-/* Chunks of every field, coded by n_wg workgroups in a grid stride over
- * the global chunk order; gw and gz are the chunk scan's exclusive
- * prefixes of the counted words and symbol-0 bins (n_chunks + 1 each);
- * max_words bounds a chunk's payload words, long_codes selects the
- * variant for codes longer than 32 bits. */
+/* Chunks of every field, one wave per chunk, as many workgroups as the
+ * device holds at once taking chunks in a grid stride over the global
+ * chunk order; gw and gz are the chunk scan's exclusive prefixes of the
+ * counted words and symbol-0 bins (n_chunks + 1 each); max_words bounds a
+ * chunk's payload words, max_tn the fields' code table sizes (the LDS
+ * window), long_codes selects the variant for codes longer than 32 bits. */
 void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
                         const uint64_t* gw, const uint64_t* gz, uint32_t nf,
-                        uint64_t n_chunks, uint32_t max_words,
-                        bool long_codes, uint32_t n_wg, hipStream_t s);
-/* workgroups of the encoding launch for the current device */
-uint32_t encode_workgroups();
+                        uint64_t n_chunks, uint32_t max_words, uint32_t max_tn,
+                        bool long_codes, hipStream_t s);
 /* payload words a chunk can need with codes of at most max_len bits */
 uint32_t encode_max_words(uint32_t max_len);
 /* zero-word packing of the payload (stream format 5): pack_bits[c] from

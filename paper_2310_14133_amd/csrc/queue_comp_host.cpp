@@ -60,7 +60,7 @@ struct CField {
   std::vector<uint64_t> keys, table;
   uint64_t n_unpred = 0, zero_entry = 0, n_words = 0, n_packed = 0;
   int32_t lo = 0;
-  uint32_t tn = 0, max_len = 0;
+  uint32_t tn = 0, max_len = 0, words_bound = 0;
   bool big = false; /* more used bins than the device sort holds */
   Layout lay0{}, lay{};
   size_t tab_up = 0, cb_up = 0, hdr_up = 0; /* in the second upload */
@@ -82,6 +82,8 @@ bool field_code(CField& f) {
   if (!huffman_lengths_sorted(keys.data(), (uint32_t)keys.size(),
                               klen.data()))
     return false;
+  f.words_bound =
+      chunk_words_bound(keys.data(), klen.data(), (uint32_t)keys.size(), kChunk);
   std::vector<uint32_t> idx(keys.size());
   for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
   std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
@@ -458,7 +460,7 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
   DevCopy* z2 = (DevCopy*)(hu + zl2);
   DevCopy* cp2 = (DevCopy*)(hu + cl2);
   uint64_t n_chunks = 0;
-  uint32_t max_words = 0;
+  uint32_t max_words = 0, max_tn = 0;
   bool long_codes = false;
   for (uint32_t k = 0; k < ne; ++k) {
     CField& f = *E[k];
@@ -495,8 +497,10 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
     n_chunks += f.nch;
     cw0[k] = count_wg;
     count_wg += count_workgroups(f.nch);
-    max_words = std::max(max_words, encode_max_words(f.max_len));
+    max_words = std::max(max_words, std::min(encode_max_words(f.max_len),
+                                             f.words_bound));
     long_codes |= f.max_len > 32;
+    max_tn = std::max(max_tn, f.tn);
     /* zero fills: the sections before the payload and the totals; then
      * the codebook and the anchors into place */
     z2[2 * k] = DevCopy{nullptr, out, f.lay0.payload};
@@ -529,7 +533,7 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
                        (const uint64_t*)(dB + c0_off),
                        (const uint64_t*)(D + gw_off),
                        (const uint64_t*)(D + gz_off), ne, n_chunks,
-                       max_words, long_codes, encode_workgroups(), s);
+                       max_words, max_tn, long_codes, s);
     QOZ_TRY(sync_q(s)); /* the second upload has been read */
     QOZ_TRY(ensure_pinned(c, hdr + al((size_t)kAl * ne) +
                                  al(sizeof(HostCopy) * ne)));
