@@ -67,6 +67,7 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   QOZ_TRY(ensure(c->scan, chunk_scan_scratch(nch)));
   QOZ_TRY(ensure(c->upre, 8 * (nch + 1)));
   QOZ_TRY(ensure(c->pcoff, 8 * (nch + 1)));
+  QOZ_TRY(ensure(c->chunk_geo, sizeof(ChunkGeo) * (nch ? nch : 1)));
   /* the code table, then the encoder's field record and chunk range */
   QOZ_TRY(ensure(c->enc_table, 8 * kNSym + 4096));
   float* W = (float*)c->W.p;
@@ -276,7 +277,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
        launch_huff_count(d_ef, d_c0,
                          (const uint32_t*)(dtab + f_off + c0_off + 16), 1,
                          count_wg, (uint32_t*)c->chunk_bits.p,
-                         (uint32_t*)c->chunk_zeros.p, s));
+                         (uint32_t*)c->chunk_zeros.p, (ChunkGeo*)c->chunk_geo.p,
+                         s));
   launch_chunk_scan((uint32_t*)c->chunk_bits.p, (uint32_t*)c->chunk_zeros.p,
                     nch, gw, gz, totals, (uint64_t*)c->scan.p, s);
   /* algorithmic bytes: the bins (as 4-byte codes), the payload (its Huffman
@@ -285,7 +287,8 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   PROF(PK_HUFF_ENC,
        kCodeBytes * P.n_codes + (double)payload_bits / 8.0 + 8.0 * n_unpred +
            46.0 * nch,
-       launch_huff_encode(d_ef, d_c0, gw, gz, 1, nch,
+       launch_huff_encode(d_ef, d_c0, (const ChunkGeo*)c->chunk_geo.p, gw, gz,
+                          1, nch,
                           std::min(encode_max_words(max_len), words_bound),
                           tab_n, max_len > 32, s));
   /* each chunk's size under zero-word packing (from the encoder, in

@@ -220,6 +220,7 @@ void qoz_ctx_destroy(qoz_ctx* c) {
                     &c->upos,       &c->hsort,      &c->scan,
                     &c->feat,       &c->mlp_io,     &c->mlp_part,
                     &c->mlp_loss,   &c->hsort_ids,  &c->pcoff,
+                    &c->chunk_geo,
                     &c->ptmp,       &c->queue,      &c->lbatch,
                     &c->cqueue,     &c->cqueue_up};
   for (DevBuf* b : bufs)

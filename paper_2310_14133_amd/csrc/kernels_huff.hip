@@ -382,7 +382,7 @@ __device__ __forceinline__ uint32_t table_window(int32_t lo, uint32_t tn,
  * from the global table); a wave counts one
  * chunk, each lane 8 groups of 8 bins read as 16-byte loads (chunks start
  * on a multiple of 64 bins).  Counts go to bits[chunk0[f] + c] and
- * zeros[chunk0[f] + c]. */
+ * zeros[chunk0[f] + c], the chunk's first bin and size to geo[..]. */
 constexpr uint32_t kCountThreads = 256;
 constexpr uint32_t kCountChunks = 8;
 constexpr uint32_t kCountLens = 16384;
@@ -390,7 +390,8 @@ constexpr uint32_t kCountLens = 16384;
 __global__ __launch_bounds__(kCountThreads) void k_huff_count(
     const EncField* __restrict__ fields, const uint64_t* __restrict__ chunk0,
     const uint32_t* __restrict__ wg0, uint32_t nf,
-    uint32_t* __restrict__ bits_out, uint32_t* __restrict__ zeros_out) {
+    uint32_t* __restrict__ bits_out, uint32_t* __restrict__ zeros_out,
+    ChunkGeo* __restrict__ geo) {
   constexpr uint32_t kGroups = kChunk / (8 * 64); /* 8 per lane */
   __shared__ uint8_t lens[kCountLens];
   const uint32_t f = find_job(wg0, nf, blockIdx.x);
@@ -445,6 +446,7 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
     if (lane == 0) {
       bits_out[chunk0[f] + c] = bits;
       zeros_out[chunk0[f] + c] = zeros;
+      geo[chunk0[f] + c] = ChunkGeo{b, n, 0u};
     }
   }
 }
@@ -455,10 +457,11 @@ uint32_t count_workgroups(uint64_t n_chunks) {
 
 void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
                        const uint32_t* wg0, uint32_t nf, uint32_t total_wg,
-                       uint32_t* bits, uint32_t* zeros, hipStream_t s) {
+                       uint32_t* bits, uint32_t* zeros, ChunkGeo* geo,
+                       hipStream_t s) {
   if (!total_wg) return;
   QOZ_LAUNCH(k_huff_count, dim3(total_wg), dim3(kCountThreads), 0, s,
-                     fields, chunk0, wg0, nf, bits, zeros);
+             fields, chunk0, wg0, nf, bits, zeros, geo);
 }
 
 /* Encoding of the chunks of one or more fields, after k_huff_count and the
@@ -491,24 +494,6 @@ void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
  * load is a vector load, whose wait would also wait for the next chunk's
  * bins and for the stores). */
 #define QOZ_CONST __attribute__((address_space(4)))
-__device__ __forceinline__ uint64_t chunk_begin(const QOZ_CONST Chunks& ch,
-                                                uint64_t c) {
-  uint32_t r = 0;
-#pragma unroll
-  for (uint32_t i = 1; i < QOZ_MAX_LEVELS; ++i)
-    r += (i < ch.n && c >= ch.first[i]) ? 1u : 0u;
-  return ch.start[r] + (c - ch.first[r]) * ch.size[r];
-}
-__device__ __forceinline__ uint32_t chunk_bins(const QOZ_CONST Chunks& ch,
-                                               uint64_t c) {
-  uint32_t r = 0;
-#pragma unroll
-  for (uint32_t i = 1; i < QOZ_MAX_LEVELS; ++i)
-    r += (i < ch.n && c >= ch.first[i]) ? 1u : 0u;
-  const uint64_t b = ch.start[r] + (c - ch.first[r]) * ch.size[r];
-  const uint64_t e = b + ch.size[r];
-  return (uint32_t)((e < ch.start[r + 1] ? e : ch.start[r + 1]) - b);
-}
 
 constexpr uint32_t kEncThreads = 256;
 constexpr uint32_t kEncLaneBins = kChunk / kEncThreads;    /* 16 */
@@ -518,35 +503,56 @@ static_assert(kEncLanesPerSeg * kEncLaneBins == kSeg, "segment lanes");
 static_assert(kEncRounds == 2 && kChunk / kSegPerChunk == kSeg,
               "chunk layout");
 
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* ws,
-                                                    uint32_t* total) {
+/* Inclusive scan over the wave by DPP: shifts by 1, 2, 4 and 8 lanes
+ * within each row of 16, then the last lane of row 0 (and of row 2) added
+ * to rows 1 and 3, and the last lane of row 1 to rows 2 and 3. */
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+  return x;
+}
+
+/* Exclusive scans of two values over the workgroup (one barrier); the
+ * totals in *ta and *tb. */
+__device__ __forceinline__ void block_excl_scan2(uint32_t a, uint32_t b,
+                                                 uint32_t (*ws)[kEncThreads / 64],
+                                                 uint32_t* ea, uint32_t* eb,
+                                                 uint32_t* ta, uint32_t* tb) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (uint32_t o = 1; o < 64; o <<= 1) {
-    const uint32_t t = __shfl_up(x, o, 64);
-    x += lane >= o ? t : 0u;
+  const uint32_t ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+  if (lane == 63) {
+    ws[0][wave] = ia;
+    ws[1][wave] = ib;
   }
-  if (lane == 63) ws[wave] = x;
   __syncthreads();
-  uint32_t pre = 0, tot = 0;
+  uint32_t pa = 0, pb = 0, sa = 0, sb = 0;
 #pragma unroll
   for (uint32_t w = 0; w < kEncThreads / 64; ++w) {
-    pre += w < wave ? ws[w] : 0u;
-    tot += ws[w];
+    pa += w < wave ? ws[0][w] : 0u;
+    pb += w < wave ? ws[1][w] : 0u;
+    sa += ws[0][w];
+    sb += ws[1][w];
   }
-  *total = tot;
-  return pre + x - v;
+  *ea = pa + ia - a;
+  *eb = pb + ib - b;
+  *ta = sa;
+  *tb = sb;
 }
 
 template <bool kLong> /* kLong: some code is longer than 32 bits */
 __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
     const EncField* __restrict__ fields, const uint64_t* __restrict__ chunk0,
-    const uint64_t* __restrict__ gw, const uint64_t* __restrict__ gz,
-    uint32_t nf, uint64_t n_total, uint32_t tcap, uint32_t max_words) {
+    const ChunkGeo* __restrict__ geo, const uint64_t* __restrict__ gw,
+    const uint64_t* __restrict__ gz, uint32_t nf, uint64_t n_total,
+    uint32_t tcap, uint32_t max_words) {
   extern __shared__ uint64_t lds64[];
-  uint64_t* tabl = lds64;                                   /* tcap */
-  uint32_t* words = reinterpret_cast<uint32_t*>(lds64 + tcap); /* max_words + 1 */
+  uint64_t* tabl = lds64; /* tcap entries, an empty one, symbol 0's */
+  /* max_words + 1 words, then a dummy word per thread */
+  uint32_t* words = reinterpret_cast<uint32_t*>(lds64 + tcap + 2);
   __shared__ __align__(16) uint16_t cbin[kChunk];
   __shared__ uint32_t ws[2][kEncThreads / 64];
   __shared__ uint32_t seg_end[kSegPerChunk];
@@ -572,16 +578,15 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
 #pragma unroll
     for (uint32_t r = 0; r < kEncRounds; ++r) qr[r] = make_uint4(0, 0, 0, 0);
     if (c2 >= n_total) return;
-    const QOZ_CONST EncField& F2 = cfields[f2];
-    const uint64_t cl = c2 - chunk0[f2];
-    const uint64_t b2 = chunk_begin(F2.ch, cl);
-    const uint32_t n2 = chunk_bins(F2.ch, cl);
+    const uint16_t* codes2 = cfields[f2].codes;
+    const uint64_t b2 = geo[c2].begin;
+    const uint32_t n2 = geo[c2].n;
 #pragma unroll
     for (uint32_t r = 0; r < kEncRounds; ++r) {
       const uint32_t m = tid + kEncThreads * r;
       /* a group the chunk ends in reads up to 7 bins past it: the bins of
        * the next chunk, or the 16 bins of padding after the last */
-      if (8 * m < n2) qr[r] = gload16(F2.codes + b2 + 8 * m);
+      if (8 * m < n2) qr[r] = gload16(codes2 + b2 + 8 * m);
     }
   };
   for (uint32_t i = tid; i <= max_words; i += kEncThreads) words[i] = 0;
@@ -607,35 +612,77 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
       wo = table_window(lo, tn, tcap);
       for (uint32_t i = tid; i < tw; i += kEncThreads)
         tabl[i] = gptr(F.tab)[wo + i];
+      /* slot tw: an empty entry (the padding symbol lo + tn of the fast
+       * path), slot tw + 1: symbol 0, which min(symbol - lo, tw + 1)
+       * reaches when the window starts at lo (symbol 0 is below every
+       * other) */
+      if (tid == 0) {
+        tabl[tw] = 0;
+        tabl[tw + 1] = zero_entry;
+      }
       loaded = f;
     }
     const uint64_t c = g - chunk0[f]; /* chunk within the field */
-    const uint64_t base = chunk_begin(F.ch, c);
-    const uint32_t nsym = chunk_bins(F.ch, c);
+    const uint64_t base = geo[g].begin;
+    const uint32_t nsym = geo[g].n;
     /* the chunk's word and unpredictable offsets within its field */
     const uint64_t w0 = gw[g] - gw[chunk0[f]];
     const uint64_t u0 = gz[g] - gz[chunk0[f]];
-    /* a full chunk whose field's table lies in the LDS window needs no
-     * checks per bin (the common case) */
-    const bool fast = nsym == kChunk && tw == tn && f == loaded;
+    /* a chunk whose field's table lies whole in the LDS window needs no
+     * check per bin (bins past a short chunk's end stage as the padding
+     * symbol lo + tn, whose entry is empty) */
+    const bool fast = tw == tn && f == loaded && (uint32_t)lo + tn <= 0xffffu;
+    const uint32_t pad = fast ? (uint32_t)lo + tn : 1u;
     /* staging: bin 8 m + i to segment i, position m */
     uint32_t zpack = 0; /* bin-0 count of round r in bits [16 r, +16) */
     uint32_t zmask = 0; /* bit 8 r + i: bin 8 m + i of round r is 0 */
+    if (fast && nsym == kChunk) {
+      /* the halves of each word go straight to LDS; a zero half is
+       * detected per word (exact: a borrow into the high half only follows
+       * a zero low half) and counted only then */
+      uint32_t hz = 0;
 #pragma unroll
-    for (uint32_t r = 0; r < kEncRounds; ++r) {
-      const uint32_t m = tid + kEncThreads * r;
-      const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
-      uint32_t z = 0;
+      for (uint32_t r = 0; r < kEncRounds; ++r) {
+        const uint32_t m = tid + kEncThreads * r;
+        const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
 #pragma unroll
-      for (uint32_t i = 0; i < 8; ++i) {
-        const uint32_t v = fast || 8 * m + i < nsym
-                               ? (w[i / 2] >> (16 * (i & 1))) & 0xffffu
-                               : 1u;
-        cbin[i * kSeg + m] = (uint16_t)v;
-        z += v == 0 ? 1u : 0u;
-        zmask |= (v == 0 ? 1u : 0u) << (8 * r + i);
+        for (uint32_t d = 0; d < 4; ++d) {
+          cbin[(2 * d) * kSeg + m] = (uint16_t)w[d];
+          cbin[(2 * d + 1) * kSeg + m] = (uint16_t)(w[d] >> 16);
+          hz |= (w[d] - 0x00010001u) & ~w[d] & 0x80008000u;
+        }
       }
-      zpack |= z << (16 * r);
+      if (hz) {
+#pragma unroll
+        for (uint32_t r = 0; r < kEncRounds; ++r) {
+          const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
+          uint32_t z = 0;
+#pragma unroll
+          for (uint32_t i = 0; i < 8; ++i) {
+            const bool zero = ((w[i / 2] >> (16 * (i & 1))) & 0xffffu) == 0;
+            z += zero ? 1u : 0u;
+            zmask |= (zero ? 1u : 0u) << (8 * r + i);
+          }
+          zpack |= z << (16 * r);
+        }
+      }
+    } else {
+#pragma unroll
+      for (uint32_t r = 0; r < kEncRounds; ++r) {
+        const uint32_t m = tid + kEncThreads * r;
+        const uint32_t w[4] = {qr[r].x, qr[r].y, qr[r].z, qr[r].w};
+        uint32_t z = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) {
+          const uint32_t v = 8 * m + i < nsym
+                                 ? (w[i / 2] >> (16 * (i & 1))) & 0xffffu
+                                 : pad;
+          cbin[i * kSeg + m] = (uint16_t)v;
+          z += v == 0 ? 1u : 0u;
+          zmask |= (v == 0 ? 1u : 0u) << (8 * r + i);
+        }
+        zpack |= z << (16 * r);
+      }
     }
     for (uint32_t i = tid; i < dirty; i += kEncThreads) words[i] = 0;
     __syncthreads();
@@ -653,11 +700,12 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
       const uint4* cb = reinterpret_cast<const uint4*>(cbin + j * kSeg + k0);
       const uint4 qa = cb[0], qb = cb[1];
       const uint32_t w[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
-      if (fast) {
+      if (fast) { /* the window is the whole table, from lo */
 #pragma unroll
         for (uint32_t k = 0; k < kEncLaneBins; ++k) {
-          const uint32_t sym = (w[k / 2] >> (16 * (k & 1))) & 0xffffu;
-          ent[k] = sym == 0 ? zero_entry : tabl[sym - (uint32_t)lo];
+          const uint32_t o =
+              ((w[k / 2] >> (16 * (k & 1))) & 0xffffu) - (uint32_t)lo;
+          ent[k] = tabl[o < tw + 1 ? o : tw + 1];
           bits += (uint32_t)(ent[k] & 0xff);
         }
       } else {
@@ -687,32 +735,34 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
         }
       }
     }
-    uint32_t tot_bits, tot_z;
-    const uint32_t pos0 = block_excl_scan(bits, ws[0], &tot_bits);
-    const uint32_t zex = block_excl_scan(zpack, ws[1], &tot_z);
+    uint32_t pos0, zex, tot_bits, tot_z;
+    block_excl_scan2(bits, zpack, ws, &pos0, &zex, &tot_bits, &tot_z);
     const uint32_t nw = (tot_bits + 31) / 32;
     if (tid % kEncLanesPerSeg == kEncLanesPerSeg - 1) seg_end[j] = pos0 + bits;
     {
-      /* acc holds the bits not yet written in its low nacc (< 32) bits; a
-       * completed word is a plain store, except the thread's first word,
-       * which it may share with the threads before it: that one and the
-       * last partial word (shared with the threads after) are ORed in */
+      /* acc holds the bits not yet written in its low nacc (< 32) bits.
+       * Every code ends in one store without a branch: the word it
+       * completes, or (when it completes none) a dummy slot of the thread.
+       * A first word that starts before pos0 is shared with the threads
+       * before: it is kept and ORed in at the end, as is the last partial
+       * word (shared with the threads after). */
       uint64_t acc = 0;
       const uint32_t first = pos0 >> 5;
+      const bool sfirst = (pos0 & 31u) != 0;
+      const uint32_t dummy = max_words + 1 + tid;
       uint32_t nacc = pos0 & 31u, wi = first;
       uint32_t firstw = 0;
       auto put = [&](uint32_t code, uint32_t len) { /* len <= 32 */
         acc = (acc << len) | code;
         nacc += len;
-        if (nacc >= 32) {
-          nacc -= 32;
-          const uint32_t v = (uint32_t)(acc >> nacc);
-          if (wi == first)
-            firstw = v;
-          else
-            words[wi] = v;
-          ++wi;
-        }
+        const bool full = nacc >= 32;
+        nacc &= 31u;
+        const uint32_t v = (uint32_t)(acc >> nacc);
+        /* bitwise, so that no branch comes of it */
+        const bool keep = full & sfirst & (wi == first);
+        firstw = keep ? v : firstw;
+        words[full & !keep ? wi : dummy] = v;
+        wi += full ? 1u : 0u;
       };
 #pragma unroll
       for (uint32_t k = 0; k < kEncLaneBins; ++k) {
@@ -726,11 +776,11 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
         }
       }
       const uint32_t tail = nacc ? (uint32_t)(acc << (32 - nacc)) : 0u;
-      if (wi == first)
-        firstw |= tail; /* the thread's bits end in its first word */
+      if (sfirst && wi == first)
+        firstw |= tail; /* the thread's bits end in its shared first word */
       else if (nacc)
         atomicOr(&words[wi], tail);
-      if (bits) atomicOr(&words[first], firstw);
+      if (sfirst && bits) atomicOr(&words[first], firstw);
     }
     __syncthreads();
     if (tid < kSegPerChunk - 1)
@@ -805,13 +855,16 @@ uint32_t encode_max_words(uint32_t max_len) {
 }
 
 void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
-                        const uint64_t* gw, const uint64_t* gz, uint32_t nf,
-                        uint64_t n_chunks, uint32_t max_words, uint32_t max_tn,
-                        bool long_codes, hipStream_t s) {
+                        const ChunkGeo* geo, const uint64_t* gw,
+                        const uint64_t* gz, uint32_t nf, uint64_t n_chunks,
+                        uint32_t max_words, uint32_t max_tn, bool long_codes,
+                        hipStream_t s) {
   if (!n_chunks || !nf) return;
-  /* LDS: the table window, then the chunk's words */
   const uint32_t tcap = max_tn < kEncTab ? (max_tn ? max_tn : 1u) : kEncTab;
-  const size_t lds = 8 * (size_t)tcap + 4 * ((size_t)max_words + 1);
+  /* LDS: the table window, an empty entry and symbol 0's, then the
+   * chunk's words and a dummy word per thread */
+  const size_t lds = 8 * ((size_t)tcap + 2) +
+                     4 * ((size_t)max_words + 1 + kEncThreads);
   /* as many workgroups as can be resident at once (each takes every
    * grid-th chunk, so one that waits for a slot would finish last) */
   int dev = 0, cus = 0, per_cu = 0;
@@ -831,10 +884,10 @@ void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
   const uint32_t grid = (uint32_t)(n_chunks < n_wg ? n_chunks : n_wg);
   if (long_codes)
     QOZ_LAUNCH(k_huff_encode<true>, dim3(grid), dim3(kEncThreads), lds, s,
-               fields, chunk0, gw, gz, nf, n_chunks, tcap, max_words);
+               fields, chunk0, geo, gw, gz, nf, n_chunks, tcap, max_words);
   else
     QOZ_LAUNCH(k_huff_encode<false>, dim3(grid), dim3(kEncThreads), lds, s,
-               fields, chunk0, gw, gz, nf, n_chunks, tcap, max_words);
+               fields, chunk0, geo, gw, gz, nf, n_chunks, tcap, max_words);
 }
 
 }  // namespace qoz

@@ -233,7 +233,7 @@ struct qoz_ctx {
       enc_table, dec_tables, dec_syms, anchors, partial, tune_x, tune_wc,
       tune_wt, tune_desc, tune_hist, tune_stats, tune_l1, ssim_part, upos,
       hsort, scan, feat, mlp_io, mlp_part, mlp_loss, hsort_ids, pcoff, ptmp,
-      queue, lbatch, cqueue, cqueue_up;
+      queue, lbatch, cqueue, cqueue_up, chunk_geo;
   /* sweep launch tiles chosen by qoz_autotune_tiles, per plan signature */
   std::map<std::vector<uint32_t>, std::vector<qoz::SweepTile>> tiles_comp,
       tiles_decomp;
@@ -432,6 +432,13 @@ struct EncField {
   uint32_t* pack_bits;
   SweepTable st;
 };
+/* A chunk's first bin and bin count, written by the count and read by the
+ * encoder (one 16-byte scalar load instead of the level table's search). */
+struct ChunkGeo {
+  uint64_t begin;
+  uint32_t n;
+  uint32_t pad;
+};
 /* Code bits and symbol-0 bins of every chunk of fields[0..nf) (chunk0[f]:
  * the first chunk of field f in the global chunk order, chunk0[nf] the
  * total) into bits[] and zeros[] at global chunk indices; field f's
@@ -440,17 +447,20 @@ struct EncField {
 uint32_t count_workgroups(uint64_t n_chunks);
 void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
                        const uint32_t* wg0, uint32_t nf, uint32_t total_wg,
-                       uint32_t* bits, uint32_t* zeros, hipStream_t s);
-/* Chunks of every field, one wave per chunk, as many workgroups as the
- * device holds at once taking chunks in a grid stride over the global
- * chunk order; gw and gz are the chunk scan's exclusive prefixes of the
- * counted words and symbol-0 bins (n_chunks + 1 each); max_words bounds a
- * chunk's payload words, max_tn the fields' code table sizes (the LDS
- * window), long_codes selects the variant for codes longer than 32 bits. */
+                       uint32_t* bits, uint32_t* zeros, ChunkGeo* geo,
+                       hipStream_t s);
+/* Chunks of every field, one workgroup per chunk at a time, as many
+ * workgroups as the device holds at once taking chunks in a grid stride
+ * over the global chunk order; gw and gz are the chunk scan's exclusive
+ * prefixes of the counted words and symbol-0 bins (n_chunks + 1 each),
+ * geo the count's chunk geometry; max_words bounds a chunk's payload
+ * words, max_tn the fields' code table sizes (the LDS window), long_codes
+ * selects the variant for codes longer than 32 bits. */
 void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
-                        const uint64_t* gw, const uint64_t* gz, uint32_t nf,
-                        uint64_t n_chunks, uint32_t max_words, uint32_t max_tn,
-                        bool long_codes, hipStream_t s);
+                        const ChunkGeo* geo, const uint64_t* gw,
+                        const uint64_t* gz, uint32_t nf, uint64_t n_chunks,
+                        uint32_t max_words, uint32_t max_tn, bool long_codes,
+                        hipStream_t s);
 /* payload words a chunk can need with codes of at most max_len bits */
 uint32_t encode_max_words(uint32_t max_len);
 /* zero-word packing of the payload (stream format 5): pack_bits[c] from

@@ -248,6 +248,8 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
   off += al(8 * (nt + 1));
   const size_t gscan_off = off;
   off += al(chunk_scan_scratch(nt));
+  const size_t geo_off = off;
+  off += al(sizeof(ChunkGeo) * (nt ? nt : 1));
   const size_t gtot_off = off; /* the batch scan's totals */
   off += kAl;
   const size_t upA = off;
@@ -523,7 +525,7 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
                       (const uint64_t*)(dB + c0_off),
                       (const uint32_t*)(dB + cw0_off), ne, count_wg,
                       (uint32_t*)(D + gbits_off), (uint32_t*)(D + gzeros_off),
-                      s);
+                      (ChunkGeo*)(D + geo_off), s);
     launch_chunk_scan((const uint32_t*)(D + gbits_off),
                       (const uint32_t*)(D + gzeros_off), n_chunks,
                       (uint64_t*)(D + gw_off), (uint64_t*)(D + gz_off),
@@ -531,6 +533,7 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
                       (uint64_t*)(D + gscan_off), s);
     launch_huff_encode((const EncField*)(dB + ef_off),
                        (const uint64_t*)(dB + c0_off),
+                       (const ChunkGeo*)(D + geo_off),
                        (const uint64_t*)(D + gw_off),
                        (const uint64_t*)(D + gz_off), ne, n_chunks,
                        max_words, max_tn, long_codes, s);
