@@ -222,13 +222,12 @@ __device__ __forceinline__ uint32_t slow_symbol(
   } else { /* a code of kRegMax bits or more, or a saturated limit */
     const uint64_t V = rd.window64(sh);
     const uint64_t h = V >> 1;
-    len = 0;
-    for (uint32_t L = kSymBits + 1; L <= maxlen; ++L)
-      if (h < sh.lim_half[L]) {
-        len = sh.cnt[L] ? L : 0;
-        break;
-      }
-    if (!len) return kInvalid;
+    /* the number of lengths the code is longer than (the limits do not
+     * decrease with L): independent loads, one LDS latency */
+    len = kSymBits + 1;
+    for (uint32_t L = kSymBits + 1; L < maxlen; ++L)
+      len += h >= sh.lim_half[L] ? 1u : 0u;
+    if (!sh.cnt[len]) return kInvalid;
     r = V >> (64 - len);
   }
   r -= sh.first[len];
