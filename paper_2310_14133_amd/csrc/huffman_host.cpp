@@ -158,21 +158,31 @@ void canonical_codes(const uint8_t* len, uint32_t nsym, uint64_t* code) {
   }
 }
 
-/* Total code bits of a whole histogram: the used symbols' counts sorted
- * by two 16-bit radix passes, then the two-queue merge above. */
-uint64_t huffman_cost_hist(const uint32_t* hist, uint32_t nsym) {
-  std::vector<uint64_t> a, b;
+void hist_keys_sorted(const uint32_t* hist, uint32_t nsym,
+                      std::vector<uint64_t>* keys) {
+  /* the used symbols in ascending order, then two stable 16-bit radix
+   * passes over the count: ascending (count, symbol) */
+  std::vector<uint64_t>& a = *keys;
+  a.clear();
   a.reserve(4096);
   for (uint32_t s = 0; s < nsym; ++s)
     if (hist[s]) a.push_back(((uint64_t)hist[s] << 16) | s);
-  b.resize(a.size());
+  std::vector<uint64_t> b(a.size());
+  std::vector<uint32_t> cnt(65537);
   for (int shift = 16; shift < 48; shift += 16) {
-    uint32_t cnt[65537] = {0};
+    std::fill(cnt.begin(), cnt.end(), 0u);
     for (uint64_t k : a) cnt[((k >> shift) & 0xffffu) + 1]++;
     for (uint32_t d = 0; d < 65536; ++d) cnt[d + 1] += cnt[d];
     for (uint64_t k : a) b[cnt[(k >> shift) & 0xffffu]++] = k;
     a.swap(b);
   }
+}
+
+/* Total code bits of a whole histogram: the used symbols' counts sorted
+ * by two 16-bit radix passes, then the two-queue merge above. */
+uint64_t huffman_cost_hist(const uint32_t* hist, uint32_t nsym) {
+  std::vector<uint64_t> a;
+  hist_keys_sorted(hist, nsym, &a);
   return huffman_cost_sorted(a.data(), (uint32_t)a.size());
 }
 

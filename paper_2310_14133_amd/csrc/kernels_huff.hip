@@ -12,7 +12,7 @@
  *                  workgroup per tile, then the tile offsets): the payload
  *                  offsets and unpredictable ranks of the chunks, and the
  *                  offsets of the zero-word packed payload.
- *  - k_huff_encode: workgroups take chunks in a grid stride, code them with
+ *  - k_huff_encode: workgroups take runs of chunks in a grid stride, code them with
  *                  the code table in LDS, pack the codes MSB-first into an LDS word
  *                  buffer (ds_or), store the words coalesced at the
  *                  chunk's scanned offset, and gather the exact values of
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
     const EncField* __restrict__ fields, const uint64_t* __restrict__ chunk0,
     const ChunkGeo* __restrict__ geo, const uint64_t* __restrict__ gw,
     const uint64_t* __restrict__ gz, uint32_t nf, uint64_t n_total,
-    uint32_t tcap, uint32_t max_words) {
+    uint32_t tcap, uint32_t max_words, uint32_t run) {
   extern __shared__ uint64_t lds64[];
   uint64_t* tabl = lds64; /* tcap entries, an empty one, symbol 0's */
   /* max_words + 1 words, then a dummy word per thread */
@@ -572,12 +572,22 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
     }
     return __builtin_amdgcn_readfirstlane(cnt - 1);
   };
+  /* runs of `run` consecutive chunks, every grid-th run to a workgroup:
+   * a run crosses few fields, so a batch of fields reloads few table
+   * windows, and every workgroup still takes a share of every part of the
+   * batch (the cost of a chunk varies much between fields) */
+  uint64_t g = (uint64_t)blockIdx.x * run;
+  const uint64_t g_end = n_total;
+  const uint64_t hop = (uint64_t)(gridDim.x - 1) * run + 1;
+  auto next_chunk = [&](uint64_t c2) -> uint64_t {
+    return ((c2 + 1) & (run - 1)) ? c2 + 1 : c2 + hop; /* run: 2^k */
+  };
   /* this thread's staging groups m = t + 256 r of a chunk */
   uint4 qr[kEncRounds];
   auto load_bins = [&](uint64_t c2, uint32_t f2) {
 #pragma unroll
     for (uint32_t r = 0; r < kEncRounds; ++r) qr[r] = make_uint4(0, 0, 0, 0);
-    if (c2 >= n_total) return;
+    if (c2 >= g_end) return;
     const uint16_t* codes2 = cfields[f2].codes;
     const uint64_t b2 = geo[c2].begin;
     const uint32_t n2 = geo[c2].n;
@@ -591,8 +601,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
   };
   for (uint32_t i = tid; i <= max_words; i += kEncThreads) words[i] = 0;
   if (tid == 0) s_nz = 0;
-  uint64_t g = blockIdx.x;
-  uint32_t fn = g < n_total ? field_of(g) : 0u;
+  uint32_t fn = g < g_end ? field_of(g) : 0u;
   load_bins(g, fn);
   uint32_t loaded = ~0u; /* field whose table window is in LDS */
   uint32_t tw = 0, wo = 0;
@@ -601,7 +610,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
   uint64_t pk_acc = 0;
   const uint32_t j = tid / kEncLanesPerSeg;
   const uint32_t k0 = (tid % kEncLanesPerSeg) * kEncLaneBins;
-  while (g < n_total) {
+  while (g < g_end) {
     const uint32_t f = fn;
     const QOZ_CONST EncField& F = cfields[f];
     const int32_t lo = F.lo;
@@ -687,8 +696,8 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
     for (uint32_t i = tid; i < dirty; i += kEncThreads) words[i] = 0;
     __syncthreads();
     /* the next chunk's bins load while this one is coded */
-    const uint64_t gn = g + gridDim.x;
-    fn = gn < n_total ? field_of(gn) : 0u;
+    const uint64_t gn = next_chunk(g);
+    fn = gn < g_end ? field_of(gn) : 0u;
     load_bins(gn, fn);
     /* the thread's 16 code table entries ((code << 8) | length; 0 past the
      * chunk's end); symbols outside the LDS window in a branch of their
@@ -866,7 +875,8 @@ void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
   const size_t lds = 8 * ((size_t)tcap + 2) +
                      4 * ((size_t)max_words + 1 + kEncThreads);
   /* as many workgroups as can be resident at once (each takes every
-   * grid-th chunk, so one that waits for a slot would finish last) */
+   * grid-th run of chunks, so one that waits for a slot would finish
+   * last) */
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
@@ -881,13 +891,20 @@ void launch_huff_encode(const EncField* fields, const uint64_t* chunk0,
       per_cu <= 0)
     per_cu = 1;
   const uint64_t n_wg = (uint64_t)cus * (uint64_t)per_cu;
-  const uint32_t grid = (uint32_t)(n_chunks < n_wg ? n_chunks : n_wg);
+  /* runs of up to 8 chunks while every workgroup still takes 4 runs or
+   * more */
+  uint32_t run = 8;
+  while (run > 1 && n_chunks < (uint64_t)run * 4 * n_wg) run /= 2;
+  const uint64_t n_runs = (n_chunks + run - 1) / run;
+  const uint32_t grid = (uint32_t)(n_runs < n_wg ? n_runs : n_wg);
   if (long_codes)
     QOZ_LAUNCH(k_huff_encode<true>, dim3(grid), dim3(kEncThreads), lds, s,
-               fields, chunk0, geo, gw, gz, nf, n_chunks, tcap, max_words);
+               fields, chunk0, geo, gw, gz, nf, n_chunks, tcap, max_words,
+               run);
   else
     QOZ_LAUNCH(k_huff_encode<false>, dim3(grid), dim3(kEncThreads), lds, s,
-               fields, chunk0, geo, gw, gz, nf, n_chunks, tcap, max_words);
+               fields, chunk0, geo, gw, gz, nf, n_chunks, tcap, max_words,
+               run);
 }
 
 }  // namespace qoz

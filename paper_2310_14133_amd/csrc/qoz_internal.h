@@ -347,6 +347,10 @@ constexpr uint32_t kSortCap = 4096;
 constexpr uint32_t kSortCapBig = 16384; /* second pass, 128 KB of LDS */
 bool huffman_lengths_sorted(const uint64_t* keys, uint32_t n, uint8_t* len);
 uint64_t huffman_cost_sorted(const uint64_t* keys, uint32_t n);
+/* The used symbols of a whole histogram as keys (count << 16) | symbol in
+ * ascending order (radix passes over the count). */
+void hist_keys_sorted(const uint32_t* hist, uint32_t nsym,
+                      std::vector<uint64_t>* keys);
 /* An upper bound on the payload words of any chunk of at most `chunk`
  * bins: the `chunk` longest code occurrences of the field (keys as above,
  * lens[i] the length of keys[i]'s symbol). */

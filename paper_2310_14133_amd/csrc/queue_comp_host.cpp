@@ -84,23 +84,29 @@ bool field_code(CField& f) {
     return false;
   f.words_bound =
       chunk_words_bound(keys.data(), klen.data(), (uint32_t)keys.size(), kChunk);
-  std::vector<uint32_t> idx(keys.size());
-  for (uint32_t i = 0; i < idx.size(); ++i) idx[i] = i;
-  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
-    return (keys[a] & 0xffffu) < (keys[b] & 0xffffu);
-  });
+  /* the used symbols in ascending order: each key's length placed at its
+   * symbol (symbols are distinct), then one pass over the alphabet */
   const size_t n_used = keys.size();
-  f.usym.resize(n_used);
-  f.ulen.resize(n_used);
+  std::vector<uint8_t> len_of(kNSym, 0);
   f.n_unpred = 0;
   f.max_len = 0;
-  for (uint32_t i = 0; i < n_used; ++i) {
-    f.usym[i] = (uint16_t)(keys[idx[i]] & 0xffffu);
-    f.ulen[i] = klen[idx[i]];
-    if (f.usym[i] == 0) f.n_unpred = keys[idx[i]] >> 16;
-    if (f.ulen[i] > 56) return false;
-    f.max_len = std::max<uint32_t>(f.max_len, f.ulen[i]);
+  for (size_t i = 0; i < n_used; ++i) {
+    const uint32_t sym = (uint32_t)(keys[i] & 0xffffu);
+    if (klen[i] == 0 || klen[i] > 56) return false;
+    len_of[sym] = klen[i];
+    if (sym == 0) f.n_unpred = keys[i] >> 16;
+    f.max_len = std::max<uint32_t>(f.max_len, klen[i]);
   }
+  f.usym.resize(n_used);
+  f.ulen.resize(n_used);
+  size_t m = 0;
+  for (uint32_t sym = 0; sym < kNSym && m < n_used; ++sym)
+    if (len_of[sym]) {
+      f.usym[m] = (uint16_t)sym;
+      f.ulen[m] = len_of[sym];
+      ++m;
+    }
+  if (m != n_used) return false; /* a symbol twice */
   std::vector<uint64_t> ucode(n_used);
   canonical_codes_sparse(f.usym.data(), f.ulen.data(), (uint32_t)n_used,
                          ucode.data());
@@ -384,29 +390,35 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
       bigs.push_back(k);
     }
   }
-  if (!bigs.empty()) { /* whole histograms of the fields with many bins */
-    const size_t hbytes = 4ull * kNSym;
+  /* whole histograms of the fields with more used bins than the device
+   * sort holds: one read-back for all of them */
+  std::vector<uint32_t> big_at(nf, 0);
+  const size_t hbytes = 4ull * kNSym;
+  if (!bigs.empty()) {
     QOZ_TRY(ensure_pinned(c, hdr + al(hbytes * bigs.size()) +
                                  al(sizeof(HostCopy) * bigs.size())));
     hb = (uint8_t*)c->pinned + hdr;
     HostCopy* hc = (HostCopy*)(hb + al(hbytes * bigs.size()));
-    for (size_t b = 0; b < bigs.size(); ++b)
+    for (size_t b = 0; b < bigs.size(); ++b) {
       hc[b] = HostCopy{D + hist_off + hbytes * bigs[b], hb + hbytes * b,
                        hbytes};
+      big_at[bigs[b]] = (uint32_t)b;
+    }
     QOZ_TRY(gather_to_host(c, hc, (uint32_t)bigs.size(), s));
     QOZ_TRY(sync_q(s));
-    for (size_t b = 0; b < bigs.size(); ++b) {
-      const uint32_t* h = (const uint32_t*)(hb + hbytes * b);
-      CField& f = F[bigs[b]];
-      for (uint32_t sy = 0; sy < kNSym; ++sy)
-        if (h[sy]) f.keys.push_back(((uint64_t)h[sy] << 16) | sy);
-      std::sort(f.keys.begin(), f.keys.end());
-    }
   }
   {
+    /* per field on the host threads: the keys of a field with many used
+     * bins from its histogram (radix passes), then its code */
+    const uint8_t* hbig = hb;
     std::vector<char> ok(nf, 1);
     on_threads(nf, [&](size_t k) {
-      if (items[F[k].item].status == QOZ_OK) ok[k] = field_code(F[k]);
+      CField& f = F[k];
+      if (items[f.item].status != QOZ_OK) return;
+      if (f.big)
+        hist_keys_sorted(
+            (const uint32_t*)(hbig + hbytes * big_at[k]), kNSym, &f.keys);
+      ok[k] = field_code(f);
     });
     for (uint32_t k = 0; k < nf; ++k)
       if (!ok[k]) items[F[k].item].status = QOZ_EINVAL;
