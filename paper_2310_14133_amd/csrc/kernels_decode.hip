@@ -29,6 +29,8 @@
  * words), a codeword is invalid, or a chunk's symbol-0 count disagrees with
  * the chunk table.
  */
+#include <mutex>
+
 #include "qoz_device.h"
 #include "qoz_internal.h"
 
@@ -337,27 +339,32 @@ __device__ __forceinline__ void decode_wg(
     uint32_t len = e & 0x3fu;
     uint32_t s = e >> 16;
     zor |= e;
-    /* a code of up to kEnt2Depth bits beyond a prefix with a second-level
-     * table: one more lookup with the bits after the prefix */
-    if (__builtin_expect(len == 0 && (e & 0x80u) != 0, 0)) {
-      const uint32_t d = (e >> 8) & 15u;
-      const uint32_t e2 = sh.ent2[(e >> 12) + ((top << kSymBits) >> (32 - d))];
-      len = e2 & 0x3fu;
-      s = e2 >> 16;
-      zor |= e2;
-    }
+    /* one test on the common path: an entry of length 0 is either a
+     * prefix with a second-level table or a code the tables do not hold */
     if (__builtin_expect(len == 0, 0)) {
-      s = slow_symbol(rd, W, top, lim, sh, tabs, syms, maxlen, &len);
-      if (s == kInvalid) {
-        inv = true;
-        s = 1;
-        len = 1;
+      /* a code of up to kEnt2Depth bits beyond the prefix: one more lookup
+       * with the bits after it */
+      if (e & 0x80u) {
+        const uint32_t d = (e >> 8) & 15u;
+        const uint32_t e2 =
+            sh.ent2[(e >> 12) + ((top << kSymBits) >> (32 - d))];
+        len = e2 & 0x3fu;
+        s = e2 >> 16;
+        zor |= e2;
       }
-      zor |= s == 0 ? kEntZero : 0u;
-      /* a code longer than the pair's guaranteed bits: seek past it */
-      if (len > 32) {
-        rd.seek(sh, W, rd.pos() + len);
-        len = 0;
+      if (len == 0) {
+        s = slow_symbol(rd, W, top, lim, sh, tabs, syms, maxlen, &len);
+        if (s == kInvalid) {
+          inv = true;
+          s = 1;
+          len = 1;
+        }
+        zor |= s == 0 ? kEntZero : 0u;
+        /* a code longer than the pair's guaranteed bits: seek past it */
+        if (len > 32) {
+          rd.seek(sh, W, rd.pos() + len);
+          len = 0;
+        }
       }
     }
     rd.advance(len, nx);
@@ -438,29 +445,65 @@ __device__ __forceinline__ void decode_wg(
   if (have && bad) atomicOr(status, kStBadStream);
 }
 
-__global__ __launch_bounds__(kDecWG) void k_huff_decode(
+static_assert(2 * sizeof(DecShared) <= 160 * 1024,
+              "two decoding workgroups share a CU's LDS");
+
+/* The decoding state lives in dynamic LDS (sizeof(DecShared), above the
+ * default limit: the launchers raise it once per device).  With the size
+ * unknown at compile time the compiler can be held to six waves per SIMD
+ * (at most 80 VGPRs): two 10-wave workgroups then fit a CU however the
+ * waves are spread over its SIMDs (with static LDS it assumes five, and a
+ * second workgroup whose waves land unevenly waits for the first). */
+__global__ __launch_bounds__(kDecWG) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void k_huff_decode(
     const uint32_t* __restrict__ payload, uint64_t n_words,
     const uint64_t* __restrict__ coff, const uint32_t* __restrict__ upre,
     const uint16_t* __restrict__ segs, Chunks ch,
     uint64_t n_unpred, const DecTables* __restrict__ tabs,
     const uint32_t* __restrict__ syms, uint16_t* __restrict__ codes,
     uint32_t* __restrict__ upos, uint32_t* status) {
-  __shared__ DecShared sh;
+  extern __shared__ DecShared dyn_sh[];
+  DecShared& sh = dyn_sh[0];
   decode_wg(sh, payload, n_words, coff, upre, segs, ch, n_unpred, tabs, syms,
             codes, upos, status, blockIdx.x);
 }
 
 /* Every stream of a batch in one launch: a workgroup decodes chunks of the
  * stream its queue entry names. */
-__global__ __launch_bounds__(kDecWG) void k_huff_decode_q(
+__global__ __launch_bounds__(kDecWG) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void k_huff_decode_q(
     const DecJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
     uint32_t n_jobs) {
-  __shared__ DecShared sh;
+  extern __shared__ DecShared dyn_sh[];
+  DecShared& sh = dyn_sh[0];
   const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
   const DecJob& a = jobs[j];
-  decode_wg(sh, a.payload, a.n_words, a.coff, a.upre, a.segs, a.ch,
-            a.n_unpred, a.tabs, a.syms, a.codes, a.upos, a.status,
-            blockIdx.x - wg0[j]);
+  /* pointers read from a record are generic (flat accesses, which also
+   * count against the LDS counter): made global again here */
+  decode_wg(sh, (const uint32_t*)gptr(a.payload), a.n_words,
+            (const uint64_t*)gptr(a.coff), (const uint32_t*)gptr(a.upre),
+            (const uint16_t*)gptr(a.segs), a.ch, a.n_unpred,
+            (const DecTables*)gptr(a.tabs), (const uint32_t*)gptr(a.syms),
+            (uint16_t*)gptr(a.codes), (uint32_t*)gptr(a.upos),
+            (uint32_t*)gptr(a.status), blockIdx.x - wg0[j]);
+}
+
+/* The decoders' dynamic LDS is above the default limit: raised once per
+ * device (the launchers run on several host threads).  A launch whose
+ * limit could not be raised fails, and its caller reports the error. */
+static void dec_lds_limit() {
+  constexpr int kMaxDev = 64;
+  static std::once_flag once[kMaxDev];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return;
+  std::call_once(once[dev], [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_huff_decode),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(DecShared));
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_huff_decode_q),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(DecShared));
+  });
 }
 
 uint32_t decode_workgroups(uint64_t n_chunks) {
@@ -470,8 +513,9 @@ uint32_t decode_workgroups(uint64_t n_chunks) {
 void launch_huff_decode_q(const DecJob* jobs, const uint32_t* wg0,
                           uint32_t n_jobs, uint32_t total_wg, hipStream_t s) {
   if (!total_wg) return;
-  QOZ_LAUNCH(k_huff_decode_q, dim3(total_wg), dim3(kDecWG), 0, s,
-                     jobs, wg0, n_jobs);
+  dec_lds_limit();
+  QOZ_LAUNCH(k_huff_decode_q, dim3(total_wg), dim3(kDecWG),
+             sizeof(DecShared), s, jobs, wg0, n_jobs);
 }
 
 void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
@@ -483,9 +527,10 @@ void launch_huff_decode(const uint32_t* payload, uint64_t n_words,
   const uint64_t n_chunks = chunks.count();
   if (!n_chunks) return;
   const uint64_t blocks = (n_chunks + kChunksPerWG - 1) / kChunksPerWG;
-  QOZ_LAUNCH(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecWG), 0,
-                     s, payload, n_words, coff, upre, segs, chunks, n_unpred,
-                     tabs, syms, codes, upos, status);
+  dec_lds_limit();
+  QOZ_LAUNCH(k_huff_decode, dim3((uint32_t)blocks), dim3(kDecWG),
+             sizeof(DecShared), s, payload, n_words, coff, upre, segs, chunks,
+             n_unpred, tabs, syms, codes, upos, status);
 }
 
 }  // namespace qoz

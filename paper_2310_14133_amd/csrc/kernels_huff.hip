@@ -81,7 +81,9 @@ __global__ __launch_bounds__(kHistThreads) void k_hist_q(
     const HistJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
     uint32_t n_jobs) {
   const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
-  hist_wg(jobs[j].codes, jobs[j].n, jobs[j].hist, blockIdx.x - wg0[j]);
+  /* the record's pointers made global (not flat) */
+  hist_wg((const uint16_t*)gptr(jobs[j].codes), jobs[j].n,
+          (uint32_t*)gptr(jobs[j].hist), blockIdx.x - wg0[j]);
 }
 
 uint32_t hist_job_workgroups(const HistJob& j) {
@@ -396,12 +398,17 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
   __shared__ uint8_t lens[kCountLens];
   const uint32_t f = find_job(wg0, nf, blockIdx.x);
   const EncField& F = fields[f];
+  /* pointers read from the record, made global (flat accesses would also
+   * count against the LDS counter) */
+  const __attribute__((address_space(1))) uint64_t* const tab = gptr(F.tab);
+  const __attribute__((address_space(1))) uint16_t* const codes =
+      gptr(F.codes);
   const uint32_t tn = F.tn;
   const uint32_t tl = tn < kCountLens ? tn : kCountLens;
   const int32_t lo = F.lo;
   const uint32_t wo = table_window(lo, tn, kCountLens);
   for (uint32_t i = threadIdx.x; i < tl; i += kCountThreads)
-    lens[i] = (uint8_t)(F.tab[wo + i] & 0xff);
+    lens[i] = (uint8_t)(tab[wo + i] & 0xff);
   __syncthreads();
   const uint32_t zlen = (uint32_t)(F.zero_entry & 0xff);
   const uint64_t c0 = (uint64_t)(blockIdx.x - wg0[f]) * kCountChunks;
@@ -411,7 +418,7 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
     const uint32_t o = sym - (uint32_t)lo;
     const uint32_t l = sym == 0 ? zlen
                        : o - wo < tl ? (uint32_t)lens[o - wo]
-                       : o < tn ? (uint32_t)(F.tab[o] & 0xff)
+                       : o < tn ? (uint32_t)(tab[o] & 0xff)
                                 : 0u;
     bits += l;
     zeros += sym == 0 ? 1u : 0u;
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
     for (uint32_t u = 0; u < kGroups; ++u) {
       const uint32_t m = lane + 64 * u;
       q[u] = 8 * m + 8 <= n
-                 ? *reinterpret_cast<const uint4*>(F.codes + b + 8 * m)
+                 ? gload16((const uint16_t*)(codes + b + 8 * m))
                  : make_uint4(0, 0, 0, 0);
     }
     uint32_t bits = 0, zeros = 0;
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(kCountThreads) void k_huff_count(
         for (uint32_t k = 0; k < 8; ++k)
           add((w[k >> 1] >> (16 * (k & 1))) & 0xffffu, bits, zeros);
       } else {
-        for (uint32_t i = 8 * m; i < n; ++i) add(F.codes[b + i], bits, zeros);
+        for (uint32_t i = 8 * m; i < n; ++i) add(codes[b + i], bits, zeros);
       }
     }
     bits = wave_sum_u32(bits);
@@ -467,10 +474,10 @@ void launch_huff_count(const EncField* fields, const uint64_t* chunk0,
 /* Encoding of the chunks of one or more fields, after k_huff_count and the
  * chunk scan: gw and gz are the exclusive prefixes of the chunks' payload
  * words and symbol-0 bins over the global chunk order (a field's offsets
- * are differences of them).  Workgroup w codes global chunks (field after
- * field) w, w + G, w + 2G, ... for a grid of G as large as the device
- * holds at once, and loads the next chunk's bins while it codes the
- * current one.  Per chunk:
+ * are differences of them).  Workgroup w codes runs of R global chunks
+ * (field after field; R up to 8): runs w, w + G, w + 2G, ... for a grid of
+ * G as large as the device holds at once, and loads the next chunk's bins
+ * while it codes the current one.  Per chunk:
  *   - segment-major staging of the bins in LDS (segment j holds the
  *     chunk's bins j, j + 8, ...; bins past the chunk's end stage as 1);
  *   - thread t codes bins [16 (t mod 32), +16) of segment t / 32 (thread

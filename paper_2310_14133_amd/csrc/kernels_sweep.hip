@@ -829,10 +829,14 @@ __global__ __launch_bounds__(kRowThreads) void k_sweep_round_q(
   const uint32_t j = find_job(wg0, n_jobs, gid);
   const SweepJob& a = jobs[j];
   const uint32_t lid = gid - wg0[j];
+  /* the record's pointers made global: flat accesses would also count
+   * against the LDS counter */
+  float* const W = (float*)gptr(a.W);
+  const uint16_t* const codes = (const uint16_t*)gptr(a.codes);
   if (a.rows)
-    row_decomp_wg(a.g, a.rj, a.W, a.codes, lid, E);
+    row_decomp_wg(a.g, a.rj, W, codes, lid, E);
   else
-    sweep_decomp_wg(a.g, a.s, a.W, a.codes, lid % a.gx, lid / a.gx, a.gy,
+    sweep_decomp_wg(a.g, a.s, W, codes, lid % a.gx, lid / a.gx, a.gy,
                     threadIdx.x % kSweepTX, threadIdx.x / kSweepTX,
                     kRowThreads / kSweepTX);
 }
@@ -847,18 +851,23 @@ __global__ __launch_bounds__(kRowThreads) void k_sweep_round_comp_q(
   const uint32_t j = find_job(wg0, n_jobs, gid);
   const CompJob& a = jobs[j];
   const uint32_t lid = gid - wg0[j];
+  /* the record's pointers made global (not flat) */
+  const float* const x = (const float*)gptr(a.x);
+  float* const W = (float*)gptr(a.W);
+  uint16_t* const codes = (uint16_t*)gptr(a.codes);
+  uint32_t* const status = (uint32_t*)gptr(a.status);
   if (a.rows) {
     if (a.write_w)
-      row_comp_wg<true>(a.g, a.rj, a.x, a.W, a.codes, a.status, lid, E);
+      row_comp_wg<true>(a.g, a.rj, x, W, codes, status, lid, E);
     else
-      row_comp_wg<false>(a.g, a.rj, a.x, a.W, a.codes, a.status, lid, E);
+      row_comp_wg<false>(a.g, a.rj, x, W, codes, status, lid, E);
   } else {
     const uint32_t tx = threadIdx.x % kSweepTX, ty = threadIdx.x / kSweepTX;
     if (a.write_w)
-      sweep_comp_wg<true>(a.g, a.s, a.x, a.W, a.codes, a.status, lid % a.gx,
+      sweep_comp_wg<true>(a.g, a.s, x, W, codes, status, lid % a.gx,
                           lid / a.gx, a.gy, tx, ty, kRowThreads / kSweepTX);
     else
-      sweep_comp_wg<false>(a.g, a.s, a.x, a.W, a.codes, a.status, lid % a.gx,
+      sweep_comp_wg<false>(a.g, a.s, x, W, codes, status, lid % a.gx,
                            lid / a.gx, a.gy, tx, ty, kRowThreads / kSweepTX);
   }
 }
