@@ -81,9 +81,9 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   PROF(PK_ANCHOR, 8.0 * P.n_anchor,
        launch_anchor_copy(P.g, P.s, P.na, d_x, W, (float*)c->anchors.p, st,
                           s));
-  size_t fa = SIZE_MAX, fb = SIZE_MAX;
+  size_t fz = SIZE_MAX, fa = SIZE_MAX, fb = SIZE_MAX;
   RowJob rj;
-  const bool fuse = level1_rows(P, &fa, &fb, &rj);
+  const bool fuse = level1_rows(P, &fz, &fa, &fb, &rj);
   const std::vector<SweepTile>* tiles = nullptr;
   {
     auto it = c->tiles_comp.find(tile_key(P));
@@ -91,10 +91,12 @@ qoz_status compress_with_plan(qoz_ctx* c, const float* d_x, const Plan& P,
   }
   for (size_t i = 0; i < P.sweeps.size(); ++i) {
     const Sweep& sw = P.sweeps[i];
-    if (fuse && (i == fa || i == fb)) {
-      if (i == fb) { /* sweep A (if any) and B as one row pass */
+    if (fuse && (i == fz || i == fa || i == fb)) {
+      if (i == fb) { /* sweeps F and A (if fused) and B as one pass */
         const bool write_w = fb + 1 < P.sweeps.size();
-        const double tg = (double)rj.B.count + (fa != SIZE_MAX ? rj.A.count : 0);
+        const double tg = (double)rj.B.count +
+                          (fa != SIZE_MAX ? rj.A.count : 0) +
+                          (fz != SIZE_MAX ? rj.F.count : 0);
         PROF(PK_ROW_COMP_L1, tg * ((write_w ? 12.0 : 8.0) + kCodeBytes),
              launch_row_comp(P.g, rj, d_x, W, codes, write_w, st, s));
       }
@@ -501,9 +503,9 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   PROF(PK_ANCHOR, 8.0 * P.n_anchor,
        launch_anchor_scatter(P.g, P.s, P.na, (const float*)(in + lay.anchors),
                              d_y, s));
-  size_t fa = SIZE_MAX, fb = SIZE_MAX;
+  size_t fz = SIZE_MAX, fa = SIZE_MAX, fb = SIZE_MAX;
   RowJob rj;
-  const bool fuse = level1_rows(P, &fa, &fb, &rj);
+  const bool fuse = level1_rows(P, &fz, &fa, &fb, &rj);
   const std::vector<SweepTile>* tiles = nullptr;
   {
     auto it = c->tiles_decomp.find(tile_key(P));
@@ -511,9 +513,11 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   }
   for (size_t i = 0; i < P.sweeps.size(); ++i) {
     const Sweep& sw = P.sweeps[i];
-    if (fuse && (i == fa || i == fb)) {
+    if (fuse && (i == fz || i == fa || i == fb)) {
       if (i == fb) {
-        const double tg = (double)rj.B.count + (fa != SIZE_MAX ? rj.A.count : 0);
+        const double tg = (double)rj.B.count +
+                          (fa != SIZE_MAX ? rj.A.count : 0) +
+                          (fz != SIZE_MAX ? rj.F.count : 0);
         PROF(PK_ROW_DEC_L1, tg * (8.0 + kCodeBytes),
              launch_row_decomp(P.g, rj, d_y, codes, s));
       }

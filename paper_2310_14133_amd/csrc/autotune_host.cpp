@@ -78,9 +78,9 @@ extern "C" qoz_status qoz_autotune_tiles(qoz_ctx* c, qoz_shape shape,
   launch_zero_u32((uint32_t*)W, N, s);
   launch_zero_u32((uint32_t*)codes, (2 * (P.n_codes + 16)) / 4, s);
   launch_init_status(st, s);
-  size_t fa = SIZE_MAX, fb = SIZE_MAX;
+  size_t fz = SIZE_MAX, fa = SIZE_MAX, fb = SIZE_MAX;
   RowJob rj;
-  const bool fuse = level1_rows(P, &fa, &fb, &rj);
+  const bool fuse = level1_rows(P, &fz, &fa, &fb, &rj);
   hipEvent_t a = nullptr, b = nullptr;
   QOZ_HIP(hipEventCreate(&a));
   if (hipEventCreate(&b) != hipSuccess) {
@@ -93,7 +93,7 @@ extern "C" qoz_status qoz_autotune_tiles(qoz_ctx* c, qoz_shape shape,
   float sum_def = 0.0f, sum_best = 0.0f, tb = 0.0f, tdf = 0.0f;
   qoz_status st_ = QOZ_OK;
   for (size_t i = 0; i < ns && st_ == QOZ_OK; ++i) {
-    if (fuse && (i == fa || i == fb)) continue;
+    if (fuse && (i == fz || i == fa || i == fb)) continue;
     const Sweep& sw = P.sweeps[i];
     const bool last = i + 1 == ns;
     st_ = best_tile(s, a, b, [&](SweepTile t) {

@@ -405,16 +405,21 @@ void launch_unpred_scatter(const Geo& g, const SweepTable& st,
 }
 
 /* ---- level-1 row kernels ------------------------------------------------
- * The sweep along the contiguous dimension (targets at odd positions of a
- * row) reads only even positions of the same row, so it is fused with the
- * sweep just before it in the level's order (its targets sit at the even
- * positions of rows that are odd along that sweep's dimension, and are
- * predicted from neighbour rows).  A workgroup takes several rows; each
- * lane takes 8-point spans.  Phase 1 computes the even positions (sweep A,
- * or the known values) into LDS, phase 2 predicts and quantizes the odd
- * positions (sweep B).  Every target is computed exactly as the per-sweep
- * kernels compute it; only the schedule and the memory access change.
- * Rows are the (p0, p1) pairs of the row set (steps 1 or 2). */
+ * The sweep along the contiguous dimension (B: targets at odd points of a
+ * row) reads only even points of the same row, so it is fused with the
+ * sweep just before it in the level's order (A: its targets sit at the
+ * even points of rows odd along a, predicted from the rows at -3 .. +3
+ * along a) and, when the level's order is (f, a, 2), with the first sweep
+ * too (F: targets at the even points of rows odd along f and even along a,
+ * predicted from rows of the coarser levels).  A workgroup takes a tile of
+ * rows along a (with two rows before and three after it, whose F values
+ * it computes again, so that the A rows find their neighbours in LDS) by
+ * up to 512 points; each lane takes 8-point spans.  Phase 1 computes the
+ * even points of the even rows (sweep F, or the known values) into LDS,
+ * phase 2 those of the odd rows (sweep A), phase 3 the odd points of the
+ * tile's rows (sweep B).  Every target is computed exactly as the
+ * per-sweep kernels compute it and coded by the one tile that owns it;
+ * only the schedule and the memory access change. */
 constexpr uint32_t kRowThreads = 256;
 constexpr uint32_t kSpan = 8;
 
@@ -476,141 +481,263 @@ __device__ __forceinline__ void store_bins4(uint16_t* __restrict__ c,
   }
 }
 
-struct RowCtx {
-  uint32_t p0, p1, row, pa;
-  bool hasA;
+/* A tile of the level-1 pass: T rows along the tile dimension td (A's
+ * dimension when A exists, else dimension 1) at row index io of the other
+ * dimension, by S points of the contiguous dimension from P0.  E holds the
+ * values at the even points P0 - 2 .. P0 + S + 2 of the rows it0 - lo ..
+ * it0 + T + hi - 1 (lo = 2, hi = 3 when A exists: the neighbour rows of
+ * the tile's A rows; else the tile's rows only).  Entry e of a row (point
+ * P0 + 2 (e - 1)) sits at index e + 3 of the row's es = S / 2 + 8 floats:
+ * the four even points of a span are one aligned 16-byte word. */
+struct L1Tile {
+  uint32_t td, it0, io, P0, lo, nr, es, nt;
 };
 
-/* item it of a workgroup: row it / spans, span it mod spans */
-struct RowItems {
-  uint32_t spans;
-  FastDiv fs, fr;
-  __device__ __forceinline__ RowItems(uint32_t sp, uint32_t items,
-                                      uint32_t rows, uint32_t rcnt1)
-      : spans(sp), fs(sp, items), fr(rcnt1, rows) {}
-};
-
-__device__ __forceinline__ RowCtx row_ctx(const Geo& g, const RowJob& rj,
-                                          const FastDiv& fr, uint32_t r) {
-  RowCtx c;
-  const uint32_t i0 = fr.div(r);
-  const uint32_t i1 = r - i0 * rj.rcnt[1];
-  c.p0 = i0 * rj.rstep[0];
-  c.p1 = i1 * rj.rstep[1];
-  c.row = c.p0 * g.st[0] + c.p1 * g.st[1];
-  c.pa = rj.a == 0 ? c.p0 : c.p1;
-  c.hasA = rj.a >= 0 && (c.pa & 1u);
-  return c;
+__device__ __forceinline__ L1Tile l1_tile(const RowJob& rj, uint32_t blk) {
+  L1Tile t;
+  t.td = rj.a >= 0 ? (uint32_t)rj.a : 1u;
+  const uint32_t s2 = blk % rj.tiles2, r = blk / rj.tiles2;
+  t.it0 = (r % rj.tilesT) * rj.T;
+  t.io = r / rj.tilesT;
+  t.P0 = s2 * rj.S;
+  t.lo = rj.a >= 0 ? 2u : 0u;
+  t.nr = rj.T + (rj.a >= 0 ? 5u : 0u);
+  t.es = rj.S / 2 + 8;
+  t.nt = rj.rcnt[t.td];
+  return t;
 }
 
-/* Sweep-A predictions of the even points of span [p, p + kSpan): the
- * neighbour rows at -3, -1, +1, +3 along a (present ones only). */
-__device__ __forceinline__ void predict_span_A(const Geo& g, const RowJob& rj,
-                                               const float* W, const RowCtx& c,
-                                               uint32_t p, float* pred) {
-  const uint32_t sa = g.st[rj.a], na = g.n[rj.a], n2 = g.n[2];
-  const bool ha = c.pa >= 3, hc = c.pa + 1 < na, hd = c.pa + 3 < na;
-  const bool cub = rj.A.cubic != 0;
+/* E row l of a tile: its coordinates and flat offset; ok: inside the row
+ * set; own: one of the tile's rows (its targets are this tile's to code). */
+struct L1Row {
+  uint32_t p0, p1, row, pt;
+  bool ok, own;
+};
+
+__device__ __forceinline__ L1Row l1_row(const Geo& g, const RowJob& rj,
+                                        const L1Tile& t, uint32_t l) {
+  L1Row r;
+  const int32_t it = (int32_t)t.it0 - (int32_t)t.lo + (int32_t)l;
+  r.ok = it >= 0 && (uint32_t)it < t.nt;
+  r.own = r.ok && l >= t.lo && l < t.lo + rj.T;
+  r.pt = (r.ok ? (uint32_t)it : 0u) * rj.rstep[t.td];
+  const uint32_t po = t.io * rj.rstep[1 - t.td];
+  r.p0 = t.td == 0 ? r.pt : po;
+  r.p1 = t.td == 0 ? po : r.pt;
+  r.row = r.p0 * g.st[0] + r.p1 * g.st[1];
+  return r;
+}
+
+/* Predictions of the even points of span [p, p + kSpan) of the row at
+ * offset row (coordinate pk along the swept dimension: stride sk, extent
+ * nk) from the rows at -3, -1, +1, +3 along it in W (present ones only). */
+__device__ __forceinline__ void predict_span(const float* W, uint32_t row,
+                                             uint32_t pk, uint32_t sk,
+                                             uint32_t nk, uint32_t cubic,
+                                             uint32_t p, uint32_t n2,
+                                             float* pred) {
+  const bool ha = pk >= 3, hc = pk + 1 < nk, hd = pk + 3 < nk;
+  const bool cub = cubic != 0;
   /* the points each rule reads (see interp_mid); the rest stay unread */
   const bool la = ha && (cub || !hc), ld = hd && cub;
   float vb[kSpan], vc[kSpan], va[kSpan], vd[kSpan];
-  load_span(W + c.row - sa, p, n2, vb);
-  if (hc) load_span(W + c.row + sa, p, n2, vc);
-  if (la) load_span(W + c.row - 3 * sa, p, n2, va);
-  if (ld) load_span(W + c.row + 3 * sa, p, n2, vd);
+  load_span(W + row - sk, p, n2, vb);
+  if (hc) load_span(W + row + sk, p, n2, vc);
+  if (la) load_span(W + row - 3 * sk, p, n2, va);
+  if (ld) load_span(W + row + 3 * sk, p, n2, vd);
 #pragma unroll
   for (uint32_t k = 0; k < kSpan / 2; ++k)
-    pred[k] = interp_mid(rj.A.cubic, la ? va[2 * k] : 0.0f, vb[2 * k],
+    pred[k] = interp_mid(cubic, la ? va[2 * k] : 0.0f, vb[2 * k],
                          hc ? vc[2 * k] : 0.0f, ld ? vd[2 * k] : 0.0f, ha, hc,
                          hd);
 }
 
-/* Workgroup blk of a fused level-1 row pair; E is the LDS row buffer. */
+/* The same along the tile dimension from the tile's E rows l - 3 .. l + 3
+ * at the 16-byte word q of each (the entries of one span). */
+__device__ __forceinline__ void predict_span_E(const float* E, uint32_t es,
+                                               uint32_t l, uint32_t q,
+                                               uint32_t pk, uint32_t nk,
+                                               uint32_t cubic, float* pred) {
+  const bool ha = pk >= 3, hc = pk + 1 < nk, hd = pk + 3 < nk;
+  const bool cub = cubic != 0;
+  const bool la = ha && (cub || !hc), ld = hd && cub;
+  const float4 vb = reinterpret_cast<const float4*>(E + (l - 1) * es)[q];
+  float4 va = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vc = va, vd = va;
+  if (hc) vc = reinterpret_cast<const float4*>(E + (l + 1) * es)[q];
+  if (la) va = reinterpret_cast<const float4*>(E + (l - 3) * es)[q];
+  if (ld) vd = reinterpret_cast<const float4*>(E + (l + 3) * es)[q];
+  const float a4[4] = {va.x, va.y, va.z, va.w}, b4[4] = {vb.x, vb.y, vb.z, vb.w};
+  const float c4[4] = {vc.x, vc.y, vc.z, vc.w}, d4[4] = {vd.x, vd.y, vd.z, vd.w};
+#pragma unroll
+  for (uint32_t k = 0; k < kSpan / 2; ++k)
+    pred[k] = interp_mid(cubic, a4[k], b4[k], c4[k], d4[k], ha, hc, hd);
+}
+
+/* The even-point values v of span u into E row Er (word u: entries
+ * 4u - 3 .. 4u; the left side span keeps only entry 0, the rest of the
+ * word lies before the row; entries past the row's points are never
+ * read). */
+__device__ __forceinline__ void store_span_E(float* Er, uint32_t u,
+                                             const float* v) {
+  if (u == 0)
+    Er[3] = v[3];
+  else
+    reinterpret_cast<float4*>(Er)[u] = make_float4(v[0], v[1], v[2], v[3]);
+}
+
+/* The entries 4u .. 4u + 6 of E row Er (the even points a phase-3 span's
+ * odd points are predicted from). */
+__device__ __forceinline__ void load_span_E(const float* Er, uint32_t u,
+                                            float* v) {
+  const float4 m = reinterpret_cast<const float4*>(Er)[u + 1];
+  const float2 h = reinterpret_cast<const float2*>(Er)[2 * u + 4];
+  v[0] = Er[4 * u + 3];
+  v[1] = m.x; v[2] = m.y; v[3] = m.z; v[4] = m.w;
+  v[5] = h.x; v[6] = h.y;
+}
+
+/* Phase items: rows of E and spans.  Phases 1 and 2 take the spans from
+ * P0 - 8 to P0 + S (the tile's spans and one on each side, whose even
+ * points P0 - 2, P0 + S and P0 + S + 2 the odd points of the tile's edge
+ * spans are predicted from); phase 3 the tile's spans. */
+struct L1Items {
+  uint32_t spans, n;
+  FastDiv fs;
+  __device__ __forceinline__ L1Items(uint32_t sp, uint32_t rows)
+      : spans(sp), n(sp * rows), fs(sp, sp * rows) {}
+};
+
+/* Workgroup blk of a level-1 pass (compression): sweep F (if fused) into
+ * the even rows of E, then sweep A into its odd rows, then sweep B along
+ * the rows; E is the LDS tile buffer. */
 template <bool WRITE_W>
 __device__ __forceinline__ void row_comp_wg(
     const Geo& g, const RowJob& rj, const float* __restrict__ x, float* W,
     uint16_t* __restrict__ codes, uint32_t* status, uint32_t blk, float* E) {
-  /* per row: E[t + 1] = value at 2t */
-  const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
-  const uint32_t spans = (n2 + kSpan - 1) / kSpan;
-  const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
-  const uint32_t r0 = blk * rj.rows_per_wg;
-  const uint32_t items = rj.rows_per_wg * spans;
-  const RowItems ri(spans, items, rows, rj.rcnt[1]);
-  /* one item per lane: the span's x values stay in registers between the
-   * phases */
-  const bool one = items <= kRowThreads;
-  float xv[kSpan];
+  const L1Tile t = l1_tile(rj, blk);
+  const uint32_t n2 = g.n[2];
+  const bool hasA = rj.a >= 0;
+  const uint32_t sp12 = rj.S / kSpan + 2, sp3 = rj.S / kSpan;
   bool bad = false;
-  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
-    if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
-    const uint32_t p = u * kSpan;
-    float* Er = E + rl * es;
-    if (c.hasA || one) load_span(x + c.row, p, n2, xv);
-    if (c.hasA) {
-      float pred[kSpan / 2];
-      predict_span_A(g, rj, W, c, p, pred);
-      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
-      const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
-      int32_t bins[kSpan / 2];
+  /* phase 1: even rows of E (all of them without A) */
+  {
+    const uint32_t rows = hasA ? (t.nr + 1) / 2 : rj.T;
+    const L1Items ii(sp12, rows);
+    for (uint32_t it = threadIdx.x; it < ii.n; it += kRowThreads) {
+      const uint32_t rl = ii.fs.div(it), u = it - rl * sp12;
+      const uint32_t l = hasA ? 2 * rl : rl;
+      const L1Row r = l1_row(g, rj, t, l);
+      if (!r.ok || t.P0 + kSpan * u < kSpan) continue;
+      const uint32_t p = t.P0 + kSpan * u - kSpan;
+      if (p >= n2) continue;
+      float* Er = E + l * t.es;
+      const bool isF = rj.f >= 0 && (((rj.f == 0 ? r.p0 : r.p1)) & 1u);
+      float v[kSpan / 2];
+      if (isF) {
+        const uint32_t pf = rj.f == 0 ? r.p0 : r.p1;
+        float pred[kSpan / 2], xv[kSpan];
+        predict_span(W, r.row, pf, g.st[rj.f], g.n[rj.f], rj.F.cubic, p, n2,
+                     pred);
+        load_span(x + r.row, p, n2, xv);
+        const bool coded = r.own && u >= 1 && u <= sp3;
+        int32_t bins[kSpan / 2];
 #pragma unroll
-      for (uint32_t k = 0; k < kSpan / 2; ++k) {
-        bins[k] = 0;
-        if (k >= nA) continue;
-        float e;
-        bins[k] =
-            quantize_bin(xv[2 * k], pred[k], rj.A.inv, rj.A.twoeb, rj.A.eb, &e);
-        bad |= !isfinite(xv[2 * k]);
-        Er[p / 2 + k + 1] = e;
+        for (uint32_t k = 0; k < kSpan / 2; ++k) {
+          bins[k] = quantize_bin(xv[2 * k], pred[k], rj.F.inv, rj.F.twoeb,
+                                 rj.F.eb, &v[k]);
+          if (coded && p + 2 * k < n2) bad |= !isfinite(xv[2 * k]);
+        }
+        if (coded) {
+          const uint32_t nF = (n2 - p + 1) / 2;
+          store_bins4(codes, stream_pos(rj.F, r.p0, r.p1, p), rj.vecF,
+                      nF < 4 ? nF : 4u, bins);
+        }
+      } else {
+        float wv[kSpan];
+        load_span(W + r.row, p, n2, wv);
+#pragma unroll
+        for (uint32_t k = 0; k < kSpan / 2; ++k) v[k] = wv[2 * k];
       }
-      store_bins4(codes, pos, rj.vecA, nA < 4 ? nA : 4u, bins);
-    } else {
-      float wv[kSpan];
-      load_span(W + c.row, p, n2, wv);
-#pragma unroll
-      for (uint32_t k = 0; k < kSpan / 2; ++k)
-        if (p + 2 * k < n2) Er[p / 2 + k + 1] = wv[2 * k];
+      store_span_E(Er, u, v);
     }
   }
   __syncthreads();
-  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
-    if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
-    const uint32_t p = u * kSpan;
-    const float* Er = E + rl * es;
-    float out[kSpan];
-    if (!one) load_span(x + c.row, p, n2, xv);
-    const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
-    const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
-    int32_t bins[kSpan / 2];
+  /* phase 2: the tile's A rows (odd along a) from the even rows of E */
+  if (hasA) {
+    const uint32_t na = g.n[rj.a];
+    const L1Items ii(sp12, rj.T / 2);
+    for (uint32_t it = threadIdx.x; it < ii.n; it += kRowThreads) {
+      const uint32_t rl = ii.fs.div(it), u = it - rl * sp12;
+      const uint32_t l = t.lo + 1 + 2 * rl;
+      const L1Row r = l1_row(g, rj, t, l);
+      if (!r.ok || t.P0 + kSpan * u < kSpan) continue;
+      const uint32_t p = t.P0 + kSpan * u - kSpan;
+      if (p >= n2) continue;
+      float pred[kSpan / 2], xv[kSpan], v[kSpan / 2];
+      predict_span_E(E, t.es, l, u, r.pt, na, rj.A.cubic, pred);
+      load_span(x + r.row, p, n2, xv);
+      const bool coded = u >= 1 && u <= sp3;
+      int32_t bins[kSpan / 2];
 #pragma unroll
-    for (uint32_t k = 0; k < kSpan / 2; ++k) {
-      const uint32_t t = p / 2 + k, q = 2 * t + 1;
-      out[2 * k] = Er[t + 1];
-      out[2 * k + 1] = 0.0f;
-      bins[k] = 0;
-      if (q >= n2) continue;
-      const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
-      const float pred =
-          interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
-                     hc ? Er[t + 2] : 0.0f, hd ? Er[t + 3] : 0.0f, ha, hc, hd);
-      float rec;
-      bins[k] =
-          quantize_bin(xv[2 * k + 1], pred, rj.B.inv, rj.B.twoeb, rj.B.eb, &rec);
-      bad |= !isfinite(xv[2 * k + 1]);
-      out[2 * k + 1] = rec;
+      for (uint32_t k = 0; k < kSpan / 2; ++k) {
+        bins[k] = quantize_bin(xv[2 * k], pred[k], rj.A.inv, rj.A.twoeb,
+                               rj.A.eb, &v[k]);
+        if (coded && p + 2 * k < n2) bad |= !isfinite(xv[2 * k]);
+      }
+      if (coded) {
+        const uint32_t nA = (n2 - p + 1) / 2;
+        store_bins4(codes, stream_pos(rj.A, r.p0, r.p1, p), rj.vecA,
+                    nA < 4 ? nA : 4u, bins);
+      }
+      store_span_E(E + l * t.es, u, v);
     }
-    store_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
-    if (WRITE_W) {
-      float* wr = W + c.row;
-      if (p + kSpan <= n2) {
-        *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
-        *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
-      } else {
-        for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+    __syncthreads();
+  }
+  /* phase 3: sweep B along the tile's rows */
+  {
+    const L1Items ii(sp3, rj.T);
+    for (uint32_t it = threadIdx.x; it < ii.n; it += kRowThreads) {
+      const uint32_t rl = ii.fs.div(it), u = it - rl * sp3;
+      const uint32_t l = t.lo + rl;
+      const L1Row r = l1_row(g, rj, t, l);
+      const uint32_t p = t.P0 + kSpan * u;
+      if (!r.ok || p >= n2) continue;
+      const float* Er = E + l * t.es;
+      float xv[kSpan], out[kSpan];
+      load_span(x + r.row, p, n2, xv);
+      const uint64_t pos = stream_pos(rj.B, r.p0, r.p1, p + 1);
+      const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
+      int32_t bins[kSpan / 2];
+      float ev[7];
+      load_span_E(Er, u, ev);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k) {
+        const uint32_t q = p + 2 * k + 1;
+        out[2 * k] = ev[k + 1];
+        out[2 * k + 1] = 0.0f;
+        bins[k] = 0;
+        if (q >= n2) continue;
+        const bool ha = q >= 3, hc = q + 1 < n2, hd = q + 3 < n2;
+        const float pred =
+            interp_mid(rj.B.cubic, ha ? ev[k] : 0.0f, ev[k + 1],
+                       hc ? ev[k + 2] : 0.0f, hd ? ev[k + 3] : 0.0f, ha, hc,
+                       hd);
+        float rec;
+        bins[k] = quantize_bin(xv[2 * k + 1], pred, rj.B.inv, rj.B.twoeb,
+                               rj.B.eb, &rec);
+        bad |= !isfinite(xv[2 * k + 1]);
+        out[2 * k + 1] = rec;
+      }
+      store_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
+      if (WRITE_W) {
+        float* wr = W + r.row;
+        if (p + kSpan <= n2) {
+          *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
+          *reinterpret_cast<F4*>(wr + p + 4) =
+              F4{out[4], out[5], out[6], out[7]};
+        } else {
+          for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+        }
       }
     }
   }
@@ -621,176 +748,153 @@ template <bool WRITE_W>
 __global__ __launch_bounds__(kRowThreads) void k_row_comp(
     Geo g, RowJob rj, const float* __restrict__ x, float* W,
     uint16_t* __restrict__ codes, uint32_t* status) {
-  extern __shared__ float E[];
-  row_comp_wg<WRITE_W>(g, rj, x, W, codes, status, blockIdx.x, E);
+  extern __shared__ __align__(16) float E[];
+  row_comp_wg<WRITE_W>(g, rj, x, W, codes, status,
+                       xcd_block(blockIdx.x, gridDim.x), E);
 }
 
-/* Decompression: bin 0 keeps the exact value already scattered into W.
- * The single-stream kernel keeps its own copy of the body of row_decomp_wg
- * below: calling the shared inline body compiled to a schedule that ran
- * 6 % slower at 512^3. */
-__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
-    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
-  extern __shared__ float E[];
-  const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
-  const uint32_t spans = (n2 + kSpan - 1) / kSpan;
-  const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
-  const uint32_t r0 = blockIdx.x * rj.rows_per_wg;
-  const uint32_t items = rj.rows_per_wg * spans;
-  const RowItems ri(spans, items, rows, rj.rcnt[1]);
-  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
-    if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
-    const uint32_t p = u * kSpan;
-    float* Er = E + rl * es;
-    if (c.hasA) {
-      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
-      const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
-      int32_t bins[kSpan / 2];
-      load_bins4(codes, pos, rj.vecA, nA < 4 ? nA : 4u, bins);
-      float pred[kSpan / 2];
-      predict_span_A(g, rj, W, c, p, pred);
-#pragma unroll
-      for (uint32_t k = 0; k < kSpan / 2; ++k) {
-        if (k >= nA) break;
-        const int32_t code = bins[k];
-        Er[p / 2 + k + 1] = code ? dequantize_bin(pred[k], code, rj.A.twoeb)
-                                 : W[c.row + p + 2 * k];
-      }
-    } else {
-      float wv[kSpan];
-      load_span(W + c.row, p, n2, wv);
-#pragma unroll
-      for (uint32_t k = 0; k < kSpan / 2; ++k)
-        if (p + 2 * k < n2) Er[p / 2 + k + 1] = wv[2 * k];
-    }
-  }
-  __syncthreads();
-  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
-    if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
-    const uint32_t p = u * kSpan;
-    const float* Er = E + rl * es;
-    float out[kSpan];
-    const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
-    const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
-    int32_t bins[kSpan / 2];
-    load_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
-#pragma unroll
-    for (uint32_t k = 0; k < kSpan / 2; ++k) {
-      const uint32_t t = p / 2 + k, q = 2 * t + 1;
-      out[2 * k] = Er[t + 1];
-      out[2 * k + 1] = 0.0f;
-      if (q >= n2) continue;
-      const int32_t code = bins[k];
-      if (code) {
-        const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
-        const float pred = interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
-                                      hc ? Er[t + 2] : 0.0f,
-                                      hd ? Er[t + 3] : 0.0f, ha, hc, hd);
-        out[2 * k + 1] = dequantize_bin(pred, code, rj.B.twoeb);
-      } else {
-        out[2 * k + 1] = W[c.row + q];
-      }
-    }
-    float* wr = W + c.row;
-    if (p + kSpan <= n2) {
-      *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
-      *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
-    } else {
-      for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
-    }
-  }
-}
-
-/* The same for workgroup wg of a queued job (kRowThreads lanes, E its
- * LDS rows). */
+/* Decompression: the same phases; bin 0 keeps the exact value already
+ * scattered into W. */
 __device__ __forceinline__ void row_decomp_wg(
     const Geo& g, const RowJob& rj, float* W,
-    const uint16_t* __restrict__ codes, uint32_t wg, float* E) {
-  const uint32_t n2 = g.n[2], ne = (n2 + 1) / 2, es = ne + 3;
-  const uint32_t spans = (n2 + kSpan - 1) / kSpan;
-  const uint32_t rows = rj.rcnt[0] * rj.rcnt[1];
-  const uint32_t r0 = wg * rj.rows_per_wg;
-  const uint32_t items = rj.rows_per_wg * spans;
-  const RowItems ri(spans, items, rows, rj.rcnt[1]);
-  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
-    if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
-    const uint32_t p = u * kSpan;
-    float* Er = E + rl * es;
-    if (c.hasA) {
-      const uint64_t pos = stream_pos(rj.A, c.p0, c.p1, p);
-      const uint32_t nA = p < n2 ? (n2 - p + 1) / 2 : 0u;
-      int32_t bins[kSpan / 2];
-      load_bins4(codes, pos, rj.vecA, nA < 4 ? nA : 4u, bins);
-      float pred[kSpan / 2];
-      predict_span_A(g, rj, W, c, p, pred);
+    const uint16_t* __restrict__ codes, uint32_t blk, float* E) {
+  const L1Tile t = l1_tile(rj, blk);
+  const uint32_t n2 = g.n[2];
+  const bool hasA = rj.a >= 0;
+  const uint32_t sp12 = rj.S / kSpan + 2, sp3 = rj.S / kSpan;
+  {
+    const uint32_t rows = hasA ? (t.nr + 1) / 2 : rj.T;
+    const L1Items ii(sp12, rows);
+    for (uint32_t it = threadIdx.x; it < ii.n; it += kRowThreads) {
+      const uint32_t rl = ii.fs.div(it), u = it - rl * sp12;
+      const uint32_t l = hasA ? 2 * rl : rl;
+      const L1Row r = l1_row(g, rj, t, l);
+      if (!r.ok || t.P0 + kSpan * u < kSpan) continue;
+      const uint32_t p = t.P0 + kSpan * u - kSpan;
+      if (p >= n2) continue;
+      float* Er = E + l * t.es;
+      const bool isF = rj.f >= 0 && (((rj.f == 0 ? r.p0 : r.p1)) & 1u);
+      float v[kSpan / 2];
+      if (isF) {
+        const uint32_t pf = rj.f == 0 ? r.p0 : r.p1;
+        float pred[kSpan / 2];
+        predict_span(W, r.row, pf, g.st[rj.f], g.n[rj.f], rj.F.cubic, p, n2,
+                     pred);
+        const uint32_t nF = (n2 - p + 1) / 2;
+        int32_t bins[kSpan / 2];
+        load_bins4(codes, stream_pos(rj.F, r.p0, r.p1, p), rj.vecF,
+                   nF < 4 ? nF : 4u, bins);
+        /* bin 0 (and the points past the row): the exact value in W */
 #pragma unroll
-      for (uint32_t k = 0; k < kSpan / 2; ++k) {
-        if (k >= nA) break;
-        const int32_t code = bins[k];
-        Er[p / 2 + k + 1] = code ? dequantize_bin(pred[k], code, rj.A.twoeb)
-                                 : W[c.row + p + 2 * k];
+        for (uint32_t k = 0; k < kSpan / 2; ++k)
+          v[k] = bins[k] ? dequantize_bin(pred[k], bins[k], rj.F.twoeb)
+                 : p + 2 * k < n2 ? W[r.row + p + 2 * k]
+                                  : 0.0f;
+      } else {
+        float wv[kSpan];
+        load_span(W + r.row, p, n2, wv);
+#pragma unroll
+        for (uint32_t k = 0; k < kSpan / 2; ++k) v[k] = wv[2 * k];
       }
-    } else {
-      float wv[kSpan];
-      load_span(W + c.row, p, n2, wv);
-#pragma unroll
-      for (uint32_t k = 0; k < kSpan / 2; ++k)
-        if (p + 2 * k < n2) Er[p / 2 + k + 1] = wv[2 * k];
+      store_span_E(Er, u, v);
     }
   }
   __syncthreads();
-  for (uint32_t it = threadIdx.x; it < items; it += kRowThreads) {
-    const uint32_t rl = ri.fs.div(it), u = it - rl * spans;
-    if (r0 + rl >= rows) break;
-    const RowCtx c = row_ctx(g, rj, ri.fr, r0 + rl);
-    const uint32_t p = u * kSpan;
-    const float* Er = E + rl * es;
-    float out[kSpan];
-    const uint64_t pos = stream_pos(rj.B, c.p0, c.p1, p + 1);
-    const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
-    int32_t bins[kSpan / 2];
-    load_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
+  if (hasA) {
+    const uint32_t na = g.n[rj.a];
+    const L1Items ii(sp12, rj.T / 2);
+    for (uint32_t it = threadIdx.x; it < ii.n; it += kRowThreads) {
+      const uint32_t rl = ii.fs.div(it), u = it - rl * sp12;
+      const uint32_t l = t.lo + 1 + 2 * rl;
+      const L1Row r = l1_row(g, rj, t, l);
+      if (!r.ok || t.P0 + kSpan * u < kSpan) continue;
+      const uint32_t p = t.P0 + kSpan * u - kSpan;
+      if (p >= n2) continue;
+      float pred[kSpan / 2], v[kSpan / 2];
+      predict_span_E(E, t.es, l, u, r.pt, na, rj.A.cubic, pred);
+      const uint32_t nA = (n2 - p + 1) / 2;
+      int32_t bins[kSpan / 2];
+      load_bins4(codes, stream_pos(rj.A, r.p0, r.p1, p), rj.vecA,
+                 nA < 4 ? nA : 4u, bins);
 #pragma unroll
-    for (uint32_t k = 0; k < kSpan / 2; ++k) {
-      const uint32_t t = p / 2 + k, q = 2 * t + 1;
-      out[2 * k] = Er[t + 1];
-      out[2 * k + 1] = 0.0f;
-      if (q >= n2) continue;
-      const int32_t code = bins[k];
-      if (code) {
-        const bool ha = t >= 1, hc = q + 1 < n2, hd = q + 3 < n2;
-        const float pred = interp_mid(rj.B.cubic, ha ? Er[t] : 0.0f, Er[t + 1],
-                                      hc ? Er[t + 2] : 0.0f,
-                                      hd ? Er[t + 3] : 0.0f, ha, hc, hd);
-        out[2 * k + 1] = dequantize_bin(pred, code, rj.B.twoeb);
-      } else {
-        out[2 * k + 1] = W[c.row + q];
-      }
+      for (uint32_t k = 0; k < kSpan / 2; ++k)
+        v[k] = bins[k] ? dequantize_bin(pred[k], bins[k], rj.A.twoeb)
+               : p + 2 * k < n2 ? W[r.row + p + 2 * k]
+                                : 0.0f;
+      store_span_E(E + l * t.es, u, v);
     }
-    float* wr = W + c.row;
-    if (p + kSpan <= n2) {
-      *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
-      *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
-    } else {
-      for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+    __syncthreads();
+  }
+  {
+    const L1Items ii(sp3, rj.T);
+    for (uint32_t it = threadIdx.x; it < ii.n; it += kRowThreads) {
+      const uint32_t rl = ii.fs.div(it), u = it - rl * sp3;
+      const uint32_t l = t.lo + rl;
+      const L1Row r = l1_row(g, rj, t, l);
+      const uint32_t p = t.P0 + kSpan * u;
+      if (!r.ok || p >= n2) continue;
+      const float* Er = E + l * t.es;
+      float out[kSpan];
+      const uint64_t pos = stream_pos(rj.B, r.p0, r.p1, p + 1);
+      const uint32_t nB = p + 1 < n2 ? (n2 - p) / 2 : 0u;
+      int32_t bins[kSpan / 2];
+      load_bins4(codes, pos, rj.vecB, nB < 4 ? nB : 4u, bins);
+      float ev[7];
+      load_span_E(Er, u, ev);
+#pragma unroll
+      for (uint32_t k = 0; k < kSpan / 2; ++k) {
+        const uint32_t q = p + 2 * k + 1;
+        out[2 * k] = ev[k + 1];
+        out[2 * k + 1] = 0.0f;
+        if (q >= n2) continue;
+        const int32_t code = bins[k];
+        if (code) {
+          const bool ha = q >= 3, hc = q + 1 < n2, hd = q + 3 < n2;
+          const float pred =
+              interp_mid(rj.B.cubic, ha ? ev[k] : 0.0f, ev[k + 1],
+                         hc ? ev[k + 2] : 0.0f, hd ? ev[k + 3] : 0.0f, ha, hc,
+                         hd);
+          out[2 * k + 1] = dequantize_bin(pred, code, rj.B.twoeb);
+        } else {
+          out[2 * k + 1] = W[r.row + q];
+        }
+      }
+      float* wr = W + r.row;
+      if (p + kSpan <= n2) {
+        *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
+        *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
+      } else {
+        for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
+      }
     }
   }
 }
 
+__global__ __launch_bounds__(kRowThreads) void k_row_decomp(
+    Geo g, RowJob rj, float* W, const uint16_t* __restrict__ codes) {
+  extern __shared__ __align__(16) float E[];
+  row_decomp_wg(g, rj, W, codes, xcd_block(blockIdx.x, gridDim.x), E);
+}
 
+/* Tile sizes: S points of the contiguous dimension (at most 512), T rows
+ * (even, so that a tile's first row is even along a) for about 8 K points
+ * per tile; E: T + 5 rows (T without A) of S / 2 + 8 values. */
 static uint32_t row_blocks(const Geo& g, RowJob* rj, size_t* lds) {
-  const uint32_t rows = rj->rcnt[0] * rj->rcnt[1];
-  const uint32_t spans = (g.n[2] + kSpan - 1) / kSpan;
-  rj->rows_per_wg = spans >= kRowThreads ? 1u : kRowThreads / spans;
-  if (rj->rows_per_wg > rows) rj->rows_per_wg = rows;
-  *lds = 4 * (size_t)rj->rows_per_wg * ((g.n[2] + 1) / 2 + 3);
-  return (rows + rj->rows_per_wg - 1) / rj->rows_per_wg;
+  const uint32_t n2 = g.n[2];
+  const uint32_t S = n2 >= 512 ? 512u : (n2 + kSpan - 1) / kSpan * kSpan;
+  uint32_t T = (8192u / S) & ~1u;
+  T = T < 2 ? 2u : T > 64 ? 64u : T;
+  const uint32_t td = rj->a >= 0 ? (uint32_t)rj->a : 1u;
+  const uint32_t nt = rj->rcnt[td], no = rj->rcnt[1 - td];
+  if (T > nt + (nt & 1u)) T = nt + (nt & 1u); /* no more than the rows */
+  if (T < 2) T = 2;
+  rj->S = S;
+  rj->T = T;
+  rj->tiles2 = (n2 + S - 1) / S;
+  rj->tilesT = (nt + T - 1) / T;
+  const uint32_t nr = T + (rj->a >= 0 ? 5u : 0u);
+  *lds = 4 * (size_t)nr * (S / 2 + 8);
+  return rj->tiles2 * rj->tilesT * no;
 }
 
 void launch_row_comp(const Geo& g, const RowJob& rj_in, const float* x,
@@ -801,11 +905,11 @@ void launch_row_comp(const Geo& g, const RowJob& rj_in, const float* x,
   size_t lds;
   const uint32_t blocks = row_blocks(g, &rj, &lds);
   if (write_w)
-    QOZ_LAUNCH(k_row_comp<true>, dim3(blocks), dim3(kRowThreads), lds,
-                       s, g, rj, x, W, codes, status);
+    QOZ_LAUNCH(k_row_comp<true>, dim3(blocks), dim3(kRowThreads), lds, s, g,
+               rj, x, W, codes, status);
   else
-    QOZ_LAUNCH(k_row_comp<false>, dim3(blocks), dim3(kRowThreads),
-                       lds, s, g, rj, x, W, codes, status);
+    QOZ_LAUNCH(k_row_comp<false>, dim3(blocks), dim3(kRowThreads), lds, s, g,
+               rj, x, W, codes, status);
 }
 
 void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
@@ -814,8 +918,8 @@ void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
   RowJob rj = rj_in;
   size_t lds;
   const uint32_t blocks = row_blocks(g, &rj, &lds);
-  QOZ_LAUNCH(k_row_decomp, dim3(blocks), dim3(kRowThreads), lds, s, g,
-                     rj, W, codes);
+  QOZ_LAUNCH(k_row_decomp, dim3(blocks), dim3(kRowThreads), lds, s, g, rj, W,
+             codes);
 }
 
 /* One round of a batch's inverse sweeps: each job is one sweep (64 x 4
@@ -824,7 +928,7 @@ void launch_row_decomp(const Geo& g, const RowJob& rj_in, float* W,
 __global__ __launch_bounds__(kRowThreads) void k_sweep_round_q(
     const SweepJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
     uint32_t n_jobs) {
-  extern __shared__ float E[];
+  extern __shared__ __align__(16) float E[];
   const uint32_t gid = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t j = find_job(wg0, n_jobs, gid);
   const SweepJob& a = jobs[j];
@@ -846,7 +950,7 @@ __global__ __launch_bounds__(kRowThreads) void k_sweep_round_q(
 __global__ __launch_bounds__(kRowThreads) void k_sweep_round_comp_q(
     const CompJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
     uint32_t n_jobs) {
-  extern __shared__ float E[];
+  extern __shared__ __align__(16) float E[];
   const uint32_t gid = xcd_block(blockIdx.x, gridDim.x);
   const uint32_t j = find_job(wg0, n_jobs, gid);
   const CompJob& a = jobs[j];

@@ -170,8 +170,10 @@ qoz_status make_plan(const qoz_shape& sh, double e, const qoz_params& p_in,
   return QOZ_OK;
 }
 
-bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj) {
+bool level1_rows(const Plan& P, size_t* iz, size_t* ia, size_t* ib,
+                 RowJob* rj) {
   const size_t ns = P.sweeps.size(), d = (size_t)P.d;
+  *iz = *ia = *ib = SIZE_MAX;
   if (ns < d || P.g.n[2] > 2 * kRowMaxEven) return false;
   const size_t first = ns - d; /* the level-1 sweeps close the schedule */
   size_t jb = d;
@@ -183,9 +185,17 @@ bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj) {
   *ia = jb > 0 ? first + jb - 1 : SIZE_MAX;
   rj->B = P.sweeps[*ib];
   rj->a = -1;
+  rj->f = -1;
   if (jb > 0) {
     rj->A = P.sweeps[*ia];
     rj->a = (int32_t)rj->A.k;
+  }
+  /* order (f, a, 2): F's targets are the even points of rows odd along f
+   * and even along a */
+  if (jb == 2 && d == 3) {
+    *iz = first;
+    rj->F = P.sweeps[first];
+    rj->f = (int32_t)rj->F.k;
   }
   /* B's targets fill rows of its (p0, p1) sub-grid; A's are those rows
    * that are odd along a */
@@ -195,6 +205,7 @@ bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj) {
   }
   rj->vecA = jb > 0 && rj->A.code_off % 4 == 0 && rj->A.cnt[2] % 4 == 0;
   rj->vecB = rj->B.code_off % 4 == 0 && rj->B.cnt[2] % 4 == 0;
+  rj->vecF = rj->f >= 0 && rj->F.code_off % 4 == 0 && rj->F.cnt[2] % 4 == 0;
   return true;
 }
 

@@ -102,16 +102,18 @@ struct Sweep {
 };
 
 /* Level-1 fusion of sweep A (along dimension a, or none: a = -1) with the
- * following sweep B along the contiguous dimension, one row at a time over
- * the rows (p0, p1) = (i0 * rstep[0], i1 * rstep[1]). */
+ * following sweep B along the contiguous dimension, over the rows (p0, p1)
+ * = (i0 * rstep[0], i1 * rstep[1]); when the level's order is (f, a, 2),
+ * also of the first sweep F (f = -1: not fused). */
 constexpr uint32_t kRowMaxEven = 8192; /* rows of up to 16384 points */
 struct RowJob {
-  int32_t a;
+  int32_t a, f;
   uint32_t rstep[2], rcnt[2];
-  uint32_t rows_per_wg; /* set by the launcher */
+  /* set by the launcher: tiles of T rows (along a) by S points */
+  uint32_t T, S, tilesT, tiles2;
   /* the sweep's bins of a row start on a multiple of 4 (8-byte access) */
-  uint32_t vecA, vecB;
-  Sweep A, B;
+  uint32_t vecA, vecB, vecF;
+  Sweep A, B, F;
 };
 
 /* Complete plan of one compression / decompression. */
@@ -337,7 +339,10 @@ void fill_sweep_table(const Plan& p, SweepTable* t);
 /* Level-1 row fusion: indices of sweeps A (SIZE_MAX if none) and B and the
  * job; false when the level has no sweep along the contiguous dimension or
  * its rows are too long for the row kernels. */
-bool level1_rows(const Plan& P, size_t* ia, size_t* ib, RowJob* rj);
+/* The fused level-1 sweeps of a plan: indices of F (SIZE_MAX when not
+ * fused), A (SIZE_MAX when none) and B; false when there is no fusion. */
+bool level1_rows(const Plan& P, size_t* iz, size_t* ia, size_t* ib,
+                 RowJob* rj);
 
 /* ---- Huffman (host side, huffman_host.cpp) ---------------------------- */
 bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);

@@ -203,14 +203,14 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
    * sort), then the upload region of the first phase */
   size_t rounds = 0;
   for (CField& f : F) {
-    size_t fa = SIZE_MAX, fb = SIZE_MAX;
+    size_t fz = SIZE_MAX, fa = SIZE_MAX, fb = SIZE_MAX;
     RowJob rj;
-    const bool fuse = level1_rows(f.P, &fa, &fb, &rj);
+    const bool fuse = level1_rows(f.P, &fz, &fa, &fb, &rj);
     for (size_t i = 0; i < f.P.sweeps.size(); ++i) {
       CompJob j;
       std::memset(&j, 0, sizeof(j));
       j.g = f.P.g;
-      if (fuse && (i == fa || i == fb)) {
+      if (fuse && (i == fz || i == fa || i == fb)) {
         if (i != fb) continue;
         j.rows = 1;
         j.rj = rj;

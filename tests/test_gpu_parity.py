@@ -124,6 +124,34 @@ def test_stream_bitexact(codec, ref, name, make, rel, s, interp, order,
     roundtrip_check(codec, ref, x, e, rp)
 
 
+# Every level-1 dimension order: with the contiguous dimension last the
+# level-1 pass takes all three sweeps in one launch (tiles of rows along the
+# middle sweep's dimension with recomputed neighbour rows, 512-point spans);
+# the shapes give several tiles per row set, several spans per row and
+# ragged ends of both.
+L1_ORDERS = [(0, 1, 2), (1, 0, 2), (0, 2, 1), (1, 2, 0), (2, 0, 1),
+             (2, 1, 0)]
+
+
+@pytest.mark.parametrize("interp", ["cubic", "linear"])
+@pytest.mark.parametrize("order", L1_ORDERS)
+def test_level1_orders(codec, ref, order, interp):
+    x = fields.grf((21, 38, 1100), 30 + L1_ORDERS.index(order))
+    e = 1e-3 * (float(x.max()) - float(x.min()))
+    rp = ref.make_params(3, interp, [order] + [(0, 1, 2)] * 15, 1.5, 2.0,
+                         anchor_stride=8)
+    roundtrip_check(codec, ref, x, e, rp)
+
+
+@pytest.mark.parametrize("order", [(0, 1), (1, 0)])
+def test_level1_orders_2d(codec, ref, order):
+    x = fields.grf((67, 1300), 40)
+    e = 1e-4 * (float(x.max()) - float(x.min()))
+    rp = ref.make_params(2, "cubic", [order] + [(0, 1)] * 15, 1.25, 3.0,
+                         anchor_stride=16)
+    roundtrip_check(codec, ref, x, e, rp)
+
+
 def test_gpu_decodes_oracle_stream(codec, ref):
     x = fields.grf((50, 60, 30), 12)
     e = 1e-4 * (float(x.max()) - float(x.min()))
