@@ -320,14 +320,15 @@ __device__ __forceinline__ void lds_sweep(const Geo& g, const uint32_t* start,
 }
 
 /* Algorithm 1 for one level in LDS: candidate blockIdx.x on block
- * blockIdx.y; the per-block sum of |x - prediction| goes to l1_part and
- * the compact reconstruction to the candidate's slot in wt (its first
- * `total` floats), from which the chosen one is committed. */
+ * blockIdx.y; the per-block sum of |x - prediction| goes to l1_part and,
+ * when a finer level follows (keep), the compact reconstruction to the
+ * candidate's slot in wt (its first `total` floats), from which the chosen
+ * one is committed. */
 template <uint32_t NT>
 __global__ __launch_bounds__(NT) void k_alg1_lds(
     BlockGeo bg, uint32_t l, const float* __restrict__ xs,
     const float* __restrict__ wc, float* __restrict__ wt,
-    const TrialDesc* __restrict__ desc, double* l1_part) {
+    const TrialDesc* __restrict__ desc, double* l1_part, uint32_t keep) {
   extern __shared__ float Ws[];
   __shared__ double red[NT / 64];
   const Item item = xcd_item();
@@ -354,8 +355,10 @@ __global__ __launch_bounds__(NT) void k_alg1_lds(
                   });
     __syncthreads();
   }
-  float* Wo = wt + ((uint64_t)c * bg.nb + blk) * bg.size;
-  for (uint32_t t = threadIdx.x; t < total; t += NT) Wo[t] = Ws[t];
+  if (keep) {
+    float* Wo = wt + ((uint64_t)c * bg.nb + blk) * bg.size;
+    for (uint32_t t = threadIdx.x; t < total; t += NT) Wo[t] = Ws[t];
+  }
   const double tot = lds_block_sum_f64<NT>(l1, red);
   if (threadIdx.x == 0) l1_part[(uint64_t)c * bg.nb + blk] = tot;
 }
@@ -412,16 +415,16 @@ bool alg1_in_lds(const BlockGeo& bg, uint32_t l) {
 void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
                        const float* wc, float* wt, uint32_t ncand,
                        const TrialDesc* cand_desc, double* l1_part,
-                       bool in_lds, hipStream_t s) {
+                       bool in_lds, bool keep, hipStream_t s) {
   if (in_lds) {
     const size_t bytes = alg1_lds_bytes(bg, l);
     if (bytes <= kAlg1WideBytes)
-      QOZ_LAUNCH(k_alg1_lds<256>, dim3(ncand, bg.nb), dim3(256),
-                         bytes, s, bg, l, xs, wc, wt, cand_desc, l1_part);
+      QOZ_LAUNCH(k_alg1_lds<256>, dim3(ncand, bg.nb), dim3(256), bytes, s,
+                 bg, l, xs, wc, wt, cand_desc, l1_part, keep ? 1u : 0u);
     else
       QOZ_LAUNCH(k_alg1_lds<kLdsThreads>, dim3(ncand, bg.nb),
-                         dim3(kLdsThreads), bytes, s, bg, l, xs, wc, wt,
-                         cand_desc, l1_part);
+                 dim3(kLdsThreads), bytes, s, bg, l, xs, wc, wt, cand_desc,
+                 l1_part, keep ? 1u : 0u);
     return;
   }
   QOZ_LAUNCH(k_alg1_level, dim3(ncand, bg.nb), dim3(kTuneThreads), 0,
@@ -456,6 +459,30 @@ __global__ __launch_bounds__(kPickThreads) void k_alg1_pick(
   }
 }
 
+/* The trials' interpolation types and orders from Algorithm 1's choices:
+ * level l of every trial takes the chosen candidate's (a choice out of
+ * range, which the host rejects afterwards, reads candidate 0). */
+__global__ void k_trial_fill(TrialDesc* __restrict__ desc, uint32_t ntrial,
+                             uint32_t Lt, const TrialDesc* __restrict__ cand,
+                             uint32_t ncand,
+                             const uint32_t* __restrict__ pick) {
+  const uint32_t t = blockIdx.x, l = threadIdx.x;
+  if (t >= ntrial || l >= Lt) return;
+  const uint32_t ci = pick[l] < ncand ? pick[l] : 0u;
+  const TrialLevel& src = cand[(size_t)l * ncand + ci].lv[l];
+  TrialLevel& dst = desc[t].lv[l];
+  dst.cubic = src.cubic;
+  for (int j = 0; j < 3; ++j) dst.order[j] = src.order[j];
+}
+
+void launch_trial_fill(TrialDesc* desc, uint32_t ntrial, uint32_t Lt,
+                       const TrialDesc* cand, uint32_t ncand,
+                       const uint32_t* pick, hipStream_t s) {
+  if (!ntrial || !Lt) return;
+  QOZ_LAUNCH(k_trial_fill, dim3(ntrial), dim3(64), 0, s, desc, ntrial, Lt,
+             cand, ncand, pick);
+}
+
 /* commit the chosen candidate's working copy: wc = wt[pick] */
 __global__ void k_commit_copy(const float* __restrict__ wt,
                               const uint32_t* __restrict__ pick, uint64_t n,
@@ -469,11 +496,12 @@ __global__ void k_commit_copy(const float* __restrict__ wt,
 void launch_alg1_pick(const BlockGeo& bg, uint32_t l, const float* xs,
                       const TrialDesc* cand_desc, const double* l1_part,
                       uint32_t ncand, double count, uint32_t* pick,
-                      const float* wt, float* wc, bool in_lds,
+                      const float* wt, float* wc, bool in_lds, bool keep,
                       hipStream_t s) {
   const uint32_t nb = bg.nb;
   QOZ_LAUNCH(k_alg1_pick, dim3(1), dim3(kPickThreads), 0, s, l1_part,
                      ncand, nb, count, pick);
+  if (!keep && in_lds) return; /* no finer level reads the working copy */
   if (in_lds) {
     const uint32_t total = (uint32_t)(alg1_lds_bytes(bg, l) / 4);
     QOZ_LAUNCH(k_alg1_commit, dim3((total + 255) / 256, nb),

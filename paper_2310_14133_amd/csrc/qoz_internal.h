@@ -690,16 +690,25 @@ void launch_gather_blocks(const float* x, const Geo& g, const BlockGeo& bg,
 /* whether Algorithm 1's level-l working copies fit in LDS on the current
  * device (then no per-candidate copies in wt are made) */
 bool alg1_in_lds(const BlockGeo& bg, uint32_t l);
+/* the trials' per-level interpolation types and orders (desc[0..ntrial),
+ * levels 1..Lt) from Algorithm 1's choices pick[l - 1] among the level's
+ * candidates cand[(l - 1) * ncand ..] */
+void launch_trial_fill(TrialDesc* desc, uint32_t ntrial, uint32_t Lt,
+                       const TrialDesc* cand, uint32_t ncand,
+                       const uint32_t* pick, hipStream_t s);
+/* keep: a finer level follows and reads the chosen reconstruction (else
+ * the in-LDS path keeps none of them) */
 void launch_alg1_level(const BlockGeo& bg, uint32_t l, const float* xs,
                        const float* wc, float* wt, uint32_t ncand,
                        const TrialDesc* cand_desc, double* l1_part,
-                       bool in_lds, hipStream_t s);
-/* the level's choice (first strict minimum) to *pick and its
+                       bool in_lds, bool keep, hipStream_t s);
+/* the level's choice (first strict minimum) to *pick and, with keep, its
  * reconstruction committed to wc */
 void launch_alg1_pick(const BlockGeo& bg, uint32_t l, const float* xs,
                       const TrialDesc* cand_desc, const double* l1_part,
                       uint32_t ncand, double count, uint32_t* pick,
-                      const float* wt, float* wc, bool in_lds, hipStream_t s);
+                      const float* wt, float* wc, bool in_lds, bool keep,
+                      hipStream_t s);
 /* keep_wt: leave each trial's reconstruction of each block in wt */
 void launch_trial(const BlockGeo& bg, const float* xs, float* wt,
                   uint32_t ntrial, const TrialDesc* desc, uint32_t* hist,

@@ -331,22 +331,23 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
     launch_gather_blocks(d_x, g, bg, dorig, xs, wc, st, s);
     prof_end(c, s, ev, PK_TUNE_GATHER, 12.0 * bsz);
   }
+  /* the status word (and range) arrive with Algorithm 1's first read-back:
+   * the gather needs no wait of its own; they are taken right after that
+   * wait, before anything can move the staging buffer */
   QOZ_TRY(to_host(c, h_status, st, 16, s));
-  QOZ_HIP(hipGetLastError());
-  QOZ_HIP(hipStreamSynchronize(s));
-  if (h_status[0] & kStNonFinite) {
-    prof_collect(c);
-    return fail(QOZ_EINVAL, "input contains NaN or Inf");
-  }
+  bool nonfinite = false;
   double vrange = 0.0; /* unused by the ratio target */
-  if (need_range) {
-    float lo = h_range[0], hi = h_range[rp];
-    for (uint32_t i = 1; i < rp; ++i) {
-      lo = std::fmin(lo, h_range[i]);
-      hi = std::fmax(hi, h_range[rp + i]);
+  auto take_status = [&]() {
+    nonfinite = (h_status[0] & kStNonFinite) != 0;
+    if (need_range) {
+      float lo = h_range[0], hi = h_range[rp];
+      for (uint32_t i = 1; i < rp; ++i) {
+        lo = std::fmin(lo, h_range[i]);
+        hi = std::fmax(hi, h_range[rp + i]);
+      }
+      vrange = (double)hi - (double)lo;
     }
-    vrange = (double)hi - (double)lo;
-  }
+  };
 
   /* ---- Algorithm 1 ---- */
   uint8_t Is_interp[QOZ_MAX_LEVELS] = {0};
@@ -357,6 +358,94 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
   float utw[QOZ_MAX_LEVELS], uiv[QOZ_MAX_LEVELS];
   level_bounds(e, 1.0, 1.0, Lt, ueb, utw, uiv);
   const double npts = (double)bg.size * bg.nb;
+
+  /* the (alpha, beta) trials' level bounds, deduplicated by level-bound
+   * vector (they do not depend on Algorithm 1's choices) */
+  const int nf = target == QOZ_TARGET_CR ? 1 : 3;
+  const double factors[3] = {1.0, 0.8, 1.2};
+  struct Vec {
+    double eb[QOZ_MAX_LEVELS];
+    float tw[QOZ_MAX_LEVELS], iv[QOZ_MAX_LEVELS];
+  };
+  std::vector<Vec> vecs;
+  int trial_of[3][20];
+  if (!(abl & QOZ_ABLATE_AB)) {
+    for (int f = 0; f < nf; ++f)
+      for (int i = 0; i < 20; ++i) {
+        Vec v;
+        std::memset(&v, 0, sizeof(v));
+        const double ef = f == 0 ? e : e * factors[f];
+        level_bounds(ef, kAlpha[i / 4], kBeta[i % 4], Lt, v.eb, v.tw, v.iv);
+        int found = -1;
+        for (size_t k = 0; k < vecs.size(); ++k)
+          if (std::memcmp(&vecs[k], &v, sizeof(Vec)) == 0) {
+            found = (int)k;
+            break;
+          }
+        if (found < 0) {
+          found = (int)vecs.size();
+          vecs.push_back(v);
+        }
+        trial_of[f][i] = found;
+      }
+  }
+  const uint32_t ntrial = (uint32_t)vecs.size();
+  /* the trials' descriptors: bounds here, interpolation types and orders
+   * (Algorithm 1's choices) filled in on the device when both searches
+   * run and the target needs no value range before the trials (then the
+   * host waits once for Algorithm 1 and the trials together) */
+  const bool dev_desc = !(abl & QOZ_ABLATE_LEVELWISE) &&
+                        !(abl & QOZ_ABLATE_AB) && target != QOZ_TARGET_SSIM;
+  auto fill_desc = [&]() {
+    std::memset(h_desc, 0, sizeof(TrialDesc) * ntrial);
+    for (uint32_t t = 0; t < ntrial; ++t)
+      for (uint32_t l = 1; l <= Lt; ++l) {
+        TrialLevel& lv = h_desc[t].lv[l - 1];
+        lv.twoeb = vecs[t].tw[l - 1];
+        lv.inv = vecs[t].iv[l - 1];
+        lv.eb = vecs[t].eb[l - 1];
+        lv.cubic = Is_interp[l - 1];
+        for (int j = 0; j < 3; ++j)
+          lv.order[j] = j < d ? Is_order[l - 1][j] + shift : 0;
+      }
+  };
+  if (dev_desc) {
+    fill_desc(); /* the choices are overwritten on the device */
+    QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ntrial, s));
+  }
+  /* Algorithm 1's choices (read back to h_pick) into Is_interp/Is_order */
+  uint32_t* const h_pick0 = h_status + 8 + 3 * (size_t)bg.nb;
+  auto apply_picks = [&](const uint32_t* h_pick) -> qoz_status {
+    for (uint32_t l = Lt; l >= 1; --l) {
+      const uint32_t ib = h_pick[l - 1];
+      if (ib >= ncand) return fail(QOZ_EDEVICE, "bad tuner choice");
+      if (tr) {
+        /* each candidate's mean as the device forms it: block sums in
+         * block order over the level's target count */
+        uint64_t on_fine = 1, on_coarse = 1;
+        for (int i = 0; i < 3; ++i) {
+          on_fine *= (bg.g.n[i] - 1) / (1u << (l - 1)) + 1;
+          on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
+        }
+        const double count = (double)(on_fine - on_coarse) * bg.nb;
+        const double* lp = h_tl1 + (size_t)(l - 1) * ncand * bg.nb;
+        for (uint32_t ci = 0; ci < ncand; ++ci) {
+          double sum = 0.0;
+          for (uint32_t k = 0; k < bg.nb; ++k) sum += lp[(size_t)ci * bg.nb + k];
+          tr->alg1_err[l - 1][ci] = count > 0 ? sum / count : 0.0;
+        }
+        tr->alg1_choice[l - 1] = ib;
+      }
+      Is_interp[l - 1] = cands[ib].interp;
+      std::memcpy(Is_order[l - 1], cands[ib].order, 3);
+    }
+    for (uint32_t l = Lt + 1; l <= L; ++l) {
+      Is_interp[l - 1] = Is_interp[Lt - 1];
+      std::memcpy(Is_order[l - 1], Is_order[Lt - 1], 3);
+    }
+    return QOZ_OK;
+  };
+
   if (abl & QOZ_ABLATE_LEVELWISE) {
     /* one interpolator for every level: each candidate trial-compresses
      * the sampled blocks at the uniform bound; the lowest bit rate wins,
@@ -387,6 +476,7 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
     QOZ_TRY(to_host(c, h_sse, dsse, 24 * (size_t)nslots * bg.nb, s));
     QOZ_HIP(hipGetLastError());
     QOZ_HIP(hipStreamSynchronize(s));
+    take_status();
     std::vector<uint64_t> cbits(ncand, 0), cU(ncand, 0);
     std::vector<uint32_t> cover;
     for (uint32_t ci = 0; ci < ncand; ++ci) {
@@ -440,7 +530,7 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
       {
         hipEvent_t ev = prof_begin(c, s, PK_TUNE_ALG1);
         launch_alg1_level(bg, l, xs, wc, wt, ncand, dadesc + (l - 1) * ncand,
-                          dl1, in_lds, s);
+                          dl1, in_lds, l > 1, s);
         prof_end(c, s, ev, PK_TUNE_ALG1, 16.0 * bsz * ncand);
       }
       if (tr)
@@ -454,84 +544,33 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
       }
       const double count = (double)(on_fine - on_coarse) * bg.nb;
       launch_alg1_pick(bg, l, xs, dadesc + (l - 1) * ncand, dl1, ncand, count,
-                       dpick + (l - 1), wt, wc, in_lds, s);
+                       dpick + (l - 1), wt, wc, in_lds, l > 1, s);
     }
-    uint32_t* h_pick = h_status + 8 + 3 * (size_t)bg.nb; /* after origins */
-    QOZ_TRY(to_host(c, h_pick, dpick, 4 * Lt, s));
-    QOZ_HIP(hipGetLastError());
-    QOZ_HIP(hipStreamSynchronize(s));
-    for (uint32_t l = Lt; l >= 1; --l) {
-      const uint32_t ib = h_pick[l - 1];
-      if (ib >= ncand) return fail(QOZ_EDEVICE, "bad tuner choice");
-      if (tr) {
-        /* each candidate's mean as the device forms it: block sums in
-         * block order over the level's target count */
-        uint64_t on_fine = 1, on_coarse = 1;
-        for (int i = 0; i < 3; ++i) {
-          on_fine *= (bg.g.n[i] - 1) / (1u << (l - 1)) + 1;
-          on_coarse *= (bg.g.n[i] - 1) / (1u << l) + 1;
-        }
-        const double count = (double)(on_fine - on_coarse) * bg.nb;
-        const double* lp = h_tl1 + (size_t)(l - 1) * ncand * bg.nb;
-        for (uint32_t ci = 0; ci < ncand; ++ci) {
-          double sum = 0.0;
-          for (uint32_t k = 0; k < bg.nb; ++k) sum += lp[(size_t)ci * bg.nb + k];
-          tr->alg1_err[l - 1][ci] = count > 0 ? sum / count : 0.0;
-        }
-        tr->alg1_choice[l - 1] = ib;
-      }
-      Is_interp[l - 1] = cands[ib].interp;
-      std::memcpy(Is_order[l - 1], cands[ib].order, 3);
+    /* the choices follow the origins in the staging buffer */
+    QOZ_TRY(to_host(c, h_pick0, dpick, 4 * Lt, s));
+    if (dev_desc) {
+      launch_trial_fill(ddesc, ntrial, Lt, dadesc, ncand, dpick, s);
+    } else {
+      QOZ_HIP(hipGetLastError());
+      QOZ_HIP(hipStreamSynchronize(s));
+      take_status();
+      QOZ_TRY(apply_picks(h_pick0));
     }
-    for (uint32_t l = Lt + 1; l <= L; ++l) {
-      Is_interp[l - 1] = Is_interp[Lt - 1];
-      std::memcpy(Is_order[l - 1], Is_order[Lt - 1], 3);
-    }
+  }
+
+  if (!dev_desc && nonfinite) {
+    prof_collect(c);
+    return fail(QOZ_EINVAL, "input contains NaN or Inf");
   }
 
   /* (alpha, beta); without the search the first pair, alpha = 1 */
   int inc = 0;
   if (!(abl & QOZ_ABLATE_AB)) {
-    /* ---- (alpha, beta) trials, deduplicated by level-bound vector ---- */
-    const int nf = target == QOZ_TARGET_CR ? 1 : 3;
-    const double factors[3] = {1.0, 0.8, 1.2};
-    struct Vec {
-      double eb[QOZ_MAX_LEVELS];
-      float tw[QOZ_MAX_LEVELS], iv[QOZ_MAX_LEVELS];
-    };
-    std::vector<Vec> vecs;
-    int trial_of[3][20];
-    for (int f = 0; f < nf; ++f)
-      for (int i = 0; i < 20; ++i) {
-        Vec v;
-        std::memset(&v, 0, sizeof(v));
-        const double ef = f == 0 ? e : e * factors[f];
-        level_bounds(ef, kAlpha[i / 4], kBeta[i % 4], Lt, v.eb, v.tw, v.iv);
-        int found = -1;
-        for (size_t k = 0; k < vecs.size(); ++k)
-          if (std::memcmp(&vecs[k], &v, sizeof(Vec)) == 0) {
-            found = (int)k;
-            break;
-          }
-        if (found < 0) {
-          found = (int)vecs.size();
-          vecs.push_back(v);
-        }
-        trial_of[f][i] = found;
-      }
-    const uint32_t ntrial = (uint32_t)vecs.size();
-    std::memset(h_desc, 0, sizeof(TrialDesc) * ntrial);
-    for (uint32_t t = 0; t < ntrial; ++t)
-      for (uint32_t l = 1; l <= Lt; ++l) {
-        TrialLevel& lv = h_desc[t].lv[l - 1];
-        lv.twoeb = vecs[t].tw[l - 1];
-        lv.inv = vecs[t].iv[l - 1];
-        lv.eb = vecs[t].eb[l - 1];
-        lv.cubic = Is_interp[l - 1];
-        for (int j = 0; j < 3; ++j)
-          lv.order[j] = j < d ? Is_order[l - 1][j] + shift : 0;
-      }
-    QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ntrial, s));
+    /* ---- (alpha, beta) trials ---- */
+    if (!dev_desc) {
+      fill_desc();
+      QOZ_TRY(to_device(c, ddesc, h_desc, sizeof(TrialDesc) * ntrial, s));
+    }
     launch_zero_u32(dhist, (uint64_t)kNSym * ntrial, s);
     {
       hipEvent_t ev = prof_begin(c, s, PK_TUNE_TRIAL);
@@ -569,6 +608,11 @@ static qoz_status tune_impl(qoz_ctx* c, const float* d_x, qoz_shape shape,
     QOZ_HIP(hipGetLastError());
     QOZ_HIP(hipStreamSynchronize(s));
     prof_collect(c);
+    if (dev_desc) {
+      take_status();
+      if (nonfinite) return fail(QOZ_EINVAL, "input contains NaN or Inf");
+      QOZ_TRY(apply_picks(h_pick0));
+    }
 
     const uint64_t per_item = sj.batch ? ssim_np / sj.batch : 0;
     const double nwin = (double)(sj.P - sj.wp + 1) *
