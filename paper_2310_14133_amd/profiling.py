@@ -34,8 +34,8 @@ KIND_KERNELS = {
     "histogram": ("k_hist", "csrc/kernels_huff.hip"),
     "row_comp_level1": ("k_row_comp", "csrc/kernels_sweep.hip"),
     "row_decomp_level1": ("k_row_decomp", "csrc/kernels_sweep.hip"),
-    "sweep_comp_level1": ("k_sweep_comp", "csrc/kernels_sweep.hip"),
-    "sweep_decomp_level1": ("k_sweep_decomp", "csrc/kernels_sweep.hip"),
+    "sweep_comp": ("k_sweep_comp", "csrc/kernels_sweep.hip"),
+    "sweep_decomp": ("k_sweep_decomp", "csrc/kernels_sweep.hip"),
     "check_range": ("k_range", "csrc/kernels_metrics.hip"),
     "tune_alg1": ("k_alg1_level", "csrc/kernels_tune.hip"),
     "tune_trial": ("k_trial", "csrc/kernels_tune.hip"),
