@@ -410,7 +410,11 @@ __device__ __forceinline__ void decode_wg(
     }
     zor = 0;
     if (nval == 8) {
-      *reinterpret_cast<uint4*>(codes + base + nat) = q;
+      /* streamed past the caches, which keep the payload's lines */
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      u32x4 w;
+      w.x = q.x; w.y = q.y; w.z = q.z; w.w = q.w;
+      __builtin_nontemporal_store(w, reinterpret_cast<u32x4*>(codes + base + nat));
     } else {
       for (uint32_t i = 0; i < nval; ++i)
         codes[base + nat + i] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));

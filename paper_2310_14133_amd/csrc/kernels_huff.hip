@@ -811,7 +811,7 @@ __global__ __launch_bounds__(kEncThreads, 4) void k_huff_encode(
         const uint32_t v = words[i];
         nz += v != 0u ? 1u : 0u;
         if (w0 + i < F.cap_words)
-          gptr(F.payload)[w0 + i] = v;
+          __builtin_nontemporal_store(v, &gptr(F.payload)[w0 + i]);
         else
           over = true;
       }

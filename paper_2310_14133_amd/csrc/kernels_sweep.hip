@@ -471,9 +471,13 @@ __device__ __forceinline__ void store_bins4(uint16_t* __restrict__ c,
                                             uint64_t pos, bool vec,
                                             uint32_t n, const int32_t* b) {
   if (vec && n == 4) {
-    *reinterpret_cast<uint2*>(c + pos) =
-        make_uint2((uint32_t)b[0] | ((uint32_t)b[1] << 16),
-                   (uint32_t)b[2] | ((uint32_t)b[3] << 16));
+    /* streamed past the caches: the bins are read again only by the next
+     * kernel, and the lines they would take are the rows' */
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 w;
+    w.x = (uint32_t)b[0] | ((uint32_t)b[1] << 16);
+    w.y = (uint32_t)b[2] | ((uint32_t)b[3] << 16);
+    __builtin_nontemporal_store(w, reinterpret_cast<u32x2*>(c + pos));
   } else {
 #pragma unroll
     for (uint32_t k = 0; k < 4; ++k)
@@ -861,8 +865,13 @@ __device__ __forceinline__ void row_decomp_wg(
       }
       float* wr = W + r.row;
       if (p + kSpan <= n2) {
-        *reinterpret_cast<F4*>(wr + p) = F4{out[0], out[1], out[2], out[3]};
-        *reinterpret_cast<F4*>(wr + p + 4) = F4{out[4], out[5], out[6], out[7]};
+        /* the output field, streamed past the caches */
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        f32x4 o0, o1;
+        o0.x = out[0]; o0.y = out[1]; o0.z = out[2]; o0.w = out[3];
+        o1.x = out[4]; o1.y = out[5]; o1.z = out[6]; o1.w = out[7];
+        __builtin_nontemporal_store(o0, reinterpret_cast<f32x4*>(wr + p));
+        __builtin_nontemporal_store(o1, reinterpret_cast<f32x4*>(wr + p + 4));
       } else {
         for (uint32_t k = 0; k < kSpan && p + k < n2; ++k) wr[p + k] = out[k];
       }
