@@ -335,7 +335,9 @@ qoz_status qoz_decompress_queue(qoz_ctx* ctx, qoz_batch_dec_item* items,
  * codes the chunks of every field.  Three waits per call (four when a
  * field uses more than 4096 distinct bins), plus the few launches of each
  * field whose zero-word packing pays.  Items without params are
- * tuned first with the online tuner (target, cfg), one at a time.  Every
+ * tuned first with the online tuner (target, cfg) on up to 8 worker
+ * contexts of ctx, each with its own stream (the call first waits for
+ * `stream`, whose work may produce the inputs).  Every
  * stream equals qoz_compress's byte for byte; sweeps use the default
  * launch tiles.  A field whose output cannot hold the sections before its
  * payload is compressed by qoz_compress after the queue (and reports the

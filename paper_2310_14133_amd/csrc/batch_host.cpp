@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <functional>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -21,7 +22,7 @@ namespace qoz {
 constexpr uint32_t kMaxWorkers = 64;
 constexpr uint32_t kDefaultWorkers = 4;
 
-static qoz_status ensure_workers(qoz_ctx* c, uint32_t n) {
+qoz_status ensure_workers(qoz_ctx* c, uint32_t n) {
   while (c->workers.size() < n) {
     qoz_ctx* w = nullptr;
     QOZ_TRY(qoz_ctx_create(c->device, &w));
@@ -41,7 +42,7 @@ static qoz_status ensure_workers(qoz_ctx* c, uint32_t n) {
  * threads (the caller's thread is worker 0). */
 template <class Fn>
 static void run_queue(const std::vector<uint32_t>& order, uint32_t workers,
-                      Fn fn) {
+                      const Fn& fn) {
   std::atomic<uint32_t> next{0};
   auto body = [&](uint32_t w) {
     for (;;) {
@@ -54,6 +55,11 @@ static void run_queue(const std::vector<uint32_t>& order, uint32_t workers,
   for (uint32_t w = 1; w < workers; ++w) th.emplace_back(body, w);
   body(0);
   for (auto& t : th) t.join();
+}
+
+void run_on_workers(const std::vector<uint32_t>& order, uint32_t workers,
+                    const std::function<void(uint32_t, uint32_t)>& fn) {
+  run_queue(order, workers, fn);
 }
 
 static double ms_since(std::chrono::steady_clock::time_point t) {

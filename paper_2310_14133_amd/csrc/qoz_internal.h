@@ -14,6 +14,7 @@
 
 #include <map>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/qoz.h"
@@ -343,6 +344,13 @@ void fill_sweep_table(const Plan& p, SweepTable* t);
  * fused), A (SIZE_MAX when none) and B; false when there is no fusion. */
 bool level1_rows(const Plan& P, size_t* iz, size_t* ia, size_t* ib,
                  RowJob* rj);
+
+/* ---- batch workers (batch_host.cpp) ---------------------------------- */
+/* at least n worker contexts (each with its own stream) on c's device */
+qoz_status ensure_workers(qoz_ctx* c, uint32_t n);
+/* fn(worker, item) over items in the given order on `workers` threads */
+void run_on_workers(const std::vector<uint32_t>& order, uint32_t workers,
+                    const std::function<void(uint32_t, uint32_t)>& fn);
 
 /* ---- Huffman (host side, huffman_host.cpp) ---------------------------- */
 bool huffman_lengths(const uint32_t* hist, uint32_t nsym, uint8_t* len);

@@ -3,8 +3,9 @@
  * many fields at once, in a number of launches that does not grow with the
  * batch:
  *
- *   1. (fields given without parameters are tuned first, one at a time,
- *      by the online tuner of Sec. VI;)
+ *   1. (fields given without parameters are tuned first by the online
+ *      tuner of Sec. VI, on up to 8 worker contexts with their own streams,
+ *      largest field first;)
  *   2. one upload of the queues, then one launch for every field's
  *      anchors, one launch per round of sweeps (the r-th sweep, or fused
  *      level-1 row pair, of every field), one launch for every field's
@@ -18,8 +19,8 @@
  *      the payload and its encoder totals, one that copies codebooks and
  *      anchors into place, one counting the code bits and symbol-0 bins of
  *      every chunk of every field, one scan over all those chunks (two
- *      launches) and one encoding launch over them (a grid stride over
- *      the chunks, field after field); one read-back of the totals (the
+ *      launches) and one encoding launch over them (runs of chunks in a
+ *      grid stride, field after field); one read-back of the totals (the
  *      second wait);
  *   5. headers: one upload and one copy launch; a field whose zero-word
  *      packing pays is packed with its own few launches (the third wait).
@@ -39,6 +40,9 @@
 #include "qoz_internal.h"
 
 namespace qoz {
+
+/* worker contexts for the tunings of a batch's fields */
+constexpr size_t kTuneWorkers = 8;
 namespace {
 
 constexpr size_t kAl = 256;
@@ -163,24 +167,51 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
   }
   if (!n) return QOZ_OK;
 
-  /* 1. parameters and plans */
+  /* 1. parameters and plans: the fields without parameters are tuned on
+   * worker contexts, each on its own stream (largest first), after the
+   * caller's stream has produced the inputs */
   std::vector<CField> F;
   F.reserve(n);
   std::vector<qoz_params> pv(n); /* given or tuned */
+  std::vector<uint32_t> to_tune;
+  std::vector<uint64_t> tsize;
   for (uint32_t i = 0; i < n; ++i) {
     qoz_batch_item& it = items[i];
     if (!it.d_x || ((uintptr_t)it.d_out & 7) != 0) {
       it.status = QOZ_EINVAL;
       continue;
     }
-    qoz_params& p = pv[i];
     if (it.params) {
-      p = *it.params;
+      pv[i] = *it.params;
     } else {
-      std::memset(&p, 0, sizeof(p));
-      it.status = qoz_tune(c, it.d_x, it.shape, it.abs_eb, target, cfg, &p, s);
-      if (it.status != QOZ_OK) continue;
+      std::memset(&pv[i], 0, sizeof(pv[i]));
+      to_tune.push_back(i);
     }
+  }
+  if (!to_tune.empty()) {
+    const uint32_t nw = (uint32_t)std::min<size_t>(kTuneWorkers, to_tune.size());
+    QOZ_HIP(hipStreamSynchronize(s));
+    QOZ_TRY(ensure_workers(c, nw));
+    std::vector<uint64_t> pts(to_tune.size(), 1);
+    for (size_t k = 0; k < to_tune.size(); ++k)
+      for (uint32_t m = 0; m < items[to_tune[k]].shape.ndim && m < 3; ++m)
+        pts[k] *= items[to_tune[k]].shape.dims[m];
+    std::vector<uint32_t> order(to_tune.size());
+    for (uint32_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return pts[a] > pts[b]; });
+    run_on_workers(order, nw, [&](uint32_t w, uint32_t k) {
+      qoz_batch_item& it = items[to_tune[k]];
+      it.status = qoz_tune(c->workers[w], it.d_x, it.shape, it.abs_eb, target,
+                           cfg, &pv[to_tune[k]], c->worker_streams[w]);
+    });
+    for (uint32_t w = 0; w < nw; ++w)
+      QOZ_HIP(hipStreamSynchronize(c->worker_streams[w]));
+  }
+  for (uint32_t i = 0; i < n; ++i) {
+    qoz_batch_item& it = items[i];
+    if (it.status != QOZ_OK) continue;
+    const qoz_params& p = pv[i];
     CField f;
     f.item = i;
     it.status = make_plan(it.shape, it.abs_eb, p, &f.P);
