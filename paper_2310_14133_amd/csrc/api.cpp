@@ -443,8 +443,12 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   QOZ_TRY(set_device(c));
   QOZ_TRY(ensure_pinned(c, kPinBase));
   if (in_bytes < kHeaderBytes) return fail(QOZ_EFORMAT, "stream too short");
+  /* the header and the bytes after it in one read: the codebook usually
+   * lies within them (else a second read fetches it) */
+  constexpr size_t kSpecBytes = 64u << 10;
+  const size_t spec = in_bytes < kSpecBytes ? in_bytes : kSpecBytes;
   uint8_t* hs = pin(c, kPinStage);
-  QOZ_TRY(to_host(c, hs, d_in, kHeaderBytes, s));
+  QOZ_TRY(to_host(c, hs, d_in, spec, s));
   QOZ_TRY(sync_checked(s));
   Plan P;
   uint64_t nu, nused, nw;
@@ -456,9 +460,13 @@ qoz_status qoz_decompress(qoz_ctx* c, const void* d_in, size_t in_bytes,
   const uint64_t nch = P.n_chunks;
   const Layout lay = layout_of(P.n_anchor, nused, nch, nu, nw, npk);
   const uint8_t* in = (const uint8_t*)d_in;
-  uint8_t* cb = pin(c, kPinStage + 256);
-  QOZ_TRY(to_host(c, cb, in + lay.syms, lay.coff - lay.syms, s));
-  QOZ_TRY(sync_checked(s));
+  const uint8_t* cb = hs + lay.syms;
+  if (lay.coff > spec) {
+    uint8_t* cbr = pin(c, kPinStage + 256);
+    QOZ_TRY(to_host(c, cbr, in + lay.syms, lay.coff - lay.syms, s));
+    QOZ_TRY(sync_checked(s));
+    cb = cbr;
+  }
   DecTables* dt = (DecTables*)pin(c, kPinTable);
   std::vector<uint32_t> sorted;
   if (!build_dec_tables((const uint16_t*)cb, cb + (lay.lens - lay.syms),
