@@ -380,6 +380,46 @@ __global__ void k_alg1_commit(BlockGeo bg, uint32_t l,
     dst[map(t)] = src[t];
 }
 
+/* Algorithm 1's choice and the commit of its reconstruction in one launch:
+ * every workgroup forms the candidates' means itself (the same sums in the
+ * same order as k_alg1_pick, a lane per candidate: at most 64) and takes
+ * the first strict minimum; workgroup (0, 0) records it. */
+__global__ __launch_bounds__(256) void k_alg1_pick_commit(
+    BlockGeo bg, uint32_t l, const double* __restrict__ l1_part,
+    uint32_t ncand, double count, uint32_t* pick,
+    const float* __restrict__ wt, float* __restrict__ wc) {
+  __shared__ uint32_t s_pick;
+  if (threadIdx.x < 64) {
+    const uint32_t ci = threadIdx.x;
+    double cur = INFINITY;
+    if (ci < ncand) {
+      double sum = 0.0;
+      for (uint32_t k = 0; k < bg.nb; ++k) sum += l1_part[(size_t)ci * bg.nb + k];
+      cur = count > 0 ? sum / count : 0.0;
+    }
+    /* the first candidate whose mean is below every earlier one's and not
+     * above any later one's: the smallest index among the minima (none
+     * when every mean is NaN or infinite: candidate 0) */
+    double m = cur;
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    const uint64_t at = __ballot(ci < ncand && cur == m && cur < INFINITY);
+    if (ci == 0) s_pick = at ? (uint32_t)__ffsll((unsigned long long)at) - 1 : 0u;
+  }
+  __syncthreads();
+  const uint32_t ib = s_pick;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *pick = ib;
+  const uint32_t blk = blockIdx.y, h = 1u << (l - 1);
+  const Geo& g = bg.g;
+  const Geo cg = compact_geo(g, h);
+  const uint32_t total = cg.n[0] * cg.n[1] * cg.n[2];
+  const float* src = wt + ((uint64_t)ib * bg.nb + blk) * bg.size;
+  float* dst = wc + (uint64_t)blk * bg.size;
+  const CompactMap map(g, cg, h, total);
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += gridDim.x * blockDim.x)
+    dst[map(t)] = src[t];
+}
+
 /* Dynamic LDS for `bytes` of working copy next to `static_bytes`, or false
  * when the device cannot give a workgroup that much. */
 static bool lds_fits(const void* fn, size_t bytes, size_t static_bytes) {
@@ -499,6 +539,12 @@ void launch_alg1_pick(const BlockGeo& bg, uint32_t l, const float* xs,
                       const float* wt, float* wc, bool in_lds, bool keep,
                       hipStream_t s) {
   const uint32_t nb = bg.nb;
+  if (in_lds && keep && ncand <= 64) {
+    const uint32_t total = (uint32_t)(alg1_lds_bytes(bg, l) / 4);
+    QOZ_LAUNCH(k_alg1_pick_commit, dim3((total + 255) / 256, nb), dim3(256),
+               0, s, bg, l, l1_part, ncand, count, pick, wt, wc);
+    return;
+  }
   QOZ_LAUNCH(k_alg1_pick, dim3(1), dim3(kPickThreads), 0, s, l1_part,
                      ncand, nb, count, pick);
   if (!keep && in_lds) return; /* no finer level reads the working copy */
