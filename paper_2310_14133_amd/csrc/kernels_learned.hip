@@ -74,17 +74,18 @@ __device__ void block_sum(double (&v)[N], double (*red)[kFeatThreads / 64]) {
 
 /* feat[b][0..30] of block b (blockIdx.y picks the part); aux[b] = (min,
  * max, non-finite flag) for the pooling kernel, which fills feat[b][31] */
-__global__ __launch_bounds__(kFeatThreads) void k_block_features(
-    const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
-    double e, float* __restrict__ feat, float* __restrict__ aux) {
+__device__ __forceinline__ void block_features_body(
+    const float* __restrict__ x, const Geo& g,
+    const uint32_t* __restrict__ origins, double e, float* __restrict__ feat,
+    float* __restrict__ aux, uint32_t bx, uint32_t part_y) {
   extern __shared__ float blk[];
   __shared__ double red[4][kFeatThreads / 64];
   __shared__ float mred[3][kFeatThreads / 64];
   __shared__ double stat[20];
   __shared__ uint32_t rhist[10][256];
   __shared__ uint32_t rpre[10], rrank[10], dpre[10], dmap[10], ndist;
-  const uint32_t tid = threadIdx.x, part = blockIdx.y;
-  const uint32_t* o = origins + 3 * blockIdx.x;
+  const uint32_t tid = threadIdx.x, part = part_y;
+  const uint32_t* o = origins + 3 * bx;
   const uint64_t base = (uint64_t)o[0] * g.st[0] + (uint64_t)o[1] * g.st[1] +
                         (uint64_t)o[2] * g.st[2];
   /* the block, 12 loads in flight per lane */
@@ -182,11 +183,11 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
           b2 = fmaxf(b2, mred[2][w]);
         }
         f = log2(1.0 + ((double)h2 - (double)l2) / e);
-        aux[3 * (uint64_t)blockIdx.x + 0] = l2;
-        aux[3 * (uint64_t)blockIdx.x + 1] = h2;
-        aux[3 * (uint64_t)blockIdx.x + 2] = b2;
+        aux[3 * (uint64_t)bx + 0] = l2;
+        aux[3 * (uint64_t)bx + 1] = h2;
+        aux[3 * (uint64_t)bx + 2] = b2;
       }
-      feat[32 * (uint64_t)blockIdx.x + tid] = (float)f;
+      feat[32 * (uint64_t)bx + tid] = (float)f;
     }
     return;
   }
@@ -285,8 +286,14 @@ __global__ __launch_bounds__(kFeatThreads) void k_block_features(
     __syncthreads();
   }
   if (tid >= 20 && tid < 30)
-    feat[32 * (uint64_t)blockIdx.x + tid] = (float)log2(
+    feat[32 * (uint64_t)bx + tid] = (float)log2(
         1.0 + sqrt((double)__uint_as_float(rpre[tid - 20])) / e);
+}
+
+__global__ __launch_bounds__(kFeatThreads) void k_block_features(
+    const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
+    double e, float* __restrict__ feat, float* __restrict__ aux) {
+  block_features_body(x, g, origins, e, feat, aux, blockIdx.x, blockIdx.y);
 }
 
 /* The same features of one 33 x 33 block of a 2D field (row stride
@@ -300,17 +307,18 @@ constexpr uint32_t kB2Pts = kB1 * kB1; /* 1089 */
 constexpr uint32_t kNG2 = 32 * 32;     /* gradient points */
 }  // namespace
 
-__global__ __launch_bounds__(kF2Threads) void k_block_features_2d(
-    const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
-    double e, float* __restrict__ feat, float* __restrict__ aux) {
+__device__ __forceinline__ void block_features_2d_body(
+    const float* __restrict__ x, const Geo& g,
+    const uint32_t* __restrict__ origins, double e, float* __restrict__ feat,
+    float* __restrict__ aux, uint32_t bx) {
   __shared__ float blk[kB2Pts];
   __shared__ uint32_t keys[kNG2];
   __shared__ double red[4][kF2Threads / 64];
   __shared__ float mred[3][kF2Threads / 64];
   const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint32_t* o = origins + 3 * blockIdx.x;
+  const uint32_t* o = origins + 3 * bx;
   const uint64_t base = (uint64_t)o[1] * g.st[1] + o[2];
-  float* out = feat + 32 * (uint64_t)blockIdx.x;
+  float* out = feat + 32 * (uint64_t)bx;
   for (uint32_t t = tid; t < kB2Pts; t += kF2Threads) {
     const uint32_t i = t / kB1, j = t - i * kB1;
     blk[t] = x[base + (uint64_t)i * g.st[1] + j];
@@ -412,19 +420,26 @@ __global__ __launch_bounds__(kF2Threads) void k_block_features_2d(
       b2 = fmaxf(b2, mred[2][w]);
     }
     out[30] = (float)log2(1.0 + ((double)h2 - (double)l2) / e);
-    aux[3 * (uint64_t)blockIdx.x + 0] = l2;
-    aux[3 * (uint64_t)blockIdx.x + 1] = h2;
-    aux[3 * (uint64_t)blockIdx.x + 2] = b2;
+    aux[3 * (uint64_t)bx + 0] = l2;
+    aux[3 * (uint64_t)bx + 1] = h2;
+    aux[3 * (uint64_t)bx + 2] = b2;
   }
+}
+
+__global__ __launch_bounds__(kF2Threads) void k_block_features_2d(
+    const float* __restrict__ x, Geo g, const uint32_t* __restrict__ origins,
+    double e, float* __restrict__ feat, float* __restrict__ aux) {
+  block_features_2d_body(x, g, origins, e, feat, aux, blockIdx.x);
 }
 
 /* Range over all blocks into every row's feature 31, the mean of each
  * feature over the blocks into out[32], and the non-finite flag into
  * status[0]. */
-__global__ void k_feat_pool(float* __restrict__ feat,
-                            const float* __restrict__ aux, uint32_t nb,
-                            double e, float* __restrict__ out,
-                            uint32_t* __restrict__ status) {
+__device__ __forceinline__ void feat_pool_body(float* __restrict__ feat,
+                                               const float* __restrict__ aux,
+                                               uint32_t nb, double e,
+                                               float* __restrict__ out,
+                                               uint32_t* __restrict__ status) {
   const uint32_t i = threadIdx.x;
   float lo = aux[0], hi = aux[1], bad = aux[2];
 #pragma unroll 8
@@ -446,7 +461,61 @@ __global__ void k_feat_pool(float* __restrict__ feat,
   for (uint32_t b = i; b < nb; b += blockDim.x) feat[32 * (uint64_t)b + 31] = f31;
 }
 
+__global__ void k_feat_pool(float* __restrict__ feat,
+                            const float* __restrict__ aux, uint32_t nb,
+                            double e, float* __restrict__ out,
+                            uint32_t* __restrict__ status) {
+  feat_pool_body(feat, aux, nb, e, out, status);
+}
+
 size_t block_features_lds() { return 4 * (size_t)kBlockPts; }
+
+/* The features of many fields in three launches: the 3D fields' blocks
+ * (job j owns workgroups [wg0[j], wg0[j+1]) of x, three parts each in y),
+ * the 2D fields' blocks, then one pooling workgroup per field.  Pointers
+ * read from a record are made global (not flat). */
+__global__ __launch_bounds__(kFeatThreads) void k_block_features_q(
+    const FeatJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
+  const FeatJob& a = jobs[j];
+  block_features_body((const float*)gptr(a.x), a.g,
+                      (const uint32_t*)gptr(a.origins), a.e,
+                      (float*)gptr(a.feat), (float*)gptr(a.aux),
+                      blockIdx.x - wg0[j], blockIdx.y);
+}
+
+__global__ __launch_bounds__(kF2Threads) void k_block_features_2d_q(
+    const FeatJob* __restrict__ jobs, const uint32_t* __restrict__ wg0,
+    uint32_t n_jobs) {
+  const uint32_t j = find_job(wg0, n_jobs, blockIdx.x);
+  const FeatJob& a = jobs[j];
+  block_features_2d_body((const float*)gptr(a.x), a.g,
+                         (const uint32_t*)gptr(a.origins), a.e,
+                         (float*)gptr(a.feat), (float*)gptr(a.aux),
+                         blockIdx.x - wg0[j]);
+}
+
+__global__ void k_feat_pool_q(const FeatJob* __restrict__ jobs) {
+  const FeatJob& a = jobs[blockIdx.x];
+  feat_pool_body((float*)gptr(a.feat), (const float*)gptr(a.aux), a.nb, a.e,
+                 (float*)gptr(a.mean), (uint32_t*)gptr(a.status));
+}
+
+void launch_block_features_q(const FeatJob* jobs3, const uint32_t* wg3,
+                             uint32_t n3, uint32_t total3,
+                             const FeatJob* jobs2, const uint32_t* wg2,
+                             uint32_t n2, uint32_t total2,
+                             const FeatJob* all, uint32_t n, hipStream_t s) {
+  if (n3 && total3)
+    QOZ_LAUNCH(k_block_features_q, dim3(total3, 3), dim3(kFeatThreads),
+               block_features_lds(), s, jobs3, wg3, n3);
+  if (n2 && total2)
+    QOZ_LAUNCH(k_block_features_2d_q, dim3(total2), dim3(kF2Threads), 0, s,
+               jobs2, wg2, n2);
+  if (n) QOZ_LAUNCH(k_feat_pool_q, dim3(n), dim3(64), 0, s, all);
+}
+
 
 bool block_features_fit() {
   int dev = 0, max_lds = 0;
@@ -459,6 +528,10 @@ bool block_features_fit() {
   if (block_features_lds() + stat_bytes > (size_t)max_lds) return false;
   return hipFuncSetAttribute(
              reinterpret_cast<const void*>(&k_block_features),
+             hipFuncAttributeMaxDynamicSharedMemorySize,
+             (int)block_features_lds()) == hipSuccess &&
+         hipFuncSetAttribute(
+             reinterpret_cast<const void*>(&k_block_features_q),
              hipFuncAttributeMaxDynamicSharedMemorySize,
              (int)block_features_lds()) == hipSuccess;
 }

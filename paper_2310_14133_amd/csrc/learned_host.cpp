@@ -378,7 +378,10 @@ extern "C" qoz_status qoz_tune_learned_batch(
      * (32 per field), logits (11 per field), status (4 words per field) */
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     const size_t o_org = 0;
-    const size_t o_aux = al(o_org + 4 * org_all.size());
+    const size_t o_jobs = al(o_org + 4 * org_all.size());
+    const size_t o_wg = o_jobs + sizeof(FeatJob) * (size_t)m;
+    const size_t up = o_wg + 4 * (size_t)m; /* bytes uploaded */
+    const size_t o_aux = al(up);
     const size_t o_feat = al(o_aux + 4 * 3 * blocks);
     const size_t o_mean = al(o_feat + 4 * (size_t)kMlpFeat * blocks);
     const size_t o_logit = al(o_mean + 4 * (size_t)kMlpFeat * m);
@@ -386,23 +389,40 @@ extern "C" qoz_status qoz_tune_learned_batch(
     QOZ_TRY(ensure(c->lbatch, o_st + 16 * (size_t)m));
     uint8_t* D = (uint8_t*)c->lbatch.p;
     const size_t pin_org = kPinSingleBytes;
-    const size_t pin_back = pin_org + (4 * org_all.size() + 255) / 256 * 256;
+    const size_t pin_back = pin_org + al(up);
     QOZ_TRY(ensure_pinned(c, pin_back + 4 * (size_t)kMlpOut * m + 16 * m));
     uint8_t* hp = (uint8_t*)c->pinned;
+    /* origins, one record per field (3D fields first) and each group's
+     * first workgroups, uploaded in one copy */
     std::memcpy(hp + pin_org, org_all.data(), 4 * org_all.size());
-    QOZ_TRY(to_device(c, D + o_org, hp + pin_org, 4 * org_all.size(), s));
+    FeatJob* fj = (FeatJob*)(hp + pin_org + o_jobs);
+    uint32_t* wg = (uint32_t*)(hp + pin_org + o_wg);
+    uint32_t total3 = 0, total2 = 0;
+    double bytes = 0.0;
     for (uint32_t k = 0; k < m; ++k) {
       const Job& j = jobs[k];
+      uint32_t& total = k < m3 ? total3 : total2;
+      wg[k] = total;
+      total += j.nb;
+      fj[k] = FeatJob{items[j.item].d_x,
+                      make_geo(j.d, j.n),
+                      (const uint32_t*)(D + o_org) + j.org,
+                      j.nb,
+                      items[j.item].abs_eb,
+                      (float*)(D + o_feat) + (size_t)kMlpFeat * j.blk,
+                      (float*)(D + o_aux) + 3 * j.blk,
+                      (float*)(D + o_mean) + (size_t)kMlpFeat * k,
+                      (uint32_t*)(D + o_st) + 4 * k};
+      bytes += 4.0 * (j.d == 2 ? 1089.0 : 35937.0) * j.nb;
+    }
+    QOZ_TRY(to_device(c, D + o_org, hp + pin_org, up, s));
+    {
+      const FeatJob* dj = (const FeatJob*)(D + o_jobs);
+      const uint32_t* dw = (const uint32_t*)(D + o_wg);
       hipEvent_t ev = prof_begin(c, s, PK_LEARN_FEAT);
-      launch_block_features(items[j.item].d_x, make_geo(j.d, j.n),
-                            (const uint32_t*)(D + o_org) + j.org, j.nb,
-                            items[j.item].abs_eb,
-                            (float*)(D + o_feat) + (size_t)kMlpFeat * j.blk,
-                            (float*)(D + o_aux) + 3 * j.blk,
-                            (float*)(D + o_mean) + (size_t)kMlpFeat * k,
-                            (uint32_t*)(D + o_st) + 4 * k, s);
-      prof_end(c, s, ev, PK_LEARN_FEAT,
-               4.0 * (j.d == 2 ? 1089.0 : 35937.0) * j.nb);
+      launch_block_features_q(dj, dw, m3, total3, dj + m3, dw + m3, m - m3,
+                              total2, dj, m, s);
+      prof_end(c, s, ev, PK_LEARN_FEAT, bytes);
     }
     if (m3) {
       hipEvent_t ev = prof_begin(c, s, PK_MLP);

@@ -634,6 +634,27 @@ bool block_features_fit();
 /* features of nb sampled 33^3 blocks into feat[nb][32] (aux: 3 floats per
  * block), their mean into mean[32], kStNonFinite into status[0] when a
  * sampled value is NaN or Inf */
+/* One field of a batched feature extraction: its blocks' origins, the
+ * per-block features and (min, max, flag) triples, the pooled features
+ * and status word. */
+struct FeatJob {
+  const float* x;
+  Geo g;
+  const uint32_t* origins;
+  uint32_t nb;
+  double e;
+  float* feat;
+  float* aux;
+  float* mean;
+  uint32_t* status;
+};
+/* the 3D jobs' blocks (total3 workgroups, wg3 their prefix), the 2D jobs'
+ * blocks, then the pooling of all n jobs (all: jobs3 then jobs2) */
+void launch_block_features_q(const FeatJob* jobs3, const uint32_t* wg3,
+                             uint32_t n3, uint32_t total3,
+                             const FeatJob* jobs2, const uint32_t* wg2,
+                             uint32_t n2, uint32_t total2,
+                             const FeatJob* all, uint32_t n, hipStream_t s);
 void launch_block_features(const float* x, const Geo& g,
                            const uint32_t* origins, uint32_t nb, double e,
                            float* feat, float* aux, float* mean,
