@@ -3,9 +3,11 @@
  * many fields at once, in a number of launches that does not grow with the
  * batch:
  *
- *   1. (fields given without parameters are tuned first by the online
- *      tuner of Sec. VI, on up to 8 worker contexts with their own streams,
- *      largest field first;)
+ *   1. (fields given without parameters are tuned by the online tuner of
+ *      Sec. VI on up to 8 worker contexts with their own streams, largest
+ *      field first, while this thread compresses the fields tuned so far,
+ *      each group as one call of the steps below with its parameters
+ *      given;)
  *   2. one upload of the queues, then one launch for every field's
  *      anchors, one launch per round of sweeps (the r-th sweep, or fused
  *      level-1 row pair, of every field), one launch for every field's
@@ -33,7 +35,10 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -151,6 +156,108 @@ void on_threads(size_t n, Fn fn) {
 
 using namespace qoz;
 
+/* Tuning overlapped with compression.  A thread hands the fields to tune
+ * to the worker contexts (largest first); this thread waits for each
+ * round of tunings (as many fields as workers, or the last ones), then
+ * compresses everything ready and not yet compressed (the fields with
+ * given parameters go with the first group) as one queue call with the
+ * parameters given.  A field's stream is the single-field call's either
+ * way. */
+static qoz_status compress_tuning(qoz_ctx* c, qoz_batch_item* items,
+                                  uint32_t n, std::vector<qoz_params>& pv,
+                                  const std::vector<uint32_t>& to_tune,
+                                  qoz_target target,
+                                  const qoz_tune_config* cfg, hipStream_t s,
+                                  std::chrono::steady_clock::time_point t0) {
+  const size_t total = to_tune.size();
+  const uint32_t nw = (uint32_t)std::min<size_t>(kTuneWorkers, total);
+  QOZ_HIP(hipStreamSynchronize(s));
+  QOZ_TRY(ensure_workers(c, nw));
+  std::vector<uint64_t> pts(total, 1);
+  for (size_t k = 0; k < total; ++k)
+    for (uint32_t m = 0; m < items[to_tune[k]].shape.ndim && m < 3; ++m)
+      pts[k] *= items[to_tune[k]].shape.dims[m];
+  std::vector<uint32_t> order(total);
+  for (uint32_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return pts[a] > pts[b]; });
+
+  std::mutex mu;
+  std::condition_variable cv;
+  std::vector<uint32_t> ready; /* items with parameters, not compressed */
+  size_t tuned = 0;            /* tunings ended (failed ones too) */
+  std::string why;             /* the first failure's message */
+  for (uint32_t i = 0; i < n; ++i)
+    if (items[i].status == QOZ_OK && items[i].params) ready.push_back(i);
+  std::thread tuner([&]() {
+    run_on_workers(order, nw, [&](uint32_t w, uint32_t k) {
+      const uint32_t i = to_tune[k];
+      qoz_batch_item& it = items[i];
+      qoz_params p = pv[i]; /* zeroed: the tuner reads its anchor stride */
+      const qoz_status st = qoz_tune(c->workers[w], it.d_x, it.shape,
+                                     it.abs_eb, target, cfg, &p,
+                                     c->worker_streams[w]);
+      std::lock_guard<std::mutex> g(mu);
+      it.status = st;
+      if (st == QOZ_OK) {
+        pv[i] = p;
+        ready.push_back(i);
+      } else if (why.empty()) {
+        why = std::string("tuning: ") + qoz_last_error();
+      }
+      ++tuned;
+      cv.notify_one();
+    });
+  });
+  size_t taken = 0; /* tunings ended at the last take */
+  for (;;) {
+    std::vector<uint32_t> grp;
+    bool last;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&]() { return tuned == total || tuned - taken >= nw; });
+      grp.swap(ready);
+      taken = tuned;
+      last = tuned == total;
+    }
+    if (!grp.empty()) {
+      std::sort(grp.begin(), grp.end());
+      std::vector<qoz_batch_item> sub(grp.size());
+      for (size_t k = 0; k < grp.size(); ++k) {
+        sub[k] = items[grp[k]];
+        sub[k].params = &pv[grp[k]];
+      }
+      /* per-item statuses carry the outcome */
+      if (qoz_compress_queue(c, sub.data(), (uint32_t)sub.size(), target,
+                             cfg, s) != QOZ_OK) {
+        std::lock_guard<std::mutex> g(mu);
+        if (why.empty()) why = qoz_last_error();
+      }
+      const double dm = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0)
+                            .count();
+      for (size_t k = 0; k < grp.size(); ++k) {
+        qoz_batch_item& it = items[grp[k]];
+        it.status = sub[k].status;
+        it.out_bytes = sub[k].out_bytes;
+        it.done_ms = dm;
+      }
+    }
+    if (last) break;
+  }
+  tuner.join();
+  const double ms = std::chrono::duration<double, std::milli>(
+                        std::chrono::steady_clock::now() - t0)
+                        .count();
+  for (uint32_t i = 0; i < n; ++i) items[i].ms = ms;
+  clear_error();
+  for (uint32_t i = 0; i < n; ++i)
+    if (items[i].status != QOZ_OK)
+      return fail(items[i].status,
+                  why.empty() ? "a field of the batch failed" : why);
+  return QOZ_OK;
+}
+
 extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
                                          uint32_t n, qoz_target target,
                                          const qoz_tune_config* cfg,
@@ -188,26 +295,8 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
       to_tune.push_back(i);
     }
   }
-  if (!to_tune.empty()) {
-    const uint32_t nw = (uint32_t)std::min<size_t>(kTuneWorkers, to_tune.size());
-    QOZ_HIP(hipStreamSynchronize(s));
-    QOZ_TRY(ensure_workers(c, nw));
-    std::vector<uint64_t> pts(to_tune.size(), 1);
-    for (size_t k = 0; k < to_tune.size(); ++k)
-      for (uint32_t m = 0; m < items[to_tune[k]].shape.ndim && m < 3; ++m)
-        pts[k] *= items[to_tune[k]].shape.dims[m];
-    std::vector<uint32_t> order(to_tune.size());
-    for (uint32_t k = 0; k < order.size(); ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t a, uint32_t b) { return pts[a] > pts[b]; });
-    run_on_workers(order, nw, [&](uint32_t w, uint32_t k) {
-      qoz_batch_item& it = items[to_tune[k]];
-      it.status = qoz_tune(c->workers[w], it.d_x, it.shape, it.abs_eb, target,
-                           cfg, &pv[to_tune[k]], c->worker_streams[w]);
-    });
-    for (uint32_t w = 0; w < nw; ++w)
-      QOZ_HIP(hipStreamSynchronize(c->worker_streams[w]));
-  }
+  if (!to_tune.empty())
+    return compress_tuning(c, items, n, pv, to_tune, target, cfg, s, t0);
   for (uint32_t i = 0; i < n; ++i) {
     qoz_batch_item& it = items[i];
     if (it.status != QOZ_OK) continue;
