@@ -335,13 +335,16 @@ qoz_status qoz_decompress_queue(qoz_ctx* ctx, qoz_batch_dec_item* items,
  * codes the chunks of every field.  Three waits per call (four when a
  * field uses more than 4096 distinct bins), plus the few launches of each
  * field whose zero-word packing pays.  Items without params are
- * tuned first with the online tuner (target, cfg) on up to 8 worker
- * contexts of ctx, each with its own stream (the call first waits for
- * `stream`, whose work may produce the inputs).  Every
+ * tuned with the online tuner (target, cfg) on up to 8 worker contexts of
+ * ctx, each with its own stream (the call first waits for `stream`, whose
+ * work may produce the inputs), largest first; meanwhile the calling
+ * thread compresses, as the steps above, the fields tuned so far each time
+ * a round of tunings (as many as workers) has ended.  Every
  * stream equals qoz_compress's byte for byte; sweeps use the default
  * launch tiles.  A field whose output cannot hold the sections before its
  * payload is compressed by qoz_compress after the queue (and reports the
- * size needed).  ms and done_ms of every item are the call's duration.
+ * size needed).  ms of every item is the call's duration; done_ms is when
+ * its group ended (the call's duration when nothing is tuned).
  * Returns as qoz_compress_batch.  Scratch: every field's reconstruction,
  * bins and histogram at once, kept in ctx.
  * Errors: EINVAL, EDEVICE, ENOMEM, or an item's status. */
