@@ -227,6 +227,25 @@ def tuning(codec, xs, ebs, total):
     po, to = timed(online)
     (pl, n_fb), tl = timed(batch)
 
+    # tune + compress of the whole batch through the queues, PSNR target:
+    # tuned inside the queue call by the online tuner, or by the batched
+    # learned tuner first and then compressed with its parameters
+    def e2e(fn, reps=3):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return min(ts)
+
+    t_on = e2e(lambda: codec.compress_batch(xs, ebs, None, "psnr", cfg,
+                                            queue=True))
+    t_le = e2e(lambda: codec.compress_batch(xs, ebs, batch()[0], "psnr", cfg,
+                                            queue=True))
+
     def stream_bytes(ps):
         return sum(int(codec.compress(x, e, p).numel())
                    for x, e, p in zip(xs, ebs, ps))
@@ -234,7 +253,9 @@ def tuning(codec, xs, ebs, total):
     return {"online_ms": to, "learned_batch_ms": tl,
             "learned_fallbacks": int(n_fb), "fields": len(xs),
             "cr_online": total / stream_bytes(po),
-            "cr_learned": total / stream_bytes(pl)}
+            "cr_learned": total / stream_bytes(pl),
+            "queue_online_tune_compress_GBps": total / t_on / 1e9,
+            "queue_learned_tune_compress_GBps": total / t_le / 1e9}
 
 
 if __name__ == "__main__":
