@@ -338,8 +338,21 @@ __global__ __launch_bounds__(NT) void k_alg1_lds(
   const Geo cg = compact_geo(g, h);
   const uint32_t total = cg.n[0] * cg.n[1] * cg.n[2];
   const float* X = xs + (uint64_t)blk * bg.size;
-  copy_mapped<NT, false>(Ws, wc + (uint64_t)blk * bg.size, total,
-                         CompactMap(g, cg, h, total));
+  const float* src = wc + (uint64_t)blk * bg.size;
+  if (h == 1) {
+    /* the whole block: a plain copy, no index map */
+    for (uint32_t t0 = threadIdx.x; t0 < total; t0 += kLdsBatch * NT) {
+      float v[kLdsBatch];
+#pragma unroll
+      for (uint32_t u = 0; u < kLdsBatch; ++u)
+        v[u] = t0 + u * NT < total ? src[t0 + u * NT] : 0.0f;
+#pragma unroll
+      for (uint32_t u = 0; u < kLdsBatch; ++u)
+        if (t0 + u * NT < total) Ws[t0 + u * NT] = v[u];
+    }
+  } else {
+    copy_mapped<NT, false>(Ws, src, total, CompactMap(g, cg, h, total));
+  }
   __syncthreads();
   const TrialLevel lv = desc[c].lv[l - 1];
   double l1 = 0.0;
