@@ -156,6 +156,11 @@ void on_threads(size_t n, Fn fn) {
 
 using namespace qoz;
 
+static qoz_status compress_queue(qoz_ctx* c, qoz_batch_item* items,
+                                 uint32_t n, qoz_target target,
+                                 const qoz_tune_config* cfg, hipStream_t s,
+                                 bool* items_only);
+
 /* Tuning overlapped with compression.  A thread hands the fields to tune
  * to the worker contexts (largest first); this thread waits for each
  * round of tunings (as many fields as workers, or the last ones), then
@@ -227,9 +232,16 @@ static qoz_status compress_tuning(qoz_ctx* c, qoz_batch_item* items,
         sub[k] = items[grp[k]];
         sub[k].params = &pv[grp[k]];
       }
-      /* per-item statuses carry the outcome */
-      if (qoz_compress_queue(c, sub.data(), (uint32_t)sub.size(), target,
-                             cfg, s) != QOZ_OK) {
+      /* per-item statuses carry the outcome; a call that fails as a whole
+       * fails every item it left marked OK */
+      bool items_only = false;
+      const qoz_status rc =
+          compress_queue(c, sub.data(), (uint32_t)sub.size(), target, cfg,
+                         s, &items_only);
+      if (rc != QOZ_OK) {
+        if (!items_only)
+          for (qoz_batch_item& it : sub)
+            if (it.status == QOZ_OK) it.status = rc;
         std::lock_guard<std::mutex> g(mu);
         if (why.empty()) why = qoz_last_error();
       }
@@ -262,6 +274,16 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
                                          uint32_t n, qoz_target target,
                                          const qoz_tune_config* cfg,
                                          hipStream_t s) {
+  return compress_queue(c, items, n, target, cfg, s, nullptr);
+}
+
+/* items_only (if given) is set when the returned error is an item's own
+ * status (every other item's status is then its outcome) rather than a
+ * failure of the call as a whole. */
+static qoz_status compress_queue(qoz_ctx* c, qoz_batch_item* items,
+                                 uint32_t n, qoz_target target,
+                                 const qoz_tune_config* cfg, hipStream_t s,
+                                 bool* items_only) {
   clear_error();
   if (!c || (n && !items)) return fail(QOZ_EINVAL, "NULL argument");
   if (n > kMaxCompQueue) return fail(QOZ_EINVAL, "batch too large");
@@ -313,8 +335,10 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
   const uint32_t nf = (uint32_t)F.size();
   if (!nf) {
     for (uint32_t i = 0; i < n; ++i)
-      if (items[i].status != QOZ_OK)
+      if (items[i].status != QOZ_OK) {
+        if (items_only) *items_only = true;
         return fail(items[i].status, "a field of the batch failed");
+      }
     return QOZ_OK;
   }
 
@@ -777,7 +801,9 @@ extern "C" qoz_status qoz_compress_queue(qoz_ctx* c, qoz_batch_item* items,
                         .count();
   for (uint32_t i = 0; i < n; ++i) items[i].ms = items[i].done_ms = ms;
   for (uint32_t i = 0; i < n; ++i)
-    if (items[i].status != QOZ_OK)
+    if (items[i].status != QOZ_OK) {
+      if (items_only) *items_only = true;
       return fail(items[i].status, "a field of the batch failed");
+    }
   return QOZ_OK;
 }

@@ -190,3 +190,41 @@ def test_compress_queue_many_fields(codec, ref):
         assert np.array_equal(zs[i].cpu().numpy(), zr[i]), i
     zs, items = codec.compress_batch([], [], None, queue=True)
     assert zs == [] and len(items) == 0
+
+
+def test_compress_queue_tuned_groups_with_failures(codec, ref):
+    """Twelve fields to tune (more than one round of the 8 tuning workers,
+    so several compression groups) next to fields with parameters given:
+    a field with a NaN fails its tuning with EINVAL, a too-small buffer
+    fails with ENOSPACE, and every other stream equals the single-field
+    call's; each field's group ends within the call."""
+    import paper_2310_14133_amd as q
+    cfg = q.make_tune_config(sample_rate=0.2)
+    cs = cases(ref)[:4]
+    xs, es, ps = [], [], []
+    for i in range(12):
+        sh = [(40, 41, 42), (130, 129), (33, 65, 17), (64, 64, 64)][i % 4]
+        x = fields.grf(sh, 700 + i, log_normal=(i % 3 == 1))
+        xs.append(to_dev(x))
+        es.append([1e-2, 1e-3, 1e-4][i % 3] * float(x.max() - x.min()))
+        ps.append(None)
+    for _, x, e, rp in cs:
+        xs.append(to_dev(x))
+        es.append(e)
+        ps.append(qparams(q, rp))
+    bad = xs[5].cpu().numpy().copy()
+    bad.flat[3] = np.nan
+    xs[5] = to_dev(bad)
+    caps = [q.qoz_compress_bound(codec._field(x)) for x in xs]
+    caps[7] = 300
+    zs, items = codec.compress_batch(xs, es, ps, "cr", cfg, queue=True,
+                                     caps=caps, check=False)
+    assert items[5].status == q.QOZ_EINVAL
+    assert items[7].status == q.QOZ_ENOSPACE
+    for i in range(len(xs)):
+        if i in (5, 7):
+            continue
+        assert items[i].status == q.QOZ_OK, i
+        z1 = codec.compress(xs[i], es[i], ps[i], "cr", cfg)
+        assert np.array_equal(zs[i].cpu().numpy(), z1.cpu().numpy()), i
+        assert 0 < items[i].done_ms <= items[i].ms, i
