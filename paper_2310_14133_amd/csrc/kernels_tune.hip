@@ -291,22 +291,55 @@ __device__ __forceinline__ void lds_sweep(const Geo& g, const uint32_t* start,
                                           const Geo& xg, uint32_t xh,
                                           Body body) {
   const uint32_t count = cnt[0] * cnt[1] * cnt[2];
+  if (count == 0) return;
   const FastDiv f2(cnt[2], count), f1(cnt[1], count);
+  /* NT = a2 cnt[2] + b2 and a2 = a1 cnt[1] + b1: with 256 threads the
+   * coordinates of t + NT follow from those of t with one carry per
+   * dimension (measured faster there; with 1024 threads, slower than the
+   * two divisions per point) */
+  constexpr bool kStep = NT <= 256;
+  const uint32_t a2 = NT / cnt[2], b2 = NT - a2 * cnt[2];
+  const uint32_t a1 = a2 / cnt[1], b1 = a2 - a1 * cnt[1];
   for (uint32_t t0 = threadIdx.x; t0 < count; t0 += kLdsBatch * NT) {
     uint32_t li[kLdsBatch], pk[kLdsBatch];
     float xv[kLdsBatch];
+    uint32_t i0, i1, i2;
+    {
+      const uint32_t r = f2.div(t0);
+      i2 = t0 - r * cnt[2];
+      i0 = f1.div(r);
+      i1 = r - i0 * cnt[1];
+    }
 #pragma unroll
     for (uint32_t u = 0; u < kLdsBatch; ++u) {
       const uint32_t t = t0 + u * NT;
-      const uint32_t tt = t < count ? t : 0u;
-      const uint32_t r = f2.div(tt), i2 = tt - r * cnt[2];
-      const uint32_t i0 = f1.div(r), i1 = r - i0 * cnt[1];
-      const uint32_t q[3] = {start[0] + i0 * step[0],
-                             start[1] + i1 * step[1],
-                             start[2] + i2 * step[2]};
+      if (!kStep) {
+        const uint32_t tt = t < count ? t : 0u;
+        const uint32_t r = f2.div(tt);
+        i2 = tt - r * cnt[2];
+        i0 = f1.div(r);
+        i1 = r - i0 * cnt[1];
+      } else if (u) {
+        i2 += b2;
+        const uint32_t c2 = i2 >= cnt[2] ? 1u : 0u;
+        i2 -= c2 ? cnt[2] : 0u;
+        i1 += b1 + c2;
+        i0 += a1;
+        if (i1 >= cnt[1]) {
+          i1 -= cnt[1];
+          ++i0;
+        }
+      }
+      /* past the end: any in-range point (nothing is read or written;
+       * the divisions above already start from point 0 there) */
+      const bool in = t < count;
+      const bool clamp = kStep && !in;
+      const uint32_t q[3] = {start[0] + (clamp ? 0u : i0) * step[0],
+                             start[1] + (clamp ? 0u : i1) * step[1],
+                             start[2] + (clamp ? 0u : i2) * step[2]};
       li[u] = q[0] * g.st[0] + q[1] * g.st[1] + q[2];
       pk[u] = q[k];
-      xv[u] = t < count
+      xv[u] = in
                   ? X[xh * (q[0] * xg.st[0] + q[1] * xg.st[1] + q[2])]
                   : 0.0f;
     }
